@@ -1,0 +1,73 @@
+"""Brute-force butterfly classification (ORACLE, test infrastructure only).
+
+Definition 1: a butterfly is a 4-cycle u - v - u' - v' with {u, u'} in U and
+{v, v'} in V and all four edges present.  Definition 2: it is balanced when
+the number of negative edges among the four is even, unbalanced otherwise.
+This module loops over every pair of U times every pair of V; it is meant for
+graphs of at most a few dozen vertices per side.
+"""
+
+from __future__ import annotations
+
+from itertools import combinations
+
+
+def _edge_map(u, v, sign):
+    e = {}
+    for a, b, s in zip(u, v, sign):
+        e[(int(a), int(b))] = int(s)
+    return e
+
+
+def brute_counts(n_u, n_v, u, v, sign):
+    """Return (balanced, unbalanced, total) by enumerating every 2x2 vertex set."""
+    e = _edge_map(u, v, sign)
+    bal = unb = 0
+    for a, a2 in combinations(range(n_u), 2):
+        for b, b2 in combinations(range(n_v), 2):
+            quad = [(a, b), (a, b2), (a2, b), (a2, b2)]
+            if not all(q in e for q in quad):
+                continue
+            negatives = sum(1 for q in quad if e[q] < 0)
+            if negatives % 2 == 0:
+                bal += 1
+            else:
+                unb += 1
+    return bal, unb, bal + unb
+
+
+def brute_per_vertex(n_u, n_v, u, v, sign):
+    """Per vertex, the number of balanced / unbalanced butterflies containing it.
+
+    Returns four lists: bal_u[n_u], bal_v[n_v], unb_u[n_u], unb_v[n_v].
+    """
+    e = _edge_map(u, v, sign)
+    bal_u, bal_v = [0] * n_u, [0] * n_v
+    unb_u, unb_v = [0] * n_u, [0] * n_v
+    for a, a2 in combinations(range(n_u), 2):
+        for b, b2 in combinations(range(n_v), 2):
+            quad = [(a, b), (a, b2), (a2, b), (a2, b2)]
+            if not all(q in e for q in quad):
+                continue
+            negatives = sum(1 for q in quad if e[q] < 0)
+            tu, tv = (bal_u, bal_v) if negatives % 2 == 0 else (unb_u, unb_v)
+            tu[a] += 1
+            tu[a2] += 1
+            tv[b] += 1
+            tv[b2] += 1
+    return bal_u, bal_v, unb_u, unb_v
+
+
+def brute_per_edge(n_u, n_v, u, v, sign):
+    """Per edge (in input order), the number of balanced butterflies containing it."""
+    e = _edge_map(u, v, sign)
+    cnt = {k: 0 for k in e}
+    for a, a2 in combinations(range(n_u), 2):
+        for b, b2 in combinations(range(n_v), 2):
+            quad = [(a, b), (a, b2), (a2, b), (a2, b2)]
+            if not all(q in e for q in quad):
+                continue
+            if sum(1 for q in quad if e[q] < 0) % 2 == 0:
+                for q in quad:
+                    cnt[q] += 1
+    return [cnt[(int(a), int(b))] for a, b in zip(u, v)]

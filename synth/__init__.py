@@ -1,0 +1,17 @@
+"""Seeded synthetic signed bipartite graphs.
+
+This package only draws inputs (vertex pairs and edge signs).  It holds none of
+the counting arithmetic, so both the CPU oracle and the GPU library may take
+their inputs from it without sharing any part of the method.
+"""
+
+from .graphs import (  # noqa: F401
+    SignedGraph,
+    uniform_graph,
+    chung_lu_graph,
+    config_graph,
+    batch_graph,
+    pool_graph,
+    upload_graph,
+    CONFIGS,
+)
