@@ -1,0 +1,217 @@
+"""Benchmark: exact balanced / unbalanced butterfly counting on one MI355X.
+
+One step = one full count (every kernel of the path) of the resident graph,
+i.e. dbbc_count on a handle whose CSR is already in HBM.  Prints ONE JSON
+line (see the keys below).  The default workload is the 50M-edge skewed
+Chung-Lu graph; --config picks another named workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GWedges/s + balanced butterflies/s at 1 MI355X; batched graphs/s vs plain"
+HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0
+
+WORKLOADS = {
+    "skewed50m": "Chung-Lu bipartite |U|=5,000,000 |V|=2,000,000 m=50,000,000, "
+                 "degree exponents 2.1 (U) / 1.9 (V), degree cap 1e5, sign -1 w.p. 0.4, seed 0",
+    "powerlaw2m": "Chung-Lu bipartite |U|=200,000 |V|=100,000 m=2,000,000, exponents 2.3 / 2.1, "
+                  "sign -1 w.p. 0.25, seed 0",
+    "tiny": "uniform bipartite |U|=2,000 |V|=1,500 m=20,000, sign -1 w.p. 0.3, seed 0",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("count.hip", "hub.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2609_21848_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(config: str, kernel: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        p = json.load(f)
+    if p.get("src_hash") != src_hash():
+        return None
+    return (p["fetch_kib_per_dispatch"] + p["write_kib_per_dispatch"]) * 1024.0 * p["copy_scale"]
+
+
+def cpu_baseline(g, fraction: int, threads: int | None):
+    """The CPU oracle on every fraction-th pivot (a fixed hash of the vertex
+    index), timed end to end; returns GWedges/s of the sample."""
+    import numpy as np
+    from oracle.vp import default_threads, vp_counts
+
+    n = g.n_u + g.n_v
+    idx = np.arange(n, dtype=np.int64)
+    pick = ((idx * 2654435761) >> 7) % fraction == 0
+    pivots = idx[pick].astype(np.int32)
+    thr = threads or default_threads()
+    t = time.perf_counter()
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, pivots=pivots, threads=thr)
+    dt = time.perf_counter() - t
+    return {
+        "value": r.wedges / dt / 1e9,
+        "unit": "GWedges/s",
+        "cores": thr,
+        "kind": "oracle",
+        "sample": f"oracle (plain C vertex-priority count, its own CSR build included) on "
+                  f"{len(pivots)} of {n} pivots (1 in {fraction} by a fixed hash), "
+                  f"{r.wedges} wedges in {dt:.2f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="skewed50m", choices=sorted(WORKLOADS))
+    ap.add_argument("--hub-T", type=int, default=-1)
+    ap.add_argument("--window-L", type=int, default=-1)
+    ap.add_argument("--cpu-fraction", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_21848_amd as dbbc
+    from synth import config_graph
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dbbc.load()
+
+    t = time.perf_counter()
+    g = config_graph(args.config)
+    t_gen = time.perf_counter() - t
+    log(f"[bench] generated {args.config}: n_u={g.n_u} n_v={g.n_v} m={g.m} in {t_gen:.1f}s")
+
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    h = dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign, stream=stream)
+    t_build = time.perf_counter() - t
+    st = h.stats()
+    w_vp = st["wedges_vp"]
+    log(f"[bench] graph built in {t_build:.2f}s; W_VP={w_vp}; device bytes={st['device_bytes']}")
+
+    opts = dict(hub_T=args.hub_T, window_L=args.window_L)
+    t = time.perf_counter()
+    first = h.count(**opts)
+    t_first = time.perf_counter() - t
+    log(f"[bench] first count (plan + run) {t_first:.2f}s: {first}")
+    for i in range(args.warmup):
+        c = h.count(**opts)
+        assert c == first, "counts changed between runs"
+    log("[bench] warmup done")
+
+    timed = dict(opts, flags=dbbc.DBBC_OPT_TIME_KERNELS)
+    per_kernel = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        c = h.count(**timed)
+        for k in h.kernel_times():
+            rec = per_kernel.setdefault(k["name"], dict(k, ms=0.0, launches=0))
+            rec["ms"] += k["ms"]
+            rec["launches"] += 1
+        assert c == first
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step")
+
+    # parity of the timed result against the committed oracle counts
+    verified = None
+    cache_path = os.path.join(ROOT, "tests", "golden", "oracle_cache.json")
+    if os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f).get(args.config)
+        if cache and (cache["n_u"], cache["n_v"], cache["m"]) == (g.n_u, g.n_v, g.m):
+            verified = (first.balanced, first.unbalanced, first.total, first.wedges) == (
+                cache["balanced"], cache["unbalanced"], cache["total"], cache["wedges"])
+
+    kernels = []
+    for name, rec in per_kernel.items():
+        avg = rec["ms"] / rec["launches"]
+        kernels.append(dict(name=name, avg_ms=avg, wedges=rec["wedges"], segments=rec["segments"],
+                            items=rec["items"], macs=rec["macs"]))
+    dom = max(kernels, key=lambda k: k["avg_ms"])
+    if dom["macs"] > 0:
+        achieved = 2 * dom["macs"] / (dom["avg_ms"] / 1e3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                "frac": achieved / INT8_PEAK_TOPS, "traffic": None, "kernel": dom["name"]}
+    else:
+        alg_bytes = 5 * dom["wedges"] + 17 * dom["segments"] + 12 * dom["items"]
+        achieved = alg_bytes / (dom["avg_ms"] / 1e3) / 1e9
+        traffic = traffic_for(args.config, dom["name"], alg_bytes)
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["name"],
+                "alg_bytes_per_launch": alg_bytes}
+
+    steps_s = (t1 - t0)
+    value = w_vp * args.steps / steps_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GWedges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
+                   "hub_T": args.hub_T, "window_L": args.window_L},
+        "roofline": roof,
+        "balanced_per_s": first.balanced * args.steps / steps_s,
+        "butterflies_per_s": first.total * args.steps / steps_s,
+        "counts": first._asdict(),
+        "verified_vs_oracle": verified,
+        "t_generate_s": t_gen,
+        "t_build_s": t_build,
+        "t_first_count_s": t_first,
+        "kernels": kernels,
+    }
+    h.close()
+    if not args.no_cpu:
+        log("[bench] cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_fraction, None)
+        log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.4f} GWedges/s")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/* dbbc.h -- exact counting of balanced and unbalanced butterflies in signed
+ * bipartite graphs on AMD Instinct MI355X (gfx950).
+ *
+ * A butterfly (Definition 1) is a 2x2 biclique {u, u'} x {v, v'} of a
+ * bipartite graph G = (U, V, E).  With edge signs s: E -> {+1, -1} it is
+ * balanced (Definition 2) when its number of negative edges is even, i.e.
+ * when the product of its four signs is +1, and unbalanced otherwise.  The
+ * library computes, exactly, the number of balanced butterflies (the
+ * problem statement of Section III), the number of unbalanced ones, their sum
+ * (the unsigned butterfly count) and the number of vertex-priority wedges the
+ * method walks (Algorithm 1, Phase 5, with the vertex priority of
+ * Definition 3), optionally per vertex.
+ *
+ * Conventions shared by every entry point:
+ *   - Vertex ids: u in [0, n_u) on side U and v in [0, n_v) on side V, two
+ *     separate id spaces.  For the tie-break of Definition 3 (equal degrees:
+ *     the larger id has the higher priority) vertex v of V has id n_u + v.
+ *     Counts do not depend on the tie-break (Theorem 1).  n_u + n_v < 2^30
+ *     and every per-side edge count below 2^31 - 1.
+ *   - Signs: int8 values +1 (positive) or -1 (negative).  The paper's edge
+ *     records use 1 for positive and 0 for negative; callers map 0 to -1.
+ *   - Duplicate (u, v) pairs: the last occurrence in input order wins (the
+ *     paper keeps the latest interaction, Section V); the number dropped is
+ *     reported.  DBBC_DUP_REJECT turns any duplicate into DBBC_E_DUPLICATE.
+ *   - Errors: every int-returning call returns DBBC_OK (0) or a negative
+ *     status; on error no output is written and dbbc_last_error() holds a
+ *     message for the calling thread.
+ *   - Streams: hip_stream is a hipStream_t (NULL = the null stream).  Device
+ *     work is ordered on it; calls that return host results synchronise it.
+ *   - Threads: distinct handles may be used from different threads at once.
+ *     One handle owns its scratch memory, so calls on the same handle must
+ *     not overlap (the caller serialises them).
+ */
+#ifndef DBBC_H
+#define DBBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define DBBC_OK 0
+#define DBBC_E_INVALID_ARG (-1) /* NULL pointer, negative size, bad flag */
+#define DBBC_E_ID_RANGE (-2)    /* u not in [0, n_u) or v not in [0, n_v) */
+#define DBBC_E_SIGN (-3)        /* sign not +1 or -1 */
+#define DBBC_E_DUPLICATE (-4)   /* duplicate pair under DBBC_DUP_REJECT */
+#define DBBC_E_OOM (-5)         /* host or device allocation failed */
+#define DBBC_E_DEVICE (-6)      /* a HIP call or kernel launch failed */
+#define DBBC_E_TOO_LARGE (-7)   /* sizes beyond the limits stated above */
+#define DBBC_E_NO_DEVICE (-8)   /* no gfx950 device visible */
+
+/* ---- flags for dbbc_graph_create ---------------------------------------- */
+#define DBBC_INPUT_DEVICE 0x1u /* u, v, sign point to device memory */
+#define DBBC_DUP_REJECT 0x2u   /* fail on duplicate pairs instead of dropping */
+
+typedef struct dbbc_graph dbbc_graph; /* opaque; owns its device memory */
+
+/* Exact results of one count. */
+typedef struct {
+  int64_t balanced;   /* butterflies with an even number of negative edges */
+  int64_t unbalanced; /* butterflies with an odd number of negative edges */
+  int64_t total;      /* all butterflies (= balanced + unbalanced) */
+  int64_t wedges;     /* vertex-priority wedges of the graph (W_VP): wedges
+                         u-v-w with v and w both of lower priority than u */
+} dbbc_counts;
+
+/* Facts about a built graph (host memory, filled by dbbc_graph_stats). */
+typedef struct {
+  int64_t n_u, n_v, m;      /* vertices per side, distinct edges kept */
+  int64_t dups_dropped;     /* input records dropped as duplicates */
+  int64_t max_deg_u, max_deg_v;
+  int64_t device_bytes;     /* device memory held by the handle */
+  int64_t wedges_vp;        /* W_VP, computed in closed form at build time */
+  int64_t pivots_active;    /* pivots that walk at least one wedge */
+} dbbc_stats;
+
+/* Tuning knobs for a count.  Pass NULL for the library's defaults (chosen
+ * from the graph's statistics).  Every setting gives the same exact counts;
+ * only the work split and speed change. */
+typedef struct {
+  int32_t hub_T;    /* side of the dense hub block counted with int8 MFMA:
+                       the T highest-priority vertices of each side (a
+                       multiple of 128, at most window_L); 0 turns
+                       the dense path off; -1 = default */
+  int32_t window_L; /* per side, the L highest-priority vertices whose pair
+                       counts are kept in on-chip direct arrays; a multiple
+                       of 256 in [256, 32768]; -1 = default */
+  int32_t small_work; /* work items with at most this many wedges use
+                         per-wavefront hash counters; -1 = default */
+  int32_t part_work;  /* wedge budget per work part of a high-priority
+                         pivot; -1 = default */
+  uint32_t flags;     /* DBBC_OPT_* bits */
+} dbbc_options;
+
+/* dbbc_options.flags: record HIP events around every kernel of a count on
+ * the count's stream; read them back with dbbc_last_kernel_times. */
+#define DBBC_OPT_TIME_KERNELS 0x1u
+
+/* One kernel launch of the last timed count and the work it was given. */
+typedef struct {
+  char name[24];     /* "direct", "small", "hash", "reduce", "hub_u", "hub_v", ... */
+  float ms;          /* launch duration between its two HIP events */
+  int64_t wedges;    /* vertex-priority wedges tallied by the launch */
+  int64_t segments;  /* CSR runs (one per expanded edge) it walked */
+  int64_t items;     /* work items (pivots, endpoints or pivot parts) */
+  int64_t macs;      /* int8 multiply-accumulates (dense hub block only) */
+} dbbc_kernel_time;
+
+/* Build a graph handle from an edge list.
+ *   n_u, n_v  : vertices per side (> 0 each, n_u + n_v < 2^30)
+ *   m         : number of input records (>= 0)
+ *   u, v, sign: m int32 / int32 / int8 values each, host memory unless
+ *               DBBC_INPUT_DEVICE; borrowed for the duration of the call
+ *   flags     : DBBC_INPUT_DEVICE | DBBC_DUP_REJECT
+ *   hip_stream: stream for the uploads
+ *   out       : receives the handle (unchanged on error)
+ * The degree-priority relabelling (Definition 3) and the rank-ordered CSR of
+ * both sides are built here and kept on the device until destroy. */
+int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t *u, const int32_t *v,
+                      const int8_t *sign, uint32_t flags, void *hip_stream, dbbc_graph **out);
+
+/* Copy the handle's statistics into *out (host memory). */
+int dbbc_graph_stats(const dbbc_graph *g, dbbc_stats *out);
+
+/* Count balanced and unbalanced butterflies (Algorithm 1 Phases 5 and 6,
+ * Lemma 1; see the file comment).  opt may be NULL.  out_host: host memory,
+ * written after the stream has drained. */
+int dbbc_count(dbbc_graph *g, const dbbc_options *opt, dbbc_counts *out_host, void *hip_stream);
+
+/* Per-vertex counts: for every vertex, the number of balanced and unbalanced
+ * butterflies containing it (the tip-style vertex measure of Section I,
+ * Applications).  Outputs are caller-owned device arrays of n_u (bal_u,
+ * unb_u) or n_v (bal_v, unb_v) int64 values; any may be NULL.  They are
+ * overwritten (not accumulated).  out_host (may be NULL) receives the global
+ * counts of the same pass. */
+int dbbc_count_per_vertex(dbbc_graph *g, int64_t *bal_u, int64_t *bal_v, int64_t *unb_u,
+                          int64_t *unb_v, dbbc_counts *out_host, void *hip_stream);
+
+/* Count k graphs in one persistent launch (batched work queue).  gs: k
+ * handles (k >= 0); out_host: k results in host memory.  The launch sequence
+ * is captured once into a HIP graph per batch shape and replayed. */
+int dbbc_count_batch(dbbc_graph *const *gs, int32_t k, const dbbc_options *opt,
+                     dbbc_counts *out_host, void *hip_stream);
+
+/* Kernel timings of the handle's last dbbc_count made with
+ * DBBC_OPT_TIME_KERNELS.  Writes at most cap entries to out (host memory)
+ * and the number available to *n_out.  Returns DBBC_E_INVALID_ARG if no timed
+ * count has run on the handle. */
+int dbbc_last_kernel_times(const dbbc_graph *g, dbbc_kernel_time *out, int32_t cap,
+                           int32_t *n_out);
+
+/* Free the handle and its device memory (NULL is a no-op). */
+void dbbc_graph_destroy(dbbc_graph *g);
+
+/* Static text for a status code. */
+const char *dbbc_status_string(int status);
+
+/* Detail of the calling thread's last error ("" if none). */
+const char *dbbc_last_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char *dbbc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBBC_H */

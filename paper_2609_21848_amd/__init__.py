@@ -1,0 +1,252 @@
+"""Python binding of libdbbc: exact balanced / unbalanced butterfly counts in
+signed bipartite graphs on AMD MI355X (gfx950).
+
+Every function below marshals arguments for the C entry point of the same
+name in ``include/dbbc.h`` and raises ``DbbcError`` on a non-zero status.
+All counting runs in the HIP kernels of ``libdbbc.so``; this module never
+computes counts itself.  PyTorch is used only for device tensors and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import NamedTuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdbbc.so")
+
+DBBC_OK = 0
+DBBC_E_INVALID_ARG = -1
+DBBC_E_ID_RANGE = -2
+DBBC_E_SIGN = -3
+DBBC_E_DUPLICATE = -4
+DBBC_E_OOM = -5
+DBBC_E_DEVICE = -6
+DBBC_E_TOO_LARGE = -7
+DBBC_E_NO_DEVICE = -8
+
+DBBC_INPUT_DEVICE = 0x1
+DBBC_DUP_REJECT = 0x2
+DBBC_OPT_TIME_KERNELS = 0x1
+
+# every symbol declared in include/dbbc.h
+EXPORTS = (
+    "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_per_vertex",
+    "dbbc_count_batch", "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string",
+    "dbbc_last_error", "dbbc_version",
+)
+
+
+class DbbcError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Counts(NamedTuple):
+    balanced: int
+    unbalanced: int
+    total: int
+    wedges: int
+
+
+class _Counts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("balanced", "unbalanced", "total", "wedges")]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "n_u", "n_v", "m", "dups_dropped", "max_deg_u", "max_deg_v", "device_bytes",
+        "wedges_vp", "pivots_active")]
+
+
+class Options(ctypes.Structure):
+    """Mirror of dbbc_options; -1 leaves a knob at the library default."""
+    _fields_ = [("hub_T", ctypes.c_int32), ("window_L", ctypes.c_int32),
+                ("small_work", ctypes.c_int32), ("part_work", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+    def __init__(self, hub_T=-1, window_L=-1, small_work=-1, part_work=-1, flags=0):
+        super().__init__(hub_T, window_L, small_work, part_work, flags)
+
+
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_float), ("wedges", ctypes.c_int64),
+                ("segments", ctypes.c_int64), ("items", ctypes.c_int64), ("macs", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdbbc.so (built by ``paper_2609_21848_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2609_21848_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.dbbc_graph_create.argtypes = [i32, i32, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    lib.dbbc_graph_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    lib.dbbc_count.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
+    lib.dbbc_count_per_vertex.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(_Counts), vp]
+    lib.dbbc_count_batch.argtypes = [vp, i32, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
+    lib.dbbc_last_kernel_times.argtypes = [vp, ctypes.POINTER(_KernelTime), i32,
+                                           ctypes.POINTER(i32)]
+    lib.dbbc_graph_destroy.argtypes = [vp]
+    lib.dbbc_graph_destroy.restype = None
+    lib.dbbc_status_string.argtypes = [ctypes.c_int]
+    lib.dbbc_status_string.restype = ctypes.c_char_p
+    lib.dbbc_last_error.restype = ctypes.c_char_p
+    lib.dbbc_version.restype = ctypes.c_char_p
+    for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_per_vertex",
+                 "dbbc_count_batch", "dbbc_last_kernel_times"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != DBBC_OK:
+        lib = load()
+        detail = lib.dbbc_last_error().decode() or lib.dbbc_status_string(status).decode()
+        raise DbbcError(status, where, detail)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:  # pragma: no cover
+            pass
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _edge_args(u, v, sign):
+    """(pointers, flags, keepalive) for host NumPy arrays or torch tensors."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(u, torch.Tensor):
+        dev = u.is_cuda
+        u = u.to(torch.int32).contiguous()
+        v = v.to(device=u.device, dtype=torch.int32).contiguous()
+        sign = sign.to(device=u.device, dtype=torch.int8).contiguous()
+        flags = DBBC_INPUT_DEVICE if dev else 0
+        return (u.data_ptr(), v.data_ptr(), sign.data_ptr()), flags, (u, v, sign), int(u.numel())
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    sign = np.ascontiguousarray(sign, dtype=np.int8)
+    return (u.ctypes.data, v.ctypes.data, sign.ctypes.data), 0, (u, v, sign), int(u.shape[0])
+
+
+def dbbc_graph_create(n_u: int, n_v: int, u, v, sign, flags: int = 0, stream=None) -> int:
+    """Build a handle; u, v, sign as NumPy arrays or torch tensors (device
+    tensors set DBBC_INPUT_DEVICE).  Returns the opaque handle."""
+    lib = load()
+    ptrs, f, keep, m = _edge_args(u, v, sign)
+    if len(np.shape(u)) != 1 or len(keep[1]) != m or len(keep[2]) != m:
+        raise ValueError("u, v and sign must be 1-D and of equal length")
+    out = ctypes.c_void_p()
+    _check(lib.dbbc_graph_create(int(n_u), int(n_v), m, *ptrs, int(flags) | f,
+                                 _stream_ptr(stream), ctypes.byref(out)), "dbbc_graph_create")
+    return out.value
+
+
+def dbbc_graph_stats(g: int) -> dict:
+    s = _Stats()
+    _check(load().dbbc_graph_stats(g, ctypes.byref(s)), "dbbc_graph_stats")
+    return {k: int(getattr(s, k)) for k, _ in _Stats._fields_}
+
+
+def dbbc_count(g: int, options: Options | None = None, stream=None) -> Counts:
+    c = _Counts()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_count(g, opt, ctypes.byref(c), _stream_ptr(stream)), "dbbc_count")
+    return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
+
+
+def dbbc_count_per_vertex(g: int, bal_u=None, bal_v=None, unb_u=None, unb_v=None,
+                          stream=None) -> Counts:
+    """Fill caller-owned int64 device tensors (any may be None)."""
+    def p(t):
+        if t is None:
+            return None
+        if t.dtype != __import__("torch").int64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("per-vertex outputs must be contiguous int64 CUDA tensors")
+        return t.data_ptr()
+    c = _Counts()
+    _check(load().dbbc_count_per_vertex(g, p(bal_u), p(bal_v), p(unb_u), p(unb_v),
+                                        ctypes.byref(c), _stream_ptr(stream)),
+           "dbbc_count_per_vertex")
+    return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
+
+
+def dbbc_count_batch(gs, options: Options | None = None, stream=None) -> list:
+    k = len(gs)
+    arr = (ctypes.c_void_p * max(k, 1))(*gs)
+    out = (_Counts * max(k, 1))()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_count_batch(arr, k, opt, out, _stream_ptr(stream)), "dbbc_count_batch")
+    return [Counts(c.balanced, c.unbalanced, c.total, c.wedges) for c in out[:k]]
+
+
+def dbbc_last_kernel_times(g: int) -> list:
+    """Per-kernel records of the last count run with DBBC_OPT_TIME_KERNELS."""
+    buf = (_KernelTime * 16)()
+    n = ctypes.c_int32()
+    _check(load().dbbc_last_kernel_times(g, buf, 16, ctypes.byref(n)), "dbbc_last_kernel_times")
+    return [dict(name=k.name.decode(), ms=float(k.ms), wedges=int(k.wedges),
+                 segments=int(k.segments), items=int(k.items), macs=int(k.macs))
+            for k in buf[:min(n.value, 16)]]
+
+
+def dbbc_graph_destroy(g: int) -> None:
+    if g:
+        load().dbbc_graph_destroy(g)
+
+
+def dbbc_version() -> str:
+    return load().dbbc_version().decode()
+
+
+class Graph:
+    """Owning wrapper: ``with Graph(n_u, n_v, u, v, sign) as g: g.count()``."""
+
+    def __init__(self, n_u, n_v, u, v, sign, flags=0, stream=None):
+        self.n_u, self.n_v = int(n_u), int(n_v)
+        self.handle = dbbc_graph_create(n_u, n_v, u, v, sign, flags, stream)
+
+    def count(self, stream=None, **opts) -> Counts:
+        return dbbc_count(self.handle, Options(**opts) if opts else None, stream)
+
+    def kernel_times(self) -> list:
+        return dbbc_last_kernel_times(self.handle)
+
+    def stats(self) -> dict:
+        return dbbc_graph_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            dbbc_graph_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,438 @@
+// HIP kernels (gfx950) for the vertex-priority wedge tally and the pair
+// reduction of Algorithm 1, Phase 5, with Lemma 1's per-endpoint
+// C(B1,2) + C(B2,2) (and the unbalanced B1 * B2, the total C(B1 + B2, 2)).
+//
+// Work arrives as items (see plan.cpp): each item owns a set of same-side
+// vertex pairs and lists the CSR runs ("segments") whose entries end its
+// wedges.  A wedge is tallied into a per-key counter packed as
+// (asymmetric << 16) | symmetric; an item never has more than 65535
+// segments, and a key gains at most one wedge per segment, so neither half
+// overflows.  After an item's walk its counters are swept: every pair's
+// counts are turned into the three int64 sums, written to a part buffer
+// (items split for load balance), or handed to the dense hub path.
+//
+// Memory layout: CSR entries are 32-bit words (neighbour side rank << 1 |
+// negative bit), rows in priority order, so each segment is a coalesced run.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace dbbc {
+namespace dev {
+
+constexpr int kWave = 64;
+constexpr uint32_t kLong = 32;     // segments this long are walked by the whole wavefront
+constexpr uint32_t kGather = 256;  // per-wavefront staging slots for short segments
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// exclusive prefix sum over the wavefront
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t y = __shfl_up(inc, d, kWave);
+    if (lane_id() >= d) inc += y;
+  }
+  *total = __shfl(inc, kWave - 1, kWave);
+  return inc - x;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Walk up to 64 segments [k0, k1) with one wavefront, calling f(entry, g)
+// once per wedge.  Long segments are read by all lanes in coalesced strides;
+// short ones are staged through gbuf (kGather words of LDS owned by this
+// wavefront) as (index | g << 31) so that lanes read consecutive wedges.
+template <class F>
+__device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
+                                           const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
+  const int lane = lane_id();
+  const uint32_t k = k0 + lane;
+  uint32_t start = 0, len = 0, g = 0;
+  if (k < k1) {
+    const Segment s = segs[k];
+    start = s.start;
+    len = s.len_g >> 1;
+    g = s.len_g & 1u;
+  }
+  uint64_t longm = __ballot(len >= kLong);
+  while (longm) {
+    const int j = __ffsll(static_cast<unsigned long long>(longm)) - 1;
+    longm &= longm - 1;
+    const uint32_t st = __shfl(start, j, kWave);
+    const uint32_t ln = __shfl(len, j, kWave);
+    const uint32_t gg = __shfl(g, j, kWave);
+    for (uint32_t t = lane; t < ln; t += kWave) f(adj[st + t], gg);
+  }
+  if (len >= kLong) len = 0;
+  uint32_t total;
+  const uint32_t excl = wave_excl_scan(len, &total);
+  for (uint32_t done = 0; done < total; done += kGather) {
+    const uint32_t lo = excl > done ? excl : done;
+    const uint32_t hi_a = excl + len, hi_b = done + kGather;
+    const uint32_t hi = hi_a < hi_b ? hi_a : hi_b;
+    for (uint32_t t = lo; t < hi; ++t) gbuf[t - done] = (start + (t - excl)) | (g << 31);
+    wave_sync_lds();
+    const uint32_t cnt = total - done < kGather ? total - done : kGather;
+    for (uint32_t t = lane; t < cnt; t += kWave) {
+      const uint32_t a = gbuf[t];
+      f(adj[a & 0x7fffffffu], a >> 31);
+    }
+    wave_sync_lds();
+  }
+}
+
+struct Sums {
+  int64_t bal = 0, unb = 0, tot = 0;
+  __device__ __forceinline__ void add(uint32_t p, uint32_t n) {
+    const int64_t P = p, N = n;
+    bal += P * (P - 1) / 2 + N * (N - 1) / 2;
+    unb += P * N;
+    tot += (P + N) * (P + N - 1) / 2;
+  }
+};
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+// Add the block's sums to res[0..2] (one atomic per wavefront).
+__device__ __forceinline__ void flush_sums(const Sums& s, unsigned long long* res) {
+  const int64_t b = wave_sum64(s.bal), u = wave_sum64(s.unb), t = wave_sum64(s.tot);
+  if (lane_id() == 0) {
+    if (b) atomicAdd(res + 0, static_cast<unsigned long long>(b));
+    if (u) atomicAdd(res + 1, static_cast<unsigned long long>(u));
+    if (t) atomicAdd(res + 2, static_cast<unsigned long long>(t));
+  }
+}
+
+// Final fate of one pair count of an item.
+__device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, uint32_t n,
+                                     const DevSideConst& sc, Sums& s) {
+  if ((it.flags & kItemHubPairs) && static_cast<int32_t>(key) < sc.T) {
+    sc.hub_pairs[static_cast<size_t>(it.owner) * sc.T + key] =
+        (static_cast<unsigned long long>(n) << 32) | p;
+  } else {
+    s.add(p, n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct-array items: one workgroup per item, counters for keys [0, L) in LDS.
+constexpr int kDirectThreads = 512;
+constexpr int kDirectWaves = kDirectThreads / kWave;
+constexpr int kDirectKeys = 32768;
+
+__global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
+  __shared__ uint32_t cnt[kDirectKeys];
+  __shared__ uint32_t gbuf[kDirectWaves][kGather];
+  __shared__ int32_t item_sh;
+  __shared__ uint32_t range_sh[2];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
+  Sums sums;
+  for (;;) {
+    if (tid == 0) {
+      item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
+      range_sh[0] = kEmpty;
+      range_sh[1] = 0;
+    }
+    __syncthreads();
+    const int32_t i = item_sh;
+    if (i >= a.n_items) break;
+    const Item it = a.items[i];
+    const DevSideConst sc = a.side[it.side];
+    const uint32_t* __restrict__ adj = sc.other_adj;
+    uint32_t kmin = kEmpty, kmax = 0;
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      // key range of the batch: rows are sorted, so the first and last entry
+      // of each segment bound its keys
+      const uint32_t k = k0 + lane_id();
+      if (k < k1) {
+        const Segment s = a.segs[k];
+        const uint32_t len = s.len_g >> 1;
+        const uint32_t f = adj[s.start] >> 1, l = adj[s.start + len - 1] >> 1;
+        kmin = f < kmin ? f : kmin;
+        kmax = l > kmax ? l : kmax;
+      }
+      walk_batch(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+        atomicAdd(&cnt[e >> 1], ((e ^ g) & 1u) ? 0x10000u : 1u);
+      });
+    }
+    atomicMin(&range_sh[0], kmin);
+    atomicMax(&range_sh[1], kmax);
+    __syncthreads();
+    const uint32_t lo = range_sh[0] & ~3u;
+    const uint32_t hi = range_sh[1] + 1;
+    if (it.flags & kItemMultiPart) {
+      // write the part's counters for the whole key window (zeros included)
+      uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
+      for (uint32_t key = it.key_lo + tid; key < static_cast<uint32_t>(it.key_hi); key += kDirectThreads) {
+        dst[key] = cnt[key];
+        cnt[key] = 0;
+      }
+    } else if (lo < hi) {
+      for (uint32_t key = lo + 4 * tid; key < hi; key += 4 * kDirectThreads) {
+        uint4 c4 = *reinterpret_cast<uint4*>(&cnt[key]);
+        if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
+        const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (cv[j]) emit(it, key + j, cv[j] & 0xffffu, cv[j] >> 16, sc, sums);
+        *reinterpret_cast<uint4*>(&cnt[key]) = make_uint4(0, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  flush_sums(sums, a.res);
+}
+
+// ---------------------------------------------------------------------------
+// Small items: one wavefront per item, open-addressing hash counters in LDS
+// sized to the item (at least twice its wedge count).
+constexpr int kSmallThreads = 256;
+constexpr int kSmallWaves = kSmallThreads / kWave;
+constexpr int kSmallSlots = 2048;  // per wavefront, >= 2 * max small work (1024)
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
+  __shared__ uint32_t keys[kSmallWaves][kSmallSlots];
+  __shared__ uint32_t vals[kSmallWaves][kSmallSlots];
+  __shared__ uint32_t gbuf[kSmallWaves][kGather];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  uint32_t* K = keys[wave];
+  uint32_t* Vv = vals[wave];
+  for (int i = lane; i < kSmallSlots; i += kWave) {
+    K[i] = kEmpty;
+    Vv[i] = 0;
+  }
+  wave_sync_lds();
+  Sums sums;
+  for (;;) {
+    int32_t i = 0;
+    if (lane == 0) i = static_cast<int32_t>(atomicAdd(a.queue, 1u));
+    i = __shfl(i, 0, kWave);
+    if (i >= a.n_items) break;
+    const Item it = a.items[i];
+    const DevSideConst sc = a.side[it.side];
+    // table size: a power of two >= 2 * work, at least 64
+    uint32_t work = 0;
+    for (uint32_t k = it.seg_begin + lane; k < it.seg_begin + it.seg_count; k += kWave)
+      work += a.segs[k].len_g >> 1;
+    for (int d = kWave / 2; d > 0; d >>= 1) work += __shfl_xor(work, d, kWave);
+    uint32_t size = 64;
+    while (size < 2 * work) size <<= 1;
+    const uint32_t mask = size - 1;
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      walk_batch(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+        const uint32_t key = e >> 1;
+        const uint32_t inc = ((e ^ g) & 1u) ? 0x10000u : 1u;
+        uint32_t h = mix32(key) & mask;
+        for (uint32_t probe = 0;; ++probe) {
+          if (probe > mask) {  // full table: cannot happen at load <= 1/2
+            atomicOr(a.res + kResError, kErrHashFull);
+            break;
+          }
+          uint32_t cur = K[h];
+          if (cur == kEmpty) {
+            cur = atomicCAS(&K[h], kEmpty, key);
+            if (cur == kEmpty) cur = key;
+          }
+          if (cur == key) {
+            atomicAdd(&Vv[h], inc);
+            break;
+          }
+          h = (h + 1) & mask;
+        }
+      });
+    }
+    wave_sync_lds();
+    for (uint32_t h = lane; h < size; h += kWave) {
+      const uint32_t key = K[h];
+      if (key != kEmpty) {
+        const uint32_t c = Vv[h];
+        emit(it, key, c & 0xffffu, c >> 16, sc, sums);
+        K[h] = kEmpty;
+        Vv[h] = 0;
+      }
+    }
+    wave_sync_lds();
+  }
+  flush_sums(sums, a.res);
+}
+
+// ---------------------------------------------------------------------------
+// Large items below the window: one workgroup per item, a shared hash table
+// with 32-bit symmetric and asymmetric counts; items with more distinct
+// endpoints than fit are walked once per key-hash partition.
+constexpr int kHashThreads = 512;
+constexpr int kHashWaves = kHashThreads / kWave;
+constexpr int kHashSlots = 8192;
+
+__global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
+  __shared__ uint32_t keys[kHashSlots];
+  __shared__ unsigned long long vals[kHashSlots];
+  __shared__ uint32_t gbuf[kHashWaves][kGather];
+  __shared__ int32_t item_sh;
+  __shared__ uint32_t work_sh;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  for (int i = tid; i < kHashSlots; i += kHashThreads) {
+    keys[i] = kEmpty;
+    vals[i] = 0;
+  }
+  Sums sums;
+  for (;;) {
+    if (tid == 0) {
+      item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
+      work_sh = 0;
+    }
+    __syncthreads();
+    const int32_t i = item_sh;
+    if (i >= a.n_items) break;
+    const Item it = a.items[i];
+    const DevSideConst sc = a.side[it.side];
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    uint32_t w = 0;
+    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kHashThreads) w += a.segs[k].len_g >> 1;
+    atomicAdd(&work_sh, w);
+    __syncthreads();
+    const uint32_t work = work_sh;
+    // about kHashSlots / 4 distinct keys per pass at most on average
+    const uint32_t passes = (work + kHashSlots / 4 - 1) / (kHashSlots / 4);
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+      for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
+        const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+        walk_batch(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+          const uint32_t key = e >> 1;
+          const uint32_t hk = mix32(key);
+          if (passes > 1 && (hk >> 16) % passes != pass) return;
+          const unsigned long long inc = ((e ^ g) & 1u) ? (1ull << 32) : 1ull;
+          uint32_t h = hk & (kHashSlots - 1);
+          for (uint32_t probe = 0;; ++probe) {
+            if (probe >= static_cast<uint32_t>(kHashSlots)) {  // full table
+              atomicOr(a.res + kResError, kErrHashFull);
+              break;
+            }
+            uint32_t cur = keys[h];
+            if (cur == kEmpty) {
+              cur = atomicCAS(&keys[h], kEmpty, key);
+              if (cur == kEmpty) cur = key;
+            }
+            if (cur == key) {
+              atomicAdd(&vals[h], inc);
+              break;
+            }
+            h = (h + 1) & (kHashSlots - 1);
+          }
+        });
+      }
+      __syncthreads();
+      for (int h = tid; h < kHashSlots; h += kHashThreads) {
+        const uint32_t key = keys[h];
+        if (key != kEmpty) {
+          const unsigned long long c = vals[h];
+          emit(it, key, static_cast<uint32_t>(c), static_cast<uint32_t>(c >> 32), sc, sums);
+          keys[h] = kEmpty;
+          vals[h] = 0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  flush_sums(sums, a.res);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-part pivots: add the parts' packed counters key by key, then take
+// C(., 2) of the combined counts.
+constexpr int kReduceThreads = 256;
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
+  Sums sums;
+  for (int32_t r = blockIdx.x; r < a.n_reduces; r += gridDim.x) {
+    const Reduce rd = a.reduces[r];
+    const DevSideConst sc = a.side[rd.side];
+    Item it{};
+    it.owner = rd.owner;
+    it.flags = rd.flags;
+    for (int32_t key = rd.key_lo + threadIdx.x; key < rd.key_hi; key += kReduceThreads) {
+      uint32_t p = 0, n = 0;
+      for (int32_t j = 0; j < rd.n_parts; ++j) {
+        const uint32_t c = a.acc[static_cast<size_t>(rd.acc_slot + j) * a.acc_width + key];
+        p += c & 0xffffu;
+        n += c >> 16;
+      }
+      if (p | n) emit(it, static_cast<uint32_t>(key), p, n, sc, sums);
+    }
+  }
+  flush_sums(sums, a.res);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+}  // namespace dev
+
+// ---- launchers ------------------------------------------------------------------
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(dev::k_fill_u64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct(const DirectArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_direct, dim3(grid), dim3(dev::kDirectThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_small(const SmallArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_small, dim3(grid), dim3(dev::kSmallThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_hash, dim3(grid), dim3(dev::kHashThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st) {
+  if (a.n_reduces == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_reduce, dim3(grid), dim3(dev::kReduceThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace dbbc

@@ -1,0 +1,120 @@
+// Internal types of libdbbc: the host-side graph, the counting plan and the
+// device-resident handle.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dbbc.h"
+
+namespace dbbc {
+
+// One side of the bipartite graph in priority order.  Vertex "side rank"
+// sr in [0, n) is the position of the vertex among its own side in the order
+// of Definition 3 (sr 0 = highest priority).  Row sr of the CSR lists the
+// neighbours on the other side, as packed words (nbr_sr << 1) | neg, sorted
+// by nbr_sr (hence by priority).
+struct HostSide {
+  int32_t n = 0;
+  std::vector<uint32_t> off;   // n + 1
+  std::vector<uint32_t> adj;   // m packed entries
+  std::vector<int32_t> rev;    // per entry e of row x: index of x inside the row of adj[e] >> 1
+  std::vector<int32_t> cut;    // per row: number of neighbours of higher priority
+  std::vector<int32_t> grank;  // side rank -> rank in the merged order of both sides
+  std::vector<int32_t> orig;   // side rank -> input id
+  int64_t max_deg = 0;
+};
+
+struct HostGraph {
+  int32_t n_u = 0, n_v = 0;
+  int64_t m = 0;
+  int64_t dups_dropped = 0;
+  int64_t wedges_vp = 0;
+  int64_t pivots_active = 0;
+  HostSide side[2];  // 0 = U, 1 = V
+};
+
+// Build the relabelled CSR pair from an edge list (host memory).  Returns a
+// DBBC status and fills err on failure.
+int build_host_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
+                     const int8_t* sign, uint32_t flags, HostGraph& g, std::string& err);
+
+// ---- counting plan -----------------------------------------------------------
+
+// A segment is a run of consecutive CSR entries of one row, all of which end
+// a wedge of the same work item; g is the negative-bit of the item's first
+// edge of those wedges (pivot-mid edge, or tail-mid edge for reverse items).
+struct Segment {
+  uint32_t start;   // absolute index into the other side's adj array
+  uint32_t len_g;   // (len << 1) | g
+};
+
+enum ItemKind : uint8_t {
+  kForwardWindow = 0,  // pivot inside the window, endpoints inside the window
+  kReverseTail = 1,    // endpoint below the window, counted from the endpoint
+  kForwardTail = 2,    // pivot below the window, counted from the pivot
+};
+
+// Flags of an item.
+enum : uint32_t {
+  kItemMultiPart = 1u,  // partial counts go to a global accumulator
+  kItemHubPairs = 2u,   // keys below hub_T are flushed to the hub-pair buffer
+};
+
+struct Item {
+  uint32_t seg_begin;
+  uint32_t seg_count;
+  int32_t owner;      // side rank of the pivot (forward) or endpoint (reverse)
+  int32_t key_lo;     // keys counted lie in [key_lo, key_hi)
+  int32_t key_hi;
+  int32_t acc_slot;   // multi-part accumulator slot (or -1)
+  uint32_t flags;
+  uint32_t side;      // side of the owner and of the keys (0 = U, 1 = V)
+};
+
+struct Reduce {       // one multi-part accumulator to reduce after its parts
+  int32_t acc_slot;   // first slot; the parts use acc_slot .. acc_slot + n_parts - 1
+  int32_t n_parts;
+  int32_t owner;
+  int32_t key_lo, key_hi;
+  uint32_t flags;
+  uint32_t side;
+};
+
+struct PlanParams {
+  int32_t hub_T = 0;
+  int32_t window_L = 0;
+  int32_t small_work = 0;
+  int32_t part_work = 0;
+  bool operator==(const PlanParams& o) const {
+    return hub_T == o.hub_T && window_L == o.window_L && small_work == o.small_work &&
+           part_work == o.part_work;
+  }
+};
+
+struct HostPlan {
+  PlanParams p;
+  int32_t L[2] = {0, 0};  // window per side
+  int32_t T[2] = {0, 0};  // hub block rows per side (pairs on that side)
+  std::vector<Segment> segs;
+  std::vector<Item> small_items;   // per-wavefront hash counters
+  std::vector<Item> direct_items;  // workgroup direct arrays over [0, L)
+  std::vector<Item> hash_items;    // workgroup hash counters, large tail pivots
+  std::vector<Reduce> reduces;
+  int32_t acc_slots = 0;
+  int32_t acc_width = 0;           // max window over the sides
+  // per sparse kernel (0 = direct, 1 = small, 2 = hash): wedges, segments, items
+  int64_t k_wedges[3] = {0, 0, 0};
+  int64_t k_segs[3] = {0, 0, 0};
+  int64_t w_sparse = 0;            // wedges tallied by the sparse kernels
+  int64_t w_skipped = 0;           // wedges of items that cannot contribute
+  // dense hub block per side s (pairs on s): row-major int8 matrices
+  // [T[s] x T[1-s]] of signs (B) and of signs masked to lower-priority mids (Bm)
+  std::vector<int8_t> hub_B[2], hub_Bm[2];
+};
+
+PlanParams default_params(const HostGraph& g);
+int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err);
+
+}  // namespace dbbc

@@ -1,0 +1,90 @@
+// Kernel argument blocks and launchers shared by the host code and the HIP
+// kernels of libdbbc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace dbbc {
+
+// Layout of the int64 result block shared by all kernels of a count.
+enum : int {
+  kResBalanced = 0,
+  kResUnbalanced = 1,
+  kResTotal = 2,
+  kResDenseWedges = 3,
+  kResError = 4,  // bit set of kErr* raised by a kernel
+};
+enum : unsigned long long {
+  kErrHashFull = 1ull,
+};
+
+// Per side s (the side of an item's keys): where the item's segments point
+// and where hub-pair partial counts go.
+struct DevSideConst {
+  const uint32_t* other_adj;     // CSR entries of the other side (entries are side-s ranks)
+  unsigned long long* hub_pairs; // [T x T] packed (asym << 32) | sym, or null
+  int32_t T;                     // hub rows of side s (0 = no dense path)
+  int32_t pad;
+};
+
+struct DirectArgs {
+  const Item* items;
+  const Segment* segs;
+  DevSideConst side[2];
+  uint32_t* queue;
+  uint32_t* acc;
+  unsigned long long* res;
+  int32_t n_items;
+  int32_t acc_width;
+};
+
+struct SmallArgs {
+  const Item* items;
+  const Segment* segs;
+  DevSideConst side[2];
+  uint32_t* queue;
+  unsigned long long* res;
+  int32_t n_items;
+};
+
+struct HashArgs {
+  const Item* items;
+  const Segment* segs;
+  DevSideConst side[2];
+  uint32_t* queue;
+  unsigned long long* res;
+  int32_t n_items;
+};
+
+struct ReduceArgs {
+  const Reduce* reduces;
+  DevSideConst side[2];
+  const uint32_t* acc;
+  unsigned long long* res;
+  int32_t n_reduces;
+  int32_t acc_width;
+};
+
+// Dense hub block of one side: X = |Bm| |B|^T and Y = Bm B^T over the T_other
+// mids, combined with the sparse hub-pair partials, reduced to res.
+struct HubArgs {
+  const int8_t* Bm;              // [T x K] row-major, K = padded mid count
+  const int8_t* B;               // [T x K]
+  const unsigned long long* hub_pairs;  // [T x T] sparse partials
+  unsigned long long* res;       // res[0..2] sums, res[3] dense wedges
+  int32_t T;                     // rows (pairs side)
+  int32_t K;                     // padded contraction length (multiple of 64)
+};
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_direct(const DirectArgs& a, int grid, hipStream_t st);
+hipError_t launch_small(const SmallArgs& a, int grid, hipStream_t st);
+hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st);
+hipError_t launch_hub(const HubArgs& a, hipStream_t st);
+
+}  // namespace dbbc

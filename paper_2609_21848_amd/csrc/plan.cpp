@@ -1,0 +1,254 @@
+// Counting plan: splits the vertex-priority wedges of Algorithm 1 (Phase 5)
+// into work items whose counters fit on chip, and lays out the dense hub
+// block for the matrix-core path.
+//
+// Every VP wedge x - y - w (y and w of lower priority than x, w on x's side)
+// belongs to exactly one same-side pair (x, w), and Lemma 1 needs all wedges
+// of a pair in one place before C(., 2) is taken.  With L the window size of
+// the side (its L highest-priority vertices), each pair is owned by one item:
+//   kForwardWindow  sr(w) < L        : at pivot x, keys w in (x, L)
+//   kReverseTail    sr(x) < L <= sr(w): at endpoint w, keys x in [0, L);
+//                                       the same wedges walked from w: for
+//                                       each neighbour y of w, the entries of
+//                                       row y that rank above both L and y
+//   kForwardTail    sr(x) >= L       : at pivot x, keys w in (x, n)
+// Inside the window, the pairs of the hub block (x, w < T, mid y < T on the
+// other side) are counted by the dense path; the forward items skip those
+// wedges and leave their other hub-pair wedges in a pair buffer that the
+// dense path adds before taking C(., 2).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace dbbc {
+
+PlanParams default_params(const HostGraph& g) {
+  PlanParams p;
+  p.window_L = 32768;
+  p.hub_T = 0;
+  // The dense block pays off when the top of both sides is dense; keep it off
+  // for small graphs where its fixed cost dominates.
+  (void)g;
+  p.small_work = 1024;
+  p.part_work = 1 << 20;
+  return p;
+}
+
+namespace {
+
+struct Builder {
+  const HostGraph& g;
+  HostPlan& plan;
+  std::vector<Item> big_direct;  // before splitting into parts
+
+  void add_item(std::vector<Item>& dst, uint32_t seg_begin, int64_t work, int32_t owner,
+                int32_t key_lo, int32_t key_hi, uint32_t flags, uint32_t side) {
+    Item it{};
+    it.seg_begin = seg_begin;
+    it.seg_count = static_cast<uint32_t>(plan.segs.size() - seg_begin);
+    it.owner = owner;
+    it.key_lo = key_lo;
+    it.key_hi = key_hi;
+    it.acc_slot = -1;
+    it.flags = flags;
+    it.side = side;
+    (void)work;
+    dst.push_back(it);
+  }
+};
+
+int64_t item_work(const HostPlan& plan, const Item& it) {
+  int64_t w = 0;
+  for (uint32_t k = 0; k < it.seg_count; ++k) w += plan.segs[it.seg_begin + k].len_g >> 1;
+  return w;
+}
+
+}  // namespace
+
+int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err) {
+  if (p.window_L < 256 || p.window_L > 32768 || p.window_L % 256 != 0) {
+    err = "window_L must be a multiple of 256 in [256, 32768]";
+    return DBBC_E_INVALID_ARG;
+  }
+  if (p.hub_T < 0 || p.hub_T > 16384 || p.hub_T % 128 != 0) {
+    err = "hub_T must be 0 or a multiple of 128 up to 16384";
+    return DBBC_E_INVALID_ARG;
+  }
+  if (p.hub_T > p.window_L) {
+    err = "hub_T must not exceed window_L";
+    return DBBC_E_INVALID_ARG;
+  }
+  if (p.small_work < 2 || p.small_work > 1024 || p.part_work < 4096) {
+    err = "small_work must be in [2, 1024] and part_work at least 4096";
+    return DBBC_E_INVALID_ARG;
+  }
+  plan = HostPlan();
+  plan.p = p;
+  for (int s = 0; s < 2; ++s) {
+    plan.L[s] = std::min<int32_t>(p.window_L, g.side[s].n);
+    // the dense block is tiled by 128 rows
+    plan.T[s] = std::min<int32_t>(p.hub_T, g.side[s].n / 128 * 128);
+  }
+  // The dense path needs a block on both sides of the pair.
+  if (plan.T[0] == 0 || plan.T[1] == 0) plan.T[0] = plan.T[1] = 0;
+
+  Builder B{g, plan, {}};
+  std::vector<Item> big_direct;
+
+  for (int s = 0; s < 2; ++s) {
+    const HostSide& S = g.side[s];
+    const HostSide& O = g.side[1 - s];
+    const int32_t L = plan.L[s];
+    const int32_t T = plan.T[s];
+    const int32_t TO = plan.T[1 - s];  // hub rows of the other side (mids)
+    // Per row y of the other side: entries below the window / below the
+    // hub block (keys on side s are the row's entries).
+    std::vector<int32_t> split(O.n), splitT(O.n);
+    for (int32_t y = 0; y < O.n; ++y) {
+      const uint32_t* b = O.adj.data() + O.off[y];
+      const uint32_t* e = O.adj.data() + O.off[y + 1];
+      split[y] = static_cast<int32_t>(
+          std::lower_bound(b, e, static_cast<uint32_t>(L) << 1) - b);
+      splitT[y] = static_cast<int32_t>(
+          std::lower_bound(b, e, static_cast<uint32_t>(T) << 1) - b);
+    }
+
+    auto place = [&](uint32_t seg_begin, int32_t owner, int32_t key_lo, int32_t key_hi,
+                     uint32_t flags, ItemKind kind) {
+      uint32_t nseg = static_cast<uint32_t>(plan.segs.size() - seg_begin);
+      int64_t work = 0;
+      for (uint32_t k = 0; k < nseg; ++k) work += plan.segs[seg_begin + k].len_g >> 1;
+      // With a single segment every pair of the item has at most one wedge
+      // and adds nothing -- unless the pair's count is completed by the
+      // dense hub block.
+      if (nseg == 0 || (nseg < 2 && !(flags & kItemHubPairs))) {
+        plan.w_skipped += work;
+        plan.segs.resize(seg_begin);
+        return;
+      }
+      plan.w_sparse += work;
+      if (work <= p.small_work) {
+        B.add_item(plan.small_items, seg_begin, work, owner, key_lo, key_hi, flags, s);
+      } else if (kind == kForwardTail) {
+        B.add_item(plan.hash_items, seg_begin, work, owner, key_lo, key_hi, flags, s);
+      } else {
+        B.add_item(big_direct, seg_begin, work, owner, key_lo, key_hi, flags, s);
+      }
+      (void)kind;
+    };
+
+    // Forward items: pivots x of side s.
+    for (int32_t x = 0; x < S.n; ++x) {
+      const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+      const bool in_window = x < L;
+      const bool hub = x < T;
+      for (uint32_t e = S.off[x] + S.cut[x]; e < S.off[x + 1]; ++e) {
+        const uint32_t y = S.adj[e] >> 1;
+        const uint32_t gbit = S.adj[e] & 1u;
+        uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
+        uint32_t end = in_window ? O.off[y] + static_cast<uint32_t>(split[y]) : O.off[y + 1];
+        if (hub && static_cast<int32_t>(y) < TO)
+          start = std::max(start, O.off[y] + static_cast<uint32_t>(splitT[y]));
+        if (end > start) plan.segs.push_back(Segment{start, ((end - start) << 1) | gbit});
+      }
+      if (in_window) {
+        place(seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
+      } else {
+        place(seg_begin, x, x + 1, S.n, 0u, kForwardTail);
+      }
+    }
+    // Reverse items: endpoints w of side s below the window.
+    for (int32_t w = L; w < S.n; ++w) {
+      const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+      for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
+        const uint32_t y = S.adj[e] >> 1;
+        const uint32_t gbit = S.adj[e] & 1u;
+        const int32_t len = std::min(split[y], O.cut[y]);
+        if (len > 0) plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(len) << 1) | gbit});
+      }
+      place(seg_begin, w, 0, L, 0u, kReverseTail);
+    }
+
+    // Dense hub block of this side: B[x][y] for x < T, y < TO.
+    if (T > 0) {
+      auto& Bs = plan.hub_B[s];
+      auto& Bm = plan.hub_Bm[s];
+      Bs.assign(static_cast<size_t>(T) * TO, 0);
+      Bm.assign(static_cast<size_t>(T) * TO, 0);
+      for (int32_t x = 0; x < T; ++x) {
+        for (uint32_t e = S.off[x]; e < S.off[x + 1]; ++e) {
+          const int32_t y = static_cast<int32_t>(S.adj[e] >> 1);
+          if (y >= TO) break;  // row sorted by y
+          const int8_t sg = (S.adj[e] & 1u) ? int8_t(-1) : int8_t(1);
+          Bs[static_cast<size_t>(x) * TO + y] = sg;
+          if (O.grank[y] > S.grank[x]) Bm[static_cast<size_t>(x) * TO + y] = sg;
+        }
+      }
+    }
+  }
+
+  // Split heavy direct items into parts (work budget, and fewer than 2^16
+  // segments so that per-part counts fit 16 bits), heaviest first.
+  std::vector<std::pair<int64_t, size_t>> order;
+  order.reserve(big_direct.size());
+  for (size_t i = 0; i < big_direct.size(); ++i) order.push_back({item_work(plan, big_direct[i]), i});
+  std::sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  int32_t width = 0;
+  for (int s = 0; s < 2; ++s) width = std::max(width, plan.L[s]);
+  plan.acc_width = width;
+  std::vector<Item> parts;
+  for (auto& [work, i] : order) {
+    const Item& it = big_direct[i];
+    if (work <= p.part_work && it.seg_count < 65536) {
+      plan.direct_items.push_back(it);
+      continue;
+    }
+    int32_t first_slot = plan.acc_slots;
+    uint32_t k = 0;
+    while (k < it.seg_count) {
+      Item part = it;
+      part.seg_begin = it.seg_begin + k;
+      int64_t pw = 0;
+      uint32_t c = 0;
+      while (k + c < it.seg_count && c < 65535) {
+        int64_t l = plan.segs[it.seg_begin + k + c].len_g >> 1;
+        if (c > 0 && pw + l > p.part_work) break;
+        pw += l;
+        ++c;
+      }
+      part.seg_count = c;
+      part.flags = it.flags | kItemMultiPart;
+      part.acc_slot = plan.acc_slots++;
+      parts.push_back(part);
+      k += c;
+    }
+    Reduce r{};
+    r.acc_slot = first_slot;
+    r.n_parts = plan.acc_slots - first_slot;
+    r.owner = it.owner;
+    r.key_lo = it.key_lo;
+    r.key_hi = it.key_hi;
+    r.flags = it.flags;
+    r.side = it.side;
+    plan.reduces.push_back(r);
+  }
+  auto tally = [&](int k, const std::vector<Item>& v) {
+    for (const Item& it : v) {
+      plan.k_wedges[k] += item_work(plan, it);
+      plan.k_segs[k] += it.seg_count;
+    }
+  };
+  tally(0, parts);
+  tally(0, plan.direct_items);
+  tally(1, plan.small_items);
+  tally(2, plan.hash_items);
+  // parts first (they are the heaviest), then the single-part items
+  parts.insert(parts.end(), plan.direct_items.begin(), plan.direct_items.end());
+  plan.direct_items.swap(parts);
+  // heavy tail pivots first as well
+  std::stable_sort(plan.hash_items.begin(), plan.hash_items.end(),
+                   [&](const Item& a, const Item& b) { return item_work(plan, a) > item_work(plan, b); });
+  return DBBC_OK;
+}
+
+}  // namespace dbbc

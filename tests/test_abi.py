@@ -1,0 +1,72 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/dbbc.h declares, and rejects bad arguments before touching a device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2609_21848_amd as dbbc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^[A-Za-z_][\w \*]*?\b(dbbc_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = dbbc.load()
+    declared = _declared()
+    assert declared == set(dbbc.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings():
+    assert dbbc.dbbc_version() == "0.1.0"
+    lib = dbbc.load()
+    for code, word in [(0, "ok"), (-2, "range"), (-3, "sign"), (-4, "duplicate"), (-8, "gfx950")]:
+        assert word in lib.dbbc_status_string(code).decode()
+
+
+def _create(n_u, n_v, u, v, s, flags=0):
+    lib = dbbc.load()
+    out = ctypes.c_void_p()
+    u = np.asarray(u, np.int32)
+    v = np.asarray(v, np.int32)
+    s = np.asarray(s, np.int8)
+    rc = lib.dbbc_graph_create(n_u, n_v, len(u), u.ctypes.data, v.ctypes.data, s.ctypes.data,
+                               flags, None, ctypes.byref(out))
+    return rc, out.value, lib.dbbc_last_error().decode()
+
+
+def test_validation_errors_need_no_device():
+    assert _create(2, 2, [0, 2], [0, 1], [1, 1])[0] == dbbc.DBBC_E_ID_RANGE
+    assert _create(2, 2, [0, 1], [0, -1], [1, 1])[0] == dbbc.DBBC_E_ID_RANGE
+    rc, h, msg = _create(2, 2, [0, 1], [0, 1], [1, 0])
+    assert rc == dbbc.DBBC_E_SIGN and h is None and "sign" in msg
+    rc, _, msg = _create(2, 2, [0, 1, 0], [0, 1, 0], [1, 1, -1], dbbc.DBBC_DUP_REJECT)
+    assert rc == dbbc.DBBC_E_DUPLICATE and "duplicate" in msg
+    assert _create(0, 2, [], [], [])[0] == dbbc.DBBC_E_INVALID_ARG
+    assert _create(2**29, 2**29, [0], [0], [1])[0] == dbbc.DBBC_E_TOO_LARGE
+    lib = dbbc.load()
+    assert lib.dbbc_graph_create(2, 2, 1, None, None, None, 0, None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create(2, 2, 0, None, None, None, 0x80, None,
+                                 ctypes.byref(ctypes.c_void_p())) == dbbc.DBBC_E_INVALID_ARG
+    # NULL handles are rejected or ignored
+    assert lib.dbbc_count(None, None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    lib.dbbc_graph_destroy(None)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    monkeypatch.setattr(dbbc, "_lib", None)
+    with pytest.raises(ImportError):
+        dbbc.load(str(tmp_path / "nope.so"))

@@ -1,0 +1,83 @@
+"""CPU checks of the library's host logic: the priority relabel, the CSR pair
+and the counting plan, walked item by item in plain loops by a test harness
+(tests/native/plan_emul.cpp) and compared with the oracle."""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import vp_counts
+from synth import chung_lu_graph, config_graph, uniform_graph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2609_21848_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def emul(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("emul") / "plan_emul.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", so,
+                           os.path.join(ROOT, "tests", "native", "plan_emul.cpp"),
+                           os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
+    lib = ctypes.CDLL(so)
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, p]
+
+    def run(g, T=-1, L=-1, sw=-1, pw=-1):
+        out = np.zeros(12, np.int64)
+        rc = lib.plan_emulate(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
+                              g.sign.ctypes.data, T, L, sw, pw, out.ctypes.data)
+        assert rc == 0, rc
+        return out
+    return run
+
+
+CONFIGS = [(0, 256, 2, 4096), (128, 256, 64, 4096), (256, 512, 1024, 8192),
+           (0, 32768, 1024, 1 << 20), (256, 1024, 16, 4096)]
+
+
+def _check(o, r):
+    assert (o[0], o[1], o[2]) == (r.balanced, r.unbalanced, r.total)
+    assert o[3] == r.wedges                      # closed-form W_VP of the library
+    assert o[4] + o[5] + o[6] == o[3]            # sparse + skipped + dense = W_VP
+    assert o[7] == o[4]                          # every planned wedge walked once
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_plan_partition_matches_oracle(emul, seed):
+    rng = np.random.default_rng(seed)
+    g = chung_lu_graph(int(rng.integers(300, 3000)), int(rng.integers(300, 3000)),
+                       int(rng.integers(1000, 30000)), 2.0, 1.9, 0.4, seed=seed)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+    for cfg in CONFIGS:
+        _check(emul(g, *cfg), r)
+
+
+def test_plan_on_tiny_workload(emul):
+    g = config_graph("tiny")
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+    for cfg in CONFIGS:
+        _check(emul(g, *cfg), r)
+
+
+def test_plan_on_small_and_degenerate_graphs(emul):
+    for seed in range(40):
+        rng = np.random.default_rng(1000 + seed)
+        n_u, n_v = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+        g = uniform_graph(n_u, n_v, int(rng.integers(0, n_u * n_v + 1)), 0.5, seed=seed)
+        r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+        for cfg in [(0, 256, 2, 4096), (0, 256, 1024, 4096)]:
+            _check(emul(g, *cfg), r)
+
+
+def test_hub_block_on_dense_graph(emul):
+    # a dense graph where the hub block covers most pairs
+    g = chung_lu_graph(600, 500, 60000, 2.5, 2.5, 0.3, seed=7)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+    for cfg in [(256, 256, 64, 4096), (384, 512, 2, 4096), (0, 512, 1024, 4096)]:
+        o = emul(g, *cfg)
+        _check(o, r)
+    assert emul(g, 256, 256, 64, 4096)[6] > 0
