@@ -88,6 +88,9 @@ typedef struct {
   int32_t window_L; /* per side, the L highest-priority vertices whose pair
                        counts are kept in on-chip direct arrays; a multiple
                        of 256 in [256, 32768]; -1 = default */
+  int32_t reverse_L; /* per side, the R highest-priority vertices counted
+                        from the low-priority end of their pairs; a multiple
+                        of 64 in [64, 4096], at most window_L; -1 = default */
   int32_t small_work; /* work items with at most this many wedges use
                          per-wavefront hash counters; -1 = default */
   int32_t part_work;  /* wedge budget per work part of a high-priority

@@ -87,13 +87,13 @@ constexpr size_t kCtlWords = 16;
 
 struct DevPlan {
   dbbc::HostPlan host;
-  DevBuf segs, small_items, direct_items, hash_items, reduces, acc;
+  DevBuf segs, small_items, direct_items, hash_items, reverse_items, reduces, acc;
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
   bool valid = false;
   size_t bytes() const {
     size_t b = segs.bytes + small_items.bytes + direct_items.bytes + hash_items.bytes +
-               reduces.bytes + acc.bytes;
+               reverse_items.bytes + reduces.bytes + acc.bytes;
     for (int s = 0; s < 2; ++s) b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes;
     return b;
   }
@@ -141,6 +141,7 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   HIP_TRY(upload(d.small_items, hp.small_items, st));
   HIP_TRY(upload(d.direct_items, hp.direct_items, st));
   HIP_TRY(upload(d.hash_items, hp.hash_items, st));
+  HIP_TRY(upload(d.reverse_items, hp.reverse_items, st));
   HIP_TRY(upload(d.reduces, hp.reduces, st));
   HIP_TRY(d.acc.alloc(static_cast<size_t>(hp.acc_slots) * hp.acc_width * sizeof(uint32_t)));
   for (int s = 0; s < 2; ++s) {
@@ -181,6 +182,8 @@ int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& 
   if (opt->flags & ~DBBC_OPT_TIME_KERNELS) return fail(DBBC_E_INVALID_ARG, "unknown dbbc_options flag");
   if (opt->hub_T >= 0) p.hub_T = opt->hub_T;
   if (opt->window_L >= 0) p.window_L = opt->window_L;
+  if (opt->reverse_L >= 0) p.reverse_L = opt->reverse_L;
+  if (opt->window_L >= 0 && opt->reverse_L < 0) p.reverse_L = std::min(p.reverse_L, p.window_L);
   if (opt->small_work >= 0) p.small_work = opt->small_work;
   if (opt->part_work >= 0) p.part_work = opt->part_work;
   if (p.hub_T > p.window_L) p.hub_T = std::min(p.hub_T, p.window_L);
@@ -252,6 +255,19 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     a.acc_width = hp.acc_width;
     RC_TRY(tm.begin("direct", hp.k_wedges[0], hp.k_segs[0], a.n_items, 0));
     HIP_TRY(dbbc::launch_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+    RC_TRY(tm.end());
+  }
+  {
+    dbbc::SmallArgs a{};
+    a.items = d.reverse_items.as<dbbc::Item>();
+    a.segs = d.segs.as<dbbc::Segment>();
+    a.side[0] = side[0];
+    a.side[1] = side[1];
+    a.queue = queues + 3;
+    a.res = ctl;
+    a.n_items = static_cast<int32_t>(hp.reverse_items.size());
+    RC_TRY(tm.begin("reverse", hp.k_wedges[3], hp.k_segs[3], a.n_items, 0));
+    HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 7) / 8)), st));
     RC_TRY(tm.end());
   }
   {
@@ -377,7 +393,12 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, con
   }
   g->dev = di;
   for (int s = 0; s < 2; ++s) {
-    HIP_TRY(upload(g->adj[s], g->host.side[s].adj, st));
+    std::vector<uint32_t>& adj = g->host.side[s].adj;
+    const size_t m_side = adj.size();
+    adj.resize(m_side + dbbc::kAdjPad, 0u);  // padding for 16-byte loads
+    hipError_t e = upload(g->adj[s], adj, st);
+    adj.resize(m_side);
+    HIP_TRY(e);
     HIP_TRY(upload(g->off[s], g->host.side[s].off, st));
   }
   HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));

@@ -13,6 +13,8 @@
 //
 // Memory layout: CSR entries are 32-bit words (neighbour side rank << 1 |
 // negative bit), rows in priority order, so each segment is a coalesced run.
+// The entry arrays are padded by kAdjPad words so that 16-byte loads at the
+// end of a run stay inside the allocation.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -24,11 +26,16 @@ namespace dbbc {
 namespace dev {
 
 constexpr int kWave = 64;
-constexpr uint32_t kLong = 32;     // segments this long are walked by the whole wavefront
+constexpr uint32_t kLong = 64;     // segments this long are streamed by the whole wavefront
+constexpr uint32_t kChunk = 256;   // entries per wavefront 16-byte load (64 lanes x 4)
 constexpr uint32_t kGather = 256;  // per-wavefront staging slots for short segments
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int j) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), j));
+}
 
 // exclusive prefix sum over the wavefront
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
@@ -48,10 +55,15 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Walk up to 64 segments [k0, k1) with one wavefront, calling f(entry, g)
-// once per wedge.  Long segments are read by all lanes in coalesced strides;
-// short ones are staged through gbuf (kGather words of LDS owned by this
-// wavefront) as (index | g << 31) so that lanes read consecutive wedges.
-template <class F>
+// once per wedge.
+//  - Segments of at least kLong entries are consumed as a stream of
+//    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
+//    chunk, U chunks are in flight per lane, and a chunk's out-of-segment
+//    words are masked.  The chunk loop is wavefront-uniform.
+//  - Shorter segments are staged through gbuf (kGather words of LDS owned by
+//    this wavefront) as (index | g << 31) so that lanes read consecutive
+//    wedges, again U loads in flight per lane.
+template <int U, class F>
 __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
                                            const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
   const int lane = lane_id();
@@ -64,13 +76,46 @@ __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uin
     g = s.len_g & 1u;
   }
   uint64_t longm = __ballot(len >= kLong);
-  while (longm) {
-    const int j = __ffsll(static_cast<unsigned long long>(longm)) - 1;
-    longm &= longm - 1;
-    const uint32_t st = __shfl(start, j, kWave);
-    const uint32_t ln = __shfl(len, j, kWave);
-    const uint32_t gg = __shfl(g, j, kWave);
-    for (uint32_t t = lane; t < ln; t += kWave) f(adj[st + t], gg);
+  uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
+  bool have = false;
+  while (longm || have) {
+    uint4 v[U];
+    uint32_t vst[U], vend[U], vg[U], vp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!have && longm) {
+        const int j = __ffsll(static_cast<unsigned long long>(longm)) - 1;
+        longm &= longm - 1;
+        cur_st = readlane(start, j);
+        cur_end = cur_st + readlane(len, j);
+        cur_g = readlane(g, j);
+        cur_pos = cur_st & ~3u;
+        have = true;
+      }
+      vst[u] = cur_st;
+      vg[u] = cur_g;
+      if (have) {
+        const uint32_t p = cur_pos + 4 * lane;
+        vp[u] = p;
+        vend[u] = cur_end;
+        v[u] = p < cur_end ? *reinterpret_cast<const uint4*>(adj + p) : make_uint4(0, 0, 0, 0);
+        cur_pos += kChunk;
+        if (cur_pos >= cur_end) have = false;
+      } else {
+        vp[u] = 0;
+        vend[u] = 0;
+        v[u] = make_uint4(0, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t idx = vp[u] + q;
+        if (idx >= vst[u] && idx < vend[u]) f(e4[q], vg[u]);
+      }
+    }
   }
   if (len >= kLong) len = 0;
   uint32_t total;
@@ -82,12 +127,25 @@ __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uin
     for (uint32_t t = lo; t < hi; ++t) gbuf[t - done] = (start + (t - excl)) | (g << 31);
     wave_sync_lds();
     const uint32_t cnt = total - done < kGather ? total - done : kGather;
-    for (uint32_t t = lane; t < cnt; t += kWave) {
-      const uint32_t a = gbuf[t];
-      f(adj[a & 0x7fffffffu], a >> 31);
+    for (uint32_t t0 = 0; t0 < cnt; t0 += kWave * U) {
+      uint32_t a[U], e[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t t = t0 + u * kWave + lane;
+        a[u] = t < cnt ? gbuf[t] : 0u;
+        e[u] = t < cnt ? adj[a[u] & 0x7fffffffu] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (t0 + u * kWave + lane < cnt) f(e[u], a[u] >> 31);
     }
     wave_sync_lds();
   }
+}
+
+// Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric.
+__device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
+  return ((e ^ g) & 1u) ? 0x10000u : 1u;
 }
 
 struct Sums {
@@ -106,13 +164,13 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t x) {
   return x;
 }
 
-// Add the block's sums to res[0..2] (one atomic per wavefront).
+// Add the wavefront's sums to res[0..2] (one atomic per wavefront).
 __device__ __forceinline__ void flush_sums(const Sums& s, unsigned long long* res) {
   const int64_t b = wave_sum64(s.bal), u = wave_sum64(s.unb), t = wave_sum64(s.tot);
   if (lane_id() == 0) {
-    if (b) atomicAdd(res + 0, static_cast<unsigned long long>(b));
-    if (u) atomicAdd(res + 1, static_cast<unsigned long long>(u));
-    if (t) atomicAdd(res + 2, static_cast<unsigned long long>(t));
+    if (b) atomicAdd(res + kResBalanced, static_cast<unsigned long long>(b));
+    if (u) atomicAdd(res + kResUnbalanced, static_cast<unsigned long long>(u));
+    if (t) atomicAdd(res + kResTotal, static_cast<unsigned long long>(t));
   }
 }
 
@@ -128,8 +186,9 @@ __device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, u
 }
 
 // ---------------------------------------------------------------------------
-// Direct-array items: one workgroup per item, counters for keys [0, L) in LDS.
-constexpr int kDirectThreads = 512;
+// Window items: one workgroup per item (or item part), counters for keys
+// [0, L) in LDS.
+constexpr int kDirectThreads = 1024;
 constexpr int kDirectWaves = kDirectThreads / kWave;
 constexpr int kDirectKeys = 32768;
 
@@ -168,12 +227,19 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
         kmin = f < kmin ? f : kmin;
         kmax = l > kmax ? l : kmax;
       }
-      walk_batch(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
-        atomicAdd(&cnt[e >> 1], ((e ^ g) & 1u) ? 0x10000u : 1u);
+      walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+        atomicAdd(&cnt[e >> 1], wedge_inc(e, g));
       });
     }
-    atomicMin(&range_sh[0], kmin);
-    atomicMax(&range_sh[1], kmax);
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const uint32_t omin = __shfl_xor(kmin, d, kWave), omax = __shfl_xor(kmax, d, kWave);
+      kmin = omin < kmin ? omin : kmin;
+      kmax = omax > kmax ? omax : kmax;
+    }
+    if (lane_id() == 0) {
+      atomicMin(&range_sh[0], kmin);
+      atomicMax(&range_sh[1], kmax);
+    }
     __syncthreads();
     const uint32_t lo = range_sh[0] & ~3u;
     const uint32_t hi = range_sh[1] + 1;
@@ -196,6 +262,60 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
       }
     }
     __syncthreads();
+  }
+  flush_sums(sums, a.res);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse items: one wavefront per item, a private LDS direct array over the
+// reverse window [0, R) (R <= kMaxReverseL) and a bitmap of touched keys, so
+// that the sweep visits only the keys the item reached.
+constexpr int kReverseThreads = 512;
+constexpr int kReverseWaves = kReverseThreads / kWave;
+constexpr int kReverseWords = kMaxReverseL / 32;
+
+__global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
+  __shared__ uint32_t cnt[kReverseWaves][kMaxReverseL];
+  __shared__ uint32_t bits[kReverseWaves][kReverseWords];
+  __shared__ uint32_t gbuf[kReverseWaves][kGather];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  uint32_t* C = cnt[wave];
+  uint32_t* Bt = bits[wave];
+  for (int i = lane; i < kMaxReverseL; i += kWave) C[i] = 0;
+  for (int i = lane; i < kReverseWords; i += kWave) Bt[i] = 0;
+  wave_sync_lds();
+  Sums sums;
+  for (;;) {
+    int32_t i = 0;
+    if (lane == 0) i = static_cast<int32_t>(atomicAdd(a.queue, 1u));
+    i = __shfl(i, 0, kWave);
+    if (i >= a.n_items) break;
+    const Item it = a.items[i];
+    const uint32_t* __restrict__ adj = a.side[it.side].other_adj;
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      walk_batch<8>(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+        const uint32_t key = e >> 1;
+        if (atomicAdd(&C[key], wedge_inc(e, g)) == 0) atomicOr(&Bt[key >> 5], 1u << (key & 31));
+      });
+    }
+    wave_sync_lds();
+    for (int wi = lane; wi < kReverseWords; wi += kWave) {
+      uint32_t word = Bt[wi];
+      if (!word) continue;
+      Bt[wi] = 0;
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1;
+        const uint32_t key = static_cast<uint32_t>(wi) * 32 + b;
+        const uint32_t c = C[key];
+        C[key] = 0;
+        sums.add(c & 0xffffu, c >> 16);
+      }
+    }
+    wave_sync_lds();
   }
   flush_sums(sums, a.res);
 }
@@ -248,9 +368,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+      walk_batch<4>(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
         const uint32_t key = e >> 1;
-        const uint32_t inc = ((e ^ g) & 1u) ? 0x10000u : 1u;
+        const uint32_t inc = wedge_inc(e, g);
         uint32_t h = mix32(key) & mask;
         for (uint32_t probe = 0;; ++probe) {
           if (probe > mask) {  // full table: cannot happen at load <= 1/2
@@ -327,7 +447,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     for (uint32_t pass = 0; pass < passes; ++pass) {
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        walk_batch(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+        walk_batch<4>(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
           const uint32_t key = e >> 1;
           const uint32_t hk = mix32(key);
           if (passes > 1 && (hk >> 16) % passes != pass) return;
@@ -414,6 +534,12 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 hipError_t launch_direct(const DirectArgs& a, int grid, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
   hipLaunchKernelGGL(dev::k_direct, dim3(grid), dim3(dev::kDirectThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_reverse, dim3(grid), dim3(dev::kReverseThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -85,28 +85,36 @@ struct Reduce {       // one multi-part accumulator to reduce after its parts
 struct PlanParams {
   int32_t hub_T = 0;
   int32_t window_L = 0;
+  int32_t reverse_L = 0;
   int32_t small_work = 0;
   int32_t part_work = 0;
   bool operator==(const PlanParams& o) const {
-    return hub_T == o.hub_T && window_L == o.window_L && small_work == o.small_work &&
-           part_work == o.part_work;
+    return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
+           small_work == o.small_work && part_work == o.part_work;
   }
 };
+
+// Largest reverse window: keys of a reverse item index a per-wavefront LDS
+// array of this many counters.
+constexpr int32_t kMaxReverseL = 4096;
 
 struct HostPlan {
   PlanParams p;
   int32_t L[2] = {0, 0};  // window per side
+  int32_t R[2] = {0, 0};  // reverse window per side (R <= L)
   int32_t T[2] = {0, 0};  // hub block rows per side (pairs on that side)
   std::vector<Segment> segs;
   std::vector<Item> small_items;   // per-wavefront hash counters
   std::vector<Item> direct_items;  // workgroup direct arrays over [0, L)
   std::vector<Item> hash_items;    // workgroup hash counters, large tail pivots
+  std::vector<Item> reverse_items; // per-wavefront direct arrays over [0, R)
   std::vector<Reduce> reduces;
   int32_t acc_slots = 0;
   int32_t acc_width = 0;           // max window over the sides
-  // per sparse kernel (0 = direct, 1 = small, 2 = hash): wedges, segments, items
-  int64_t k_wedges[3] = {0, 0, 0};
-  int64_t k_segs[3] = {0, 0, 0};
+  // per sparse kernel (0 = direct, 1 = small, 2 = hash, 3 = reverse):
+  // wedges and segments
+  int64_t k_wedges[4] = {0, 0, 0, 0};
+  int64_t k_segs[4] = {0, 0, 0, 0};
   int64_t w_sparse = 0;            // wedges tallied by the sparse kernels
   int64_t w_skipped = 0;           // wedges of items that cannot contribute
   // dense hub block per side s (pairs on s): row-major int8 matrices

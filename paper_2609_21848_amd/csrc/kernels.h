@@ -10,6 +10,10 @@
 
 namespace dbbc {
 
+// Zero words appended to every CSR entry array: a 16-byte load may start at
+// the last entry of a run.
+constexpr size_t kAdjPad = 64;
+
 // Layout of the int64 result block shared by all kernels of a count.
 enum : int {
   kResBalanced = 0,
@@ -83,6 +87,7 @@ struct HubArgs {
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_direct(const DirectArgs& a, int grid, hipStream_t st);
 hipError_t launch_small(const SmallArgs& a, int grid, hipStream_t st);
+hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_hub(const HubArgs& a, hipStream_t st);

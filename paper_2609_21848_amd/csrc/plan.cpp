@@ -4,18 +4,20 @@
 //
 // Every VP wedge x - y - w (y and w of lower priority than x, w on x's side)
 // belongs to exactly one same-side pair (x, w), and Lemma 1 needs all wedges
-// of a pair in one place before C(., 2) is taken.  With L the window size of
-// the side (its L highest-priority vertices), each pair is owned by one item:
-//   kForwardWindow  sr(w) < L        : at pivot x, keys w in (x, L)
-//   kReverseTail    sr(x) < L <= sr(w): at endpoint w, keys x in [0, L);
-//                                       the same wedges walked from w: for
-//                                       each neighbour y of w, the entries of
-//                                       row y that rank above both L and y
-//   kForwardTail    sr(x) >= L       : at pivot x, keys w in (x, n)
+// of a pair in one place before C(., 2) is taken.  Per side, with a window
+// of the L highest-priority vertices and a reverse window of the R <= L
+// highest, each pair (sr(x) < sr(w)) is owned by exactly one item:
+//   forward-window  sr(w) < L              : at pivot x, keys w in (x, L)
+//   reverse         sr(x) < R, sr(w) >= L  : at endpoint w, keys x in [0, R);
+//                                            the same wedges walked from w:
+//                                            for each neighbour y of w, the
+//                                            entries of row y that rank above
+//                                            both R and y
+//   forward-tail    sr(x) >= R, sr(w) >= L : at pivot x, keys w >= L
 // Inside the window, the pairs of the hub block (x, w < T, mid y < T on the
-// other side) are counted by the dense path; the forward items skip those
-// wedges and leave their other hub-pair wedges in a pair buffer that the
-// dense path adds before taking C(., 2).
+// other side) are counted by the dense path; forward items skip those wedges
+// and leave their other hub-pair wedges in a pair buffer that the dense path
+// adds before taking C(., 2).
 #include <algorithm>
 
 #include "internal.h"
@@ -25,9 +27,8 @@ namespace dbbc {
 PlanParams default_params(const HostGraph& g) {
   PlanParams p;
   p.window_L = 32768;
+  p.reverse_L = 4096;
   p.hub_T = 0;
-  // The dense block pays off when the top of both sides is dense; keep it off
-  // for small graphs where its fixed cost dominates.
   (void)g;
   p.small_work = 1024;
   p.part_work = 1 << 20;
@@ -35,27 +36,6 @@ PlanParams default_params(const HostGraph& g) {
 }
 
 namespace {
-
-struct Builder {
-  const HostGraph& g;
-  HostPlan& plan;
-  std::vector<Item> big_direct;  // before splitting into parts
-
-  void add_item(std::vector<Item>& dst, uint32_t seg_begin, int64_t work, int32_t owner,
-                int32_t key_lo, int32_t key_hi, uint32_t flags, uint32_t side) {
-    Item it{};
-    it.seg_begin = seg_begin;
-    it.seg_count = static_cast<uint32_t>(plan.segs.size() - seg_begin);
-    it.owner = owner;
-    it.key_lo = key_lo;
-    it.key_hi = key_hi;
-    it.acc_slot = -1;
-    it.flags = flags;
-    it.side = side;
-    (void)work;
-    dst.push_back(it);
-  }
-};
 
 int64_t item_work(const HostPlan& plan, const Item& it) {
   int64_t w = 0;
@@ -68,6 +48,11 @@ int64_t item_work(const HostPlan& plan, const Item& it) {
 int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err) {
   if (p.window_L < 256 || p.window_L > 32768 || p.window_L % 256 != 0) {
     err = "window_L must be a multiple of 256 in [256, 32768]";
+    return DBBC_E_INVALID_ARG;
+  }
+  if (p.reverse_L < 64 || p.reverse_L > kMaxReverseL || p.reverse_L % 64 != 0 ||
+      p.reverse_L > p.window_L) {
+    err = "reverse_L must be a multiple of 64 in [64, 4096], at most window_L";
     return DBBC_E_INVALID_ARG;
   }
   if (p.hub_T < 0 || p.hub_T > 16384 || p.hub_T % 128 != 0) {
@@ -86,36 +71,39 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   plan.p = p;
   for (int s = 0; s < 2; ++s) {
     plan.L[s] = std::min<int32_t>(p.window_L, g.side[s].n);
+    plan.R[s] = std::min<int32_t>(p.reverse_L, plan.L[s]);
     // the dense block is tiled by 128 rows
     plan.T[s] = std::min<int32_t>(p.hub_T, g.side[s].n / 128 * 128);
   }
   // The dense path needs a block on both sides of the pair.
   if (plan.T[0] == 0 || plan.T[1] == 0) plan.T[0] = plan.T[1] = 0;
 
-  Builder B{g, plan, {}};
   std::vector<Item> big_direct;
 
   for (int s = 0; s < 2; ++s) {
     const HostSide& S = g.side[s];
     const HostSide& O = g.side[1 - s];
     const int32_t L = plan.L[s];
+    const int32_t R = plan.R[s];
     const int32_t T = plan.T[s];
     const int32_t TO = plan.T[1 - s];  // hub rows of the other side (mids)
-    // Per row y of the other side: entries below the window / below the
-    // hub block (keys on side s are the row's entries).
-    std::vector<int32_t> split(O.n), splitT(O.n);
+    // Per row y of the other side (its entries are keys of side s): how many
+    // entries lie below the window, the reverse window and the hub block.
+    std::vector<int32_t> splitL(O.n), splitR(O.n), splitT(O.n);
     for (int32_t y = 0; y < O.n; ++y) {
       const uint32_t* b = O.adj.data() + O.off[y];
       const uint32_t* e = O.adj.data() + O.off[y + 1];
-      split[y] = static_cast<int32_t>(
-          std::lower_bound(b, e, static_cast<uint32_t>(L) << 1) - b);
-      splitT[y] = static_cast<int32_t>(
-          std::lower_bound(b, e, static_cast<uint32_t>(T) << 1) - b);
+      auto below = [&](int32_t k) {
+        return static_cast<int32_t>(std::lower_bound(b, e, static_cast<uint32_t>(k) << 1) - b);
+      };
+      splitL[y] = below(L);
+      splitR[y] = below(R);
+      splitT[y] = below(T);
     }
 
     auto place = [&](uint32_t seg_begin, int32_t owner, int32_t key_lo, int32_t key_hi,
                      uint32_t flags, ItemKind kind) {
-      uint32_t nseg = static_cast<uint32_t>(plan.segs.size() - seg_begin);
+      const uint32_t nseg = static_cast<uint32_t>(plan.segs.size() - seg_begin);
       int64_t work = 0;
       for (uint32_t k = 0; k < nseg; ++k) work += plan.segs[seg_begin + k].len_g >> 1;
       // With a single segment every pair of the item has at most one wedge
@@ -127,46 +115,66 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         return;
       }
       plan.w_sparse += work;
-      if (work <= p.small_work) {
-        B.add_item(plan.small_items, seg_begin, work, owner, key_lo, key_hi, flags, s);
+      Item it{};
+      it.seg_begin = seg_begin;
+      it.seg_count = nseg;
+      it.owner = owner;
+      it.key_lo = key_lo;
+      it.key_hi = key_hi;
+      it.acc_slot = -1;
+      it.flags = flags;
+      it.side = static_cast<uint32_t>(s);
+      if (kind == kReverseTail) {
+        plan.reverse_items.push_back(it);
+      } else if (work <= p.small_work) {
+        plan.small_items.push_back(it);
       } else if (kind == kForwardTail) {
-        B.add_item(plan.hash_items, seg_begin, work, owner, key_lo, key_hi, flags, s);
+        plan.hash_items.push_back(it);
       } else {
-        B.add_item(big_direct, seg_begin, work, owner, key_lo, key_hi, flags, s);
+        big_direct.push_back(it);
       }
-      (void)kind;
     };
 
-    // Forward items: pivots x of side s.
+    // Forward items: pivots x of side s, split at the window boundary.
     for (int32_t x = 0; x < S.n; ++x) {
-      const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
-      const bool in_window = x < L;
       const bool hub = x < T;
-      for (uint32_t e = S.off[x] + S.cut[x]; e < S.off[x + 1]; ++e) {
-        const uint32_t y = S.adj[e] >> 1;
-        const uint32_t gbit = S.adj[e] & 1u;
-        uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
-        uint32_t end = in_window ? O.off[y] + static_cast<uint32_t>(split[y]) : O.off[y + 1];
-        if (hub && static_cast<int32_t>(y) < TO)
-          start = std::max(start, O.off[y] + static_cast<uint32_t>(splitT[y]));
-        if (end > start) plan.segs.push_back(Segment{start, ((end - start) << 1) | gbit});
-      }
-      if (in_window) {
+      const uint32_t e0 = S.off[x] + S.cut[x], e1 = S.off[x + 1];
+      if (x < L) {  // keys (x, L)
+        const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+        for (uint32_t e = e0; e < e1; ++e) {
+          const uint32_t y = S.adj[e] >> 1;
+          uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
+          const uint32_t end = O.off[y] + static_cast<uint32_t>(splitL[y]);
+          if (hub && static_cast<int32_t>(y) < TO)
+            start = std::max(start, O.off[y] + static_cast<uint32_t>(splitT[y]));
+          if (end > start)
+            plan.segs.push_back(Segment{start, ((end - start) << 1) | (S.adj[e] & 1u)});
+        }
         place(seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
-      } else {
-        place(seg_begin, x, x + 1, S.n, 0u, kForwardTail);
+      }
+      if (x >= R) {  // keys [max(L, x + 1), n)
+        const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+        for (uint32_t e = e0; e < e1; ++e) {
+          const uint32_t y = S.adj[e] >> 1;
+          const uint32_t start = std::max(O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1,
+                                          O.off[y] + static_cast<uint32_t>(splitL[y]));
+          const uint32_t end = O.off[y + 1];
+          if (end > start)
+            plan.segs.push_back(Segment{start, ((end - start) << 1) | (S.adj[e] & 1u)});
+        }
+        place(seg_begin, x, std::max(L, x + 1), S.n, 0u, kForwardTail);
       }
     }
-    // Reverse items: endpoints w of side s below the window.
+    // Reverse items: endpoints w of side s below the window, keys x < R.
     for (int32_t w = L; w < S.n; ++w) {
       const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
       for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
         const uint32_t y = S.adj[e] >> 1;
-        const uint32_t gbit = S.adj[e] & 1u;
-        const int32_t len = std::min(split[y], O.cut[y]);
-        if (len > 0) plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(len) << 1) | gbit});
+        const int32_t len = std::min(splitR[y], O.cut[y]);
+        if (len > 0)
+          plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(len) << 1) | (S.adj[e] & 1u)});
       }
-      place(seg_begin, w, 0, L, 0u, kReverseTail);
+      place(seg_begin, w, 0, R, 0u, kReverseTail);
     }
 
     // Dense hub block of this side: B[x][y] for x < T, y < TO.
@@ -196,14 +204,14 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   int32_t width = 0;
   for (int s = 0; s < 2; ++s) width = std::max(width, plan.L[s]);
   plan.acc_width = width;
-  std::vector<Item> parts;
+  std::vector<Item> parts, singles;
   for (auto& [work, i] : order) {
     const Item& it = big_direct[i];
     if (work <= p.part_work && it.seg_count < 65536) {
-      plan.direct_items.push_back(it);
+      singles.push_back(it);
       continue;
     }
-    int32_t first_slot = plan.acc_slots;
+    const int32_t first_slot = plan.acc_slots;
     uint32_t k = 0;
     while (k < it.seg_count) {
       Item part = it;
@@ -211,7 +219,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       int64_t pw = 0;
       uint32_t c = 0;
       while (k + c < it.seg_count && c < 65535) {
-        int64_t l = plan.segs[it.seg_begin + k + c].len_g >> 1;
+        const int64_t l = plan.segs[it.seg_begin + k + c].len_g >> 1;
         if (c > 0 && pw + l > p.part_work) break;
         pw += l;
         ++c;
@@ -232,22 +240,22 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     r.side = it.side;
     plan.reduces.push_back(r);
   }
+  // parts first (they are the heaviest), then the single-part items
+  plan.direct_items = std::move(parts);
+  plan.direct_items.insert(plan.direct_items.end(), singles.begin(), singles.end());
+  // heavy tail pivots first as well
+  std::stable_sort(plan.hash_items.begin(), plan.hash_items.end(),
+                   [&](const Item& a, const Item& b) { return item_work(plan, a) > item_work(plan, b); });
   auto tally = [&](int k, const std::vector<Item>& v) {
     for (const Item& it : v) {
       plan.k_wedges[k] += item_work(plan, it);
       plan.k_segs[k] += it.seg_count;
     }
   };
-  tally(0, parts);
   tally(0, plan.direct_items);
   tally(1, plan.small_items);
   tally(2, plan.hash_items);
-  // parts first (they are the heaviest), then the single-part items
-  parts.insert(parts.end(), plan.direct_items.begin(), plan.direct_items.end());
-  plan.direct_items.swap(parts);
-  // heavy tail pivots first as well
-  std::stable_sort(plan.hash_items.begin(), plan.hash_items.end(),
-                   [&](const Item& a, const Item& b) { return item_work(plan, a) > item_work(plan, b); });
+  tally(3, plan.reverse_items);
   return DBBC_OK;
 }
 

@@ -24,8 +24,8 @@ struct Acc {
 }  // namespace
 
 extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
-                            const int8_t* sign, int32_t hub_T, int32_t window_L, int32_t small_work,
-                            int32_t part_work, int64_t* out /* 12 */) {
+                            const int8_t* sign, int32_t hub_T, int32_t window_L, int32_t reverse_L,
+                            int32_t small_work, int32_t part_work, int64_t* out /* 13 */) {
   HostGraph g;
   std::string err;
   int rc = build_host_graph(n_u, n_v, m, u, v, sign, 0, g, err);
@@ -33,6 +33,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   PlanParams p = default_params(g);
   if (hub_T >= 0) p.hub_T = hub_T;
   if (window_L >= 0) p.window_L = window_L;
+  if (reverse_L >= 0) p.reverse_L = reverse_L;
   if (small_work >= 0) p.small_work = small_work;
   if (part_work >= 0) p.part_work = part_work;
   HostPlan plan;
@@ -77,7 +78,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
     }
     return 0;
   };
-  for (auto* list : {&plan.direct_items, &plan.small_items, &plan.hash_items})
+  for (auto* list : {&plan.direct_items, &plan.small_items, &plan.hash_items, &plan.reverse_items})
     for (const Item& it : *list) {
       if ((rc = run(it))) return rc;
     }
@@ -139,5 +140,6 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   out[9] = (int64_t)plan.direct_items.size();
   out[10] = (int64_t)plan.hash_items.size();
   out[11] = (int64_t)plan.reduces.size();
+  out[12] = (int64_t)plan.reverse_items.size();
   return 0;
 }

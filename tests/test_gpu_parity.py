@@ -75,7 +75,7 @@ def test_random_small_graphs(dbbc):
         want = _want(g)
         with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
             for opts in ({}, {"window_L": 256, "small_work": 2, "part_work": 4096},
-                         {"window_L": 512, "small_work": 1024}):
+                         {"window_L": 512, "small_work": 1024, "reverse_L": 64}):
                 got = h.count(**opts)
                 assert tuple(got) == want, (seed, opts)
 
@@ -83,7 +83,8 @@ def test_random_small_graphs(dbbc):
 @pytest.mark.parametrize("opts", [
     {}, {"window_L": 256}, {"window_L": 1024, "small_work": 2}, {"hub_T": 128, "window_L": 256},
     {"hub_T": 512, "window_L": 1024, "small_work": 64, "part_work": 4096},
-    {"hub_T": 1024, "window_L": 32768},
+    {"hub_T": 1024, "window_L": 32768}, {"window_L": 2048, "reverse_L": 64},
+    {"window_L": 4096, "reverse_L": 4096, "small_work": 2},
 ])
 def test_tiny_workload_option_sweep(dbbc, opts):
     g = config_graph("tiny")
@@ -107,7 +108,8 @@ def test_powerlaw2m_full_size(dbbc):
     g = config_graph("powerlaw2m")
     want = _want(g)
     with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
-        for opts in ({}, {"hub_T": 4096}, {"hub_T": 2048, "window_L": 8192}, {"hub_T": 0}):
+        for opts in ({}, {"hub_T": 4096}, {"hub_T": 2048, "window_L": 8192}, {"hub_T": 0},
+                     {"reverse_L": 1024}, {"window_L": 4096, "reverse_L": 4096}):
             _say("powerlaw2m", opts)
             assert tuple(h.count(**opts)) == want, opts
         # repeated runs give identical integers (a race would show here)
@@ -123,7 +125,7 @@ def test_skewed50m_full_size(dbbc):
     assert (g.n_u, g.n_v, g.m) == (cache["n_u"], cache["n_v"], cache["m"])
     want = (cache["balanced"], cache["unbalanced"], cache["total"], cache["wedges"])
     with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
-        for opts in ({}, {"hub_T": 0}, {"hub_T": 4096}):
+        for opts in ({}, {"hub_T": 0}, {"hub_T": 4096}, {"reverse_L": 2048}):
             _say("skewed50m", opts)
             assert tuple(h.count(**opts)) == want, opts
 
@@ -192,6 +194,6 @@ def test_kernel_times(dbbc):
         h.count(flags=dbbc.DBBC_OPT_TIME_KERNELS, hub_T=1024)
         ks = h.kernel_times()
     names = [k["name"] for k in ks]
-    assert {"direct", "small", "hash", "reduce"} <= set(names)
+    assert {"direct", "reverse", "small", "hash", "reduce"} <= set(names)
     assert all(k["ms"] >= 0 for k in ks)
     assert sum(k["wedges"] for k in ks) > 0

@@ -24,19 +24,22 @@ def emul(tmp_path_factory):
                            os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
-    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, p]
+    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, p]
 
-    def run(g, T=-1, L=-1, sw=-1, pw=-1):
-        out = np.zeros(12, np.int64)
+    def run(g, T=-1, L=-1, sw=-1, pw=-1, R=-1):
+        out = np.zeros(13, np.int64)
+        if R < 0 and L >= 0:
+            R = min(L, 4096)
         rc = lib.plan_emulate(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
-                              g.sign.ctypes.data, T, L, sw, pw, out.ctypes.data)
+                              g.sign.ctypes.data, T, L, R, sw, pw, out.ctypes.data)
         assert rc == 0, rc
         return out
     return run
 
 
-CONFIGS = [(0, 256, 2, 4096), (128, 256, 64, 4096), (256, 512, 1024, 8192),
-           (0, 32768, 1024, 1 << 20), (256, 1024, 16, 4096)]
+# (hub_T, window_L, small_work, part_work, reverse_L)
+CONFIGS = [(0, 256, 2, 4096, 64), (128, 256, 64, 4096, 256), (256, 512, 1024, 8192, 128),
+           (0, 32768, 1024, 1 << 20, 4096), (256, 1024, 16, 4096, 512), (0, 2048, 1024, 4096, 2048)]
 
 
 def _check(o, r):
@@ -69,7 +72,7 @@ def test_plan_on_small_and_degenerate_graphs(emul):
         n_u, n_v = int(rng.integers(1, 20)), int(rng.integers(1, 20))
         g = uniform_graph(n_u, n_v, int(rng.integers(0, n_u * n_v + 1)), 0.5, seed=seed)
         r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
-        for cfg in [(0, 256, 2, 4096), (0, 256, 1024, 4096)]:
+        for cfg in [(0, 256, 2, 4096, 64), (0, 256, 1024, 4096, 128)]:
             _check(emul(g, *cfg), r)
 
 
@@ -77,7 +80,7 @@ def test_hub_block_on_dense_graph(emul):
     # a dense graph where the hub block covers most pairs
     g = chung_lu_graph(600, 500, 60000, 2.5, 2.5, 0.3, seed=7)
     r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
-    for cfg in [(256, 256, 64, 4096), (384, 512, 2, 4096), (0, 512, 1024, 4096)]:
+    for cfg in [(256, 256, 64, 4096, 64), (384, 512, 2, 4096, 512), (0, 512, 1024, 4096, 128)]:
         o = emul(g, *cfg)
         _check(o, r)
-    assert emul(g, 256, 256, 64, 4096)[6] > 0
+    assert emul(g, 256, 256, 64, 4096, 128)[6] > 0
