@@ -264,10 +264,12 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     a.side[0] = side[0];
     a.side[1] = side[1];
     a.queue = queues + 3;
+    a.acc = d.acc.as<uint32_t>();
+    a.acc_width = hp.acc_width;
     a.res = ctl;
     a.n_items = static_cast<int32_t>(hp.reverse_items.size());
     RC_TRY(tm.begin("reverse", hp.k_wedges[3], hp.k_segs[3], a.n_items, 0));
-    HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 7) / 8)), st));
+    HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 15) / 16)), st));
     RC_TRY(tm.end());
   }
   {

@@ -54,8 +54,25 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Walk up to 64 segments [k0, k1) with one wavefront, calling f(entry, g)
-// once per wedge.
+// One lane's segment of a batch (len 0 = none).
+struct SegReg {
+  uint32_t start, len, g;
+};
+
+__device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1) {
+  const uint32_t k = k0 + lane_id();
+  SegReg r{0, 0, 0};
+  if (k < k1) {
+    const Segment s = segs[k];
+    r.start = s.start;
+    r.len = s.len_g >> 1;
+    r.g = s.len_g & 1u;
+  }
+  return r;
+}
+
+// Walk a batch of up to 64 segments (one per lane, in registers) with one
+// wavefront, calling f(entry, g) once per wedge.
 //  - Segments of at least kLong entries are consumed as a stream of
 //    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
 //    chunk, U chunks are in flight per lane, and a chunk's out-of-segment
@@ -64,17 +81,11 @@ __device__ __forceinline__ void wave_sync_lds() {
 //    this wavefront) as (index | g << 31) so that lanes read consecutive
 //    wedges, again U loads in flight per lane.
 template <int U, class F>
-__device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
-                                           const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
+__device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, uint32_t* gbuf,
+                                          F&& f) {
   const int lane = lane_id();
-  const uint32_t k = k0 + lane;
-  uint32_t start = 0, len = 0, g = 0;
-  if (k < k1) {
-    const Segment s = segs[k];
-    start = s.start;
-    len = s.len_g >> 1;
-    g = s.len_g & 1u;
-  }
+  const uint32_t start = sr.start, g = sr.g;
+  uint32_t len = sr.len;
   uint64_t longm = __ballot(len >= kLong);
   uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
@@ -143,6 +154,30 @@ __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uin
   }
 }
 
+template <int U, class F>
+__device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
+                                           const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
+  walk_regs<U>(load_seg(segs, k0, k1), adj, gbuf, f);
+}
+
+// Walk every segment of an item with one wavefront; the first batch of 64
+// segments was loaded beforehand (first).
+template <int U, class F>
+__device__ __forceinline__ void walk_item(const Item& it, SegReg first, const Segment* __restrict__ segs,
+                                          const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
+  const uint32_t seg_end = it.seg_begin + it.seg_count;
+  walk_regs<U>(first, adj, gbuf, f);
+  for (uint32_t k0 = it.seg_begin + kWave; k0 < seg_end; k0 += kWave) {
+    const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+    walk_regs<U>(load_seg(segs, k0, k1), adj, gbuf, f);
+  }
+}
+
+__device__ __forceinline__ SegReg first_batch(const Item& it, const Segment* __restrict__ segs) {
+  const uint32_t seg_end = it.seg_begin + it.seg_count;
+  return load_seg(segs, it.seg_begin, it.seg_begin + kWave < seg_end ? it.seg_begin + kWave : seg_end);
+}
+
 // Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric.
 __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
   return ((e ^ g) & 1u) ? 0x10000u : 1u;
@@ -187,62 +222,39 @@ __device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, u
 
 // ---------------------------------------------------------------------------
 // Window items: one workgroup per item (or item part), counters for keys
-// [0, L) in LDS.
+// [0, L) in LDS and a bitmap of the keys the item touched.
 constexpr int kDirectThreads = 1024;
 constexpr int kDirectWaves = kDirectThreads / kWave;
 constexpr int kDirectKeys = 32768;
+constexpr int kDirectWords = kDirectKeys / 32;  // == kDirectThreads
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t cnt[kDirectKeys];
+  __shared__ uint32_t bits[kDirectWords];
   __shared__ uint32_t gbuf[kDirectWaves][kGather];
   __shared__ int32_t item_sh;
-  __shared__ uint32_t range_sh[2];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
+  for (int i = tid; i < kDirectWords; i += kDirectThreads) bits[i] = 0;
   Sums sums;
   for (;;) {
-    if (tid == 0) {
-      item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
-      range_sh[0] = kEmpty;
-      range_sh[1] = 0;
-    }
+    if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
     __syncthreads();
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
     const Item it = a.items[i];
     const DevSideConst sc = a.side[it.side];
     const uint32_t* __restrict__ adj = sc.other_adj;
-    uint32_t kmin = kEmpty, kmax = 0;
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      // key range of the batch: rows are sorted, so the first and last entry
-      // of each segment bound its keys
-      const uint32_t k = k0 + lane_id();
-      if (k < k1) {
-        const Segment s = a.segs[k];
-        const uint32_t len = s.len_g >> 1;
-        const uint32_t f = adj[s.start] >> 1, l = adj[s.start + len - 1] >> 1;
-        kmin = f < kmin ? f : kmin;
-        kmax = l > kmax ? l : kmax;
-      }
       walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
-        atomicAdd(&cnt[e >> 1], wedge_inc(e, g));
+        const uint32_t key = e >> 1;
+        if (atomicAdd(&cnt[key], wedge_inc(e, g)) == 0) atomicOr(&bits[key >> 5], 1u << (key & 31));
       });
     }
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-      const uint32_t omin = __shfl_xor(kmin, d, kWave), omax = __shfl_xor(kmax, d, kWave);
-      kmin = omin < kmin ? omin : kmin;
-      kmax = omax > kmax ? omax : kmax;
-    }
-    if (lane_id() == 0) {
-      atomicMin(&range_sh[0], kmin);
-      atomicMax(&range_sh[1], kmax);
-    }
     __syncthreads();
-    const uint32_t lo = range_sh[0] & ~3u;
-    const uint32_t hi = range_sh[1] + 1;
     if (it.flags & kItemMultiPart) {
       // write the part's counters for the whole key window (zeros included)
       uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
@@ -250,15 +262,19 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
         dst[key] = cnt[key];
         cnt[key] = 0;
       }
-    } else if (lo < hi) {
-      for (uint32_t key = lo + 4 * tid; key < hi; key += 4 * kDirectThreads) {
-        uint4 c4 = *reinterpret_cast<uint4*>(&cnt[key]);
-        if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
-        const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (cv[j]) emit(it, key + j, cv[j] & 0xffffu, cv[j] >> 16, sc, sums);
-        *reinterpret_cast<uint4*>(&cnt[key]) = make_uint4(0, 0, 0, 0);
+      bits[tid] = 0;
+    } else {
+      uint32_t word = bits[tid];
+      if (word) {
+        bits[tid] = 0;
+        while (word) {
+          const int b = __ffs(word) - 1;
+          word &= word - 1;
+          const uint32_t key = static_cast<uint32_t>(tid) * 32 + b;
+          const uint32_t c = cnt[key];
+          cnt[key] = 0;
+          emit(it, key, c & 0xffffu, c >> 16, sc, sums);
+        }
       }
     }
     __syncthreads();
@@ -268,51 +284,76 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 
 // ---------------------------------------------------------------------------
 // Reverse items: one wavefront per item, a private LDS direct array over the
-// reverse window [0, R) (R <= kMaxReverseL) and a bitmap of touched keys, so
-// that the sweep visits only the keys the item reached.
-constexpr int kReverseThreads = 512;
+// reverse window [0, R) (R <= kMaxReverseL) and a bitmap of touched keys.
+// Counters are 8-bit (symmetric | asymmetric << 8) in 16-bit halves, two
+// keys per 32-bit word: an item (or part) has at most kReverseMaxSegs
+// segments, so no half overflows.  Items are dealt to wavefronts in a fixed
+// stride and the next item's descriptor and first segments are loaded while
+// the current one is walked.
+constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 32;
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
-  __shared__ uint32_t cnt[kReverseWaves][kMaxReverseL];
+  __shared__ uint32_t cnt[kReverseWaves][kMaxReverseL / 2];
   __shared__ uint32_t bits[kReverseWaves][kReverseWords];
   __shared__ uint32_t gbuf[kReverseWaves][kGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
   uint32_t* Bt = bits[wave];
-  for (int i = lane; i < kMaxReverseL; i += kWave) C[i] = 0;
+  for (int i = lane; i < kMaxReverseL / 2; i += kWave) C[i] = 0;
   for (int i = lane; i < kReverseWords; i += kWave) Bt[i] = 0;
   wave_sync_lds();
   Sums sums;
-  for (;;) {
-    int32_t i = 0;
-    if (lane == 0) i = static_cast<int32_t>(atomicAdd(a.queue, 1u));
-    i = __shfl(i, 0, kWave);
-    if (i >= a.n_items) break;
-    const Item it = a.items[i];
+  const int32_t stride = static_cast<int32_t>(gridDim.x) * kReverseWaves;
+  int32_t i = static_cast<int32_t>(blockIdx.x) * kReverseWaves + wave;
+  Item nxt{};
+  SegReg nfirst{0, 0, 0};
+  if (i < a.n_items) {
+    nxt = a.items[i];
+    nfirst = first_batch(nxt, a.segs);
+  }
+  for (; i < a.n_items; i += stride) {
+    const Item it = nxt;
+    const SegReg first = nfirst;
+    const int32_t j = i + stride;
+    if (j < a.n_items) nxt = a.items[j];
     const uint32_t* __restrict__ adj = a.side[it.side].other_adj;
-    const uint32_t seg_end = it.seg_begin + it.seg_count;
-    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
-      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<8>(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
-        const uint32_t key = e >> 1;
-        if (atomicAdd(&C[key], wedge_inc(e, g)) == 0) atomicOr(&Bt[key >> 5], 1u << (key & 31));
-      });
-    }
+    walk_item<8>(it, first, a.segs, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+      const uint32_t key = e >> 1;
+      const uint32_t sh = (key & 1u) << 4;
+      const uint32_t inc = (((e ^ g) & 1u) ? 0x100u : 1u) << sh;
+      if (((atomicAdd(&C[key >> 1], inc) >> sh) & 0xffffu) == 0)
+        atomicOr(&Bt[key >> 5], 1u << (key & 31));
+    });
+    if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
     wave_sync_lds();
-    for (int wi = lane; wi < kReverseWords; wi += kWave) {
-      uint32_t word = Bt[wi];
-      if (!word) continue;
-      Bt[wi] = 0;
-      while (word) {
-        const int b = __ffs(word) - 1;
-        word &= word - 1;
-        const uint32_t key = static_cast<uint32_t>(wi) * 32 + b;
-        const uint32_t c = C[key];
-        C[key] = 0;
-        sums.add(c & 0xffffu, c >> 16);
+    if (it.flags & kItemMultiPart) {
+      uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
+      for (int32_t key = it.key_lo + lane; key < it.key_hi; key += kWave) {
+        const uint32_t c = (C[key >> 1] >> ((key & 1) << 4)) & 0xffffu;
+        dst[key] = (c & 0xffu) | ((c >> 8) << 16);
+      }
+      wave_sync_lds();
+      for (int w2 = lane; w2 < kMaxReverseL / 2; w2 += kWave) C[w2] = 0;
+      for (int w2 = lane; w2 < kReverseWords; w2 += kWave) Bt[w2] = 0;
+    } else {
+      for (int wi = lane; wi < kReverseWords; wi += kWave) {
+        const uint32_t word = Bt[wi];
+        if (!word) continue;
+        Bt[wi] = 0;
+        // keys 2q and 2q + 1 share counter word 16 * wi + q
+        uint32_t pairs = (word | (word >> 1)) & 0x55555555u;
+        while (pairs) {
+          const int b = __ffs(pairs) - 1;
+          pairs &= pairs - 1;
+          const int q = b >> 1;
+          const uint32_t c2 = C[wi * 16 + q];
+          C[wi * 16 + q] = 0;
+          if ((word >> b) & 1u) sums.add(c2 & 0xffu, (c2 >> 8) & 0xffu);
+          if ((word >> (b + 1)) & 1u) sums.add((c2 >> 16) & 0xffu, c2 >> 24);
+        }
       }
     }
     wave_sync_lds();
@@ -350,25 +391,26 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   }
   wave_sync_lds();
   Sums sums;
-  for (;;) {
-    int32_t i = 0;
-    if (lane == 0) i = static_cast<int32_t>(atomicAdd(a.queue, 1u));
-    i = __shfl(i, 0, kWave);
-    if (i >= a.n_items) break;
-    const Item it = a.items[i];
+  const int32_t stride = static_cast<int32_t>(gridDim.x) * kSmallWaves;
+  int32_t i = static_cast<int32_t>(blockIdx.x) * kSmallWaves + wave;
+  Item nxt{};
+  SegReg nfirst{0, 0, 0};
+  if (i < a.n_items) {
+    nxt = a.items[i];
+    nfirst = first_batch(nxt, a.segs);
+  }
+  for (; i < a.n_items; i += stride) {
+    const Item it = nxt;
+    const SegReg first = nfirst;
+    const int32_t j = i + stride;
+    if (j < a.n_items) nxt = a.items[j];
     const DevSideConst sc = a.side[it.side];
     // table size: a power of two >= 2 * work, at least 64
-    uint32_t work = 0;
-    for (uint32_t k = it.seg_begin + lane; k < it.seg_begin + it.seg_count; k += kWave)
-      work += a.segs[k].len_g >> 1;
-    for (int d = kWave / 2; d > 0; d >>= 1) work += __shfl_xor(work, d, kWave);
     uint32_t size = 64;
-    while (size < 2 * work) size <<= 1;
+    while (size < 2 * it.work) size <<= 1;
     const uint32_t mask = size - 1;
-    const uint32_t seg_end = it.seg_begin + it.seg_count;
-    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
-      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<4>(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+    {
+      walk_item<4>(it, first, a.segs, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
         const uint32_t key = e >> 1;
         const uint32_t inc = wedge_inc(e, g);
         uint32_t h = mix32(key) & mask;
@@ -390,6 +432,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
         }
       });
     }
+    if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
     wave_sync_lds();
     for (uint32_t h = lane; h < size; h += kWave) {
       const uint32_t key = K[h];

@@ -52,9 +52,15 @@ struct Segment {
 
 enum ItemKind : uint8_t {
   kForwardWindow = 0,  // pivot inside the window, endpoints inside the window
-  kReverseTail = 1,    // endpoint below the window, counted from the endpoint
+  kReverseTail = 1,    // endpoint below the window, pivot in the reverse window
   kForwardTail = 2,    // pivot below the window, counted from the pivot
+  kReverseMid = 3,     // endpoint below the window, pivot in the window but
+                       // not in the reverse window
 };
+
+// Reverse items keep two 8-bit counters per key (symmetric, asymmetric), so
+// a reverse item (or item part) has at most this many segments.
+constexpr uint32_t kReverseMaxSegs = 255;
 
 // Flags of an item.
 enum : uint32_t {
@@ -71,6 +77,7 @@ struct Item {
   int32_t acc_slot;   // multi-part accumulator slot (or -1)
   uint32_t flags;
   uint32_t side;      // side of the owner and of the keys (0 = U, 1 = V)
+  uint32_t work;      // wedges of the item (saturated at 2^32 - 1)
 };
 
 struct Reduce {       // one multi-part accumulator to reduce after its parts

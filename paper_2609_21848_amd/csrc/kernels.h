@@ -51,8 +51,10 @@ struct SmallArgs {
   const Segment* segs;
   DevSideConst side[2];
   uint32_t* queue;
+  uint32_t* acc;  // part buffers (reverse items split into parts)
   unsigned long long* res;
   int32_t n_items;
+  int32_t acc_width;
 };
 
 struct HashArgs {

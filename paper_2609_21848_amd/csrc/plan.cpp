@@ -13,7 +13,8 @@
 //                                            for each neighbour y of w, the
 //                                            entries of row y that rank above
 //                                            both R and y
-//   forward-tail    sr(x) >= R, sr(w) >= L : at pivot x, keys w >= L
+//   reverse-mid     R <= sr(x) < L <= sr(w): at endpoint w, keys x in [R, L)
+//   forward-tail    sr(x) >= L             : at pivot x, keys w in (x, n)
 // Inside the window, the pairs of the hub block (x, w < T, mid y < T on the
 // other side) are counted by the dense path; forward items skip those wedges
 // and leave their other hub-pair wedges in a pair buffer that the dense path
@@ -124,8 +125,32 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       it.acc_slot = -1;
       it.flags = flags;
       it.side = static_cast<uint32_t>(s);
+      it.work = static_cast<uint32_t>(std::min<int64_t>(work, 0xffffffffll));
       if (kind == kReverseTail) {
-        plan.reverse_items.push_back(it);
+        // parts of at most kReverseMaxSegs segments (8-bit counters)
+        if (nseg <= kReverseMaxSegs) {
+          plan.reverse_items.push_back(it);
+          return;
+        }
+        const int32_t first_slot = plan.acc_slots;
+        for (uint32_t k = 0; k < nseg; k += kReverseMaxSegs) {
+          Item part = it;
+          part.seg_begin = seg_begin + k;
+          part.seg_count = std::min(kReverseMaxSegs, nseg - k);
+          part.flags |= kItemMultiPart;
+          part.acc_slot = plan.acc_slots++;
+          part.work = static_cast<uint32_t>(std::min<int64_t>(item_work(plan, part), 0xffffffffll));
+          plan.reverse_items.push_back(part);
+        }
+        Reduce r{};
+        r.acc_slot = first_slot;
+        r.n_parts = plan.acc_slots - first_slot;
+        r.owner = owner;
+        r.key_lo = key_lo;
+        r.key_hi = key_hi;
+        r.flags = flags;
+        r.side = static_cast<uint32_t>(s);
+        plan.reduces.push_back(r);
       } else if (work <= p.small_work) {
         plan.small_items.push_back(it);
       } else if (kind == kForwardTail) {
@@ -152,22 +177,23 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         }
         place(seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
       }
-      if (x >= R) {  // keys [max(L, x + 1), n)
+      if (x >= L) {  // keys (x, n): every endpoint is below the window
         const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
         for (uint32_t e = e0; e < e1; ++e) {
           const uint32_t y = S.adj[e] >> 1;
-          const uint32_t start = std::max(O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1,
-                                          O.off[y] + static_cast<uint32_t>(splitL[y]));
+          const uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
           const uint32_t end = O.off[y + 1];
           if (end > start)
             plan.segs.push_back(Segment{start, ((end - start) << 1) | (S.adj[e] & 1u)});
         }
-        place(seg_begin, x, std::max(L, x + 1), S.n, 0u, kForwardTail);
+        place(seg_begin, x, x + 1, S.n, 0u, kForwardTail);
       }
     }
-    // Reverse items: endpoints w of side s below the window, keys x < R.
+    // Reverse items: endpoints w of side s below the window; keys x < R
+    // (reverse), then keys x in [R, L) (reverse-mid).  Within row y the keys
+    // above y form the prefix [0, cut[y]).
     for (int32_t w = L; w < S.n; ++w) {
-      const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+      uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
       for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
         const uint32_t y = S.adj[e] >> 1;
         const int32_t len = std::min(splitR[y], O.cut[y]);
@@ -175,6 +201,16 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(len) << 1) | (S.adj[e] & 1u)});
       }
       place(seg_begin, w, 0, R, 0u, kReverseTail);
+      if (R == L) continue;
+      seg_begin = static_cast<uint32_t>(plan.segs.size());
+      for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
+        const uint32_t y = S.adj[e] >> 1;
+        const int32_t end = std::min(splitL[y], O.cut[y]);
+        if (end > splitR[y])
+          plan.segs.push_back(Segment{O.off[y] + static_cast<uint32_t>(splitR[y]),
+                                      (static_cast<uint32_t>(end - splitR[y]) << 1) | (S.adj[e] & 1u)});
+      }
+      place(seg_begin, w, R, L, 0u, kReverseMid);
     }
 
     // Dense hub block of this side: B[x][y] for x < T, y < TO.
@@ -225,6 +261,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         ++c;
       }
       part.seg_count = c;
+      part.work = static_cast<uint32_t>(std::min<int64_t>(pw, 0xffffffffll));
       part.flags = it.flags | kItemMultiPart;
       part.acc_slot = plan.acc_slots++;
       parts.push_back(part);

@@ -47,7 +47,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   std::map<std::tuple<int, int, int>, std::pair<int64_t, int64_t>> hub;
   std::map<int32_t, std::vector<std::pair<int64_t, int64_t>>> parts;  // acc slot -> per key
   int64_t walked = 0;
-  auto run = [&](const Item& it) {
+  auto run = [&](const Item& it, int64_t limit) {
     const HostSide& O = g.side[1 - it.side];
     std::unordered_map<uint32_t, std::pair<int64_t, int64_t>> cnt;
     for (uint32_t k = 0; k < it.seg_count; ++k) {
@@ -62,7 +62,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
       }
     }
     for (auto& [key, pn] : cnt) {
-      if (pn.first > 65535 || pn.second > 65535) return -101;
+      if (pn.first > limit || pn.second > limit) return -101;  // packed counter overflow
       if (it.flags & kItemMultiPart) {
         auto& vec = parts[it.acc_slot];
         if (vec.empty()) vec.assign(plan.acc_width, {0, 0});
@@ -78,10 +78,12 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
     }
     return 0;
   };
-  for (auto* list : {&plan.direct_items, &plan.small_items, &plan.hash_items, &plan.reverse_items})
+  for (auto* list : {&plan.direct_items, &plan.small_items, &plan.hash_items})
     for (const Item& it : *list) {
-      if ((rc = run(it))) return rc;
+      if ((rc = run(it, 65535))) return rc;
     }
+  for (const Item& it : plan.reverse_items)
+    if ((rc = run(it, kReverseMaxSegs))) return rc;
   for (const Reduce& r : plan.reduces) {
     for (int32_t key = r.key_lo; key < r.key_hi; ++key) {
       int64_t P = 0, N = 0;

@@ -104,6 +104,18 @@ def test_dense_hub_block_paths(dbbc):
                 assert tuple(got) == want, (T, L)
 
 
+def test_reverse_parts_and_windows(dbbc):
+    # dense enough that reverse items exceed 255 segments (split into parts)
+    g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
+    want = _want(g)
+    with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
+        for opts in ({"window_L": 256, "reverse_L": 64}, {"window_L": 256, "reverse_L": 256},
+                     {"window_L": 256, "reverse_L": 128, "hub_T": 128, "small_work": 2},
+                     {"window_L": 512, "reverse_L": 192, "part_work": 4096}):
+            _say("reverse parts", opts)
+            assert tuple(h.count(**opts)) == want, opts
+
+
 def test_powerlaw2m_full_size(dbbc):
     g = config_graph("powerlaw2m")
     want = _want(g)

@@ -84,3 +84,14 @@ def test_hub_block_on_dense_graph(emul):
         o = emul(g, *cfg)
         _check(o, r)
     assert emul(g, 256, 256, 64, 4096, 128)[6] > 0
+
+
+def test_reverse_items_split_into_parts(emul):
+    # every vertex below a 256 window has about 250-300 neighbours, so reverse
+    # items exceed 255 segments and are split into parts
+    g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+    for cfg in [(0, 256, 1024, 1 << 20, 64), (0, 256, 2, 4096, 256), (128, 256, 64, 4096, 128)]:
+        o = emul(g, *cfg)
+        _check(o, r)
+        assert o[11] > 0  # multi-part reduces exist
