@@ -118,14 +118,23 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         v[u] = make_uint4(0, 0, 0, 0);
       }
     }
+    // all counter updates of the group first, then the checks on their
+    // returned values, so that the wavefront waits on the LDS once per group
+    uint32_t old[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t idx = vp[u] + q;
-        if (idx >= vst[u] && idx < vend[u]) f(e4[q], vg[u]);
+        old[u][q] = f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
       }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) f.fin(e4[q], old[u][q]);
     }
   }
   if (len >= kLong) len = 0;
@@ -146,9 +155,12 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         a[u] = t < cnt ? gbuf[t] : 0u;
         e[u] = t < cnt ? adj[a[u] & 0x7fffffffu] : 0u;
       }
+      uint32_t old[U];
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (t0 + u * kWave + lane < cnt) f(e[u], a[u] >> 31);
+        old[u] = f.add(e[u], a[u] >> 31, t0 + u * kWave + lane < cnt);
+#pragma unroll
+      for (int u = 0; u < U; ++u) f.fin(e[u], old[u]);
     }
     wave_sync_lds();
   }
@@ -181,6 +193,54 @@ __device__ __forceinline__ SegReg first_batch(const Item& it, const Segment* __r
 // Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric.
 __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
   return ((e ^ g) & 1u) ? 0x10000u : 1u;
+}
+
+// Tally functors for walk_regs: add(entry, g, valid) updates the counter of
+// the wedge's key and returns a value that is 0 exactly when a valid entry's
+// key was not yet touched by the item; fin(entry, that value) records first
+// touches.  add is branch-free: an invalid entry adds 0 to counter word 0
+// (no effect) and reports nonzero, so that a wavefront can issue all the
+// LDS atomics of a group before waiting for their results.
+struct DirectTally {  // 16 | 16-bit counters, one per key, touched bitmap
+  uint32_t* cnt;
+  uint32_t* bits;
+  __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t g, bool valid) const {
+    const uint32_t old = atomicAdd(&cnt[valid ? e >> 1 : 0u], valid ? wedge_inc(e, g) : 0u);
+    return valid ? old : 1u;
+  }
+  __device__ __forceinline__ void fin(uint32_t e, uint32_t old) const {
+    if (old == 0) atomicOr(&bits[(e >> 1) >> 5], 1u << ((e >> 1) & 31));
+  }
+};
+
+struct PairTally {  // 8 | 8-bit counters, two keys per word, touched bitmap
+  uint32_t* cnt;
+  uint32_t* bits;
+  __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t g, bool valid) const {
+    const uint32_t key = e >> 1;
+    const uint32_t sh = (key & 1u) << 4;
+    const uint32_t inc = valid ? (((e ^ g) & 1u) ? 0x100u : 1u) << sh : 0u;
+    const uint32_t old = atomicAdd(&cnt[valid ? key >> 1 : 0u], inc);
+    return valid ? (old >> sh) & 0xffffu : 1u;
+  }
+  __device__ __forceinline__ void fin(uint32_t e, uint32_t old) const {
+    if (old == 0) atomicOr(&bits[(e >> 1) >> 5], 1u << ((e >> 1) & 31));
+  }
+};
+
+// Hash tallies do all their work in add (a probe loop) and return nonzero.
+template <class G>
+struct HashTally {
+  G g;
+  __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t gb, bool valid) const {
+    if (valid) g(e, gb);
+    return 1u;
+  }
+  __device__ __forceinline__ void fin(uint32_t, uint32_t) const {}
+};
+template <class G>
+__device__ __forceinline__ HashTally<G> hash_tally(G g) {
+  return HashTally<G>{g};
 }
 
 struct Sums {
@@ -249,10 +309,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
-        const uint32_t key = e >> 1;
-        if (atomicAdd(&cnt[key], wedge_inc(e, g)) == 0) atomicOr(&bits[key >> 5], 1u << (key & 31));
-      });
+      walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], DirectTally{cnt, bits});
     }
     __syncthreads();
     if (it.flags & kItemMultiPart) {
@@ -320,13 +377,7 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     const int32_t j = i + stride;
     if (j < a.n_items) nxt = a.items[j];
     const uint32_t* __restrict__ adj = a.side[it.side].other_adj;
-    walk_item<8>(it, first, a.segs, adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
-      const uint32_t key = e >> 1;
-      const uint32_t sh = (key & 1u) << 4;
-      const uint32_t inc = (((e ^ g) & 1u) ? 0x100u : 1u) << sh;
-      if (((atomicAdd(&C[key >> 1], inc) >> sh) & 0xffffu) == 0)
-        atomicOr(&Bt[key >> 5], 1u << (key & 31));
-    });
+    walk_item<8>(it, first, a.segs, adj, gbuf[wave], PairTally{C, Bt});
     if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
     wave_sync_lds();
     if (it.flags & kItemMultiPart) {
@@ -410,7 +461,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     while (size < 2 * it.work) size <<= 1;
     const uint32_t mask = size - 1;
     {
-      walk_item<4>(it, first, a.segs, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+      walk_item<4>(it, first, a.segs, sc.other_adj, gbuf[wave], hash_tally([&](uint32_t e, uint32_t g) {
         const uint32_t key = e >> 1;
         const uint32_t inc = wedge_inc(e, g);
         uint32_t h = mix32(key) & mask;
@@ -430,7 +481,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
           }
           h = (h + 1) & mask;
         }
-      });
+      }));
     }
     if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
     wave_sync_lds();
@@ -490,7 +541,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     for (uint32_t pass = 0; pass < passes; ++pass) {
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        walk_batch<4>(a.segs, k0, k1, sc.other_adj, gbuf[wave], [&](uint32_t e, uint32_t g) {
+        walk_batch<4>(a.segs, k0, k1, sc.other_adj, gbuf[wave], hash_tally([&](uint32_t e, uint32_t g) {
           const uint32_t key = e >> 1;
           const uint32_t hk = mix32(key);
           if (passes > 1 && (hk >> 16) % passes != pass) return;
@@ -512,7 +563,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
             }
             h = (h + 1) & (kHashSlots - 1);
           }
-        });
+        }));
       }
       __syncthreads();
       for (int h = tid; h < kHashSlots; h += kHashThreads) {
