@@ -198,14 +198,16 @@ __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
 // Tally functors for walk_regs: add(entry, g, valid) updates the counter of
 // the wedge's key and returns a value that is 0 exactly when a valid entry's
 // key was not yet touched by the item; fin(entry, that value) records first
-// touches.  add is branch-free: an invalid entry adds 0 to counter word 0
-// (no effect) and reports nonzero, so that a wavefront can issue all the
-// LDS atomics of a group before waiting for their results.
+// touches.  add is branch-free: an invalid entry adds 0 to a counter word of
+// its own lane (no effect, and no two lanes of one instruction share it) and
+// reports nonzero, so that a wavefront can issue all the LDS atomics of a
+// group before waiting for their results.
 struct DirectTally {  // 16 | 16-bit counters, one per key, touched bitmap
   uint32_t* cnt;
   uint32_t* bits;
   __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t g, bool valid) const {
-    const uint32_t old = atomicAdd(&cnt[valid ? e >> 1 : 0u], valid ? wedge_inc(e, g) : 0u);
+    const uint32_t key = valid ? e >> 1 : static_cast<uint32_t>(lane_id());
+    const uint32_t old = atomicAdd(&cnt[key], valid ? wedge_inc(e, g) : 0u);
     return valid ? old : 1u;
   }
   __device__ __forceinline__ void fin(uint32_t e, uint32_t old) const {
@@ -217,11 +219,12 @@ struct PairTally {  // 8 | 8-bit counters, two keys per word, touched bitmap
   uint32_t* cnt;
   uint32_t* bits;
   __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t g, bool valid) const {
-    const uint32_t key = e >> 1;
-    const uint32_t sh = (key & 1u) << 4;
-    const uint32_t inc = valid ? (((e ^ g) & 1u) ? 0x100u : 1u) << sh : 0u;
-    const uint32_t old = atomicAdd(&cnt[valid ? key >> 1 : 0u], inc);
-    return valid ? (old >> sh) & 0xffffu : 1u;
+    // the entry's low bits select the half-word: bit 0 (negative) ^ g picks
+    // the symmetric / asymmetric byte, bit 1 (key parity) the 16-bit half
+    const uint32_t sh = ((e ^ g) & 3u) << 3;
+    const uint32_t word = valid ? e >> 2 : static_cast<uint32_t>(lane_id());
+    const uint32_t old = atomicAdd(&cnt[word], valid ? 1u << sh : 0u);
+    return valid ? (old >> (sh & 16u)) & 0xffffu : 1u;
   }
   __device__ __forceinline__ void fin(uint32_t e, uint32_t old) const {
     if (old == 0) atomicOr(&bits[(e >> 1) >> 5], 1u << ((e >> 1) & 31));
