@@ -49,8 +49,10 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) 
   return inc - x;
 }
 
+// Order this wavefront's LDS accesses (not its global loads, which may stay
+// in flight, e.g. prefetches of the next item).
 __device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -103,19 +105,19 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         cur_pos = cur_st & ~3u;
         have = true;
       }
+      // The load is unconditional (no wait on registers of a skipped load):
+      // lanes past the segment end and empty slots read the first entries of
+      // the array, and their words fail the index test below.
+      const bool h = have;
+      const uint32_t p = cur_pos + 4 * lane;
       vst[u] = cur_st;
       vg[u] = cur_g;
-      if (have) {
-        const uint32_t p = cur_pos + 4 * lane;
-        vp[u] = p;
-        vend[u] = cur_end;
-        v[u] = p < cur_end ? *reinterpret_cast<const uint4*>(adj + p) : make_uint4(0, 0, 0, 0);
+      vp[u] = p;
+      vend[u] = h ? cur_end : 0u;
+      v[u] = *reinterpret_cast<const uint4*>(adj + ((h && p < cur_end) ? p : 0u));
+      if (h) {
         cur_pos += kChunk;
         if (cur_pos >= cur_end) have = false;
-      } else {
-        vp[u] = 0;
-        vend[u] = 0;
-        v[u] = make_uint4(0, 0, 0, 0);
       }
     }
     // all counter updates of the group first, then the checks on their
@@ -147,20 +149,20 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
     for (uint32_t t = lo; t < hi; ++t) gbuf[t - done] = (start + (t - excl)) | (g << 31);
     wave_sync_lds();
     const uint32_t cnt = total - done < kGather ? total - done : kGather;
-    for (uint32_t t0 = 0; t0 < cnt; t0 += kWave * U) {
-      uint32_t a[U], e[U];
+    constexpr int UG = U < static_cast<int>(kGather / kWave) ? U : static_cast<int>(kGather / kWave);
+    for (uint32_t t0 = 0; t0 < cnt; t0 += kWave * UG) {
+      uint32_t a[UG], e[UG];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UG; ++u) {
         const uint32_t t = t0 + u * kWave + lane;
-        a[u] = t < cnt ? gbuf[t] : 0u;
-        e[u] = t < cnt ? adj[a[u] & 0x7fffffffu] : 0u;
+        a[u] = gbuf[t < cnt ? t : 0u];
+        e[u] = adj[t < cnt ? a[u] & 0x7fffffffu : 0u];
       }
-      uint32_t old[U];
+      uint32_t old[UG];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        old[u] = f.add(e[u], a[u] >> 31, t0 + u * kWave + lane < cnt);
+      for (int u = 0; u < UG; ++u) old[u] = f.add(e[u], a[u] >> 31, t0 + u * kWave + lane < cnt);
 #pragma unroll
-      for (int u = 0; u < U; ++u) f.fin(e[u], old[u]);
+      for (int u = 0; u < UG; ++u) f.fin(e[u], old[u]);
     }
     wave_sync_lds();
   }
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     const int32_t j = i + stride;
     if (j < a.n_items) nxt = a.items[j];
     const uint32_t* __restrict__ adj = a.side[it.side].other_adj;
-    walk_item<8>(it, first, a.segs, adj, gbuf[wave], PairTally{C, Bt});
+    walk_item<4>(it, first, a.segs, adj, gbuf[wave], PairTally{C, Bt});
     if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
     wave_sync_lds();
     if (it.flags & kItemMultiPart) {
