@@ -37,16 +37,26 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int j) {
   return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), j));
 }
 
-// exclusive prefix sum over the wavefront
+// DPP move of v within the wavefront (lanes without a source read 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), kCtrl, kRowMask, 0xf, false));
+}
+
+// Exclusive prefix sum over the wavefront with DPP: an inclusive scan inside
+// each row of 16 lanes (row_shr 1, 2, 4, 8), then row_bcast:15 and
+// row_bcast:31 carry the row totals upward.
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
-  uint32_t inc = x;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    uint32_t y = __shfl_up(inc, d, kWave);
-    if (lane_id() >= d) inc += y;
-  }
-  *total = __shfl(inc, kWave - 1, kWave);
-  return inc - x;
+  uint32_t v = x;
+  v += dpp<0x111, 0xf>(v);  // row_shr:1
+  v += dpp<0x112, 0xf>(v);  // row_shr:2
+  v += dpp<0x114, 0xf>(v);  // row_shr:4
+  v += dpp<0x118, 0xf>(v);  // row_shr:8
+  v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  *total = readlane(v, kWave - 1);
+  return v - x;
 }
 
 // Order this wavefront's LDS accesses (not its global loads, which may stay
@@ -120,23 +130,14 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         if (cur_pos >= cur_end) have = false;
       }
     }
-    // all counter updates of the group first, then the checks on their
-    // returned values, so that the wavefront waits on the LDS once per group
-    uint32_t old[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t idx = vp[u] + q;
-        old[u][q] = f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
+        f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
       }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) f.fin(e4[q], old[u][q]);
     }
   }
   if (len >= kLong) len = 0;
@@ -158,11 +159,8 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         a[u] = gbuf[t < cnt ? t : 0u];
         e[u] = adj[t < cnt ? a[u] & 0x7fffffffu : 0u];
       }
-      uint32_t old[UG];
 #pragma unroll
-      for (int u = 0; u < UG; ++u) old[u] = f.add(e[u], a[u] >> 31, t0 + u * kWave + lane < cnt);
-#pragma unroll
-      for (int u = 0; u < UG; ++u) f.fin(e[u], old[u]);
+      for (int u = 0; u < UG; ++u) f.add(e[u], a[u] >> 31, t0 + u * kWave + lane < cnt);
     }
     wave_sync_lds();
   }
@@ -197,51 +195,32 @@ __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
   return ((e ^ g) & 1u) ? 0x10000u : 1u;
 }
 
-// Tally functors for walk_regs: add(entry, g, valid) updates the counter of
-// the wedge's key and returns a value that is 0 exactly when a valid entry's
-// key was not yet touched by the item; fin(entry, that value) records first
-// touches.  add is branch-free: an invalid entry adds 0 to a counter word of
-// its own lane (no effect, and no two lanes of one instruction share it) and
-// reports nonzero, so that a wavefront can issue all the LDS atomics of a
-// group before waiting for their results.
-struct DirectTally {  // 16 | 16-bit counters, one per key, touched bitmap
+// Tally functors for walk_regs: add(entry, g, valid) counts a valid
+// entry's wedge in the counter of its key (a non-returning LDS atomic, so a
+// wavefront never waits on its own counter updates).
+struct DirectTally {  // 16 | 16-bit counters, one 32-bit word per key
   uint32_t* cnt;
-  uint32_t* bits;
-  __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t g, bool valid) const {
-    const uint32_t key = valid ? e >> 1 : static_cast<uint32_t>(lane_id());
-    const uint32_t old = atomicAdd(&cnt[key], valid ? wedge_inc(e, g) : 0u);
-    return valid ? old : 1u;
-  }
-  __device__ __forceinline__ void fin(uint32_t e, uint32_t old) const {
-    if (old == 0) atomicOr(&bits[(e >> 1) >> 5], 1u << ((e >> 1) & 31));
+  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
+    if (valid) atomicAdd(&cnt[e >> 1], wedge_inc(e, g));
   }
 };
 
-struct PairTally {  // 8 | 8-bit counters, two keys per word, touched bitmap
+struct PairTally {  // 8 | 8-bit counters, two keys per 32-bit word
   uint32_t* cnt;
-  uint32_t* bits;
-  __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t g, bool valid) const {
-    // the entry's low bits select the half-word: bit 0 (negative) ^ g picks
-    // the symmetric / asymmetric byte, bit 1 (key parity) the 16-bit half
-    const uint32_t sh = ((e ^ g) & 3u) << 3;
-    const uint32_t word = valid ? e >> 2 : static_cast<uint32_t>(lane_id());
-    const uint32_t old = atomicAdd(&cnt[word], valid ? 1u << sh : 0u);
-    return valid ? (old >> (sh & 16u)) & 0xffffu : 1u;
-  }
-  __device__ __forceinline__ void fin(uint32_t e, uint32_t old) const {
-    if (old == 0) atomicOr(&bits[(e >> 1) >> 5], 1u << ((e >> 1) & 31));
+  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
+    // the entry's low bits select the byte: bit 0 (negative) ^ g picks the
+    // symmetric / asymmetric byte, bit 1 (key parity) the 16-bit half
+    if (valid) atomicAdd(&cnt[e >> 2], 1u << (((e ^ g) & 3u) << 3));
   }
 };
 
-// Hash tallies do all their work in add (a probe loop) and return nonzero.
+// Hash tallies do all their work in add (a probe loop).
 template <class G>
 struct HashTally {
   G g;
-  __device__ __forceinline__ uint32_t add(uint32_t e, uint32_t gb, bool valid) const {
+  __device__ __forceinline__ void add(uint32_t e, uint32_t gb, bool valid) const {
     if (valid) g(e, gb);
-    return 1u;
   }
-  __device__ __forceinline__ void fin(uint32_t, uint32_t) const {}
 };
 template <class G>
 __device__ __forceinline__ HashTally<G> hash_tally(G g) {
@@ -287,21 +266,20 @@ __device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, u
 
 // ---------------------------------------------------------------------------
 // Window items: one workgroup per item (or item part), counters for keys
-// [0, L) in LDS and a bitmap of the keys the item touched.
+// [0, L) in LDS; the sweep reads the item's whole key window.
 constexpr int kDirectThreads = 1024;
 constexpr int kDirectWaves = kDirectThreads / kWave;
 constexpr int kDirectKeys = 32768;
-constexpr int kDirectWords = kDirectKeys / 32;  // == kDirectThreads
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t cnt[kDirectKeys];
-  __shared__ uint32_t bits[kDirectWords];
   __shared__ uint32_t gbuf[kDirectWaves][kGather];
   __shared__ int32_t item_sh;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
-  for (int i = tid; i < kDirectWords; i += kDirectThreads) bits[i] = 0;
+  // staged slots always hold valid entry indices
+  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&gbuf[0][0])[i] = 0;
   Sums sums;
   for (;;) {
     if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
@@ -314,7 +292,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], DirectTally{cnt, bits});
+      walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], DirectTally{cnt});
     }
     __syncthreads();
     if (it.flags & kItemMultiPart) {
@@ -324,19 +302,17 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
         dst[key] = cnt[key];
         cnt[key] = 0;
       }
-      bits[tid] = 0;
     } else {
-      uint32_t word = bits[tid];
-      if (word) {
-        bits[tid] = 0;
-        while (word) {
-          const int b = __ffs(word) - 1;
-          word &= word - 1;
-          const uint32_t key = static_cast<uint32_t>(tid) * 32 + b;
-          const uint32_t c = cnt[key];
-          cnt[key] = 0;
-          emit(it, key, c & 0xffffu, c >> 16, sc, sums);
-        }
+      const uint32_t lo = static_cast<uint32_t>(it.key_lo) & ~3u;
+      const uint32_t hi = static_cast<uint32_t>(it.key_hi);
+      for (uint32_t key = lo + 4 * tid; key < hi; key += 4 * kDirectThreads) {
+        const uint4 c4 = *reinterpret_cast<uint4*>(&cnt[key]);
+        if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
+        const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (cv[j]) emit(it, key + j, cv[j] & 0xffffu, cv[j] >> 16, sc, sums);
+        *reinterpret_cast<uint4*>(&cnt[key]) = make_uint4(0, 0, 0, 0);
       }
     }
     __syncthreads();
@@ -346,26 +322,37 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 
 // ---------------------------------------------------------------------------
 // Reverse items: one wavefront per item, a private LDS direct array over the
-// reverse window [0, R) (R <= kMaxReverseL) and a bitmap of touched keys.
-// Counters are 8-bit (symmetric | asymmetric << 8) in 16-bit halves, two
-// keys per 32-bit word: an item (or part) has at most kReverseMaxSegs
-// segments, so no half overflows.  Items are dealt to wavefronts in a fixed
-// stride and the next item's descriptor and first segments are loaded while
-// the current one is walked.
+// reverse window [0, R) (R <= kMaxReverseL).  Counters are 8-bit
+// (symmetric | asymmetric << 8) in 16-bit halves, two keys per 32-bit word:
+// an item (or part) has at most kReverseMaxSegs segments, so no byte
+// overflows.  Items are dealt to wavefronts in a fixed stride and the next
+// item's descriptor and first segments are loaded while the current one is
+// walked; the sweep reads the whole window with 16-byte LDS loads.
 constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
-constexpr int kReverseWords = kMaxReverseL / 32;
+constexpr int kReverseWords = kMaxReverseL / 2;
+
+__device__ __forceinline__ void add_pair_word(uint32_t c2, Sums& s) {
+  // two keys of one counter word; all counts are at most 255, so the
+  // per-word products fit 32 bits
+  const uint32_t p0 = c2 & 0xffu, n0 = (c2 >> 8) & 0xffu;
+  const uint32_t p1 = (c2 >> 16) & 0xffu, n1 = c2 >> 24;
+  const uint32_t bal = (p0 * (p0 - 1) + n0 * (n0 - 1) + p1 * (p1 - 1) + n1 * (n1 - 1)) >> 1;
+  const uint32_t unb = p0 * n0 + p1 * n1;
+  const uint32_t t0 = p0 + n0, t1 = p1 + n1;
+  s.bal += bal;
+  s.unb += unb;
+  s.tot += (t0 * (t0 - 1) + t1 * (t1 - 1)) >> 1;
+}
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
-  __shared__ uint32_t cnt[kReverseWaves][kMaxReverseL / 2];
-  __shared__ uint32_t bits[kReverseWaves][kReverseWords];
+  __shared__ uint32_t cnt[kReverseWaves][kReverseWords];
   __shared__ uint32_t gbuf[kReverseWaves][kGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
-  uint32_t* Bt = bits[wave];
-  for (int i = lane; i < kMaxReverseL / 2; i += kWave) C[i] = 0;
-  for (int i = lane; i < kReverseWords; i += kWave) Bt[i] = 0;
+  for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) gbuf[wave][i] = 0;
   wave_sync_lds();
   Sums sums;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kReverseWaves;
@@ -382,34 +369,27 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     const int32_t j = i + stride;
     if (j < a.n_items) nxt = a.items[j];
     const uint32_t* __restrict__ adj = a.side[it.side].other_adj;
-    walk_item<4>(it, first, a.segs, adj, gbuf[wave], PairTally{C, Bt});
+    walk_item<4>(it, first, a.segs, adj, gbuf[wave], PairTally{C});
     if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
     wave_sync_lds();
+    const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the window
     if (it.flags & kItemMultiPart) {
       uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
-      for (int32_t key = it.key_lo + lane; key < it.key_hi; key += kWave) {
-        const uint32_t c = (C[key >> 1] >> ((key & 1) << 4)) & 0xffffu;
-        dst[key] = (c & 0xffu) | ((c >> 8) << 16);
+      for (int32_t wd = lane; wd < w_hi; wd += kWave) {
+        const uint32_t c2 = C[wd];
+        C[wd] = 0;
+        dst[2 * wd] = (c2 & 0xffu) | (((c2 >> 8) & 0xffu) << 16);
+        if (2 * wd + 1 < it.key_hi) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
       }
-      wave_sync_lds();
-      for (int w2 = lane; w2 < kMaxReverseL / 2; w2 += kWave) C[w2] = 0;
-      for (int w2 = lane; w2 < kReverseWords; w2 += kWave) Bt[w2] = 0;
     } else {
-      for (int wi = lane; wi < kReverseWords; wi += kWave) {
-        const uint32_t word = Bt[wi];
-        if (!word) continue;
-        Bt[wi] = 0;
-        // keys 2q and 2q + 1 share counter word 16 * wi + q
-        uint32_t pairs = (word | (word >> 1)) & 0x55555555u;
-        while (pairs) {
-          const int b = __ffs(pairs) - 1;
-          pairs &= pairs - 1;
-          const int q = b >> 1;
-          const uint32_t c2 = C[wi * 16 + q];
-          C[wi * 16 + q] = 0;
-          if ((word >> b) & 1u) sums.add(c2 & 0xffu, (c2 >> 8) & 0xffu);
-          if ((word >> (b + 1)) & 1u) sums.add((c2 >> 16) & 0xffu, c2 >> 24);
-        }
+      for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
+        const uint4 c4 = *reinterpret_cast<uint4*>(&C[wd]);
+        if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
+        *reinterpret_cast<uint4*>(&C[wd]) = make_uint4(0, 0, 0, 0);
+        add_pair_word(c4.x, sums);
+        add_pair_word(c4.y, sums);
+        add_pair_word(c4.z, sums);
+        add_pair_word(c4.w, sums);
       }
     }
     wave_sync_lds();
@@ -445,6 +425,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     K[i] = kEmpty;
     Vv[i] = 0;
   }
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) gbuf[wave][i] = 0;
   wave_sync_lds();
   Sums sums;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kSmallWaves;
@@ -524,6 +505,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     keys[i] = kEmpty;
     vals[i] = 0;
   }
+  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&gbuf[0][0])[i] = 0;
   Sums sums;
   for (;;) {
     if (tid == 0) {
