@@ -237,7 +237,7 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     side[s].other_adj = g->adj[1 - s].as<uint32_t>();
     side[s].hub_pairs = d.hub_pairs[s].as<unsigned long long>();
     side[s].T = hp.T[s];
-    side[s].pad = 0;
+    side[s].R = hp.R[s];
     if (hp.T[s] > 0)
       HIP_TRY(dbbc::launch_fill_u64(side[s].hub_pairs, static_cast<size_t>(hp.T[s]) * hp.T[s], 0ull, st));
   }

@@ -83,22 +83,49 @@ __device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uin
   return r;
 }
 
+// Stage the short-segment wedges with flat positions [done, done + G) of the
+// batch into gbuf as (entry index | g << 31).
+template <int G>
+__device__ __forceinline__ void stage_short(uint32_t* gbuf, uint32_t excl, uint32_t slen, uint32_t start,
+                                            uint32_t g, uint32_t done) {
+  const uint32_t lo = excl > done ? excl : done;
+  const uint32_t hi_a = excl + slen, hi_b = done + G;
+  const uint32_t hi = hi_a < hi_b ? hi_a : hi_b;
+  for (uint32_t t = lo; t < hi; ++t) gbuf[t - done] = (start + (t - excl)) | (g << 31);
+}
+
 // Walk a batch of up to 64 segments (one per lane, in registers) with one
-// wavefront, calling f(entry, g) once per wedge.
+// wavefront, calling f.add(entry, g, valid) once per wedge slot.
 //  - Segments of at least kLong entries are consumed as a stream of
 //    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
 //    chunk, U chunks are in flight per lane, and a chunk's out-of-segment
 //    words are masked.  The chunk loop is wavefront-uniform.
-//  - Shorter segments are staged through gbuf (kGather words of LDS owned by
-//    this wavefront) as (index | g << 31) so that lanes read consecutive
-//    wedges, again U loads in flight per lane.
-template <int U, class F>
+//  - Shorter segments are staged through gbuf (G words of LDS owned by this
+//    wavefront) so that lanes read consecutive wedges.  The loads of the
+//    first G staged wedges are issued before the long-segment stream, so the
+//    two paths wait on memory together.
+template <int U, int G, class F>
 __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, uint32_t* gbuf,
                                           F&& f) {
+  constexpr int UG = G / kWave;
   const int lane = lane_id();
-  const uint32_t start = sr.start, g = sr.g;
-  uint32_t len = sr.len;
+  const uint32_t start = sr.start, g = sr.g, len = sr.len;
   uint64_t longm = __ballot(len >= kLong);
+  const uint32_t slen = len >= kLong ? 0u : len;
+  uint32_t total;
+  const uint32_t excl = wave_excl_scan(slen, &total);
+  const uint32_t cnt0 = total < static_cast<uint32_t>(G) ? total : static_cast<uint32_t>(G);
+  uint32_t sa[UG], se[UG];
+  if (total) {
+    stage_short<G>(gbuf, excl, slen, start, g, 0);
+    wave_sync_lds();
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+      const uint32_t t = u * kWave + lane;
+      sa[u] = gbuf[t < cnt0 ? t : 0u];
+      se[u] = adj[t < cnt0 ? sa[u] & 0x7fffffffu : 0u];
+    }
+  }
   uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
   while (longm || have) {
@@ -140,48 +167,42 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       }
     }
   }
-  if (len >= kLong) len = 0;
-  uint32_t total;
-  const uint32_t excl = wave_excl_scan(len, &total);
-  for (uint32_t done = 0; done < total; done += kGather) {
-    const uint32_t lo = excl > done ? excl : done;
-    const uint32_t hi_a = excl + len, hi_b = done + kGather;
-    const uint32_t hi = hi_a < hi_b ? hi_a : hi_b;
-    for (uint32_t t = lo; t < hi; ++t) gbuf[t - done] = (start + (t - excl)) | (g << 31);
+  if (!total) return;
+#pragma unroll
+  for (int u = 0; u < UG; ++u) f.add(se[u], sa[u] >> 31, u * kWave + lane < cnt0);
+  for (uint32_t done = G; done < total; done += G) {
     wave_sync_lds();
-    const uint32_t cnt = total - done < kGather ? total - done : kGather;
-    constexpr int UG = U < static_cast<int>(kGather / kWave) ? U : static_cast<int>(kGather / kWave);
-    for (uint32_t t0 = 0; t0 < cnt; t0 += kWave * UG) {
-      uint32_t a[UG], e[UG];
+    stage_short<G>(gbuf, excl, slen, start, g, done);
+    wave_sync_lds();
+    const uint32_t cnt = total - done < static_cast<uint32_t>(G) ? total - done : static_cast<uint32_t>(G);
 #pragma unroll
-      for (int u = 0; u < UG; ++u) {
-        const uint32_t t = t0 + u * kWave + lane;
-        a[u] = gbuf[t < cnt ? t : 0u];
-        e[u] = adj[t < cnt ? a[u] & 0x7fffffffu : 0u];
-      }
-#pragma unroll
-      for (int u = 0; u < UG; ++u) f.add(e[u], a[u] >> 31, t0 + u * kWave + lane < cnt);
+    for (int u = 0; u < UG; ++u) {
+      const uint32_t t = u * kWave + lane;
+      sa[u] = gbuf[t < cnt ? t : 0u];
+      se[u] = adj[t < cnt ? sa[u] & 0x7fffffffu : 0u];
     }
-    wave_sync_lds();
+#pragma unroll
+    for (int u = 0; u < UG; ++u) f.add(se[u], sa[u] >> 31, u * kWave + lane < cnt);
   }
+  wave_sync_lds();
 }
 
-template <int U, class F>
+template <int U, int G = kGather, class F>
 __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
                                            const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
-  walk_regs<U>(load_seg(segs, k0, k1), adj, gbuf, f);
+  walk_regs<U, G>(load_seg(segs, k0, k1), adj, gbuf, f);
 }
 
 // Walk every segment of an item with one wavefront; the first batch of 64
 // segments was loaded beforehand (first).
-template <int U, class F>
+template <int U, int G = kGather, class F>
 __device__ __forceinline__ void walk_item(const Item& it, SegReg first, const Segment* __restrict__ segs,
                                           const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
   const uint32_t seg_end = it.seg_begin + it.seg_count;
-  walk_regs<U>(first, adj, gbuf, f);
+  walk_regs<U, G>(first, adj, gbuf, f);
   for (uint32_t k0 = it.seg_begin + kWave; k0 < seg_end; k0 += kWave) {
     const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-    walk_regs<U>(load_seg(segs, k0, k1), adj, gbuf, f);
+    walk_regs<U, G>(load_seg(segs, k0, k1), adj, gbuf, f);
   }
 }
 
@@ -325,61 +346,110 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 // reverse window [0, R) (R <= kMaxReverseL).  Counters are 8-bit
 // (symmetric | asymmetric << 8) in 16-bit halves, two keys per 32-bit word:
 // an item (or part) has at most kReverseMaxSegs segments, so no byte
-// overflows.  Items are dealt to wavefronts in a fixed stride and the next
-// item's descriptor and first segments are loaded while the current one is
-// walked; the sweep reads the whole window with 16-byte LDS loads.
+// overflows.  Items flagged kItemMidHash also carry a few keys in [R, L);
+// those go to a per-wavefront hash whose 32-bit slots hold
+// (key - R + 1) << 16 | asymmetric << 8 | symmetric.
+// Items are dealt to wavefronts in a fixed stride; the next item's first
+// segments and the descriptor of the one after are loaded while the current
+// item is walked.  The sweep reads the whole window with 16-byte LDS loads.
 constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
+constexpr int kReverseGather = 128;
+
+__device__ __forceinline__ void add_pn(uint32_t p, uint32_t n, Sums& s) {
+  // p, n <= 255: the products fit 32 bits
+  s.bal += (p * (p - 1) + n * (n - 1)) >> 1;
+  s.unb += p * n;
+  s.tot += ((p + n) * (p + n - 1)) >> 1;
+}
 
 __device__ __forceinline__ void add_pair_word(uint32_t c2, Sums& s) {
-  // two keys of one counter word; all counts are at most 255, so the
-  // per-word products fit 32 bits
-  const uint32_t p0 = c2 & 0xffu, n0 = (c2 >> 8) & 0xffu;
-  const uint32_t p1 = (c2 >> 16) & 0xffu, n1 = c2 >> 24;
-  const uint32_t bal = (p0 * (p0 - 1) + n0 * (n0 - 1) + p1 * (p1 - 1) + n1 * (n1 - 1)) >> 1;
-  const uint32_t unb = p0 * n0 + p1 * n1;
-  const uint32_t t0 = p0 + n0, t1 = p1 + n1;
-  s.bal += bal;
-  s.unb += unb;
-  s.tot += (t0 * (t0 - 1) + t1 * (t1 - 1)) >> 1;
+  add_pn(c2 & 0xffu, (c2 >> 8) & 0xffu, s);
+  add_pn((c2 >> 16) & 0xffu, c2 >> 24, s);
 }
+
+struct RevTally {
+  uint32_t* cnt;
+  uint32_t* hsh;
+  uint32_t R;
+  unsigned long long* res;
+  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
+    if (!valid) return;
+    const uint32_t key = e >> 1;
+    if (key < R) {
+      // bit 0 (negative) ^ g picks the symmetric / asymmetric byte, bit 1
+      // (key parity) the 16-bit half of the word
+      atomicAdd(&cnt[e >> 2], 1u << (((e ^ g) & 3u) << 3));
+      return;
+    }
+    const uint32_t k = key - R + 1;
+    const uint32_t inc = ((e ^ g) & 1u) ? 0x100u : 1u;
+    uint32_t h = (k * 0x9e3779b1u) >> 24;
+    for (int probe = 0; probe < kMidHashSlots; ++probe) {
+      const uint32_t cur = hsh[h];
+      if ((cur >> 16) == k) {
+        atomicAdd(&hsh[h], inc);
+        return;
+      }
+      if (cur == 0) {
+        const uint32_t old = atomicCAS(&hsh[h], 0u, (k << 16) | inc);
+        if (old == 0) return;
+        if ((old >> 16) == k) {
+          atomicAdd(&hsh[h], inc);
+          return;
+        }
+      }
+      h = (h + 1) & (kMidHashSlots - 1);
+    }
+    atomicOr(res + kResError, kErrHashFull);  // cannot happen at load <= 1/2
+  }
+};
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kReverseWaves][kReverseWords];
-  __shared__ uint32_t gbuf[kReverseWaves][kGather];
+  __shared__ uint32_t hsh[kReverseWaves][kMidHashSlots];
+  __shared__ uint32_t gbuf[kReverseWaves][kReverseGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
+  uint32_t* H = hsh[wave];
   for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) gbuf[wave][i] = 0;
+  for (int i = lane; i < kMidHashSlots; i += kWave) H[i] = 0;
+  for (int i = lane; i < kReverseGather; i += kWave) gbuf[wave][i] = 0;
   wave_sync_lds();
   Sums sums;
+  const int32_t n = a.n_items;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kReverseWaves;
   int32_t i = static_cast<int32_t>(blockIdx.x) * kReverseWaves + wave;
-  Item nxt{};
-  SegReg nfirst{0, 0, 0};
-  if (i < a.n_items) {
-    nxt = a.items[i];
-    nfirst = first_batch(nxt, a.segs);
+  Item cur{}, nxt{};
+  SegReg cfirst{0, 0, 0};
+  if (i < n) {
+    cur = a.items[i];
+    cfirst = first_batch(cur, a.segs);
   }
-  for (; i < a.n_items; i += stride) {
-    const Item it = nxt;
-    const SegReg first = nfirst;
-    const int32_t j = i + stride;
-    if (j < a.n_items) nxt = a.items[j];
-    const uint32_t* __restrict__ adj = a.side[it.side].other_adj;
-    walk_item<4>(it, first, a.segs, adj, gbuf[wave], PairTally{C});
-    if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
+  if (i + stride < n) nxt = a.items[i + stride];
+  for (; i < n; i += stride) {
+    const Item it = cur;
+    const SegReg first = cfirst;
+    const int32_t j = i + stride, j2 = j + stride;
+    SegReg nfirst{0, 0, 0};
+    if (j < n) nfirst = first_batch(nxt, a.segs);
+    Item nxt2{};
+    if (j2 < n) nxt2 = a.items[j2];
+    const DevSideConst sc = a.side[it.side];
+    walk_item<4, kReverseGather>(it, first, a.segs, sc.other_adj, gbuf[wave],
+                                 RevTally{C, H, static_cast<uint32_t>(sc.R), a.res});
     wave_sync_lds();
-    const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the window
+    const int32_t kh = it.key_hi < sc.R ? it.key_hi : sc.R;
+    const int32_t w_hi = (kh + 1) >> 1;  // counter words of the direct window
     if (it.flags & kItemMultiPart) {
       uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
       for (int32_t wd = lane; wd < w_hi; wd += kWave) {
         const uint32_t c2 = C[wd];
         C[wd] = 0;
         dst[2 * wd] = (c2 & 0xffu) | (((c2 >> 8) & 0xffu) << 16);
-        if (2 * wd + 1 < it.key_hi) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
+        if (2 * wd + 1 < kh) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
       }
     } else {
       for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
@@ -391,8 +461,21 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
         add_pair_word(c4.z, sums);
         add_pair_word(c4.w, sums);
       }
+      if (it.flags & kItemMidHash) {
+        const uint4 h4 = *reinterpret_cast<uint4*>(&H[4 * lane]);
+        if (h4.x | h4.y | h4.z | h4.w) {
+          *reinterpret_cast<uint4*>(&H[4 * lane]) = make_uint4(0, 0, 0, 0);
+          const uint32_t hv[4] = {h4.x, h4.y, h4.z, h4.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (hv[q]) add_pn(hv[q] & 0xffu, (hv[q] >> 8) & 0xffu, sums);
+        }
+      }
     }
     wave_sync_lds();
+    cur = nxt;
+    cfirst = nfirst;
+    nxt = nxt2;
   }
   flush_sums(sums, a.res);
 }

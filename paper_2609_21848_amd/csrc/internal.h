@@ -66,6 +66,7 @@ constexpr uint32_t kReverseMaxSegs = 255;
 enum : uint32_t {
   kItemMultiPart = 1u,  // partial counts go to a global accumulator
   kItemHubPairs = 2u,   // keys below hub_T are flushed to the hub-pair buffer
+  kItemMidHash = 4u,    // reverse item whose keys in [R, L) go to a small hash
 };
 
 struct Item {
@@ -104,6 +105,12 @@ struct PlanParams {
 // Largest reverse window: keys of a reverse item index a per-wavefront LDS
 // array of this many counters.
 constexpr int32_t kMaxReverseL = 4096;
+
+// A reverse item may also carry the keys in [R, L) of its endpoint when it
+// has at most this many wedges there; they are counted in a per-wavefront
+// hash of kMidHashSlots slots (load factor at most 1/2).
+constexpr int32_t kMidHashSlots = 256;
+constexpr int32_t kMidHashWork = kMidHashSlots / 2;
 
 struct HostPlan {
   PlanParams p;

@@ -32,7 +32,7 @@ struct DevSideConst {
   const uint32_t* other_adj;     // CSR entries of the other side (entries are side-s ranks)
   unsigned long long* hub_pairs; // [T x T] packed (asym << 32) | sym, or null
   int32_t T;                     // hub rows of side s (0 = no dense path)
-  int32_t pad;
+  int32_t R;                     // reverse window of side s
 };
 
 struct DirectArgs {

@@ -191,8 +191,31 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     }
     // Reverse items: endpoints w of side s below the window; keys x < R
     // (reverse), then keys x in [R, L) (reverse-mid).  Within row y the keys
-    // above y form the prefix [0, cut[y]).
+    // above y form the prefix [0, cut[y]).  When the keys in [R, L) have few
+    // wedges, one item walks both ranges (one run [0, min(splitL, cut)) per
+    // neighbour) and counts the upper keys in a small hash.
     for (int32_t w = L; w < S.n; ++w) {
+      if (R < L) {
+        int64_t mid_work = 0;
+        uint32_t nseg = 0;
+        for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
+          const uint32_t y = S.adj[e] >> 1;
+          const int32_t end = std::min(splitL[y], O.cut[y]);
+          mid_work += std::max(0, end - splitR[y]);
+          nseg += end > 0;
+        }
+        if (mid_work > 0 && mid_work <= kMidHashWork && nseg <= kReverseMaxSegs) {
+          const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+          for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
+            const uint32_t y = S.adj[e] >> 1;
+            const int32_t end = std::min(splitL[y], O.cut[y]);
+            if (end > 0)
+              plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(end) << 1) | (S.adj[e] & 1u)});
+          }
+          place(seg_begin, w, 0, L, kItemMidHash, kReverseTail);
+          continue;
+        }
+      }
       uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
       for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
         const uint32_t y = S.adj[e] >> 1;

@@ -61,6 +61,11 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
         ++walked;
       }
     }
+    if (it.flags & kItemMidHash) {  // the small hash of upper keys must not fill up
+      int64_t upper = 0;
+      for (auto& kv : cnt) upper += (int32_t)kv.first >= plan.R[it.side];
+      if (upper > kMidHashWork) return -104;
+    }
     for (auto& [key, pn] : cnt) {
       if (pn.first > limit || pn.second > limit) return -101;  // packed counter overflow
       if (it.flags & kItemMultiPart) {
