@@ -91,6 +91,11 @@ def main():
     ap.add_argument("--config", default="skewed50m", choices=sorted(WORKLOADS))
     ap.add_argument("--hub-T", type=int, default=-1)
     ap.add_argument("--window-L", type=int, default=-1)
+    ap.add_argument("--reverse-L", type=int, default=-1)
+    ap.add_argument("--mid-work", type=int, default=-1)
+    ap.add_argument("--sweep", default="",
+                    help="option sets to time after the main run, e.g. "
+                         "'hub_T=4096;mid_work=0,reverse_L=2048' (reported on stderr)")
     ap.add_argument("--cpu-fraction", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -122,7 +127,8 @@ def main():
     w_vp = st["wedges_vp"]
     log(f"[bench] graph built in {t_build:.2f}s; W_VP={w_vp}; device bytes={st['device_bytes']}")
 
-    opts = dict(hub_T=args.hub_T, window_L=args.window_L)
+    opts = dict(hub_T=args.hub_T, window_L=args.window_L, reverse_L=args.reverse_L,
+                mid_work=args.mid_work)
     t = time.perf_counter()
     first = h.count(**opts)
     t_first = time.perf_counter() - t
@@ -192,7 +198,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
-                   "hub_T": args.hub_T, "window_L": args.window_L},
+                   "hub_T": args.hub_T, "window_L": args.window_L,
+                   "reverse_L": args.reverse_L, "mid_work": args.mid_work},
         "roofline": roof,
         "balanced_per_s": first.balanced * args.steps / steps_s,
         "butterflies_per_s": first.total * args.steps / steps_s,
@@ -203,6 +210,25 @@ def main():
         "t_first_count_s": t_first,
         "kernels": kernels,
     }
+    for spec in filter(None, args.sweep.split(";")):
+        sopts = dict(opts)
+        for kv in spec.split(","):
+            k, v = kv.split("=")
+            sopts[k.strip()] = int(v)
+        c = h.count(**sopts)
+        assert c == first, f"counts changed under {sopts}"
+        sopts["flags"] = dbbc.DBBC_OPT_TIME_KERNELS
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ks = {}
+        for _ in range(args.steps):
+            h.count(**sopts)
+            for k in h.kernel_times():
+                ks[k["name"]] = ks.get(k["name"], 0.0) + k["ms"] / args.steps
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ts) * 1e3 / args.steps
+        log(f"[sweep] {spec}: {ms:.3f} ms/step " +
+            " ".join(f"{k}={v:.3f}" for k, v in ks.items()))
     h.close()
     if not args.no_cpu:
         log("[bench] cpu baseline ...")

@@ -95,6 +95,10 @@ typedef struct {
                          per-wavefront hash counters; -1 = default */
   int32_t part_work;  /* wedge budget per work part of a high-priority
                          pivot; -1 = default */
+  int32_t mid_work;   /* an endpoint's pairs with pivots ranked in
+                         [reverse_L, window_L) are counted together with its
+                         reverse item when they have at most this many wedges
+                         (0 = never, at most 128); -1 = default */
   uint32_t flags;     /* DBBC_OPT_* bits */
 } dbbc_options;
 

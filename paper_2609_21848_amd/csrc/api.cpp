@@ -186,6 +186,7 @@ int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& 
   if (opt->window_L >= 0 && opt->reverse_L < 0) p.reverse_L = std::min(p.reverse_L, p.window_L);
   if (opt->small_work >= 0) p.small_work = opt->small_work;
   if (opt->part_work >= 0) p.part_work = opt->part_work;
+  if (opt->mid_work >= 0) p.mid_work = opt->mid_work;
   if (p.hub_T > p.window_L) p.hub_T = std::min(p.hub_T, p.window_L);
   return DBBC_OK;
 }

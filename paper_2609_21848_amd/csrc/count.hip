@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
-constexpr int kReverseGather = 128;
+constexpr int kReverseGather = 256;
 
 __device__ __forceinline__ void add_pn(uint32_t p, uint32_t n, Sums& s) {
   // p, n <= 255: the products fit 32 bits

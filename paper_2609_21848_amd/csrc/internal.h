@@ -96,9 +96,10 @@ struct PlanParams {
   int32_t reverse_L = 0;
   int32_t small_work = 0;
   int32_t part_work = 0;
+  int32_t mid_work = 0;  // reverse-mid wedges folded into a reverse item (<= kMidHashWork)
   bool operator==(const PlanParams& o) const {
     return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
-           small_work == o.small_work && part_work == o.part_work;
+           small_work == o.small_work && part_work == o.part_work && mid_work == o.mid_work;
   }
 };
 

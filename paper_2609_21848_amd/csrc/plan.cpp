@@ -20,6 +20,7 @@
 // and leave their other hub-pair wedges in a pair buffer that the dense path
 // adds before taking C(., 2).
 #include <algorithm>
+#include <string>
 
 #include "internal.h"
 
@@ -33,6 +34,7 @@ PlanParams default_params(const HostGraph& g) {
   (void)g;
   p.small_work = 1024;
   p.part_work = 1 << 20;
+  p.mid_work = kMidHashWork;
   return p;
 }
 
@@ -66,6 +68,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   }
   if (p.small_work < 2 || p.small_work > 1024 || p.part_work < 4096) {
     err = "small_work must be in [2, 1024] and part_work at least 4096";
+    return DBBC_E_INVALID_ARG;
+  }
+  if (p.mid_work < 0 || p.mid_work > kMidHashWork) {
+    err = "mid_work must be in [0, " + std::to_string(kMidHashWork) + "]";
     return DBBC_E_INVALID_ARG;
   }
   plan = HostPlan();
@@ -204,7 +210,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           mid_work += std::max(0, end - splitR[y]);
           nseg += end > 0;
         }
-        if (mid_work > 0 && mid_work <= kMidHashWork && nseg <= kReverseMaxSegs) {
+        if (mid_work > 0 && mid_work <= p.mid_work && nseg <= kReverseMaxSegs) {
           const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
           for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
             const uint32_t y = S.adj[e] >> 1;

@@ -25,7 +25,8 @@ struct Acc {
 
 extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
                             const int8_t* sign, int32_t hub_T, int32_t window_L, int32_t reverse_L,
-                            int32_t small_work, int32_t part_work, int64_t* out /* 13 */) {
+                            int32_t small_work, int32_t part_work, int32_t mid_work,
+                            int64_t* out /* 13 */) {
   HostGraph g;
   std::string err;
   int rc = build_host_graph(n_u, n_v, m, u, v, sign, 0, g, err);
@@ -36,6 +37,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   if (reverse_L >= 0) p.reverse_L = reverse_L;
   if (small_work >= 0) p.small_work = small_work;
   if (part_work >= 0) p.part_work = part_work;
+  if (mid_work >= 0) p.mid_work = mid_work;
   HostPlan plan;
   rc = make_plan(g, p, plan, err);
   if (rc) {

@@ -24,14 +24,14 @@ def emul(tmp_path_factory):
                            os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
-    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, p]
+    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, i32, p]
 
-    def run(g, T=-1, L=-1, sw=-1, pw=-1, R=-1):
+    def run(g, T=-1, L=-1, sw=-1, pw=-1, R=-1, mid=-1):
         out = np.zeros(13, np.int64)
         if R < 0 and L >= 0:
             R = min(L, 4096)
         rc = lib.plan_emulate(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
-                              g.sign.ctypes.data, T, L, R, sw, pw, out.ctypes.data)
+                              g.sign.ctypes.data, T, L, R, sw, pw, mid, out.ctypes.data)
         assert rc == 0, rc
         return out
     return run
@@ -57,6 +57,8 @@ def test_plan_partition_matches_oracle(emul, seed):
     r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
     for cfg in CONFIGS:
         _check(emul(g, *cfg), r)
+        _check(emul(g, *cfg, mid=0), r)
+        _check(emul(g, *cfg, mid=16), r)
 
 
 def test_plan_on_tiny_workload(emul):
