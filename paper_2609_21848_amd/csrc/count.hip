@@ -26,7 +26,7 @@ namespace dbbc {
 namespace dev {
 
 constexpr int kWave = 64;
-constexpr uint32_t kLong = 64;     // segments this long are streamed by the whole wavefront
+constexpr uint32_t kLong = 16;     // segments this long are streamed by the whole wavefront
 constexpr uint32_t kChunk = 256;   // entries per wavefront 16-byte load (64 lanes x 4)
 constexpr uint32_t kGather = 256;  // per-wavefront staging slots for short segments
 constexpr uint32_t kEmpty = 0xffffffffu;
@@ -357,17 +357,23 @@ constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
 constexpr int kReverseGather = 256;
 
-__device__ __forceinline__ void add_pn(uint32_t p, uint32_t n, Sums& s) {
-  // p, n <= 255: the products fit 32 bits
-  s.bal += (p * (p - 1) + n * (n - 1)) >> 1;
-  s.unb += p * n;
-  s.tot += ((p + n) * (p + n - 1)) >> 1;
-}
-
-__device__ __forceinline__ void add_pair_word(uint32_t c2, Sums& s) {
-  add_pn(c2 & 0xffu, (c2 >> 8) & 0xffu, s);
-  add_pn((c2 >> 16) & 0xffu, c2 >> 24, s);
-}
+// Reverse items sum, per key, p^2 + n^2 and p * n (24-bit multiply-adds on
+// 32-bit per-item accumulators: at most 64 keys per lane of <= 255 each).
+// With W = sum of p + n over the item (its wedge count), the item adds
+// (sum p^2 + n^2 - W) / 2 = sum C(p,2) + C(n,2) balanced butterflies and
+// sum p * n unbalanced ones; the halving is done once per wavefront.
+struct SqSums {
+  uint32_t sq = 0, pn = 0;
+  __device__ __forceinline__ void add(uint32_t p, uint32_t n) {
+    sq += __umul24(p, p);
+    sq += __umul24(n, n);
+    pn += __umul24(p, n);
+  }
+  __device__ __forceinline__ void add_word(uint32_t c2) {  // two keys
+    add(c2 & 0xffu, (c2 >> 8) & 0xffu);
+    add((c2 >> 16) & 0xffu, c2 >> 24);
+  }
+};
 
 struct RevTally {
   uint32_t* cnt;
@@ -418,7 +424,8 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   for (int i = lane; i < kMidHashSlots; i += kWave) H[i] = 0;
   for (int i = lane; i < kReverseGather; i += kWave) gbuf[wave][i] = 0;
   wave_sync_lds();
-  Sums sums;
+  uint64_t sq_total = 0, pn_total = 0;  // per lane
+  uint64_t w_total = 0;                 // wavefront-uniform: wedges of swept items
   const int32_t n = a.n_items;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kReverseWaves;
   int32_t i = static_cast<int32_t>(blockIdx.x) * kReverseWaves + wave;
@@ -438,8 +445,11 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     Item nxt2{};
     if (j2 < n) nxt2 = a.items[j2];
     const DevSideConst sc = a.side[it.side];
-    walk_item<4, kReverseGather>(it, first, a.segs, sc.other_adj, gbuf[wave],
-                                 RevTally{C, H, static_cast<uint32_t>(sc.R), a.res});
+    if (it.flags & kItemMidHash)
+      walk_item<8, kReverseGather>(it, first, a.segs, sc.other_adj, gbuf[wave],
+                                   RevTally{C, H, static_cast<uint32_t>(sc.R), a.res});
+    else
+      walk_item<8, kReverseGather>(it, first, a.segs, sc.other_adj, gbuf[wave], PairTally{C});
     wave_sync_lds();
     const int32_t kh = it.key_hi < sc.R ? it.key_hi : sc.R;
     const int32_t w_hi = (kh + 1) >> 1;  // counter words of the direct window
@@ -452,32 +462,44 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
         if (2 * wd + 1 < kh) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
       }
     } else {
+      SqSums ss;
       for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&C[wd]);
         if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
         *reinterpret_cast<uint4*>(&C[wd]) = make_uint4(0, 0, 0, 0);
-        add_pair_word(c4.x, sums);
-        add_pair_word(c4.y, sums);
-        add_pair_word(c4.z, sums);
-        add_pair_word(c4.w, sums);
+        ss.add_word(c4.x);
+        ss.add_word(c4.y);
+        ss.add_word(c4.z);
+        ss.add_word(c4.w);
       }
       if (it.flags & kItemMidHash) {
         const uint4 h4 = *reinterpret_cast<uint4*>(&H[4 * lane]);
         if (h4.x | h4.y | h4.z | h4.w) {
           *reinterpret_cast<uint4*>(&H[4 * lane]) = make_uint4(0, 0, 0, 0);
-          const uint32_t hv[4] = {h4.x, h4.y, h4.z, h4.w};
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (hv[q]) add_pn(hv[q] & 0xffu, (hv[q] >> 8) & 0xffu, sums);
+          // slot = key << 16 | asym << 8 | sym: the low half is a counter word
+          ss.add(h4.x & 0xffu, (h4.x >> 8) & 0xffu);
+          ss.add(h4.y & 0xffu, (h4.y >> 8) & 0xffu);
+          ss.add(h4.z & 0xffu, (h4.z >> 8) & 0xffu);
+          ss.add(h4.w & 0xffu, (h4.w >> 8) & 0xffu);
         }
       }
+      sq_total += ss.sq;
+      pn_total += ss.pn;
+      w_total += it.work;
     }
     wave_sync_lds();
     cur = nxt;
     cfirst = nfirst;
     nxt = nxt2;
   }
-  flush_sums(sums, a.res);
+  const int64_t sq = wave_sum64(static_cast<int64_t>(sq_total));
+  const int64_t pn = wave_sum64(static_cast<int64_t>(pn_total));
+  if (lane == 0) {
+    const int64_t bal = (sq - static_cast<int64_t>(w_total)) / 2;
+    if (bal) atomicAdd(a.res + kResBalanced, static_cast<unsigned long long>(bal));
+    if (pn) atomicAdd(a.res + kResUnbalanced, static_cast<unsigned long long>(pn));
+    if (bal + pn) atomicAdd(a.res + kResTotal, static_cast<unsigned long long>(bal + pn));
+  }
 }
 
 // ---------------------------------------------------------------------------
