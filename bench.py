@@ -92,10 +92,10 @@ def main():
     ap.add_argument("--hub-T", type=int, default=-1)
     ap.add_argument("--window-L", type=int, default=-1)
     ap.add_argument("--reverse-L", type=int, default=-1)
-    ap.add_argument("--mid-work", type=int, default=-1)
+    ap.add_argument("--long-len", type=int, default=-1)
     ap.add_argument("--sweep", default="",
                     help="option sets to time after the main run, e.g. "
-                         "'hub_T=4096;mid_work=0,reverse_L=2048' (reported on stderr)")
+                         "'hub_T=4096;long_len=64,reverse_L=2048' (reported on stderr)")
     ap.add_argument("--cpu-fraction", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -128,7 +128,7 @@ def main():
     log(f"[bench] graph built in {t_build:.2f}s; W_VP={w_vp}; device bytes={st['device_bytes']}")
 
     opts = dict(hub_T=args.hub_T, window_L=args.window_L, reverse_L=args.reverse_L,
-                mid_work=args.mid_work)
+                long_len=args.long_len)
     t = time.perf_counter()
     first = h.count(**opts)
     t_first = time.perf_counter() - t
@@ -199,7 +199,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
                    "hub_T": args.hub_T, "window_L": args.window_L,
-                   "reverse_L": args.reverse_L, "mid_work": args.mid_work},
+                   "reverse_L": args.reverse_L, "long_len": args.long_len},
         "roofline": roof,
         "balanced_per_s": first.balanced * args.steps / steps_s,
         "butterflies_per_s": first.total * args.steps / steps_s,

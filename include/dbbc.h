@@ -91,14 +91,15 @@ typedef struct {
   int32_t reverse_L; /* per side, the R highest-priority vertices counted
                         from the low-priority end of their pairs; a multiple
                         of 64 in [64, 4096], at most window_L; -1 = default */
-  int32_t small_work; /* work items with at most this many wedges use
+  int32_t small_work; /* work items with at most this many wedges (at most
+                         512) are packed into groups counted with
                          per-wavefront hash counters; -1 = default */
   int32_t part_work;  /* wedge budget per work part of a high-priority
                          pivot; -1 = default */
-  int32_t mid_work;   /* an endpoint's pairs with pivots ranked in
-                         [reverse_L, window_L) are counted together with its
-                         reverse item when they have at most this many wedges
-                         (0 = never, at most 128); -1 = default */
+  int32_t long_len;   /* CSR runs of at least this many entries are streamed
+                         by a whole wavefront with 16-byte loads; shorter
+                         runs are packed end to end across the wavefront's
+                         lanes; in [16, 65536]; -1 = default */
   uint32_t flags;     /* DBBC_OPT_* bits */
 } dbbc_options;
 

@@ -67,12 +67,12 @@ class Options(ctypes.Structure):
     """Mirror of dbbc_options; -1 leaves a knob at the library default."""
     _fields_ = [("hub_T", ctypes.c_int32), ("window_L", ctypes.c_int32),
                 ("reverse_L", ctypes.c_int32), ("small_work", ctypes.c_int32),
-                ("part_work", ctypes.c_int32), ("mid_work", ctypes.c_int32),
+                ("part_work", ctypes.c_int32), ("long_len", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
 
     def __init__(self, hub_T=-1, window_L=-1, small_work=-1, part_work=-1, flags=0,
-                 reverse_L=-1, mid_work=-1):
-        super().__init__(hub_T, window_L, reverse_L, small_work, part_work, mid_work, flags)
+                 reverse_L=-1, long_len=-1):
+        super().__init__(hub_T, window_L, reverse_L, small_work, part_work, long_len, flags)
 
 
 class _KernelTime(ctypes.Structure):

@@ -87,13 +87,13 @@ constexpr size_t kCtlWords = 16;
 
 struct DevPlan {
   dbbc::HostPlan host;
-  DevBuf segs, small_items, direct_items, hash_items, reverse_items, reduces, acc;
+  DevBuf segs, small_segs, small_groups, direct_items, hash_items, reverse_items, reduces, acc;
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
   bool valid = false;
   size_t bytes() const {
-    size_t b = segs.bytes + small_items.bytes + direct_items.bytes + hash_items.bytes +
-               reverse_items.bytes + reduces.bytes + acc.bytes;
+    size_t b = segs.bytes + small_segs.bytes + small_groups.bytes + direct_items.bytes +
+               hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes;
     for (int s = 0; s < 2; ++s) b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes;
     return b;
   }
@@ -138,7 +138,8 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   if (rc != DBBC_OK) return fail(rc, err);
   DevPlan& d = g->plan;
   HIP_TRY(upload(d.segs, hp.segs, st));
-  HIP_TRY(upload(d.small_items, hp.small_items, st));
+  HIP_TRY(upload(d.small_segs, hp.small_segs, st));
+  HIP_TRY(upload(d.small_groups, hp.small_groups, st));
   HIP_TRY(upload(d.direct_items, hp.direct_items, st));
   HIP_TRY(upload(d.hash_items, hp.hash_items, st));
   HIP_TRY(upload(d.reverse_items, hp.reverse_items, st));
@@ -171,13 +172,21 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   // the host plan keeps only what later launches need
   hp.segs.clear();
   hp.segs.shrink_to_fit();
+  hp.small_segs.clear();
+  hp.small_segs.shrink_to_fit();
+  hp.small_items.clear();
+  hp.small_items.shrink_to_fit();
   d.host = std::move(hp);
   d.valid = true;
   return DBBC_OK;
 }
 
-int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& p) {
+// Runs of at least this many entries are streamed by a whole wavefront.
+constexpr int32_t kDefaultLongLen = 256;
+
+int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& p, uint32_t& long_len) {
   p = dbbc::default_params(g->host);
+  long_len = kDefaultLongLen;
   if (!opt) return DBBC_OK;
   if (opt->flags & ~DBBC_OPT_TIME_KERNELS) return fail(DBBC_E_INVALID_ARG, "unknown dbbc_options flag");
   if (opt->hub_T >= 0) p.hub_T = opt->hub_T;
@@ -186,7 +195,11 @@ int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& 
   if (opt->window_L >= 0 && opt->reverse_L < 0) p.reverse_L = std::min(p.reverse_L, p.window_L);
   if (opt->small_work >= 0) p.small_work = opt->small_work;
   if (opt->part_work >= 0) p.part_work = opt->part_work;
-  if (opt->mid_work >= 0) p.mid_work = opt->mid_work;
+  if (opt->long_len >= 0) {
+    if (opt->long_len < 16 || opt->long_len > 65536)
+      return fail(DBBC_E_INVALID_ARG, "long_len must be in [16, 65536]");
+    long_len = static_cast<uint32_t>(opt->long_len);
+  }
   if (p.hub_T > p.window_L) p.hub_T = std::min(p.hub_T, p.window_L);
   return DBBC_OK;
 }
@@ -225,7 +238,7 @@ struct Timing {
   } while (0)
 
 // Enqueue the whole count on stream st; results land in g->ctl.
-int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
+int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed, uint32_t long_len) {
   Timing tm{g, st, timed};
   g->timers_used = 0;
   DevPlan& d = g->plan;
@@ -239,6 +252,7 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     side[s].hub_pairs = d.hub_pairs[s].as<unsigned long long>();
     side[s].T = hp.T[s];
     side[s].R = hp.R[s];
+    side[s].key_bits = hp.key_bits[s];
     if (hp.T[s] > 0)
       HIP_TRY(dbbc::launch_fill_u64(side[s].hub_pairs, static_cast<size_t>(hp.T[s]) * hp.T[s], 0ull, st));
   }
@@ -254,6 +268,7 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     a.res = ctl;
     a.n_items = static_cast<int32_t>(hp.direct_items.size());
     a.acc_width = hp.acc_width;
+    a.long_len = long_len;
     RC_TRY(tm.begin("direct", hp.k_wedges[0], hp.k_segs[0], a.n_items, 0));
     HIP_TRY(dbbc::launch_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
     RC_TRY(tm.end());
@@ -269,21 +284,23 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     a.acc_width = hp.acc_width;
     a.res = ctl;
     a.n_items = static_cast<int32_t>(hp.reverse_items.size());
+    a.long_len = long_len;
     RC_TRY(tm.begin("reverse", hp.k_wedges[3], hp.k_segs[3], a.n_items, 0));
     HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 15) / 16)), st));
     RC_TRY(tm.end());
   }
   {
     dbbc::SmallArgs a{};
-    a.items = d.small_items.as<dbbc::Item>();
-    a.segs = d.segs.as<dbbc::Segment>();
+    a.items = d.small_groups.as<dbbc::Item>();
+    a.segs = d.small_segs.as<dbbc::Segment>();
     a.side[0] = side[0];
     a.side[1] = side[1];
     a.queue = queues + 1;
     a.res = ctl;
-    a.n_items = static_cast<int32_t>(hp.small_items.size());
+    a.n_items = static_cast<int32_t>(hp.small_groups.size());
+    a.long_len = long_len;
     RC_TRY(tm.begin("small", hp.k_wedges[1], hp.k_segs[1], a.n_items, 0));
-    HIP_TRY(dbbc::launch_small(a, std::min<int>(2 * cus, std::max(1, (a.n_items + 3) / 4)), st));
+    HIP_TRY(dbbc::launch_small(a, std::min<int>(4 * cus, std::max(1, (a.n_items + 3) / 4)), st));
     RC_TRY(tm.end());
   }
   {
@@ -295,6 +312,7 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed) {
     a.queue = queues + 2;
     a.res = ctl;
     a.n_items = static_cast<int32_t>(hp.hash_items.size());
+    a.long_len = long_len;
     RC_TRY(tm.begin("hash", hp.k_wedges[2], hp.k_segs[2], a.n_items, 0));
     HIP_TRY(dbbc::launch_hash(a, std::min<int>(cus, std::max(1, a.n_items)), st));
     RC_TRY(tm.end());
@@ -435,13 +453,14 @@ int dbbc_count(dbbc_graph* g, const dbbc_options* opt, dbbc_counts* out_host, vo
   if (!g || !out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   dbbc::PlanParams p;
-  int rc = params_from(g, opt, p);
+  uint32_t long_len = 0;
+  int rc = params_from(g, opt, p, long_len);
   if (rc != DBBC_OK) return rc;
   rc = ensure_plan(g, p, st);
   if (rc != DBBC_OK) return rc;
   const bool timed = opt && (opt->flags & DBBC_OPT_TIME_KERNELS);
   g->timed_valid = false;
-  rc = enqueue_count(g, st, timed);
+  rc = enqueue_count(g, st, timed, long_len);
   if (rc != DBBC_OK) return rc;
   HIP_TRY(hipMemcpyAsync(g->pinned, g->ctl.p, kCtlWords * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, st));

@@ -26,9 +26,8 @@ namespace dbbc {
 namespace dev {
 
 constexpr int kWave = 64;
-constexpr uint32_t kLong = 16;     // segments this long are streamed by the whole wavefront
 constexpr uint32_t kChunk = 256;   // entries per wavefront 16-byte load (64 lanes x 4)
-constexpr uint32_t kGather = 256;  // per-wavefront staging slots for short segments
+constexpr uint32_t kGather = 256;  // positions per staging round of short runs
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -66,66 +65,102 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// One lane's segment of a batch (len 0 = none).
+// One lane's run of a batch (len 0 = none).  Bit 0 of tag is the sign bit g
+// of the run's first wedge edge; the runs of a small-item group also carry
+// the item's index in the group above it (tag = index << 1 | g).
 struct SegReg {
-  uint32_t start, len, g;
+  uint32_t start, len, tag;
 };
 
+template <bool kTagged>
 __device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1) {
   const uint32_t k = k0 + lane_id();
   SegReg r{0, 0, 0};
   if (k < k1) {
     const Segment s = segs[k];
     r.start = s.start;
-    r.len = s.len_g >> 1;
-    r.g = s.len_g & 1u;
+    if (kTagged) {
+      r.len = (s.len_g & 0xffffu) >> 1;
+      r.tag = (s.len_g & 1u) | ((s.len_g >> 16) << 1);
+    } else {
+      r.len = s.len_g >> 1;
+      r.tag = s.len_g & 1u;
+    }
   }
   return r;
 }
 
-// Stage the short-segment wedges with flat positions [done, done + G) of the
-// batch into gbuf as (entry index | g << 31).
-template <int G>
-__device__ __forceinline__ void stage_short(uint32_t* gbuf, uint32_t excl, uint32_t slen, uint32_t start,
-                                            uint32_t g, uint32_t done) {
-  const uint32_t lo = excl > done ? excl : done;
-  const uint32_t hi_a = excl + slen, hi_b = done + G;
-  const uint32_t hi = hi_a < hi_b ? hi_a : hi_b;
-  for (uint32_t t = lo; t < hi; ++t) gbuf[t - done] = (start + (t - excl)) | (g << 31);
+// v of lane src (all lanes must be active).
+__device__ __forceinline__ uint32_t bpermute(uint32_t v, uint32_t src) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_ds_bpermute(static_cast<int>(src << 2), static_cast<int>(v)));
 }
 
-// Walk a batch of up to 64 segments (one per lane, in registers) with one
-// wavefront, calling f.add(entry, g, valid) once per wedge slot.
-//  - Segments of at least kLong entries are consumed as a stream of
-//    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
-//    chunk, U chunks are in flight per lane, and a chunk's out-of-segment
-//    words are masked.  The chunk loop is wavefront-uniform.
-//  - Shorter segments are staged through gbuf (G words of LDS owned by this
-//    wavefront) so that lanes read consecutive wedges.  The loads of the
-//    first G staged wedges are issued before the long-segment stream, so the
-//    two paths wait on memory together.
-template <int U, int G, class F>
-__device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, uint32_t* gbuf,
-                                          F&& f) {
-  constexpr int UG = G / kWave;
+// Short runs of a batch are laid end to end: flat position t (0 <= t <
+// total) is entry base + t of its run's row, with base = start - excl of
+// the run.  A staging round covers positions [done, done + kGather), dealt
+// to lanes as t = done + 64 u + lane (coalesced loads).  Every run that
+// starts in the round, or continues into it, writes lane + 1 at its first
+// position of the round into the wavefront's marks buffer; a position's run
+// is then the last mark at or before it: a ballot per block of 64 positions,
+// carried across blocks.  Each lane clears the marks it read, so the buffer
+// is all zeros between rounds.
+constexpr int kStageU = kGather / kWave;
+
+struct Staged {
+  uint32_t e[kStageU], tag[kStageU];
+  bool valid[kStageU];
+};
+
+__device__ __forceinline__ void stage_round(Staged& s, uint32_t* marks, uint32_t excl, uint32_t slen,
+                                            uint32_t base, uint32_t tag, uint32_t total, uint32_t done,
+                                            const uint32_t* __restrict__ adj) {
   const int lane = lane_id();
-  const uint32_t start = sr.start, g = sr.g, len = sr.len;
-  uint64_t longm = __ballot(len >= kLong);
-  const uint32_t slen = len >= kLong ? 0u : len;
+  wave_sync_lds();
+  if (slen != 0 && excl < done + kGather && excl + slen > done)
+    marks[excl > done ? excl - done : 0u] = static_cast<uint32_t>(lane) + 1u;
+  wave_sync_lds();
+  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane
+  uint32_t carry = 0;
+#pragma unroll
+  for (int u = 0; u < kStageU; ++u) {
+    const uint32_t m = marks[u * kWave + lane];
+    marks[u * kWave + lane] = 0;
+    const uint64_t below = __ballot(m != 0) & upto;
+    const uint32_t mv = bpermute(m, below ? 63u - static_cast<uint32_t>(__clzll(below)) : 0u);
+    const uint32_t own = below ? mv : carry;  // lane + 1 of the position's run
+    carry = readlane(own, kWave - 1);
+    // positions past the end may have no run (own = 0): masked below
+    const uint32_t j = own - 1u;
+    const uint32_t b = bpermute(base, j);
+    s.tag[u] = bpermute(tag, j);
+    const uint32_t t = done + static_cast<uint32_t>(u * kWave + lane);
+    s.valid[u] = t < total;
+    s.e[u] = adj[s.valid[u] ? b + t : 0u];
+  }
+}
+
+// Walk a batch of up to 64 runs (one per lane, in registers) with one
+// wavefront, calling f.add(entry, tag, valid) once per wedge slot.
+//  - Runs of at least long_len entries are consumed as a stream of
+//    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
+//    chunk, U chunks are in flight per lane, and a chunk's out-of-run words
+//    are masked.  The chunk loop is wavefront-uniform.
+//  - Shorter runs are staged (stage_round) so that every lane holds wedges;
+//    the loads of the first round are issued before the long stream and the
+//    next round's loads before the current round is tallied.
+template <int U, class F>
+__device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, uint32_t* marks,
+                                          uint32_t long_len, F&& f) {
+  const int lane = lane_id();
+  const uint32_t start = sr.start, tag = sr.tag, len = sr.len;
+  uint64_t longm = __ballot(len >= long_len);
+  const uint32_t slen = len >= long_len ? 0u : len;
   uint32_t total;
   const uint32_t excl = wave_excl_scan(slen, &total);
-  const uint32_t cnt0 = total < static_cast<uint32_t>(G) ? total : static_cast<uint32_t>(G);
-  uint32_t sa[UG], se[UG];
-  if (total) {
-    stage_short<G>(gbuf, excl, slen, start, g, 0);
-    wave_sync_lds();
-#pragma unroll
-    for (int u = 0; u < UG; ++u) {
-      const uint32_t t = u * kWave + lane;
-      sa[u] = gbuf[t < cnt0 ? t : 0u];
-      se[u] = adj[t < cnt0 ? sa[u] & 0x7fffffffu : 0u];
-    }
-  }
+  const uint32_t base = start - excl;
+  Staged cur;
+  if (total) stage_round(cur, marks, excl, slen, base, tag, total, 0, adj);
   uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
   while (longm || have) {
@@ -138,12 +173,12 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         longm &= longm - 1;
         cur_st = readlane(start, j);
         cur_end = cur_st + readlane(len, j);
-        cur_g = readlane(g, j);
+        cur_g = readlane(tag, j);
         cur_pos = cur_st & ~3u;
         have = true;
       }
       // The load is unconditional (no wait on registers of a skipped load):
-      // lanes past the segment end and empty slots read the first entries of
+      // lanes past the run's end and empty slots read the first entries of
       // the array, and their words fail the index test below.
       const bool h = have;
       const uint32_t p = cur_pos + 4 * lane;
@@ -167,48 +202,43 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       }
     }
   }
-  if (!total) return;
+  for (uint32_t done = 0; done < total; done += kGather) {
+    const bool more = done + kGather < total;
+    Staged nxt;
+    if (more) stage_round(nxt, marks, excl, slen, base, tag, total, done + kGather, adj);
 #pragma unroll
-  for (int u = 0; u < UG; ++u) f.add(se[u], sa[u] >> 31, u * kWave + lane < cnt0);
-  for (uint32_t done = G; done < total; done += G) {
-    wave_sync_lds();
-    stage_short<G>(gbuf, excl, slen, start, g, done);
-    wave_sync_lds();
-    const uint32_t cnt = total - done < static_cast<uint32_t>(G) ? total - done : static_cast<uint32_t>(G);
-#pragma unroll
-    for (int u = 0; u < UG; ++u) {
-      const uint32_t t = u * kWave + lane;
-      sa[u] = gbuf[t < cnt ? t : 0u];
-      se[u] = adj[t < cnt ? sa[u] & 0x7fffffffu : 0u];
-    }
-#pragma unroll
-    for (int u = 0; u < UG; ++u) f.add(se[u], sa[u] >> 31, u * kWave + lane < cnt);
+    for (int u = 0; u < kStageU; ++u) f.add(cur.e[u], cur.tag[u], cur.valid[u]);
+    if (!more) break;
+    cur = nxt;
   }
-  wave_sync_lds();
 }
 
-template <int U, int G = kGather, class F>
+template <int U, bool kTagged = false, class F>
 __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
-                                           const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
-  walk_regs<U, G>(load_seg(segs, k0, k1), adj, gbuf, f);
+                                           const uint32_t* __restrict__ adj, uint32_t* marks,
+                                           uint32_t long_len, F&& f) {
+  walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
 }
 
-// Walk every segment of an item with one wavefront; the first batch of 64
-// segments was loaded beforehand (first).
-template <int U, int G = kGather, class F>
+// Walk every run of an item with one wavefront; the first batch of 64 runs
+// was loaded beforehand (first).
+template <int U, bool kTagged = false, class F>
 __device__ __forceinline__ void walk_item(const Item& it, SegReg first, const Segment* __restrict__ segs,
-                                          const uint32_t* __restrict__ adj, uint32_t* gbuf, F&& f) {
+                                          const uint32_t* __restrict__ adj, uint32_t* marks,
+                                          uint32_t long_len, F&& f) {
   const uint32_t seg_end = it.seg_begin + it.seg_count;
-  walk_regs<U, G>(first, adj, gbuf, f);
+  walk_regs<U>(first, adj, marks, long_len, f);
   for (uint32_t k0 = it.seg_begin + kWave; k0 < seg_end; k0 += kWave) {
     const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-    walk_regs<U, G>(load_seg(segs, k0, k1), adj, gbuf, f);
+    walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
   }
 }
 
+template <bool kTagged = false>
 __device__ __forceinline__ SegReg first_batch(const Item& it, const Segment* __restrict__ segs) {
   const uint32_t seg_end = it.seg_begin + it.seg_count;
-  return load_seg(segs, it.seg_begin, it.seg_begin + kWave < seg_end ? it.seg_begin + kWave : seg_end);
+  return load_seg<kTagged>(segs, it.seg_begin,
+                           it.seg_begin + kWave < seg_end ? it.seg_begin + kWave : seg_end);
 }
 
 // Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric.
@@ -231,7 +261,7 @@ struct PairTally {  // 8 | 8-bit counters, two keys per 32-bit word
   __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
     // the entry's low bits select the byte: bit 0 (negative) ^ g picks the
     // symmetric / asymmetric byte, bit 1 (key parity) the 16-bit half
-    if (valid) atomicAdd(&cnt[e >> 2], 1u << (((e ^ g) & 3u) << 3));
+    if (valid) atomicAdd(&cnt[e >> 2], 1u << (((e ^ (g & 1u)) & 3u) << 3));
   }
 };
 
@@ -294,13 +324,12 @@ constexpr int kDirectKeys = 32768;
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t cnt[kDirectKeys];
-  __shared__ uint32_t gbuf[kDirectWaves][kGather];
+  __shared__ uint32_t marks[kDirectWaves][kGather];
   __shared__ int32_t item_sh;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
-  // staged slots always hold valid entry indices
-  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&gbuf[0][0])[i] = 0;
+  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&marks[0][0])[i] = 0;
   Sums sums;
   for (;;) {
     if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<4>(a.segs, k0, k1, adj, gbuf[wave], DirectTally{cnt});
+      walk_batch<4>(a.segs, k0, k1, adj, marks[wave], a.long_len, DirectTally{cnt});
     }
     __syncthreads();
     if (it.flags & kItemMultiPart) {
@@ -346,86 +375,63 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 // reverse window [0, R) (R <= kMaxReverseL).  Counters are 8-bit
 // (symmetric | asymmetric << 8) in 16-bit halves, two keys per 32-bit word:
 // an item (or part) has at most kReverseMaxSegs segments, so no byte
-// overflows.  Items flagged kItemMidHash also carry a few keys in [R, L);
-// those go to a per-wavefront hash whose 32-bit slots hold
-// (key - R + 1) << 16 | asymmetric << 8 | symmetric.
-// Items are dealt to wavefronts in a fixed stride; the next item's first
-// segments and the descriptor of the one after are loaded while the current
-// item is walked.  The sweep reads the whole window with 16-byte LDS loads.
+// overflows.  Items are dealt to wavefronts in a fixed stride; the next
+// item's first segments and the descriptor of the one after are loaded while
+// the current item is walked.  The sweep reads the whole window with 16-byte
+// LDS loads.
 constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
-constexpr int kReverseGather = 256;
 
-// Reverse items sum, per key, p^2 + n^2 and p * n (24-bit multiply-adds on
-// 32-bit per-item accumulators: at most 64 keys per lane of <= 255 each).
-// With W = sum of p + n over the item (its wedge count), the item adds
-// (sum p^2 + n^2 - W) / 2 = sum C(p,2) + C(n,2) balanced butterflies and
-// sum p * n unbalanced ones; the halving is done once per wavefront.
+// Per-key sums of squares: with W the wedges of the swept keys (sum of
+// p + n), sum C(p,2) + C(n,2) = (sum p^2 + n^2 - W) / 2 and the unbalanced
+// sum is sum p * n.  24-bit multiply-adds on 32-bit per-item accumulators:
+// the callers bound p and n so that an item's sums stay below 2^32.
 struct SqSums {
-  uint32_t sq = 0, pn = 0;
+  uint32_t sq = 0, pn = 0, w = 0;
   __device__ __forceinline__ void add(uint32_t p, uint32_t n) {
     sq += __umul24(p, p);
     sq += __umul24(n, n);
     pn += __umul24(p, n);
+    w += p + n;
   }
-  __device__ __forceinline__ void add_word(uint32_t c2) {  // two keys
+  __device__ __forceinline__ void add_word(uint32_t c2) {  // two 8|8-bit keys
     add(c2 & 0xffu, (c2 >> 8) & 0xffu);
     add((c2 >> 16) & 0xffu, c2 >> 24);
   }
 };
 
-struct RevTally {
-  uint32_t* cnt;
-  uint32_t* hsh;
-  uint32_t R;
-  unsigned long long* res;
-  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    if (!valid) return;
-    const uint32_t key = e >> 1;
-    if (key < R) {
-      // bit 0 (negative) ^ g picks the symmetric / asymmetric byte, bit 1
-      // (key parity) the 16-bit half of the word
-      atomicAdd(&cnt[e >> 2], 1u << (((e ^ g) & 3u) << 3));
-      return;
+// Running per-lane totals of SqSums, flushed once per wavefront.
+struct SqTotals {
+  uint64_t sq = 0, pn = 0, w = 0;
+  __device__ __forceinline__ void add(const SqSums& s) {
+    sq += s.sq;
+    pn += s.pn;
+    w += s.w;
+  }
+  __device__ __forceinline__ void flush(unsigned long long* res) const {
+    const int64_t q = wave_sum64(static_cast<int64_t>(sq));
+    const int64_t x = wave_sum64(static_cast<int64_t>(pn));
+    const int64_t ww = wave_sum64(static_cast<int64_t>(w));
+    if (lane_id() == 0) {
+      const int64_t bal = (q - ww) / 2;
+      if (bal) atomicAdd(res + kResBalanced, static_cast<unsigned long long>(bal));
+      if (x) atomicAdd(res + kResUnbalanced, static_cast<unsigned long long>(x));
+      if (bal + x) atomicAdd(res + kResTotal, static_cast<unsigned long long>(bal + x));
     }
-    const uint32_t k = key - R + 1;
-    const uint32_t inc = ((e ^ g) & 1u) ? 0x100u : 1u;
-    uint32_t h = (k * 0x9e3779b1u) >> 24;
-    for (int probe = 0; probe < kMidHashSlots; ++probe) {
-      const uint32_t cur = hsh[h];
-      if ((cur >> 16) == k) {
-        atomicAdd(&hsh[h], inc);
-        return;
-      }
-      if (cur == 0) {
-        const uint32_t old = atomicCAS(&hsh[h], 0u, (k << 16) | inc);
-        if (old == 0) return;
-        if ((old >> 16) == k) {
-          atomicAdd(&hsh[h], inc);
-          return;
-        }
-      }
-      h = (h + 1) & (kMidHashSlots - 1);
-    }
-    atomicOr(res + kResError, kErrHashFull);  // cannot happen at load <= 1/2
   }
 };
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kReverseWaves][kReverseWords];
-  __shared__ uint32_t hsh[kReverseWaves][kMidHashSlots];
-  __shared__ uint32_t gbuf[kReverseWaves][kReverseGather];
+  __shared__ uint32_t marks[kReverseWaves][kGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
-  uint32_t* H = hsh[wave];
   for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
-  for (int i = lane; i < kMidHashSlots; i += kWave) H[i] = 0;
-  for (int i = lane; i < kReverseGather; i += kWave) gbuf[wave][i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) marks[wave][i] = 0;
   wave_sync_lds();
-  uint64_t sq_total = 0, pn_total = 0;  // per lane
-  uint64_t w_total = 0;                 // wavefront-uniform: wedges of swept items
+  SqTotals tot;
   const int32_t n = a.n_items;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kReverseWaves;
   int32_t i = static_cast<int32_t>(blockIdx.x) * kReverseWaves + wave;
@@ -445,23 +451,19 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     Item nxt2{};
     if (j2 < n) nxt2 = a.items[j2];
     const DevSideConst sc = a.side[it.side];
-    if (it.flags & kItemMidHash)
-      walk_item<8, kReverseGather>(it, first, a.segs, sc.other_adj, gbuf[wave],
-                                   RevTally{C, H, static_cast<uint32_t>(sc.R), a.res});
-    else
-      walk_item<8, kReverseGather>(it, first, a.segs, sc.other_adj, gbuf[wave], PairTally{C});
+    walk_item<8>(it, first, a.segs, sc.other_adj, marks[wave], a.long_len, PairTally{C});
     wave_sync_lds();
-    const int32_t kh = it.key_hi < sc.R ? it.key_hi : sc.R;
-    const int32_t w_hi = (kh + 1) >> 1;  // counter words of the direct window
+    const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the item's keys
     if (it.flags & kItemMultiPart) {
       uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
       for (int32_t wd = lane; wd < w_hi; wd += kWave) {
         const uint32_t c2 = C[wd];
         C[wd] = 0;
         dst[2 * wd] = (c2 & 0xffu) | (((c2 >> 8) & 0xffu) << 16);
-        if (2 * wd + 1 < kh) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
+        if (2 * wd + 1 < it.key_hi) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
       }
     } else {
+      // p, n <= 255 and at most 2 * kReverseWords / 64 = 64 keys per lane
       SqSums ss;
       for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&C[wd]);
@@ -472,42 +474,25 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
         ss.add_word(c4.z);
         ss.add_word(c4.w);
       }
-      if (it.flags & kItemMidHash) {
-        const uint4 h4 = *reinterpret_cast<uint4*>(&H[4 * lane]);
-        if (h4.x | h4.y | h4.z | h4.w) {
-          *reinterpret_cast<uint4*>(&H[4 * lane]) = make_uint4(0, 0, 0, 0);
-          // slot = key << 16 | asym << 8 | sym: the low half is a counter word
-          ss.add(h4.x & 0xffu, (h4.x >> 8) & 0xffu);
-          ss.add(h4.y & 0xffu, (h4.y >> 8) & 0xffu);
-          ss.add(h4.z & 0xffu, (h4.z >> 8) & 0xffu);
-          ss.add(h4.w & 0xffu, (h4.w >> 8) & 0xffu);
-        }
-      }
-      sq_total += ss.sq;
-      pn_total += ss.pn;
-      w_total += it.work;
+      tot.add(ss);
     }
     wave_sync_lds();
     cur = nxt;
     cfirst = nfirst;
     nxt = nxt2;
   }
-  const int64_t sq = wave_sum64(static_cast<int64_t>(sq_total));
-  const int64_t pn = wave_sum64(static_cast<int64_t>(pn_total));
-  if (lane == 0) {
-    const int64_t bal = (sq - static_cast<int64_t>(w_total)) / 2;
-    if (bal) atomicAdd(a.res + kResBalanced, static_cast<unsigned long long>(bal));
-    if (pn) atomicAdd(a.res + kResUnbalanced, static_cast<unsigned long long>(pn));
-    if (bal + pn) atomicAdd(a.res + kResTotal, static_cast<unsigned long long>(bal + pn));
-  }
+  tot.flush(a.res);
 }
 
 // ---------------------------------------------------------------------------
-// Small items: one wavefront per item, open-addressing hash counters in LDS
-// sized to the item (at least twice its wedge count).
+// Small items, packed into groups (see plan.cpp): one wavefront per group,
+// an open-addressing hash in LDS keyed by (item index in the group <<
+// key_bits) | key, with 16 | 16-bit counts (a group has at most
+// kSmallGroupWork wedges).  The table is sized to the group (a power of two
+// at least twice its wedges), so the sweep reads only that many slots.
 constexpr int kSmallThreads = 256;
 constexpr int kSmallWaves = kSmallThreads / kWave;
-constexpr int kSmallSlots = 2048;  // per wavefront, >= 2 * max small work (1024)
+constexpr int kSmallSlots = 2 * kSmallGroupWork;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
@@ -521,7 +506,7 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   __shared__ uint32_t keys[kSmallWaves][kSmallSlots];
   __shared__ uint32_t vals[kSmallWaves][kSmallSlots];
-  __shared__ uint32_t gbuf[kSmallWaves][kGather];
+  __shared__ uint32_t marks[kSmallWaves][kGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* K = keys[wave];
@@ -530,16 +515,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     K[i] = kEmpty;
     Vv[i] = 0;
   }
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) gbuf[wave][i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) marks[wave][i] = 0;
   wave_sync_lds();
-  Sums sums;
+  SqTotals tot;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kSmallWaves;
   int32_t i = static_cast<int32_t>(blockIdx.x) * kSmallWaves + wave;
   Item nxt{};
   SegReg nfirst{0, 0, 0};
   if (i < a.n_items) {
     nxt = a.items[i];
-    nfirst = first_batch(nxt, a.segs);
+    nfirst = first_batch<true>(nxt, a.segs);
   }
   for (; i < a.n_items; i += stride) {
     const Item it = nxt;
@@ -547,47 +532,58 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     const int32_t j = i + stride;
     if (j < a.n_items) nxt = a.items[j];
     const DevSideConst sc = a.side[it.side];
+    const uint32_t kb = static_cast<uint32_t>(sc.key_bits);
     // table size: a power of two >= 2 * work, at least 64
     uint32_t size = 64;
     while (size < 2 * it.work) size <<= 1;
     const uint32_t mask = size - 1;
-    {
-      walk_item<4>(it, first, a.segs, sc.other_adj, gbuf[wave], hash_tally([&](uint32_t e, uint32_t g) {
-        const uint32_t key = e >> 1;
-        const uint32_t inc = wedge_inc(e, g);
-        uint32_t h = mix32(key) & mask;
-        for (uint32_t probe = 0;; ++probe) {
-          if (probe > mask) {  // full table: cannot happen at load <= 1/2
-            atomicOr(a.res + kResError, kErrHashFull);
-            break;
-          }
-          uint32_t cur = K[h];
-          if (cur == kEmpty) {
-            cur = atomicCAS(&K[h], kEmpty, key);
-            if (cur == kEmpty) cur = key;
-          }
-          if (cur == key) {
-            atomicAdd(&Vv[h], inc);
-            break;
-          }
-          h = (h + 1) & mask;
-        }
-      }));
-    }
-    if (j < a.n_items) nfirst = first_batch(nxt, a.segs);
+    walk_item<4, true>(it, first, a.segs, sc.other_adj, marks[wave], a.long_len,
+                       hash_tally([&](uint32_t e, uint32_t tag) {
+                         const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
+                         const uint32_t inc = wedge_inc(e, tag);
+                         uint32_t h = mix32(key) & mask;
+                         for (uint32_t probe = 0;; ++probe) {
+                           if (probe > mask) {  // full table: cannot happen at load <= 1/2
+                             atomicOr(a.res + kResError, kErrHashFull);
+                             break;
+                           }
+                           uint32_t c = K[h];
+                           if (c == kEmpty) {
+                             c = atomicCAS(&K[h], kEmpty, key);
+                             if (c == kEmpty) c = key;
+                           }
+                           if (c == key) {
+                             atomicAdd(&Vv[h], inc);
+                             break;
+                           }
+                           h = (h + 1) & mask;
+                         }
+                       }));
+    if (j < a.n_items) nfirst = first_batch<true>(nxt, a.segs);
     wave_sync_lds();
+    // p, n <= kSmallGroupWork per key and sum p + n <= kSmallGroupWork
+    // per group, so the group's sums of squares stay below 2^19
+    SqSums ss;
+    const bool hub = (it.flags & kItemHubPairs) != 0;
+    const uint32_t kmask = (1u << kb) - 1u;
     for (uint32_t h = lane; h < size; h += kWave) {
       const uint32_t key = K[h];
       if (key != kEmpty) {
         const uint32_t c = Vv[h];
-        emit(it, key, c & 0xffffu, c >> 16, sc, sums);
+        const uint32_t p = c & 0xffffu, q = c >> 16;
         K[h] = kEmpty;
         Vv[h] = 0;
+        if (hub && static_cast<int32_t>(key & kmask) < sc.T)  // singleton group
+          sc.hub_pairs[static_cast<size_t>(it.owner) * sc.T + (key & kmask)] =
+              (static_cast<unsigned long long>(q) << 32) | p;
+        else
+          ss.add(p, q);
       }
     }
+    tot.add(ss);
     wave_sync_lds();
   }
-  flush_sums(sums, a.res);
+  tot.flush(a.res);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,7 +597,7 @@ constexpr int kHashSlots = 8192;
 __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
   __shared__ uint32_t keys[kHashSlots];
   __shared__ unsigned long long vals[kHashSlots];
-  __shared__ uint32_t gbuf[kHashWaves][kGather];
+  __shared__ uint32_t marks[kHashWaves][kGather];
   __shared__ int32_t item_sh;
   __shared__ uint32_t work_sh;
   const int tid = threadIdx.x;
@@ -610,7 +606,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     keys[i] = kEmpty;
     vals[i] = 0;
   }
-  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&gbuf[0][0])[i] = 0;
+  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&marks[0][0])[i] = 0;
   Sums sums;
   for (;;) {
     if (tid == 0) {
@@ -633,7 +629,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     for (uint32_t pass = 0; pass < passes; ++pass) {
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        walk_batch<4>(a.segs, k0, k1, sc.other_adj, gbuf[wave], hash_tally([&](uint32_t e, uint32_t g) {
+        walk_batch<4>(a.segs, k0, k1, sc.other_adj, marks[wave], a.long_len, hash_tally([&](uint32_t e, uint32_t g) {
           const uint32_t key = e >> 1;
           const uint32_t hk = mix32(key);
           if (passes > 1 && (hk >> 16) % passes != pass) return;

@@ -58,6 +58,13 @@ enum ItemKind : uint8_t {
                        // not in the reverse window
 };
 
+// Small items are packed into groups that one wavefront counts in a single
+// hash table; a group holds at most this many wedges (the table has twice as
+// many slots).  Inside a group, segments carry the item's index in the group
+// in the high half of len_g: (index << 16) | (len << 1) | g.
+constexpr uint32_t kSmallGroupWork = 512;
+constexpr uint32_t kSmallMaxItems = 65535;
+
 // Reverse items keep two 8-bit counters per key (symmetric, asymmetric), so
 // a reverse item (or item part) has at most this many segments.
 constexpr uint32_t kReverseMaxSegs = 255;
@@ -66,7 +73,6 @@ constexpr uint32_t kReverseMaxSegs = 255;
 enum : uint32_t {
   kItemMultiPart = 1u,  // partial counts go to a global accumulator
   kItemHubPairs = 2u,   // keys below hub_T are flushed to the hub-pair buffer
-  kItemMidHash = 4u,    // reverse item whose keys in [R, L) go to a small hash
 };
 
 struct Item {
@@ -96,10 +102,9 @@ struct PlanParams {
   int32_t reverse_L = 0;
   int32_t small_work = 0;
   int32_t part_work = 0;
-  int32_t mid_work = 0;  // reverse-mid wedges folded into a reverse item (<= kMidHashWork)
   bool operator==(const PlanParams& o) const {
     return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
-           small_work == o.small_work && part_work == o.part_work && mid_work == o.mid_work;
+           small_work == o.small_work && part_work == o.part_work;
   }
 };
 
@@ -107,19 +112,16 @@ struct PlanParams {
 // array of this many counters.
 constexpr int32_t kMaxReverseL = 4096;
 
-// A reverse item may also carry the keys in [R, L) of its endpoint when it
-// has at most this many wedges there; they are counted in a per-wavefront
-// hash of kMidHashSlots slots (load factor at most 1/2).
-constexpr int32_t kMidHashSlots = 256;
-constexpr int32_t kMidHashWork = kMidHashSlots / 2;
-
 struct HostPlan {
   PlanParams p;
   int32_t L[2] = {0, 0};  // window per side
   int32_t R[2] = {0, 0};  // reverse window per side (R <= L)
   int32_t T[2] = {0, 0};  // hub block rows per side (pairs on that side)
   std::vector<Segment> segs;
-  std::vector<Item> small_items;   // per-wavefront hash counters
+  std::vector<Item> small_items;   // items counted with per-wavefront hash counters
+  std::vector<Item> small_groups;  // ... packed into groups (segments in small_segs)
+  std::vector<Segment> small_segs; // tagged segments of the groups
+  int32_t key_bits[2] = {1, 1};    // per side: bits of a side rank in a group hash key
   std::vector<Item> direct_items;  // workgroup direct arrays over [0, L)
   std::vector<Item> hash_items;    // workgroup hash counters, large tail pivots
   std::vector<Item> reverse_items; // per-wavefront direct arrays over [0, R)

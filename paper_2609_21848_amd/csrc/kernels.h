@@ -33,6 +33,7 @@ struct DevSideConst {
   unsigned long long* hub_pairs; // [T x T] packed (asym << 32) | sym, or null
   int32_t T;                     // hub rows of side s (0 = no dense path)
   int32_t R;                     // reverse window of side s
+  int32_t key_bits;              // bits of a side-s rank in a small-group hash key
 };
 
 struct DirectArgs {
@@ -44,8 +45,10 @@ struct DirectArgs {
   unsigned long long* res;
   int32_t n_items;
   int32_t acc_width;
+  uint32_t long_len;  // runs at least this long are streamed by the whole wavefront
 };
 
+// Reverse items (items) or small-item groups (items = groups, segs tagged).
 struct SmallArgs {
   const Item* items;
   const Segment* segs;
@@ -55,6 +58,7 @@ struct SmallArgs {
   unsigned long long* res;
   int32_t n_items;
   int32_t acc_width;
+  uint32_t long_len;
 };
 
 struct HashArgs {
@@ -64,6 +68,7 @@ struct HashArgs {
   uint32_t* queue;
   unsigned long long* res;
   int32_t n_items;
+  uint32_t long_len;
 };
 
 struct ReduceArgs {

@@ -32,9 +32,8 @@ PlanParams default_params(const HostGraph& g) {
   p.reverse_L = 4096;
   p.hub_T = 0;
   (void)g;
-  p.small_work = 1024;
+  p.small_work = static_cast<int32_t>(kSmallGroupWork);
   p.part_work = 1 << 20;
-  p.mid_work = kMidHashWork;
   return p;
 }
 
@@ -44,6 +43,73 @@ int64_t item_work(const HostPlan& plan, const Item& it) {
   int64_t w = 0;
   for (uint32_t k = 0; k < it.seg_count; ++k) w += plan.segs[it.seg_begin + k].len_g >> 1;
   return w;
+}
+
+// Pack the small items, in plan order, into groups of at most
+// kSmallGroupWork wedges that one wavefront counts in one hash table.  A
+// group's hash key is (index of the item in the group << key_bits) | key, so
+// the group may hold at most 2^(32 - key_bits) - 1 items (the all-ones word
+// marks an empty slot).  Items whose hub-pair counts go to the dense path
+// stay alone in their group (the group's owner and flags are theirs).
+void pack_small_groups(const HostGraph& g, HostPlan& plan) {
+  for (int s = 0; s < 2; ++s) {
+    int32_t kb = 1;
+    while ((int64_t{1} << kb) < g.side[s].n) ++kb;
+    plan.key_bits[s] = kb;
+  }
+  plan.small_groups.clear();
+  plan.small_segs.clear();
+  Item grp{};
+  bool open = false;
+  uint32_t local = 0;
+  auto close = [&]() {
+    if (!open) return;
+    grp.seg_count = static_cast<uint32_t>(plan.small_segs.size()) - grp.seg_begin;
+    grp.key_hi = static_cast<int32_t>(local);  // items in the group
+    plan.small_groups.push_back(grp);
+    open = false;
+  };
+  for (const Item& it : plan.small_items) {
+    const uint32_t max_items =
+        std::min<uint32_t>(kSmallMaxItems, (1u << (32 - plan.key_bits[it.side])) - 1u);
+    const bool hub = (it.flags & kItemHubPairs) != 0;
+    if (open && (hub || (grp.flags & kItemHubPairs) || grp.side != it.side ||
+                 grp.work + it.work > kSmallGroupWork || local >= max_items))
+      close();
+    if (!open) {
+      grp = Item{};
+      grp.seg_begin = static_cast<uint32_t>(plan.small_segs.size());
+      grp.owner = it.owner;
+      grp.acc_slot = -1;
+      grp.flags = it.flags & kItemHubPairs;
+      grp.side = it.side;
+      local = 0;
+      open = true;
+    }
+    for (uint32_t k = 0; k < it.seg_count; ++k) {
+      const Segment sg = plan.segs[it.seg_begin + k];
+      plan.small_segs.push_back(Segment{sg.start, (local << 16) | sg.len_g});
+    }
+    grp.work += it.work;
+    ++local;
+  }
+  close();
+}
+
+// Drop the segments of the small items (copied into the groups) from segs.
+void compact_segments(HostPlan& plan) {
+  std::vector<Segment> out;
+  size_t n = 0;
+  for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
+    for (const Item& it : *v) n += it.seg_count;
+  out.reserve(n);
+  for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
+    for (Item& it : *v) {
+      const uint32_t b = static_cast<uint32_t>(out.size());
+      out.insert(out.end(), plan.segs.begin() + it.seg_begin, plan.segs.begin() + it.seg_begin + it.seg_count);
+      it.seg_begin = b;
+    }
+  plan.segs = std::move(out);
 }
 
 }  // namespace
@@ -66,12 +132,9 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     err = "hub_T must not exceed window_L";
     return DBBC_E_INVALID_ARG;
   }
-  if (p.small_work < 2 || p.small_work > 1024 || p.part_work < 4096) {
-    err = "small_work must be in [2, 1024] and part_work at least 4096";
-    return DBBC_E_INVALID_ARG;
-  }
-  if (p.mid_work < 0 || p.mid_work > kMidHashWork) {
-    err = "mid_work must be in [0, " + std::to_string(kMidHashWork) + "]";
+  if (p.small_work < 2 || p.small_work > static_cast<int32_t>(kSmallGroupWork) || p.part_work < 4096) {
+    err = "small_work must be in [2, " + std::to_string(kSmallGroupWork) +
+          "] and part_work at least 4096";
     return DBBC_E_INVALID_ARG;
   }
   plan = HostPlan();
@@ -197,31 +260,8 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     }
     // Reverse items: endpoints w of side s below the window; keys x < R
     // (reverse), then keys x in [R, L) (reverse-mid).  Within row y the keys
-    // above y form the prefix [0, cut[y]).  When the keys in [R, L) have few
-    // wedges, one item walks both ranges (one run [0, min(splitL, cut)) per
-    // neighbour) and counts the upper keys in a small hash.
+    // above y form the prefix [0, cut[y]).
     for (int32_t w = L; w < S.n; ++w) {
-      if (R < L) {
-        int64_t mid_work = 0;
-        uint32_t nseg = 0;
-        for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
-          const uint32_t y = S.adj[e] >> 1;
-          const int32_t end = std::min(splitL[y], O.cut[y]);
-          mid_work += std::max(0, end - splitR[y]);
-          nseg += end > 0;
-        }
-        if (mid_work > 0 && mid_work <= p.mid_work && nseg <= kReverseMaxSegs) {
-          const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
-          for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
-            const uint32_t y = S.adj[e] >> 1;
-            const int32_t end = std::min(splitL[y], O.cut[y]);
-            if (end > 0)
-              plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(end) << 1) | (S.adj[e] & 1u)});
-          }
-          place(seg_begin, w, 0, L, kItemMidHash, kReverseTail);
-          continue;
-        }
-      }
       uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
       for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
         const uint32_t y = S.adj[e] >> 1;
@@ -312,6 +352,8 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   // heavy tail pivots first as well
   std::stable_sort(plan.hash_items.begin(), plan.hash_items.end(),
                    [&](const Item& a, const Item& b) { return item_work(plan, a) > item_work(plan, b); });
+  pack_small_groups(g, plan);
+  compact_segments(plan);
   auto tally = [&](int k, const std::vector<Item>& v) {
     for (const Item& it : v) {
       plan.k_wedges[k] += item_work(plan, it);
@@ -319,9 +361,12 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     }
   };
   tally(0, plan.direct_items);
-  tally(1, plan.small_items);
   tally(2, plan.hash_items);
   tally(3, plan.reverse_items);
+  for (const Item& grp : plan.small_groups) {  // group work never saturates
+    plan.k_wedges[1] += grp.work;
+    plan.k_segs[1] += grp.seg_count;
+  }
   return DBBC_OK;
 }
 

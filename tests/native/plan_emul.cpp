@@ -25,8 +25,7 @@ struct Acc {
 
 extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
                             const int8_t* sign, int32_t hub_T, int32_t window_L, int32_t reverse_L,
-                            int32_t small_work, int32_t part_work, int32_t mid_work,
-                            int64_t* out /* 13 */) {
+                            int32_t small_work, int32_t part_work, int64_t* out /* 13 */) {
   HostGraph g;
   std::string err;
   int rc = build_host_graph(n_u, n_v, m, u, v, sign, 0, g, err);
@@ -37,7 +36,6 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   if (reverse_L >= 0) p.reverse_L = reverse_L;
   if (small_work >= 0) p.small_work = small_work;
   if (part_work >= 0) p.part_work = part_work;
-  if (mid_work >= 0) p.mid_work = mid_work;
   HostPlan plan;
   rc = make_plan(g, p, plan, err);
   if (rc) {
@@ -63,11 +61,6 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
         ++walked;
       }
     }
-    if (it.flags & kItemMidHash) {  // the small hash of upper keys must not fill up
-      int64_t upper = 0;
-      for (auto& kv : cnt) upper += (int32_t)kv.first >= plan.R[it.side];
-      if (upper > kMidHashWork) return -104;
-    }
     for (auto& [key, pn] : cnt) {
       if (pn.first > limit || pn.second > limit) return -101;  // packed counter overflow
       if (it.flags & kItemMultiPart) {
@@ -85,10 +78,46 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
     }
     return 0;
   };
-  for (auto* list : {&plan.direct_items, &plan.small_items, &plan.hash_items})
+  for (auto* list : {&plan.direct_items, &plan.hash_items})
     for (const Item& it : *list) {
       if ((rc = run(it, 65535))) return rc;
     }
+  // small-item groups: tagged runs, one hash per group keyed by
+  // (index in group << key_bits) | key, as the kernel keys it
+  for (const Item& grp : plan.small_groups) {
+    const HostSide& O = g.side[1 - grp.side];
+    const uint32_t kb = (uint32_t)plan.key_bits[grp.side];
+    if (grp.work > kSmallGroupWork) return -105;
+    if ((grp.flags & kItemHubPairs) && grp.key_hi != 1) return -106;  // hub items stay alone
+    std::unordered_map<uint32_t, std::pair<int64_t, int64_t>> cnt;
+    int64_t w = 0;
+    for (uint32_t k = 0; k < grp.seg_count; ++k) {
+      const Segment s = plan.small_segs[grp.seg_begin + k];
+      const uint32_t local = s.len_g >> 16, len = (s.len_g & 0xffffu) >> 1, gb = s.len_g & 1u;
+      if ((int32_t)local >= grp.key_hi) return -107;
+      for (uint32_t t = 0; t < len; ++t) {
+        const uint32_t e = O.adj[s.start + t];
+        const uint32_t key = e >> 1;
+        if ((key >> kb) != 0) return -108;
+        const uint32_t hk = (local << kb) | key;
+        if (hk == 0xffffffffu) return -109;  // would collide with the empty marker
+        if (((e ^ gb) & 1u) == 0) cnt[hk].first++; else cnt[hk].second++;
+        ++walked;
+        ++w;
+      }
+    }
+    if (w != grp.work) return -110;
+    for (auto& [hk, pn] : cnt) {
+      const int32_t key = (int32_t)(hk & ((1u << kb) - 1u));
+      if ((grp.flags & kItemHubPairs) && key < plan.T[grp.side]) {
+        auto& h = hub[{(int)grp.side, grp.owner, key}];
+        h.first += pn.first;
+        h.second += pn.second;
+      } else {
+        acc.add(pn.first, pn.second);
+      }
+    }
+  }
   for (const Item& it : plan.reverse_items)
     if ((rc = run(it, kReverseMaxSegs))) return rc;
   for (const Reduce& r : plan.reduces) {
@@ -145,7 +174,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   out[5] = plan.w_skipped;
   out[6] = wdense;
   out[7] = walked;
-  out[8] = (int64_t)plan.small_items.size();
+  out[8] = (int64_t)plan.small_groups.size();
   out[9] = (int64_t)plan.direct_items.size();
   out[10] = (int64_t)plan.hash_items.size();
   out[11] = (int64_t)plan.reduces.size();

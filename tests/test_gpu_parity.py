@@ -75,7 +75,8 @@ def test_random_small_graphs(dbbc):
         want = _want(g)
         with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
             for opts in ({}, {"window_L": 256, "small_work": 2, "part_work": 4096},
-                         {"window_L": 512, "small_work": 1024, "reverse_L": 64}):
+                         {"window_L": 512, "small_work": 512, "reverse_L": 64},
+                         {"window_L": 256, "long_len": 16}, {"long_len": 65536}):
                 got = h.count(**opts)
                 assert tuple(got) == want, (seed, opts)
 
@@ -85,6 +86,7 @@ def test_random_small_graphs(dbbc):
     {"hub_T": 512, "window_L": 1024, "small_work": 64, "part_work": 4096},
     {"hub_T": 1024, "window_L": 32768}, {"window_L": 2048, "reverse_L": 64},
     {"window_L": 4096, "reverse_L": 4096, "small_work": 2},
+    {"long_len": 16}, {"long_len": 65536, "window_L": 256}, {"long_len": 48, "small_work": 300},
 ])
 def test_tiny_workload_option_sweep(dbbc, opts):
     g = config_graph("tiny")
@@ -121,7 +123,8 @@ def test_powerlaw2m_full_size(dbbc):
     want = _want(g)
     with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
         for opts in ({}, {"hub_T": 4096}, {"hub_T": 2048, "window_L": 8192}, {"hub_T": 0},
-                     {"reverse_L": 1024}, {"window_L": 4096, "reverse_L": 4096}):
+                     {"reverse_L": 1024}, {"window_L": 4096, "reverse_L": 4096},
+                     {"long_len": 16}, {"long_len": 4096}, {"small_work": 8}):
             _say("powerlaw2m", opts)
             assert tuple(h.count(**opts)) == want, opts
         # repeated runs give identical integers (a race would show here)

@@ -24,22 +24,23 @@ def emul(tmp_path_factory):
                            os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
-    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, i32, p]
+    lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, p]
 
-    def run(g, T=-1, L=-1, sw=-1, pw=-1, R=-1, mid=-1):
+    def run(g, T=-1, L=-1, sw=-1, pw=-1, R=-1):
         out = np.zeros(13, np.int64)
         if R < 0 and L >= 0:
             R = min(L, 4096)
         rc = lib.plan_emulate(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
-                              g.sign.ctypes.data, T, L, R, sw, pw, mid, out.ctypes.data)
+                              g.sign.ctypes.data, T, L, R, sw, pw, out.ctypes.data)
         assert rc == 0, rc
         return out
     return run
 
 
 # (hub_T, window_L, small_work, part_work, reverse_L)
-CONFIGS = [(0, 256, 2, 4096, 64), (128, 256, 64, 4096, 256), (256, 512, 1024, 8192, 128),
-           (0, 32768, 1024, 1 << 20, 4096), (256, 1024, 16, 4096, 512), (0, 2048, 1024, 4096, 2048)]
+CONFIGS = [(0, 256, 2, 4096, 64), (128, 256, 64, 4096, 256), (256, 512, 512, 8192, 128),
+           (0, 32768, 512, 1 << 20, 4096), (256, 1024, 16, 4096, 512), (0, 2048, 512, 4096, 2048),
+           (128, 1024, 300, 4096, 1024)]
 
 
 def _check(o, r):
@@ -57,8 +58,6 @@ def test_plan_partition_matches_oracle(emul, seed):
     r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
     for cfg in CONFIGS:
         _check(emul(g, *cfg), r)
-        _check(emul(g, *cfg, mid=0), r)
-        _check(emul(g, *cfg, mid=16), r)
 
 
 def test_plan_on_tiny_workload(emul):
@@ -74,7 +73,7 @@ def test_plan_on_small_and_degenerate_graphs(emul):
         n_u, n_v = int(rng.integers(1, 20)), int(rng.integers(1, 20))
         g = uniform_graph(n_u, n_v, int(rng.integers(0, n_u * n_v + 1)), 0.5, seed=seed)
         r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
-        for cfg in [(0, 256, 2, 4096, 64), (0, 256, 1024, 4096, 128)]:
+        for cfg in [(0, 256, 2, 4096, 64), (0, 256, 512, 4096, 128)]:
             _check(emul(g, *cfg), r)
 
 
@@ -82,7 +81,7 @@ def test_hub_block_on_dense_graph(emul):
     # a dense graph where the hub block covers most pairs
     g = chung_lu_graph(600, 500, 60000, 2.5, 2.5, 0.3, seed=7)
     r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
-    for cfg in [(256, 256, 64, 4096, 64), (384, 512, 2, 4096, 512), (0, 512, 1024, 4096, 128)]:
+    for cfg in [(256, 256, 64, 4096, 64), (384, 512, 2, 4096, 512), (0, 512, 512, 4096, 128)]:
         o = emul(g, *cfg)
         _check(o, r)
     assert emul(g, 256, 256, 64, 4096, 128)[6] > 0
@@ -93,7 +92,7 @@ def test_reverse_items_split_into_parts(emul):
     # items exceed 255 segments and are split into parts
     g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
     r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
-    for cfg in [(0, 256, 1024, 1 << 20, 64), (0, 256, 2, 4096, 256), (128, 256, 64, 4096, 128)]:
+    for cfg in [(0, 256, 512, 1 << 20, 64), (0, 256, 2, 4096, 256), (128, 256, 64, 4096, 128)]:
         o = emul(g, *cfg)
         _check(o, r)
         assert o[11] > 0  # multi-part reduces exist
