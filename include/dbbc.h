@@ -147,11 +147,74 @@ int dbbc_count(dbbc_graph *g, const dbbc_options *opt, dbbc_counts *out_host, vo
 int dbbc_count_per_vertex(dbbc_graph *g, int64_t *bal_u, int64_t *bal_v, int64_t *unb_u,
                           int64_t *unb_v, dbbc_counts *out_host, void *hip_stream);
 
-/* Count k graphs in one persistent launch (batched work queue).  gs: k
- * handles (k >= 0); out_host: k results in host memory.  The launch sequence
- * is captured once into a HIP graph per batch shape and replayed. */
+/* Asynchronous count: enqueue the same work as dbbc_count on hip_stream,
+ * with the results copied to host memory owned by the handle, and return
+ * without waiting.  Once the stream has passed this point (an event or a
+ * stream synchronisation of the caller), dbbc_count_read(g, out_host) checks
+ * and returns the results.  Until then no other call may use g.  Kernel
+ * timing (DBBC_OPT_TIME_KERNELS) is not available here. */
+int dbbc_count_async(dbbc_graph *g, const dbbc_options *opt, void *hip_stream);
+int dbbc_count_read(dbbc_graph *g, dbbc_counts *out_host);
+
+/* ---- batches: many graphs counted by one launch sequence ------------------ */
+
+/* A batch counts k distinct graphs with one launch of each kernel: the
+ * graphs' work lists are concatenated on the device and every item knows its
+ * graph, so the kernels' persistent workgroups drain the work of all graphs
+ * together and each graph's sums land in its own result slot.  Counts are
+ * exactly those of dbbc_count on each graph alone (same plans, same
+ * arithmetic).  With DBBC_BATCH_CAPTURE the launch sequence is captured once
+ * into a HIP graph and each dbbc_batch_launch replays it. */
+typedef struct dbbc_batch dbbc_batch;
+
+#define DBBC_BATCH_CAPTURE 0x1u
+
+/* Make a batch of the k graphs gs[0..k) (k >= 0, no handle twice).  opt
+ * applies to every graph (NULL = defaults; kernel timing not allowed) and
+ * plans each graph like dbbc_count would.  The batch borrows the handles:
+ * they must outlive it, and a graph must not be counted or re-planned
+ * elsewhere while the batch is in use (dbbc_batch_launch fails with
+ * DBBC_E_INVALID_ARG if a graph was re-planned since).  hip_stream orders the
+ * set-up copies; the call returns once they are done. */
+int dbbc_batch_create(dbbc_graph *const *gs, int32_t k, const dbbc_options *opt, uint32_t flags,
+                      void *hip_stream, dbbc_batch **out);
+
+/* Enqueue one count of every graph of the batch on hip_stream (replaying the
+ * captured HIP graph if there is one) and the copy of the k results to host
+ * memory owned by the batch; returns without waiting.  After the stream has
+ * passed this point, dbbc_batch_read writes the k results (host memory, in
+ * batch order) to out_host.  Launches of one batch must not overlap. */
+int dbbc_batch_launch(dbbc_batch *b, void *hip_stream);
+int dbbc_batch_read(const dbbc_batch *b, dbbc_counts *out_host);
+
+/* dbbc_batch_launch, a synchronisation of hip_stream and dbbc_batch_read. */
+int dbbc_batch_count(dbbc_batch *b, dbbc_counts *out_host, void *hip_stream);
+
+/* Number of graphs in the batch (0 for NULL). */
+int32_t dbbc_batch_size(const dbbc_batch *b);
+
+/* Free the batch (NULL is a no-op); the graphs stay. */
+void dbbc_batch_destroy(dbbc_batch *b);
+
+/* One-shot batch: make an uncaptured batch of gs[0..k), count it into
+ * out_host (k results, host memory) and free it. */
 int dbbc_count_batch(dbbc_graph *const *gs, int32_t k, const dbbc_options *opt,
                      dbbc_counts *out_host, void *hip_stream);
+
+/* Autotuner: picks the knobs of dbbc_options for the graphs gs[0..k)
+ * counted together as a batch (k = 1 tunes one graph).  Starting from
+ * *start (NULL = all defaults), a coordinate search visits the knobs in the
+ * order long_len, small_work (hash versus direct counters), window_L (direct
+ * array window, with reverse_L = min(window_L, 4096)), hub_T (the
+ * high-degree block counted with int8 MFMA) and part_work, tries each value
+ * of the knob's list with the others fixed, and keeps the fastest.  Every
+ * try captures the batch into a HIP graph, replays it once to warm up and
+ * times reps replays with HIP events on hip_stream.  Writes the winner to
+ * *best and its time per batch in ms to *best_ms (may be NULL).  Every
+ * candidate gives the same counts; only speed differs.  On return the
+ * graphs are planned with *best (batches made before are invalidated). */
+int dbbc_autotune(dbbc_graph *const *gs, int32_t k, const dbbc_options *start, int32_t reps,
+                  void *hip_stream, dbbc_options *best, float *best_ms);
 
 /* Kernel timings of the handle's last dbbc_count made with
  * DBBC_OPT_TIME_KERNELS.  Writes at most cap entries to out (host memory)

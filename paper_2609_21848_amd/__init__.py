@@ -31,12 +31,15 @@ DBBC_E_NO_DEVICE = -8
 DBBC_INPUT_DEVICE = 0x1
 DBBC_DUP_REJECT = 0x2
 DBBC_OPT_TIME_KERNELS = 0x1
+DBBC_BATCH_CAPTURE = 0x1
 
 # every symbol declared in include/dbbc.h
 EXPORTS = (
-    "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_per_vertex",
-    "dbbc_count_batch", "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string",
-    "dbbc_last_error", "dbbc_version",
+    "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async", "dbbc_count_read",
+    "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_launch", "dbbc_batch_read",
+    "dbbc_batch_count", "dbbc_batch_size", "dbbc_batch_destroy", "dbbc_count_batch", "dbbc_autotune",
+    "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string", "dbbc_last_error",
+    "dbbc_version",
 )
 
 
@@ -96,7 +99,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_graph_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
     lib.dbbc_count.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_per_vertex.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(_Counts), vp]
+    lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
+    lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
+    lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
+    lib.dbbc_batch_launch.argtypes = [vp, vp]
+    lib.dbbc_batch_read.argtypes = [vp, ctypes.POINTER(_Counts)]
+    lib.dbbc_batch_count.argtypes = [vp, ctypes.POINTER(_Counts), vp]
+    lib.dbbc_batch_size.argtypes = [vp]
+    lib.dbbc_batch_size.restype = i32
+    lib.dbbc_batch_destroy.argtypes = [vp]
+    lib.dbbc_batch_destroy.restype = None
     lib.dbbc_count_batch.argtypes = [vp, i32, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
+    lib.dbbc_autotune.argtypes = [vp, i32, ctypes.POINTER(Options), i32, vp, ctypes.POINTER(Options),
+                                  ctypes.POINTER(ctypes.c_float)]
     lib.dbbc_last_kernel_times.argtypes = [vp, ctypes.POINTER(_KernelTime), i32,
                                            ctypes.POINTER(i32)]
     lib.dbbc_graph_destroy.argtypes = [vp]
@@ -105,8 +120,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_status_string.restype = ctypes.c_char_p
     lib.dbbc_last_error.restype = ctypes.c_char_p
     lib.dbbc_version.restype = ctypes.c_char_p
-    for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_per_vertex",
-                 "dbbc_count_batch", "dbbc_last_kernel_times"):
+    for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async",
+                 "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_launch",
+                 "dbbc_batch_read", "dbbc_batch_count", "dbbc_count_batch", "dbbc_autotune",
+                 "dbbc_last_kernel_times"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -176,6 +193,17 @@ def dbbc_count(g: int, options: Options | None = None, stream=None) -> Counts:
     return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
 
 
+def dbbc_count_async(g: int, options: Options | None = None, stream=None) -> None:
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_count_async(g, opt, _stream_ptr(stream)), "dbbc_count_async")
+
+
+def dbbc_count_read(g: int) -> Counts:
+    c = _Counts()
+    _check(load().dbbc_count_read(g, ctypes.byref(c)), "dbbc_count_read")
+    return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
+
+
 def dbbc_count_per_vertex(g: int, bal_u=None, bal_v=None, unb_u=None, unb_v=None,
                           stream=None) -> Counts:
     """Fill caller-owned int64 device tensors (any may be None)."""
@@ -192,13 +220,61 @@ def dbbc_count_per_vertex(g: int, bal_u=None, bal_v=None, unb_u=None, unb_v=None
     return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
 
 
+def _handles(gs):
+    hs = [getattr(g, "handle", g) for g in gs]
+    return (ctypes.c_void_p * max(len(hs), 1))(*hs), len(hs)
+
+
+def dbbc_batch_create(gs, options: Options | None = None, flags: int = 0, stream=None) -> int:
+    arr, k = _handles(gs)
+    out = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_batch_create(arr, k, opt, int(flags), _stream_ptr(stream), ctypes.byref(out)),
+           "dbbc_batch_create")
+    return out.value
+
+
+def dbbc_batch_launch(b: int, stream=None) -> None:
+    _check(load().dbbc_batch_launch(b, _stream_ptr(stream)), "dbbc_batch_launch")
+
+
+def dbbc_batch_read(b: int) -> list:
+    k = load().dbbc_batch_size(b)
+    out = (_Counts * max(k, 1))()
+    _check(load().dbbc_batch_read(b, out), "dbbc_batch_read")
+    return [Counts(c.balanced, c.unbalanced, c.total, c.wedges) for c in out[:k]]
+
+
+def dbbc_batch_count(b: int, stream=None) -> list:
+    k = load().dbbc_batch_size(b)
+    out = (_Counts * max(k, 1))()
+    _check(load().dbbc_batch_count(b, out, _stream_ptr(stream)), "dbbc_batch_count")
+    return [Counts(c.balanced, c.unbalanced, c.total, c.wedges) for c in out[:k]]
+
+
+def dbbc_batch_destroy(b: int) -> None:
+    if b:
+        load().dbbc_batch_destroy(b)
+
+
 def dbbc_count_batch(gs, options: Options | None = None, stream=None) -> list:
-    k = len(gs)
-    arr = (ctypes.c_void_p * max(k, 1))(*gs)
+    arr, k = _handles(gs)
     out = (_Counts * max(k, 1))()
     opt = ctypes.byref(options) if options is not None else None
     _check(load().dbbc_count_batch(arr, k, opt, out, _stream_ptr(stream)), "dbbc_count_batch")
     return [Counts(c.balanced, c.unbalanced, c.total, c.wedges) for c in out[:k]]
+
+
+def dbbc_autotune(gs, start: Options | None = None, reps: int = 3, stream=None):
+    """(best options as a dict of the knobs, ms per batch) for graphs gs."""
+    arr, k = _handles(gs)
+    best = Options()
+    ms = ctypes.c_float()
+    opt = ctypes.byref(start) if start is not None else None
+    _check(load().dbbc_autotune(arr, k, opt, int(reps), _stream_ptr(stream), ctypes.byref(best),
+                                ctypes.byref(ms)), "dbbc_autotune")
+    knobs = {k: int(getattr(best, k)) for k, _ in Options._fields_ if k != "flags"}
+    return knobs, float(ms.value)
 
 
 def dbbc_last_kernel_times(g: int) -> list:
@@ -230,6 +306,12 @@ class Graph:
     def count(self, stream=None, **opts) -> Counts:
         return dbbc_count(self.handle, Options(**opts) if opts else None, stream)
 
+    def count_async(self, stream=None, **opts) -> None:
+        dbbc_count_async(self.handle, Options(**opts) if opts else None, stream)
+
+    def read(self) -> Counts:
+        return dbbc_count_read(self.handle)
+
     def kernel_times(self) -> list:
         return dbbc_last_kernel_times(self.handle)
 
@@ -239,6 +321,41 @@ class Graph:
     def close(self):
         if self.handle:
             dbbc_graph_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owning wrapper of a batch of Graph objects (kept alive by the batch)."""
+
+    def __init__(self, graphs, capture: bool = False, stream=None, **opts):
+        self.graphs = list(graphs)
+        self.handle = dbbc_batch_create(self.graphs, Options(**opts) if opts else None,
+                                        DBBC_BATCH_CAPTURE if capture else 0, stream)
+
+    def count(self, stream=None) -> list:
+        return dbbc_batch_count(self.handle, stream)
+
+    def launch(self, stream=None) -> None:
+        dbbc_batch_launch(self.handle, stream)
+
+    def read(self) -> list:
+        return dbbc_batch_read(self.handle)
+
+    def close(self):
+        if self.handle:
+            dbbc_batch_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

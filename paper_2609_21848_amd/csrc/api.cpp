@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "internal.h"
@@ -82,24 +84,27 @@ hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
   return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
-// Control block: res[0..7] int64 results, then 8 uint32 work-queue heads.
+
+// Control block of a count: [0, 4) the result slot of a lone count,
+// [4] kernel error bits, [8, 16) sixteen uint32 work-queue heads.
 constexpr size_t kCtlWords = 16;
+constexpr size_t kCtlErr = 4;
+constexpr size_t kCtlQueues = 8;
 
 struct DevPlan {
   dbbc::HostPlan host;
-  DevBuf segs, small_segs, small_groups, direct_items, hash_items, reverse_items, reduces, acc;
+  DevBuf segs, small_segs, small_groups, direct_items, hash_items, reverse_items, reduces, acc, sides;
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
+  dbbc::DevSideConst side[2] = {};  // host copy of the side table
   bool valid = false;
   size_t bytes() const {
     size_t b = segs.bytes + small_segs.bytes + small_groups.bytes + direct_items.bytes +
-               hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes;
+               hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes + sides.bytes;
     for (int s = 0; s < 2; ++s) b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes;
     return b;
   }
 };
-
-}  // namespace
 
 // HIP events around one kernel launch of a timed count.
 struct KernelRec {
@@ -109,16 +114,179 @@ struct KernelRec {
   float ms = 0.f;
 };
 
+// One dense hub launch (one side of one graph).
+struct HubLaunch {
+  dbbc::HubArgs a;
+  int64_t tiles = 0, macs = 0;
+  const char* name = "";
+};
+
+// Everything one count (of one graph or of a batch) launches.
+struct LaunchSet {
+  const dbbc::Item* direct = nullptr;
+  const dbbc::Item* reverse = nullptr;
+  const dbbc::Item* small = nullptr;
+  const dbbc::Item* hash = nullptr;
+  const dbbc::Reduce* reduces = nullptr;
+  int32_t n[5] = {0, 0, 0, 0, 0};  // direct, reverse, small, hash, reduces
+  int64_t wedges[4] = {0, 0, 0, 0}, segs[4] = {0, 0, 0, 0};  // direct, small, hash, reverse
+  const dbbc::DevSideConst* sides = nullptr;
+  unsigned long long* res = nullptr;
+  size_t n_res = 0;  // result words zeroed before the count
+  unsigned long long* ctl = nullptr;
+  std::vector<std::pair<unsigned long long*, size_t>> zero;  // hub-pair buffers
+  std::vector<HubLaunch> hubs;
+  uint32_t long_len = 0;
+  int cus = 0;
+};
+
+// Begin / end one timed launch (no-ops when recs is null).
+struct Timing {
+  std::vector<KernelRec>* recs;
+  size_t used = 0;
+  hipStream_t st;
+  int begin(const char* name, int64_t wedges, int64_t segs, int64_t items, int64_t macs) {
+    if (!recs) return DBBC_OK;
+    if (used == recs->size()) recs->emplace_back();
+    KernelRec& r = (*recs)[used];
+    for (auto& e : r.ev)
+      if (!e) HIP_TRY(hipEventCreate(&e));
+    r.name = name;
+    r.wedges = wedges;
+    r.segments = segs;
+    r.items = items;
+    r.macs = macs;
+    HIP_TRY(hipEventRecord(r.ev[0], st));
+    return DBBC_OK;
+  }
+  int end() {
+    if (!recs) return DBBC_OK;
+    HIP_TRY(hipEventRecord((*recs)[used++].ev[1], st));
+    return DBBC_OK;
+  }
+};
+
+#define RC_TRY(expr)                \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != DBBC_OK) return rc_; \
+  } while (0)
+
+// Enqueue a whole count on stream st.  Every buffer the kernels accumulate
+// into is cleared by a fill kernel first (never a memset node, so that the
+// sequence can be captured into a HIP graph and replayed).
+int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
+  HIP_TRY(dbbc::launch_fill_u64(L.ctl, kCtlWords, 0ull, st));
+  if (L.res != L.ctl) HIP_TRY(dbbc::launch_fill_u64(L.res, L.n_res, 0ull, st));
+  for (const auto& z : L.zero) HIP_TRY(dbbc::launch_fill_u64(z.first, z.second, 0ull, st));
+  unsigned long long* err = L.ctl + kCtlErr;
+  uint32_t* queues = reinterpret_cast<uint32_t*>(L.ctl + kCtlQueues);
+  const int cus = L.cus;
+  {
+    dbbc::DirectArgs a{};
+    a.items = L.direct;
+    a.sides = L.sides;
+    a.queue = queues + 0;
+    a.res = L.res;
+    a.err = err;
+    a.n_items = L.n[0];
+    a.long_len = L.long_len;
+    RC_TRY(tm.begin("direct", L.wedges[0], L.segs[0], a.n_items, 0));
+    HIP_TRY(dbbc::launch_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+    RC_TRY(tm.end());
+  }
+  {
+    dbbc::SmallArgs a{};
+    a.items = L.reverse;
+    a.sides = L.sides;
+    a.res = L.res;
+    a.err = err;
+    a.n_items = L.n[1];
+    a.long_len = L.long_len;
+    RC_TRY(tm.begin("reverse", L.wedges[3], L.segs[3], a.n_items, 0));
+    HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 15) / 16)), st));
+    RC_TRY(tm.end());
+  }
+  {
+    dbbc::SmallArgs a{};
+    a.items = L.small;
+    a.sides = L.sides;
+    a.res = L.res;
+    a.err = err;
+    a.n_items = L.n[2];
+    a.long_len = L.long_len;
+    RC_TRY(tm.begin("small", L.wedges[1], L.segs[1], a.n_items, 0));
+    HIP_TRY(dbbc::launch_small(a, std::min<int>(4 * cus, std::max(1, (a.n_items + 3) / 4)), st));
+    RC_TRY(tm.end());
+  }
+  {
+    dbbc::HashArgs a{};
+    a.items = L.hash;
+    a.sides = L.sides;
+    a.queue = queues + 2;
+    a.res = L.res;
+    a.err = err;
+    a.n_items = L.n[3];
+    a.long_len = L.long_len;
+    RC_TRY(tm.begin("hash", L.wedges[2], L.segs[2], a.n_items, 0));
+    HIP_TRY(dbbc::launch_hash(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+    RC_TRY(tm.end());
+  }
+  {
+    dbbc::ReduceArgs a{};
+    a.reduces = L.reduces;
+    a.sides = L.sides;
+    a.res = L.res;
+    a.err = err;
+    a.n_reduces = L.n[4];
+    RC_TRY(tm.begin("reduce", 0, 0, a.n_reduces, 0));
+    HIP_TRY(dbbc::launch_reduce(a, std::min<int>(4 * cus, std::max(1, a.n_reduces)), st));
+    RC_TRY(tm.end());
+  }
+  for (const HubLaunch& h : L.hubs) {
+    RC_TRY(tm.begin(h.name, 0, 0, h.tiles, h.macs));
+    HIP_TRY(dbbc::launch_hub(h.a, st));
+    RC_TRY(tm.end());
+  }
+  return DBBC_OK;
+}
+
+// Dense hub launches of a graph's plan, results into res (its slot).
+void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L) {
+  const dbbc::HostPlan& hp = d.host;
+  for (int s = 0; s < 2; ++s) {
+    if (hp.T[s] == 0) continue;
+    L.zero.push_back({d.hub_pairs[s].as<unsigned long long>(), static_cast<size_t>(hp.T[s]) * hp.T[s]});
+    HubLaunch h;
+    h.a.Bm = d.hub_Bm[s].as<int8_t>();
+    h.a.B = d.hub_B[s].as<int8_t>();
+    h.a.hub_pairs = d.hub_pairs[s].as<unsigned long long>();
+    h.a.res = res;
+    h.a.T = hp.T[s];
+    h.a.K = d.hub_K[s];
+    // two contractions over K for every tile of the upper triangle
+    const int64_t nt = h.a.T / 128;
+    h.tiles = nt * (nt + 1) / 2;
+    h.macs = 2 * h.tiles * 128 * 128 * static_cast<int64_t>(h.a.K);
+    h.name = s == 0 ? "hub_u" : "hub_v";
+    L.hubs.push_back(h);
+  }
+}
+
+}  // namespace
+
 struct dbbc_graph {
   dbbc::HostGraph host;
   DeviceInfo dev;
   DevBuf adj[2], off[2];
   DevBuf ctl;
-  unsigned long long* pinned = nullptr;  // host mirror of ctl results
+  unsigned long long* pinned = nullptr;  // host mirror of ctl
   DevPlan plan;
+  uint64_t plan_gen = 0;  // bumped whenever the device plan is rebuilt
   std::vector<KernelRec> timers;  // events are reused across timed counts
   size_t timers_used = 0;
   bool timed_valid = false;
+  bool in_flight = false;  // an asynchronous count awaits dbbc_count_read
   ~dbbc_graph() {
     if (pinned) (void)hipHostFree(pinned);
     for (auto& t : timers)
@@ -127,14 +295,38 @@ struct dbbc_graph {
   }
 };
 
+struct dbbc_batch {
+  std::vector<dbbc_graph*> gs;
+  std::vector<uint64_t> gens;  // plan generation of each graph at creation
+  DeviceInfo dev;
+  DevBuf direct, reverse, small, hash, reduces, sides, srcs, res, ctl;
+  LaunchSet L;
+  unsigned long long* pinned = nullptr;  // k result slots, then the error word
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~dbbc_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
 namespace {
 
 int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   if (g->plan.valid && g->plan.host.p == p) return DBBC_OK;
   g->plan.valid = false;
+  ++g->plan_gen;
   std::string err;
   dbbc::HostPlan hp;
-  int rc = dbbc::make_plan(g->host, p, hp, err);
+  int rc;
+  try {
+    rc = dbbc::make_plan(g->host, p, hp, err);
+  } catch (const std::bad_alloc&) {
+    return fail(DBBC_E_OOM, "host allocation failed while planning");
+  }
   if (rc != DBBC_OK) return fail(rc, err);
   DevPlan& d = g->plan;
   HIP_TRY(upload(d.segs, hp.segs, st));
@@ -168,6 +360,21 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
     hp.hub_Bm[s].clear();
     hp.hub_Bm[s].shrink_to_fit();
   }
+  for (int s = 0; s < 2; ++s) {
+    dbbc::DevSideConst& c = d.side[s];
+    c = dbbc::DevSideConst{};
+    c.other_adj = g->adj[1 - s].as<uint32_t>();
+    c.segs = d.segs.as<dbbc::Segment>();
+    c.small_segs = d.small_segs.as<dbbc::Segment>();
+    c.hub_pairs = d.hub_pairs[s].as<unsigned long long>();
+    c.acc = d.acc.as<uint32_t>();
+    c.T = hp.T[s];
+    c.R = hp.R[s];
+    c.key_bits = hp.key_bits[s];
+    c.acc_width = hp.acc_width;
+  }
+  HIP_TRY(d.sides.alloc(sizeof(d.side)));
+  HIP_TRY(hipMemcpyAsync(d.sides.p, d.side, sizeof(d.side), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   // the host plan keeps only what later launches need
   hp.segs.clear();
@@ -176,13 +383,24 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   hp.small_segs.shrink_to_fit();
   hp.small_items.clear();
   hp.small_items.shrink_to_fit();
+  for (auto* v : {&hp.small_groups, &hp.direct_items, &hp.hash_items, &hp.reverse_items}) {
+    v->clear();
+    v->shrink_to_fit();
+  }
+  hp.n_items_kept[0] = static_cast<int32_t>(d.direct_items.bytes / sizeof(dbbc::Item));
+  hp.n_items_kept[1] = static_cast<int32_t>(d.reverse_items.bytes / sizeof(dbbc::Item));
+  hp.n_items_kept[2] = static_cast<int32_t>(d.small_groups.bytes / sizeof(dbbc::Item));
+  hp.n_items_kept[3] = static_cast<int32_t>(d.hash_items.bytes / sizeof(dbbc::Item));
+  hp.n_items_kept[4] = static_cast<int32_t>(d.reduces.bytes / sizeof(dbbc::Reduce));
+  hp.reduces.clear();
+  hp.reduces.shrink_to_fit();
   d.host = std::move(hp);
   d.valid = true;
   return DBBC_OK;
 }
 
 // Runs of at least this many entries are streamed by a whole wavefront.
-constexpr int32_t kDefaultLongLen = 256;
+constexpr int32_t kDefaultLongLen = 128;
 
 int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& p, uint32_t& long_len) {
   p = dbbc::default_params(g->host);
@@ -204,148 +422,77 @@ int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& 
   return DBBC_OK;
 }
 
-// Begin / end one timed launch (no-ops when timing is off).
-struct Timing {
-  dbbc_graph* g;
-  hipStream_t st;
-  bool on;
-  KernelRec* cur = nullptr;
-  int begin(const char* name, int64_t wedges, int64_t segs, int64_t items, int64_t macs) {
-    if (!on) return DBBC_OK;
-    if (g->timers_used == g->timers.size()) g->timers.emplace_back();
-    cur = &g->timers[g->timers_used++];
-    for (auto& e : cur->ev)
-      if (!e) HIP_TRY(hipEventCreate(&e));
-    cur->name = name;
-    cur->wedges = wedges;
-    cur->segments = segs;
-    cur->items = items;
-    cur->macs = macs;
-    HIP_TRY(hipEventRecord(cur->ev[0], st));
-    return DBBC_OK;
-  }
-  int end() {
-    if (!on) return DBBC_OK;
-    HIP_TRY(hipEventRecord(cur->ev[1], st));
-    return DBBC_OK;
-  }
-};
-
-#define RC_TRY(expr)            \
-  do {                          \
-    int rc_ = (expr);           \
-    if (rc_ != DBBC_OK) return rc_; \
-  } while (0)
-
-// Enqueue the whole count on stream st; results land in g->ctl.
-int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed, uint32_t long_len) {
-  Timing tm{g, st, timed};
-  g->timers_used = 0;
+// The launch set of a lone count of g (results into g's control block).
+LaunchSet lone_launches(dbbc_graph* g, uint32_t long_len) {
   DevPlan& d = g->plan;
   const dbbc::HostPlan& hp = d.host;
-  unsigned long long* ctl = g->ctl.as<unsigned long long>();
-  uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + 8);
-  HIP_TRY(dbbc::launch_fill_u64(ctl, kCtlWords, 0ull, st));
-  dbbc::DevSideConst side[2];
-  for (int s = 0; s < 2; ++s) {
-    side[s].other_adj = g->adj[1 - s].as<uint32_t>();
-    side[s].hub_pairs = d.hub_pairs[s].as<unsigned long long>();
-    side[s].T = hp.T[s];
-    side[s].R = hp.R[s];
-    side[s].key_bits = hp.key_bits[s];
-    if (hp.T[s] > 0)
-      HIP_TRY(dbbc::launch_fill_u64(side[s].hub_pairs, static_cast<size_t>(hp.T[s]) * hp.T[s], 0ull, st));
+  LaunchSet L;
+  L.direct = d.direct_items.as<dbbc::Item>();
+  L.reverse = d.reverse_items.as<dbbc::Item>();
+  L.small = d.small_groups.as<dbbc::Item>();
+  L.hash = d.hash_items.as<dbbc::Item>();
+  L.reduces = d.reduces.as<dbbc::Reduce>();
+  for (int k = 0; k < 5; ++k) L.n[k] = hp.n_items_kept[k];
+  for (int k = 0; k < 4; ++k) {
+    L.wedges[k] = hp.k_wedges[k];
+    L.segs[k] = hp.k_segs[k];
   }
-  const int cus = g->dev.cus;
-  {
-    dbbc::DirectArgs a{};
-    a.items = d.direct_items.as<dbbc::Item>();
-    a.segs = d.segs.as<dbbc::Segment>();
-    a.side[0] = side[0];
-    a.side[1] = side[1];
-    a.queue = queues + 0;
-    a.acc = d.acc.as<uint32_t>();
-    a.res = ctl;
-    a.n_items = static_cast<int32_t>(hp.direct_items.size());
-    a.acc_width = hp.acc_width;
-    a.long_len = long_len;
-    RC_TRY(tm.begin("direct", hp.k_wedges[0], hp.k_segs[0], a.n_items, 0));
-    HIP_TRY(dbbc::launch_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
-    RC_TRY(tm.end());
+  L.sides = d.sides.as<dbbc::DevSideConst>();
+  L.ctl = g->ctl.as<unsigned long long>();
+  L.res = L.ctl;
+  L.n_res = dbbc::kResStride;
+  add_hub_launches(d, L.res, L);
+  L.long_len = long_len;
+  L.cus = g->dev.cus;
+  return L;
+}
+
+int check_graph(const dbbc_graph* g) {
+  if (!g) return fail(DBBC_E_INVALID_ARG, "NULL graph");
+  if (g->in_flight) return fail(DBBC_E_INVALID_ARG, "the graph has an asynchronous count in flight");
+  return DBBC_OK;
+}
+
+void read_counts(const dbbc_graph* g, const unsigned long long* slot, dbbc_counts* out) {
+  out->balanced = static_cast<int64_t>(slot[dbbc::kResBalanced]);
+  out->unbalanced = static_cast<int64_t>(slot[dbbc::kResUnbalanced]);
+  out->total = static_cast<int64_t>(slot[dbbc::kResTotal]);
+  out->wedges = g->host.wedges_vp;
+}
+
+// Plan (if needed) and enqueue a lone count of g, then the copy of its
+// control block to pinned host memory.
+int enqueue_lone(dbbc_graph* g, const dbbc_options* opt, hipStream_t st) {
+  dbbc::PlanParams p;
+  uint32_t long_len = 0;
+  int rc = params_from(g, opt, p, long_len);
+  if (rc != DBBC_OK) return rc;
+  rc = ensure_plan(g, p, st);
+  if (rc != DBBC_OK) return rc;
+  const bool timed = opt && (opt->flags & DBBC_OPT_TIME_KERNELS);
+  g->timed_valid = false;
+  Timing tm{timed ? &g->timers : nullptr, 0, st};
+  const LaunchSet L = lone_launches(g, long_len);
+  rc = enqueue(L, st, tm);
+  g->timers_used = tm.used;
+  if (rc != DBBC_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(g->pinned, g->ctl.p, kCtlWords * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, st));
+  return DBBC_OK;
+}
+
+int finish_lone(dbbc_graph* g, dbbc_counts* out_host, bool timed) {
+  if (g->pinned[kCtlErr] != 0)
+    return fail(DBBC_E_DEVICE, "a kernel reported an internal overflow (error bits " +
+                                   std::to_string(g->pinned[kCtlErr]) + ")");
+  if (timed) {
+    for (size_t i = 0; i < g->timers_used; ++i) {
+      KernelRec& t = g->timers[i];
+      HIP_TRY(hipEventElapsedTime(&t.ms, t.ev[0], t.ev[1]));
+    }
+    g->timed_valid = true;
   }
-  {
-    dbbc::SmallArgs a{};
-    a.items = d.reverse_items.as<dbbc::Item>();
-    a.segs = d.segs.as<dbbc::Segment>();
-    a.side[0] = side[0];
-    a.side[1] = side[1];
-    a.queue = queues + 3;
-    a.acc = d.acc.as<uint32_t>();
-    a.acc_width = hp.acc_width;
-    a.res = ctl;
-    a.n_items = static_cast<int32_t>(hp.reverse_items.size());
-    a.long_len = long_len;
-    RC_TRY(tm.begin("reverse", hp.k_wedges[3], hp.k_segs[3], a.n_items, 0));
-    HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 15) / 16)), st));
-    RC_TRY(tm.end());
-  }
-  {
-    dbbc::SmallArgs a{};
-    a.items = d.small_groups.as<dbbc::Item>();
-    a.segs = d.small_segs.as<dbbc::Segment>();
-    a.side[0] = side[0];
-    a.side[1] = side[1];
-    a.queue = queues + 1;
-    a.res = ctl;
-    a.n_items = static_cast<int32_t>(hp.small_groups.size());
-    a.long_len = long_len;
-    RC_TRY(tm.begin("small", hp.k_wedges[1], hp.k_segs[1], a.n_items, 0));
-    HIP_TRY(dbbc::launch_small(a, std::min<int>(4 * cus, std::max(1, (a.n_items + 3) / 4)), st));
-    RC_TRY(tm.end());
-  }
-  {
-    dbbc::HashArgs a{};
-    a.items = d.hash_items.as<dbbc::Item>();
-    a.segs = d.segs.as<dbbc::Segment>();
-    a.side[0] = side[0];
-    a.side[1] = side[1];
-    a.queue = queues + 2;
-    a.res = ctl;
-    a.n_items = static_cast<int32_t>(hp.hash_items.size());
-    a.long_len = long_len;
-    RC_TRY(tm.begin("hash", hp.k_wedges[2], hp.k_segs[2], a.n_items, 0));
-    HIP_TRY(dbbc::launch_hash(a, std::min<int>(cus, std::max(1, a.n_items)), st));
-    RC_TRY(tm.end());
-  }
-  {
-    dbbc::ReduceArgs a{};
-    a.reduces = d.reduces.as<dbbc::Reduce>();
-    a.side[0] = side[0];
-    a.side[1] = side[1];
-    a.acc = d.acc.as<uint32_t>();
-    a.res = ctl;
-    a.n_reduces = static_cast<int32_t>(hp.reduces.size());
-    a.acc_width = hp.acc_width;
-    RC_TRY(tm.begin("reduce", 0, 0, a.n_reduces, 0));
-    HIP_TRY(dbbc::launch_reduce(a, std::min<int>(4 * cus, std::max(1, a.n_reduces)), st));
-    RC_TRY(tm.end());
-  }
-  for (int s = 0; s < 2; ++s) {
-    if (hp.T[s] == 0) continue;
-    dbbc::HubArgs a{};
-    a.Bm = d.hub_Bm[s].as<int8_t>();
-    a.B = d.hub_B[s].as<int8_t>();
-    a.hub_pairs = side[s].hub_pairs;
-    a.res = ctl;
-    a.T = hp.T[s];
-    a.K = d.hub_K[s];
-    // two contractions over K for every tile of the upper triangle
-    const int64_t nt = a.T / 128;
-    const int64_t macs = 2 * (nt * (nt + 1) / 2) * 128 * 128 * static_cast<int64_t>(a.K);
-    RC_TRY(tm.begin(s == 0 ? "hub_u" : "hub_v", 0, 0, nt * (nt + 1) / 2, macs));
-    HIP_TRY(dbbc::launch_hub(a, st));
-    RC_TRY(tm.end());
-  }
+  read_counts(g, g->pinned, out_host);
   return DBBC_OK;
 }
 
@@ -353,7 +500,7 @@ int enqueue_count(dbbc_graph* g, hipStream_t st, bool timed, uint32_t long_len) 
 
 extern "C" {
 
-const char* dbbc_version(void) { return "0.1.0"; }
+const char* dbbc_version(void) { return "0.2.0"; }
 
 const char* dbbc_last_error(void) { return g_last_error.c_str(); }
 
@@ -450,36 +597,34 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
 
 int dbbc_count(dbbc_graph* g, const dbbc_options* opt, dbbc_counts* out_host, void* hip_stream) {
   g_last_error.clear();
-  if (!g || !out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
+  if (!out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
+  int rc = check_graph(g);
+  if (rc != DBBC_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  dbbc::PlanParams p;
-  uint32_t long_len = 0;
-  int rc = params_from(g, opt, p, long_len);
+  rc = enqueue_lone(g, opt, st);
   if (rc != DBBC_OK) return rc;
-  rc = ensure_plan(g, p, st);
-  if (rc != DBBC_OK) return rc;
-  const bool timed = opt && (opt->flags & DBBC_OPT_TIME_KERNELS);
-  g->timed_valid = false;
-  rc = enqueue_count(g, st, timed, long_len);
-  if (rc != DBBC_OK) return rc;
-  HIP_TRY(hipMemcpyAsync(g->pinned, g->ctl.p, kCtlWords * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (g->pinned[dbbc::kResError] != 0)
-    return fail(DBBC_E_DEVICE, "a kernel reported an internal overflow (error bits " +
-                                   std::to_string(g->pinned[dbbc::kResError]) + ")");
-  if (timed) {
-    for (size_t i = 0; i < g->timers_used; ++i) {
-      KernelRec& t = g->timers[i];
-      HIP_TRY(hipEventElapsedTime(&t.ms, t.ev[0], t.ev[1]));
-    }
-    g->timed_valid = true;
-  }
-  out_host->balanced = static_cast<int64_t>(g->pinned[0]);
-  out_host->unbalanced = static_cast<int64_t>(g->pinned[1]);
-  out_host->total = static_cast<int64_t>(g->pinned[2]);
-  out_host->wedges = g->host.wedges_vp;
+  return finish_lone(g, out_host, opt && (opt->flags & DBBC_OPT_TIME_KERNELS));
+}
+
+int dbbc_count_async(dbbc_graph* g, const dbbc_options* opt, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_graph(g);
+  if (rc != DBBC_OK) return rc;
+  if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
+    return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
+  rc = enqueue_lone(g, opt, static_cast<hipStream_t>(hip_stream));
+  if (rc != DBBC_OK) return rc;
+  g->in_flight = true;
   return DBBC_OK;
+}
+
+int dbbc_count_read(dbbc_graph* g, dbbc_counts* out_host) {
+  g_last_error.clear();
+  if (!g || !out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
+  if (!g->in_flight) return fail(DBBC_E_INVALID_ARG, "no asynchronous count on this graph");
+  g->in_flight = false;
+  return finish_lone(g, out_host, false);
 }
 
 int dbbc_count_per_vertex(dbbc_graph* g, int64_t* bal_u, int64_t* bal_v, int64_t* unb_u,
@@ -488,14 +633,251 @@ int dbbc_count_per_vertex(dbbc_graph* g, int64_t* bal_u, int64_t* bal_v, int64_t
   return fail(DBBC_E_INVALID_ARG, "per-vertex counts are not available in this build");
 }
 
-int dbbc_count_batch(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
-                     dbbc_counts* out_host, void* hip_stream) {
+int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt, uint32_t flags,
+                      void* hip_stream, dbbc_batch** out) {
   g_last_error.clear();
-  if (k < 0 || (k > 0 && (!gs || !out_host))) return fail(DBBC_E_INVALID_ARG, "bad batch arguments");
+  if (!out || k < 0 || (k > 0 && !gs)) return fail(DBBC_E_INVALID_ARG, "bad batch arguments");
+  if (flags & ~DBBC_BATCH_CAPTURE) return fail(DBBC_E_INVALID_ARG, "unknown batch flag");
+  if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
+    return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
+  std::unique_ptr<dbbc_batch> b(new (std::nothrow) dbbc_batch());
+  if (!b) return fail(DBBC_E_OOM, "host allocation failed");
+  std::unordered_set<const dbbc_graph*> seen;
   for (int32_t i = 0; i < k; ++i) {
-    int rc = dbbc_count(gs[i], opt, &out_host[i], hip_stream);
+    int rc = check_graph(gs[i]);
+    if (rc != DBBC_OK) return rc;
+    if (!seen.insert(gs[i]).second) return fail(DBBC_E_INVALID_ARG, "a graph appears twice in the batch");
+  }
+  int rc = current_device(b->dev);
+  if (rc != DBBC_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  uint32_t long_len = kDefaultLongLen;
+  int64_t tot[5] = {0, 0, 0, 0, 0};
+  LaunchSet& L = b->L;
+  for (int32_t i = 0; i < k; ++i) {
+    dbbc::PlanParams p;
+    rc = params_from(gs[i], opt, p, long_len);
+    if (rc != DBBC_OK) return rc;
+    rc = ensure_plan(gs[i], p, st);
+    if (rc != DBBC_OK) return rc;
+    const dbbc::HostPlan& hp = gs[i]->plan.host;
+    for (int j = 0; j < 5; ++j) tot[j] += hp.n_items_kept[j];
+    for (int j = 0; j < 4; ++j) {
+      L.wedges[j] += hp.k_wedges[j];
+      L.segs[j] += hp.k_segs[j];
+    }
+  }
+  for (int j = 0; j < 5; ++j)
+    if (tot[j] > INT32_MAX) return fail(DBBC_E_TOO_LARGE, "too many work items in one batch");
+  b->gs.assign(gs, gs + k);
+  for (int32_t i = 0; i < k; ++i) b->gens.push_back(gs[i]->plan_gen);
+  HIP_TRY(b->res.alloc(static_cast<size_t>(std::max(k, 1)) * dbbc::kResStride * sizeof(unsigned long long)));
+  HIP_TRY(b->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->pinned),
+                        (static_cast<size_t>(k) * dbbc::kResStride + 1) * sizeof(unsigned long long),
+                        hipHostMallocDefault));
+  if (k == 0) {
+    *out = b.release();
+    return DBBC_OK;
+  }
+  // Assemble the k graphs' lists into one list per kernel, on the device.
+  DevBuf* lists[5] = {&b->direct, &b->reverse, &b->small, &b->hash, &b->reduces};
+  std::vector<dbbc::AssembleSrc> srcs(static_cast<size_t>(5) * k);
+  for (int j = 0; j < 5; ++j) {
+    const size_t esz = j == 4 ? sizeof(dbbc::Reduce) : sizeof(dbbc::Item);
+    HIP_TRY(lists[j]->alloc(static_cast<size_t>(tot[j]) * esz));
+    uint32_t off = 0;
+    for (int32_t i = 0; i < k; ++i) {
+      const DevPlan& d = gs[i]->plan;
+      const DevBuf* src[5] = {&d.direct_items, &d.reverse_items, &d.small_groups, &d.hash_items, &d.reduces};
+      dbbc::AssembleSrc& a = srcs[static_cast<size_t>(j) * k + i];
+      a.src = src[j]->p;
+      a.n = static_cast<uint32_t>(d.host.n_items_kept[j]);
+      a.dst_off = off;
+      a.graph = static_cast<uint32_t>(i);
+      off += a.n;
+    }
+  }
+  HIP_TRY(upload(b->srcs, srcs, st));
+  const dbbc::AssembleSrc* dsrc = b->srcs.as<dbbc::AssembleSrc>();
+  for (int j = 0; j < 4; ++j)
+    if (tot[j]) HIP_TRY(dbbc::launch_assemble_items(dsrc + static_cast<size_t>(j) * k, k, lists[j]->as<dbbc::Item>(), st));
+  if (tot[4]) HIP_TRY(dbbc::launch_assemble_reduces(dsrc + static_cast<size_t>(4) * k, k, b->reduces.as<dbbc::Reduce>(), st));
+  std::vector<dbbc::DevSideConst> side(static_cast<size_t>(2) * k);
+  for (int32_t i = 0; i < k; ++i) {
+    side[2 * static_cast<size_t>(i)] = gs[i]->plan.side[0];
+    side[2 * static_cast<size_t>(i) + 1] = gs[i]->plan.side[1];
+  }
+  HIP_TRY(upload(b->sides, side, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  L.direct = b->direct.as<dbbc::Item>();
+  L.reverse = b->reverse.as<dbbc::Item>();
+  L.small = b->small.as<dbbc::Item>();
+  L.hash = b->hash.as<dbbc::Item>();
+  L.reduces = b->reduces.as<dbbc::Reduce>();
+  for (int j = 0; j < 5; ++j) L.n[j] = static_cast<int32_t>(tot[j]);
+  L.sides = b->sides.as<dbbc::DevSideConst>();
+  L.ctl = b->ctl.as<unsigned long long>();
+  L.res = b->res.as<unsigned long long>();
+  L.n_res = static_cast<size_t>(k) * dbbc::kResStride;
+  for (int32_t i = 0; i < k; ++i)
+    add_hub_launches(gs[i]->plan, L.res + static_cast<size_t>(i) * dbbc::kResStride, L);
+  L.long_len = long_len;
+  L.cus = b->dev.cus;
+  if (flags & DBBC_BATCH_CAPTURE) {
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    Timing tm{nullptr, 0, b->cap};
+    rc = enqueue(L, b->cap, tm);
+    const hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
+    if (rc != DBBC_OK) return rc;
+    HIP_TRY(e);
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  *out = b.release();
+  return DBBC_OK;
+}
+
+int dbbc_batch_launch(dbbc_batch* b, void* hip_stream) {
+  g_last_error.clear();
+  if (!b) return fail(DBBC_E_INVALID_ARG, "NULL batch");
+  const size_t k = b->gs.size();
+  if (k == 0) return DBBC_OK;
+  for (size_t i = 0; i < k; ++i)
+    if (!b->gs[i]->plan.valid || b->gs[i]->plan_gen != b->gens[i])
+      return fail(DBBC_E_INVALID_ARG, "a graph of the batch was planned again since the batch was made");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (b->exec) {
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+  } else {
+    Timing tm{nullptr, 0, st};
+    int rc = enqueue(b->L, st, tm);
     if (rc != DBBC_OK) return rc;
   }
+  HIP_TRY(hipMemcpyAsync(b->pinned, b->res.p, k * dbbc::kResStride * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(b->pinned + k * dbbc::kResStride, b->ctl.as<unsigned long long>() + kCtlErr,
+                         sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  return DBBC_OK;
+}
+
+int dbbc_batch_read(const dbbc_batch* b, dbbc_counts* out_host) {
+  g_last_error.clear();
+  if (!b || (!out_host && !b->gs.empty())) return fail(DBBC_E_INVALID_ARG, "NULL argument");
+  const size_t k = b->gs.size();
+  if (k == 0) return DBBC_OK;
+  if (b->pinned[k * dbbc::kResStride] != 0)
+    return fail(DBBC_E_DEVICE, "a kernel reported an internal overflow (error bits " +
+                                   std::to_string(b->pinned[k * dbbc::kResStride]) + ")");
+  for (size_t i = 0; i < k; ++i) read_counts(b->gs[i], b->pinned + i * dbbc::kResStride, &out_host[i]);
+  return DBBC_OK;
+}
+
+int dbbc_batch_count(dbbc_batch* b, dbbc_counts* out_host, void* hip_stream) {
+  int rc = dbbc_batch_launch(b, hip_stream);
+  if (rc != DBBC_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+  return dbbc_batch_read(b, out_host);
+}
+
+int32_t dbbc_batch_size(const dbbc_batch* b) { return b ? static_cast<int32_t>(b->gs.size()) : 0; }
+
+void dbbc_batch_destroy(dbbc_batch* b) { delete b; }
+
+int dbbc_count_batch(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt, dbbc_counts* out_host,
+                     void* hip_stream) {
+  g_last_error.clear();
+  if (k < 0 || (k > 0 && (!gs || !out_host))) return fail(DBBC_E_INVALID_ARG, "bad batch arguments");
+  dbbc_batch* b = nullptr;
+  int rc = dbbc_batch_create(gs, k, opt, 0u, hip_stream, &b);
+  if (rc != DBBC_OK) return rc;
+  rc = dbbc_batch_count(b, out_host, hip_stream);
+  dbbc_batch_destroy(b);
+  return rc;
+}
+
+int dbbc_autotune(dbbc_graph* const* gs, int32_t k, const dbbc_options* start, int32_t reps,
+                  void* hip_stream, dbbc_options* best, float* best_ms) {
+  g_last_error.clear();
+  if (k <= 0 || !gs || !best || reps <= 0) return fail(DBBC_E_INVALID_ARG, "bad autotune arguments");
+  if (start && (start->flags & DBBC_OPT_TIME_KERNELS))
+    return fail(DBBC_E_INVALID_ARG, "kernel timing cannot be tuned");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  dbbc_options cur;
+  if (start) {
+    cur = *start;
+  } else {
+    cur = dbbc_options{-1, -1, -1, -1, -1, -1, 0u};
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  struct Ev {
+    hipEvent_t* e;
+    ~Ev() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{ev};
+  // Time one option set: a captured batch, one warm-up replay, reps timed
+  // replays.  Options the plan rejects time as +inf.
+  auto time_opts = [&](const dbbc_options& o, float& ms) -> int {
+    ms = INFINITY;
+    dbbc_batch* b = nullptr;
+    int rc = dbbc_batch_create(gs, k, &o, DBBC_BATCH_CAPTURE, hip_stream, &b);
+    if (rc == DBBC_E_INVALID_ARG) return DBBC_OK;  // not a valid combination
+    if (rc != DBBC_OK) return rc;
+    std::unique_ptr<dbbc_batch, void (*)(dbbc_batch*)> guard(b, dbbc_batch_destroy);
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    HIP_TRY(hipEventRecord(ev[0], st));
+    for (int32_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(b->exec, st));
+    HIP_TRY(hipEventRecord(ev[1], st));
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    ms /= static_cast<float>(reps);
+    return DBBC_OK;
+  };
+  float cur_ms = 0.f;
+  int rc = time_opts(cur, cur_ms);
+  if (rc != DBBC_OK) return rc;
+  if (!std::isfinite(cur_ms)) return fail(DBBC_E_INVALID_ARG, "the starting options are not valid");
+  // Coordinate search: each knob in turn over its values, keeping the best.
+  struct Knob {
+    int32_t dbbc_options::*field;
+    std::vector<int32_t> values;
+  };
+  const Knob knobs[] = {
+      {&dbbc_options::long_len, {32, 64, 128, 256, 512}},
+      {&dbbc_options::small_work, {64, 256, 512}},
+      {&dbbc_options::window_L, {512, 2048, 8192, 32768}},
+      {&dbbc_options::hub_T, {0, 256, 1024, 4096}},
+      {&dbbc_options::part_work, {1 << 18, 1 << 20, 1 << 22}},
+  };
+  for (const Knob& kn : knobs) {
+    for (int32_t v : kn.values) {
+      if (cur.*kn.field == v) continue;
+      dbbc_options o = cur;
+      o.*kn.field = v;
+      if (kn.field == &dbbc_options::window_L) o.reverse_L = std::min(v, 4096);
+      float ms = 0.f;
+      rc = time_opts(o, ms);
+      if (rc != DBBC_OK) return rc;
+      if (ms < cur_ms) {
+        cur = o;
+        cur_ms = ms;
+      }
+    }
+  }
+  // leave the graphs planned with the winner
+  for (int32_t i = 0; i < k; ++i) {
+    dbbc::PlanParams p;
+    uint32_t long_len = 0;
+    rc = params_from(gs[i], &cur, p, long_len);
+    if (rc != DBBC_OK) return rc;
+    rc = ensure_plan(gs[i], p, st);
+    if (rc != DBBC_OK) return rc;
+  }
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
   return DBBC_OK;
 }
 
@@ -505,14 +887,14 @@ int dbbc_last_kernel_times(const dbbc_graph* g, dbbc_kernel_time* out, int32_t c
   const int32_t n = static_cast<int32_t>(g->timers_used);
   for (int32_t i = 0; i < n && i < cap; ++i) {
     const KernelRec& t = g->timers[i];
-    dbbc_kernel_time k{};
-    std::strncpy(k.name, t.name.c_str(), sizeof(k.name) - 1);
-    k.ms = t.ms;
-    k.wedges = t.wedges;
-    k.segments = t.segments;
-    k.items = t.items;
-    k.macs = t.macs;
-    out[i] = k;
+    dbbc_kernel_time kt{};
+    std::strncpy(kt.name, t.name.c_str(), sizeof(kt.name) - 1);
+    kt.ms = t.ms;
+    kt.wedges = t.wedges;
+    kt.segments = t.segments;
+    kt.items = t.items;
+    kt.macs = t.macs;
+    out[i] = kt;
   }
   *n_out = n;
   return DBBC_OK;

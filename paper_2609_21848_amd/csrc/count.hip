@@ -100,40 +100,56 @@ __device__ __forceinline__ uint32_t bpermute(uint32_t v, uint32_t src) {
 // total) is entry base + t of its run's row, with base = start - excl of
 // the run.  A staging round covers positions [done, done + kGather), dealt
 // to lanes as t = done + 64 u + lane (coalesced loads).  Every run that
-// starts in the round, or continues into it, writes lane + 1 at its first
-// position of the round into the wavefront's marks buffer; a position's run
-// is then the last mark at or before it: a ballot per block of 64 positions,
-// carried across blocks.  Each lane clears the marks it read, so the buffer
-// is all zeros between rounds.
+// starts in the round, or continues into it, writes its base and its tag
+// (with bit 31 set as a presence flag) at its first position of the round
+// into the wavefront's marks buffers; a position's run is then the last
+// mark at or before it: a ballot per block of 64 positions, carried across
+// blocks.  Each lane clears the presence words it read, so they are all
+// zero between rounds.
 constexpr int kStageU = kGather / kWave;
+
+// TagT holds a run's tag plus the presence bit (its top bit): 8 bits for
+// plain runs (tag = g), 32 bits for small-item groups.
+template <class TagT>
+struct Marks {
+  uint32_t* base;  // kGather words
+  TagT* tag;       // kGather entries, zero when no run starts there
+  static constexpr uint32_t kBit = 1u << (8 * sizeof(TagT) - 1);
+};
 
 struct Staged {
   uint32_t e[kStageU], tag[kStageU];
   bool valid[kStageU];
 };
 
-__device__ __forceinline__ void stage_round(Staged& s, uint32_t* marks, uint32_t excl, uint32_t slen,
+template <class M>
+__device__ __forceinline__ void stage_round(Staged& s, M mk, uint32_t excl, uint32_t slen,
                                             uint32_t base, uint32_t tag, uint32_t total, uint32_t done,
                                             const uint32_t* __restrict__ adj) {
   const int lane = lane_id();
   wave_sync_lds();
-  if (slen != 0 && excl < done + kGather && excl + slen > done)
-    marks[excl > done ? excl - done : 0u] = static_cast<uint32_t>(lane) + 1u;
+  if (slen != 0 && excl < done + kGather && excl + slen > done) {
+    const uint32_t pos = excl > done ? excl - done : 0u;
+    mk.base[pos] = base;
+    mk.tag[pos] = static_cast<decltype(+mk.tag[0])>(tag | M::kBit);
+  }
   wave_sync_lds();
   const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane
-  uint32_t carry = 0;
+  uint32_t cb = 0, ct = 0;
 #pragma unroll
   for (int u = 0; u < kStageU; ++u) {
-    const uint32_t m = marks[u * kWave + lane];
-    marks[u * kWave + lane] = 0;
-    const uint64_t below = __ballot(m != 0) & upto;
-    const uint32_t mv = bpermute(m, below ? 63u - static_cast<uint32_t>(__clzll(below)) : 0u);
-    const uint32_t own = below ? mv : carry;  // lane + 1 of the position's run
-    carry = readlane(own, kWave - 1);
-    // positions past the end may have no run (own = 0): masked below
-    const uint32_t j = own - 1u;
-    const uint32_t b = bpermute(base, j);
-    s.tag[u] = bpermute(tag, j);
+    const uint32_t mt = static_cast<uint32_t>(mk.tag[u * kWave + lane]);
+    const uint32_t mb = mk.base[u * kWave + lane];
+    mk.tag[u * kWave + lane] = 0;
+    const uint64_t below = __ballot(mt != 0) & upto;
+    const uint32_t src = below ? 63u - static_cast<uint32_t>(__clzll(below)) : 0u;
+    const uint32_t pb = bpermute(mb, src), pt = bpermute(mt, src);
+    // positions past the end may have no run: masked below
+    const uint32_t b = below ? pb : cb;
+    const uint32_t tg = below ? pt : ct;
+    cb = readlane(b, kWave - 1);
+    ct = readlane(tg, kWave - 1);
+    s.tag[u] = tg & ~M::kBit;
     const uint32_t t = done + static_cast<uint32_t>(u * kWave + lane);
     s.valid[u] = t < total;
     s.e[u] = adj[s.valid[u] ? b + t : 0u];
@@ -149,8 +165,8 @@ __device__ __forceinline__ void stage_round(Staged& s, uint32_t* marks, uint32_t
 //  - Shorter runs are staged (stage_round) so that every lane holds wedges;
 //    the loads of the first round are issued before the long stream and the
 //    next round's loads before the current round is tallied.
-template <int U, class F>
-__device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, uint32_t* marks,
+template <int U, class M, class F>
+__device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, M marks,
                                           uint32_t long_len, F&& f) {
   const int lane = lane_id();
   const uint32_t start = sr.start, tag = sr.tag, len = sr.len;
@@ -213,18 +229,18 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
   }
 }
 
-template <int U, bool kTagged = false, class F>
+template <int U, bool kTagged = false, class M, class F>
 __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
-                                           const uint32_t* __restrict__ adj, uint32_t* marks,
+                                           const uint32_t* __restrict__ adj, M marks,
                                            uint32_t long_len, F&& f) {
   walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
 }
 
 // Walk every run of an item with one wavefront; the first batch of 64 runs
 // was loaded beforehand (first).
-template <int U, bool kTagged = false, class F>
+template <int U, bool kTagged = false, class M, class F>
 __device__ __forceinline__ void walk_item(const Item& it, SegReg first, const Segment* __restrict__ segs,
-                                          const uint32_t* __restrict__ adj, uint32_t* marks,
+                                          const uint32_t* __restrict__ adj, M marks,
                                           uint32_t long_len, F&& f) {
   const uint32_t seg_end = it.seg_begin + it.seg_count;
   walk_regs<U>(first, adj, marks, long_len, f);
@@ -288,13 +304,19 @@ struct Sums {
   }
 };
 
+// The sums of a wavefront (or workgroup) belong to one graph at a time:
+// items of a graph are contiguous in every list, and the running sums are
+// flushed to the graph's result slot when an item of another graph comes.
+constexpr uint32_t kNoGraph = 0xffffffffu;
+
 __device__ __forceinline__ int64_t wave_sum64(int64_t x) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
   return x;
 }
 
-// Add the wavefront's sums to res[0..2] (one atomic per wavefront).
+// Add the wavefront's sums to a graph's results (one atomic per wavefront
+// and value).
 __device__ __forceinline__ void flush_sums(const Sums& s, unsigned long long* res) {
   const int64_t b = wave_sum64(s.bal), u = wave_sum64(s.unb), t = wave_sum64(s.tot);
   if (lane_id() == 0) {
@@ -324,30 +346,37 @@ constexpr int kDirectKeys = 32768;
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t cnt[kDirectKeys];
-  __shared__ uint32_t marks[kDirectWaves][kGather];
+  __shared__ uint32_t mbase[kDirectWaves][kGather];
+  __shared__ uint8_t mtag[kDirectWaves][kGather];
   __shared__ int32_t item_sh;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
-  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&marks[0][0])[i] = 0;
+  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&mtag[0][0])[i] = 0;
   Sums sums;
+  uint32_t graph = kNoGraph;
   for (;;) {
     if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
     __syncthreads();
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
     const Item it = a.items[i];
-    const DevSideConst sc = a.side[it.side];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
     const uint32_t* __restrict__ adj = sc.other_adj;
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<4>(a.segs, k0, k1, adj, marks[wave], a.long_len, DirectTally{cnt});
+      walk_batch<4>(sc.segs, k0, k1, adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len, DirectTally{cnt});
     }
     __syncthreads();
     if (it.flags & kItemMultiPart) {
       // write the part's counters for the whole key window (zeros included)
-      uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
+      uint32_t* __restrict__ dst = sc.acc + static_cast<size_t>(it.acc_slot) * sc.acc_width;
       for (uint32_t key = it.key_lo + tid; key < static_cast<uint32_t>(it.key_hi); key += kDirectThreads) {
         dst[key] = cnt[key];
         cnt[key] = 0;
@@ -367,7 +396,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     }
     __syncthreads();
   }
-  flush_sums(sums, a.res);
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,12 +453,13 @@ struct SqTotals {
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kReverseWaves][kReverseWords];
-  __shared__ uint32_t marks[kReverseWaves][kGather];
+  __shared__ uint32_t mbase[kReverseWaves][kGather];
+  __shared__ uint8_t mtag[kReverseWaves][kGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
   for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) marks[wave][i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
   wave_sync_lds();
   SqTotals tot;
   const int32_t n = a.n_items;
@@ -439,23 +469,30 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   SegReg cfirst{0, 0, 0};
   if (i < n) {
     cur = a.items[i];
-    cfirst = first_batch(cur, a.segs);
+    cfirst = first_batch(cur, a.sides[2 * cur.graph + cur.side].segs);
   }
   if (i + stride < n) nxt = a.items[i + stride];
+  uint32_t graph = kNoGraph;
   for (; i < n; i += stride) {
     const Item it = cur;
     const SegReg first = cfirst;
     const int32_t j = i + stride, j2 = j + stride;
+    if (it.graph != graph) {
+      if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+      tot = SqTotals{};
+      graph = it.graph;
+    }
     SegReg nfirst{0, 0, 0};
-    if (j < n) nfirst = first_batch(nxt, a.segs);
+    if (j < n) nfirst = first_batch(nxt, a.sides[2 * nxt.graph + nxt.side].segs);
     Item nxt2{};
     if (j2 < n) nxt2 = a.items[j2];
-    const DevSideConst sc = a.side[it.side];
-    walk_item<8>(it, first, a.segs, sc.other_adj, marks[wave], a.long_len, PairTally{C});
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    walk_item<8>(it, first, sc.segs, sc.other_adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len,
+                 PairTally{C});
     wave_sync_lds();
     const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the item's keys
     if (it.flags & kItemMultiPart) {
-      uint32_t* __restrict__ dst = a.acc + static_cast<size_t>(it.acc_slot) * a.acc_width;
+      uint32_t* __restrict__ dst = sc.acc + static_cast<size_t>(it.acc_slot) * sc.acc_width;
       for (int32_t wd = lane; wd < w_hi; wd += kWave) {
         const uint32_t c2 = C[wd];
         C[wd] = 0;
@@ -481,7 +518,7 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     cfirst = nfirst;
     nxt = nxt2;
   }
-  tot.flush(a.res);
+  if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,7 +543,7 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   __shared__ uint32_t keys[kSmallWaves][kSmallSlots];
   __shared__ uint32_t vals[kSmallWaves][kSmallSlots];
-  __shared__ uint32_t marks[kSmallWaves][kGather];
+  __shared__ uint32_t marks[kSmallWaves][2][kGather];
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   uint32_t* K = keys[wave];
@@ -515,7 +552,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     K[i] = kEmpty;
     Vv[i] = 0;
   }
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) marks[wave][i] = 0;
+  for (int i = lane; i < 2 * static_cast<int>(kGather); i += kWave) (&marks[wave][0][0])[i] = 0;
   wave_sync_lds();
   SqTotals tot;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kSmallWaves;
@@ -524,27 +561,34 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   SegReg nfirst{0, 0, 0};
   if (i < a.n_items) {
     nxt = a.items[i];
-    nfirst = first_batch<true>(nxt, a.segs);
+    nfirst = first_batch<true>(nxt, a.sides[2 * nxt.graph + nxt.side].small_segs);
   }
+  uint32_t graph = kNoGraph;
   for (; i < a.n_items; i += stride) {
     const Item it = nxt;
     const SegReg first = nfirst;
     const int32_t j = i + stride;
     if (j < a.n_items) nxt = a.items[j];
-    const DevSideConst sc = a.side[it.side];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+      tot = SqTotals{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
     const uint32_t kb = static_cast<uint32_t>(sc.key_bits);
     // table size: a power of two >= 2 * work, at least 64
     uint32_t size = 64;
     while (size < 2 * it.work) size <<= 1;
     const uint32_t mask = size - 1;
-    walk_item<4, true>(it, first, a.segs, sc.other_adj, marks[wave], a.long_len,
+    walk_item<4, true>(it, first, sc.small_segs, sc.other_adj, Marks<uint32_t>{marks[wave][0], marks[wave][1]},
+                       a.long_len,
                        hash_tally([&](uint32_t e, uint32_t tag) {
                          const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
                          const uint32_t inc = wedge_inc(e, tag);
                          uint32_t h = mix32(key) & mask;
                          for (uint32_t probe = 0;; ++probe) {
                            if (probe > mask) {  // full table: cannot happen at load <= 1/2
-                             atomicOr(a.res + kResError, kErrHashFull);
+                             atomicOr(a.err, kErrHashFull);
                              break;
                            }
                            uint32_t c = K[h];
@@ -559,7 +603,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
                            h = (h + 1) & mask;
                          }
                        }));
-    if (j < a.n_items) nfirst = first_batch<true>(nxt, a.segs);
+    if (j < a.n_items) nfirst = first_batch<true>(nxt, a.sides[2 * nxt.graph + nxt.side].small_segs);
     wave_sync_lds();
     // p, n <= kSmallGroupWork per key and sum p + n <= kSmallGroupWork
     // per group, so the group's sums of squares stay below 2^19
@@ -583,7 +627,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     tot.add(ss);
     wave_sync_lds();
   }
-  tot.flush(a.res);
+  if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
 }
 
 // ---------------------------------------------------------------------------
@@ -597,7 +641,8 @@ constexpr int kHashSlots = 8192;
 __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
   __shared__ uint32_t keys[kHashSlots];
   __shared__ unsigned long long vals[kHashSlots];
-  __shared__ uint32_t marks[kHashWaves][kGather];
+  __shared__ uint32_t mbase[kHashWaves][kGather];
+  __shared__ uint8_t mtag[kHashWaves][kGather];
   __shared__ int32_t item_sh;
   __shared__ uint32_t work_sh;
   const int tid = threadIdx.x;
@@ -606,8 +651,9 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     keys[i] = kEmpty;
     vals[i] = 0;
   }
-  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&marks[0][0])[i] = 0;
+  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&mtag[0][0])[i] = 0;
   Sums sums;
+  uint32_t graph = kNoGraph;
   for (;;) {
     if (tid == 0) {
       item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
@@ -617,10 +663,15 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
     const Item it = a.items[i];
-    const DevSideConst sc = a.side[it.side];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     uint32_t w = 0;
-    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kHashThreads) w += a.segs[k].len_g >> 1;
+    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kHashThreads) w += sc.segs[k].len_g >> 1;
     atomicAdd(&work_sh, w);
     __syncthreads();
     const uint32_t work = work_sh;
@@ -629,7 +680,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     for (uint32_t pass = 0; pass < passes; ++pass) {
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        walk_batch<4>(a.segs, k0, k1, sc.other_adj, marks[wave], a.long_len, hash_tally([&](uint32_t e, uint32_t g) {
+        walk_batch<4>(sc.segs, k0, k1, sc.other_adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len, hash_tally([&](uint32_t e, uint32_t g) {
           const uint32_t key = e >> 1;
           const uint32_t hk = mix32(key);
           if (passes > 1 && (hk >> 16) % passes != pass) return;
@@ -637,7 +688,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
           uint32_t h = hk & (kHashSlots - 1);
           for (uint32_t probe = 0;; ++probe) {
             if (probe >= static_cast<uint32_t>(kHashSlots)) {  // full table
-              atomicOr(a.res + kResError, kErrHashFull);
+              atomicOr(a.err, kErrHashFull);
               break;
             }
             uint32_t cur = keys[h];
@@ -666,7 +717,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
       __syncthreads();
     }
   }
-  flush_sums(sums, a.res);
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,23 +727,41 @@ constexpr int kReduceThreads = 256;
 
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
   Sums sums;
+  uint32_t graph = kNoGraph;
   for (int32_t r = blockIdx.x; r < a.n_reduces; r += gridDim.x) {
     const Reduce rd = a.reduces[r];
-    const DevSideConst sc = a.side[rd.side];
+    if (rd.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = rd.graph;
+    }
+    const DevSideConst sc = a.sides[2 * rd.graph + rd.side];
     Item it{};
     it.owner = rd.owner;
     it.flags = rd.flags;
     for (int32_t key = rd.key_lo + threadIdx.x; key < rd.key_hi; key += kReduceThreads) {
       uint32_t p = 0, n = 0;
       for (int32_t j = 0; j < rd.n_parts; ++j) {
-        const uint32_t c = a.acc[static_cast<size_t>(rd.acc_slot + j) * a.acc_width + key];
+        const uint32_t c = sc.acc[static_cast<size_t>(rd.acc_slot + j) * sc.acc_width + key];
         p += c & 0xffffu;
         n += c >> 16;
       }
       if (p | n) emit(it, static_cast<uint32_t>(key), p, n, sc, sums);
     }
   }
-  flush_sums(sums, a.res);
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+}
+
+// Batch assembly: block b copies graph b's list, setting the graph index.
+template <class T>
+__global__ void k_assemble(const AssembleSrc* __restrict__ srcs, T* __restrict__ dst) {
+  const AssembleSrc s = srcs[blockIdx.x];
+  const T* __restrict__ src = static_cast<const T*>(s.src);
+  for (uint32_t i = threadIdx.x; i < s.n; i += blockDim.x) {
+    T v = src[i];
+    v.graph = s.graph;
+    dst[s.dst_off + i] = v;
+  }
 }
 
 __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
@@ -710,6 +779,18 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(dev::k_fill_u64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_items(const AssembleSrc* srcs, int k, Item* dst, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_assemble<Item>, dim3(k), dim3(256), 0, st, srcs, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_reduces(const AssembleSrc* srcs, int k, Reduce* dst, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_assemble<Reduce>, dim3(k), dim3(256), 0, st, srcs, dst);
   return hipGetLastError();
 }
 

@@ -85,6 +85,7 @@ struct Item {
   uint32_t flags;
   uint32_t side;      // side of the owner and of the keys (0 = U, 1 = V)
   uint32_t work;      // wedges of the item (saturated at 2^32 - 1)
+  uint32_t graph;     // index of the item's graph in a batch (0 alone)
 };
 
 struct Reduce {       // one multi-part accumulator to reduce after its parts
@@ -94,6 +95,7 @@ struct Reduce {       // one multi-part accumulator to reduce after its parts
   int32_t key_lo, key_hi;
   uint32_t flags;
   uint32_t side;
+  uint32_t graph;
 };
 
 struct PlanParams {
@@ -126,6 +128,9 @@ struct HostPlan {
   std::vector<Item> hash_items;    // workgroup hash counters, large tail pivots
   std::vector<Item> reverse_items; // per-wavefront direct arrays over [0, R)
   std::vector<Reduce> reduces;
+  // list lengths (direct, reverse, small groups, hash, reduces) once the
+  // lists live on the device only
+  int32_t n_items_kept[5] = {0, 0, 0, 0, 0};
   int32_t acc_slots = 0;
   int32_t acc_width = 0;           // max window over the sides
   // per sparse kernel (0 = direct, 1 = small, 2 = hash, 3 = reverse):

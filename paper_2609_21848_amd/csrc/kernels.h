@@ -14,70 +14,77 @@ namespace dbbc {
 // the last entry of a run.
 constexpr size_t kAdjPad = 64;
 
-// Layout of the int64 result block shared by all kernels of a count.
+// Layout of a graph's int64 result slot (res + graph * kResStride).
 enum : int {
   kResBalanced = 0,
   kResUnbalanced = 1,
   kResTotal = 2,
   kResDenseWedges = 3,
-  kResError = 4,  // bit set of kErr* raised by a kernel
+  kResStride = 4,
 };
 enum : unsigned long long {
   kErrHashFull = 1ull,
 };
 
-// Per side s (the side of an item's keys): where the item's segments point
-// and where hub-pair partial counts go.
+// Per graph and side s (the side of an item's keys): where the item's
+// segments point and where hub-pair partial counts go.  Kernels read them
+// from a table indexed 2 * item.graph + item.side.
 struct DevSideConst {
   const uint32_t* other_adj;     // CSR entries of the other side (entries are side-s ranks)
+  const Segment* segs;           // the graph's runs (direct, reverse and hash items)
+  const Segment* small_segs;     // the graph's tagged runs (small-item groups)
   unsigned long long* hub_pairs; // [T x T] packed (asym << 32) | sym, or null
+  uint32_t* acc;                 // the graph's multi-part accumulators
   int32_t T;                     // hub rows of side s (0 = no dense path)
   int32_t R;                     // reverse window of side s
   int32_t key_bits;              // bits of a side-s rank in a small-group hash key
+  int32_t acc_width;             // words per accumulator slot
 };
 
 struct DirectArgs {
   const Item* items;
-  const Segment* segs;
-  DevSideConst side[2];
+  const DevSideConst* sides;
   uint32_t* queue;
-  uint32_t* acc;
-  unsigned long long* res;
+  unsigned long long* res;   // per-graph result slots
+  unsigned long long* err;   // kErr* bits
   int32_t n_items;
-  int32_t acc_width;
   uint32_t long_len;  // runs at least this long are streamed by the whole wavefront
 };
 
 // Reverse items (items) or small-item groups (items = groups, segs tagged).
 struct SmallArgs {
   const Item* items;
-  const Segment* segs;
-  DevSideConst side[2];
-  uint32_t* queue;
-  uint32_t* acc;  // part buffers (reverse items split into parts)
-  unsigned long long* res;
+  const DevSideConst* sides;
+  unsigned long long* res;   // per-graph result slots
+  unsigned long long* err;   // kErr* bits
   int32_t n_items;
-  int32_t acc_width;
   uint32_t long_len;
 };
 
 struct HashArgs {
   const Item* items;
-  const Segment* segs;
-  DevSideConst side[2];
+  const DevSideConst* sides;
   uint32_t* queue;
-  unsigned long long* res;
+  unsigned long long* res;   // per-graph result slots
+  unsigned long long* err;   // kErr* bits
   int32_t n_items;
   uint32_t long_len;
 };
 
 struct ReduceArgs {
   const Reduce* reduces;
-  DevSideConst side[2];
-  const uint32_t* acc;
-  unsigned long long* res;
+  const DevSideConst* sides;
+  unsigned long long* res;   // per-graph result slots
+  unsigned long long* err;   // kErr* bits
   int32_t n_reduces;
-  int32_t acc_width;
+};
+
+// Source of one graph's item (or reduce) list for the batch assembly copy.
+struct AssembleSrc {
+  const void* src;
+  uint32_t n;
+  uint32_t dst_off;  // first destination index
+  uint32_t graph;    // index of the graph in the batch
 };
 
 // Dense hub block of one side: X = |Bm| |B|^T and Y = Bm B^T over the T_other
@@ -98,5 +105,9 @@ hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_hub(const HubArgs& a, hipStream_t st);
+// Copy k graphs' item lists (or reduce lists) into one list, setting each
+// entry's graph field.
+hipError_t launch_assemble_items(const AssembleSrc* srcs, int k, Item* dst, hipStream_t st);
+hipError_t launch_assemble_reduces(const AssembleSrc* srcs, int k, Reduce* dst, hipStream_t st);
 
 }  // namespace dbbc

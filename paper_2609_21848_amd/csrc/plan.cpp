@@ -26,12 +26,34 @@
 
 namespace dbbc {
 
+// Density of the top T x T block of the bi-adjacency matrix (rows and
+// columns in priority order).
+double hub_density(const HostGraph& g, int32_t T) {
+  const HostSide& S = g.side[0];
+  int64_t nnz = 0;
+  for (int32_t x = 0; x < T; ++x) {
+    const uint32_t* b = S.adj.data() + S.off[x];
+    const uint32_t* e = S.adj.data() + S.off[x + 1];
+    nnz += std::lower_bound(b, e, static_cast<uint32_t>(T) << 1) - b;
+  }
+  return static_cast<double>(nnz) / (static_cast<double>(T) * T);
+}
+
 PlanParams default_params(const HostGraph& g) {
   PlanParams p;
   p.window_L = 32768;
   p.reverse_L = 4096;
+  // The dense path costs T^3 MACs whatever the block holds, and saves the
+  // sparse wedges inside it: take the largest T whose block is at least
+  // 15% full (both sides need 2T vertices).
   p.hub_T = 0;
-  (void)g;
+  for (int32_t T : {4096, 2048, 1024}) {
+    if (g.side[0].n < 2 * T || g.side[1].n < 2 * T) continue;
+    if (hub_density(g, T) >= 0.15) {
+      p.hub_T = T;
+      break;
+    }
+  }
   p.small_work = static_cast<int32_t>(kSmallGroupWork);
   p.part_work = 1 << 20;
   return p;

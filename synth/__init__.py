@@ -11,6 +11,7 @@ from .graphs import (  # noqa: F401
     chung_lu_graph,
     config_graph,
     batch_graph,
+    batch_graphs,
     pool_graph,
     upload_graph,
     CONFIGS,

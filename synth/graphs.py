@@ -153,7 +153,10 @@ def batch_graph(i: int, n_graphs: int = 4096, seed: int = 0) -> SignedGraph:
     ``SeedSequence(seed).spawn(4096)``; |U|, |V| uniform in [50, 5000], m
     uniform in [200, 50000] clipped to floor(|U||V| / 2), Chung-Lu exponent
     2.2 on both sides, negative probability uniform in [0.1, 0.5]."""
-    ss = np.random.SeedSequence(seed).spawn(n_graphs)[i]
+    return _batch_like(np.random.SeedSequence(seed).spawn(n_graphs)[i], f"batch{i}")
+
+
+def _batch_like(ss, name: str) -> SignedGraph:
     rng = np.random.Generator(np.random.PCG64(ss))
     n_u = int(rng.integers(50, 5001))
     n_v = int(rng.integers(50, 5001))
@@ -161,12 +164,15 @@ def batch_graph(i: int, n_graphs: int = 4096, seed: int = 0) -> SignedGraph:
     m = min(m, (n_u * n_v) // 2)
     q = float(rng.uniform(0.1, 0.5))
     sub = int(rng.integers(0, 2**63 - 1))
-    return chung_lu_graph(n_u, n_v, m, 2.2, 2.2, q, seed=sub, name=f"batch{i}")
+    return chung_lu_graph(n_u, n_v, m, 2.2, 2.2, q, seed=sub, name=name)
 
 
 def batch_graphs(n_graphs: int = 4096, seed: int = 0, first: int = 0, count=None):
+    """Graphs first .. first + count - 1 of the batched workload (the same
+    graphs as batch_graph, with the seed sequence spawned once)."""
     count = n_graphs - first if count is None else count
-    return [batch_graph(i, n_graphs, seed) for i in range(first, first + count)]
+    kids = np.random.SeedSequence(seed).spawn(n_graphs)
+    return [_batch_like(kids[i], f"batch{i}") for i in range(first, first + count)]
 
 
 def pool_graph(i: int, n_pool: int = 1000, seed: int = 0) -> SignedGraph:

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version_and_status_strings():
-    assert dbbc.dbbc_version() == "0.1.0"
+    assert dbbc.dbbc_version() == "0.2.0"
     lib = dbbc.load()
     for code, word in [(0, "ok"), (-2, "range"), (-3, "sign"), (-4, "duplicate"), (-8, "gfx950")]:
         assert word in lib.dbbc_status_string(code).decode()
@@ -63,7 +63,19 @@ def test_validation_errors_need_no_device():
                                  ctypes.byref(ctypes.c_void_p())) == dbbc.DBBC_E_INVALID_ARG
     # NULL handles are rejected or ignored
     assert lib.dbbc_count(None, None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_count_async(None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_count_read(None, None) == dbbc.DBBC_E_INVALID_ARG
     lib.dbbc_graph_destroy(None)
+    # batches: bad arguments are rejected before any device work
+    out = ctypes.c_void_p()
+    assert lib.dbbc_batch_create(None, 1, None, 0, None, ctypes.byref(out)) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_batch_create(None, -1, None, 0, None, ctypes.byref(out)) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_batch_create(None, 0, None, 0x80, None, ctypes.byref(out)) == dbbc.DBBC_E_INVALID_ARG
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.dbbc_batch_create(arr, 1, None, 0, None, ctypes.byref(out)) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_batch_launch(None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_batch_size(None) == 0
+    lib.dbbc_batch_destroy(None)
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
