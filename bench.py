@@ -175,6 +175,145 @@ def bench_batched(dbbc, steps: int, warmup: int, n_graphs: int, oracle_sample: i
     }
 
 
+def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: float,
+                 n_uploads: int, seed: int = 0):
+    """Served workload: a resident pool of n_pool graphs (sizes log-uniform in
+    [1e3, 5e6] edges), Poisson arrivals at `rate` requests/s for `seconds`,
+    each a count of a pool graph picked uniformly, or with probability
+    upload_frac an upload of a new graph (n_uploads distinct upload graphs,
+    each upload built anew).  Latency is arrival (submit) to result.  Then a
+    saturation run (all requests submitted at once) against one launch
+    sequence per graph on the same request mix."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    from synth import pool_graphs, upload_graph
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(16) as ex:
+        gs = list(ex.map(lambda i: pool_graphs(n_pool, seed, idx=[i])[0], range(n_pool)))
+        ups = list(ex.map(upload_graph, range(n_uploads)))
+    log(f"[serve] generated pool of {n_pool} ({sum(g.m for g in gs)} edges) and {n_uploads} "
+        f"uploads in {time.perf_counter() - t:.1f}s")
+    srv = dbbc.Server()
+    t = time.perf_counter()
+    with ThreadPoolExecutor(16) as ex:
+        ids = list(ex.map(lambda g: srv.add_graph(g.n_u, g.n_v, g.u, g.v, g.sign), gs))
+    st0 = srv.stats()
+    log(f"[serve] resident pool built in {time.perf_counter() - t:.1f}s: "
+        f"{st0['resident_bytes'] / 2**30:.2f} GiB")
+
+    rng = np.random.default_rng(seed)
+    n_req = int(rate * seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    is_up = rng.random(n_req) < upload_frac
+    picks = rng.integers(0, n_pool, n_req)
+    # warm-up: every pool graph once
+    for t_ in [srv.submit(i) for i in ids]:
+        srv.wait(t_)
+    tickets = []
+    t0 = time.perf_counter()
+    u_next = 0
+    for k in range(n_req):
+        target = t0 + arrivals[k]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            time.sleep(min(target - now, 5e-4))
+        if is_up[k]:
+            g = ups[u_next % n_uploads]
+            u_next += 1
+            tickets.append((-1, srv.submit_upload(g.n_u, g.n_v, g.u, g.v, g.sign)))
+        else:
+            tickets.append((int(picks[k]), srv.submit(ids[picks[k]])))
+        if k and k % int(rate * 5) == 0:
+            log(f"[serve] {k} requests submitted")
+    t_sub = time.perf_counter() - t0
+    lat, sizes, first = [], [], {}
+    t_first = t_last = None
+    consistent = True
+    bad = 0
+    for gi, tk in tickets:
+        status, c, info = srv.wait(tk)
+        if status != dbbc.DBBC_OK:
+            bad += 1
+            continue
+        lat.append((info["t_done_ns"] - info["t_submit_ns"]) / 1e6)
+        sizes.append(info["batch_size"])
+        t_first = info["t_submit_ns"] if t_first is None else min(t_first, info["t_submit_ns"])
+        t_last = info["t_done_ns"] if t_last is None else max(t_last, info["t_done_ns"])
+        if gi >= 0:
+            if first.setdefault(gi, tuple(c)) != tuple(c):
+                consistent = False
+    st = srv.stats()
+    lat = np.array(lat)
+    span = (t_last - t_first) / 1e9
+    res = {
+        "workload": f"pool of {n_pool} Chung-Lu graphs (m log-uniform in [1e3, 5e6], "
+                    f"|U|=m/10, |V|=m/20, exponent 2.2, sign -1 w.p. 0.3), Poisson arrivals "
+                    f"at {rate:g} req/s for {seconds:g} s, {upload_frac:.0%} uploads of new graphs",
+        "requests": n_req,
+        "completed": int(len(lat)),
+        "not_ok": bad,
+        "offered_rate": n_req / t_sub,
+        "graphs_per_s": len(lat) / span,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                       "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean()),
+                       "max": float(lat.max())},
+        "mean_batch": float(np.mean(sizes)),
+        "launches": st["launches"] - st0["launches"],
+        "max_queue": st["max_queue"],
+        "rejected": st["rejected"],
+        "evicted": st["evicted"],
+        "uploads": st["uploads"],
+        "resident_gib": st["resident_bytes"] / 2**30,
+        "same_graph_same_result": consistent,
+    }
+    log(f"[serve] {len(lat)} done, {res['graphs_per_s']:.0f} graphs/s, p50 "
+        f"{res['latency_ms']['p50']:.2f} ms, p99 {res['latency_ms']['p99']:.2f} ms, "
+        f"mean batch {res['mean_batch']:.1f}")
+
+    # saturation: 2000 requests on 200 pool graphs (drawn uniformly) submitted
+    # at once, against one launch sequence per request (dbbc_count on handles
+    # of their own, one graph at a time)
+    n_sat = 2000
+    subset = rng.choice(n_pool, size=min(200, n_pool), replace=False)
+    sat = subset[rng.integers(0, len(subset), n_sat)]
+    t = time.perf_counter()
+    sat_t = [srv.submit(ids[i]) for i in sat]
+    got = [srv.wait(tk) for tk in sat_t]
+    dt_srv = time.perf_counter() - t
+    assert all(x[0] == dbbc.DBBC_OK for x in got)
+    srv.close()
+    uniq = sorted(set(int(i) for i in sat))
+    hs = {}
+    with ThreadPoolExecutor(16) as ex:
+        for i, h in zip(uniq, ex.map(lambda i: dbbc.Graph(gs[i].n_u, gs[i].n_v, gs[i].u, gs[i].v,
+                                                          gs[i].sign), uniq)):
+            hs[i] = h
+    for i in uniq:
+        hs[i].count()  # plans
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [hs[int(i)].count() for i in sat]
+    dt_plain = time.perf_counter() - t
+    same = all(tuple(p) == tuple(g[1]) for p, g in zip(plain, got))
+    for h in hs.values():
+        h.close()
+    res["saturated"] = {
+        "requests": n_sat,
+        "graphs_per_s_served": n_sat / dt_srv,
+        "graphs_per_s_plain": n_sat / dt_plain,
+        "speedup_vs_plain": dt_plain / dt_srv,
+        "served_equals_alone": same,
+    }
+    log(f"[serve] saturated: served {n_sat / dt_srv:.0f} graphs/s, plain {n_sat / dt_plain:.0f} "
+        f"graphs/s, equal={same}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +331,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
+    ap.add_argument("--serve-pool", type=int, default=1000)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -326,6 +469,9 @@ def main():
     h.close()
     if not args.no_batch:
         out["batched"] = bench_batched(dbbc, args.steps, args.warmup, args.batch_graphs, 64)
+    if not args.no_serve:
+        out["served"] = bench_served(dbbc, args.serve_seconds, args.serve_pool, args.serve_rate,
+                                     0.01, 64)
     if not args.no_cpu:
         log("[bench] cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_fraction, None)

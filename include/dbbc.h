@@ -147,6 +147,11 @@ int dbbc_count(dbbc_graph *g, const dbbc_options *opt, dbbc_counts *out_host, vo
 int dbbc_count_per_vertex(dbbc_graph *g, int64_t *bal_u, int64_t *bal_v, int64_t *unb_u,
                           int64_t *unb_v, dbbc_counts *out_host, void *hip_stream);
 
+/* Build the handle's counting plan for opt now (NULL = defaults), so that
+ * the next count with the same options starts at once; returns when the plan
+ * is on the device.  Counts re-plan by themselves when the options change. */
+int dbbc_graph_plan(dbbc_graph *g, const dbbc_options *opt, void *hip_stream);
+
 /* Asynchronous count: enqueue the same work as dbbc_count on hip_stream,
  * with the results copied to host memory owned by the handle, and return
  * without waiting.  Once the stream has passed this point (an event or a
@@ -178,6 +183,13 @@ typedef struct dbbc_batch dbbc_batch;
  * set-up copies; the call returns once they are done. */
 int dbbc_batch_create(dbbc_graph *const *gs, int32_t k, const dbbc_options *opt, uint32_t flags,
                       void *hip_stream, dbbc_batch **out);
+
+/* Re-target batch b at the graphs gs[0..k) (same rules as
+ * dbbc_batch_create), reusing b's device and pinned buffers when they are
+ * large enough: for request loops that form a new batch for every launch.
+ * The previous launch of b must have completed.  On error b is left empty. */
+int dbbc_batch_reset(dbbc_batch *b, dbbc_graph *const *gs, int32_t k, const dbbc_options *opt,
+                     uint32_t flags, void *hip_stream);
 
 /* Enqueue one count of every graph of the batch on hip_stream (replaying the
  * captured HIP graph if there is one) and the copy of the k results to host
@@ -215,6 +227,84 @@ int dbbc_count_batch(dbbc_graph *const *gs, int32_t k, const dbbc_options *opt,
  * graphs are planned with *best (batches made before are invalidated). */
 int dbbc_autotune(dbbc_graph *const *gs, int32_t k, const dbbc_options *start, int32_t reps,
                   void *hip_stream, dbbc_options *best, float *best_ms);
+
+/* ---- request server: continuous batching over resident graphs ------------ */
+
+/* A server keeps graphs resident on the device and answers count requests
+ * on them from a scheduler thread of its own.  Whenever one of its launch
+ * slots (a HIP stream each) is free, it takes the oldest waiting requests: a
+ * graph with at least solo_wedges vertex-priority wedges is counted alone;
+ * smaller graphs are packed, oldest request first, into one batch of at most
+ * max_batch graphs and batch_wedges wedges.  Requests arriving while
+ * launches run join the next free slot, so several launches overlap on the
+ * device; requests for a graph already being counted wait for the next
+ * launch, and requests for one graph waiting together share one count.
+ * Uploaded graphs are built by a worker thread and admitted against
+ * hbm_budget (device bytes of all resident graphs): idle uploaded graphs are
+ * evicted least recently used first; an upload that still does not fit is
+ * rejected with DBBC_E_OOM.  Counts equal those of dbbc_count on each graph
+ * alone. */
+typedef struct dbbc_server dbbc_server;
+
+typedef struct {
+  int64_t hbm_budget;   /* device bytes for resident graphs; <= 0: 85% of the
+                           free device memory at creation */
+  int32_t slots;        /* launches in flight at once, 1..16; <= 0: 4 */
+  int32_t max_batch;    /* graphs per batch; <= 0: 512 */
+  int64_t solo_wedges;  /* graphs with at least this many wedges are counted
+                           alone; <= 0: 2^26 */
+  int64_t batch_wedges; /* a batch stops growing at this many wedges; <= 0:
+                           2^28 */
+} dbbc_server_config;
+
+/* What happened to one request (times from dbbc_now_ns). */
+typedef struct {
+  int32_t status;       /* DBBC_OK or the request's error */
+  int32_t graph_id;     /* graph counted (-1 for a rejected upload) */
+  int32_t batch_size;   /* graphs in the launch that counted it (1 = alone) */
+  int32_t queued_ahead; /* requests waiting when it arrived */
+  int64_t t_submit_ns, t_launch_ns, t_done_ns;
+} dbbc_request_info;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected, uploads, evicted;
+  int64_t launches, batched_graphs; /* launches made and graphs they held */
+  int64_t max_queue, queued;        /* waiting requests: peak and now */
+  int64_t resident_graphs, resident_bytes;
+} dbbc_server_stats;
+
+/* Steady-clock time in ns (the clock of dbbc_request_info). */
+int64_t dbbc_now_ns(void);
+
+/* Start a server on the current device.  cfg and opt may be NULL (defaults;
+ * opt applies to every count, kernel timing not allowed). */
+int dbbc_server_create(const dbbc_server_config *cfg, const dbbc_options *opt, dbbc_server **out);
+
+/* Build and plan a resident graph (host edge arrays, rules of
+ * dbbc_graph_create); it is never evicted.  Writes its id.  May be called
+ * from several threads at once. */
+int dbbc_server_add_graph(dbbc_server *s, int32_t n_u, int32_t n_v, int64_t m, const int32_t *u,
+                          const int32_t *v, const int8_t *sign, int32_t *graph_id);
+
+/* Request a count of resident graph graph_id; writes a ticket. */
+int dbbc_server_submit(dbbc_server *s, int32_t graph_id, int64_t *ticket);
+
+/* Upload a new graph (host arrays, copied before return) and request its
+ * count; writes a ticket.  The graph stays resident (evictable) afterwards. */
+int dbbc_server_submit_upload(dbbc_server *s, int32_t n_u, int32_t n_v, int64_t m, const int32_t *u,
+                              const int32_t *v, const int8_t *sign, int64_t *ticket);
+
+/* Wait for a request; writes its counts and info (either may be NULL) and
+ * forgets the ticket.  Returns the request's status. */
+int dbbc_server_wait(dbbc_server *s, int64_t ticket, dbbc_counts *out, dbbc_request_info *info);
+
+int dbbc_server_get_stats(dbbc_server *s, dbbc_server_stats *out);
+
+/* Detail of the calling thread's last server error ("" if none). */
+const char *dbbc_server_last_error(void);
+
+/* Finish every accepted request, stop the threads, free all graphs. */
+void dbbc_server_destroy(dbbc_server *s);
 
 /* Kernel timings of the handle's last dbbc_count made with
  * DBBC_OPT_TIME_KERNELS.  Writes at most cap entries to out (host memory)

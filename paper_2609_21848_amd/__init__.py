@@ -36,10 +36,13 @@ DBBC_BATCH_CAPTURE = 0x1
 # every symbol declared in include/dbbc.h
 EXPORTS = (
     "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async", "dbbc_count_read",
-    "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_launch", "dbbc_batch_read",
+    "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_reset", "dbbc_batch_launch",
+    "dbbc_batch_read",
     "dbbc_batch_count", "dbbc_batch_size", "dbbc_batch_destroy", "dbbc_count_batch", "dbbc_autotune",
     "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string", "dbbc_last_error",
-    "dbbc_version",
+    "dbbc_version", "dbbc_graph_plan", "dbbc_now_ns", "dbbc_server_create", "dbbc_server_add_graph",
+    "dbbc_server_submit", "dbbc_server_submit_upload", "dbbc_server_wait", "dbbc_server_get_stats",
+    "dbbc_server_last_error", "dbbc_server_destroy",
 )
 
 
@@ -78,6 +81,26 @@ class Options(ctypes.Structure):
         super().__init__(hub_T, window_L, reverse_L, small_work, part_work, long_len, flags)
 
 
+class ServerConfig(ctypes.Structure):
+    """Mirror of dbbc_server_config (zero = default)."""
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("solo_wedges", ctypes.c_int64),
+                ("batch_wedges", ctypes.c_int64)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("graph_id", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("queued_ahead", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "completed", "failed", "rejected", "uploads", "evicted", "launches",
+        "batched_graphs", "max_queue", "queued", "resident_graphs", "resident_bytes")]
+
+
 class _KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_float), ("wedges", ctypes.c_int64),
                 ("segments", ctypes.c_int64), ("items", ctypes.c_int64), ("macs", ctypes.c_int64)]
@@ -102,6 +125,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
     lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
+    lib.dbbc_batch_reset.argtypes = [vp, vp, i32, ctypes.POINTER(Options), u32, vp]
     lib.dbbc_batch_launch.argtypes = [vp, vp]
     lib.dbbc_batch_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_count.argtypes = [vp, ctypes.POINTER(_Counts), vp]
@@ -114,6 +138,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                   ctypes.POINTER(ctypes.c_float)]
     lib.dbbc_last_kernel_times.argtypes = [vp, ctypes.POINTER(_KernelTime), i32,
                                            ctypes.POINTER(i32)]
+    lib.dbbc_graph_plan.argtypes = [vp, ctypes.POINTER(Options), vp]
+    lib.dbbc_now_ns.restype = i64
+    lib.dbbc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(Options),
+                                       ctypes.POINTER(vp)]
+    lib.dbbc_server_add_graph.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(i32)]
+    lib.dbbc_server_submit.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.dbbc_server_submit_upload.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.dbbc_server_wait.argtypes = [vp, i64, ctypes.POINTER(_Counts), ctypes.POINTER(RequestInfo)]
+    lib.dbbc_server_get_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+    lib.dbbc_server_last_error.restype = ctypes.c_char_p
+    lib.dbbc_server_destroy.argtypes = [vp]
+    lib.dbbc_server_destroy.restype = None
     lib.dbbc_graph_destroy.argtypes = [vp]
     lib.dbbc_graph_destroy.restype = None
     lib.dbbc_status_string.argtypes = [ctypes.c_int]
@@ -121,9 +157,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_last_error.restype = ctypes.c_char_p
     lib.dbbc_version.restype = ctypes.c_char_p
     for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async",
-                 "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_launch",
+                 "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_reset",
+                 "dbbc_batch_launch",
                  "dbbc_batch_read", "dbbc_batch_count", "dbbc_count_batch", "dbbc_autotune",
-                 "dbbc_last_kernel_times"):
+                 "dbbc_last_kernel_times", "dbbc_graph_plan", "dbbc_server_create",
+                 "dbbc_server_add_graph", "dbbc_server_submit", "dbbc_server_submit_upload",
+                 "dbbc_server_wait", "dbbc_server_get_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -132,7 +171,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 def _check(status: int, where: str):
     if status != DBBC_OK:
         lib = load()
-        detail = lib.dbbc_last_error().decode() or lib.dbbc_status_string(status).decode()
+        detail = lib.dbbc_last_error().decode()
+        if where.startswith("dbbc_server"):
+            detail = lib.dbbc_server_last_error().decode() or detail
+        detail = detail or lib.dbbc_status_string(status).decode()
         raise DbbcError(status, where, detail)
 
 
@@ -232,6 +274,12 @@ def dbbc_batch_create(gs, options: Options | None = None, flags: int = 0, stream
     _check(load().dbbc_batch_create(arr, k, opt, int(flags), _stream_ptr(stream), ctypes.byref(out)),
            "dbbc_batch_create")
     return out.value
+
+
+def dbbc_batch_reset(b: int, gs, options: Options | None = None, flags: int = 0, stream=None) -> None:
+    arr, k = _handles(gs)
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_batch_reset(b, arr, k, opt, int(flags), _stream_ptr(stream)), "dbbc_batch_reset")
 
 
 def dbbc_batch_launch(b: int, stream=None) -> None:
@@ -347,6 +395,11 @@ class Batch:
     def count(self, stream=None) -> list:
         return dbbc_batch_count(self.handle, stream)
 
+    def reset(self, graphs, capture: bool = False, stream=None, **opts) -> None:
+        self.graphs = list(graphs)
+        dbbc_batch_reset(self.handle, self.graphs, Options(**opts) if opts else None,
+                         DBBC_BATCH_CAPTURE if capture else 0, stream)
+
     def launch(self, stream=None) -> None:
         dbbc_batch_launch(self.handle, stream)
 
@@ -356,6 +409,87 @@ class Batch:
     def close(self):
         if self.handle:
             dbbc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dbbc_graph_plan(g: int, options: Options | None = None, stream=None) -> None:
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_graph_plan(g, opt, _stream_ptr(stream)), "dbbc_graph_plan")
+
+
+def dbbc_now_ns() -> int:
+    return int(load().dbbc_now_ns())
+
+
+class Server:
+    """Owning wrapper of dbbc_server_*: resident graphs and count requests
+    answered by the library's scheduler thread (continuous batching)."""
+
+    def __init__(self, hbm_budget=0, slots=0, max_batch=0, solo_wedges=0, batch_wedges=0,
+                 **opts):
+        cfg = ServerConfig(int(hbm_budget), int(slots), int(max_batch), int(solo_wedges),
+                           int(batch_wedges))
+        out = ctypes.c_void_p()
+        opt = ctypes.byref(Options(**opts)) if opts else None
+        _check(load().dbbc_server_create(ctypes.byref(cfg), opt, ctypes.byref(out)),
+               "dbbc_server_create")
+        self.handle = out.value
+
+    def add_graph(self, n_u, n_v, u, v, sign) -> int:
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        sign = np.ascontiguousarray(sign, dtype=np.int8)
+        gid = ctypes.c_int32()
+        _check(load().dbbc_server_add_graph(self.handle, int(n_u), int(n_v), len(u), u.ctypes.data,
+                                            v.ctypes.data, sign.ctypes.data, ctypes.byref(gid)),
+               "dbbc_server_add_graph")
+        return gid.value
+
+    def submit(self, graph_id: int) -> int:
+        t = ctypes.c_int64()
+        _check(load().dbbc_server_submit(self.handle, int(graph_id), ctypes.byref(t)),
+               "dbbc_server_submit")
+        return t.value
+
+    def submit_upload(self, n_u, n_v, u, v, sign) -> int:
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        sign = np.ascontiguousarray(sign, dtype=np.int8)
+        t = ctypes.c_int64()
+        _check(load().dbbc_server_submit_upload(self.handle, int(n_u), int(n_v), len(u),
+                                                u.ctypes.data, v.ctypes.data, sign.ctypes.data,
+                                                ctypes.byref(t)), "dbbc_server_submit_upload")
+        return t.value
+
+    def wait(self, ticket: int):
+        """(status, Counts or None, info dict) of a request."""
+        c = _Counts()
+        info = RequestInfo()
+        st = load().dbbc_server_wait(self.handle, int(ticket), ctypes.byref(c), ctypes.byref(info))
+        d = {k: int(getattr(info, k)) for k, _ in RequestInfo._fields_}
+        counts = Counts(c.balanced, c.unbalanced, c.total, c.wedges) if st == DBBC_OK else None
+        return st, counts, d
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(load().dbbc_server_get_stats(self.handle, ctypes.byref(s)), "dbbc_server_get_stats")
+        return {k: int(getattr(s, k)) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            load().dbbc_server_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

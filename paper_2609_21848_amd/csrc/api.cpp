@@ -64,6 +64,11 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
+  // keep the allocation if it is already large enough
+  hipError_t reserve(size_t n) {
+    if (n <= bytes && (p || n == 0)) return hipSuccess;
+    return alloc(n);
+  }
   hipError_t alloc(size_t n) {
     release();
     if (n == 0) return hipSuccess;
@@ -76,6 +81,14 @@ struct DevBuf {
     return static_cast<T*>(p);
   }
 };
+
+// Copy v into b, growing b only when v does not fit.
+template <class T>
+hipError_t upload_reuse(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  hipError_t e = b.reserve(v.size() * sizeof(T));
+  if (e != hipSuccess || v.empty()) return e;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
 
 template <class T>
 hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
@@ -287,6 +300,8 @@ struct dbbc_graph {
   size_t timers_used = 0;
   bool timed_valid = false;
   bool in_flight = false;  // an asynchronous count awaits dbbc_count_read
+  mutable bool defaults_valid = false;  // default plan knobs, computed once
+  mutable dbbc::PlanParams defaults;
   ~dbbc_graph() {
     if (pinned) (void)hipHostFree(pinned);
     for (auto& t : timers)
@@ -302,12 +317,18 @@ struct dbbc_batch {
   DevBuf direct, reverse, small, hash, reduces, sides, srcs, res, ctl;
   LaunchSet L;
   unsigned long long* pinned = nullptr;  // k result slots, then the error word
+  size_t pinned_words = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  ~dbbc_batch() {
+  void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~dbbc_batch() {
+    drop_graph();
     if (cap) (void)hipStreamDestroy(cap);
     if (pinned) (void)hipHostFree(pinned);
   }
@@ -403,7 +424,11 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
 constexpr int32_t kDefaultLongLen = 128;
 
 int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& p, uint32_t& long_len) {
-  p = dbbc::default_params(g->host);
+  if (!g->defaults_valid) {
+    g->defaults = dbbc::default_params(g->host);
+    g->defaults_valid = true;
+  }
+  p = g->defaults;
   long_len = kDefaultLongLen;
   if (!opt) return DBBC_OK;
   if (opt->flags & ~DBBC_OPT_TIME_KERNELS) return fail(DBBC_E_INVALID_ARG, "unknown dbbc_options flag");
@@ -607,6 +632,17 @@ int dbbc_count(dbbc_graph* g, const dbbc_options* opt, dbbc_counts* out_host, vo
   return finish_lone(g, out_host, opt && (opt->flags & DBBC_OPT_TIME_KERNELS));
 }
 
+int dbbc_graph_plan(dbbc_graph* g, const dbbc_options* opt, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_graph(g);
+  if (rc != DBBC_OK) return rc;
+  dbbc::PlanParams p;
+  uint32_t long_len = 0;
+  rc = params_from(g, opt, p, long_len);
+  if (rc != DBBC_OK) return rc;
+  return ensure_plan(g, p, static_cast<hipStream_t>(hip_stream));
+}
+
 int dbbc_count_async(dbbc_graph* g, const dbbc_options* opt, void* hip_stream) {
   g_last_error.clear();
   int rc = check_graph(g);
@@ -633,24 +669,30 @@ int dbbc_count_per_vertex(dbbc_graph* g, int64_t* bal_u, int64_t* bal_v, int64_t
   return fail(DBBC_E_INVALID_ARG, "per-vertex counts are not available in this build");
 }
 
-int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt, uint32_t flags,
-                      void* hip_stream, dbbc_batch** out) {
-  g_last_error.clear();
-  if (!out || k < 0 || (k > 0 && !gs)) return fail(DBBC_E_INVALID_ARG, "bad batch arguments");
+}  // extern "C"
+
+namespace {
+
+// (Re)target batch b at the graphs gs[0..k): plan them, assemble their work
+// lists on the device into b's buffers (grown only when too small) and, with
+// DBBC_BATCH_CAPTURE, capture the launch sequence into a HIP graph.
+int assemble_batch(dbbc_batch* b, dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
+                   uint32_t flags, hipStream_t st) {
+  if (k < 0 || (k > 0 && !gs)) return fail(DBBC_E_INVALID_ARG, "bad batch arguments");
   if (flags & ~DBBC_BATCH_CAPTURE) return fail(DBBC_E_INVALID_ARG, "unknown batch flag");
   if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
     return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
-  std::unique_ptr<dbbc_batch> b(new (std::nothrow) dbbc_batch());
-  if (!b) return fail(DBBC_E_OOM, "host allocation failed");
   std::unordered_set<const dbbc_graph*> seen;
   for (int32_t i = 0; i < k; ++i) {
     int rc = check_graph(gs[i]);
     if (rc != DBBC_OK) return rc;
     if (!seen.insert(gs[i]).second) return fail(DBBC_E_INVALID_ARG, "a graph appears twice in the batch");
   }
-  int rc = current_device(b->dev);
-  if (rc != DBBC_OK) return rc;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  b->drop_graph();
+  b->gs.clear();
+  b->gens.clear();
+  b->L = LaunchSet{};
+  int rc;
   uint32_t long_len = kDefaultLongLen;
   int64_t tot[5] = {0, 0, 0, 0, 0};
   LaunchSet& L = b->L;
@@ -669,23 +711,26 @@ int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
   }
   for (int j = 0; j < 5; ++j)
     if (tot[j] > INT32_MAX) return fail(DBBC_E_TOO_LARGE, "too many work items in one batch");
+  HIP_TRY(b->res.reserve(static_cast<size_t>(std::max(k, 1)) * dbbc::kResStride * sizeof(unsigned long long)));
+  HIP_TRY(b->ctl.reserve(kCtlWords * sizeof(unsigned long long)));
+  const size_t words = static_cast<size_t>(k) * dbbc::kResStride + 1;
+  if (words > b->pinned_words) {
+    if (b->pinned) HIP_TRY(hipHostFree(b->pinned));
+    b->pinned = nullptr;
+    b->pinned_words = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->pinned), words * sizeof(unsigned long long),
+                          hipHostMallocDefault));
+    b->pinned_words = words;
+  }
   b->gs.assign(gs, gs + k);
   for (int32_t i = 0; i < k; ++i) b->gens.push_back(gs[i]->plan_gen);
-  HIP_TRY(b->res.alloc(static_cast<size_t>(std::max(k, 1)) * dbbc::kResStride * sizeof(unsigned long long)));
-  HIP_TRY(b->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->pinned),
-                        (static_cast<size_t>(k) * dbbc::kResStride + 1) * sizeof(unsigned long long),
-                        hipHostMallocDefault));
-  if (k == 0) {
-    *out = b.release();
-    return DBBC_OK;
-  }
+  if (k == 0) return DBBC_OK;
   // Assemble the k graphs' lists into one list per kernel, on the device.
   DevBuf* lists[5] = {&b->direct, &b->reverse, &b->small, &b->hash, &b->reduces};
   std::vector<dbbc::AssembleSrc> srcs(static_cast<size_t>(5) * k);
   for (int j = 0; j < 5; ++j) {
     const size_t esz = j == 4 ? sizeof(dbbc::Reduce) : sizeof(dbbc::Item);
-    HIP_TRY(lists[j]->alloc(static_cast<size_t>(tot[j]) * esz));
+    HIP_TRY(lists[j]->reserve(static_cast<size_t>(tot[j]) * esz));
     uint32_t off = 0;
     for (int32_t i = 0; i < k; ++i) {
       const DevPlan& d = gs[i]->plan;
@@ -698,7 +743,7 @@ int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
       off += a.n;
     }
   }
-  HIP_TRY(upload(b->srcs, srcs, st));
+  HIP_TRY(upload_reuse(b->srcs, srcs, st));
   const dbbc::AssembleSrc* dsrc = b->srcs.as<dbbc::AssembleSrc>();
   for (int j = 0; j < 4; ++j)
     if (tot[j]) HIP_TRY(dbbc::launch_assemble_items(dsrc + static_cast<size_t>(j) * k, k, lists[j]->as<dbbc::Item>(), st));
@@ -708,7 +753,7 @@ int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
     side[2 * static_cast<size_t>(i)] = gs[i]->plan.side[0];
     side[2 * static_cast<size_t>(i) + 1] = gs[i]->plan.side[1];
   }
-  HIP_TRY(upload(b->sides, side, st));
+  HIP_TRY(upload_reuse(b->sides, side, st));
   HIP_TRY(hipStreamSynchronize(st));
   L.direct = b->direct.as<dbbc::Item>();
   L.reverse = b->reverse.as<dbbc::Item>();
@@ -725,7 +770,7 @@ int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
   L.long_len = long_len;
   L.cus = b->dev.cus;
   if (flags & DBBC_BATCH_CAPTURE) {
-    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     Timing tm{nullptr, 0, b->cap};
     rc = enqueue(L, b->cap, tm);
@@ -734,8 +779,45 @@ int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
     HIP_TRY(e);
     HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
+  return DBBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt, uint32_t flags,
+                      void* hip_stream, dbbc_batch** out) {
+  g_last_error.clear();
+  if (!out) return fail(DBBC_E_INVALID_ARG, "bad batch arguments");
+  if (k < 0 || (k > 0 && !gs) || (flags & ~DBBC_BATCH_CAPTURE))
+    return assemble_batch(nullptr, gs, k, opt, flags, nullptr);  // reports the argument error
+  for (int32_t i = 0; i < k; ++i) {
+    const int rc = check_graph(gs[i]);
+    if (rc != DBBC_OK) return rc;
+  }
+  std::unique_ptr<dbbc_batch> b(new (std::nothrow) dbbc_batch());
+  if (!b) return fail(DBBC_E_OOM, "host allocation failed");
+  int rc = current_device(b->dev);
+  if (rc != DBBC_OK) return rc;
+  rc = assemble_batch(b.get(), gs, k, opt, flags, static_cast<hipStream_t>(hip_stream));
+  if (rc != DBBC_OK) return rc;
   *out = b.release();
   return DBBC_OK;
+}
+
+int dbbc_batch_reset(dbbc_batch* b, dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
+                     uint32_t flags, void* hip_stream) {
+  g_last_error.clear();
+  if (!b) return fail(DBBC_E_INVALID_ARG, "NULL batch");
+  const int rc = assemble_batch(b, gs, k, opt, flags, static_cast<hipStream_t>(hip_stream));
+  if (rc != DBBC_OK) {  // leave an empty batch behind
+    b->drop_graph();
+    b->gs.clear();
+    b->gens.clear();
+    b->L = LaunchSet{};
+  }
+  return rc;
 }
 
 int dbbc_batch_launch(dbbc_batch* b, void* hip_stream) {

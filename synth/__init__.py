@@ -13,6 +13,7 @@ from .graphs import (  # noqa: F401
     batch_graph,
     batch_graphs,
     pool_graph,
+    pool_graphs,
     upload_graph,
     CONFIGS,
 )

@@ -182,6 +182,14 @@ def pool_graph(i: int, n_pool: int = 1000, seed: int = 0) -> SignedGraph:
     return _pool_like(ss, f"pool{i}")
 
 
+def pool_graphs(n_pool: int = 1000, seed: int = 0, idx=None):
+    """Graphs idx (default: all) of the serving pool, the seed sequence
+    spawned once; the same graphs as pool_graph."""
+    kids = np.random.SeedSequence(seed).spawn(n_pool)
+    idx = range(n_pool) if idx is None else idx
+    return [_pool_like(kids[i], f"pool{i}") for i in idx]
+
+
 def upload_graph(j: int, seed: int = 1) -> SignedGraph:
     """Graph ``j`` of the newly uploaded stream (same law as the pool)."""
     ss = np.random.SeedSequence([seed, j])

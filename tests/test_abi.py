@@ -76,6 +76,13 @@ def test_validation_errors_need_no_device():
     assert lib.dbbc_batch_launch(None, None) == dbbc.DBBC_E_INVALID_ARG
     assert lib.dbbc_batch_size(None) == 0
     lib.dbbc_batch_destroy(None)
+    # servers
+    assert lib.dbbc_server_create(None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    t = ctypes.c_int64()
+    assert lib.dbbc_server_submit(None, 0, ctypes.byref(t)) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_server_wait(None, 1, None, None) == dbbc.DBBC_E_INVALID_ARG
+    lib.dbbc_server_destroy(None)
+    assert lib.dbbc_now_ns() > 0
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
