@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
     ap.add_argument("--serve-pool", type=int, default=1000)
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)  # 60 for the full run
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
 
