@@ -330,6 +330,7 @@ def main():
     ap.add_argument("--cpu-fraction", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-pv", action="store_true", help="skip the per-vertex pass")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
     ap.add_argument("--serve-pool", type=int, default=1000)
@@ -466,6 +467,23 @@ def main():
         ms = (time.perf_counter() - ts) * 1e3 / args.steps
         log(f"[sweep] {spec}: {ms:.3f} ms/step " +
             " ".join(f"{k}={v:.3f}" for k, v in ks.items()))
+    if not args.no_pv:
+        # the per-vertex pass (second enumeration) on the same resident graph
+        pv0 = h.count_per_vertex()
+        assert tuple(pv0[0]) == tuple(first), "per-vertex pass counts differ"
+        sums_ok = all(int(t.sum()) == 2 * w for t, w in zip(pv0[1:], (first.balanced, first.balanced,
+                                                                      first.unbalanced, first.unbalanced)))
+        del pv0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            h.count_per_vertex()
+        torch.cuda.synchronize()
+        ms_pv = (time.perf_counter() - t) * 1e3 / reps
+        out["per_vertex"] = {"ms_per_pass": ms_pv, "gwedges_per_s": w_vp / (ms_pv / 1e3) / 1e9,
+                             "side_sums_equal_twice_counts": sums_ok}
+        log(f"[bench] per-vertex pass {ms_pv:.2f} ms ({w_vp / ms_pv / 1e6:.1f} GWedges/s)")
     h.close()
     if not args.no_batch:
         out["batched"] = bench_batched(dbbc, args.steps, args.warmup, args.batch_graphs, 64)

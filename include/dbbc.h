@@ -138,14 +138,26 @@ int dbbc_graph_stats(const dbbc_graph *g, dbbc_stats *out);
  * written after the stream has drained. */
 int dbbc_count(dbbc_graph *g, const dbbc_options *opt, dbbc_counts *out_host, void *hip_stream);
 
-/* Per-vertex counts: for every vertex, the number of balanced and unbalanced
- * butterflies containing it (the tip-style vertex measure of Section I,
- * Applications).  Outputs are caller-owned device arrays of n_u (bal_u,
- * unb_u) or n_v (bal_v, unb_v) int64 values; any may be NULL.  They are
- * overwritten (not accumulated).  out_host (may be NULL) receives the global
- * counts of the same pass. */
-int dbbc_count_per_vertex(dbbc_graph *g, int64_t *bal_u, int64_t *bal_v, int64_t *unb_u,
-                          int64_t *unb_v, dbbc_counts *out_host, void *hip_stream);
+/* Per-vertex counts (Section I, Applications: the butterflies a vertex
+ * participates in): for every vertex, the number of balanced and of
+ * unbalanced butterflies that contain it.  A second pass walks each
+ * priority-owned pair's wedges again once the pair's symmetric and
+ * asymmetric counts p and n are known: the pair's two same-side vertices
+ * each lie in C(p,2) + C(n,2) balanced and p n unbalanced of its
+ * butterflies, a mid of a symmetric wedge in p - 1 balanced and n
+ * unbalanced ones, a mid of an asymmetric wedge in n - 1 and p.  Every
+ * vertex of U (and of V) is in 2 of each butterfly's 4 places, so the U
+ * entries (and the V entries) sum to twice the global counts.
+ *   opt      : window_L, reverse_L, small_work and long_len apply (NULL =
+ *              defaults); there is no dense block in this pass
+ *   bal_u, unb_u: n_u int64 values, bal_v, unb_v: n_v int64 values, in input
+ *              id order, caller-owned device memory; any may be NULL; they
+ *              are overwritten
+ *   out_host : the global counts of the same pass (host memory, may be NULL)
+ * The pass keeps a plan and four n-sized int64 arrays of its own on the
+ * handle, beside those of dbbc_count. */
+int dbbc_count_per_vertex(dbbc_graph *g, const dbbc_options *opt, int64_t *bal_u, int64_t *bal_v,
+                          int64_t *unb_u, int64_t *unb_v, dbbc_counts *out_host, void *hip_stream);
 
 /* Build the handle's counting plan for opt now (NULL = defaults), so that
  * the next count with the same options starts at once; returns when the plan

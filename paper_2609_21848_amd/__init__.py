@@ -121,7 +121,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_graph_create.argtypes = [i32, i32, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
     lib.dbbc_graph_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
     lib.dbbc_count.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
-    lib.dbbc_count_per_vertex.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(_Counts), vp]
+    lib.dbbc_count_per_vertex.argtypes = [vp, ctypes.POINTER(Options), vp, vp, vp, vp,
+                                          ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
     lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
@@ -247,7 +248,7 @@ def dbbc_count_read(g: int) -> Counts:
 
 
 def dbbc_count_per_vertex(g: int, bal_u=None, bal_v=None, unb_u=None, unb_v=None,
-                          stream=None) -> Counts:
+                          options: Options | None = None, stream=None) -> Counts:
     """Fill caller-owned int64 device tensors (any may be None)."""
     def p(t):
         if t is None:
@@ -256,7 +257,8 @@ def dbbc_count_per_vertex(g: int, bal_u=None, bal_v=None, unb_u=None, unb_v=None
             raise ValueError("per-vertex outputs must be contiguous int64 CUDA tensors")
         return t.data_ptr()
     c = _Counts()
-    _check(load().dbbc_count_per_vertex(g, p(bal_u), p(bal_v), p(unb_u), p(unb_v),
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_count_per_vertex(g, opt, p(bal_u), p(bal_v), p(unb_u), p(unb_v),
                                         ctypes.byref(c), _stream_ptr(stream)),
            "dbbc_count_per_vertex")
     return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
@@ -353,6 +355,18 @@ class Graph:
 
     def count(self, stream=None, **opts) -> Counts:
         return dbbc_count(self.handle, Options(**opts) if opts else None, stream)
+
+    def count_per_vertex(self, stream=None, **opts):
+        """(Counts, bal_u, bal_v, unb_u, unb_v): int64 CUDA tensors in input id order."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        bu = torch.empty(self.n_u, dtype=torch.int64, device=dev)
+        bv = torch.empty(self.n_v, dtype=torch.int64, device=dev)
+        uu = torch.empty(self.n_u, dtype=torch.int64, device=dev)
+        uv = torch.empty(self.n_v, dtype=torch.int64, device=dev)
+        c = dbbc_count_per_vertex(self.handle, bu, bv, uu, uv, Options(**opts) if opts else None,
+                                  stream)
+        return c, bu, bv, uu, uv
 
     def count_async(self, stream=None, **opts) -> None:
         dbbc_count_async(self.handle, Options(**opts) if opts else None, stream)

@@ -107,13 +107,15 @@ constexpr size_t kCtlQueues = 8;
 struct DevPlan {
   dbbc::HostPlan host;
   DevBuf segs, small_segs, small_groups, direct_items, hash_items, reverse_items, reduces, acc, sides;
+  DevBuf seg_mid, small_seg_mid, small_owner;  // per-vertex plans
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
   dbbc::DevSideConst side[2] = {};  // host copy of the side table
   bool valid = false;
   size_t bytes() const {
     size_t b = segs.bytes + small_segs.bytes + small_groups.bytes + direct_items.bytes +
-               hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes + sides.bytes;
+               hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes + sides.bytes +
+               seg_mid.bytes + small_seg_mid.bytes + small_owner.bytes;
     for (int s = 0; s < 2; ++s) b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes;
     return b;
   }
@@ -296,6 +298,9 @@ struct dbbc_graph {
   unsigned long long* pinned = nullptr;  // host mirror of ctl
   DevPlan plan;
   uint64_t plan_gen = 0;  // bumped whenever the device plan is rebuilt
+  DevPlan pv_plan;        // plan of the per-vertex pass
+  DevBuf orig[2];         // side rank -> input id, per side (per-vertex pass)
+  DevBuf pv_out[2][2];    // per-vertex outputs [side][balanced, unbalanced]
   std::vector<KernelRec> timers;  // events are reused across timed counts
   size_t timers_used = 0;
   bool timed_valid = false;
@@ -336,10 +341,10 @@ struct dbbc_batch {
 
 namespace {
 
-int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
-  if (g->plan.valid && g->plan.host.p == p) return DBBC_OK;
-  g->plan.valid = false;
-  ++g->plan_gen;
+int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, DevPlan& d) {
+  if (d.valid && d.host.p == p) return DBBC_OK;
+  d.valid = false;
+  if (&d == &g->plan) ++g->plan_gen;
   std::string err;
   dbbc::HostPlan hp;
   int rc;
@@ -349,8 +354,10 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
     return fail(DBBC_E_OOM, "host allocation failed while planning");
   }
   if (rc != DBBC_OK) return fail(rc, err);
-  DevPlan& d = g->plan;
   HIP_TRY(upload(d.segs, hp.segs, st));
+  HIP_TRY(upload(d.seg_mid, hp.seg_mid, st));
+  HIP_TRY(upload(d.small_seg_mid, hp.small_seg_mid, st));
+  HIP_TRY(upload(d.small_owner, hp.small_owner, st));
   HIP_TRY(upload(d.small_segs, hp.small_segs, st));
   HIP_TRY(upload(d.small_groups, hp.small_groups, st));
   HIP_TRY(upload(d.direct_items, hp.direct_items, st));
@@ -393,6 +400,17 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
     c.R = hp.R[s];
     c.key_bits = hp.key_bits[s];
     c.acc_width = hp.acc_width;
+    if (p.per_vertex) {
+      c.seg_mid = d.seg_mid.as<uint32_t>();
+      c.small_seg_mid = d.small_seg_mid.as<uint32_t>();
+      c.small_owner = d.small_owner.as<int32_t>();
+      c.orig = g->orig[s].as<int32_t>();
+      c.orig_mid = g->orig[1 - s].as<int32_t>();
+      c.bal = g->pv_out[s][0].as<unsigned long long>();
+      c.unb = g->pv_out[s][1].as<unsigned long long>();
+      c.bal_mid = g->pv_out[1 - s][0].as<unsigned long long>();
+      c.unb_mid = g->pv_out[1 - s][1].as<unsigned long long>();
+    }
   }
   HIP_TRY(d.sides.alloc(sizeof(d.side)));
   HIP_TRY(hipMemcpyAsync(d.sides.p, d.side, sizeof(d.side), hipMemcpyHostToDevice, st));
@@ -400,6 +418,12 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   // the host plan keeps only what later launches need
   hp.segs.clear();
   hp.segs.shrink_to_fit();
+  hp.seg_mid.clear();
+  hp.seg_mid.shrink_to_fit();
+  hp.small_seg_mid.clear();
+  hp.small_seg_mid.shrink_to_fit();
+  hp.small_owner.clear();
+  hp.small_owner.shrink_to_fit();
   hp.small_segs.clear();
   hp.small_segs.shrink_to_fit();
   hp.small_items.clear();
@@ -418,6 +442,10 @@ int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
   d.host = std::move(hp);
   d.valid = true;
   return DBBC_OK;
+}
+
+int ensure_plan(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st) {
+  return ensure_plan_into(g, p, st, g->plan);
 }
 
 // Runs of at least this many entries are streamed by a whole wavefront.
@@ -663,10 +691,94 @@ int dbbc_count_read(dbbc_graph* g, dbbc_counts* out_host) {
   return finish_lone(g, out_host, false);
 }
 
-int dbbc_count_per_vertex(dbbc_graph* g, int64_t* bal_u, int64_t* bal_v, int64_t* unb_u,
-                          int64_t* unb_v, dbbc_counts* out_host, void* hip_stream) {
-  (void)g; (void)bal_u; (void)bal_v; (void)unb_u; (void)unb_v; (void)out_host; (void)hip_stream;
-  return fail(DBBC_E_INVALID_ARG, "per-vertex counts are not available in this build");
+int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u, int64_t* bal_v,
+                          int64_t* unb_u, int64_t* unb_v, dbbc_counts* out_host, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_graph(g);
+  if (rc != DBBC_OK) return rc;
+  if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
+    return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  dbbc::PlanParams p;
+  uint32_t long_len = 0;
+  rc = params_from(g, opt, p, long_len);
+  if (rc != DBBC_OK) return rc;
+  p.per_vertex = true;
+  p.hub_T = 0;
+  const int32_t n[2] = {g->host.n_u, g->host.n_v};
+  for (int s = 0; s < 2; ++s) {
+    if (!g->orig[s].p) HIP_TRY(upload(g->orig[s], g->host.side[s].orig, st));
+    for (int k = 0; k < 2; ++k)
+      HIP_TRY(g->pv_out[s][k].reserve(static_cast<size_t>(n[s]) * sizeof(unsigned long long)));
+  }
+  rc = ensure_plan_into(g, p, st, g->pv_plan);
+  if (rc != DBBC_OK) return rc;
+  DevPlan& d = g->pv_plan;
+  const dbbc::HostPlan& hp = d.host;
+  unsigned long long* ctl = g->ctl.as<unsigned long long>();
+  HIP_TRY(dbbc::launch_fill_u64(ctl, kCtlWords, 0ull, st));
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 2; ++k)
+      HIP_TRY(dbbc::launch_fill_u64(g->pv_out[s][k].as<unsigned long long>(), static_cast<size_t>(n[s]), 0ull, st));
+  unsigned long long* err = ctl + kCtlErr;
+  uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + kCtlQueues);
+  const dbbc::DevSideConst* sides = d.sides.as<dbbc::DevSideConst>();
+  const int cus = g->dev.cus;
+  {
+    dbbc::DirectArgs a{};
+    a.items = d.direct_items.as<dbbc::Item>();
+    a.sides = sides;
+    a.queue = queues + 0;
+    a.res = ctl;
+    a.err = err;
+    a.n_items = hp.n_items_kept[0];
+    a.long_len = long_len;
+    HIP_TRY(dbbc::launch_pv_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+  }
+  {
+    dbbc::SmallArgs a{};
+    a.items = d.reverse_items.as<dbbc::Item>();
+    a.sides = sides;
+    a.res = ctl;
+    a.err = err;
+    a.n_items = hp.n_items_kept[1];
+    a.long_len = long_len;
+    HIP_TRY(dbbc::launch_pv_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 11) / 12)), st));
+  }
+  {
+    dbbc::SmallArgs a{};
+    a.items = d.small_groups.as<dbbc::Item>();
+    a.sides = sides;
+    a.res = ctl;
+    a.err = err;
+    a.n_items = hp.n_items_kept[2];
+    a.long_len = long_len;
+    HIP_TRY(dbbc::launch_pv_small(a, std::min<int>(3 * cus, std::max(1, (a.n_items + 3) / 4)), st));
+  }
+  {
+    dbbc::HashArgs a{};
+    a.items = d.hash_items.as<dbbc::Item>();
+    a.sides = sides;
+    a.queue = queues + 2;
+    a.res = ctl;
+    a.err = err;
+    a.n_items = hp.n_items_kept[3];
+    a.long_len = long_len;
+    HIP_TRY(dbbc::launch_pv_hash(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+  }
+  int64_t* outs[2][2] = {{bal_u, unb_u}, {bal_v, unb_v}};
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 2; ++k)
+      if (outs[s][k])
+        HIP_TRY(hipMemcpyAsync(outs[s][k], g->pv_out[s][k].p, static_cast<size_t>(n[s]) * sizeof(int64_t),
+                               hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(g->pinned, g->ctl.p, kCtlWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  dbbc_counts c{};
+  rc = finish_lone(g, &c, false);
+  if (rc != DBBC_OK) return rc;
+  if (out_host) *out_host = c;
+  return DBBC_OK;
 }
 
 }  // extern "C"

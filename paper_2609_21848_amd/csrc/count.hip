@@ -21,321 +21,10 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "walk.h"
 
 namespace dbbc {
 namespace dev {
-
-constexpr int kWave = 64;
-constexpr uint32_t kChunk = 256;   // entries per wavefront 16-byte load (64 lanes x 4)
-constexpr uint32_t kGather = 256;  // positions per staging round of short runs
-constexpr uint32_t kEmpty = 0xffffffffu;
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ uint32_t readlane(uint32_t v, int j) {
-  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), j));
-}
-
-// DPP move of v within the wavefront (lanes without a source read 0).
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ uint32_t dpp(uint32_t v) {
-  return static_cast<uint32_t>(
-      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), kCtrl, kRowMask, 0xf, false));
-}
-
-// Exclusive prefix sum over the wavefront with DPP: an inclusive scan inside
-// each row of 16 lanes (row_shr 1, 2, 4, 8), then row_bcast:15 and
-// row_bcast:31 carry the row totals upward.
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
-  uint32_t v = x;
-  v += dpp<0x111, 0xf>(v);  // row_shr:1
-  v += dpp<0x112, 0xf>(v);  // row_shr:2
-  v += dpp<0x114, 0xf>(v);  // row_shr:4
-  v += dpp<0x118, 0xf>(v);  // row_shr:8
-  v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  *total = readlane(v, kWave - 1);
-  return v - x;
-}
-
-// Order this wavefront's LDS accesses (not its global loads, which may stay
-// in flight, e.g. prefetches of the next item).
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// One lane's run of a batch (len 0 = none).  Bit 0 of tag is the sign bit g
-// of the run's first wedge edge; the runs of a small-item group also carry
-// the item's index in the group above it (tag = index << 1 | g).
-struct SegReg {
-  uint32_t start, len, tag;
-};
-
-template <bool kTagged>
-__device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1) {
-  const uint32_t k = k0 + lane_id();
-  SegReg r{0, 0, 0};
-  if (k < k1) {
-    const Segment s = segs[k];
-    r.start = s.start;
-    if (kTagged) {
-      r.len = (s.len_g & 0xffffu) >> 1;
-      r.tag = (s.len_g & 1u) | ((s.len_g >> 16) << 1);
-    } else {
-      r.len = s.len_g >> 1;
-      r.tag = s.len_g & 1u;
-    }
-  }
-  return r;
-}
-
-// v of lane src (all lanes must be active).
-__device__ __forceinline__ uint32_t bpermute(uint32_t v, uint32_t src) {
-  return static_cast<uint32_t>(
-      __builtin_amdgcn_ds_bpermute(static_cast<int>(src << 2), static_cast<int>(v)));
-}
-
-// Short runs of a batch are laid end to end: flat position t (0 <= t <
-// total) is entry base + t of its run's row, with base = start - excl of
-// the run.  A staging round covers positions [done, done + kGather), dealt
-// to lanes as t = done + 64 u + lane (coalesced loads).  Every run that
-// starts in the round, or continues into it, writes its base and its tag
-// (with bit 31 set as a presence flag) at its first position of the round
-// into the wavefront's marks buffers; a position's run is then the last
-// mark at or before it: a ballot per block of 64 positions, carried across
-// blocks.  Each lane clears the presence words it read, so they are all
-// zero between rounds.
-constexpr int kStageU = kGather / kWave;
-
-// TagT holds a run's tag plus the presence bit (its top bit): 8 bits for
-// plain runs (tag = g), 32 bits for small-item groups.
-template <class TagT>
-struct Marks {
-  uint32_t* base;  // kGather words
-  TagT* tag;       // kGather entries, zero when no run starts there
-  static constexpr uint32_t kBit = 1u << (8 * sizeof(TagT) - 1);
-};
-
-struct Staged {
-  uint32_t e[kStageU], tag[kStageU];
-  bool valid[kStageU];
-};
-
-template <class M>
-__device__ __forceinline__ void stage_round(Staged& s, M mk, uint32_t excl, uint32_t slen,
-                                            uint32_t base, uint32_t tag, uint32_t total, uint32_t done,
-                                            const uint32_t* __restrict__ adj) {
-  const int lane = lane_id();
-  wave_sync_lds();
-  if (slen != 0 && excl < done + kGather && excl + slen > done) {
-    const uint32_t pos = excl > done ? excl - done : 0u;
-    mk.base[pos] = base;
-    mk.tag[pos] = static_cast<decltype(+mk.tag[0])>(tag | M::kBit);
-  }
-  wave_sync_lds();
-  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane
-  uint32_t cb = 0, ct = 0;
-#pragma unroll
-  for (int u = 0; u < kStageU; ++u) {
-    const uint32_t mt = static_cast<uint32_t>(mk.tag[u * kWave + lane]);
-    const uint32_t mb = mk.base[u * kWave + lane];
-    mk.tag[u * kWave + lane] = 0;
-    const uint64_t below = __ballot(mt != 0) & upto;
-    const uint32_t src = below ? 63u - static_cast<uint32_t>(__clzll(below)) : 0u;
-    const uint32_t pb = bpermute(mb, src), pt = bpermute(mt, src);
-    // positions past the end may have no run: masked below
-    const uint32_t b = below ? pb : cb;
-    const uint32_t tg = below ? pt : ct;
-    cb = readlane(b, kWave - 1);
-    ct = readlane(tg, kWave - 1);
-    s.tag[u] = tg & ~M::kBit;
-    const uint32_t t = done + static_cast<uint32_t>(u * kWave + lane);
-    s.valid[u] = t < total;
-    s.e[u] = adj[s.valid[u] ? b + t : 0u];
-  }
-}
-
-// Walk a batch of up to 64 runs (one per lane, in registers) with one
-// wavefront, calling f.add(entry, tag, valid) once per wedge slot.
-//  - Runs of at least long_len entries are consumed as a stream of
-//    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
-//    chunk, U chunks are in flight per lane, and a chunk's out-of-run words
-//    are masked.  The chunk loop is wavefront-uniform.
-//  - Shorter runs are staged (stage_round) so that every lane holds wedges;
-//    the loads of the first round are issued before the long stream and the
-//    next round's loads before the current round is tallied.
-template <int U, class M, class F>
-__device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, M marks,
-                                          uint32_t long_len, F&& f) {
-  const int lane = lane_id();
-  const uint32_t start = sr.start, tag = sr.tag, len = sr.len;
-  uint64_t longm = __ballot(len >= long_len);
-  const uint32_t slen = len >= long_len ? 0u : len;
-  uint32_t total;
-  const uint32_t excl = wave_excl_scan(slen, &total);
-  const uint32_t base = start - excl;
-  Staged cur;
-  if (total) stage_round(cur, marks, excl, slen, base, tag, total, 0, adj);
-  uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
-  bool have = false;
-  while (longm || have) {
-    uint4 v[U];
-    uint32_t vst[U], vend[U], vg[U], vp[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!have && longm) {
-        const int j = __ffsll(static_cast<unsigned long long>(longm)) - 1;
-        longm &= longm - 1;
-        cur_st = readlane(start, j);
-        cur_end = cur_st + readlane(len, j);
-        cur_g = readlane(tag, j);
-        cur_pos = cur_st & ~3u;
-        have = true;
-      }
-      // The load is unconditional (no wait on registers of a skipped load):
-      // lanes past the run's end and empty slots read the first entries of
-      // the array, and their words fail the index test below.
-      const bool h = have;
-      const uint32_t p = cur_pos + 4 * lane;
-      vst[u] = cur_st;
-      vg[u] = cur_g;
-      vp[u] = p;
-      vend[u] = h ? cur_end : 0u;
-      v[u] = *reinterpret_cast<const uint4*>(adj + ((h && p < cur_end) ? p : 0u));
-      if (h) {
-        cur_pos += kChunk;
-        if (cur_pos >= cur_end) have = false;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t idx = vp[u] + q;
-        f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
-      }
-    }
-  }
-  for (uint32_t done = 0; done < total; done += kGather) {
-    const bool more = done + kGather < total;
-    Staged nxt;
-    if (more) stage_round(nxt, marks, excl, slen, base, tag, total, done + kGather, adj);
-#pragma unroll
-    for (int u = 0; u < kStageU; ++u) f.add(cur.e[u], cur.tag[u], cur.valid[u]);
-    if (!more) break;
-    cur = nxt;
-  }
-}
-
-template <int U, bool kTagged = false, class M, class F>
-__device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
-                                           const uint32_t* __restrict__ adj, M marks,
-                                           uint32_t long_len, F&& f) {
-  walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
-}
-
-// Walk every run of an item with one wavefront; the first batch of 64 runs
-// was loaded beforehand (first).
-template <int U, bool kTagged = false, class M, class F>
-__device__ __forceinline__ void walk_item(const Item& it, SegReg first, const Segment* __restrict__ segs,
-                                          const uint32_t* __restrict__ adj, M marks,
-                                          uint32_t long_len, F&& f) {
-  const uint32_t seg_end = it.seg_begin + it.seg_count;
-  walk_regs<U>(first, adj, marks, long_len, f);
-  for (uint32_t k0 = it.seg_begin + kWave; k0 < seg_end; k0 += kWave) {
-    const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-    walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
-  }
-}
-
-template <bool kTagged = false>
-__device__ __forceinline__ SegReg first_batch(const Item& it, const Segment* __restrict__ segs) {
-  const uint32_t seg_end = it.seg_begin + it.seg_count;
-  return load_seg<kTagged>(segs, it.seg_begin,
-                           it.seg_begin + kWave < seg_end ? it.seg_begin + kWave : seg_end);
-}
-
-// Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric.
-__device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
-  return ((e ^ g) & 1u) ? 0x10000u : 1u;
-}
-
-// Tally functors for walk_regs: add(entry, g, valid) counts a valid
-// entry's wedge in the counter of its key (a non-returning LDS atomic, so a
-// wavefront never waits on its own counter updates).
-struct DirectTally {  // 16 | 16-bit counters, one 32-bit word per key
-  uint32_t* cnt;
-  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    if (valid) atomicAdd(&cnt[e >> 1], wedge_inc(e, g));
-  }
-};
-
-struct PairTally {  // 8 | 8-bit counters, two keys per 32-bit word
-  uint32_t* cnt;
-  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    // the entry's low bits select the byte: bit 0 (negative) ^ g picks the
-    // symmetric / asymmetric byte, bit 1 (key parity) the 16-bit half
-    if (valid) atomicAdd(&cnt[e >> 2], 1u << (((e ^ (g & 1u)) & 3u) << 3));
-  }
-};
-
-// Hash tallies do all their work in add (a probe loop).
-template <class G>
-struct HashTally {
-  G g;
-  __device__ __forceinline__ void add(uint32_t e, uint32_t gb, bool valid) const {
-    if (valid) g(e, gb);
-  }
-};
-template <class G>
-__device__ __forceinline__ HashTally<G> hash_tally(G g) {
-  return HashTally<G>{g};
-}
-
-struct Sums {
-  int64_t bal = 0, unb = 0, tot = 0;
-  __device__ __forceinline__ void add(uint32_t p, uint32_t n) {
-    const int64_t P = p, N = n;
-    bal += P * (P - 1) / 2 + N * (N - 1) / 2;
-    unb += P * N;
-    tot += (P + N) * (P + N - 1) / 2;
-  }
-};
-
-// The sums of a wavefront (or workgroup) belong to one graph at a time:
-// items of a graph are contiguous in every list, and the running sums are
-// flushed to the graph's result slot when an item of another graph comes.
-constexpr uint32_t kNoGraph = 0xffffffffu;
-
-__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
-}
-
-// Add the wavefront's sums to a graph's results (one atomic per wavefront
-// and value).
-__device__ __forceinline__ void flush_sums(const Sums& s, unsigned long long* res) {
-  const int64_t b = wave_sum64(s.bal), u = wave_sum64(s.unb), t = wave_sum64(s.tot);
-  if (lane_id() == 0) {
-    if (b) atomicAdd(res + kResBalanced, static_cast<unsigned long long>(b));
-    if (u) atomicAdd(res + kResUnbalanced, static_cast<unsigned long long>(u));
-    if (t) atomicAdd(res + kResTotal, static_cast<unsigned long long>(t));
-  }
-}
-
-// Final fate of one pair count of an item.
-__device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, uint32_t n,
-                                     const DevSideConst& sc, Sums& s) {
-  if ((it.flags & kItemHubPairs) && static_cast<int32_t>(key) < sc.T) {
-    sc.hub_pairs[static_cast<size_t>(it.owner) * sc.T + key] =
-        (static_cast<unsigned long long>(n) << 32) | p;
-  } else {
-    s.add(p, n);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Window items: one workgroup per item (or item part), counters for keys
@@ -411,45 +100,6 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
-
-// Per-key sums of squares: with W the wedges of the swept keys (sum of
-// p + n), sum C(p,2) + C(n,2) = (sum p^2 + n^2 - W) / 2 and the unbalanced
-// sum is sum p * n.  24-bit multiply-adds on 32-bit per-item accumulators:
-// the callers bound p and n so that an item's sums stay below 2^32.
-struct SqSums {
-  uint32_t sq = 0, pn = 0, w = 0;
-  __device__ __forceinline__ void add(uint32_t p, uint32_t n) {
-    sq += __umul24(p, p);
-    sq += __umul24(n, n);
-    pn += __umul24(p, n);
-    w += p + n;
-  }
-  __device__ __forceinline__ void add_word(uint32_t c2) {  // two 8|8-bit keys
-    add(c2 & 0xffu, (c2 >> 8) & 0xffu);
-    add((c2 >> 16) & 0xffu, c2 >> 24);
-  }
-};
-
-// Running per-lane totals of SqSums, flushed once per wavefront.
-struct SqTotals {
-  uint64_t sq = 0, pn = 0, w = 0;
-  __device__ __forceinline__ void add(const SqSums& s) {
-    sq += s.sq;
-    pn += s.pn;
-    w += s.w;
-  }
-  __device__ __forceinline__ void flush(unsigned long long* res) const {
-    const int64_t q = wave_sum64(static_cast<int64_t>(sq));
-    const int64_t x = wave_sum64(static_cast<int64_t>(pn));
-    const int64_t ww = wave_sum64(static_cast<int64_t>(w));
-    if (lane_id() == 0) {
-      const int64_t bal = (q - ww) / 2;
-      if (bal) atomicAdd(res + kResBalanced, static_cast<unsigned long long>(bal));
-      if (x) atomicAdd(res + kResUnbalanced, static_cast<unsigned long long>(x));
-      if (bal + x) atomicAdd(res + kResTotal, static_cast<unsigned long long>(bal + x));
-    }
-  }
-};
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kReverseWaves][kReverseWords];
@@ -530,15 +180,6 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
 constexpr int kSmallThreads = 256;
 constexpr int kSmallWaves = kSmallThreads / kWave;
 constexpr int kSmallSlots = 2 * kSmallGroupWork;
-
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {
-  x ^= x >> 16;
-  x *= 0x7feb352du;
-  x ^= x >> 15;
-  x *= 0x846ca68bu;
-  x ^= x >> 16;
-  return x;
-}
 
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   __shared__ uint32_t keys[kSmallWaves][kSmallSlots];

@@ -104,15 +104,20 @@ struct PlanParams {
   int32_t reverse_L = 0;
   int32_t small_work = 0;
   int32_t part_work = 0;
+  bool per_vertex = false;  // plan for the per-vertex pass (no dense block, no parts)
   bool operator==(const PlanParams& o) const {
     return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
-           small_work == o.small_work && part_work == o.part_work;
+           small_work == o.small_work && part_work == o.part_work && per_vertex == o.per_vertex;
   }
 };
 
 // Largest reverse window: keys of a reverse item index a per-wavefront LDS
 // array of this many counters.
 constexpr int32_t kMaxReverseL = 4096;
+
+// Key window of a direct item of the per-vertex pass (32-bit counters in
+// LDS); wider windows are split into items that share their runs.
+constexpr int32_t kPVWindow = 8192;
 
 struct HostPlan {
   PlanParams p;
@@ -123,6 +128,10 @@ struct HostPlan {
   std::vector<Item> small_items;   // items counted with per-wavefront hash counters
   std::vector<Item> small_groups;  // ... packed into groups (segments in small_segs)
   std::vector<Segment> small_segs; // tagged segments of the groups
+  // per-vertex plans only: the mid (row) of every run, and the owner of
+  // every item of every group (a group's owners start at its acc_slot)
+  std::vector<uint32_t> seg_mid, small_seg_mid;
+  std::vector<int32_t> small_owner;
   int32_t key_bits[2] = {1, 1};    // per side: bits of a side rank in a group hash key
   std::vector<Item> direct_items;  // workgroup direct arrays over [0, L)
   std::vector<Item> hash_items;    // workgroup hash counters, large tail pivots

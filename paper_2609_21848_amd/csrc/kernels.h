@@ -39,6 +39,16 @@ struct DevSideConst {
   int32_t R;                     // reverse window of side s
   int32_t key_bits;              // bits of a side-s rank in a small-group hash key
   int32_t acc_width;             // words per accumulator slot
+  // per-vertex pass only
+  const uint32_t* seg_mid;        // mid (other-side rank) of every run of segs
+  const uint32_t* small_seg_mid;  // ... of every run of small_segs
+  const int32_t* small_owner;     // owners of the items of the groups (from acc_slot)
+  const int32_t* orig;            // side-s rank -> input id
+  const int32_t* orig_mid;        // other-side rank -> input id
+  unsigned long long* bal;        // per-vertex outputs of side s (input id order)
+  unsigned long long* unb;
+  unsigned long long* bal_mid;    // ... of the other side
+  unsigned long long* unb_mid;
 };
 
 struct DirectArgs {
@@ -105,6 +115,12 @@ hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st);
 hipError_t launch_hub(const HubArgs& a, hipStream_t st);
+// Per-vertex pass (plans made with per_vertex): direct items, reverse items,
+// small-item groups and hash items.
+hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st);
+hipError_t launch_pv_reverse(const SmallArgs& a, int grid, hipStream_t st);
+hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st);
+hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st);
 // Copy k graphs' item lists (or reduce lists) into one list, setting each
 // entry's graph field.
 hipError_t launch_assemble_items(const AssembleSrc* srcs, int k, Item* dst, hipStream_t st);

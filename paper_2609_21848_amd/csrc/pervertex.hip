@@ -1,0 +1,557 @@
+// HIP kernels (gfx950) of the per-vertex pass: for every vertex, the number
+// of balanced and unbalanced butterflies that contain it (the vertex measure
+// of Section I's applications).
+//
+// Each butterfly is counted once, at the pair (x, w) that owns it under the
+// vertex priority (Algorithm 1, Phase 5): x and w are its two same-side
+// vertices and its two mids are wedge mids of the pair.  With the pair's
+// symmetric and asymmetric wedge counts p and n (Lemma 1):
+//   - x and w each lie in C(p,2) + C(n,2) balanced and p n unbalanced
+//     butterflies of the pair;
+//   - the mid of a symmetric wedge lies in p - 1 balanced ones (paired with
+//     each other symmetric mid) and n unbalanced ones, the mid of an
+//     asymmetric wedge in n - 1 balanced and p unbalanced ones.
+// So every item is walked twice: a tally of p and n per key as in the count
+// pass, then a credit walk that reads each wedge's final p and n and adds
+// the mid's share; the sweep credits the key vertices and, summed, the
+// item's owner.  The plan of this pass has no dense block and no multi-part
+// items, so every pair's counts are complete inside one item.
+//
+// Mid credits are summed per run (a run has one mid) in registers, then per
+// batch in a per-wavefront LDS slot of the run's lane, and reach HBM as one
+// 64-bit atomic per run; key and owner credits are one atomic per nonzero
+// pair and per item.  Walk tags here are (item index in group << 7) |
+// (run lane << 1) | g.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "kernels.h"
+#include "walk.h"
+
+namespace dbbc {
+namespace dev {
+
+// The runs k0 .. k1 - 1 of a batch with per-vertex tags, and each lane's mid.
+template <bool kTagged>
+__device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
+                                              const uint32_t* __restrict__ mids, uint32_t k0, uint32_t k1,
+                                              uint32_t& mid) {
+  SegReg r = load_seg<kTagged>(segs, k0, k1);
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+  const uint32_t g = r.tag & 1u;
+  r.tag = kTagged ? (((r.tag >> 1) << 7) | (lane << 1) | g) : ((lane << 1) | g);
+  mid = k0 + lane < k1 ? mids[k0 + lane] : 0u;
+  return r;
+}
+
+// Credit walk: Look(e, tag, p, n) gives the pair counts of a wedge's key
+// (false: the key is not counted by this item or pass).  Credits of the
+// lane's current run are kept in registers and added to the run's LDS slot
+// when the lane moves to another run.
+template <class Look>
+struct Credit {
+  Look look;
+  unsigned long long* cb;  // per-wavefront LDS: balanced credit per run lane
+  unsigned long long* cu;  // unbalanced
+  uint32_t cur = 0xffffffffu;
+  unsigned long long sb = 0, su = 0;
+  __device__ __forceinline__ void put() {
+    if (cur != 0xffffffffu) {
+      if (sb) atomicAdd(&cb[cur], sb);
+      if (su) atomicAdd(&cu[cur], su);
+    }
+    sb = su = 0;
+  }
+  __device__ __forceinline__ void add(uint32_t e, uint32_t tag, bool valid) {
+    uint32_t p, n;
+    if (!valid || !look(e, tag, p, n)) return;
+    const uint32_t j = (tag >> 1) & 63u;
+    if (j != cur) {
+      put();
+      cur = j;
+    }
+    if (((e ^ tag) & 1u) == 0) {  // symmetric wedge
+      sb += p - 1u;
+      su += n;
+    } else {
+      sb += n - 1u;
+      su += p;
+    }
+  }
+  __device__ __forceinline__ void flush() {
+    put();
+    cur = 0xffffffffu;
+  }
+};
+
+template <class Look>
+__device__ __forceinline__ Credit<Look> credit(Look l, unsigned long long* cb, unsigned long long* cu) {
+  Credit<Look> c{l, cb, cu};
+  return c;
+}
+
+// After a batch's credit walk: each lane adds its run's credits to the mid.
+__device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsigned long long* cu, uint32_t mid,
+                                                  const DevSideConst& sc) {
+  wave_sync_lds();
+  const int lane = lane_id();
+  const unsigned long long b = cb[lane], u = cu[lane];
+  if (b | u) {
+    cb[lane] = 0;
+    cu[lane] = 0;
+    const int32_t id = sc.orig_mid[mid];
+    if (b) atomicAdd(&sc.bal_mid[id], b);
+    if (u) atomicAdd(&sc.unb_mid[id], u);
+  }
+  wave_sync_lds();
+}
+
+// Key credits of one pair (p, n) at key vertex `key` of side s.
+struct PairCredit {
+  int64_t c = 0, x = 0;  // owner sums
+  __device__ __forceinline__ void add(const DevSideConst& sc, uint32_t key, uint32_t p, uint32_t n, Sums& s) {
+    s.add(p, n);
+    const int64_t P = p, N = n;
+    const int64_t cb = P * (P - 1) / 2 + N * (N - 1) / 2, cx = P * N;
+    if (cb) atomicAdd(&sc.bal[sc.orig[key]], static_cast<unsigned long long>(cb));
+    if (cx) atomicAdd(&sc.unb[sc.orig[key]], static_cast<unsigned long long>(cx));
+    c += cb;
+    x += cx;
+  }
+  // The wavefront's owner sums to `owner` (one atomic per wavefront).
+  __device__ __forceinline__ void to_owner(const DevSideConst& sc, int32_t owner) {
+    const int64_t c2 = wave_sum64(c), x2 = wave_sum64(x);
+    if (lane_id() == 0) {
+      if (c2) atomicAdd(&sc.bal[sc.orig[owner]], static_cast<unsigned long long>(c2));
+      if (x2) atomicAdd(&sc.unb[sc.orig[owner]], static_cast<unsigned long long>(x2));
+    }
+    c = x = 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Direct items: one workgroup per item, 32-bit p and n counters over the
+// item's key window (at most kPVWindow keys; windows of one pivot share
+// their runs and skip the keys of the others).
+constexpr int kPVDirectThreads = 1024;
+constexpr int kPVDirectWaves = kPVDirectThreads / kWave;
+
+__global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
+  __shared__ uint32_t P[kPVWindow], N[kPVWindow];
+  __shared__ uint32_t mbase[kPVDirectWaves][kGather];
+  __shared__ uint32_t mtag[kPVDirectWaves][kGather];
+  __shared__ unsigned long long cb[kPVDirectWaves][kWave], cu[kPVDirectWaves][kWave];
+  __shared__ int32_t item_sh;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = lane_id();
+  for (int i = tid; i < kPVWindow; i += kPVDirectThreads) P[i] = N[i] = 0;
+  for (int i = tid; i < kPVDirectWaves * static_cast<int>(kGather); i += kPVDirectThreads) (&mtag[0][0])[i] = 0;
+  cb[wave][lane] = 0;
+  cu[wave][lane] = 0;
+  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  Sums sums;
+  uint32_t graph = kNoGraph;
+  for (;;) {
+    if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
+    __syncthreads();
+    const int32_t i = item_sh;
+    if (i >= a.n_items) break;
+    const Item it = a.items[i];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const uint32_t lo = static_cast<uint32_t>(it.key_lo), hi = static_cast<uint32_t>(it.key_hi);
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    // tally
+    for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      uint32_t mid;
+      const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
+      walk_regs<4>(sr, sc.other_adj, mk, a.long_len,
+                   hash_tally([&](uint32_t e, uint32_t tag) {
+                     const uint32_t key = e >> 1;
+                     if (key >= lo && key < hi) atomicAdd(((e ^ tag) & 1u) ? &N[key - lo] : &P[key - lo], 1u);
+                   }));
+    }
+    __syncthreads();
+    // credit the mids
+    for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      uint32_t mid;
+      const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
+      auto c = credit(
+          [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
+            const uint32_t key = e >> 1;
+            if (key < lo || key >= hi) return false;
+            p = P[key - lo];
+            n = N[key - lo];
+            return true;
+          },
+          cb[wave], cu[wave]);
+      walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+      c.flush();
+      flush_mid_credits(cb[wave], cu[wave], mid, sc);
+    }
+    __syncthreads();
+    // credit the keys and the owner
+    PairCredit pc;
+    for (uint32_t k = tid; k < hi - lo; k += kPVDirectThreads) {
+      const uint32_t p = P[k], n = N[k];
+      if (p | n) {
+        P[k] = N[k] = 0;
+        pc.add(sc, lo + k, p, n, sums);
+      }
+    }
+    pc.to_owner(sc, it.owner);
+    __syncthreads();
+  }
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse items (at most kReverseMaxSegs runs): one wavefront per item, 8-bit
+// p and n per key over the reverse window, two keys per 32-bit word.
+constexpr int kPVReverseThreads = 768;
+constexpr int kPVReverseWaves = kPVReverseThreads / kWave;
+constexpr int kPVReverseWords = kMaxReverseL / 2;
+
+__global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
+  __shared__ uint32_t cnt[kPVReverseWaves][kPVReverseWords];
+  __shared__ uint32_t mbase[kPVReverseWaves][kGather];
+  __shared__ uint32_t mtag[kPVReverseWaves][kGather];
+  __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  uint32_t* C = cnt[wave];
+  for (int i = lane; i < kPVReverseWords; i += kWave) C[i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
+  cb[wave][lane] = 0;
+  cu[wave][lane] = 0;
+  wave_sync_lds();
+  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  Sums sums;
+  uint32_t graph = kNoGraph;
+  const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVReverseWaves;
+  for (int32_t i = static_cast<int32_t>(blockIdx.x) * kPVReverseWaves + wave; i < a.n_items; i += stride) {
+    const Item it = a.items[i];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      uint32_t mid;
+      walk_regs<8>(load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid), sc.other_adj, mk, a.long_len,
+                   PairTally{C});
+    }
+    wave_sync_lds();
+    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      uint32_t mid;
+      const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
+      auto c = credit(
+          [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
+            const uint32_t key = e >> 1;
+            const uint32_t h = C[key >> 1] >> ((key & 1u) << 4);
+            p = h & 0xffu;
+            n = (h >> 8) & 0xffu;
+            return true;
+          },
+          cb[wave], cu[wave]);
+      walk_regs<8>(sr, sc.other_adj, mk, a.long_len, c);
+      c.flush();
+      flush_mid_credits(cb[wave], cu[wave], mid, sc);
+    }
+    PairCredit pc;
+    const int32_t w_hi = (it.key_hi + 1) >> 1;
+    for (int32_t wd = lane; wd < w_hi; wd += kWave) {
+      const uint32_t c2 = C[wd];
+      if (!c2) continue;
+      C[wd] = 0;
+      if (c2 & 0xffffu) pc.add(sc, 2 * wd, c2 & 0xffu, (c2 >> 8) & 0xffu, sums);
+      if (c2 >> 16) pc.add(sc, 2 * wd + 1, (c2 >> 16) & 0xffu, c2 >> 24, sums);
+    }
+    pc.to_owner(sc, it.owner);
+    wave_sync_lds();
+  }
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+}
+
+// ---------------------------------------------------------------------------
+// Small-item groups: one wavefront per group, the group hash of the count
+// pass; owners come from the group's owner list.
+constexpr int kPVSmallThreads = 256;
+constexpr int kPVSmallWaves = kPVSmallThreads / kWave;
+constexpr int kPVSmallSlots = 2 * kSmallGroupWork;
+
+__global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
+  __shared__ uint32_t keys[kPVSmallWaves][kPVSmallSlots];
+  __shared__ uint32_t vals[kPVSmallWaves][kPVSmallSlots];
+  __shared__ uint32_t mbase[kPVSmallWaves][kGather];
+  __shared__ uint32_t mtag[kPVSmallWaves][kGather];
+  __shared__ unsigned long long cb[kPVSmallWaves][kWave], cu[kPVSmallWaves][kWave];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  uint32_t* K = keys[wave];
+  uint32_t* V = vals[wave];
+  for (int i = lane; i < kPVSmallSlots; i += kWave) {
+    K[i] = kEmpty;
+    V[i] = 0;
+  }
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
+  cb[wave][lane] = 0;
+  cu[wave][lane] = 0;
+  wave_sync_lds();
+  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  Sums sums;
+  uint32_t graph = kNoGraph;
+  const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVSmallWaves;
+  for (int32_t i = static_cast<int32_t>(blockIdx.x) * kPVSmallWaves + wave; i < a.n_items; i += stride) {
+    const Item it = a.items[i];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const uint32_t kb = static_cast<uint32_t>(sc.key_bits);
+    uint32_t size = 64;
+    while (size < 2 * it.work) size <<= 1;
+    const uint32_t mask = size - 1;
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    auto hkey = [&](uint32_t e, uint32_t tag) { return ((tag >> 7) << kb) | (e >> 1); };
+    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      uint32_t mid;
+      walk_regs<4>(load_seg_pv<true>(sc.small_segs, sc.small_seg_mid, k0, k1, mid), sc.other_adj, mk,
+                   a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
+                     const uint32_t key = hkey(e, tag);
+                     const uint32_t inc = ((e ^ tag) & 1u) ? 0x10000u : 1u;
+                     uint32_t h = mix32(key) & mask;
+                     for (uint32_t probe = 0;; ++probe) {
+                       if (probe > mask) {  // full table: cannot happen at load <= 1/2
+                         atomicOr(a.err, kErrHashFull);
+                         break;
+                       }
+                       uint32_t c = K[h];
+                       if (c == kEmpty) {
+                         c = atomicCAS(&K[h], kEmpty, key);
+                         if (c == kEmpty) c = key;
+                       }
+                       if (c == key) {
+                         atomicAdd(&V[h], inc);
+                         break;
+                       }
+                       h = (h + 1) & mask;
+                     }
+                   }));
+    }
+    wave_sync_lds();
+    for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
+      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+      uint32_t mid;
+      const SegReg sr = load_seg_pv<true>(sc.small_segs, sc.small_seg_mid, k0, k1, mid);
+      auto c = credit(
+          [&](uint32_t e, uint32_t tag, uint32_t& p, uint32_t& n) {
+            const uint32_t key = hkey(e, tag);
+            uint32_t h = mix32(key) & mask;
+            for (uint32_t probe = 0; probe <= mask; ++probe) {
+              if (K[h] == key) {
+                const uint32_t v = V[h];
+                p = v & 0xffffu;
+                n = v >> 16;
+                return true;
+              }
+              h = (h + 1) & mask;
+            }
+            atomicOr(a.err, kErrHashFull);  // a tallied key must be there
+            return false;
+          },
+          cb[wave], cu[wave]);
+      walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+      c.flush();
+      flush_mid_credits(cb[wave], cu[wave], mid, sc);
+    }
+    const uint32_t kmask = (1u << kb) - 1u;
+    for (uint32_t h = lane; h < size; h += kWave) {
+      const uint32_t key = K[h];
+      if (key == kEmpty) continue;
+      const uint32_t v = V[h];
+      K[h] = kEmpty;
+      V[h] = 0;
+      PairCredit pc;
+      pc.add(sc, key & kmask, v & 0xffffu, v >> 16, sums);
+      const int32_t owner = sc.small_owner[it.acc_slot + static_cast<int32_t>(key >> kb)];
+      if (pc.c) atomicAdd(&sc.bal[sc.orig[owner]], static_cast<unsigned long long>(pc.c));
+      if (pc.x) atomicAdd(&sc.unb[sc.orig[owner]], static_cast<unsigned long long>(pc.x));
+    }
+    wave_sync_lds();
+  }
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+}
+
+// ---------------------------------------------------------------------------
+// Hash items (large pivots below the window): one workgroup per item, a
+// shared hash with 32-bit p and n; items with many endpoints are done in
+// passes over a partition of the keys, each pass tallying, crediting and
+// sweeping its keys.
+constexpr int kPVHashThreads = 512;
+constexpr int kPVHashWaves = kPVHashThreads / kWave;
+constexpr int kPVHashSlots = 8192;
+
+__global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
+  __shared__ uint32_t keys[kPVHashSlots];
+  __shared__ unsigned long long vals[kPVHashSlots];
+  __shared__ uint32_t mbase[kPVHashWaves][kGather];
+  __shared__ uint32_t mtag[kPVHashWaves][kGather];
+  __shared__ unsigned long long cb[kPVHashWaves][kWave], cu[kPVHashWaves][kWave];
+  __shared__ int32_t item_sh;
+  __shared__ uint32_t work_sh;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = lane_id();
+  for (int i = tid; i < kPVHashSlots; i += kPVHashThreads) {
+    keys[i] = kEmpty;
+    vals[i] = 0;
+  }
+  for (int i = tid; i < kPVHashWaves * static_cast<int>(kGather); i += kPVHashThreads) (&mtag[0][0])[i] = 0;
+  cb[wave][lane] = 0;
+  cu[wave][lane] = 0;
+  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  Sums sums;
+  uint32_t graph = kNoGraph;
+  for (;;) {
+    if (tid == 0) {
+      item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
+      work_sh = 0;
+    }
+    __syncthreads();
+    const int32_t i = item_sh;
+    if (i >= a.n_items) break;
+    const Item it = a.items[i];
+    if (it.graph != graph) {
+      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+      sums = Sums{};
+      graph = it.graph;
+    }
+    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const uint32_t seg_end = it.seg_begin + it.seg_count;
+    uint32_t w = 0;
+    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kPVHashThreads) w += sc.segs[k].len_g >> 1;
+    atomicAdd(&work_sh, w);
+    __syncthreads();
+    const uint32_t passes = (work_sh + kPVHashSlots / 4 - 1) / (kPVHashSlots / 4);
+    PairCredit pc;
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+      auto mine = [&](uint32_t key, uint32_t& hk) {
+        hk = mix32(key);
+        return passes == 1 || (hk >> 16) % passes == pass;
+      };
+      for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVHashThreads) {
+        const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+        uint32_t mid;
+        walk_regs<4>(load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid), sc.other_adj, mk, a.long_len,
+                     hash_tally([&](uint32_t e, uint32_t tag) {
+                       const uint32_t key = e >> 1;
+                       uint32_t hk;
+                       if (!mine(key, hk)) return;
+                       const unsigned long long inc = ((e ^ tag) & 1u) ? (1ull << 32) : 1ull;
+                       uint32_t h = hk & (kPVHashSlots - 1);
+                       for (uint32_t probe = 0;; ++probe) {
+                         if (probe >= static_cast<uint32_t>(kPVHashSlots)) {
+                           atomicOr(a.err, kErrHashFull);
+                           break;
+                         }
+                         uint32_t c = keys[h];
+                         if (c == kEmpty) {
+                           c = atomicCAS(&keys[h], kEmpty, key);
+                           if (c == kEmpty) c = key;
+                         }
+                         if (c == key) {
+                           atomicAdd(&vals[h], inc);
+                           break;
+                         }
+                         h = (h + 1) & (kPVHashSlots - 1);
+                       }
+                     }));
+      }
+      __syncthreads();
+      for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVHashThreads) {
+        const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+        uint32_t mid;
+        const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
+        auto c = credit(
+            [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
+              const uint32_t key = e >> 1;
+              uint32_t hk;
+              if (!mine(key, hk)) return false;
+              uint32_t h = hk & (kPVHashSlots - 1);
+              for (int probe = 0; probe < kPVHashSlots; ++probe) {
+                if (keys[h] == key) {
+                  const unsigned long long v = vals[h];
+                  p = static_cast<uint32_t>(v);
+                  n = static_cast<uint32_t>(v >> 32);
+                  return true;
+                }
+                h = (h + 1) & (kPVHashSlots - 1);
+              }
+              atomicOr(a.err, kErrHashFull);
+              return false;
+            },
+            cb[wave], cu[wave]);
+        walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+        c.flush();
+        flush_mid_credits(cb[wave], cu[wave], mid, sc);
+      }
+      __syncthreads();
+      for (int h = tid; h < kPVHashSlots; h += kPVHashThreads) {
+        const uint32_t key = keys[h];
+        if (key == kEmpty) continue;
+        const unsigned long long v = vals[h];
+        keys[h] = kEmpty;
+        vals[h] = 0;
+        pc.add(sc, key, static_cast<uint32_t>(v), static_cast<uint32_t>(v >> 32), sums);
+      }
+      __syncthreads();
+    }
+    pc.to_owner(sc, it.owner);
+  }
+  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+}
+
+}  // namespace dev
+
+hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_pv_direct, dim3(grid), dim3(dev::kPVDirectThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pv_reverse(const SmallArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_pv_reverse, dim3(grid), dim3(dev::kPVReverseThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_pv_small, dim3(grid), dim3(dev::kPVSmallThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_pv_hash, dim3(grid), dim3(dev::kPVHashThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace dbbc

@@ -102,7 +102,7 @@ void pack_small_groups(const HostGraph& g, HostPlan& plan) {
       grp = Item{};
       grp.seg_begin = static_cast<uint32_t>(plan.small_segs.size());
       grp.owner = it.owner;
-      grp.acc_slot = -1;
+      grp.acc_slot = plan.p.per_vertex ? static_cast<int32_t>(plan.small_owner.size()) : -1;
       grp.flags = it.flags & kItemHubPairs;
       grp.side = it.side;
       local = 0;
@@ -111,7 +111,9 @@ void pack_small_groups(const HostGraph& g, HostPlan& plan) {
     for (uint32_t k = 0; k < it.seg_count; ++k) {
       const Segment sg = plan.segs[it.seg_begin + k];
       plan.small_segs.push_back(Segment{sg.start, (local << 16) | sg.len_g});
+      if (plan.p.per_vertex) plan.small_seg_mid.push_back(plan.seg_mid[it.seg_begin + k]);
     }
+    if (plan.p.per_vertex) plan.small_owner.push_back(it.owner);
     grp.work += it.work;
     ++local;
   }
@@ -119,19 +121,36 @@ void pack_small_groups(const HostGraph& g, HostPlan& plan) {
 }
 
 // Drop the segments of the small items (copied into the groups) from segs.
+// Consecutive items with the same runs (key windows of one item) keep
+// sharing them.
 void compact_segments(HostPlan& plan) {
+  const bool pv = plan.p.per_vertex;
   std::vector<Segment> out;
+  std::vector<uint32_t> out_mid;
   size_t n = 0;
   for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
     for (const Item& it : *v) n += it.seg_count;
   out.reserve(n);
-  for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
+  if (pv) out_mid.reserve(n);
+  for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items}) {
+    uint32_t last_begin = 0xffffffffu, last_count = 0, last_new = 0;
     for (Item& it : *v) {
-      const uint32_t b = static_cast<uint32_t>(out.size());
+      if (it.seg_begin == last_begin && it.seg_count == last_count) {
+        it.seg_begin = last_new;
+        continue;
+      }
+      last_begin = it.seg_begin;
+      last_count = it.seg_count;
+      last_new = static_cast<uint32_t>(out.size());
       out.insert(out.end(), plan.segs.begin() + it.seg_begin, plan.segs.begin() + it.seg_begin + it.seg_count);
-      it.seg_begin = b;
+      if (pv)
+        out_mid.insert(out_mid.end(), plan.seg_mid.begin() + it.seg_begin,
+                       plan.seg_mid.begin() + it.seg_begin + it.seg_count);
+      it.seg_begin = last_new;
     }
+  }
   plan.segs = std::move(out);
+  plan.seg_mid = std::move(out_mid);
 }
 
 }  // namespace
@@ -161,11 +180,12 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   }
   plan = HostPlan();
   plan.p = p;
+  const bool pv = p.per_vertex;
   for (int s = 0; s < 2; ++s) {
     plan.L[s] = std::min<int32_t>(p.window_L, g.side[s].n);
     plan.R[s] = std::min<int32_t>(p.reverse_L, plan.L[s]);
-    // the dense block is tiled by 128 rows
-    plan.T[s] = std::min<int32_t>(p.hub_T, g.side[s].n / 128 * 128);
+    // the dense block is tiled by 128 rows; the per-vertex pass has none
+    plan.T[s] = pv ? 0 : std::min<int32_t>(p.hub_T, g.side[s].n / 128 * 128);
   }
   // The dense path needs a block on both sides of the pair.
   if (plan.T[0] == 0 || plan.T[1] == 0) plan.T[0] = plan.T[1] = 0;
@@ -193,6 +213,13 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       splitT[y] = below(T);
     }
 
+    // A run of entries of row y (the wedges' mid) whose first edge is the
+    // packed entry first (its negative bit is the run's g).
+    auto add_seg = [&](uint32_t start, uint32_t len, uint32_t first) {
+      plan.segs.push_back(Segment{start, (len << 1) | (first & 1u)});
+      if (pv) plan.seg_mid.push_back(first >> 1);
+    };
+
     auto place = [&](uint32_t seg_begin, int32_t owner, int32_t key_lo, int32_t key_hi,
                      uint32_t flags, ItemKind kind) {
       const uint32_t nseg = static_cast<uint32_t>(plan.segs.size() - seg_begin);
@@ -204,6 +231,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       if (nseg == 0 || (nseg < 2 && !(flags & kItemHubPairs))) {
         plan.w_skipped += work;
         plan.segs.resize(seg_begin);
+        if (pv) plan.seg_mid.resize(seg_begin);
         return;
       }
       plan.w_sparse += work;
@@ -217,7 +245,9 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       it.flags = flags;
       it.side = static_cast<uint32_t>(s);
       it.work = static_cast<uint32_t>(std::min<int64_t>(work, 0xffffffffll));
-      if (kind == kReverseTail) {
+      if (kind == kReverseTail && pv && nseg > kReverseMaxSegs) {
+        big_direct.push_back(it);  // per-vertex counts: one direct item
+      } else if (kind == kReverseTail) {
         // parts of at most kReverseMaxSegs segments (8-bit counters)
         if (nseg <= kReverseMaxSegs) {
           plan.reverse_items.push_back(it);
@@ -264,7 +294,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           if (hub && static_cast<int32_t>(y) < TO)
             start = std::max(start, O.off[y] + static_cast<uint32_t>(splitT[y]));
           if (end > start)
-            plan.segs.push_back(Segment{start, ((end - start) << 1) | (S.adj[e] & 1u)});
+            add_seg(start, end - start, S.adj[e]);
         }
         place(seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
       }
@@ -275,7 +305,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           const uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
           const uint32_t end = O.off[y + 1];
           if (end > start)
-            plan.segs.push_back(Segment{start, ((end - start) << 1) | (S.adj[e] & 1u)});
+            add_seg(start, end - start, S.adj[e]);
         }
         place(seg_begin, x, x + 1, S.n, 0u, kForwardTail);
       }
@@ -289,7 +319,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         const uint32_t y = S.adj[e] >> 1;
         const int32_t len = std::min(splitR[y], O.cut[y]);
         if (len > 0)
-          plan.segs.push_back(Segment{O.off[y], (static_cast<uint32_t>(len) << 1) | (S.adj[e] & 1u)});
+          add_seg(O.off[y], static_cast<uint32_t>(len), S.adj[e]);
       }
       place(seg_begin, w, 0, R, 0u, kReverseTail);
       if (R == L) continue;
@@ -298,8 +328,8 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         const uint32_t y = S.adj[e] >> 1;
         const int32_t end = std::min(splitL[y], O.cut[y]);
         if (end > splitR[y])
-          plan.segs.push_back(Segment{O.off[y] + static_cast<uint32_t>(splitR[y]),
-                                      (static_cast<uint32_t>(end - splitR[y]) << 1) | (S.adj[e] & 1u)});
+          add_seg(O.off[y] + static_cast<uint32_t>(splitR[y]), static_cast<uint32_t>(end - splitR[y]),
+                  S.adj[e]);
       }
       place(seg_begin, w, R, L, 0u, kReverseMid);
     }
@@ -334,6 +364,15 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   std::vector<Item> parts, singles;
   for (auto& [work, i] : order) {
     const Item& it = big_direct[i];
+    if (pv) {  // whole items, key windows of at most kPVWindow keys
+      for (int32_t lo = it.key_lo; lo < it.key_hi; lo += kPVWindow) {
+        Item w = it;
+        w.key_lo = lo;
+        w.key_hi = std::min(it.key_hi, lo + kPVWindow);
+        singles.push_back(w);
+      }
+      continue;
+    }
     if (work <= p.part_work && it.seg_count < 65536) {
       singles.push_back(it);
       continue;

@@ -1,6 +1,7 @@
 // Test harness (CPU only): builds the library's host graph and counting plan
 // and walks every planned item the way the kernels do, in plain loops, so the
 // split of the vertex-priority wedges into items can be checked on the CPU.
+#include <climits>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -179,5 +180,103 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
   out[10] = (int64_t)plan.hash_items.size();
   out[11] = (int64_t)plan.reduces.size();
   out[12] = (int64_t)plan.reverse_items.size();
+  return 0;
+}
+
+// The per-vertex pass as the kernels take it: every item of the per-vertex
+// plan (no dense block, no parts) is tallied, then its wedges are walked
+// again to credit each mid with p - 1 (symmetric wedge) or n - 1 balanced
+// and n or p unbalanced butterflies of the pair, and each pair's
+// C(p,2) + C(n,2) and p n go to its key vertex and, summed, to the owner.
+// Outputs are per input id: bal / unb of size n_u + n_v (U first).
+extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
+                               const int8_t* sign, int32_t window_L, int32_t reverse_L, int32_t small_work,
+                               int64_t* bal, int64_t* unb, int64_t* out /* 4 */) {
+  HostGraph g;
+  std::string err;
+  int rc = build_host_graph(n_u, n_v, m, u, v, sign, 0, g, err);
+  if (rc) return rc;
+  PlanParams p = default_params(g);
+  p.hub_T = 0;
+  if (window_L >= 0) p.window_L = window_L;
+  if (reverse_L >= 0) p.reverse_L = reverse_L;
+  if (small_work >= 0) p.small_work = small_work;
+  p.per_vertex = true;
+  HostPlan plan;
+  rc = make_plan(g, p, plan, err);
+  if (rc) {
+    fprintf(stderr, "make_plan: %s\n", err.c_str());
+    return rc;
+  }
+  if (!plan.reduces.empty() || plan.acc_slots != 0) return -120;  // no parts in this plan
+  if (plan.seg_mid.size() != plan.segs.size() || plan.small_seg_mid.size() != plan.small_segs.size())
+    return -121;
+  const int64_t base[2] = {0, n_u};
+  Acc acc;
+  auto id = [&](int s, uint32_t sr) { return base[s] + g.side[s].orig[sr]; };
+  // one item: runs [b, b + c) of segs / mids, key filter, owner lookup
+  auto run = [&](int side, const Segment* segs, const uint32_t* mids, uint32_t b, uint32_t c, int32_t lo,
+                 int32_t hi, bool tagged, const int32_t* owners, int32_t owner, int32_t maxcnt) -> int {
+    const HostSide& O = g.side[1 - side];
+    std::map<std::pair<uint32_t, uint32_t>, std::pair<int64_t, int64_t>> cnt;  // (local, key)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (uint32_t k = b; k < b + c; ++k) {
+        const Segment sg = segs[k];
+        const uint32_t local = tagged ? sg.len_g >> 16 : 0;
+        const uint32_t len = tagged ? (sg.len_g & 0xffffu) >> 1 : sg.len_g >> 1, gb = sg.len_g & 1u;
+        for (uint32_t t = 0; t < len; ++t) {
+          const uint32_t e = O.adj[sg.start + t];
+          const int32_t key = (int32_t)(e >> 1);
+          if (key < lo || key >= hi) {
+            if (!tagged && lo == 0 && hi == INT32_MAX) return -122;
+            continue;  // another key window of the same runs
+          }
+          const bool sym = ((e ^ gb) & 1u) == 0;
+          auto& pn = cnt[{local, (uint32_t)key}];
+          if (pass == 0) {
+            (sym ? pn.first : pn.second)++;
+          } else {
+            const int64_t mid = id(1 - side, mids[k]);
+            bal[mid] += sym ? pn.first - 1 : pn.second - 1;
+            unb[mid] += sym ? pn.second : pn.first;
+          }
+        }
+      }
+    }
+    std::map<uint32_t, std::pair<int64_t, int64_t>> own;  // per local: owner sums
+    for (auto& [lk, pn] : cnt) {
+      if (pn.first > maxcnt || pn.second > maxcnt) return -123;
+      const int64_t P = pn.first, N = pn.second;
+      const int64_t cb = P * (P - 1) / 2 + N * (N - 1) / 2, cu = P * N;
+      acc.add(P, N);
+      bal[id(side, lk.second)] += cb;
+      unb[id(side, lk.second)] += cu;
+      own[lk.first].first += cb;
+      own[lk.first].second += cu;
+    }
+    for (auto& [local, s] : own) {
+      const int32_t ow = owners ? owners[local] : owner;
+      bal[id(side, (uint32_t)ow)] += s.first;
+      unb[id(side, (uint32_t)ow)] += s.second;
+    }
+    return 0;
+  };
+  for (auto* list : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
+    for (const Item& it : *list) {
+      const int32_t lim = list == &plan.reverse_items ? (int32_t)kReverseMaxSegs : INT32_MAX;
+      if (list == &plan.direct_items && it.key_hi - it.key_lo > kPVWindow) return -124;
+      if ((rc = run(it.side, plan.segs.data(), plan.seg_mid.data(), it.seg_begin, it.seg_count, it.key_lo,
+                    it.key_hi, false, nullptr, it.owner, lim)))
+        return rc;
+    }
+  for (const Item& grp : plan.small_groups) {
+    if ((rc = run(grp.side, plan.small_segs.data(), plan.small_seg_mid.data(), grp.seg_begin, grp.seg_count,
+                  0, INT32_MAX - 1, true, plan.small_owner.data() + grp.acc_slot, 0, 65535)))
+      return rc;
+  }
+  out[0] = acc.bal;
+  out[1] = acc.unb;
+  out[2] = acc.tot;
+  out[3] = g.wedges_vp;
   return 0;
 }

@@ -96,3 +96,64 @@ def test_reverse_items_split_into_parts(emul):
         o = emul(g, *cfg)
         _check(o, r)
         assert o[11] > 0  # multi-part reduces exist
+
+
+@pytest.fixture(scope="module")
+def emul_pv(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("emulpv") / "plan_emul.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", so,
+                           os.path.join(ROOT, "tests", "native", "plan_emul.cpp"),
+                           os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
+    lib = ctypes.CDLL(so)
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.plan_emulate_pv.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, p, p, p]
+
+    def run(g, L=-1, R=-1, sw=-1):
+        n = g.n_u + g.n_v
+        bal = np.zeros(n, np.int64)
+        unb = np.zeros(n, np.int64)
+        out = np.zeros(4, np.int64)
+        if R < 0 and L >= 0:
+            R = min(L, 4096)
+        rc = lib.plan_emulate_pv(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
+                                 g.sign.ctypes.data, L, R, sw, bal.ctypes.data, unb.ctypes.data,
+                                 out.ctypes.data)
+        assert rc == 0, rc
+        return out, bal, unb
+    return run
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_per_vertex_plan_matches_oracle(emul_pv, seed):
+    rng = np.random.default_rng(50 + seed)
+    g = chung_lu_graph(int(rng.integers(300, 2500)), int(rng.integers(300, 2500)),
+                       int(rng.integers(1000, 30000)), 2.0, 1.9, 0.4, seed=seed)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True)
+    want_bal = np.concatenate([r.bal_u, r.bal_v])
+    want_unb = np.concatenate([r.unb_u, r.unb_v])
+    for L, R, sw in [(-1, -1, -1), (256, 64, 2), (512, 512, 64), (1024, 128, 512)]:
+        out, bal, unb = emul_pv(g, L, R, sw)
+        assert (out[0], out[1], out[2]) == (r.balanced, r.unbalanced, r.total)
+        assert np.array_equal(bal, want_bal), (L, R, sw)
+        assert np.array_equal(unb, want_unb), (L, R, sw)
+
+
+def test_per_vertex_plan_dense_graph(emul_pv):
+    # reverse endpoints with more than 255 runs become direct items, and
+    # pivots with wide windows are split into key windows
+    g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True)
+    for L, R in [(256, 64), (512, 256), (-1, -1)]:
+        out, bal, unb = emul_pv(g, L, R)
+        assert np.array_equal(bal, np.concatenate([r.bal_u, r.bal_v]))
+        assert np.array_equal(unb, np.concatenate([r.unb_u, r.unb_v]))
+
+
+def test_per_vertex_plan_key_windows(emul_pv):
+    # sides wider than one key window: direct items split into windows
+    g = chung_lu_graph(20000, 12000, 120000, 2.1, 1.9, 0.4, seed=4)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True)
+    out, bal, unb = emul_pv(g)
+    assert (out[0], out[1], out[2]) == (r.balanced, r.unbalanced, r.total)
+    assert np.array_equal(bal, np.concatenate([r.bal_u, r.bal_v]))
+    assert np.array_equal(unb, np.concatenate([r.unb_u, r.unb_v]))
