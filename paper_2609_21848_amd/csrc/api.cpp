@@ -155,13 +155,14 @@ struct LaunchSet {
   int cus = 0;
 };
 
-// Begin / end one timed launch (no-ops when recs is null).
+// Begin / end one timed launch on stream st (no-ops when recs is null).
 struct Timing {
   std::vector<KernelRec>* recs;
   size_t used = 0;
   hipStream_t st;
-  int begin(const char* name, int64_t wedges, int64_t segs, int64_t items, int64_t macs) {
+  int begin(hipStream_t s, const char* name, int64_t wedges, int64_t segs, int64_t items, int64_t macs) {
     if (!recs) return DBBC_OK;
+    st = s;
     if (used == recs->size()) recs->emplace_back();
     KernelRec& r = (*recs)[used];
     for (auto& e : r.ev)
@@ -189,7 +190,10 @@ struct Timing {
 
 // Enqueue a whole count on stream st.  Every buffer the kernels accumulate
 // into is cleared by a fill kernel first (never a memset node, so that the
-// sequence can be captured into a HIP graph and replayed).
+// sequence can be captured into a HIP graph and replayed).  The kernels run
+// one after the other: the direct and reverse kernels each need most of a
+// CU's LDS, so they cannot share CUs, and running them side by side on
+// several streams was measured slower than in sequence.
 int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
   HIP_TRY(dbbc::launch_fill_u64(L.ctl, kCtlWords, 0ull, st));
   if (L.res != L.ctl) HIP_TRY(dbbc::launch_fill_u64(L.res, L.n_res, 0ull, st));
@@ -206,7 +210,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
     a.err = err;
     a.n_items = L.n[0];
     a.long_len = L.long_len;
-    RC_TRY(tm.begin("direct", L.wedges[0], L.segs[0], a.n_items, 0));
+    RC_TRY(tm.begin(st, "direct", L.wedges[0], L.segs[0], a.n_items, 0));
     HIP_TRY(dbbc::launch_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
     RC_TRY(tm.end());
   }
@@ -218,7 +222,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
     a.err = err;
     a.n_items = L.n[1];
     a.long_len = L.long_len;
-    RC_TRY(tm.begin("reverse", L.wedges[3], L.segs[3], a.n_items, 0));
+    RC_TRY(tm.begin(st, "reverse", L.wedges[3], L.segs[3], a.n_items, 0));
     HIP_TRY(dbbc::launch_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 15) / 16)), st));
     RC_TRY(tm.end());
   }
@@ -230,7 +234,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
     a.err = err;
     a.n_items = L.n[2];
     a.long_len = L.long_len;
-    RC_TRY(tm.begin("small", L.wedges[1], L.segs[1], a.n_items, 0));
+    RC_TRY(tm.begin(st, "small", L.wedges[1], L.segs[1], a.n_items, 0));
     HIP_TRY(dbbc::launch_small(a, std::min<int>(4 * cus, std::max(1, (a.n_items + 3) / 4)), st));
     RC_TRY(tm.end());
   }
@@ -243,7 +247,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
     a.err = err;
     a.n_items = L.n[3];
     a.long_len = L.long_len;
-    RC_TRY(tm.begin("hash", L.wedges[2], L.segs[2], a.n_items, 0));
+    RC_TRY(tm.begin(st, "hash", L.wedges[2], L.segs[2], a.n_items, 0));
     HIP_TRY(dbbc::launch_hash(a, std::min<int>(cus, std::max(1, a.n_items)), st));
     RC_TRY(tm.end());
   }
@@ -254,12 +258,12 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
     a.res = L.res;
     a.err = err;
     a.n_reduces = L.n[4];
-    RC_TRY(tm.begin("reduce", 0, 0, a.n_reduces, 0));
+    RC_TRY(tm.begin(st, "reduce", 0, 0, a.n_reduces, 0));
     HIP_TRY(dbbc::launch_reduce(a, std::min<int>(4 * cus, std::max(1, a.n_reduces)), st));
     RC_TRY(tm.end());
   }
   for (const HubLaunch& h : L.hubs) {
-    RC_TRY(tm.begin(h.name, 0, 0, h.tiles, h.macs));
+    RC_TRY(tm.begin(st, h.name, 0, 0, h.tiles, h.macs));
     HIP_TRY(dbbc::launch_hub(h.a, st));
     RC_TRY(tm.end());
   }

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       uint32_t mid;
-      walk_regs<8>(load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid), sc.other_adj, mk, a.long_len,
+      walk_regs<4>(load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid), sc.other_adj, mk, a.long_len,
                    PairTally{C});
     }
     wave_sync_lds();
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
             return true;
           },
           cb[wave], cu[wave]);
-      walk_regs<8>(sr, sc.other_adj, mk, a.long_len, c);
+      walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits(cb[wave], cu[wave], mid, sc);
     }
