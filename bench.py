@@ -39,7 +39,7 @@ def log(*a):
 
 def src_hash() -> str:
     h = hashlib.sha256()
-    for f in ("count.hip", "hub.hip", "kernels.h"):
+    for f in ("count.hip", "hub.hip", "kernels.h", "walk.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2609_21848_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -49,13 +49,13 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     __syncthreads();
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
-    const Item it = a.items[i];
+    const Item it = load_const(a.items, i);
     if (it.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t* __restrict__ adj = sc.other_adj;
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     __syncthreads();
     if (it.flags & kItemMultiPart) {
       // write the part's counters for the whole key window (zeros included)
-      uint32_t* __restrict__ dst = sc.acc + static_cast<size_t>(it.acc_slot) * sc.acc_width;
+      global_t<uint32_t>* __restrict__ dst = as_global(sc.acc) + static_cast<size_t>(it.acc_slot) * sc.acc_width;
       for (uint32_t key = it.key_lo + tid; key < static_cast<uint32_t>(it.key_hi); key += kDirectThreads) {
         dst[key] = cnt[key];
         cnt[key] = 0;
@@ -105,7 +105,8 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kReverseWaves][kReverseWords];
   __shared__ uint32_t mbase[kReverseWaves][kGather];
   __shared__ uint8_t mtag[kReverseWaves][kGather];
-  const int wave = threadIdx.x / kWave;
+  // wave index, known to the compiler as wavefront-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
   for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
@@ -118,10 +119,10 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   Item cur{}, nxt{};
   SegReg cfirst{0, 0, 0};
   if (i < n) {
-    cur = a.items[i];
-    cfirst = first_batch(cur, a.sides[2 * cur.graph + cur.side].segs);
+    cur = load_const(a.items, i);
+    cfirst = first_batch(cur, load_const(a.sides, 2 * cur.graph + cur.side).segs);
   }
-  if (i + stride < n) nxt = a.items[i + stride];
+  if (i + stride < n) nxt = load_const(a.items, i + stride);
   uint32_t graph = kNoGraph;
   for (; i < n; i += stride) {
     const Item it = cur;
@@ -133,16 +134,16 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
       graph = it.graph;
     }
     SegReg nfirst{0, 0, 0};
-    if (j < n) nfirst = first_batch(nxt, a.sides[2 * nxt.graph + nxt.side].segs);
+    if (j < n) nfirst = first_batch(nxt, load_const(a.sides, 2 * nxt.graph + nxt.side).segs);
     Item nxt2{};
-    if (j2 < n) nxt2 = a.items[j2];
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    if (j2 < n) nxt2 = load_const(a.items, j2);
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     walk_item<8>(it, first, sc.segs, sc.other_adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len,
                  PairTally{C});
     wave_sync_lds();
     const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the item's keys
     if (it.flags & kItemMultiPart) {
-      uint32_t* __restrict__ dst = sc.acc + static_cast<size_t>(it.acc_slot) * sc.acc_width;
+      global_t<uint32_t>* __restrict__ dst = as_global(sc.acc) + static_cast<size_t>(it.acc_slot) * sc.acc_width;
       for (int32_t wd = lane; wd < w_hi; wd += kWave) {
         const uint32_t c2 = C[wd];
         C[wd] = 0;
@@ -185,7 +186,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   __shared__ uint32_t keys[kSmallWaves][kSmallSlots];
   __shared__ uint32_t vals[kSmallWaves][kSmallSlots];
   __shared__ uint32_t marks[kSmallWaves][2][kGather];
-  const int wave = threadIdx.x / kWave;
+  // wave index, known to the compiler as wavefront-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* K = keys[wave];
   uint32_t* Vv = vals[wave];
@@ -201,21 +203,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   Item nxt{};
   SegReg nfirst{0, 0, 0};
   if (i < a.n_items) {
-    nxt = a.items[i];
-    nfirst = first_batch<true>(nxt, a.sides[2 * nxt.graph + nxt.side].small_segs);
+    nxt = load_const(a.items, i);
+    nfirst = first_batch<true>(nxt, load_const(a.sides, 2 * nxt.graph + nxt.side).small_segs);
   }
   uint32_t graph = kNoGraph;
   for (; i < a.n_items; i += stride) {
     const Item it = nxt;
     const SegReg first = nfirst;
     const int32_t j = i + stride;
-    if (j < a.n_items) nxt = a.items[j];
+    if (j < a.n_items) nxt = load_const(a.items, j);
     if (it.graph != graph) {
       if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
       tot = SqTotals{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t kb = static_cast<uint32_t>(sc.key_bits);
     // table size: a power of two >= 2 * work, at least 64
     uint32_t size = 64;
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
                            h = (h + 1) & mask;
                          }
                        }));
-    if (j < a.n_items) nfirst = first_batch<true>(nxt, a.sides[2 * nxt.graph + nxt.side].small_segs);
+    if (j < a.n_items) nfirst = first_batch<true>(nxt, load_const(a.sides, 2 * nxt.graph + nxt.side).small_segs);
     wave_sync_lds();
     // p, n <= kSmallGroupWork per key and sum p + n <= kSmallGroupWork
     // per group, so the group's sums of squares stay below 2^19
@@ -303,16 +305,16 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     __syncthreads();
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
-    const Item it = a.items[i];
+    const Item it = load_const(a.items, i);
     if (it.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     uint32_t w = 0;
-    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kHashThreads) w += sc.segs[k].len_g >> 1;
+    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kHashThreads) w += as_global(&sc.segs[k].len_g)[0] >> 1;
     atomicAdd(&work_sh, w);
     __syncthreads();
     const uint32_t work = work_sh;
@@ -370,20 +372,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
   Sums sums;
   uint32_t graph = kNoGraph;
   for (int32_t r = blockIdx.x; r < a.n_reduces; r += gridDim.x) {
-    const Reduce rd = a.reduces[r];
+    const Reduce rd = load_const(a.reduces, r);
     if (rd.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = rd.graph;
     }
-    const DevSideConst sc = a.sides[2 * rd.graph + rd.side];
+    const DevSideConst sc = load_const(a.sides, 2 * rd.graph + rd.side);
     Item it{};
     it.owner = rd.owner;
     it.flags = rd.flags;
     for (int32_t key = rd.key_lo + threadIdx.x; key < rd.key_hi; key += kReduceThreads) {
       uint32_t p = 0, n = 0;
       for (int32_t j = 0; j < rd.n_parts; ++j) {
-        const uint32_t c = sc.acc[static_cast<size_t>(rd.acc_slot + j) * sc.acc_width + key];
+        const uint32_t c = as_global(sc.acc)[static_cast<size_t>(rd.acc_slot + j) * sc.acc_width + key];
         p += c & 0xffffu;
         n += c >> 16;
       }

@@ -42,7 +42,7 @@ __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
   const uint32_t lane = static_cast<uint32_t>(lane_id());
   const uint32_t g = r.tag & 1u;
   r.tag = kTagged ? (((r.tag >> 1) << 7) | (lane << 1) | g) : ((lane << 1) | g);
-  mid = k0 + lane < k1 ? mids[k0 + lane] : 0u;
+  mid = k0 + lane < k1 ? as_global(mids)[k0 + lane] : 0u;
   return r;
 }
 
@@ -159,13 +159,13 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     __syncthreads();
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
-    const Item it = a.items[i];
+    const Item it = load_const(a.items, i);
     if (it.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t lo = static_cast<uint32_t>(it.key_lo), hi = static_cast<uint32_t>(it.key_hi);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     // tally
@@ -226,7 +226,8 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ uint32_t mbase[kPVReverseWaves][kGather];
   __shared__ uint32_t mtag[kPVReverseWaves][kGather];
   __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
-  const int wave = threadIdx.x / kWave;
+  // wave index, known to the compiler as wavefront-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
   for (int i = lane; i < kPVReverseWords; i += kWave) C[i] = 0;
@@ -239,13 +240,13 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   uint32_t graph = kNoGraph;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVReverseWaves;
   for (int32_t i = static_cast<int32_t>(blockIdx.x) * kPVReverseWaves + wave; i < a.n_items; i += stride) {
-    const Item it = a.items[i];
+    const Item it = load_const(a.items, i);
     if (it.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
@@ -299,7 +300,8 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
   __shared__ uint32_t mbase[kPVSmallWaves][kGather];
   __shared__ uint32_t mtag[kPVSmallWaves][kGather];
   __shared__ unsigned long long cb[kPVSmallWaves][kWave], cu[kPVSmallWaves][kWave];
-  const int wave = threadIdx.x / kWave;
+  // wave index, known to the compiler as wavefront-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* K = keys[wave];
   uint32_t* V = vals[wave];
@@ -316,13 +318,13 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
   uint32_t graph = kNoGraph;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVSmallWaves;
   for (int32_t i = static_cast<int32_t>(blockIdx.x) * kPVSmallWaves + wave; i < a.n_items; i += stride) {
-    const Item it = a.items[i];
+    const Item it = load_const(a.items, i);
     if (it.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t kb = static_cast<uint32_t>(sc.key_bits);
     uint32_t size = 64;
     while (size < 2 * it.work) size <<= 1;
@@ -437,16 +439,16 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
     __syncthreads();
     const int32_t i = item_sh;
     if (i >= a.n_items) break;
-    const Item it = a.items[i];
+    const Item it = load_const(a.items, i);
     if (it.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
       sums = Sums{};
       graph = it.graph;
     }
-    const DevSideConst sc = a.sides[2 * it.graph + it.side];
+    const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     uint32_t w = 0;
-    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kPVHashThreads) w += sc.segs[k].len_g >> 1;
+    for (uint32_t k = it.seg_begin + tid; k < seg_end; k += kPVHashThreads) w += as_global(&sc.segs[k].len_g)[0] >> 1;
     atomicAdd(&work_sh, w);
     __syncthreads();
     const uint32_t passes = (work_sh + kPVHashSlots / 4 - 1) / (kPVHashSlots / 4);

@@ -14,6 +14,42 @@ namespace dbbc {
 namespace dev {
 
 constexpr int kWave = 64;
+
+// Address-space views.  Pointers read from device tables (the per-graph side
+// constants) are generic to the compiler, which would then emit flat
+// accesses; CSR runs, entries and accumulators are global memory, so they
+// are accessed through global (address space 1) views.  Work lists and side
+// tables are never written while a kernel runs, so they are read through
+// constant (address space 4) views, which the compiler turns into scalar
+// loads when the index is uniform.
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+using const_t = __attribute__((address_space(4))) T;
+
+template <class T>
+__device__ __forceinline__ const global_t<T>* as_global(const T* p) {
+  return (const global_t<T>*)p;
+}
+template <class T>
+__device__ __forceinline__ global_t<T>* as_global(T* p) {
+  return (global_t<T>*)p;
+}
+// Element i of a read-only table (work list, side table), through a
+// constant view, word by word (structs cannot be copied out of another
+// address space directly; the words merge into one wide scalar load).
+template <class T>
+__device__ __forceinline__ T load_const(const T* p, size_t i) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  const const_t<uint32_t>* w = (const const_t<uint32_t>*)(p + i);
+  T out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (size_t k = 0; k < sizeof(T) / 4; ++k) o[k] = w[k];
+  return out;
+}
 constexpr uint32_t kChunk = 256;   // entries per wavefront 16-byte load (64 lanes x 4)
 constexpr uint32_t kGather = 256;  // positions per staging round of short runs
 constexpr uint32_t kEmpty = 0xffffffffu;
@@ -65,7 +101,8 @@ __device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uin
   const uint32_t k = k0 + lane_id();
   SegReg r{0, 0, 0};
   if (k < k1) {
-    const Segment s = segs[k];
+    const u32x2 w = *(const global_t<u32x2>*)(segs + k);
+    const Segment s{w.x, w.y};
     r.start = s.start;
     if (kTagged) {
       r.len = (s.len_g & 0xffffu) >> 1;
@@ -140,7 +177,7 @@ __device__ __forceinline__ void stage_round(Staged& s, M mk, uint32_t excl, uint
     s.tag[u] = tg & ~M::kBit;
     const uint32_t t = done + static_cast<uint32_t>(u * kWave + lane);
     s.valid[u] = t < total;
-    s.e[u] = adj[s.valid[u] ? b + t : 0u];
+    s.e[u] = as_global(adj)[s.valid[u] ? b + t : 0u];
   }
 }
 
@@ -168,7 +205,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
   uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
   while (longm || have) {
-    uint4 v[U];
+    u32x4 v[U];
     uint32_t vst[U], vend[U], vg[U], vp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -190,7 +227,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       vg[u] = cur_g;
       vp[u] = p;
       vend[u] = h ? cur_end : 0u;
-      v[u] = *reinterpret_cast<const uint4*>(adj + ((h && p < cur_end) ? p : 0u));
+      v[u] = *(const global_t<u32x4>*)(adj + ((h && p < cur_end) ? p : 0u));
       if (h) {
         cur_pos += kChunk;
         if (cur_pos >= cur_end) have = false;
@@ -318,7 +355,7 @@ __device__ __forceinline__ void flush_sums(const Sums& s, unsigned long long* re
 __device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, uint32_t n,
                                      const DevSideConst& sc, Sums& s) {
   if ((it.flags & kItemHubPairs) && static_cast<int32_t>(key) < sc.T) {
-    sc.hub_pairs[static_cast<size_t>(it.owner) * sc.T + key] =
+    as_global(sc.hub_pairs)[static_cast<size_t>(it.owner) * sc.T + key] =
         (static_cast<unsigned long long>(n) << 32) | p;
   } else {
     s.add(p, n);
