@@ -55,7 +55,8 @@ def traffic_for(config: str, kernel: str, launches_bytes: float):
         p = json.load(f)
     if p.get("src_hash") != src_hash():
         return None
-    return (p["fetch_kib_per_dispatch"] + p["write_kib_per_dispatch"]) * 1024.0 * p["copy_scale"]
+    return (p["fetch_kib_per_dispatch"] * p["fetch_scale"] +
+            p["write_kib_per_dispatch"] * p["write_scale"]) * 1024.0
 
 
 def cpu_baseline(g, fraction: int, threads: int | None):
