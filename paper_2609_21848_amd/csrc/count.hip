@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<4>(sc.segs, k0, k1, adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len, DirectTally{cnt});
+      walk_batch<8>(sc.segs, k0, k1, adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len, DirectTally{cnt});
     }
     __syncthreads();
     if (it.flags & kItemMultiPart) {
@@ -151,7 +151,9 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
         if (2 * wd + 1 < it.key_hi) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
       }
     } else {
-      // p, n <= 255 and at most 2 * kReverseWords / 64 = 64 keys per lane
+      // p, n <= 255 and at most 2 * kReverseWords / 64 = 64 keys per lane;
+      // every key of the item lies in the window, so its swept wedges are
+      // the item's wedges (added once, by lane 0)
       SqSums ss;
       for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&C[wd]);
@@ -162,6 +164,7 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
         ss.add_word(c4.z);
         ss.add_word(c4.w);
       }
+      ss.w = lane == 0 ? it.work : 0u;
       tot.add(ss);
     }
     wave_sync_lds();
