@@ -385,10 +385,23 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
     Item it{};
     it.owner = rd.owner;
     it.flags = rd.flags;
+    const global_t<uint32_t>* acc = as_global(sc.acc) + static_cast<size_t>(rd.acc_slot) * sc.acc_width;
     for (int32_t key = rd.key_lo + threadIdx.x; key < rd.key_hi; key += kReduceThreads) {
       uint32_t p = 0, n = 0;
-      for (int32_t j = 0; j < rd.n_parts; ++j) {
-        const uint32_t c = as_global(sc.acc)[static_cast<size_t>(rd.acc_slot + j) * sc.acc_width + key];
+      // eight independent part loads per step
+      int32_t j = 0;
+      for (; j + 8 <= rd.n_parts; j += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = acc[static_cast<size_t>(j + q) * sc.acc_width + key];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          p += c[q] & 0xffffu;
+          n += c[q] >> 16;
+        }
+      }
+      for (; j < rd.n_parts; ++j) {
+        const uint32_t c = acc[static_cast<size_t>(j) * sc.acc_width + key];
         p += c & 0xffffu;
         n += c >> 16;
       }

@@ -23,10 +23,18 @@ namespace dev {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kHubTile = 128;   // output tile (rows x and columns w)
+constexpr int kHubTile = 128;     // output tile (rows x and columns w)
 constexpr int kHubThreads = 256;  // 2 x 2 wavefronts, each 64 x 64 of the tile
+constexpr int kHubKStep = 64;     // k bytes of both operands staged per step
+constexpr int kHubRow = 80;       // LDS bytes per staged row (64 + 16: spreads banks)
 
-__global__ __launch_bounds__(kHubThreads) void k_hub(HubArgs a) {
+// One 128 x 128 tile of the upper triangle per workgroup.  Each step stages
+// 128 rows x 64 k of Bm (rows x) and of B (rows w) in LDS with coalesced
+// 16-byte loads (4 lanes per row), double-buffered: the next step's loads
+// are in flight while the current step's 16 MFMAs per wavefront run.
+__global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
+  __shared__ __attribute__((aligned(16))) int8_t sA[2][kHubTile * kHubRow];
+  __shared__ __attribute__((aligned(16))) int8_t sB[2][kHubTile * kHubRow];
   // upper-triangular tile (ti <= tj) from the linear block index
   const int nt = a.T / kHubTile;
   int t = blockIdx.x, ti = 0;
@@ -35,8 +43,9 @@ __global__ __launch_bounds__(kHubThreads) void k_hub(HubArgs a) {
     ++ti;
   }
   const int tj = ti + t;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
   const int row0 = ti * kHubTile + (wave >> 1) * 64;
   const int col0 = tj * kHubTile + (wave & 1) * 64;
   const int r = lane & 31;
@@ -49,28 +58,61 @@ __global__ __launch_bounds__(kHubThreads) void k_hub(HubArgs a) {
       X[i][j] = v16i{};
       Y[i][j] = v16i{};
     }
-  // A lane feeds 16 consecutive k of its row to both operands, so the two
-  // operands agree on which k each byte slot holds.
-  const int8_t* pa0 = a.Bm + static_cast<size_t>(row0 + r) * a.K + kh;
-  const int8_t* pa1 = a.Bm + static_cast<size_t>(row0 + 32 + r) * a.K + kh;
-  const int8_t* pb0 = a.B + static_cast<size_t>(col0 + r) * a.K + kh;
-  const int8_t* pb1 = a.B + static_cast<size_t>(col0 + 32 + r) * a.K + kh;
+  // staging: chunk c = tid + 256 i (i = 0, 1) is row c / 4, bytes 16 (c % 4)
+  const size_t K = static_cast<size_t>(a.K);
+  const int8_t* gA = a.Bm + static_cast<size_t>(ti * kHubTile) * K;
+  const int8_t* gB = a.B + static_cast<size_t>(tj * kHubTile) * K;
+  int srow[2], spart[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int c = tid + kHubThreads * i;
+    srow[i] = c >> 2;
+    spart[i] = (c & 3) * 16;
+  }
+  v4i ra[2], rb[2];
+  auto gload = [&](int k) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ra[i] = *reinterpret_cast<const v4i*>(gA + srow[i] * K + k + spart[i]);
+      rb[i] = *reinterpret_cast<const v4i*>(gB + srow[i] * K + k + spart[i]);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      *reinterpret_cast<v4i*>(&sA[buf][srow[i] * kHubRow + spart[i]]) = ra[i];
+      *reinterpret_cast<v4i*>(&sB[buf][srow[i] * kHubRow + spart[i]]) = rb[i];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
   const v4i ones = {0x01010101, 0x01010101, 0x01010101, 0x01010101};
-  for (int k = 0; k < a.K; k += 32) {
-    const v4i A0 = *reinterpret_cast<const v4i*>(pa0 + k);
-    const v4i A1 = *reinterpret_cast<const v4i*>(pa1 + k);
-    const v4i B0 = *reinterpret_cast<const v4i*>(pb0 + k);
-    const v4i B1 = *reinterpret_cast<const v4i*>(pb1 + k);
-    // |s| of an int8 in {-1, 0, 1} is its lowest bit
-    const v4i A0a = A0 & ones, A1a = A1 & ones, B0a = B0 & ones, B1a = B1 & ones;
-    X[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0a, B0a, X[0][0], 0, 0, 0);
-    X[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0a, B1a, X[0][1], 0, 0, 0);
-    X[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1a, B0a, X[1][0], 0, 0, 0);
-    X[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1a, B1a, X[1][1], 0, 0, 0);
-    Y[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B0, Y[0][0], 0, 0, 0);
-    Y[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B1, Y[0][1], 0, 0, 0);
-    Y[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, Y[1][0], 0, 0, 0);
-    Y[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, Y[1][1], 0, 0, 0);
+  const int ar = (wave >> 1) * 64 + r, br = (wave & 1) * 64 + r;
+  for (int k0 = 0, buf = 0; k0 < a.K; k0 += kHubKStep, buf ^= 1) {
+    const bool more = k0 + kHubKStep < a.K;
+    if (more) gload(k0 + kHubKStep);
+#pragma unroll
+    for (int kk = 0; kk < kHubKStep; kk += 32) {
+      // a lane feeds 16 consecutive k of its row to both operands, so the
+      // two operands agree on which k each byte slot holds
+      const v4i A0 = *reinterpret_cast<const v4i*>(&sA[buf][ar * kHubRow + kk + kh]);
+      const v4i A1 = *reinterpret_cast<const v4i*>(&sA[buf][(ar + 32) * kHubRow + kk + kh]);
+      const v4i B0 = *reinterpret_cast<const v4i*>(&sB[buf][br * kHubRow + kk + kh]);
+      const v4i B1 = *reinterpret_cast<const v4i*>(&sB[buf][(br + 32) * kHubRow + kk + kh]);
+      // |s| of an int8 in {-1, 0, 1} is its lowest bit
+      const v4i A0a = A0 & ones, A1a = A1 & ones, B0a = B0 & ones, B1a = B1 & ones;
+      X[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0a, B0a, X[0][0], 0, 0, 0);
+      X[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0a, B1a, X[0][1], 0, 0, 0);
+      X[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1a, B0a, X[1][0], 0, 0, 0);
+      X[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1a, B1a, X[1][1], 0, 0, 0);
+      Y[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B0, Y[0][0], 0, 0, 0);
+      Y[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B1, Y[0][1], 0, 0, 0);
+      Y[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, Y[1][0], 0, 0, 0);
+      Y[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, Y[1][1], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
   }
   // Epilogue.  32 x 32 accumulator layout: lane l, register q holds row
   // 8 * (q / 4) + 4 * (l / 32) + q % 4 and column l % 32 of the block.
@@ -112,7 +154,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub(HubArgs a) {
 
 hipError_t launch_hub(const HubArgs& a, hipStream_t st) {
   if (a.T <= 0) return hipSuccess;
-  if (a.T % dev::kHubTile != 0 || a.K % 32 != 0) return hipErrorInvalidValue;
+  if (a.T % dev::kHubTile != 0 || a.K % dev::kHubKStep != 0) return hipErrorInvalidValue;
   const int nt = a.T / dev::kHubTile;
   const int tiles = nt * (nt + 1) / 2;
   hipLaunchKernelGGL(dev::k_hub, dim3(tiles), dim3(dev::kHubThreads), 0, st, a);
