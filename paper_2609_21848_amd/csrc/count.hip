@@ -38,11 +38,36 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t mbase[kDirectWaves][kGather];
   __shared__ uint8_t mtag[kDirectWaves][kGather];
   __shared__ int32_t item_sh;
+  __shared__ unsigned long long blk[2];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
   for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&mtag[0][0])[i] = 0;
-  Sums sums;
+  if (tid == 0) blk[0] = blk[1] = 0;
+  // Per thread, for the current graph: twice the balanced count (sum of
+  // p^2 + n^2 minus the wedges) and the unbalanced count.  Only the
+  // workgroup's total of sq2 is even, so the halving happens there.
+  int64_t sq2 = 0;
+  uint64_t pnx = 0;
+  auto flush_block = [&](uint32_t g) {
+    const int64_t q = wave_sum64(sq2), x = wave_sum64(static_cast<int64_t>(pnx));
+    if ((tid & (kWave - 1)) == 0) {
+      atomicAdd(&blk[0], static_cast<unsigned long long>(q));
+      atomicAdd(&blk[1], static_cast<unsigned long long>(x));
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t bal = static_cast<int64_t>(blk[0]) / 2, unb = static_cast<int64_t>(blk[1]);
+      unsigned long long* res = a.res + static_cast<size_t>(g) * kResStride;
+      if (bal) atomicAdd(res + kResBalanced, static_cast<unsigned long long>(bal));
+      if (unb) atomicAdd(res + kResUnbalanced, static_cast<unsigned long long>(unb));
+      if (bal + unb) atomicAdd(res + kResTotal, static_cast<unsigned long long>(bal + unb));
+      blk[0] = blk[1] = 0;
+    }
+    __syncthreads();
+    sq2 = 0;
+    pnx = 0;
+  };
   uint32_t graph = kNoGraph;
   for (;;) {
     if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
@@ -51,8 +76,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     if (i >= a.n_items) break;
     const Item it = load_const(a.items, i);
     if (it.graph != graph) {
-      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
-      sums = Sums{};
+      if (graph != kNoGraph) flush_block(graph);
       graph = it.graph;
     }
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
@@ -71,21 +95,38 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
         cnt[key] = 0;
       }
     } else {
+      // Sums of squares (see SqSums): every wedge of a single-part item lies
+      // in its window, so thread 0 takes the item's wedges off once; the
+      // wedges of pairs handed to the dense path are added back.  p, n <
+      // 2^16, so squares and products are exact 24-bit multiplies.
+      if (tid == 0) sq2 -= static_cast<int64_t>(it.work);
+      const bool hub = (it.flags & kItemHubPairs) != 0;
       const uint32_t lo = static_cast<uint32_t>(it.key_lo) & ~3u;
       const uint32_t hi = static_cast<uint32_t>(it.key_hi);
       for (uint32_t key = lo + 4 * tid; key < hi; key += 4 * kDirectThreads) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&cnt[key]);
         if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
+        *reinterpret_cast<uint4*>(&cnt[key]) = make_uint4(0, 0, 0, 0);
         const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (cv[j]) emit(it, key + j, cv[j] & 0xffffu, cv[j] >> 16, sc, sums);
-        *reinterpret_cast<uint4*>(&cnt[key]) = make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t p = cv[j] & 0xffffu, n = cv[j] >> 16;
+          if (hub && static_cast<int32_t>(key + j) < sc.T) {
+            if (cv[j]) {
+              as_global(sc.hub_pairs)[static_cast<size_t>(it.owner) * sc.T + key + j] =
+                  (static_cast<unsigned long long>(n) << 32) | p;
+              sq2 += p + n;
+            }
+          } else {
+            sq2 += static_cast<int64_t>(__umul24(p, p)) + static_cast<int64_t>(__umul24(n, n));
+            pnx += __umul24(p, n);
+          }
+        }
       }
     }
     __syncthreads();
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  if (graph != kNoGraph) flush_block(graph);
 }
 
 // ---------------------------------------------------------------------------

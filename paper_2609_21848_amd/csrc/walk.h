@@ -207,6 +207,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
   while (longm || have) {
     u32x4 v[U];
     uint32_t vst[U], vend[U], vg[U], vp[U];
+    int nv = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (!have && longm) {
@@ -229,17 +230,22 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       vend[u] = h ? cur_end : 0u;
       v[u] = *(const global_t<u32x4>*)(adj + ((h && p < cur_end) ? p : 0u));
       if (h) {
+        nv = u + 1;
         cur_pos += kChunk;
         if (cur_pos >= cur_end) have = false;
       }
     }
+    // slots past the last real chunk (the batch's long runs ran out) hold
+    // no entries: skip them (nv is wavefront-uniform)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+      if (u < nv) {
+        const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t idx = vp[u] + q;
-        f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t idx = vp[u] + q;
+          f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
+        }
       }
     }
   }
