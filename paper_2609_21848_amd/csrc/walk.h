@@ -312,6 +312,25 @@ struct PairTally {  // 8 | 8-bit counters, two keys per 32-bit word
   }
 };
 
+// Branch-free forms: a masked slot adds into a dummy word of its own lane
+// (dummy, past the counters) instead of switching the execution mask around
+// every atomic; dummy words are never read.
+struct DirectTallyBF {
+  uint32_t* cnt;
+  uint32_t dummy;  // word index of this lane's dummy
+  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
+    atomicAdd(&cnt[valid ? e >> 1 : dummy], wedge_inc(e, g));
+  }
+};
+
+struct PairTallyBF {
+  uint32_t* cnt;
+  uint32_t dummy;
+  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
+    atomicAdd(&cnt[valid ? e >> 2 : dummy], 1u << (((e ^ (g & 1u)) & 3u) << 3));
+  }
+};
+
 // Hash tallies do all their work in add (a probe loop).
 template <class G>
 struct HashTally {
