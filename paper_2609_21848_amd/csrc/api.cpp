@@ -728,26 +728,34 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
   uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + kCtlQueues);
   const dbbc::DevSideConst* sides = d.sides.as<dbbc::DevSideConst>();
   const int cus = g->dev.cus;
-  {
+  // direct items: one launch per side (hot-key credits are summed per
+  // workgroup for one side)
+  for (int s = 0; s < 2; ++s) {
+    const int32_t lo = s == 0 ? 0 : hp.n_direct_side0;
+    const int32_t hi = s == 0 ? hp.n_direct_side0 : hp.n_items_kept[0];
     dbbc::DirectArgs a{};
-    a.items = d.direct_items.as<dbbc::Item>();
+    a.items = d.direct_items.as<dbbc::Item>() + lo;
     a.sides = sides;
-    a.queue = queues + 0;
+    a.queue = queues + s;
     a.res = ctl;
     a.err = err;
-    a.n_items = hp.n_items_kept[0];
+    a.n_items = hi - lo;
     a.long_len = long_len;
     HIP_TRY(dbbc::launch_pv_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
   }
-  {
+  // reverse items: one launch per side (their key credits are summed per
+  // workgroup for one side's reverse window)
+  for (int s = 0; s < 2; ++s) {
+    const int32_t lo = s == 0 ? 0 : hp.n_reverse_side0;
+    const int32_t hi = s == 0 ? hp.n_reverse_side0 : hp.n_items_kept[1];
     dbbc::SmallArgs a{};
-    a.items = d.reverse_items.as<dbbc::Item>();
+    a.items = d.reverse_items.as<dbbc::Item>() + lo;
     a.sides = sides;
     a.res = ctl;
     a.err = err;
-    a.n_items = hp.n_items_kept[1];
+    a.n_items = hi - lo;
     a.long_len = long_len;
-    HIP_TRY(dbbc::launch_pv_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 11) / 12)), st));
+    HIP_TRY(dbbc::launch_pv_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 7) / 8)), st));
   }
   {
     dbbc::SmallArgs a{};

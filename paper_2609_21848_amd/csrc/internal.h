@@ -140,6 +140,8 @@ struct HostPlan {
   // list lengths (direct, reverse, small groups, hash, reduces) once the
   // lists live on the device only
   int32_t n_items_kept[5] = {0, 0, 0, 0, 0};
+  int32_t n_reverse_side0 = 0;  // reverse items are listed side 0 first
+  int32_t n_direct_side0 = 0;   // per-vertex plans: direct items side 0 first
   int32_t acc_slots = 0;
   int32_t acc_width = 0;           // max window over the sides
   // per sparse kernel (0 = direct, 1 = small, 2 = hash, 3 = reverse):

@@ -134,8 +134,12 @@ struct PairCredit {
 // ---------------------------------------------------------------------------
 // Direct items: one workgroup per item, 32-bit p and n counters over the
 // item's key window (at most kPVWindow keys; windows of one pivot share
-// their runs and skip the keys of the others).
+// their runs and skip the keys of the others).  Credits of keys below
+// kPVHotKeys (the side's highest-priority vertices, the keys of most items)
+// are summed per workgroup in LDS and reach HBM once per workgroup; a launch
+// holds the items of one side.
 constexpr int kPVDirectThreads = 1024;
+constexpr int kPVHotKeys = 2048;
 constexpr int kPVDirectWaves = kPVDirectThreads / kWave;
 
 __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
@@ -143,11 +147,13 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
   __shared__ uint32_t mbase[kPVDirectWaves][kGather];
   __shared__ uint32_t mtag[kPVDirectWaves][kGather];
   __shared__ unsigned long long cb[kPVDirectWaves][kWave], cu[kPVDirectWaves][kWave];
+  __shared__ unsigned long long hbal[kPVHotKeys], hunb[kPVHotKeys];
   __shared__ int32_t item_sh;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = lane_id();
   for (int i = tid; i < kPVWindow; i += kPVDirectThreads) P[i] = N[i] = 0;
+  for (int i = tid; i < kPVHotKeys; i += kPVDirectThreads) hbal[i] = hunb[i] = 0;
   for (int i = tid; i < kPVDirectWaves * static_cast<int>(kGather); i += kPVDirectThreads) (&mtag[0][0])[i] = 0;
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
@@ -205,19 +211,44 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
       const uint32_t p = P[k], n = N[k];
       if (p | n) {
         P[k] = N[k] = 0;
-        pc.add(sc, lo + k, p, n, sums);
+        const uint32_t key = lo + k;
+        if (key < static_cast<uint32_t>(kPVHotKeys)) {
+          sums.add(p, n);
+          const int64_t Pp = p, Nn = n;
+          const int64_t cb2 = Pp * (Pp - 1) / 2 + Nn * (Nn - 1) / 2, cx = Pp * Nn;
+          if (cb2) atomicAdd(&hbal[key], static_cast<unsigned long long>(cb2));
+          if (cx) atomicAdd(&hunb[key], static_cast<unsigned long long>(cx));
+          pc.c += cb2;
+          pc.x += cx;
+        } else {
+          pc.add(sc, key, p, n, sums);
+        }
       }
     }
     pc.to_owner(sc, it.owner);
     __syncthreads();
   }
   if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  // the workgroup's hot-key credits (all items of a launch are of one side)
+  __syncthreads();
+  if (a.n_items > 0) {
+    const Item i0 = load_const(a.items, 0);
+    const DevSideConst sc = load_const(a.sides, 2 * i0.graph + i0.side);
+    for (int k = tid; k < kPVHotKeys; k += kPVDirectThreads) {
+      const unsigned long long b = hbal[k], u = hunb[k];
+      if (b) atomicAdd(&sc.bal[sc.orig[k]], b);
+      if (u) atomicAdd(&sc.unb[sc.orig[k]], u);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Reverse items (at most kReverseMaxSegs runs): one wavefront per item, 8-bit
-// p and n per key over the reverse window, two keys per 32-bit word.
-constexpr int kPVReverseThreads = 768;
+// p and n per key over the reverse window, two keys per 32-bit word.  The
+// keys are the reverse window's vertices, shared by every item of a side, so
+// their credits are summed per workgroup in LDS and reach HBM once per
+// workgroup at the end (a launch holds the items of one side).
+constexpr int kPVReverseThreads = 512;
 constexpr int kPVReverseWaves = kPVReverseThreads / kWave;
 constexpr int kPVReverseWords = kMaxReverseL / 2;
 
@@ -226,10 +257,12 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ uint32_t mbase[kPVReverseWaves][kGather];
   __shared__ uint32_t mtag[kPVReverseWaves][kGather];
   __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
+  __shared__ unsigned long long kbal[kMaxReverseL], kunb[kMaxReverseL];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
+  for (int i = threadIdx.x; i < kMaxReverseL; i += kPVReverseThreads) kbal[i] = kunb[i] = 0;
   for (int i = lane; i < kPVReverseWords; i += kWave) C[i] = 0;
   for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
   cb[wave][lane] = 0;
@@ -273,18 +306,39 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
       flush_mid_credits(cb[wave], cu[wave], mid, sc);
     }
     PairCredit pc;
+    auto local = [&](uint32_t key, uint32_t p, uint32_t n) {
+      sums.add(p, n);
+      const int64_t P = p, N = n;
+      const int64_t cb2 = P * (P - 1) / 2 + N * (N - 1) / 2, cx = P * N;
+      if (cb2) atomicAdd(&kbal[key], static_cast<unsigned long long>(cb2));
+      if (cx) atomicAdd(&kunb[key], static_cast<unsigned long long>(cx));
+      pc.c += cb2;
+      pc.x += cx;
+    };
     const int32_t w_hi = (it.key_hi + 1) >> 1;
     for (int32_t wd = lane; wd < w_hi; wd += kWave) {
       const uint32_t c2 = C[wd];
       if (!c2) continue;
       C[wd] = 0;
-      if (c2 & 0xffffu) pc.add(sc, 2 * wd, c2 & 0xffu, (c2 >> 8) & 0xffu, sums);
-      if (c2 >> 16) pc.add(sc, 2 * wd + 1, (c2 >> 16) & 0xffu, c2 >> 24, sums);
+      if (c2 & 0xffffu) local(2 * wd, c2 & 0xffu, (c2 >> 8) & 0xffu);
+      if (c2 >> 16) local(2 * wd + 1, (c2 >> 16) & 0xffu, c2 >> 24);
     }
     pc.to_owner(sc, it.owner);
     wave_sync_lds();
   }
   if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  // the workgroup's key credits (all items of a launch are of one side)
+  __syncthreads();
+  if (a.n_items > 0) {
+    const Item i0 = load_const(a.items, 0);
+    const DevSideConst sc = load_const(a.sides, 2 * i0.graph + i0.side);
+    const int32_t nkeys = sc.R < kMaxReverseL ? sc.R : kMaxReverseL;
+    for (int k = threadIdx.x; k < nkeys; k += kPVReverseThreads) {
+      const unsigned long long b = kbal[k], u = kunb[k];
+      if (b) atomicAdd(&sc.bal[sc.orig[k]], b);
+      if (u) atomicAdd(&sc.unb[sc.orig[k]], u);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -410,6 +410,11 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   // parts first (they are the heaviest), then the single-part items
   plan.direct_items = std::move(parts);
   plan.direct_items.insert(plan.direct_items.end(), singles.begin(), singles.end());
+  if (pv) {  // the per-vertex pass launches each side's direct items apart
+    std::stable_partition(plan.direct_items.begin(), plan.direct_items.end(),
+                          [](const Item& it) { return it.side == 0; });
+    for (const Item& it : plan.direct_items) plan.n_direct_side0 += it.side == 0;
+  }
   // heavy tail pivots first as well
   std::stable_sort(plan.hash_items.begin(), plan.hash_items.end(),
                    [&](const Item& a, const Item& b) { return item_work(plan, a) > item_work(plan, b); });
@@ -421,6 +426,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       plan.k_segs[k] += it.seg_count;
     }
   };
+  for (const Item& it : plan.reverse_items) plan.n_reverse_side0 += it.side == 0;
   tally(0, plan.direct_items);
   tally(2, plan.hash_items);
   tally(3, plan.reverse_items);
