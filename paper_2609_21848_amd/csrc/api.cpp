@@ -1056,7 +1056,7 @@ int dbbc_autotune(dbbc_graph* const* gs, int32_t k, const dbbc_options* start, i
       {&dbbc_options::small_work, {64, 256, 512}},
       {&dbbc_options::window_L, {512, 2048, 8192, 32768}},
       {&dbbc_options::hub_T, {0, 256, 1024, 4096}},
-      {&dbbc_options::part_work, {1 << 18, 1 << 20, 1 << 22}},
+      {&dbbc_options::part_work, {1 << 20, 1 << 22, 1 << 24}},
   };
   for (const Knob& kn : knobs) {
     for (int32_t v : kn.values) {

@@ -55,7 +55,7 @@ PlanParams default_params(const HostGraph& g) {
     }
   }
   p.small_work = static_cast<int32_t>(kSmallGroupWork);
-  p.part_work = 1 << 20;
+  p.part_work = 1 << 24;
   return p;
 }
 
