@@ -235,6 +235,17 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         return;
       }
       plan.w_sparse += work;
+      if (kind == kReverseTail) {
+        // rows are sorted by rank, so a run's last entry is its largest key:
+        // the item's counters (and its parts' and reduce's) need only the
+        // keys up to the largest one
+        int32_t mx = key_lo;
+        for (uint32_t k = 0; k < nseg; ++k) {
+          const Segment sg = plan.segs[seg_begin + k];
+          mx = std::max(mx, static_cast<int32_t>(O.adj[sg.start + (sg.len_g >> 1) - 1] >> 1));
+        }
+        key_hi = std::min(key_hi, mx + 1);
+      }
       Item it{};
       it.seg_begin = seg_begin;
       it.seg_count = nseg;
