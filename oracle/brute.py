@@ -59,15 +59,18 @@ def brute_per_vertex(n_u, n_v, u, v, sign):
 
 
 def brute_per_edge(n_u, n_v, u, v, sign):
-    """Per edge (in input order), the number of balanced butterflies containing it."""
+    """Per edge (in input order), the number of balanced and of unbalanced
+    butterflies containing it.  Returns two lists: bal_e[m], unb_e[m]."""
     e = _edge_map(u, v, sign)
-    cnt = {k: 0 for k in e}
+    bal = {k: 0 for k in e}
+    unb = {k: 0 for k in e}
     for a, a2 in combinations(range(n_u), 2):
         for b, b2 in combinations(range(n_v), 2):
             quad = [(a, b), (a, b2), (a2, b), (a2, b2)]
             if not all(q in e for q in quad):
                 continue
-            if sum(1 for q in quad if e[q] < 0) % 2 == 0:
-                for q in quad:
-                    cnt[q] += 1
-    return [cnt[(int(a), int(b))] for a, b in zip(u, v)]
+            cnt = bal if sum(1 for q in quad if e[q] < 0) % 2 == 0 else unb
+            for q in quad:
+                cnt[q] += 1
+    keys = [(int(a), int(b)) for a, b in zip(u, v)]
+    return [bal[k] for k in keys], [unb[k] for k in keys]

@@ -16,8 +16,8 @@
  * B1[w] * B2[w] unbalanced butterflies (a symmetric wedge paired with an
  * asymmetric one has an odd number of negative edges) and C(B1[w]+B2[w], 2)
  * butterflies in total, computed separately so that tests can check that the
- * two classes add up.  Optionally it also counts, per vertex, the balanced
- * and unbalanced butterflies containing that vertex.
+ * two classes add up.  Optionally it also counts, per vertex and per edge,
+ * the balanced and unbalanced butterflies containing that vertex or edge.
  *
  * Pivots are spread over POSIX threads; each thread has private buckets, as
  * in the paper's thread-private counters.  Integer sums are exact (int64).
@@ -37,6 +37,7 @@ typedef struct {
   const int64_t *adj_off; /* [n+1] */
   const int32_t *adj;     /* neighbour global index */
   const int8_t *adj_sign; /* +1 / -1 */
+  const int64_t *adj_eid; /* input record of each adjacency entry */
   const int64_t *deg;
   const int64_t *id; /* tie-break id per vertex */
   const int32_t *pivots;
@@ -46,6 +47,8 @@ typedef struct {
   int64_t *per_pivot_bal; /* optional [n] */
   int64_t *bal_vertex;    /* optional [n] */
   int64_t *unb_vertex;    /* optional [n] */
+  int64_t *bal_edge;      /* optional [m], by input record */
+  int64_t *unb_edge;      /* optional [m] */
   oracle_counts sum;
 } job;
 
@@ -69,6 +72,7 @@ static void *worker(void *arg) {
   int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   oracle_counts c = {0, 0, 0, 0, 0};
   const int per_vertex = J->bal_vertex != NULL || J->unb_vertex != NULL;
+  const int per_edge = J->bal_edge != NULL || J->unb_edge != NULL;
   for (;;) {
     int64_t k = __atomic_fetch_add(&J->next, 1, __ATOMIC_RELAXED);
     if (k >= J->n_pivots) break;
@@ -109,10 +113,14 @@ static void *worker(void *arg) {
     if (per_vertex) {
       if (J->bal_vertex) add_vertex(J->bal_vertex, u, pivot_bal);
       if (J->unb_vertex) add_vertex(J->unb_vertex, u, pivot_unb);
-      /* a mid v of a symmetric wedge to w lies in every balanced butterfly
-       * that pairs this wedge with another symmetric wedge to w (B1[w] - 1 of
-       * them) and in every unbalanced one that pairs it with an asymmetric
-       * wedge (B2[w]); the asymmetric case swaps the roles. */
+    }
+    if (per_vertex || per_edge) {
+      /* A wedge u-v-w lies in the butterflies that pair it with another wedge
+       * u-v'-w.  A symmetric one lies in B1[w] - 1 balanced butterflies (the
+       * other symmetric wedges) and in B2[w] unbalanced ones (the asymmetric
+       * wedges); an asymmetric one swaps the roles.  Each butterfly counted
+       * at (u, w) is the union of exactly two such wedges, so this credit
+       * goes once to the mid v and once to each of the wedge's two edges. */
       for (int64_t a = J->adj_off[u]; a < J->adj_off[u + 1]; ++a) {
         int64_t v = J->adj[a];
         if (!higher(J, u, v)) continue;
@@ -120,12 +128,23 @@ static void *worker(void *arg) {
         for (int64_t b = J->adj_off[v]; b < J->adj_off[v + 1]; ++b) {
           int64_t w = J->adj[b];
           if (!higher(J, u, w)) continue;
+          int64_t bw, uw;
           if (J->adj_sign[a] == J->adj_sign[b]) {
-            bv += B1[w] - 1;
-            uv += B2[w];
+            bw = B1[w] - 1;
+            uw = B2[w];
           } else {
-            bv += B2[w] - 1;
-            uv += B1[w];
+            bw = B2[w] - 1;
+            uw = B1[w];
+          }
+          bv += bw;
+          uv += uw;
+          if (J->bal_edge) {
+            add_vertex(J->bal_edge, J->adj_eid[a], bw);
+            add_vertex(J->bal_edge, J->adj_eid[b], bw);
+          }
+          if (J->unb_edge) {
+            add_vertex(J->unb_edge, J->adj_eid[a], uw);
+            add_vertex(J->unb_edge, J->adj_eid[b], uw);
           }
         }
         if (J->bal_vertex) add_vertex(J->bal_vertex, v, bv);
@@ -154,13 +173,15 @@ static void *worker(void *arg) {
  * Vertex x of U has global index x, vertex y of V has global index n_u + y.
  * id: tie-break id per global index (NULL: the global index itself).
  * pivots / n_pivots: restrict Phase 5 to these global indices (NULL: all).
- * The per-vertex and per-pivot arrays (length n_u + n_v) are optional and
- * must be zeroed by the caller.  Returns 0, or -1 on bad input / no memory.
+ * The per-vertex and per-pivot arrays (length n_u + n_v) and the per-edge
+ * arrays (length m, indexed by input record) are optional and must be zeroed
+ * by the caller.  Returns 0, or -1 on bad input / no memory.
  * Duplicate (u, v) pairs are not allowed here. */
 int oracle_vp_count(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u, const int32_t *v,
                     const int8_t *sign, const int64_t *id, int nthreads, const int32_t *pivots,
                     int64_t n_pivots, int64_t *per_pivot_bal, int64_t *bal_vertex,
-                    int64_t *unb_vertex, oracle_counts *out) {
+                    int64_t *unb_vertex, int64_t *bal_edge, int64_t *unb_edge,
+                    oracle_counts *out) {
   int64_t n = n_u + n_v;
   if (n_u < 0 || n_v < 0 || m < 0 || !out) return -1;
   memset(out, 0, sizeof(*out));
@@ -170,8 +191,9 @@ int oracle_vp_count(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u, const
   int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
   int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
   int8_t *adj_sign = (int8_t *)malloc((size_t)(2 * m + 1));
+  int64_t *adj_eid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
   int rc = -1;
-  if (!deg || !off || !fill || !ids || !adj || !adj_sign) goto done;
+  if (!deg || !off || !fill || !ids || !adj || !adj_sign || !adj_eid) goto done;
   for (int64_t i = 0; i < m; ++i) {
     if (u[i] < 0 || u[i] >= n_u || v[i] < 0 || v[i] >= n_v) goto done;
     if (sign[i] != 1 && sign[i] != -1) goto done;
@@ -185,8 +207,10 @@ int oracle_vp_count(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u, const
   for (int64_t i = 0; i < m; ++i) {
     int64_t a = u[i], b = n_u + v[i];
     adj[off[a] + fill[a]] = (int32_t)b;
+    adj_eid[off[a] + fill[a]] = i;
     adj_sign[off[a] + fill[a]++] = sign[i];
     adj[off[b] + fill[b]] = (int32_t)a;
+    adj_eid[off[b] + fill[b]] = i;
     adj_sign[off[b] + fill[b]++] = sign[i];
   }
   {
@@ -196,6 +220,7 @@ int oracle_vp_count(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u, const
     J.adj_off = off;
     J.adj = adj;
     J.adj_sign = adj_sign;
+    J.adj_eid = adj_eid;
     J.deg = deg;
     J.id = ids;
     J.pivots = pivots;
@@ -203,6 +228,8 @@ int oracle_vp_count(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u, const
     J.per_pivot_bal = per_pivot_bal;
     J.bal_vertex = bal_vertex;
     J.unb_vertex = unb_vertex;
+    J.bal_edge = bal_edge;
+    J.unb_edge = unb_edge;
     pthread_mutex_init(&J.lock, NULL);
     if (nthreads < 1) nthreads = 1;
     pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
@@ -221,5 +248,6 @@ done:
   free(ids);
   free(adj);
   free(adj_sign);
+  free(adj_eid);
   return rc;
 }

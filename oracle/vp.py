@@ -36,6 +36,8 @@ class OracleResult:
     bal_v: np.ndarray | None = None
     unb_u: np.ndarray | None = None
     unb_v: np.ndarray | None = None
+    bal_e: np.ndarray | None = None
+    unb_e: np.ndarray | None = None
 
 
 def build(force: bool = False) -> str:
@@ -54,7 +56,7 @@ def _declare(lib):
     i64, p = ctypes.c_int64, ctypes.c_void_p
     lib.oracle_vp_count.restype = ctypes.c_int
     lib.oracle_vp_count.argtypes = [i64, i64, i64, p, p, p, p, ctypes.c_int, p, i64,
-                                    p, p, p, ctypes.POINTER(_Counts)]
+                                    p, p, p, p, p, ctypes.POINTER(_Counts)]
     return lib
 
 
@@ -81,10 +83,12 @@ def default_threads() -> int:
 
 
 def vp_counts(n_u, n_v, u, v, sign, ids=None, threads=None, pivots=None,
-              per_pivot=False, per_vertex=False, lib_path=None) -> OracleResult:
+              per_pivot=False, per_vertex=False, per_edge=False, lib_path=None) -> OracleResult:
     """Algorithm 1 Phase 5 over the whole graph (or over ``pivots``, global
     indices: U vertex x is x, V vertex y is n_u + y).  ``ids`` overrides the
-    tie-break id of Definition 3 per global index."""
+    tie-break id of Definition 3 per global index.  ``per_edge`` adds, per
+    input record, the balanced and unbalanced butterflies containing it
+    (``bal_e``, ``unb_e``); records must name distinct (u, v) pairs."""
     lib = _load(lib_path)
     u = np.ascontiguousarray(u, dtype=np.int32)
     v = np.ascontiguousarray(v, dtype=np.int32)
@@ -104,11 +108,14 @@ def vp_counts(n_u, n_v, u, v, sign, ids=None, threads=None, pivots=None,
     ppb = np.zeros(n, np.int64) if per_pivot else None
     bal = np.zeros(n, np.int64) if per_vertex else None
     unb = np.zeros(n, np.int64) if per_vertex else None
+    bal_e = np.zeros(m, np.int64) if per_edge else None
+    unb_e = np.zeros(m, np.int64) if per_edge else None
     out = _Counts()
     rc = lib.oracle_vp_count(int(n_u), int(n_v), m, ptr(u), ptr(v), ptr(s), ptr(id_arr),
                              int(threads or default_threads()), ptr(piv),
                              0 if piv is None else int(piv.shape[0]),
-                             ptr(ppb), ptr(bal), ptr(unb), ctypes.byref(out))
+                             ptr(ppb), ptr(bal), ptr(unb), ptr(bal_e), ptr(unb_e),
+                             ctypes.byref(out))
     if rc != 0:
         raise ValueError("oracle_vp_count rejected the graph")
     res = OracleResult(out.balanced, out.unbalanced, out.total, out.wedges, out.expansions)
@@ -117,4 +124,6 @@ def vp_counts(n_u, n_v, u, v, sign, ids=None, threads=None, pivots=None,
     if per_vertex:
         res.bal_u, res.bal_v = bal[:n_u], bal[n_u:]
         res.unb_u, res.unb_v = unb[:n_u], unb[n_u:]
+    if per_edge:
+        res.bal_e, res.unb_e = bal_e, unb_e
     return res

@@ -12,8 +12,8 @@ from math import comb
 import numpy as np
 import pytest
 
-from oracle import brute_counts, brute_per_vertex, pair_counts, pair_per_vertex, vp_counts
-from oracle.brute import brute_per_edge
+from oracle import (brute_counts, brute_per_edge, brute_per_vertex, pair_counts,
+                    pair_per_vertex, vp_counts)
 from synth import chung_lu_graph, config_graph, uniform_graph
 
 from golden_io import load
@@ -55,8 +55,8 @@ def test_fig_comparison_vertex_and_edge_counts():
     n_u, n_v, u, v, s = fx.arrays()
     bu, bv, uu, uv = brute_per_vertex(n_u, n_v, u, v, s)
     pu, pv, _, _ = pair_per_vertex(n_u, n_v, u, v, s)
-    r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, threads=2)
-    per_edge = brute_per_edge(n_u, n_v, u, v, s)
+    r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, per_edge=True, threads=2)
+    be, ue = brute_per_edge(n_u, n_v, u, v, s)
     edge_index = {(a, b): i for i, (a, b, _) in enumerate(fx.edges)}
     for e in fx.expect:
         if e[0] == "vertex_balanced":
@@ -64,7 +64,12 @@ def test_fig_comparison_vertex_and_edge_counts():
             assert bu[x] == pu[x] == r.bal_u[x] == int(e[2]), e
         elif e[0] == "edge_balanced":
             i = edge_index[(fx.left[e[1]], fx.right[e[2]])]
-            assert per_edge[i] == int(e[3]), e
+            assert be[i] == r.bal_e[i] == int(e[3]), e
+    # edges the figure does not list lie in no balanced butterfly
+    listed = {edge_index[(fx.left[e[1]], fx.right[e[2]])] for e in fx.expect
+              if e[0] == "edge_balanced"}
+    assert all(r.bal_e[i] == be[i] == 0 for i in range(len(fx.edges)) if i not in listed)
+    assert list(r.unb_e) == list(ue) == [0] * len(fx.edges)
     # Right-side values follow from the same figure (each of 1, 2, 5, 6 lies
     # in three balanced butterflies, 3 and 4 in one).
     assert list(bv) == list(pv) == list(r.bal_v) == [3, 3, 1, 1, 3, 3]
@@ -139,6 +144,24 @@ def test_complete_bipartite_closed_forms(a, b):
     assert r.expansions == a * b
 
 
+@pytest.mark.parametrize("a,b", [(2, 2), (3, 5), (7, 4), (9, 6)])
+def test_complete_bipartite_per_edge_closed_forms(a, b):
+    u, v = _complete(a, b)
+    k = (a - 1) * (b - 1)  # butterflies through one edge of K(a,b)
+    r = vp_counts(a, b, u, v, np.ones(u.shape, np.int8), per_edge=True, threads=2)
+    assert (r.bal_e == k).all() and (r.unb_e == 0).all()
+    # one negative edge e0 = (0, 0): every butterfly through e0 is unbalanced;
+    # an edge (0, y) meets e0 in a-1 butterflies (any second U vertex, V pair
+    # fixed), an edge (x, 0) in b-1, an edge disjoint from e0 in exactly one
+    s = np.ones(u.shape, np.int8)
+    s[0] = -1
+    r = vp_counts(a, b, u, v, s, per_edge=True, threads=2)
+    for i in range(u.shape[0]):
+        x, y = int(u[i]), int(v[i])
+        with_e0 = k if (x, y) == (0, 0) else (a - 1 if x == 0 else b - 1 if y == 0 else 1)
+        assert (r.unb_e[i], r.bal_e[i]) == (with_e0, k - with_e0), (i, x, y)
+
+
 # --- agreement of the three tiers --------------------------------------------------
 
 def test_tiers_agree_on_random_tiny_graphs():
@@ -151,10 +174,13 @@ def test_tiers_agree_on_random_tiny_graphs():
         assert len(set(got.values())) == 1, (seed, got)
         if seed % 4 == 0:
             bvx = brute_per_vertex(g.n_u, g.n_v, g.u, g.v, g.sign)
-            r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True, threads=2)
+            r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True, per_edge=True,
+                          threads=2)
             pvx = pair_per_vertex(g.n_u, g.n_v, g.u, g.v, g.sign)
             for a, b, c in zip(bvx, pvx, (r.bal_u, r.bal_v, r.unb_u, r.unb_v)):
                 assert list(a) == list(b) == list(c), seed
+            be, ue = brute_per_edge(g.n_u, g.n_v, g.u, g.v, g.sign)
+            assert list(r.bal_e) == be and list(r.unb_e) == ue, seed
 
 
 def test_tiers_agree_on_skewed_small_graphs():
@@ -188,7 +214,7 @@ def _vp(n_u, n_v, u, v, s, **kw):
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_invariants(seed):
     g = _graph(seed)
-    base = _vp(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True)
+    base = _vp(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True, per_edge=True)
     assert base.balanced + base.unbalanced == base.total
     assert base.expansions == g.m
     # unsigned total = the count with every sign positive
@@ -198,14 +224,23 @@ def test_invariants(seed):
     for arr, tot in ((base.bal_u, base.balanced), (base.bal_v, base.balanced),
                      (base.unb_u, base.unbalanced), (base.unb_v, base.unbalanced)):
         assert int(arr.sum()) == 2 * tot
+    # per-edge sums: four edges per butterfly, and two of them at each of its
+    # vertices
+    assert int(base.bal_e.sum()) == 4 * base.balanced
+    assert int(base.unb_e.sum()) == 4 * base.unbalanced
+    for per_e, pu_, pv_ in ((base.bal_e, base.bal_u, base.bal_v),
+                            (base.unb_e, base.unb_u, base.unb_v)):
+        assert np.array_equal(np.bincount(g.u, per_e, g.n_u).astype(np.int64), 2 * pu_)
+        assert np.array_equal(np.bincount(g.v, per_e, g.n_v).astype(np.int64), 2 * pv_)
     rng = np.random.default_rng(seed)
     # switching: negate every edge at a random set of vertices
     flip_u = rng.random(g.n_u) < 0.5
     flip_v = rng.random(g.n_v) < 0.5
     s2 = g.sign * np.where(flip_u[g.u] ^ flip_v[g.v], -1, 1).astype(np.int8)
-    sw = _vp(g.n_u, g.n_v, g.u, g.v, s2, per_vertex=True)
+    sw = _vp(g.n_u, g.n_v, g.u, g.v, s2, per_vertex=True, per_edge=True)
     assert (sw.balanced, sw.unbalanced) == (base.balanced, base.unbalanced)
     assert np.array_equal(sw.bal_u, base.bal_u) and np.array_equal(sw.unb_v, base.unb_v)
+    assert np.array_equal(sw.bal_e, base.bal_e) and np.array_equal(sw.unb_e, base.unb_e)
     # any strict total order (Theorem 1): random tie-break ids and random
     # degree-free orders give the same totals
     ids = rng.permutation(g.n_u + g.n_v).astype(np.int64)
@@ -220,8 +255,9 @@ def test_invariants(seed):
     assert (r.balanced, r.unbalanced) == (base.balanced, base.unbalanced)
     # edge order does not matter
     perm = rng.permutation(g.m)
-    r = _vp(g.n_u, g.n_v, g.u[perm], g.v[perm], g.sign[perm])
+    r = _vp(g.n_u, g.n_v, g.u[perm], g.v[perm], g.sign[perm], per_edge=True)
     assert (r.balanced, r.unbalanced, r.wedges) == (base.balanced, base.unbalanced, base.wedges)
+    assert np.array_equal(r.bal_e, base.bal_e[perm]) and np.array_equal(r.unb_e, base.unb_e[perm])
 
 
 def test_disjoint_union_is_additive():
