@@ -332,6 +332,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-pv", action="store_true", help="skip the per-vertex pass")
+    ap.add_argument("--no-pe", action="store_true", help="skip the per-edge pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (for scaling the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -497,6 +498,22 @@ def main():
         out["per_vertex"] = {"ms_per_pass": ms_pv, "gwedges_per_s": w_vp / (ms_pv / 1e3) / 1e9,
                              "side_sums_equal_twice_counts": sums_ok}
         log(f"[bench] per-vertex pass {ms_pv:.2f} ms ({w_vp / ms_pv / 1e6:.1f} GWedges/s)")
+    if not args.no_pe:
+        # the per-edge pass (the per-vertex pass plus a credit per wedge edge)
+        pe0 = h.count_per_edge()
+        assert tuple(pe0[0]) == tuple(first), "per-edge pass counts differ"
+        sums_ok = int(pe0[1].sum()) == 4 * first.balanced and int(pe0[2].sum()) == 4 * first.unbalanced
+        del pe0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            h.count_per_edge()
+        torch.cuda.synchronize()
+        ms_pe = (time.perf_counter() - t) * 1e3 / reps
+        out["per_edge"] = {"ms_per_pass": ms_pe, "gwedges_per_s": w_vp / (ms_pe / 1e3) / 1e9,
+                           "sums_equal_four_times_counts": sums_ok}
+        log(f"[bench] per-edge pass {ms_pe:.2f} ms ({w_vp / ms_pe / 1e6:.1f} GWedges/s)")
     h.close()
     if not args.no_batch:
         out["batched"] = bench_batched(dbbc, args.steps, args.warmup, args.batch_graphs, 64)

@@ -159,6 +159,26 @@ int dbbc_count(dbbc_graph *g, const dbbc_options *opt, dbbc_counts *out_host, vo
 int dbbc_count_per_vertex(dbbc_graph *g, const dbbc_options *opt, int64_t *bal_u, int64_t *bal_v,
                           int64_t *unb_u, int64_t *unb_v, dbbc_counts *out_host, void *hip_stream);
 
+/* Per-edge counts (Section I, Applications: the butterflies an edge takes
+ * part in, the measure of the wing decomposition): for every input record i,
+ * the number of balanced and of unbalanced butterflies that contain the
+ * edge (u[i], v[i]).  The same pass as dbbc_count_per_vertex: a butterfly
+ * of a pair is the union of two of the pair's wedges, so each edge of a
+ * symmetric wedge lies in p - 1 balanced and n unbalanced butterflies of the
+ * pair, each edge of an asymmetric wedge in n - 1 and p.  Each butterfly has
+ * four edges, so the entries sum to four times the global counts.
+ *   opt      : as for dbbc_count_per_vertex
+ *   bal_e, unb_e: m int64 values each (m = the records passed to
+ *              dbbc_graph_create, duplicates included), in input record
+ *              order, caller-owned device memory; either may be NULL; they
+ *              are overwritten.  A record dropped as a duplicate reads 0
+ *              (the last record of the pair carries the edge's counts).
+ *   out_host : the global counts of the same pass (host memory, may be NULL)
+ * Besides the per-vertex pass's state, the handle keeps four int64 arrays
+ * and two int32 maps of the edge count on the device. */
+int dbbc_count_per_edge(dbbc_graph *g, const dbbc_options *opt, int64_t *bal_e, int64_t *unb_e,
+                        dbbc_counts *out_host, void *hip_stream);
+
 /* Build the handle's counting plan for opt now (NULL = defaults), so that
  * the next count with the same options starts at once; returns when the plan
  * is on the device.  Counts re-plan by themselves when the options change. */

@@ -36,7 +36,7 @@ DBBC_BATCH_CAPTURE = 0x1
 # every symbol declared in include/dbbc.h
 EXPORTS = (
     "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async", "dbbc_count_read",
-    "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_reset", "dbbc_batch_launch",
+    "dbbc_count_per_vertex", "dbbc_count_per_edge", "dbbc_batch_create", "dbbc_batch_reset", "dbbc_batch_launch",
     "dbbc_batch_read",
     "dbbc_batch_count", "dbbc_batch_size", "dbbc_batch_destroy", "dbbc_count_batch", "dbbc_autotune",
     "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string", "dbbc_last_error",
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_count.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_per_vertex.argtypes = [vp, ctypes.POINTER(Options), vp, vp, vp, vp,
                                           ctypes.POINTER(_Counts), vp]
+    lib.dbbc_count_per_edge.argtypes = [vp, ctypes.POINTER(Options), vp, vp,
+                                        ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
     lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
@@ -158,7 +160,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_last_error.restype = ctypes.c_char_p
     lib.dbbc_version.restype = ctypes.c_char_p
     for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async",
-                 "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_batch_create", "dbbc_batch_reset",
+                 "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_count_per_edge",
+                 "dbbc_batch_create", "dbbc_batch_reset",
                  "dbbc_batch_launch",
                  "dbbc_batch_read", "dbbc_batch_count", "dbbc_count_batch", "dbbc_autotune",
                  "dbbc_last_kernel_times", "dbbc_graph_plan", "dbbc_server_create",
@@ -247,20 +250,34 @@ def dbbc_count_read(g: int) -> Counts:
     return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
 
 
+def _out_ptr(t):
+    if t is None:
+        return None
+    if t.dtype != __import__("torch").int64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("per-vertex and per-edge outputs must be contiguous int64 CUDA tensors")
+    return t.data_ptr()
+
+
 def dbbc_count_per_vertex(g: int, bal_u=None, bal_v=None, unb_u=None, unb_v=None,
                           options: Options | None = None, stream=None) -> Counts:
     """Fill caller-owned int64 device tensors (any may be None)."""
-    def p(t):
-        if t is None:
-            return None
-        if t.dtype != __import__("torch").int64 or not t.is_cuda or not t.is_contiguous():
-            raise ValueError("per-vertex outputs must be contiguous int64 CUDA tensors")
-        return t.data_ptr()
+    p = _out_ptr
     c = _Counts()
     opt = ctypes.byref(options) if options is not None else None
     _check(load().dbbc_count_per_vertex(g, opt, p(bal_u), p(bal_v), p(unb_u), p(unb_v),
                                         ctypes.byref(c), _stream_ptr(stream)),
            "dbbc_count_per_vertex")
+    return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
+
+
+def dbbc_count_per_edge(g: int, bal_e=None, unb_e=None, options: Options | None = None,
+                        stream=None) -> Counts:
+    """Fill caller-owned int64 device tensors of one entry per input record
+    (either may be None)."""
+    c = _Counts()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_count_per_edge(g, opt, _out_ptr(bal_e), _out_ptr(unb_e), ctypes.byref(c),
+                                      _stream_ptr(stream)), "dbbc_count_per_edge")
     return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
 
 
@@ -351,6 +368,7 @@ class Graph:
 
     def __init__(self, n_u, n_v, u, v, sign, flags=0, stream=None):
         self.n_u, self.n_v = int(n_u), int(n_v)
+        self.m_in = int(len(u))  # input records, duplicates included
         self.handle = dbbc_graph_create(n_u, n_v, u, v, sign, flags, stream)
 
     def count(self, stream=None, **opts) -> Counts:
@@ -367,6 +385,15 @@ class Graph:
         c = dbbc_count_per_vertex(self.handle, bu, bv, uu, uv, Options(**opts) if opts else None,
                                   stream)
         return c, bu, bv, uu, uv
+
+    def count_per_edge(self, stream=None, **opts):
+        """(Counts, bal_e, unb_e): int64 CUDA tensors, one entry per input record."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        be = torch.empty(self.m_in, dtype=torch.int64, device=dev)
+        ue = torch.empty(self.m_in, dtype=torch.int64, device=dev)
+        c = dbbc_count_per_edge(self.handle, be, ue, Options(**opts) if opts else None, stream)
+        return c, be, ue
 
     def count_async(self, stream=None, **opts) -> None:
         dbbc_count_async(self.handle, Options(**opts) if opts else None, stream)

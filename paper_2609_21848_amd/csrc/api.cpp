@@ -108,6 +108,7 @@ struct DevPlan {
   dbbc::HostPlan host;
   DevBuf segs, small_segs, small_groups, direct_items, hash_items, reverse_items, reduces, acc, sides;
   DevBuf seg_mid, small_seg_mid, small_owner;  // per-vertex plans
+  DevBuf seg_edge, small_seg_edge;
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
   dbbc::DevSideConst side[2] = {};  // host copy of the side table
@@ -115,7 +116,8 @@ struct DevPlan {
   size_t bytes() const {
     size_t b = segs.bytes + small_segs.bytes + small_groups.bytes + direct_items.bytes +
                hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes + sides.bytes +
-               seg_mid.bytes + small_seg_mid.bytes + small_owner.bytes;
+               seg_mid.bytes + small_seg_mid.bytes + small_owner.bytes + seg_edge.bytes +
+               small_seg_edge.bytes;
     for (int s = 0; s < 2; ++s) b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes;
     return b;
   }
@@ -305,6 +307,9 @@ struct dbbc_graph {
   DevPlan pv_plan;        // plan of the per-vertex pass
   DevBuf orig[2];         // side rank -> input id, per side (per-vertex pass)
   DevBuf pv_out[2][2];    // per-vertex outputs [side][balanced, unbalanced]
+  DevBuf pe_out[2][2];    // per-edge credits by CSR position [side][balanced, unbalanced]
+  DevBuf edge_rec, edge_pos_v;  // U-CSR position -> input record, -> V-CSR position
+  DevBuf pe_tmp;          // stands in for a NULL per-edge output
   std::vector<KernelRec> timers;  // events are reused across timed counts
   size_t timers_used = 0;
   bool timed_valid = false;
@@ -361,6 +366,8 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   HIP_TRY(upload(d.segs, hp.segs, st));
   HIP_TRY(upload(d.seg_mid, hp.seg_mid, st));
   HIP_TRY(upload(d.small_seg_mid, hp.small_seg_mid, st));
+  HIP_TRY(upload(d.seg_edge, hp.seg_edge, st));
+  HIP_TRY(upload(d.small_seg_edge, hp.small_seg_edge, st));
   HIP_TRY(upload(d.small_owner, hp.small_owner, st));
   HIP_TRY(upload(d.small_segs, hp.small_segs, st));
   HIP_TRY(upload(d.small_groups, hp.small_groups, st));
@@ -414,6 +421,12 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
       c.unb = g->pv_out[s][1].as<unsigned long long>();
       c.bal_mid = g->pv_out[1 - s][0].as<unsigned long long>();
       c.unb_mid = g->pv_out[1 - s][1].as<unsigned long long>();
+      c.seg_edge = d.seg_edge.as<uint32_t>();
+      c.small_seg_edge = d.small_seg_edge.as<uint32_t>();
+      c.ebal = g->pe_out[s][0].as<unsigned long long>();
+      c.eunb = g->pe_out[s][1].as<unsigned long long>();
+      c.ebal_o = g->pe_out[1 - s][0].as<unsigned long long>();
+      c.eunb_o = g->pe_out[1 - s][1].as<unsigned long long>();
     }
   }
   HIP_TRY(d.sides.alloc(sizeof(d.side)));
@@ -426,6 +439,10 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   hp.seg_mid.shrink_to_fit();
   hp.small_seg_mid.clear();
   hp.small_seg_mid.shrink_to_fit();
+  hp.seg_edge.clear();
+  hp.seg_edge.shrink_to_fit();
+  hp.small_seg_edge.clear();
+  hp.small_seg_edge.shrink_to_fit();
   hp.small_owner.clear();
   hp.small_owner.shrink_to_fit();
   hp.small_segs.clear();
@@ -643,8 +660,12 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
   s.dups_dropped = g->host.dups_dropped;
   s.max_deg_u = g->host.side[0].max_deg;
   s.max_deg_v = g->host.side[1].max_deg;
-  size_t b = g->ctl.bytes + g->plan.bytes();
-  for (int k = 0; k < 2; ++k) b += g->adj[k].bytes + g->off[k].bytes;
+  size_t b = g->ctl.bytes + g->plan.bytes() + g->pv_plan.bytes() + g->edge_rec.bytes +
+             g->edge_pos_v.bytes + g->pe_tmp.bytes;
+  for (int k = 0; k < 2; ++k) {
+    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes;
+    for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes + g->pe_out[k][j].bytes;
+  }
   s.device_bytes = static_cast<int64_t>(b);
   s.wedges_vp = g->host.wedges_vp;
   s.pivots_active = g->host.pivots_active;
@@ -695,14 +716,19 @@ int dbbc_count_read(dbbc_graph* g, dbbc_counts* out_host) {
   return finish_lone(g, out_host, false);
 }
 
-int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u, int64_t* bal_v,
-                          int64_t* unb_u, int64_t* unb_v, dbbc_counts* out_host, void* hip_stream) {
-  g_last_error.clear();
+}  // extern "C"
+
+namespace {
+
+// The per-vertex pass, with per-edge credits when edge is set: tally and
+// credit walks over every item of the per-vertex plan, then (per-edge) the
+// combination of the two CSRs' credits into input-record order.
+int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][2], bool edge,
+                 int64_t* bal_e, int64_t* unb_e, dbbc_counts* out_host, hipStream_t st) {
   int rc = check_graph(g);
   if (rc != DBBC_OK) return rc;
   if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
     return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   dbbc::PlanParams p;
   uint32_t long_len = 0;
   rc = params_from(g, opt, p, long_len);
@@ -710,20 +736,48 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
   p.per_vertex = true;
   p.hub_T = 0;
   const int32_t n[2] = {g->host.n_u, g->host.n_v};
+  const size_t m = static_cast<size_t>(g->host.m);
   for (int s = 0; s < 2; ++s) {
     if (!g->orig[s].p) HIP_TRY(upload(g->orig[s], g->host.side[s].orig, st));
     for (int k = 0; k < 2; ++k)
       HIP_TRY(g->pv_out[s][k].reserve(static_cast<size_t>(n[s]) * sizeof(unsigned long long)));
   }
+  if (edge) {
+    for (int s = 0; s < 2; ++s)
+      for (int k = 0; k < 2; ++k) HIP_TRY(g->pe_out[s][k].reserve(m * sizeof(unsigned long long)));
+    if (!g->edge_rec.p && m > 0) {
+      const dbbc::HostSide& U = g->host.side[0];
+      const dbbc::HostSide& V = g->host.side[1];
+      std::vector<uint32_t> pos_v(m);
+      for (size_t k = 0; k < m; ++k)
+        pos_v[k] = V.off[U.adj[k] >> 1] + static_cast<uint32_t>(U.rev[k]);
+      HIP_TRY(upload(g->edge_pos_v, pos_v, st));
+      HIP_TRY(upload(g->edge_rec, U.rec, st));
+      HIP_TRY(hipStreamSynchronize(st));  // pos_v leaves scope
+    }
+  }
   rc = ensure_plan_into(g, p, st, g->pv_plan);
   if (rc != DBBC_OK) return rc;
   DevPlan& d = g->pv_plan;
   const dbbc::HostPlan& hp = d.host;
+  // the per-edge buffers may have been allocated after the plan's side table
+  if (edge && d.side[0].ebal != g->pe_out[0][0].as<unsigned long long>()) {
+    for (int s = 0; s < 2; ++s) {
+      d.side[s].ebal = g->pe_out[s][0].as<unsigned long long>();
+      d.side[s].eunb = g->pe_out[s][1].as<unsigned long long>();
+      d.side[s].ebal_o = g->pe_out[1 - s][0].as<unsigned long long>();
+      d.side[s].eunb_o = g->pe_out[1 - s][1].as<unsigned long long>();
+    }
+    HIP_TRY(hipMemcpyAsync(d.sides.p, d.side, sizeof(d.side), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   unsigned long long* ctl = g->ctl.as<unsigned long long>();
   HIP_TRY(dbbc::launch_fill_u64(ctl, kCtlWords, 0ull, st));
   for (int s = 0; s < 2; ++s)
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
       HIP_TRY(dbbc::launch_fill_u64(g->pv_out[s][k].as<unsigned long long>(), static_cast<size_t>(n[s]), 0ull, st));
+      if (edge) HIP_TRY(dbbc::launch_fill_u64(g->pe_out[s][k].as<unsigned long long>(), m, 0ull, st));
+    }
   unsigned long long* err = ctl + kCtlErr;
   uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + kCtlQueues);
   const dbbc::DevSideConst* sides = d.sides.as<dbbc::DevSideConst>();
@@ -741,7 +795,8 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
     a.err = err;
     a.n_items = hi - lo;
     a.long_len = long_len;
-    HIP_TRY(dbbc::launch_pv_direct(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+    const int grid = std::min<int>(cus, std::max(1, a.n_items));
+    HIP_TRY(edge ? dbbc::launch_pe_direct(a, grid, st) : dbbc::launch_pv_direct(a, grid, st));
   }
   // reverse items: one launch per side (their key credits are summed per
   // workgroup for one side's reverse window)
@@ -755,7 +810,8 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
     a.err = err;
     a.n_items = hi - lo;
     a.long_len = long_len;
-    HIP_TRY(dbbc::launch_pv_reverse(a, std::min<int>(cus, std::max(1, (a.n_items + 7) / 8)), st));
+    const int grid = std::min<int>(cus, std::max(1, (a.n_items + 7) / 8));
+    HIP_TRY(edge ? dbbc::launch_pe_reverse(a, grid, st) : dbbc::launch_pv_reverse(a, grid, st));
   }
   {
     dbbc::SmallArgs a{};
@@ -765,7 +821,8 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
     a.err = err;
     a.n_items = hp.n_items_kept[2];
     a.long_len = long_len;
-    HIP_TRY(dbbc::launch_pv_small(a, std::min<int>(3 * cus, std::max(1, (a.n_items + 3) / 4)), st));
+    const int grid = std::min<int>(3 * cus, std::max(1, (a.n_items + 3) / 4));
+    HIP_TRY(edge ? dbbc::launch_pe_small(a, grid, st) : dbbc::launch_pv_small(a, grid, st));
   }
   {
     dbbc::HashArgs a{};
@@ -776,13 +833,38 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
     a.err = err;
     a.n_items = hp.n_items_kept[3];
     a.long_len = long_len;
-    HIP_TRY(dbbc::launch_pv_hash(a, std::min<int>(cus, std::max(1, a.n_items)), st));
+    const int grid = std::min<int>(cus, std::max(1, a.n_items));
+    HIP_TRY(edge ? dbbc::launch_pe_hash(a, grid, st) : dbbc::launch_pv_hash(a, grid, st));
   }
-  int64_t* outs[2][2] = {{bal_u, unb_u}, {bal_v, unb_v}};
+  if (edge) {
+    const size_t m_in = static_cast<size_t>(g->host.m_in);
+    // duplicate records (dropped from the graph) read 0
+    const bool dups = g->host.m_in > g->host.m;
+    dbbc::EdgeCombineArgs a{};
+    for (int s = 0; s < 2; ++s) {
+      a.e_bal[s] = g->pe_out[s][0].as<unsigned long long>();
+      a.e_unb[s] = g->pe_out[s][1].as<unsigned long long>();
+    }
+    a.rec = g->edge_rec.as<uint32_t>();
+    a.pos_v = g->edge_pos_v.as<uint32_t>();
+    a.m = g->host.m;
+    // the combine kernel writes both outputs: a NULL one goes to a buffer of
+    // the graph's
+    DevBuf& tmp = g->pe_tmp;
+    if (!bal_e || !unb_e) HIP_TRY(tmp.reserve(m_in * sizeof(long long)));
+    a.out_bal = reinterpret_cast<long long*>(bal_e ? bal_e : tmp.as<int64_t>());
+    a.out_unb = reinterpret_cast<long long*>(unb_e ? unb_e : tmp.as<int64_t>());
+    if (dups) {
+      if (bal_e) HIP_TRY(dbbc::launch_fill_u64(reinterpret_cast<unsigned long long*>(bal_e), m_in, 0ull, st));
+      if (unb_e) HIP_TRY(dbbc::launch_fill_u64(reinterpret_cast<unsigned long long*>(unb_e), m_in, 0ull, st));
+    }
+    const int grid = static_cast<int>(std::min<int64_t>(8 * cus, std::max<int64_t>(1, (a.m + 255) / 256)));
+    HIP_TRY(dbbc::launch_edge_combine(a, grid, st));
+  }
   for (int s = 0; s < 2; ++s)
     for (int k = 0; k < 2; ++k)
-      if (outs[s][k])
-        HIP_TRY(hipMemcpyAsync(outs[s][k], g->pv_out[s][k].p, static_cast<size_t>(n[s]) * sizeof(int64_t),
+      if (vout[s][k])
+        HIP_TRY(hipMemcpyAsync(vout[s][k], g->pv_out[s][k].p, static_cast<size_t>(n[s]) * sizeof(int64_t),
                                hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(g->pinned, g->ctl.p, kCtlWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -791,6 +873,24 @@ int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u
   if (rc != DBBC_OK) return rc;
   if (out_host) *out_host = c;
   return DBBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u, int64_t* bal_v,
+                          int64_t* unb_u, int64_t* unb_v, dbbc_counts* out_host, void* hip_stream) {
+  g_last_error.clear();
+  int64_t* const outs[2][2] = {{bal_u, unb_u}, {bal_v, unb_v}};
+  return local_counts(g, opt, outs, false, nullptr, nullptr, out_host, static_cast<hipStream_t>(hip_stream));
+}
+
+int dbbc_count_per_edge(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_e, int64_t* unb_e,
+                        dbbc_counts* out_host, void* hip_stream) {
+  g_last_error.clear();
+  int64_t* const outs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  return local_counts(g, opt, outs, true, bal_e, unb_e, out_host, static_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

@@ -84,6 +84,7 @@ int build_host_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, cons
   g.n_u = n_u;
   g.n_v = n_v;
   g.m = me;
+  g.m_in = m;
   g.dups_dropped = dups;
 
   // Degrees and the priority order of Definition 3 within each side.
@@ -175,6 +176,8 @@ int build_host_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, cons
       V.rev[pv] = static_cast<int32_t>(static_cast<uint32_t>(k) - U.off[ru]);
     }
   }
+  // the input record of every U entry (per-edge outputs are by record)
+  U.rec = std::move(by_u);
 
   // cut: neighbours of higher priority form a prefix of each row.
   auto fill_cut = [&](HostSide& S, const HostSide& O) {

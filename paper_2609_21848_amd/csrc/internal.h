@@ -23,12 +23,14 @@ struct HostSide {
   std::vector<int32_t> cut;    // per row: number of neighbours of higher priority
   std::vector<int32_t> grank;  // side rank -> rank in the merged order of both sides
   std::vector<int32_t> orig;   // side rank -> input id
+  std::vector<uint32_t> rec;   // per entry: the input record it came from (U side only)
   int64_t max_deg = 0;
 };
 
 struct HostGraph {
   int32_t n_u = 0, n_v = 0;
-  int64_t m = 0;
+  int64_t m = 0;       // distinct edges
+  int64_t m_in = 0;    // input records (duplicates included)
   int64_t dups_dropped = 0;
   int64_t wedges_vp = 0;
   int64_t pivots_active = 0;
@@ -128,9 +130,12 @@ struct HostPlan {
   std::vector<Item> small_items;   // items counted with per-wavefront hash counters
   std::vector<Item> small_groups;  // ... packed into groups (segments in small_segs)
   std::vector<Segment> small_segs; // tagged segments of the groups
-  // per-vertex plans only: the mid (row) of every run, and the owner of
-  // every item of every group (a group's owners start at its acc_slot)
+  // per-vertex plans only: the mid (row) of every run, the position of the
+  // run's first edge in its side's CSR (the pivot-mid edge of forward runs,
+  // the endpoint-mid edge of reverse runs), and the owner of every item of
+  // every group (a group's owners start at its acc_slot)
   std::vector<uint32_t> seg_mid, small_seg_mid;
+  std::vector<uint32_t> seg_edge, small_seg_edge;
   std::vector<int32_t> small_owner;
   int32_t key_bits[2] = {1, 1};    // per side: bits of a side rank in a group hash key
   std::vector<Item> direct_items;  // workgroup direct arrays over [0, L)

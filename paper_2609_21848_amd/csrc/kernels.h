@@ -49,6 +49,15 @@ struct DevSideConst {
   unsigned long long* unb;
   unsigned long long* bal_mid;    // ... of the other side
   unsigned long long* unb_mid;
+  // per-edge credits (per-edge pass only): every wedge credits its two
+  // edges, the run's first edge (a position in side s's CSR) and the walked
+  // entry (a position in the other side's CSR)
+  const uint32_t* seg_edge;       // position of every run's first edge in side s's CSR
+  const uint32_t* small_seg_edge; // ... of every run of small_segs
+  unsigned long long* ebal;       // [m] by position in side s's CSR
+  unsigned long long* eunb;
+  unsigned long long* ebal_o;     // [m] by position in the other side's CSR
+  unsigned long long* eunb_o;
 };
 
 struct DirectArgs {
@@ -121,6 +130,26 @@ hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st);
 hipError_t launch_pv_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st);
+// Per-edge outputs by input record: out[rec[k]] = e[0][k] + e[1][pos_v[k]]
+// over the U-CSR positions k (e[s] holds the credits by position in side s's
+// CSR; records dropped as duplicates are not written).
+struct EdgeCombineArgs {
+  const unsigned long long* e_bal[2];
+  const unsigned long long* e_unb[2];
+  const uint32_t* rec;    // [m] input record of U-CSR entry k
+  const uint32_t* pos_v;  // [m] position of the same edge in the V CSR
+  long long* out_bal;     // [m_in] by input record
+  long long* out_unb;
+  int64_t m;
+};
+
+// The per-vertex pass with per-edge credits as well (the same plans).
+hipError_t launch_pe_direct(const DirectArgs& a, int grid, hipStream_t st);
+hipError_t launch_pe_reverse(const SmallArgs& a, int grid, hipStream_t st);
+hipError_t launch_pe_small(const SmallArgs& a, int grid, hipStream_t st);
+hipError_t launch_pe_hash(const HashArgs& a, int grid, hipStream_t st);
+hipError_t launch_edge_combine(const EdgeCombineArgs& a, int grid, hipStream_t st);
+
 // Copy k graphs' item lists (or reduce lists) into one list, setting each
 // entry's graph field.
 hipError_t launch_assemble_items(const AssembleSrc* srcs, int k, Item* dst, hipStream_t st);

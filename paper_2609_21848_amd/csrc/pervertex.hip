@@ -22,6 +22,14 @@
 // 64-bit atomic per run; key and owner credits are one atomic per nonzero
 // pair and per item.  Walk tags here are (item index in group << 7) |
 // (run lane << 1) | g.
+//
+// Per-edge counts (the edge measure of the same section, kEdge): a wedge's
+// share (p - 1 and n, or n - 1 and p) is also the number of butterflies of
+// the pair that contain each of its two edges, since such a butterfly is the
+// union of this wedge and one other wedge of the pair.  The run's first edge
+// takes the run's summed share with the mid; the walked entry's edge takes
+// its wedge's share, one 64-bit atomic per nonzero value, at its position in
+// the other side's CSR.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -33,28 +41,44 @@
 namespace dbbc {
 namespace dev {
 
-// The runs k0 .. k1 - 1 of a batch with per-vertex tags, and each lane's mid.
-template <bool kTagged>
+// The runs k0 .. k1 - 1 of a batch with per-vertex tags, and each lane's mid
+// (and, with kEdge, the position of its first edge).
+struct RunEnds {
+  uint32_t mid = 0, edge = 0;
+};
+
+template <bool kTagged, bool kEdge>
 __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
-                                              const uint32_t* __restrict__ mids, uint32_t k0, uint32_t k1,
-                                              uint32_t& mid) {
+                                              const uint32_t* __restrict__ mids,
+                                              const uint32_t* __restrict__ edges, uint32_t k0, uint32_t k1,
+                                              RunEnds& re) {
   SegReg r = load_seg<kTagged>(segs, k0, k1);
   const uint32_t lane = static_cast<uint32_t>(lane_id());
   const uint32_t g = r.tag & 1u;
   r.tag = kTagged ? (((r.tag >> 1) << 7) | (lane << 1) | g) : ((lane << 1) | g);
-  mid = k0 + lane < k1 ? as_global(mids)[k0 + lane] : 0u;
+  const bool in = k0 + lane < k1;
+  re.mid = in ? as_global(mids)[k0 + lane] : 0u;
+  if (kEdge) re.edge = in ? as_global(edges)[k0 + lane] : 0u;
   return r;
 }
 
 // Credit walk: Look(e, tag, p, n) gives the pair counts of a wedge's key
 // (false: the key is not counted by this item or pass).  Credits of the
 // lane's current run are kept in registers and added to the run's LDS slot
-// when the lane moves to another run.
-template <class Look>
+// when the lane moves to another run; with kEdge every wedge's share is
+// also added to the walked entry's edge (eb, eu: by entry position).
+// Non-returning 64-bit add to global memory (device scope).
+__device__ __forceinline__ void add_global(global_t<unsigned long long>* p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class Look, bool kEdge>
 struct Credit {
   Look look;
   unsigned long long* cb;  // per-wavefront LDS: balanced credit per run lane
   unsigned long long* cu;  // unbalanced
+  global_t<unsigned long long>* eb;
+  global_t<unsigned long long>* eu;
   uint32_t cur = 0xffffffffu;
   unsigned long long sb = 0, su = 0;
   __device__ __forceinline__ void put() {
@@ -64,7 +88,7 @@ struct Credit {
     }
     sb = su = 0;
   }
-  __device__ __forceinline__ void add(uint32_t e, uint32_t tag, bool valid) {
+  __device__ __forceinline__ void add(uint32_t e, uint32_t tag, bool valid, uint32_t pos) {
     uint32_t p, n;
     if (!valid || !look(e, tag, p, n)) return;
     const uint32_t j = (tag >> 1) & 63u;
@@ -72,12 +96,14 @@ struct Credit {
       put();
       cur = j;
     }
-    if (((e ^ tag) & 1u) == 0) {  // symmetric wedge
-      sb += p - 1u;
-      su += n;
-    } else {
-      sb += n - 1u;
-      su += p;
+    const bool sym = ((e ^ tag) & 1u) == 0;
+    const uint32_t b = sym ? p - 1u : n - 1u;
+    const uint32_t u = sym ? n : p;
+    sb += b;
+    su += u;
+    if (kEdge) {
+      if (b) add_global(eb + pos, b);
+      if (u) add_global(eu + pos, u);
     }
   }
   __device__ __forceinline__ void flush() {
@@ -86,14 +112,17 @@ struct Credit {
   }
 };
 
-template <class Look>
-__device__ __forceinline__ Credit<Look> credit(Look l, unsigned long long* cb, unsigned long long* cu) {
-  Credit<Look> c{l, cb, cu};
+template <bool kEdge, class Look>
+__device__ __forceinline__ Credit<Look, kEdge> credit(Look l, unsigned long long* cb, unsigned long long* cu,
+                                                      const DevSideConst& sc) {
+  Credit<Look, kEdge> c{l, cb, cu, as_global(sc.ebal_o), as_global(sc.eunb_o)};
   return c;
 }
 
-// After a batch's credit walk: each lane adds its run's credits to the mid.
-__device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsigned long long* cu, uint32_t mid,
+// After a batch's credit walk: each lane adds its run's credits to the mid
+// (and, with kEdge, to the run's first edge).
+template <bool kEdge>
+__device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsigned long long* cu, RunEnds re,
                                                   const DevSideConst& sc) {
   wave_sync_lds();
   const int lane = lane_id();
@@ -101,9 +130,13 @@ __device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsign
   if (b | u) {
     cb[lane] = 0;
     cu[lane] = 0;
-    const int32_t id = sc.orig_mid[mid];
+    const int32_t id = sc.orig_mid[re.mid];
     if (b) atomicAdd(&sc.bal_mid[id], b);
     if (u) atomicAdd(&sc.unb_mid[id], u);
+    if (kEdge) {
+      if (b) add_global(as_global(sc.ebal) + re.edge, b);
+      if (u) add_global(as_global(sc.eunb) + re.edge, u);
+    }
   }
   wave_sync_lds();
 }
@@ -142,6 +175,7 @@ constexpr int kPVDirectThreads = 1024;
 constexpr int kPVHotKeys = 2048;
 constexpr int kPVDirectWaves = kPVDirectThreads / kWave;
 
+template <bool kEdge>
 __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
   __shared__ uint32_t P[kPVWindow], N[kPVWindow];
   __shared__ uint32_t mbase[kPVDirectWaves][kGather];
@@ -177,8 +211,8 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     // tally
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      uint32_t mid;
-      const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
+      RunEnds re;
+      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
       walk_regs<4>(sr, sc.other_adj, mk, a.long_len,
                    hash_tally([&](uint32_t e, uint32_t tag) {
                      const uint32_t key = e >> 1;
@@ -189,9 +223,9 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     // credit the mids
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      uint32_t mid;
-      const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
-      auto c = credit(
+      RunEnds re;
+      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
+      auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;
             if (key < lo || key >= hi) return false;
@@ -199,10 +233,10 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
             n = N[key - lo];
             return true;
           },
-          cb[wave], cu[wave]);
+          cb[wave], cu[wave], sc);
       walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
-      flush_mid_credits(cb[wave], cu[wave], mid, sc);
+      flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
     __syncthreads();
     // credit the keys and the owner
@@ -252,6 +286,7 @@ constexpr int kPVReverseThreads = 512;
 constexpr int kPVReverseWaves = kPVReverseThreads / kWave;
 constexpr int kPVReverseWords = kMaxReverseL / 2;
 
+template <bool kEdge>
 __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kPVReverseWaves][kPVReverseWords];
   __shared__ uint32_t mbase[kPVReverseWaves][kGather];
@@ -283,16 +318,16 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      uint32_t mid;
-      walk_regs<4>(load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid), sc.other_adj, mk, a.long_len,
+      RunEnds re;
+      walk_regs<4>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj, mk, a.long_len,
                    PairTally{C});
     }
     wave_sync_lds();
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      uint32_t mid;
-      const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
-      auto c = credit(
+      RunEnds re;
+      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
+      auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;
             const uint32_t h = C[key >> 1] >> ((key & 1u) << 4);
@@ -300,10 +335,10 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
             n = (h >> 8) & 0xffu;
             return true;
           },
-          cb[wave], cu[wave]);
+          cb[wave], cu[wave], sc);
       walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
-      flush_mid_credits(cb[wave], cu[wave], mid, sc);
+      flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
     PairCredit pc;
     auto local = [&](uint32_t key, uint32_t p, uint32_t n) {
@@ -348,6 +383,7 @@ constexpr int kPVSmallThreads = 256;
 constexpr int kPVSmallWaves = kPVSmallThreads / kWave;
 constexpr int kPVSmallSlots = 2 * kSmallGroupWork;
 
+template <bool kEdge>
 __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
   __shared__ uint32_t keys[kPVSmallWaves][kPVSmallSlots];
   __shared__ uint32_t vals[kPVSmallWaves][kPVSmallSlots];
@@ -387,8 +423,8 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
     auto hkey = [&](uint32_t e, uint32_t tag) { return ((tag >> 7) << kb) | (e >> 1); };
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      uint32_t mid;
-      walk_regs<4>(load_seg_pv<true>(sc.small_segs, sc.small_seg_mid, k0, k1, mid), sc.other_adj, mk,
+      RunEnds re;
+      walk_regs<4>(load_seg_pv<true, kEdge>(sc.small_segs, sc.small_seg_mid, sc.small_seg_edge, k0, k1, re), sc.other_adj, mk,
                    a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
                      const uint32_t key = hkey(e, tag);
                      const uint32_t inc = ((e ^ tag) & 1u) ? 0x10000u : 1u;
@@ -414,9 +450,9 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
     wave_sync_lds();
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      uint32_t mid;
-      const SegReg sr = load_seg_pv<true>(sc.small_segs, sc.small_seg_mid, k0, k1, mid);
-      auto c = credit(
+      RunEnds re;
+      const SegReg sr = load_seg_pv<true, kEdge>(sc.small_segs, sc.small_seg_mid, sc.small_seg_edge, k0, k1, re);
+      auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t tag, uint32_t& p, uint32_t& n) {
             const uint32_t key = hkey(e, tag);
             uint32_t h = mix32(key) & mask;
@@ -432,10 +468,10 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
             atomicOr(a.err, kErrHashFull);  // a tallied key must be there
             return false;
           },
-          cb[wave], cu[wave]);
+          cb[wave], cu[wave], sc);
       walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
-      flush_mid_credits(cb[wave], cu[wave], mid, sc);
+      flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
     const uint32_t kmask = (1u << kb) - 1u;
     for (uint32_t h = lane; h < size; h += kWave) {
@@ -464,6 +500,7 @@ constexpr int kPVHashThreads = 512;
 constexpr int kPVHashWaves = kPVHashThreads / kWave;
 constexpr int kPVHashSlots = 8192;
 
+template <bool kEdge>
 __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
   __shared__ uint32_t keys[kPVHashSlots];
   __shared__ unsigned long long vals[kPVHashSlots];
@@ -514,8 +551,8 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
       };
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        uint32_t mid;
-        walk_regs<4>(load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid), sc.other_adj, mk, a.long_len,
+        RunEnds re;
+        walk_regs<4>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj, mk, a.long_len,
                      hash_tally([&](uint32_t e, uint32_t tag) {
                        const uint32_t key = e >> 1;
                        uint32_t hk;
@@ -543,9 +580,9 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
       __syncthreads();
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        uint32_t mid;
-        const SegReg sr = load_seg_pv<false>(sc.segs, sc.seg_mid, k0, k1, mid);
-        auto c = credit(
+        RunEnds re;
+        const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
+        auto c = credit<kEdge>(
             [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
               const uint32_t key = e >> 1;
               uint32_t hk;
@@ -563,10 +600,10 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
               atomicOr(a.err, kErrHashFull);
               return false;
             },
-            cb[wave], cu[wave]);
+            cb[wave], cu[wave], sc);
         walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
         c.flush();
-        flush_mid_credits(cb[wave], cu[wave], mid, sc);
+        flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
       }
       __syncthreads();
       for (int h = tid; h < kPVHashSlots; h += kPVHashThreads) {
@@ -584,29 +621,66 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
   if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
 }
 
+// ---------------------------------------------------------------------------
+// Per-edge outputs in input-record order: each edge's credits from both
+// CSRs (as a run's first edge on one side and as a walked entry on the
+// other) added together.  One thread per U-CSR position, grid-stride.
+__global__ __launch_bounds__(256) void k_edge_combine(EdgeCombineArgs a) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < a.m; k += stride) {
+    const uint32_t r = as_global(a.rec)[k];
+    const uint32_t q = as_global(a.pos_v)[k];
+    as_global(a.out_bal)[r] = static_cast<long long>(as_global(a.e_bal[0])[k] + as_global(a.e_bal[1])[q]);
+    as_global(a.out_unb)[r] = static_cast<long long>(as_global(a.e_unb[0])[k] + as_global(a.e_unb[1])[q]);
+  }
+}
+
 }  // namespace dev
 
-hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st) {
+namespace {
+
+template <bool kEdge>
+hipError_t direct_(const DirectArgs& a, int grid, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::k_pv_direct, dim3(grid), dim3(dev::kPVDirectThreads), 0, st, a);
+  hipLaunchKernelGGL(dev::k_pv_direct<kEdge>, dim3(grid), dim3(dev::kPVDirectThreads), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_pv_reverse(const SmallArgs& a, int grid, hipStream_t st) {
+template <bool kEdge>
+hipError_t reverse_(const SmallArgs& a, int grid, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::k_pv_reverse, dim3(grid), dim3(dev::kPVReverseThreads), 0, st, a);
+  hipLaunchKernelGGL(dev::k_pv_reverse<kEdge>, dim3(grid), dim3(dev::kPVReverseThreads), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st) {
+template <bool kEdge>
+hipError_t small_(const SmallArgs& a, int grid, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::k_pv_small, dim3(grid), dim3(dev::kPVSmallThreads), 0, st, a);
+  hipLaunchKernelGGL(dev::k_pv_small<kEdge>, dim3(grid), dim3(dev::kPVSmallThreads), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st) {
+template <bool kEdge>
+hipError_t hash_(const HashArgs& a, int grid, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::k_pv_hash, dim3(grid), dim3(dev::kPVHashThreads), 0, st, a);
+  hipLaunchKernelGGL(dev::k_pv_hash<kEdge>, dim3(grid), dim3(dev::kPVHashThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st) { return direct_<false>(a, grid, st); }
+hipError_t launch_pv_reverse(const SmallArgs& a, int grid, hipStream_t st) { return reverse_<false>(a, grid, st); }
+hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st) { return small_<false>(a, grid, st); }
+hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st) { return hash_<false>(a, grid, st); }
+hipError_t launch_pe_direct(const DirectArgs& a, int grid, hipStream_t st) { return direct_<true>(a, grid, st); }
+hipError_t launch_pe_reverse(const SmallArgs& a, int grid, hipStream_t st) { return reverse_<true>(a, grid, st); }
+hipError_t launch_pe_small(const SmallArgs& a, int grid, hipStream_t st) { return small_<true>(a, grid, st); }
+hipError_t launch_pe_hash(const HashArgs& a, int grid, hipStream_t st) { return hash_<true>(a, grid, st); }
+
+hipError_t launch_edge_combine(const EdgeCombineArgs& a, int grid, hipStream_t st) {
+  if (a.m == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_edge_combine, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

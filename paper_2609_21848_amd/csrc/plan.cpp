@@ -111,7 +111,10 @@ void pack_small_groups(const HostGraph& g, HostPlan& plan) {
     for (uint32_t k = 0; k < it.seg_count; ++k) {
       const Segment sg = plan.segs[it.seg_begin + k];
       plan.small_segs.push_back(Segment{sg.start, (local << 16) | sg.len_g});
-      if (plan.p.per_vertex) plan.small_seg_mid.push_back(plan.seg_mid[it.seg_begin + k]);
+      if (plan.p.per_vertex) {
+        plan.small_seg_mid.push_back(plan.seg_mid[it.seg_begin + k]);
+        plan.small_seg_edge.push_back(plan.seg_edge[it.seg_begin + k]);
+      }
     }
     if (plan.p.per_vertex) plan.small_owner.push_back(it.owner);
     grp.work += it.work;
@@ -126,12 +129,15 @@ void pack_small_groups(const HostGraph& g, HostPlan& plan) {
 void compact_segments(HostPlan& plan) {
   const bool pv = plan.p.per_vertex;
   std::vector<Segment> out;
-  std::vector<uint32_t> out_mid;
+  std::vector<uint32_t> out_mid, out_edge;
   size_t n = 0;
   for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
     for (const Item& it : *v) n += it.seg_count;
   out.reserve(n);
-  if (pv) out_mid.reserve(n);
+  if (pv) {
+    out_mid.reserve(n);
+    out_edge.reserve(n);
+  }
   for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items}) {
     uint32_t last_begin = 0xffffffffu, last_count = 0, last_new = 0;
     for (Item& it : *v) {
@@ -143,14 +149,18 @@ void compact_segments(HostPlan& plan) {
       last_count = it.seg_count;
       last_new = static_cast<uint32_t>(out.size());
       out.insert(out.end(), plan.segs.begin() + it.seg_begin, plan.segs.begin() + it.seg_begin + it.seg_count);
-      if (pv)
+      if (pv) {
         out_mid.insert(out_mid.end(), plan.seg_mid.begin() + it.seg_begin,
                        plan.seg_mid.begin() + it.seg_begin + it.seg_count);
+        out_edge.insert(out_edge.end(), plan.seg_edge.begin() + it.seg_begin,
+                        plan.seg_edge.begin() + it.seg_begin + it.seg_count);
+      }
       it.seg_begin = last_new;
     }
   }
   plan.segs = std::move(out);
   plan.seg_mid = std::move(out_mid);
+  plan.seg_edge = std::move(out_edge);
 }
 
 }  // namespace
@@ -214,10 +224,14 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     }
 
     // A run of entries of row y (the wedges' mid) whose first edge is the
-    // packed entry first (its negative bit is the run's g).
-    auto add_seg = [&](uint32_t start, uint32_t len, uint32_t first) {
+    // entry e of side s's CSR (its negative bit is the run's g).
+    auto add_seg = [&](uint32_t start, uint32_t len, uint32_t e) {
+      const uint32_t first = S.adj[e];
       plan.segs.push_back(Segment{start, (len << 1) | (first & 1u)});
-      if (pv) plan.seg_mid.push_back(first >> 1);
+      if (pv) {
+        plan.seg_mid.push_back(first >> 1);
+        plan.seg_edge.push_back(e);
+      }
     };
 
     auto place = [&](uint32_t seg_begin, int32_t owner, int32_t key_lo, int32_t key_hi,
@@ -231,7 +245,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       if (nseg == 0 || (nseg < 2 && !(flags & kItemHubPairs))) {
         plan.w_skipped += work;
         plan.segs.resize(seg_begin);
-        if (pv) plan.seg_mid.resize(seg_begin);
+        if (pv) {
+          plan.seg_mid.resize(seg_begin);
+          plan.seg_edge.resize(seg_begin);
+        }
         return;
       }
       plan.w_sparse += work;
@@ -305,7 +322,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           if (hub && static_cast<int32_t>(y) < TO)
             start = std::max(start, O.off[y] + static_cast<uint32_t>(splitT[y]));
           if (end > start)
-            add_seg(start, end - start, S.adj[e]);
+            add_seg(start, end - start, e);
         }
         place(seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
       }
@@ -316,7 +333,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           const uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
           const uint32_t end = O.off[y + 1];
           if (end > start)
-            add_seg(start, end - start, S.adj[e]);
+            add_seg(start, end - start, e);
         }
         place(seg_begin, x, x + 1, S.n, 0u, kForwardTail);
       }
@@ -330,7 +347,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         const uint32_t y = S.adj[e] >> 1;
         const int32_t len = std::min(splitR[y], O.cut[y]);
         if (len > 0)
-          add_seg(O.off[y], static_cast<uint32_t>(len), S.adj[e]);
+          add_seg(O.off[y], static_cast<uint32_t>(len), e);
       }
       place(seg_begin, w, 0, R, 0u, kReverseTail);
       if (R == L) continue;
@@ -339,8 +356,7 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         const uint32_t y = S.adj[e] >> 1;
         const int32_t end = std::min(splitL[y], O.cut[y]);
         if (end > splitR[y])
-          add_seg(O.off[y] + static_cast<uint32_t>(splitR[y]), static_cast<uint32_t>(end - splitR[y]),
-                  S.adj[e]);
+          add_seg(O.off[y] + static_cast<uint32_t>(splitR[y]), static_cast<uint32_t>(end - splitR[y]), e);
       }
       place(seg_begin, w, R, L, 0u, kReverseMid);
     }

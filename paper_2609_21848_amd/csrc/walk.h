@@ -143,7 +143,7 @@ struct Marks {
 };
 
 struct Staged {
-  uint32_t e[kStageU], tag[kStageU];
+  uint32_t e[kStageU], tag[kStageU], pos[kStageU];
   bool valid[kStageU];
 };
 
@@ -177,12 +177,26 @@ __device__ __forceinline__ void stage_round(Staged& s, M mk, uint32_t excl, uint
     s.tag[u] = tg & ~M::kBit;
     const uint32_t t = done + static_cast<uint32_t>(u * kWave + lane);
     s.valid[u] = t < total;
+    s.pos[u] = b + t;
     s.e[u] = as_global(adj)[s.valid[u] ? b + t : 0u];
   }
 }
 
+// Hand one wedge slot to a walk functor: f.add(entry, tag, valid, pos) when
+// the functor takes the entry's position in the CSR array (per-edge
+// credits), else f.add(entry, tag, valid).
+template <class F>
+__device__ __forceinline__ auto walk_add(F& f, uint32_t e, uint32_t tag, bool valid, uint32_t pos, int)
+    -> decltype(f.add(e, tag, valid, pos), void()) {
+  f.add(e, tag, valid, pos);
+}
+template <class F>
+__device__ __forceinline__ void walk_add(F& f, uint32_t e, uint32_t tag, bool valid, uint32_t, long) {
+  f.add(e, tag, valid);
+}
+
 // Walk a batch of up to 64 runs (one per lane, in registers) with one
-// wavefront, calling f.add(entry, tag, valid) once per wedge slot.
+// wavefront, calling f.add(entry, tag, valid[, pos]) once per wedge slot.
 //  - Runs of at least long_len entries are consumed as a stream of
 //    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
 //    chunk, U chunks are in flight per lane, and a chunk's out-of-run words
@@ -244,7 +258,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint32_t idx = vp[u] + q;
-          f.add(e4[q], vg[u], idx >= vst[u] && idx < vend[u]);
+          walk_add(f, e4[q], vg[u], idx >= vst[u] && idx < vend[u], idx, 0);
         }
       }
     }
@@ -254,7 +268,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
     Staged nxt;
     if (more) stage_round(nxt, marks, excl, slen, base, tag, total, done + kGather, adj);
 #pragma unroll
-    for (int u = 0; u < kStageU; ++u) f.add(cur.e[u], cur.tag[u], cur.valid[u]);
+    for (int u = 0; u < kStageU; ++u) walk_add(f, cur.e[u], cur.tag[u], cur.valid[u], cur.pos[u], 0);
     if (!more) break;
     cur = nxt;
   }

@@ -191,7 +191,8 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
 // Outputs are per input id: bal / unb of size n_u + n_v (U first).
 extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
                                const int8_t* sign, int32_t window_L, int32_t reverse_L, int32_t small_work,
-                               int64_t* bal, int64_t* unb, int64_t* out /* 4 */) {
+                               int64_t* bal, int64_t* unb, int64_t* bal_e, int64_t* unb_e,
+                               int64_t* out /* 4 */) {
   HostGraph g;
   std::string err;
   int rc = build_host_graph(n_u, n_v, m, u, v, sign, 0, g, err);
@@ -211,12 +212,22 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
   if (!plan.reduces.empty() || plan.acc_slots != 0) return -120;  // no parts in this plan
   if (plan.seg_mid.size() != plan.segs.size() || plan.small_seg_mid.size() != plan.small_segs.size())
     return -121;
+  if (plan.seg_edge.size() != plan.segs.size() || plan.small_seg_edge.size() != plan.small_segs.size())
+    return -125;
+  // input record of the entry at position q of side s's CSR (V entries map
+  // to their U entry through the reverse positions)
+  auto rec = [&](int s, uint32_t q) -> int64_t {
+    if (s == 0) return g.side[0].rec[q];
+    const uint32_t x = g.side[1].adj[q] >> 1;
+    return g.side[0].rec[g.side[0].off[x] + static_cast<uint32_t>(g.side[1].rev[q])];
+  };
   const int64_t base[2] = {0, n_u};
   Acc acc;
   auto id = [&](int s, uint32_t sr) { return base[s] + g.side[s].orig[sr]; };
   // one item: runs [b, b + c) of segs / mids, key filter, owner lookup
-  auto run = [&](int side, const Segment* segs, const uint32_t* mids, uint32_t b, uint32_t c, int32_t lo,
-                 int32_t hi, bool tagged, const int32_t* owners, int32_t owner, int32_t maxcnt) -> int {
+  auto run = [&](int side, const Segment* segs, const uint32_t* mids, const uint32_t* edges, uint32_t b,
+                 uint32_t c, int32_t lo, int32_t hi, bool tagged, const int32_t* owners, int32_t owner,
+                 int32_t maxcnt) -> int {
     const HostSide& O = g.side[1 - side];
     std::map<std::pair<uint32_t, uint32_t>, std::pair<int64_t, int64_t>> cnt;  // (local, key)
     for (int pass = 0; pass < 2; ++pass) {
@@ -237,8 +248,16 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
             (sym ? pn.first : pn.second)++;
           } else {
             const int64_t mid = id(1 - side, mids[k]);
-            bal[mid] += sym ? pn.first - 1 : pn.second - 1;
-            unb[mid] += sym ? pn.second : pn.first;
+            const int64_t cb = sym ? pn.first - 1 : pn.second - 1, cu = sym ? pn.second : pn.first;
+            bal[mid] += cb;
+            unb[mid] += cu;
+            if (bal_e) {  // the run's first edge and the walked entry's edge
+              const int64_t r0 = rec(side, edges[k]), r1 = rec(1 - side, sg.start + t);
+              bal_e[r0] += cb;
+              unb_e[r0] += cu;
+              bal_e[r1] += cb;
+              unb_e[r1] += cu;
+            }
           }
         }
       }
@@ -265,13 +284,14 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
     for (const Item& it : *list) {
       const int32_t lim = list == &plan.reverse_items ? (int32_t)kReverseMaxSegs : INT32_MAX;
       if (list == &plan.direct_items && it.key_hi - it.key_lo > kPVWindow) return -124;
-      if ((rc = run(it.side, plan.segs.data(), plan.seg_mid.data(), it.seg_begin, it.seg_count, it.key_lo,
-                    it.key_hi, false, nullptr, it.owner, lim)))
+      if ((rc = run(it.side, plan.segs.data(), plan.seg_mid.data(), plan.seg_edge.data(), it.seg_begin,
+                    it.seg_count, it.key_lo, it.key_hi, false, nullptr, it.owner, lim)))
         return rc;
     }
   for (const Item& grp : plan.small_groups) {
-    if ((rc = run(grp.side, plan.small_segs.data(), plan.small_seg_mid.data(), grp.seg_begin, grp.seg_count,
-                  0, INT32_MAX - 1, true, plan.small_owner.data() + grp.acc_slot, 0, 65535)))
+    if ((rc = run(grp.side, plan.small_segs.data(), plan.small_seg_mid.data(), plan.small_seg_edge.data(),
+                  grp.seg_begin, grp.seg_count, 0, INT32_MAX - 1, true, plan.small_owner.data() + grp.acc_slot, 0,
+                  65535)))
       return rc;
   }
   out[0] = acc.bal;

@@ -106,19 +106,24 @@ def emul_pv(tmp_path_factory):
                            os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
-    lib.plan_emulate_pv.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, p, p, p]
+    lib.plan_emulate_pv.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, p, p, p, p, p]
 
-    def run(g, L=-1, R=-1, sw=-1):
+    def run(g, L=-1, R=-1, sw=-1, edges=False):
         n = g.n_u + g.n_v
         bal = np.zeros(n, np.int64)
         unb = np.zeros(n, np.int64)
+        be = np.zeros(g.m, np.int64) if edges else None
+        ue = np.zeros(g.m, np.int64) if edges else None
         out = np.zeros(4, np.int64)
         if R < 0 and L >= 0:
             R = min(L, 4096)
         rc = lib.plan_emulate_pv(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
                                  g.sign.ctypes.data, L, R, sw, bal.ctypes.data, unb.ctypes.data,
-                                 out.ctypes.data)
+                                 None if be is None else be.ctypes.data,
+                                 None if ue is None else ue.ctypes.data, out.ctypes.data)
         assert rc == 0, rc
+        if edges:
+            return out, bal, unb, be, ue
         return out, bal, unb
     return run
 
@@ -157,3 +162,25 @@ def test_per_vertex_plan_key_windows(emul_pv):
     assert (out[0], out[1], out[2]) == (r.balanced, r.unbalanced, r.total)
     assert np.array_equal(bal, np.concatenate([r.bal_u, r.bal_v]))
     assert np.array_equal(unb, np.concatenate([r.unb_u, r.unb_v]))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_per_edge_plan_matches_oracle(emul_pv, seed):
+    # every wedge of the per-vertex plan credits its run's first edge and its
+    # walked entry's edge, found through the positions the plan records
+    rng = np.random.default_rng(90 + seed)
+    g = chung_lu_graph(int(rng.integers(300, 2500)), int(rng.integers(300, 2500)),
+                       int(rng.integers(1000, 30000)), 2.0, 1.9, 0.4, seed=seed)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_edge=True)
+    for L, R, sw in [(-1, -1, -1), (256, 64, 2), (1024, 128, 512)]:
+        out, _, _, be, ue = emul_pv(g, L, R, sw, edges=True)
+        assert np.array_equal(be, r.bal_e), (L, R, sw)
+        assert np.array_equal(ue, r.unb_e), (L, R, sw)
+
+
+def test_per_edge_plan_dense_graph(emul_pv):
+    g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_edge=True)
+    for L, R in [(256, 64), (-1, -1)]:
+        out, _, _, be, ue = emul_pv(g, L, R, edges=True)
+        assert np.array_equal(be, r.bal_e) and np.array_equal(ue, r.unb_e)

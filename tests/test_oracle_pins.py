@@ -12,7 +12,7 @@ from math import comb
 import numpy as np
 import pytest
 
-from oracle import (brute_counts, brute_per_edge, brute_per_vertex, pair_counts,
+from oracle import (brute_counts, brute_per_edge, brute_per_vertex, edge_counts_at, pair_counts,
                     pair_per_vertex, vp_counts)
 from synth import chung_lu_graph, config_graph, uniform_graph
 
@@ -181,6 +181,8 @@ def test_tiers_agree_on_random_tiny_graphs():
                 assert list(a) == list(b) == list(c), seed
             be, ue = brute_per_edge(g.n_u, g.n_v, g.u, g.v, g.sign)
             assert list(r.bal_e) == be and list(r.unb_e) == ue, seed
+            lb, lu = edge_counts_at(g.n_u, g.n_v, g.u, g.v, g.sign, range(g.m))
+            assert lb == be and lu == ue, seed
 
 
 def test_tiers_agree_on_skewed_small_graphs():
@@ -228,6 +230,9 @@ def test_invariants(seed):
     # vertices
     assert int(base.bal_e.sum()) == 4 * base.balanced
     assert int(base.unb_e.sum()) == 4 * base.unbalanced
+    some = np.random.default_rng(seed + 17).choice(g.m, 40, replace=False)
+    lb, lu = edge_counts_at(g.n_u, g.n_v, g.u, g.v, g.sign, some)
+    assert lb == list(base.bal_e[some]) and lu == list(base.unb_e[some])
     for per_e, pu_, pv_ in ((base.bal_e, base.bal_u, base.bal_v),
                             (base.unb_e, base.unb_u, base.unb_v)):
         assert np.array_equal(np.bincount(g.u, per_e, g.n_u).astype(np.int64), 2 * pu_)
