@@ -106,6 +106,10 @@ typedef struct {
 /* dbbc_options.flags: record HIP events around every kernel of a count on
  * the count's stream; read them back with dbbc_last_kernel_times. */
 #define DBBC_OPT_TIME_KERNELS 0x1u
+/* dbbc_options.flags, per-edge pass: keep every edge's credits in two 64-bit
+ * words (the form the pass uses for edges that may lie in 2^32 or more
+ * butterflies) instead of one packed word; for testing the two forms. */
+#define DBBC_OPT_WIDE_EDGES 0x2u
 
 /* One kernel launch of the last timed count and the work it was given. */
 typedef struct {

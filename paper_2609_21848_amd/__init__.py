@@ -31,6 +31,7 @@ DBBC_E_NO_DEVICE = -8
 DBBC_INPUT_DEVICE = 0x1
 DBBC_DUP_REJECT = 0x2
 DBBC_OPT_TIME_KERNELS = 0x1
+DBBC_OPT_WIDE_EDGES = 0x2
 DBBC_BATCH_CAPTURE = 0x1
 
 # every symbol declared in include/dbbc.h

@@ -307,7 +307,7 @@ struct dbbc_graph {
   DevPlan pv_plan;        // plan of the per-vertex pass
   DevBuf orig[2];         // side rank -> input id, per side (per-vertex pass)
   DevBuf pv_out[2][2];    // per-vertex outputs [side][balanced, unbalanced]
-  DevBuf pe_out[2][2];    // per-edge credits by CSR position [side][balanced, unbalanced]
+  DevBuf pe_out[2][3];    // per-edge credits by CSR position [side][packed, wide bal, wide unb]
   DevBuf edge_rec, edge_pos_v;  // U-CSR position -> input record, -> V-CSR position
   DevBuf pe_tmp;          // stands in for a NULL per-edge output
   std::vector<KernelRec> timers;  // events are reused across timed counts
@@ -423,10 +423,12 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
       c.unb_mid = g->pv_out[1 - s][1].as<unsigned long long>();
       c.seg_edge = d.seg_edge.as<uint32_t>();
       c.small_seg_edge = d.small_seg_edge.as<uint32_t>();
-      c.ebal = g->pe_out[s][0].as<unsigned long long>();
-      c.eunb = g->pe_out[s][1].as<unsigned long long>();
-      c.ebal_o = g->pe_out[1 - s][0].as<unsigned long long>();
-      c.eunb_o = g->pe_out[1 - s][1].as<unsigned long long>();
+      c.epack = g->pe_out[s][0].as<unsigned long long>();
+      c.ewb = g->pe_out[s][1].as<unsigned long long>();
+      c.ewu = g->pe_out[s][2].as<unsigned long long>();
+      c.epack_o = g->pe_out[1 - s][0].as<unsigned long long>();
+      c.ewb_o = g->pe_out[1 - s][1].as<unsigned long long>();
+      c.ewu_o = g->pe_out[1 - s][2].as<unsigned long long>();
     }
   }
   HIP_TRY(d.sides.alloc(sizeof(d.side)));
@@ -480,7 +482,8 @@ int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& 
   p = g->defaults;
   long_len = kDefaultLongLen;
   if (!opt) return DBBC_OK;
-  if (opt->flags & ~DBBC_OPT_TIME_KERNELS) return fail(DBBC_E_INVALID_ARG, "unknown dbbc_options flag");
+  if (opt->flags & ~(DBBC_OPT_TIME_KERNELS | DBBC_OPT_WIDE_EDGES))
+    return fail(DBBC_E_INVALID_ARG, "unknown dbbc_options flag");
   if (opt->hub_T >= 0) p.hub_T = opt->hub_T;
   if (opt->window_L >= 0) p.window_L = opt->window_L;
   if (opt->reverse_L >= 0) p.reverse_L = opt->reverse_L;
@@ -664,7 +667,8 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
              g->edge_pos_v.bytes + g->pe_tmp.bytes;
   for (int k = 0; k < 2; ++k) {
     b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes;
-    for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes + g->pe_out[k][j].bytes;
+    for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes;
+    for (int j = 0; j < 3; ++j) b += g->pe_out[k][j].bytes;
   }
   s.device_bytes = static_cast<int64_t>(b);
   s.wedges_vp = g->host.wedges_vp;
@@ -735,6 +739,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   if (rc != DBBC_OK) return rc;
   p.per_vertex = true;
   p.hub_T = 0;
+  p.wide_all = edge && opt && (opt->flags & DBBC_OPT_WIDE_EDGES);
   const int32_t n[2] = {g->host.n_u, g->host.n_v};
   const size_t m = static_cast<size_t>(g->host.m);
   for (int s = 0; s < 2; ++s) {
@@ -744,7 +749,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   }
   if (edge) {
     for (int s = 0; s < 2; ++s)
-      for (int k = 0; k < 2; ++k) HIP_TRY(g->pe_out[s][k].reserve(m * sizeof(unsigned long long)));
+      for (int k = 0; k < 3; ++k) HIP_TRY(g->pe_out[s][k].reserve(m * sizeof(unsigned long long)));
     if (!g->edge_rec.p && m > 0) {
       const dbbc::HostSide& U = g->host.side[0];
       const dbbc::HostSide& V = g->host.side[1];
@@ -761,23 +766,26 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   DevPlan& d = g->pv_plan;
   const dbbc::HostPlan& hp = d.host;
   // the per-edge buffers may have been allocated after the plan's side table
-  if (edge && d.side[0].ebal != g->pe_out[0][0].as<unsigned long long>()) {
+  if (edge && d.side[0].epack != g->pe_out[0][0].as<unsigned long long>()) {
     for (int s = 0; s < 2; ++s) {
-      d.side[s].ebal = g->pe_out[s][0].as<unsigned long long>();
-      d.side[s].eunb = g->pe_out[s][1].as<unsigned long long>();
-      d.side[s].ebal_o = g->pe_out[1 - s][0].as<unsigned long long>();
-      d.side[s].eunb_o = g->pe_out[1 - s][1].as<unsigned long long>();
+      d.side[s].epack = g->pe_out[s][0].as<unsigned long long>();
+      d.side[s].ewb = g->pe_out[s][1].as<unsigned long long>();
+      d.side[s].ewu = g->pe_out[s][2].as<unsigned long long>();
+      d.side[s].epack_o = g->pe_out[1 - s][0].as<unsigned long long>();
+      d.side[s].ewb_o = g->pe_out[1 - s][1].as<unsigned long long>();
+      d.side[s].ewu_o = g->pe_out[1 - s][2].as<unsigned long long>();
     }
     HIP_TRY(hipMemcpyAsync(d.sides.p, d.side, sizeof(d.side), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
   unsigned long long* ctl = g->ctl.as<unsigned long long>();
   HIP_TRY(dbbc::launch_fill_u64(ctl, kCtlWords, 0ull, st));
-  for (int s = 0; s < 2; ++s)
-    for (int k = 0; k < 2; ++k) {
+  for (int s = 0; s < 2; ++s) {
+    for (int k = 0; k < 2; ++k)
       HIP_TRY(dbbc::launch_fill_u64(g->pv_out[s][k].as<unsigned long long>(), static_cast<size_t>(n[s]), 0ull, st));
-      if (edge) HIP_TRY(dbbc::launch_fill_u64(g->pe_out[s][k].as<unsigned long long>(), m, 0ull, st));
-    }
+    for (int k = 0; k < 3 && edge; ++k)
+      HIP_TRY(dbbc::launch_fill_u64(g->pe_out[s][k].as<unsigned long long>(), m, 0ull, st));
+  }
   unsigned long long* err = ctl + kCtlErr;
   uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + kCtlQueues);
   const dbbc::DevSideConst* sides = d.sides.as<dbbc::DevSideConst>();
@@ -842,8 +850,9 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
     const bool dups = g->host.m_in > g->host.m;
     dbbc::EdgeCombineArgs a{};
     for (int s = 0; s < 2; ++s) {
-      a.e_bal[s] = g->pe_out[s][0].as<unsigned long long>();
-      a.e_unb[s] = g->pe_out[s][1].as<unsigned long long>();
+      a.e_pack[s] = g->pe_out[s][0].as<unsigned long long>();
+      a.e_wb[s] = g->pe_out[s][1].as<unsigned long long>();
+      a.e_wu[s] = g->pe_out[s][2].as<unsigned long long>();
     }
     a.rec = g->edge_rec.as<uint32_t>();
     a.pos_v = g->edge_pos_v.as<uint32_t>();

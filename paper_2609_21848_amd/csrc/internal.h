@@ -107,9 +107,11 @@ struct PlanParams {
   int32_t small_work = 0;
   int32_t part_work = 0;
   bool per_vertex = false;  // plan for the per-vertex pass (no dense block, no parts)
+  bool wide_all = false;    // per-vertex plans: flag every run kMidWide
   bool operator==(const PlanParams& o) const {
     return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
-           small_work == o.small_work && part_work == o.part_work && per_vertex == o.per_vertex;
+           small_work == o.small_work && part_work == o.part_work && per_vertex == o.per_vertex &&
+           wide_all == o.wide_all;
   }
 };
 
@@ -120,6 +122,13 @@ constexpr int32_t kMaxReverseL = 4096;
 // Key window of a direct item of the per-vertex pass (32-bit counters in
 // LDS); wider windows are split into items that share their runs.
 constexpr int32_t kPVWindow = 8192;
+
+// Flag in a per-vertex plan's run mid (seg_mid, small_seg_mid): the mid's
+// degree times the largest degree of the keys' side reaches 2^32, so an edge
+// of the run may lie in 2^32 or more butterflies and its per-edge credits
+// cannot share one 64-bit word (balanced low, unbalanced high).  Side ranks
+// are below 2^30, so the bit is free.
+constexpr uint32_t kMidWide = 1u << 30;
 
 struct HostPlan {
   PlanParams p;

@@ -51,13 +51,17 @@ struct DevSideConst {
   unsigned long long* unb_mid;
   // per-edge credits (per-edge pass only): every wedge credits its two
   // edges, the run's first edge (a position in side s's CSR) and the walked
-  // entry (a position in the other side's CSR)
+  // entry (a position in the other side's CSR).  Credits of runs without the
+  // kMidWide flag go to one word per edge, balanced in the low and
+  // unbalanced in the high 32 bits; those of wide runs to two words.
   const uint32_t* seg_edge;       // position of every run's first edge in side s's CSR
   const uint32_t* small_seg_edge; // ... of every run of small_segs
-  unsigned long long* ebal;       // [m] by position in side s's CSR
-  unsigned long long* eunb;
-  unsigned long long* ebal_o;     // [m] by position in the other side's CSR
-  unsigned long long* eunb_o;
+  unsigned long long* epack;      // [m] by position in side s's CSR
+  unsigned long long* ewb;        // [m] wide balanced
+  unsigned long long* ewu;        // [m] wide unbalanced
+  unsigned long long* epack_o;    // ... by position in the other side's CSR
+  unsigned long long* ewb_o;
+  unsigned long long* ewu_o;
 };
 
 struct DirectArgs {
@@ -132,10 +136,12 @@ hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st);
 // Per-edge outputs by input record: out[rec[k]] = e[0][k] + e[1][pos_v[k]]
 // over the U-CSR positions k (e[s] holds the credits by position in side s's
-// CSR; records dropped as duplicates are not written).
+// CSR, packed and wide words; records dropped as duplicates are not
+// written).
 struct EdgeCombineArgs {
-  const unsigned long long* e_bal[2];
-  const unsigned long long* e_unb[2];
+  const unsigned long long* e_pack[2];
+  const unsigned long long* e_wb[2];
+  const unsigned long long* e_wu[2];
   const uint32_t* rec;    // [m] input record of U-CSR entry k
   const uint32_t* pos_v;  // [m] position of the same edge in the V CSR
   long long* out_bal;     // [m_in] by input record

@@ -28,8 +28,10 @@
 // the pair that contain each of its two edges, since such a butterfly is the
 // union of this wedge and one other wedge of the pair.  The run's first edge
 // takes the run's summed share with the mid; the walked entry's edge takes
-// its wedge's share, one 64-bit atomic per nonzero value, at its position in
-// the other side's CSR.
+// its wedge's share at its position in the other side's CSR, one 64-bit
+// atomic per wedge with both values packed (two for runs flagged kMidWide).
+// The credit walk then reads long runs lane-major, so that the atomics of a
+// wavefront hit consecutive positions.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -44,7 +46,7 @@ namespace dev {
 // The runs k0 .. k1 - 1 of a batch with per-vertex tags, and each lane's mid
 // (and, with kEdge, the position of its first edge).
 struct RunEnds {
-  uint32_t mid = 0, edge = 0;
+  uint32_t mid = 0, edge = 0, wide = 0;
 };
 
 template <bool kTagged, bool kEdge>
@@ -57,8 +59,13 @@ __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
   const uint32_t g = r.tag & 1u;
   r.tag = kTagged ? (((r.tag >> 1) << 7) | (lane << 1) | g) : ((lane << 1) | g);
   const bool in = k0 + lane < k1;
-  re.mid = in ? as_global(mids)[k0 + lane] : 0u;
-  if (kEdge) re.edge = in ? as_global(edges)[k0 + lane] : 0u;
+  const uint32_t m = in ? as_global(mids)[k0 + lane] : 0u;
+  re.mid = m & ~kMidWide;
+  if (kEdge) {
+    re.edge = in ? as_global(edges)[k0 + lane] : 0u;
+    re.wide = m & kMidWide;
+    r.tag |= re.wide;  // the run's wedges carry the flag to the credit walk
+  }
   return r;
 }
 
@@ -66,7 +73,8 @@ __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
 // (false: the key is not counted by this item or pass).  Credits of the
 // lane's current run are kept in registers and added to the run's LDS slot
 // when the lane moves to another run; with kEdge every wedge's share is
-// also added to the walked entry's edge (eb, eu: by entry position).
+// also added to the walked entry's edge (by entry position: packed in ep,
+// or in wb and wu for a wide run).
 // Non-returning 64-bit add to global memory (device scope).
 __device__ __forceinline__ void add_global(global_t<unsigned long long>* p, unsigned long long v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -77,8 +85,9 @@ struct Credit {
   Look look;
   unsigned long long* cb;  // per-wavefront LDS: balanced credit per run lane
   unsigned long long* cu;  // unbalanced
-  global_t<unsigned long long>* eb;
-  global_t<unsigned long long>* eu;
+  global_t<unsigned long long>* ep;
+  global_t<unsigned long long>* wb;
+  global_t<unsigned long long>* wu;
   uint32_t cur = 0xffffffffu;
   unsigned long long sb = 0, su = 0;
   __device__ __forceinline__ void put() {
@@ -102,8 +111,12 @@ struct Credit {
     sb += b;
     su += u;
     if (kEdge) {
-      if (b) add_global(eb + pos, b);
-      if (u) add_global(eu + pos, u);
+      if (tag & kMidWide) {
+        if (b) add_global(wb + pos, b);
+        if (u) add_global(wu + pos, u);
+      } else if (b | u) {
+        add_global(ep + pos, (static_cast<unsigned long long>(u) << 32) | b);
+      }
     }
   }
   __device__ __forceinline__ void flush() {
@@ -115,7 +128,7 @@ struct Credit {
 template <bool kEdge, class Look>
 __device__ __forceinline__ Credit<Look, kEdge> credit(Look l, unsigned long long* cb, unsigned long long* cu,
                                                       const DevSideConst& sc) {
-  Credit<Look, kEdge> c{l, cb, cu, as_global(sc.ebal_o), as_global(sc.eunb_o)};
+  Credit<Look, kEdge> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
   return c;
 }
 
@@ -134,8 +147,12 @@ __device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsign
     if (b) atomicAdd(&sc.bal_mid[id], b);
     if (u) atomicAdd(&sc.unb_mid[id], u);
     if (kEdge) {
-      if (b) add_global(as_global(sc.ebal) + re.edge, b);
-      if (u) add_global(as_global(sc.eunb) + re.edge, u);
+      if (re.wide) {
+        if (b) add_global(as_global(sc.ewb) + re.edge, b);
+        if (u) add_global(as_global(sc.ewu) + re.edge, u);
+      } else {  // the run's credits are below 2^32 (no wide flag)
+        add_global(as_global(sc.epack) + re.edge, (u << 32) | b);
+      }
     }
   }
   wave_sync_lds();
@@ -234,7 +251,7 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
             return true;
           },
           cb[wave], cu[wave], sc);
-      walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+      walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
@@ -336,7 +353,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
             return true;
           },
           cb[wave], cu[wave], sc);
-      walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+      walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
@@ -420,7 +437,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
     while (size < 2 * it.work) size <<= 1;
     const uint32_t mask = size - 1;
     const uint32_t seg_end = it.seg_begin + it.seg_count;
-    auto hkey = [&](uint32_t e, uint32_t tag) { return ((tag >> 7) << kb) | (e >> 1); };
+    auto hkey = [&](uint32_t e, uint32_t tag) { return (((tag & ~kMidWide) >> 7) << kb) | (e >> 1); };
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
@@ -469,7 +486,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
             return false;
           },
           cb[wave], cu[wave], sc);
-      walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+      walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
@@ -601,7 +618,7 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
               return false;
             },
             cb[wave], cu[wave], sc);
-        walk_regs<4>(sr, sc.other_adj, mk, a.long_len, c);
+        walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
         c.flush();
         flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
       }
@@ -630,8 +647,12 @@ __global__ __launch_bounds__(256) void k_edge_combine(EdgeCombineArgs a) {
   for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < a.m; k += stride) {
     const uint32_t r = as_global(a.rec)[k];
     const uint32_t q = as_global(a.pos_v)[k];
-    as_global(a.out_bal)[r] = static_cast<long long>(as_global(a.e_bal[0])[k] + as_global(a.e_bal[1])[q]);
-    as_global(a.out_unb)[r] = static_cast<long long>(as_global(a.e_unb[0])[k] + as_global(a.e_unb[1])[q]);
+    const unsigned long long p0 = as_global(a.e_pack[0])[k], p1 = as_global(a.e_pack[1])[q];
+    const unsigned long long b = (p0 & 0xffffffffull) + (p1 & 0xffffffffull) + as_global(a.e_wb[0])[k] +
+                                 as_global(a.e_wb[1])[q];
+    const unsigned long long u = (p0 >> 32) + (p1 >> 32) + as_global(a.e_wu[0])[k] + as_global(a.e_wu[1])[q];
+    as_global(a.out_bal)[r] = static_cast<long long>(b);
+    as_global(a.out_unb)[r] = static_cast<long long>(u);
   }
 }
 

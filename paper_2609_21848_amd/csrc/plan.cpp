@@ -229,7 +229,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       const uint32_t first = S.adj[e];
       plan.segs.push_back(Segment{start, (len << 1) | (first & 1u)});
       if (pv) {
-        plan.seg_mid.push_back(first >> 1);
+        const uint32_t y = first >> 1;
+        const uint64_t bound = static_cast<uint64_t>(O.off[y + 1] - O.off[y]) * static_cast<uint64_t>(S.max_deg);
+        const bool wide = p.wide_all || bound >= (uint64_t{1} << 32);
+        plan.seg_mid.push_back(y | (wide ? kMidWide : 0u));
         plan.seg_edge.push_back(e);
       }
     };

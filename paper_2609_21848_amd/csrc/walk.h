@@ -200,11 +200,14 @@ __device__ __forceinline__ void walk_add(F& f, uint32_t e, uint32_t tag, bool va
 //  - Runs of at least long_len entries are consumed as a stream of
 //    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
 //    chunk, U chunks are in flight per lane, and a chunk's out-of-run words
-//    are masked.  The chunk loop is wavefront-uniform.
+//    are masked.  The chunk loop is wavefront-uniform.  With kLaneMajor the
+//    lane's 4 entries are instead 64 apart (four 4-byte loads), so that each
+//    of the 4 calls of a chunk sees 64 consecutive positions across the
+//    lanes (per-position global atomics of a functor then coalesce).
 //  - Shorter runs are staged (stage_round) so that every lane holds wedges;
 //    the loads of the first round are issued before the long stream and the
 //    next round's loads before the current round is tallied.
-template <int U, class M, class F>
+template <int U, bool kLaneMajor = false, class M, class F>
 __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, M marks,
                                           uint32_t long_len, F&& f) {
   const int lane = lane_id();
@@ -237,12 +240,20 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       // lanes past the run's end and empty slots read the first entries of
       // the array, and their words fail the index test below.
       const bool h = have;
-      const uint32_t p = cur_pos + 4 * lane;
+      const uint32_t p = cur_pos + (kLaneMajor ? lane : 4 * lane);
       vst[u] = cur_st;
       vg[u] = cur_g;
       vp[u] = p;
       vend[u] = h ? cur_end : 0u;
-      v[u] = *(const global_t<u32x4>*)(adj + ((h && p < cur_end) ? p : 0u));
+      if (kLaneMajor) {
+        const global_t<uint32_t>* a = as_global(adj);
+        v[u].x = a[(h && p < cur_end) ? p : 0u];
+        v[u].y = a[(h && p + kWave < cur_end) ? p + kWave : 0u];
+        v[u].z = a[(h && p + 2 * kWave < cur_end) ? p + 2 * kWave : 0u];
+        v[u].w = a[(h && p + 3 * kWave < cur_end) ? p + 3 * kWave : 0u];
+      } else {
+        v[u] = *(const global_t<u32x4>*)(adj + ((h && p < cur_end) ? p : 0u));
+      }
       if (h) {
         nv = u + 1;
         cur_pos += kChunk;
@@ -257,7 +268,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const uint32_t idx = vp[u] + q;
+          const uint32_t idx = vp[u] + (kLaneMajor ? q * kWave : q);
           walk_add(f, e4[q], vg[u], idx >= vst[u] && idx < vend[u], idx, 0);
         }
       }

@@ -247,7 +247,7 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
           if (pass == 0) {
             (sym ? pn.first : pn.second)++;
           } else {
-            const int64_t mid = id(1 - side, mids[k]);
+            const int64_t mid = id(1 - side, mids[k] & ~kMidWide);
             const int64_t cb = sym ? pn.first - 1 : pn.second - 1, cu = sym ? pn.second : pn.first;
             bal[mid] += cb;
             unb[mid] += cu;

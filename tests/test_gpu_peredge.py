@@ -18,6 +18,8 @@ from golden_io import GOLDEN, load
 
 pytestmark = pytest.mark.gpu
 
+WIDE = 0x2  # DBBC_OPT_WIDE_EDGES: every edge's credits in two words
+
 
 @pytest.fixture(scope="module")
 def dbbc():
@@ -67,8 +69,9 @@ def test_tiny_graphs_against_brute_force(dbbc):
         g = uniform_graph(n_u, n_v, int(rng.integers(0, n_u * n_v + 1)), float(rng.random()), seed=seed)
         bb, bu = brute_per_edge(g.n_u, g.n_v, g.u, g.v, g.sign)
         _say("tiny pe", seed, n_u, n_v, g.m)
-        c, be, ue = _pe(dbbc, g.n_u, g.n_v, g.u, g.v, g.sign)
-        assert list(be) == bb and list(ue) == bu
+        for opts in ({}, {"flags": WIDE}):
+            c, be, ue = _pe(dbbc, g.n_u, g.n_v, g.u, g.v, g.sign, **opts)
+            assert list(be) == bb and list(ue) == bu, opts
 
 
 def test_duplicate_records(dbbc):
@@ -93,13 +96,15 @@ def test_random_graphs_and_options(dbbc):
                            int(rng.integers(500, 30000)), 2.0, 1.9, 0.4, seed=seed)
         _say("random pe", seed, g.n_u, g.n_v, g.m)
         _check(dbbc, g, ({}, {"window_L": 256, "reverse_L": 64, "small_work": 2},
-                         {"window_L": 512, "long_len": 16}, {"long_len": 65536, "small_work": 64}))
+                         {"window_L": 512, "long_len": 16}, {"long_len": 65536, "small_work": 64},
+                         {"flags": WIDE}, {"window_L": 256, "reverse_L": 64, "small_work": 2,
+                                           "flags": WIDE}))
 
 
 def test_dense_graph_reverse_items_as_direct(dbbc):
     g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
     _say("dense pe")
-    _check(dbbc, g, ({"window_L": 256, "reverse_L": 64}, {}))
+    _check(dbbc, g, ({"window_L": 256, "reverse_L": 64}, {}, {"flags": WIDE}))
 
 
 def test_tiny_workload_key_windows_and_repeat(dbbc):
