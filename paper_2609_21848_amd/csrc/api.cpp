@@ -11,6 +11,7 @@
 #include <unordered_set>
 #include <vector>
 
+#include "build_dev.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -601,50 +602,28 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, con
   g_last_error.clear();
   if (!out) return fail(DBBC_E_INVALID_ARG, "out must not be NULL");
   if (flags & ~(DBBC_INPUT_DEVICE | DBBC_DUP_REJECT)) return fail(DBBC_E_INVALID_ARG, "unknown flag");
+  // argument checks that need no device (the records themselves are checked
+  // by the device build)
+  if (n_u <= 0 || n_v <= 0 || m < 0) return fail(DBBC_E_INVALID_ARG, "n_u and n_v must be positive and m non-negative");
+  if (static_cast<int64_t>(n_u) + n_v >= (int64_t(1) << 30) || m >= (int64_t(1) << 31) - 1)
+    return fail(DBBC_E_TOO_LARGE, "graph too large: need n_u + n_v < 2^30 and m < 2^31 - 1");
+  if (m > 0 && (!u || !v || !sign)) return fail(DBBC_E_INVALID_ARG, "edge arrays must not be NULL");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DeviceInfo di;
-  int rc;
-  if (flags & DBBC_INPUT_DEVICE) {
-    rc = current_device(di);
-    if (rc != DBBC_OK) return rc;
-  }
-  std::vector<int32_t> hu, hv;
-  std::vector<int8_t> hs;
-  if ((flags & DBBC_INPUT_DEVICE) && m > 0) {
-    if (!u || !v || !sign) return fail(DBBC_E_INVALID_ARG, "edge arrays must not be NULL");
-    hu.resize(static_cast<size_t>(m));
-    hv.resize(static_cast<size_t>(m));
-    hs.resize(static_cast<size_t>(m));
-    HIP_TRY(hipMemcpyAsync(hu.data(), u, m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hv.data(), v, m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hs.data(), sign, m * sizeof(int8_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    u = hu.data();
-    v = hv.data();
-    sign = hs.data();
-  }
+  int rc = current_device(di);
+  if (rc != DBBC_OK) return rc;
   std::unique_ptr<dbbc_graph> g(new (std::nothrow) dbbc_graph());
   if (!g) return fail(DBBC_E_OOM, "host allocation failed");
-  std::string err;
-  try {
-    rc = dbbc::build_host_graph(n_u, n_v, m, u, v, sign, flags, g->host, err);
-  } catch (const std::bad_alloc&) {
-    return fail(DBBC_E_OOM, "host allocation failed while building the graph");
-  }
-  if (rc != DBBC_OK) return fail(rc, err);
-  if (!di.ok) {
-    rc = current_device(di);
-    if (rc != DBBC_OK) return rc;
-  }
   g->dev = di;
-  for (int s = 0; s < 2; ++s) {
-    std::vector<uint32_t>& adj = g->host.side[s].adj;
-    const size_t m_side = adj.size();
-    adj.resize(m_side + dbbc::kAdjPad, 0u);  // padding for 16-byte loads
-    hipError_t e = upload(g->adj[s], adj, st);
-    adj.resize(m_side);
-    HIP_TRY(e);
-    HIP_TRY(upload(g->off[s], g->host.side[s].off, st));
+  std::string err;
+  dbbc::DeviceCsr csr;
+  rc = dbbc::build_device_graph(n_u, n_v, m, u, v, sign, flags, st, g->host, csr, err);
+  if (rc != DBBC_OK) return fail(rc, err);
+  for (int s = 0; s < 2; ++s) {  // the handle owns the device CSR from here
+    g->adj[s].p = csr.adj[s];
+    g->adj[s].bytes = csr.adj_bytes[s];
+    g->off[s].p = csr.off[s];
+    g->off[s].bytes = csr.off_bytes[s];
   }
   HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), kCtlWords * sizeof(unsigned long long),

@@ -37,10 +37,8 @@ struct HostGraph {
   HostSide side[2];  // 0 = U, 1 = V
 };
 
-// Build the relabelled CSR pair from an edge list (host memory).  Returns a
-// DBBC status and fills err on failure.
-int build_host_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
-                     const int8_t* sign, uint32_t flags, HostGraph& g, std::string& err);
+// The graph is built on the device (build.hip, build_device_graph); the
+// host keeps the copy above for planning.
 
 // ---- counting plan -----------------------------------------------------------
 

@@ -1,11 +1,13 @@
-// Host construction of the priority-ordered CSR pair (Definition 3 relabel,
-// the paper's Phase 2 "global index" on one device) with the per-entry
-// reverse positions that let a wedge walk start without a search.
+// Test harness (CPU only): the library's host graph (the priority-ordered
+// CSR pair of Definition 3 with per-entry reverse positions, cut, W_VP and
+// the U-entry record map) built in plain loops on the host, so the planner
+// can be checked on the CPU.  The library builds the same layout on the
+// device (build.hip).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
 
-#include "internal.h"
+#include "host_build.h"
 
 namespace dbbc {
 namespace {

@@ -9,7 +9,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../paper_2609_21848_amd/csrc/internal.h"
+#include "host_build.h"
 
 using namespace dbbc;
 

@@ -48,13 +48,8 @@ def _create(n_u, n_v, u, v, s, flags=0):
     return rc, out.value, lib.dbbc_last_error().decode()
 
 
-def test_validation_errors_need_no_device():
-    assert _create(2, 2, [0, 2], [0, 1], [1, 1])[0] == dbbc.DBBC_E_ID_RANGE
-    assert _create(2, 2, [0, 1], [0, -1], [1, 1])[0] == dbbc.DBBC_E_ID_RANGE
-    rc, h, msg = _create(2, 2, [0, 1], [0, 1], [1, 0])
-    assert rc == dbbc.DBBC_E_SIGN and h is None and "sign" in msg
-    rc, _, msg = _create(2, 2, [0, 1, 0], [0, 1, 0], [1, 1, -1], dbbc.DBBC_DUP_REJECT)
-    assert rc == dbbc.DBBC_E_DUPLICATE and "duplicate" in msg
+def test_argument_errors_need_no_device():
+    # (ids, signs and duplicates are checked by the device build: GPU tests)
     assert _create(0, 2, [], [], [])[0] == dbbc.DBBC_E_INVALID_ARG
     assert _create(2**29, 2**29, [0], [0], [1])[0] == dbbc.DBBC_E_TOO_LARGE
     lib = dbbc.load()

@@ -21,7 +21,7 @@ def emul(tmp_path_factory):
     so = str(tmp_path_factory.mktemp("emul") / "plan_emul.so")
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", so,
                            os.path.join(ROOT, "tests", "native", "plan_emul.cpp"),
-                           os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
+                           os.path.join(ROOT, "tests", "native", "host_build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, p]
@@ -103,7 +103,7 @@ def emul_pv(tmp_path_factory):
     so = str(tmp_path_factory.mktemp("emulpv") / "plan_emul.so")
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", so,
                            os.path.join(ROOT, "tests", "native", "plan_emul.cpp"),
-                           os.path.join(CSRC, "build.cpp"), os.path.join(CSRC, "plan.cpp")])
+                           os.path.join(ROOT, "tests", "native", "host_build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.plan_emulate_pv.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, p, p, p, p, p]
