@@ -385,8 +385,8 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
     const int32_t T = hp.T[s], TO = hp.T[1 - s];
     if (T == 0) continue;
     HIP_TRY(d.hub_pairs[s].alloc(static_cast<size_t>(T) * T * sizeof(unsigned long long)));
-    // pad the contraction dimension to a multiple of 64
-    const int32_t K = (TO + 63) / 64 * 64;
+    // pad the contraction dimension to a multiple of kHubKPad
+    const int32_t K = (TO + dbbc::kHubKPad - 1) / dbbc::kHubKPad * dbbc::kHubKPad;
     std::vector<int8_t> B(static_cast<size_t>(T) * K, 0), Bm(static_cast<size_t>(T) * K, 0);
     for (int32_t x = 0; x < T; ++x) {
       std::memcpy(&B[static_cast<size_t>(x) * K], &hp.hub_B[s][static_cast<size_t>(x) * TO], TO);

@@ -25,13 +25,15 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kHubTile = 128;     // output tile (rows x and columns w)
 constexpr int kHubThreads = 256;  // 2 x 2 wavefronts, each 64 x 64 of the tile
-constexpr int kHubKStep = 64;     // k bytes of both operands staged per step
-constexpr int kHubRow = 80;       // LDS bytes per staged row (64 + 16: spreads banks)
+constexpr int kHubKStep = kHubKPad;  // k bytes of both operands staged per step
+constexpr int kHubRow = kHubKStep + 16;  // LDS bytes per staged row (+16 spreads banks)
+constexpr int kHubLoads = kHubTile * kHubKStep / 16 / kHubThreads;  // 16-byte loads per thread and operand
 
 // One 128 x 128 tile of the upper triangle per workgroup.  Each step stages
-// 128 rows x 64 k of Bm (rows x) and of B (rows w) in LDS with coalesced
-// 16-byte loads (4 lanes per row), double-buffered: the next step's loads
-// are in flight while the current step's 16 MFMAs per wavefront run.
+// 128 rows x 128 k of Bm (rows x) and of B (rows w) in LDS with coalesced
+// 16-byte loads (8 lanes per row), double-buffered: the next step's loads
+// are in flight while the current step's 32 MFMAs per wavefront run (a step
+// of 128 k gives each load round trip twice the matrix work of 64 k).
 __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t sA[2][kHubTile * kHubRow];
   __shared__ __attribute__((aligned(16))) int8_t sB[2][kHubTile * kHubRow];
@@ -58,28 +60,28 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
       X[i][j] = v16i{};
       Y[i][j] = v16i{};
     }
-  // staging: chunk c = tid + 256 i (i = 0, 1) is row c / 4, bytes 16 (c % 4)
+  // staging: chunk c = tid + 256 i is row c / 8, bytes 16 (c % 8)
   const size_t K = static_cast<size_t>(a.K);
   const int8_t* gA = a.Bm + static_cast<size_t>(ti * kHubTile) * K;
   const int8_t* gB = a.B + static_cast<size_t>(tj * kHubTile) * K;
-  int srow[2], spart[2];
+  int srow[kHubLoads], spart[kHubLoads];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kHubLoads; ++i) {
     const int c = tid + kHubThreads * i;
-    srow[i] = c >> 2;
-    spart[i] = (c & 3) * 16;
+    srow[i] = c / (kHubKStep / 16);
+    spart[i] = (c % (kHubKStep / 16)) * 16;
   }
-  v4i ra[2], rb[2];
+  v4i ra[kHubLoads], rb[kHubLoads];
   auto gload = [&](int k) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kHubLoads; ++i) {
       ra[i] = *reinterpret_cast<const v4i*>(gA + srow[i] * K + k + spart[i]);
       rb[i] = *reinterpret_cast<const v4i*>(gB + srow[i] * K + k + spart[i]);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kHubLoads; ++i) {
       *reinterpret_cast<v4i*>(&sA[buf][srow[i] * kHubRow + spart[i]]) = ra[i];
       *reinterpret_cast<v4i*>(&sB[buf][srow[i] * kHubRow + spart[i]]) = rb[i];
     }

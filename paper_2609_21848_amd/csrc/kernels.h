@@ -111,14 +111,16 @@ struct AssembleSrc {
 };
 
 // Dense hub block of one side: X = |Bm| |B|^T and Y = Bm B^T over the T_other
-// mids, combined with the sparse hub-pair partials, reduced to res.
+// mids, combined with the sparse hub-pair partials, reduced to res.  The
+// contraction length is padded with zero columns to a multiple of kHubKPad.
+constexpr int32_t kHubKPad = 128;
 struct HubArgs {
   const int8_t* Bm;              // [T x K] row-major, K = padded mid count
   const int8_t* B;               // [T x K]
   const unsigned long long* hub_pairs;  // [T x T] sparse partials
   unsigned long long* res;       // res[0..2] sums, res[3] dense wedges
   int32_t T;                     // rows (pairs side)
-  int32_t K;                     // padded contraction length (multiple of 64)
+  int32_t K;                     // padded contraction length (multiple of kHubKPad)
 };
 
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
