@@ -25,18 +25,24 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kHubTile = 128;     // output tile (rows x and columns w)
 constexpr int kHubThreads = 256;  // 2 x 2 wavefronts, each 64 x 64 of the tile
-constexpr int kHubKStep = kHubKPad;  // k bytes of both operands staged per step
-constexpr int kHubRow = kHubKStep + 16;  // LDS bytes per staged row (+16 spreads banks)
-constexpr int kHubLoads = kHubTile * kHubKStep / 16 / kHubThreads;  // 16-byte loads per thread and operand
+constexpr int kHubKStep = kHubKPad;  // k bytes of both operands per pipeline stage
+constexpr int kHubStages = 4;        // stages in flight (LDS ring)
+constexpr int kHubStage = kHubTile * kHubKStep;  // bytes of one operand per stage
 
-// One 128 x 128 tile of the upper triangle per workgroup.  Each step stages
-// 128 rows x 128 k of Bm (rows x) and of B (rows w) in LDS with coalesced
-// 16-byte loads (8 lanes per row), double-buffered: the next step's loads
-// are in flight while the current step's 32 MFMAs per wavefront run (a step
-// of 128 k gives each load round trip twice the matrix work of 64 k).
+// LDS position of the 16-byte chunk c of a staged row: rows are 64 bytes,
+// chunks permuted by ((row >> 1) ^ (row >> 3)) mod 4 so that the 16-byte
+// operand reads of 8 (or 16) consecutive rows hit distinct banks.
+__device__ __forceinline__ int hub_slot(int row, int c) { return row * kHubKStep + ((c ^ ((row >> 1) ^ (row >> 3))) & 3) * 16; }
+
+// One 128 x 128 tile of the upper triangle per workgroup.  The operands
+// stream through a ring of kHubStages LDS stages (128 rows x 64 k of Bm for
+// rows x and of B for rows w per stage), filled by direct global-to-LDS
+// loads (global_load_lds_dwordx4: no staging registers), kHubStages - 1
+// stages ahead of the matrix work: each wavefront waits only for its own
+// loads of the stage it is about to read, then the workgroup barrier makes
+// every wavefront's part visible.
 __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
-  __shared__ __attribute__((aligned(16))) int8_t sA[2][kHubTile * kHubRow];
-  __shared__ __attribute__((aligned(16))) int8_t sB[2][kHubTile * kHubRow];
+  __shared__ __attribute__((aligned(16))) int8_t sm[kHubStages][2][kHubStage];
   // upper-triangular tile (ti <= tj) from the linear block index
   const int nt = a.T / kHubTile;
   int t = blockIdx.x, ti = 0;
@@ -46,12 +52,11 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
   }
   const int tj = ti + t;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int row0 = ti * kHubTile + (wave >> 1) * 64;
   const int col0 = tj * kHubTile + (wave & 1) * 64;
   const int r = lane & 31;
-  const int kh = (lane >> 5) * 16;
   v16i X[2][2], Y[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -60,48 +65,69 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
       X[i][j] = v16i{};
       Y[i][j] = v16i{};
     }
-  // staging: chunk c = tid + 256 i is row c / 8, bytes 16 (c % 8)
   const size_t K = static_cast<size_t>(a.K);
-  const int8_t* gA = a.Bm + static_cast<size_t>(ti * kHubTile) * K;
-  const int8_t* gB = a.B + static_cast<size_t>(tj * kHubTile) * K;
-  int srow[kHubLoads], spart[kHubLoads];
+  // Loads of one stage: each wavefront fills 2 x 1 KB of each operand; lane
+  // l of part q writes LDS chunk 64 q + l (row (64 q + l) / 4, slot l % 4)
+  // and so fetches the global chunk that belongs in that slot.
+  const int8_t* src[2][2];
+  int dst[2];
 #pragma unroll
-  for (int i = 0; i < kHubLoads; ++i) {
-    const int c = tid + kHubThreads * i;
-    srow[i] = c / (kHubKStep / 16);
-    spart[i] = (c % (kHubKStep / 16)) * 16;
+  for (int q = 0; q < 2; ++q) {
+    const int part = wave * 2 + q;
+    const int S = part * 64 + lane;
+    const int row = S >> 2, slot = S & 3;
+    const int c = (slot ^ ((row >> 1) ^ (row >> 3))) & 3;
+    src[0][q] = a.Bm + static_cast<size_t>(ti * kHubTile + row) * K + c * 16;
+    src[1][q] = a.B + static_cast<size_t>(tj * kHubTile + row) * K + c * 16;
+    dst[q] = part * 1024;
   }
-  v4i ra[kHubLoads], rb[kHubLoads];
-  auto gload = [&](int k) {
+  auto issue = [&](int stage, int k) {
 #pragma unroll
-    for (int i = 0; i < kHubLoads; ++i) {
-      ra[i] = *reinterpret_cast<const v4i*>(gA + srow[i] * K + k + spart[i]);
-      rb[i] = *reinterpret_cast<const v4i*>(gB + srow[i] * K + k + spart[i]);
-    }
-  };
-  auto sstore = [&](int buf) {
+    for (int op = 0; op < 2; ++op)
 #pragma unroll
-    for (int i = 0; i < kHubLoads; ++i) {
-      *reinterpret_cast<v4i*>(&sA[buf][srow[i] * kHubRow + spart[i]]) = ra[i];
-      *reinterpret_cast<v4i*>(&sB[buf][srow[i] * kHubRow + spart[i]]) = rb[i];
-    }
+      for (int q = 0; q < 2; ++q)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[op][q] + k),
+                                         (__attribute__((address_space(3))) void*)(&sm[stage][op][dst[q]]), 16, 0, 0);
   };
-  gload(0);
-  sstore(0);
-  __syncthreads();
+  const int nsteps = a.K / kHubKStep;
+#pragma unroll
+  for (int st = 0; st < kHubStages - 1; ++st)
+    if (st < nsteps) issue(st, st * kHubKStep);
   const v4i ones = {0x01010101, 0x01010101, 0x01010101, 0x01010101};
   const int ar = (wave >> 1) * 64 + r, br = (wave & 1) * 64 + r;
-  for (int k0 = 0, buf = 0; k0 < a.K; k0 += kHubKStep, buf ^= 1) {
-    const bool more = k0 + kHubKStep < a.K;
-    if (more) gload(k0 + kHubKStep);
+  const int ch = lane >> 5;  // the lane's 16-byte chunk within 32 k
+  for (int step = 0; step < nsteps; ++step) {
+    // this wavefront's loads of stage `step` are complete once at most the
+    // loads of the stages after it (issued before this point) are pending
+    const int after = min(nsteps, step + kHubStages - 1) - step - 1;
+    if (after >= 2)
+      __builtin_amdgcn_s_waitcnt(0xF70 | 8);  // vmcnt(8): 4 loads per stage
+    else if (after == 1)
+      __builtin_amdgcn_s_waitcnt(0xF70 | 4);
+    else
+      __builtin_amdgcn_s_waitcnt(0xF70 | 0);
+    // every wavefront's part of the stage is in LDS (each waited for its own
+    // loads above), and every wavefront's reads of the stage read last step
+    // have returned (its matrix work used them), so that stage may be
+    // refilled.  A bare barrier: a __syncthreads fence would also wait for
+    // the loads of the later stages; the empty asm statements keep the
+    // compiler from moving memory accesses across it.
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const int nxt = step + kHubStages - 1;
+    if (nxt < nsteps) issue(nxt % kHubStages, nxt * kHubKStep);
+    const int8_t* sA = sm[step % kHubStages][0];
+    const int8_t* sB = sm[step % kHubStages][1];
 #pragma unroll
-    for (int kk = 0; kk < kHubKStep; kk += 32) {
+    for (int kk = 0; kk < kHubKStep / 16; kk += 2) {
       // a lane feeds 16 consecutive k of its row to both operands, so the
       // two operands agree on which k each byte slot holds
-      const v4i A0 = *reinterpret_cast<const v4i*>(&sA[buf][ar * kHubRow + kk + kh]);
-      const v4i A1 = *reinterpret_cast<const v4i*>(&sA[buf][(ar + 32) * kHubRow + kk + kh]);
-      const v4i B0 = *reinterpret_cast<const v4i*>(&sB[buf][br * kHubRow + kk + kh]);
-      const v4i B1 = *reinterpret_cast<const v4i*>(&sB[buf][(br + 32) * kHubRow + kk + kh]);
+      const int c = kk + ch;
+      const v4i A0 = *reinterpret_cast<const v4i*>(&sA[hub_slot(ar, c)]);
+      const v4i A1 = *reinterpret_cast<const v4i*>(&sA[hub_slot(ar + 32, c)]);
+      const v4i B0 = *reinterpret_cast<const v4i*>(&sB[hub_slot(br, c)]);
+      const v4i B1 = *reinterpret_cast<const v4i*>(&sB[hub_slot(br + 32, c)]);
       // |s| of an int8 in {-1, 0, 1} is its lowest bit
       const v4i A0a = A0 & ones, A1a = A1 & ones, B0a = B0 & ones, B1a = B1 & ones;
       X[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0a, B0a, X[0][0], 0, 0, 0);
@@ -113,8 +139,6 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
       Y[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, Y[1][0], 0, 0, 0);
       Y[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, Y[1][1], 0, 0, 0);
     }
-    if (more) sstore(buf ^ 1);
-    __syncthreads();
   }
   // Epilogue.  32 x 32 accumulator layout: lane l, register q holds row
   // 8 * (q / 4) + 4 * (l / 32) + q % 4 and column l % 32 of the block.

@@ -113,7 +113,7 @@ struct AssembleSrc {
 // Dense hub block of one side: X = |Bm| |B|^T and Y = Bm B^T over the T_other
 // mids, combined with the sparse hub-pair partials, reduced to res.  The
 // contraction length is padded with zero columns to a multiple of kHubKPad.
-constexpr int32_t kHubKPad = 128;
+constexpr int32_t kHubKPad = 64;
 struct HubArgs {
   const int8_t* Bm;              // [T x K] row-major, K = padded mid count
   const int8_t* B;               // [T x K]
