@@ -278,11 +278,12 @@ void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L) {
   const dbbc::HostPlan& hp = d.host;
   for (int s = 0; s < 2; ++s) {
     if (hp.T[s] == 0) continue;
+    // two int32 T x T planes, cleared as T x T 64-bit words
     L.zero.push_back({d.hub_pairs[s].as<unsigned long long>(), static_cast<size_t>(hp.T[s]) * hp.T[s]});
     HubLaunch h;
     h.a.Bm = d.hub_Bm[s].as<int8_t>();
     h.a.B = d.hub_B[s].as<int8_t>();
-    h.a.hub_pairs = d.hub_pairs[s].as<unsigned long long>();
+    h.a.hub_xy = d.hub_pairs[s].as<int32_t>();
     h.a.res = res;
     h.a.T = hp.T[s];
     h.a.K = d.hub_K[s];
@@ -384,7 +385,7 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
     d.hub_K[s] = 0;
     const int32_t T = hp.T[s], TO = hp.T[1 - s];
     if (T == 0) continue;
-    HIP_TRY(d.hub_pairs[s].alloc(static_cast<size_t>(T) * T * sizeof(unsigned long long)));
+    HIP_TRY(d.hub_pairs[s].alloc(2 * static_cast<size_t>(T) * T * sizeof(int32_t)));
     // pad the contraction dimension to a multiple of kHubKPad
     const int32_t K = (TO + dbbc::kHubKPad - 1) / dbbc::kHubKPad * dbbc::kHubKPad;
     std::vector<int8_t> B(static_cast<size_t>(T) * K, 0), Bm(static_cast<size_t>(T) * K, 0);
@@ -406,7 +407,7 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
     c.other_adj = g->adj[1 - s].as<uint32_t>();
     c.segs = d.segs.as<dbbc::Segment>();
     c.small_segs = d.small_segs.as<dbbc::Segment>();
-    c.hub_pairs = d.hub_pairs[s].as<unsigned long long>();
+    c.hub_xy = d.hub_pairs[s].as<int32_t>();
     c.acc = d.acc.as<uint32_t>();
     c.T = hp.T[s];
     c.R = hp.R[s];

@@ -114,8 +114,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
           const uint32_t p = cv[j] & 0xffffu, n = cv[j] >> 16;
           if (hub && static_cast<int32_t>(key + j) < sc.T) {
             if (cv[j]) {
-              as_global(sc.hub_pairs)[static_cast<size_t>(it.owner) * sc.T + key + j] =
-                  (static_cast<unsigned long long>(n) << 32) | p;
+              hub_partial(sc, it.owner, key + j, p, n);
               sq2 += p + n;
             }
           } else {
@@ -306,8 +305,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
         K[h] = kEmpty;
         Vv[h] = 0;
         if (hub && static_cast<int32_t>(key & kmask) < sc.T)  // singleton group
-          sc.hub_pairs[static_cast<size_t>(it.owner) * sc.T + (key & kmask)] =
-              (static_cast<unsigned long long>(q) << 32) | p;
+          hub_partial(sc, it.owner, key & kmask, p, q);
         else
           ss.add(p, q);
       }

@@ -8,9 +8,13 @@
 //   Y[x][w] = sum_y  Bm[x][y]   B[w][y]    (symmetric minus asymmetric)
 // so the hub-mid wedges split as P = (X + Y) / 2 symmetric and
 // N = (X - Y) / 2 asymmetric (Definitions 5 and 6).  The sparse kernels
-// leave the remaining wedges of each hub pair in hub_pairs; the epilogue adds
-// them before taking Lemma 1's C(P,2) + C(N,2), P * N and C(P + N, 2), since
-// the binomials are not additive.  Entries are at most K < 2^31: exact.
+// leave the remaining wedges of each hub pair as p + n and p - n in hub_xy;
+// they are the accumulators' starting values, so the accumulators end as
+// the pair's full X = P + N and Y = P - N before Lemma 1 is applied (the
+// binomials are not additive).  In these terms
+//   C(P,2) + C(N,2) = (X^2 + Y^2 - 2X) / 4,   P N = (X^2 - Y^2) / 4,
+// both exact (X and Y have the same parity), and C(P + N, 2) is their sum.
+// Entries are below 2^31: exact in int32.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -57,14 +61,34 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
   const int row0 = ti * kHubTile + (wave >> 1) * 64;
   const int col0 = tj * kHubTile + (wave & 1) * 64;
   const int r = lane & 31;
+  // accumulators start at the sparse partials.  32 x 32 accumulator layout:
+  // lane l, register q holds row 8 (q / 4) + 4 (l / 32) + q % 4 and column
+  // l % 32 of the block.
+  const size_t TT = static_cast<size_t>(a.T) * a.T;
   v16i X[2][2], Y[2][2];
+  int64_t x0 = 0;  // sparse wedges of the wave's pairs
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      X[i][j] = v16i{};
-      Y[i][j] = v16i{};
+      const int32_t* px = a.hub_xy + static_cast<size_t>(row0 + i * 32 + 4 * (lane >> 5)) * a.T + col0 + j * 32 +
+                          (lane & 31);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int off = (8 * (q >> 2) + (q & 3)) * a.T;  // wavefront-uniform
+        X[i][j][q] = px[off];
+        Y[i][j][q] = px[TT + off];
+      }
     }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x0 += X[i][j][q];
+  // keep the sum here (sunk past the loop it would hold the starting
+  // values live through the loop)
+  asm volatile("" : "+v"(x0));
   const size_t K = static_cast<size_t>(a.K);
   // Loads of one stage: each wavefront fills 2 x 1 KB of each operand; lane
   // l of part q writes LDS chunk 64 q + l (row (64 q + l) / 4, slot l % 4)
@@ -140,9 +164,10 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
       Y[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, Y[1][1], 0, 0, 0);
     }
   }
-  // Epilogue.  32 x 32 accumulator layout: lane l, register q holds row
-  // 8 * (q / 4) + 4 * (l / 32) + q % 4 and column l % 32 of the block.
-  int64_t bal = 0, unb = 0, tot = 0, wd = 0;
+  // Epilogue: sums of X^2, Y^2 and X over the pairs with w below x.
+  // (only diagonal tiles hold pairs with w not below x)
+  int64_t sxx = 0, syy = 0, sx = 0;
+  const bool diag = ti == tj;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -151,16 +176,14 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
       for (int q = 0; q < 16; ++q) {
         const int x = row0 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
         const int w = col0 + j * 32 + (lane & 31);
-        if (w <= x) continue;
-        const int32_t xv = X[i][j][q], yv = Y[i][j][q];
-        const unsigned long long sp = a.hub_pairs[static_cast<size_t>(x) * a.T + w];
-        const int64_t P = (xv + yv) / 2 + static_cast<int64_t>(sp & 0xffffffffull);
-        const int64_t N = (xv - yv) / 2 + static_cast<int64_t>(sp >> 32);
-        bal += P * (P - 1) / 2 + N * (N - 1) / 2;
-        unb += P * N;
-        tot += (P + N) * (P + N - 1) / 2;
-        wd += xv;
+        const bool keep = !diag || w > x;
+        const int32_t xv = keep ? X[i][j][q] : 0, yv = keep ? Y[i][j][q] : 0;
+        sxx += static_cast<int64_t>(xv) * xv;
+        syy += static_cast<int64_t>(yv) * yv;
+        sx += xv;
       }
+  int64_t bal = (sxx + syy - 2 * sx) / 4, unb = (sxx - syy) / 4;
+  int64_t tot = bal + unb, wd = sx - x0;
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     bal += __shfl_xor(bal, d, 64);

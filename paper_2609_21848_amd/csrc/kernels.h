@@ -33,7 +33,8 @@ struct DevSideConst {
   const uint32_t* other_adj;     // CSR entries of the other side (entries are side-s ranks)
   const Segment* segs;           // the graph's runs (direct, reverse and hash items)
   const Segment* small_segs;     // the graph's tagged runs (small-item groups)
-  unsigned long long* hub_pairs; // [T x T] packed (asym << 32) | sym, or null
+  int32_t* hub_xy;               // [2 x T x T]: p + n, then p - n, of each hub pair's
+                                 // sparse wedges (w > x), or null
   uint32_t* acc;                 // the graph's multi-part accumulators
   int32_t T;                     // hub rows of side s (0 = no dense path)
   int32_t R;                     // reverse window of side s
@@ -117,7 +118,7 @@ constexpr int32_t kHubKPad = 64;
 struct HubArgs {
   const int8_t* Bm;              // [T x K] row-major, K = padded mid count
   const int8_t* B;               // [T x K]
-  const unsigned long long* hub_pairs;  // [T x T] sparse partials
+  const int32_t* hub_xy;         // [2 x T x T] sparse partials: p + n, then p - n
   unsigned long long* res;       // res[0..2] sums, res[3] dense wedges
   int32_t T;                     // rows (pairs side)
   int32_t K;                     // padded contraction length (multiple of kHubKPad)

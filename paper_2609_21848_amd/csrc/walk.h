@@ -401,12 +401,21 @@ __device__ __forceinline__ void flush_sums(const Sums& s, unsigned long long* re
   }
 }
 
+// The sparse wedges of hub pair (owner, key), handed to the dense path as
+// p + n and p - n (the form of its accumulators).
+__device__ __forceinline__ void hub_partial(const DevSideConst& sc, int32_t owner, uint32_t key, uint32_t p,
+                                            uint32_t n) {
+  const size_t i = static_cast<size_t>(owner) * sc.T + key;
+  global_t<int32_t>* xy = as_global(sc.hub_xy);
+  xy[i] = static_cast<int32_t>(p + n);
+  xy[i + static_cast<size_t>(sc.T) * sc.T] = static_cast<int32_t>(p) - static_cast<int32_t>(n);
+}
+
 // Final fate of one pair count of an item.
 __device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, uint32_t n,
                                      const DevSideConst& sc, Sums& s) {
   if ((it.flags & kItemHubPairs) && static_cast<int32_t>(key) < sc.T) {
-    as_global(sc.hub_pairs)[static_cast<size_t>(it.owner) * sc.T + key] =
-        (static_cast<unsigned long long>(n) << 32) | p;
+    hub_partial(sc, it.owner, key, p, n);
   } else {
     s.add(p, n);
   }
