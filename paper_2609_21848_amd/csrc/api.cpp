@@ -478,7 +478,7 @@ constexpr int32_t kDefaultLongLen = 128;
 
 int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& p, uint32_t& long_len) {
   if (!g->defaults_valid) {
-    g->defaults = dbbc::default_params(g->host);
+    g->defaults = dbbc::default_params(g->host, 2 * g->dev.cus);  // two hub workgroups per CU
     g->defaults_valid = true;
   }
   p = g->defaults;

@@ -167,7 +167,10 @@ struct HostPlan {
   std::vector<int8_t> hub_B[2], hub_Bm[2];
 };
 
-PlanParams default_params(const HostGraph& g);
+// hub_slots: dense-block tiles (128 x 128 workgroups) the device runs at
+// once; the default block is trimmed so that its upper triangle of tiles
+// fits in one round.
+PlanParams default_params(const HostGraph& g, int32_t hub_slots = 512);
 int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err);
 
 }  // namespace dbbc

@@ -39,7 +39,7 @@ double hub_density(const HostGraph& g, int32_t T) {
   return static_cast<double>(nnz) / (static_cast<double>(T) * T);
 }
 
-PlanParams default_params(const HostGraph& g) {
+PlanParams default_params(const HostGraph& g, int32_t hub_slots) {
   PlanParams p;
   p.window_L = 32768;
   p.reverse_L = 4096;
@@ -54,6 +54,12 @@ PlanParams default_params(const HostGraph& g) {
       break;
     }
   }
+  // A tile round past the device's slots would run a few tiles alone for a
+  // whole tile time: trim the block to the largest one whose nt (nt + 1) / 2
+  // tiles fit (4096 -> 3968 with 512 slots).
+  int32_t nt = p.hub_T / 128;
+  while (nt > 1 && nt * (nt + 1) / 2 > hub_slots) --nt;
+  if (p.hub_T > 0) p.hub_T = nt * 128;
   p.small_work = static_cast<int32_t>(kSmallGroupWork);
   p.part_work = 1 << 24;
   return p;
