@@ -20,7 +20,9 @@
 // and leave their other hub-pair wedges in a pair buffer that the dense path
 // adds before taking C(., 2).
 #include <algorithm>
+#include <atomic>
 #include <string>
+#include <thread>
 
 #include "internal.h"
 
@@ -79,25 +81,52 @@ int64_t item_work(const HostPlan& plan, const Item& it) {
 // the group may hold at most 2^(32 - key_bits) - 1 items (the all-ones word
 // marks an empty slot).  Items whose hub-pair counts go to the dense path
 // stay alone in their group (the group's owner and flags are theirs).
+int planner_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return static_cast<int>(std::max(1u, std::min(hw == 0 ? 1u : hw, 16u)));
+}
+
+// f(i) for i in [0, n), in blocks of 4096 taken in turn by a pool of threads.
+template <class F>
+void parallel_for(size_t n, F f) {
+  const size_t blocks = (n + 4095) / 4096;
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (size_t b; (b = next.fetch_add(1)) < blocks;)
+      for (size_t i = b * 4096; i < std::min(n, b * 4096 + 4096); ++i) f(i);
+  };
+  std::vector<std::thread> pool;
+  const int nt = planner_threads();
+  for (int t = 1; t < nt && static_cast<size_t>(t) < blocks; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+}
+
 void pack_small_groups(const HostGraph& g, HostPlan& plan) {
   for (int s = 0; s < 2; ++s) {
     int32_t kb = 1;
     while ((int64_t{1} << kb) < g.side[s].n) ++kb;
     plan.key_bits[s] = kb;
   }
+  const bool pv = plan.p.per_vertex;
   plan.small_groups.clear();
   plan.small_segs.clear();
+  // the grouping (sequential: a group closes when the next item does not
+  // fit), then each item's runs copied to its place in the groups' runs
+  const size_t ni = plan.small_items.size();
+  std::vector<uint32_t> dest(ni), local_of(ni);
   Item grp{};
   bool open = false;
-  uint32_t local = 0;
+  uint32_t local = 0, nsegs = 0;
   auto close = [&]() {
     if (!open) return;
-    grp.seg_count = static_cast<uint32_t>(plan.small_segs.size()) - grp.seg_begin;
+    grp.seg_count = nsegs - grp.seg_begin;
     grp.key_hi = static_cast<int32_t>(local);  // items in the group
     plan.small_groups.push_back(grp);
     open = false;
   };
-  for (const Item& it : plan.small_items) {
+  for (size_t i = 0; i < ni; ++i) {
+    const Item& it = plan.small_items[i];
     const uint32_t max_items =
         std::min<uint32_t>(kSmallMaxItems, (1u << (32 - plan.key_bits[it.side])) - 1u);
     const bool hub = (it.flags & kItemHubPairs) != 0;
@@ -106,44 +135,49 @@ void pack_small_groups(const HostGraph& g, HostPlan& plan) {
       close();
     if (!open) {
       grp = Item{};
-      grp.seg_begin = static_cast<uint32_t>(plan.small_segs.size());
+      grp.seg_begin = nsegs;
       grp.owner = it.owner;
-      grp.acc_slot = plan.p.per_vertex ? static_cast<int32_t>(plan.small_owner.size()) : -1;
+      grp.acc_slot = pv ? static_cast<int32_t>(i) : -1;  // owners are listed per item
       grp.flags = it.flags & kItemHubPairs;
       grp.side = it.side;
       local = 0;
       open = true;
     }
-    for (uint32_t k = 0; k < it.seg_count; ++k) {
-      const Segment sg = plan.segs[it.seg_begin + k];
-      plan.small_segs.push_back(Segment{sg.start, (local << 16) | sg.len_g});
-      if (plan.p.per_vertex) {
-        plan.small_seg_mid.push_back(plan.seg_mid[it.seg_begin + k]);
-        plan.small_seg_edge.push_back(plan.seg_edge[it.seg_begin + k]);
-      }
-    }
-    if (plan.p.per_vertex) plan.small_owner.push_back(it.owner);
+    dest[i] = nsegs;
+    local_of[i] = local;
+    nsegs += it.seg_count;
     grp.work += it.work;
     ++local;
   }
   close();
+  plan.small_segs.resize(nsegs);
+  if (pv) {
+    plan.small_seg_mid.resize(nsegs);
+    plan.small_seg_edge.resize(nsegs);
+    plan.small_owner.resize(ni);
+  }
+  parallel_for(ni, [&](size_t i) {
+    const Item& it = plan.small_items[i];
+    for (uint32_t k = 0; k < it.seg_count; ++k) {
+      const Segment sg = plan.segs[it.seg_begin + k];
+      plan.small_segs[dest[i] + k] = Segment{sg.start, (local_of[i] << 16) | sg.len_g};
+      if (pv) {
+        plan.small_seg_mid[dest[i] + k] = plan.seg_mid[it.seg_begin + k];
+        plan.small_seg_edge[dest[i] + k] = plan.seg_edge[it.seg_begin + k];
+      }
+    }
+    if (pv) plan.small_owner[i] = it.owner;
+  });
 }
 
 // Drop the segments of the small items (copied into the groups) from segs.
 // Consecutive items with the same runs (key windows of one item) keep
-// sharing them.
+// sharing them.  New places first (in list order), then parallel copies.
 void compact_segments(HostPlan& plan) {
   const bool pv = plan.p.per_vertex;
-  std::vector<Segment> out;
-  std::vector<uint32_t> out_mid, out_edge;
+  std::vector<Item*> items;
+  std::vector<uint32_t> from;  // old seg_begin of the items that copy
   size_t n = 0;
-  for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
-    for (const Item& it : *v) n += it.seg_count;
-  out.reserve(n);
-  if (pv) {
-    out_mid.reserve(n);
-    out_edge.reserve(n);
-  }
   for (auto* v : {&plan.direct_items, &plan.hash_items, &plan.reverse_items}) {
     uint32_t last_begin = 0xffffffffu, last_count = 0, last_new = 0;
     for (Item& it : *v) {
@@ -153,20 +187,149 @@ void compact_segments(HostPlan& plan) {
       }
       last_begin = it.seg_begin;
       last_count = it.seg_count;
-      last_new = static_cast<uint32_t>(out.size());
-      out.insert(out.end(), plan.segs.begin() + it.seg_begin, plan.segs.begin() + it.seg_begin + it.seg_count);
-      if (pv) {
-        out_mid.insert(out_mid.end(), plan.seg_mid.begin() + it.seg_begin,
-                       plan.seg_mid.begin() + it.seg_begin + it.seg_count);
-        out_edge.insert(out_edge.end(), plan.seg_edge.begin() + it.seg_begin,
-                        plan.seg_edge.begin() + it.seg_begin + it.seg_count);
-      }
+      last_new = static_cast<uint32_t>(n);
+      items.push_back(&it);
+      from.push_back(it.seg_begin);
       it.seg_begin = last_new;
+      n += it.seg_count;
     }
   }
+  std::vector<Segment> out(n);
+  std::vector<uint32_t> out_mid(pv ? n : 0), out_edge(pv ? n : 0);
+  parallel_for(items.size(), [&](size_t i) {
+    const Item& it = *items[i];
+    std::copy(plan.segs.begin() + from[i], plan.segs.begin() + from[i] + it.seg_count, out.begin() + it.seg_begin);
+    if (pv) {
+      std::copy(plan.seg_mid.begin() + from[i], plan.seg_mid.begin() + from[i] + it.seg_count,
+                out_mid.begin() + it.seg_begin);
+      std::copy(plan.seg_edge.begin() + from[i], plan.seg_edge.begin() + from[i] + it.seg_count,
+                out_edge.begin() + it.seg_begin);
+    }
+  });
   plan.segs = std::move(out);
   plan.seg_mid = std::move(out_mid);
   plan.seg_edge = std::move(out_edge);
+}
+
+// The runs and items of a range of owners of one side, built apart (one
+// range per task) and appended to the plan in owner order, so the plan does
+// not depend on how the owners were shared among threads.
+struct Piece {
+  std::vector<Segment> segs;
+  std::vector<uint32_t> seg_mid, seg_edge;
+  std::vector<Item> small_items, hash_items, reverse_items, big_direct;
+  std::vector<Reduce> reduces;  // acc_slot relative to the piece
+  int32_t acc_slots = 0;
+  int64_t w_sparse = 0, w_skipped = 0;
+};
+
+// Split rows [r0, r1) of a CSR with offsets off into about 64 ranges per
+// thread of equal entry counts and run f(lo, hi, range index) on a pool of
+// threads taking ranges in turn.  Returns the number of ranges.
+template <class F>
+size_t parallel_ranges(const std::vector<uint32_t>& off, int32_t r0, int32_t r1, F f) {
+  if (r1 <= r0) return 0;
+  const int nt = planner_threads();
+  const uint64_t total = static_cast<uint64_t>(off[r1] - off[r0]) + static_cast<uint64_t>(r1 - r0);
+  const size_t want = static_cast<size_t>(nt) * 64;
+  std::vector<int32_t> cuts{r0};
+  for (size_t k = 1; k < want; ++k) {
+    // first row whose (entries + rows) prefix reaches k / want of the total
+    const uint64_t goal = total * k / want;
+    int32_t lo = cuts.back(), hi = r1;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      if (static_cast<uint64_t>(off[mid] - off[r0]) + static_cast<uint64_t>(mid - r0) < goal)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo > cuts.back() && lo < r1) cuts.push_back(lo);
+  }
+  cuts.push_back(r1);
+  const size_t n = cuts.size() - 1;
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (size_t i; (i = next.fetch_add(1)) < n;) f(cuts[i], cuts[i + 1], i);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt && static_cast<size_t>(t) < n; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  return n;
+}
+
+// One Piece per range of owners in [r0, r1), each owner handled by f(P, owner).
+template <class F>
+std::vector<Piece> build_pieces(const std::vector<uint32_t>& off, int32_t r0, int32_t r1, F f) {
+  std::vector<Piece> pieces(static_cast<size_t>(planner_threads()) * 64 + 2);
+  const size_t n = parallel_ranges(off, r0, r1, [&](int32_t lo, int32_t hi, size_t i) {
+    for (int32_t x = lo; x < hi; ++x) f(pieces[i], x);
+  });
+  pieces.resize(n);
+  return pieces;
+}
+
+void merge_pieces(HostPlan& plan, std::vector<Piece>& pieces, std::vector<Item>& big_direct) {
+  // every piece's place in each list, then the copies in parallel
+  const size_t n = pieces.size();
+  struct At {
+    size_t seg, mid, small, hash, rev, big, red;
+    int32_t slot;
+  };
+  std::vector<At> at(n + 1);
+  at[0] = At{plan.segs.size(), plan.seg_mid.size(), plan.small_items.size(), plan.hash_items.size(),
+             plan.reverse_items.size(), big_direct.size(), plan.reduces.size(), plan.acc_slots};
+  for (size_t i = 0; i < n; ++i) {
+    const Piece& P = pieces[i];
+    at[i + 1] = At{at[i].seg + P.segs.size(), at[i].mid + P.seg_mid.size(), at[i].small + P.small_items.size(),
+                   at[i].hash + P.hash_items.size(), at[i].rev + P.reverse_items.size(),
+                   at[i].big + P.big_direct.size(), at[i].red + P.reduces.size(), at[i].slot + P.acc_slots};
+    plan.w_sparse += P.w_sparse;
+    plan.w_skipped += P.w_skipped;
+  }
+  plan.segs.resize(at[n].seg);
+  plan.seg_mid.resize(at[n].mid);
+  plan.seg_edge.resize(at[n].mid);
+  plan.small_items.resize(at[n].small);
+  plan.hash_items.resize(at[n].hash);
+  plan.reverse_items.resize(at[n].rev);
+  big_direct.resize(at[n].big);
+  plan.reduces.resize(at[n].red);
+  plan.acc_slots = at[n].slot;
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (size_t i; (i = next.fetch_add(1)) < n;) {
+      Piece& P = pieces[i];
+      const uint32_t base = static_cast<uint32_t>(at[i].seg);
+      const int32_t slot0 = at[i].slot;
+      auto shift = [&](const std::vector<Item>& from, std::vector<Item>& to, size_t pos) {
+        for (Item it : from) {
+          it.seg_begin += base;
+          if (it.acc_slot >= 0) it.acc_slot += slot0;
+          to[pos++] = it;
+        }
+      };
+      std::copy(P.segs.begin(), P.segs.end(), plan.segs.begin() + at[i].seg);
+      std::copy(P.seg_mid.begin(), P.seg_mid.end(), plan.seg_mid.begin() + at[i].mid);
+      std::copy(P.seg_edge.begin(), P.seg_edge.end(), plan.seg_edge.begin() + at[i].mid);
+      shift(P.small_items, plan.small_items, at[i].small);
+      shift(P.hash_items, plan.hash_items, at[i].hash);
+      shift(P.reverse_items, plan.reverse_items, at[i].rev);
+      shift(P.big_direct, big_direct, at[i].big);
+      size_t r = at[i].red;
+      for (Reduce red : P.reduces) {
+        red.acc_slot += slot0;
+        plan.reduces[r++] = red;
+      }
+      P = Piece();  // free as we go
+    }
+  };
+  std::vector<std::thread> pool;
+  const int nt = planner_threads();
+  for (int t = 1; t < nt && static_cast<size_t>(t) < n; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
 }
 
 }  // namespace
@@ -207,6 +370,12 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   if (plan.T[0] == 0 || plan.T[1] == 0) plan.T[0] = plan.T[1] = 0;
 
   std::vector<Item> big_direct;
+  // pieces of both sides in plan order (side 0 forward, side 0 reverse,
+  // side 1 forward, side 1 reverse), merged once at the end
+  std::vector<Piece> pieces;
+  auto keep = [&](std::vector<Piece>&& v) {
+    for (Piece& P : v) pieces.push_back(std::move(P));
+  };
 
   for (int s = 0; s < 2; ++s) {
     const HostSide& S = g.side[s];
@@ -218,56 +387,58 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     // Per row y of the other side (its entries are keys of side s): how many
     // entries lie below the window, the reverse window and the hub block.
     std::vector<int32_t> splitL(O.n), splitR(O.n), splitT(O.n);
-    for (int32_t y = 0; y < O.n; ++y) {
-      const uint32_t* b = O.adj.data() + O.off[y];
-      const uint32_t* e = O.adj.data() + O.off[y + 1];
-      auto below = [&](int32_t k) {
-        return static_cast<int32_t>(std::lower_bound(b, e, static_cast<uint32_t>(k) << 1) - b);
-      };
-      splitL[y] = below(L);
-      splitR[y] = below(R);
-      splitT[y] = below(T);
-    }
+    parallel_ranges(O.off, 0, O.n, [&](int32_t y0, int32_t y1, size_t) {
+      for (int32_t y = y0; y < y1; ++y) {
+        const uint32_t* b = O.adj.data() + O.off[y];
+        const uint32_t* e = O.adj.data() + O.off[y + 1];
+        auto below = [&](int32_t k) {
+          return static_cast<int32_t>(std::lower_bound(b, e, static_cast<uint32_t>(k) << 1) - b);
+        };
+        splitL[y] = below(L);
+        splitR[y] = below(R);
+        splitT[y] = below(T);
+      }
+    });
 
     // A run of entries of row y (the wedges' mid) whose first edge is the
     // entry e of side s's CSR (its negative bit is the run's g).
-    auto add_seg = [&](uint32_t start, uint32_t len, uint32_t e) {
+    auto add_seg = [&](Piece& P, uint32_t start, uint32_t len, uint32_t e) {
       const uint32_t first = S.adj[e];
-      plan.segs.push_back(Segment{start, (len << 1) | (first & 1u)});
+      P.segs.push_back(Segment{start, (len << 1) | (first & 1u)});
       if (pv) {
         const uint32_t y = first >> 1;
         const uint64_t bound = static_cast<uint64_t>(O.off[y + 1] - O.off[y]) * static_cast<uint64_t>(S.max_deg);
         const bool wide = p.wide_all || bound >= (uint64_t{1} << 32);
-        plan.seg_mid.push_back(y | (wide ? kMidWide : 0u));
-        plan.seg_edge.push_back(e);
+        P.seg_mid.push_back(y | (wide ? kMidWide : 0u));
+        P.seg_edge.push_back(e);
       }
     };
 
-    auto place = [&](uint32_t seg_begin, int32_t owner, int32_t key_lo, int32_t key_hi,
+    auto place = [&](Piece& P, uint32_t seg_begin, int32_t owner, int32_t key_lo, int32_t key_hi,
                      uint32_t flags, ItemKind kind) {
-      const uint32_t nseg = static_cast<uint32_t>(plan.segs.size() - seg_begin);
+      const uint32_t nseg = static_cast<uint32_t>(P.segs.size() - seg_begin);
       int64_t work = 0;
-      for (uint32_t k = 0; k < nseg; ++k) work += plan.segs[seg_begin + k].len_g >> 1;
+      for (uint32_t k = 0; k < nseg; ++k) work += P.segs[seg_begin + k].len_g >> 1;
       // With a single segment every pair of the item has at most one wedge
       // and adds nothing -- unless the pair's count is completed by the
       // dense hub block.
       if (nseg == 0 || (nseg < 2 && !(flags & kItemHubPairs))) {
-        plan.w_skipped += work;
-        plan.segs.resize(seg_begin);
+        P.w_skipped += work;
+        P.segs.resize(seg_begin);
         if (pv) {
-          plan.seg_mid.resize(seg_begin);
-          plan.seg_edge.resize(seg_begin);
+          P.seg_mid.resize(seg_begin);
+          P.seg_edge.resize(seg_begin);
         }
         return;
       }
-      plan.w_sparse += work;
+      P.w_sparse += work;
       if (kind == kReverseTail) {
         // rows are sorted by rank, so a run's last entry is its largest key:
         // the item's counters (and its parts' and reduce's) need only the
         // keys up to the largest one
         int32_t mx = key_lo;
         for (uint32_t k = 0; k < nseg; ++k) {
-          const Segment sg = plan.segs[seg_begin + k];
+          const Segment sg = P.segs[seg_begin + k];
           mx = std::max(mx, static_cast<int32_t>(O.adj[sg.start + (sg.len_g >> 1) - 1] >> 1));
         }
         key_hi = std::min(key_hi, mx + 1);
@@ -283,47 +454,49 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       it.side = static_cast<uint32_t>(s);
       it.work = static_cast<uint32_t>(std::min<int64_t>(work, 0xffffffffll));
       if (kind == kReverseTail && pv && nseg > kReverseMaxSegs) {
-        big_direct.push_back(it);  // per-vertex counts: one direct item
+        P.big_direct.push_back(it);  // per-vertex counts: one direct item
       } else if (kind == kReverseTail) {
         // parts of at most kReverseMaxSegs segments (8-bit counters)
         if (nseg <= kReverseMaxSegs) {
-          plan.reverse_items.push_back(it);
+          P.reverse_items.push_back(it);
           return;
         }
-        const int32_t first_slot = plan.acc_slots;
+        const int32_t first_slot = P.acc_slots;
         for (uint32_t k = 0; k < nseg; k += kReverseMaxSegs) {
           Item part = it;
           part.seg_begin = seg_begin + k;
           part.seg_count = std::min(kReverseMaxSegs, nseg - k);
           part.flags |= kItemMultiPart;
-          part.acc_slot = plan.acc_slots++;
-          part.work = static_cast<uint32_t>(std::min<int64_t>(item_work(plan, part), 0xffffffffll));
-          plan.reverse_items.push_back(part);
+          part.acc_slot = P.acc_slots++;
+          int64_t pw = 0;
+          for (uint32_t j = 0; j < part.seg_count; ++j) pw += P.segs[part.seg_begin + j].len_g >> 1;
+          part.work = static_cast<uint32_t>(std::min<int64_t>(pw, 0xffffffffll));
+          P.reverse_items.push_back(part);
         }
         Reduce r{};
         r.acc_slot = first_slot;
-        r.n_parts = plan.acc_slots - first_slot;
+        r.n_parts = P.acc_slots - first_slot;
         r.owner = owner;
         r.key_lo = key_lo;
         r.key_hi = key_hi;
         r.flags = flags;
         r.side = static_cast<uint32_t>(s);
-        plan.reduces.push_back(r);
+        P.reduces.push_back(r);
       } else if (work <= p.small_work) {
-        plan.small_items.push_back(it);
+        P.small_items.push_back(it);
       } else if (kind == kForwardTail) {
-        plan.hash_items.push_back(it);
+        P.hash_items.push_back(it);
       } else {
-        big_direct.push_back(it);
+        P.big_direct.push_back(it);
       }
     };
 
     // Forward items: pivots x of side s, split at the window boundary.
-    for (int32_t x = 0; x < S.n; ++x) {
+    std::vector<Piece> fwd = build_pieces(S.off, 0, S.n, [&](Piece& P, int32_t x) {
       const bool hub = x < T;
       const uint32_t e0 = S.off[x] + S.cut[x], e1 = S.off[x + 1];
       if (x < L) {  // keys (x, L)
-        const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+        const uint32_t seg_begin = static_cast<uint32_t>(P.segs.size());
         for (uint32_t e = e0; e < e1; ++e) {
           const uint32_t y = S.adj[e] >> 1;
           uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
@@ -331,44 +504,46 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           if (hub && static_cast<int32_t>(y) < TO)
             start = std::max(start, O.off[y] + static_cast<uint32_t>(splitT[y]));
           if (end > start)
-            add_seg(start, end - start, e);
+            add_seg(P, start, end - start, e);
         }
-        place(seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
+        place(P, seg_begin, x, x + 1, L, hub ? kItemHubPairs : 0u, kForwardWindow);
       }
       if (x >= L) {  // keys (x, n): every endpoint is below the window
-        const uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+        const uint32_t seg_begin = static_cast<uint32_t>(P.segs.size());
         for (uint32_t e = e0; e < e1; ++e) {
           const uint32_t y = S.adj[e] >> 1;
           const uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
           const uint32_t end = O.off[y + 1];
           if (end > start)
-            add_seg(start, end - start, e);
+            add_seg(P, start, end - start, e);
         }
-        place(seg_begin, x, x + 1, S.n, 0u, kForwardTail);
+        place(P, seg_begin, x, x + 1, S.n, 0u, kForwardTail);
       }
-    }
+    });
+    keep(std::move(fwd));
     // Reverse items: endpoints w of side s below the window; keys x < R
     // (reverse), then keys x in [R, L) (reverse-mid).  Within row y the keys
     // above y form the prefix [0, cut[y]).
-    for (int32_t w = L; w < S.n; ++w) {
-      uint32_t seg_begin = static_cast<uint32_t>(plan.segs.size());
+    std::vector<Piece> rev = build_pieces(S.off, L, S.n, [&](Piece& P, int32_t w) {
+      uint32_t seg_begin = static_cast<uint32_t>(P.segs.size());
       for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
         const uint32_t y = S.adj[e] >> 1;
         const int32_t len = std::min(splitR[y], O.cut[y]);
         if (len > 0)
-          add_seg(O.off[y], static_cast<uint32_t>(len), e);
+          add_seg(P, O.off[y], static_cast<uint32_t>(len), e);
       }
-      place(seg_begin, w, 0, R, 0u, kReverseTail);
-      if (R == L) continue;
-      seg_begin = static_cast<uint32_t>(plan.segs.size());
+      place(P, seg_begin, w, 0, R, 0u, kReverseTail);
+      if (R == L) return;
+      seg_begin = static_cast<uint32_t>(P.segs.size());
       for (uint32_t e = S.off[w]; e < S.off[w + 1]; ++e) {
         const uint32_t y = S.adj[e] >> 1;
         const int32_t end = std::min(splitL[y], O.cut[y]);
         if (end > splitR[y])
-          add_seg(O.off[y] + static_cast<uint32_t>(splitR[y]), static_cast<uint32_t>(end - splitR[y]), e);
+          add_seg(P, O.off[y] + static_cast<uint32_t>(splitR[y]), static_cast<uint32_t>(end - splitR[y]), e);
       }
-      place(seg_begin, w, R, L, 0u, kReverseMid);
-    }
+      place(P, seg_begin, w, R, L, 0u, kReverseMid);
+    });
+    keep(std::move(rev));
 
     // Dense hub block of this side: B[x][y] for x < T, y < TO.
     if (T > 0) {
@@ -387,6 +562,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       }
     }
   }
+
+  merge_pieces(plan, pieces, big_direct);
+  pieces.clear();
+  pieces.shrink_to_fit();
 
   // Split heavy direct items into parts (work budget, and fewer than 2^16
   // segments so that per-part counts fit 16 bits), heaviest first.
