@@ -73,6 +73,7 @@ constexpr uint32_t kReverseMaxSegs = 255;
 enum : uint32_t {
   kItemMultiPart = 1u,  // partial counts go to a global accumulator
   kItemHubPairs = 2u,   // keys below hub_T are flushed to the hub-pair buffer
+  kItemPacked = 4u,     // per-vertex direct item: p and n share one 32-bit word
 };
 
 struct Item {
@@ -120,6 +121,9 @@ constexpr int32_t kMaxReverseL = 4096;
 // Key window of a direct item of the per-vertex pass (32-bit counters in
 // LDS); wider windows are split into items that share their runs.
 constexpr int32_t kPVWindow = 8192;
+// Items with fewer than 2^16 runs (so p, n < 2^16 for every key) pack p and
+// n into one 32-bit word and take twice the window.
+constexpr int32_t kPVWindowPacked = 2 * kPVWindow;
 
 // Flag in a per-vertex plan's run mid (seg_mid, small_seg_mid): the mid's
 // degree times the largest degree of the keys' side reaches 2^32, so an edge

@@ -182,9 +182,11 @@ struct PairCredit {
 };
 
 // ---------------------------------------------------------------------------
-// Direct items: one workgroup per item, 32-bit p and n counters over the
-// item's key window (at most kPVWindow keys; windows of one pivot share
-// their runs and skip the keys of the others).  Credits of keys below
+// Direct items: one workgroup per item, p and n counters over the item's
+// key window, 32-bit each (at most kPVWindow keys) or, for items with fewer
+// than 2^16 runs (kItemPacked), 16|16 bits in one word (at most
+// kPVWindowPacked keys); windows of one pivot share their runs and skip the
+// keys of the others.  Credits of keys below
 // kPVHotKeys (the side's highest-priority vertices, the keys of most items)
 // are summed per workgroup in LDS and reach HBM once per workgroup; a launch
 // holds the items of one side.
@@ -194,7 +196,7 @@ constexpr int kPVDirectWaves = kPVDirectThreads / kWave;
 
 template <bool kEdge>
 __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
-  __shared__ uint32_t P[kPVWindow], N[kPVWindow];
+  __shared__ uint32_t C[2 * kPVWindow];  // P | N, or packed words
   __shared__ uint32_t mbase[kPVDirectWaves][kGather];
   __shared__ uint32_t mtag[kPVDirectWaves][kGather];
   __shared__ unsigned long long cb[kPVDirectWaves][kWave], cu[kPVDirectWaves][kWave];
@@ -203,7 +205,9 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = lane_id();
-  for (int i = tid; i < kPVWindow; i += kPVDirectThreads) P[i] = N[i] = 0;
+  for (int i = tid; i < 2 * kPVWindow; i += kPVDirectThreads) C[i] = 0;
+  uint32_t* const P = C;
+  uint32_t* const N = C + kPVWindow;
   for (int i = tid; i < kPVHotKeys; i += kPVDirectThreads) hbal[i] = hunb[i] = 0;
   for (int i = tid; i < kPVDirectWaves * static_cast<int>(kGather); i += kPVDirectThreads) (&mtag[0][0])[i] = 0;
   cb[wave][lane] = 0;
@@ -225,16 +229,22 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t lo = static_cast<uint32_t>(it.key_lo), hi = static_cast<uint32_t>(it.key_hi);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
+    const bool packed = (it.flags & kItemPacked) != 0;
     // tally
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
       const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
-      walk_regs<4>(sr, sc.other_adj, mk, a.long_len,
-                   hash_tally([&](uint32_t e, uint32_t tag) {
-                     const uint32_t key = e >> 1;
-                     if (key >= lo && key < hi) atomicAdd(((e ^ tag) & 1u) ? &N[key - lo] : &P[key - lo], 1u);
-                   }));
+      if (packed)
+        walk_regs<4>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
+                       const uint32_t key = e >> 1;
+                       if (key >= lo && key < hi) atomicAdd(&C[key - lo], wedge_inc(e, tag));
+                     }));
+      else
+        walk_regs<4>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
+                       const uint32_t key = e >> 1;
+                       if (key >= lo && key < hi) atomicAdd(((e ^ tag) & 1u) ? &N[key - lo] : &P[key - lo], 1u);
+                     }));
     }
     __syncthreads();
     // credit the mids
@@ -246,8 +256,14 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;
             if (key < lo || key >= hi) return false;
-            p = P[key - lo];
-            n = N[key - lo];
+            if (packed) {
+              const uint32_t v = C[key - lo];
+              p = v & 0xffffu;
+              n = v >> 16;
+            } else {
+              p = P[key - lo];
+              n = N[key - lo];
+            }
             return true;
           },
           cb[wave], cu[wave], sc);
@@ -259,9 +275,11 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     // credit the keys and the owner
     PairCredit pc;
     for (uint32_t k = tid; k < hi - lo; k += kPVDirectThreads) {
-      const uint32_t p = P[k], n = N[k];
+      const uint32_t v = C[k];
+      const uint32_t p = packed ? v & 0xffffu : v, n = packed ? v >> 16 : N[k];
       if (p | n) {
-        P[k] = N[k] = 0;
+        C[k] = 0;
+        if (!packed) N[k] = 0;
         const uint32_t key = lo + k;
         if (key < static_cast<uint32_t>(kPVHotKeys)) {
           sums.add(p, n);

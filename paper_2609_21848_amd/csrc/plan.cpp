@@ -579,11 +579,14 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   std::vector<Item> parts, singles;
   for (auto& [work, i] : order) {
     const Item& it = big_direct[i];
-    if (pv) {  // whole items, key windows of at most kPVWindow keys
-      for (int32_t lo = it.key_lo; lo < it.key_hi; lo += kPVWindow) {
+    if (pv) {  // whole items, key windows of at most kPVWindow(Packed) keys
+      const bool packed = it.seg_count < 65536;
+      const int32_t win = packed ? kPVWindowPacked : kPVWindow;
+      for (int32_t lo = it.key_lo; lo < it.key_hi; lo += win) {
         Item w = it;
         w.key_lo = lo;
-        w.key_hi = std::min(it.key_hi, lo + kPVWindow);
+        w.key_hi = std::min(it.key_hi, lo + win);
+        if (packed) w.flags |= kItemPacked;
         singles.push_back(w);
       }
       continue;

@@ -283,7 +283,10 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
   for (auto* list : {&plan.direct_items, &plan.hash_items, &plan.reverse_items})
     for (const Item& it : *list) {
       const int32_t lim = list == &plan.reverse_items ? (int32_t)kReverseMaxSegs : INT32_MAX;
-      if (list == &plan.direct_items && it.key_hi - it.key_lo > kPVWindow) return -124;
+      if (list == &plan.direct_items &&
+          it.key_hi - it.key_lo > ((it.flags & kItemPacked) ? kPVWindowPacked : kPVWindow))
+        return -124;
+      if ((it.flags & kItemPacked) && it.seg_count >= 65536) return -126;
       if ((rc = run(it.side, plan.segs.data(), plan.seg_mid.data(), plan.seg_edge.data(), it.seg_begin,
                     it.seg_count, it.key_lo, it.key_hi, false, nullptr, it.owner, lim)))
         return rc;
