@@ -51,6 +51,7 @@ extern "C" {
 #define DBBC_E_DEVICE (-6)      /* a HIP call or kernel launch failed */
 #define DBBC_E_TOO_LARGE (-7)   /* sizes beyond the limits stated above */
 #define DBBC_E_NO_DEVICE (-8)   /* no gfx950 device visible */
+#define DBBC_E_PARSE (-9)       /* malformed record in an edge-list text */
 
 /* ---- flags for dbbc_graph_create ---------------------------------------- */
 #define DBBC_INPUT_DEVICE 0x1u /* u, v, sign point to device memory */
@@ -133,6 +134,39 @@ typedef struct {
  * both sides are built here and kept on the device until destroy. */
 int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t *u, const int32_t *v,
                       const int8_t *sign, uint32_t flags, void *hip_stream, dbbc_graph **out);
+
+/* Build a graph handle from an edge list in text form, parsed on the device
+ * (the paper's Phase 1 loading aligned to whole records and Phase 2 compact
+ * identifiers, Section IV-A, on one GPU).
+ *   text, len: the bytes (host memory, or device memory with
+ *              DBBC_INPUT_DEVICE); len < 2^31 - 1.  One record per line:
+ *              "u v s", fields separated by spaces, tabs or commas, "\n" or
+ *              "\r\n" line ends; u and v decimal ids below 2^63 (the two
+ *              sides are separate id spaces); s = 1 or +1 (positive), 0 or -1
+ *              (negative), the paper's record format (Section III) with
+ *              either sign convention; fields after the third are ignored;
+ *              blank lines and lines starting with '#' or '%' are skipped.
+ *   flags    : DBBC_INPUT_DEVICE | DBBC_DUP_REJECT (duplicates: as in
+ *              dbbc_graph_create, in line order)
+ *   info     : optional (host memory): lines and records read, n_u, n_v
+ * Each side's distinct ids become the compact ids 0 .. n - 1 in increasing
+ * raw id order; dbbc_graph_raw_ids returns the map.  Per-vertex outputs of
+ * such a graph are in compact id order; per-edge outputs in record order
+ * (the records being the non-skipped lines).  A malformed line fails with
+ * DBBC_E_PARSE, its line number in dbbc_last_error(); a text without
+ * records fails with DBBC_E_INVALID_ARG. */
+typedef struct {
+  int64_t lines, records; /* lines in the text, edge records among them */
+  int64_t n_u, n_v;       /* distinct ids per side */
+} dbbc_text_info;
+int dbbc_graph_create_text(const char *text, int64_t len, uint32_t flags, void *hip_stream,
+                           dbbc_graph **out, dbbc_text_info *info);
+
+/* The raw id of every compact id of one side (side 0 = U, 1 = V) of a graph
+ * made by dbbc_graph_create_text: n_side int64 values written to out
+ * (caller-owned device memory), ascending.  DBBC_E_INVALID_ARG for a graph
+ * made from id arrays (its ids are the compact ids). */
+int dbbc_graph_raw_ids(const dbbc_graph *g, int32_t side, int64_t *out, void *hip_stream);
 
 /* Copy the handle's statistics into *out (host memory). */
 int dbbc_graph_stats(const dbbc_graph *g, dbbc_stats *out);

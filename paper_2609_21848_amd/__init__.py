@@ -27,6 +27,7 @@ DBBC_E_OOM = -5
 DBBC_E_DEVICE = -6
 DBBC_E_TOO_LARGE = -7
 DBBC_E_NO_DEVICE = -8
+DBBC_E_PARSE = -9
 
 DBBC_INPUT_DEVICE = 0x1
 DBBC_DUP_REJECT = 0x2
@@ -37,7 +38,8 @@ DBBC_BATCH_CAPTURE = 0x1
 # every symbol declared in include/dbbc.h
 EXPORTS = (
     "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async", "dbbc_count_read",
-    "dbbc_count_per_vertex", "dbbc_count_per_edge", "dbbc_batch_create", "dbbc_batch_reset", "dbbc_batch_launch",
+    "dbbc_count_per_vertex", "dbbc_count_per_edge", "dbbc_graph_create_text", "dbbc_graph_raw_ids",
+    "dbbc_batch_create", "dbbc_batch_reset", "dbbc_batch_launch",
     "dbbc_batch_read",
     "dbbc_batch_count", "dbbc_batch_size", "dbbc_batch_destroy", "dbbc_count_batch", "dbbc_autotune",
     "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string", "dbbc_last_error",
@@ -102,6 +104,10 @@ class _ServerStats(ctypes.Structure):
         "batched_graphs", "max_queue", "queued", "resident_graphs", "resident_bytes")]
 
 
+class _TextInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("lines", "records", "n_u", "n_v")]
+
+
 class _KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_float), ("wedges", ctypes.c_int64),
                 ("segments", ctypes.c_int64), ("items", ctypes.c_int64), ("macs", ctypes.c_int64)]
@@ -126,6 +132,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                           ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_per_edge.argtypes = [vp, ctypes.POINTER(Options), vp, vp,
                                         ctypes.POINTER(_Counts), vp]
+    lib.dbbc_graph_create_text.argtypes = [vp, i64, u32, vp, ctypes.POINTER(vp),
+                                           ctypes.POINTER(_TextInfo)]
+    lib.dbbc_graph_raw_ids.argtypes = [vp, i32, vp, vp]
     lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
     lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
@@ -162,6 +171,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_version.restype = ctypes.c_char_p
     for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async",
                  "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_count_per_edge",
+                 "dbbc_graph_create_text", "dbbc_graph_raw_ids",
                  "dbbc_batch_create", "dbbc_batch_reset",
                  "dbbc_batch_launch",
                  "dbbc_batch_read", "dbbc_batch_count", "dbbc_count_batch", "dbbc_autotune",
@@ -225,6 +235,26 @@ def dbbc_graph_create(n_u: int, n_v: int, u, v, sign, flags: int = 0, stream=Non
     _check(lib.dbbc_graph_create(int(n_u), int(n_v), m, *ptrs, int(flags) | f,
                                  _stream_ptr(stream), ctypes.byref(out)), "dbbc_graph_create")
     return out.value
+
+
+def dbbc_graph_create_text(text, flags: int = 0, stream=None):
+    """Build a handle from an edge-list text parsed on the device.  text:
+    bytes / str (host), or a uint8 CUDA tensor (sets DBBC_INPUT_DEVICE).
+    Returns (handle, info dict with lines, records, n_u, n_v)."""
+    lib = load()
+    keep = None
+    if hasattr(text, "is_cuda") and text.is_cuda:
+        if not text.is_contiguous():
+            raise ValueError("text tensor must be contiguous")
+        ptr, n, flags = text.data_ptr(), int(text.numel() * text.element_size()), flags | DBBC_INPUT_DEVICE
+    else:
+        keep = np.frombuffer(text.encode() if isinstance(text, str) else bytes(text), dtype=np.uint8)
+        ptr, n = (keep.ctypes.data if keep.size else None), int(keep.size)
+    out = ctypes.c_void_p()
+    info = _TextInfo()
+    _check(lib.dbbc_graph_create_text(ptr, n, int(flags), _stream_ptr(stream), ctypes.byref(out),
+                                      ctypes.byref(info)), "dbbc_graph_create_text")
+    return out.value, {k: int(getattr(info, k)) for k, _ in _TextInfo._fields_}
 
 
 def dbbc_graph_stats(g: int) -> dict:
@@ -386,6 +416,28 @@ class Graph:
         c = dbbc_count_per_vertex(self.handle, bu, bv, uu, uv, Options(**opts) if opts else None,
                                   stream)
         return c, bu, bv, uu, uv
+
+    @classmethod
+    def from_text(cls, text, flags=0, stream=None):
+        """A graph read from an edge-list text on the device (ids compacted
+        per side; ``raw_ids`` maps them back).  ``info`` holds the line and
+        record counts."""
+        handle, info = dbbc_graph_create_text(text, flags, stream)
+        g = cls.__new__(cls)
+        g.handle = handle
+        g.n_u, g.n_v = info["n_u"], info["n_v"]
+        g.m_in = info["records"]
+        g.info = info
+        return g
+
+    def raw_ids(self, side: int, stream=None):
+        """int64 CUDA tensor: the raw id of each compact id of a side (0 = U)."""
+        import torch
+        n = self.n_u if side == 0 else self.n_v
+        t = torch.empty(n, dtype=torch.int64, device=torch.device("cuda", torch.cuda.current_device()))
+        _check(load().dbbc_graph_raw_ids(self.handle, int(side), t.data_ptr(), _stream_ptr(stream)),
+               "dbbc_graph_raw_ids")
+        return t
 
     def count_per_edge(self, stream=None, **opts):
         """(Counts, bal_e, unb_e): int64 CUDA tensors, one entry per input record."""

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdbbc.so")
-SOURCES = ["build.hip", "plan.cpp", "api.cpp", "server.cpp", "count.hip", "pervertex.hip", "hub.hip"]
+SOURCES = ["build.hip", "ingest.hip", "plan.cpp", "api.cpp", "server.cpp", "count.hip", "pervertex.hip",
+           "hub.hip"]
 HEADERS = ["internal.h", "kernels.h"]
 ARCH = "gfx950"
 FLAGS = [

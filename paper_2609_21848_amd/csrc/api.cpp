@@ -312,6 +312,7 @@ struct dbbc_graph {
   DevBuf pe_out[2][3];    // per-edge credits by CSR position [side][packed, wide bal, wide unb]
   DevBuf edge_rec, edge_pos_v;  // U-CSR position -> input record, -> V-CSR position
   DevBuf pe_tmp;          // stands in for a NULL per-edge output
+  DevBuf raw_ids[2];      // graphs read from text: compact -> raw id per side
   std::vector<KernelRec> timers;  // events are reused across timed counts
   size_t timers_used = 0;
   bool timed_valid = false;
@@ -594,6 +595,7 @@ const char* dbbc_status_string(int status) {
     case DBBC_E_DEVICE: return "device error";
     case DBBC_E_TOO_LARGE: return "graph too large";
     case DBBC_E_NO_DEVICE: return "no gfx950 device";
+    case DBBC_E_PARSE: return "malformed edge record";
     default: return "unknown status";
   }
 }
@@ -634,6 +636,53 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, con
   return DBBC_OK;
 }
 
+int dbbc_graph_create_text(const char* text, int64_t len, uint32_t flags, void* hip_stream, dbbc_graph** out,
+                           dbbc_text_info* info) {
+  g_last_error.clear();
+  if (!out) return fail(DBBC_E_INVALID_ARG, "out must not be NULL");
+  if (flags & ~(DBBC_INPUT_DEVICE | DBBC_DUP_REJECT)) return fail(DBBC_E_INVALID_ARG, "unknown flag");
+  if (len < 0 || (len > 0 && !text)) return fail(DBBC_E_INVALID_ARG, "text must not be NULL and len non-negative");
+  if (len >= (int64_t(1) << 31) - 1) return fail(DBBC_E_TOO_LARGE, "text longer than 2^31 - 2 bytes");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  DeviceInfo di;
+  int rc = current_device(di);
+  if (rc != DBBC_OK) return rc;
+  std::unique_ptr<dbbc_graph> g(new (std::nothrow) dbbc_graph());
+  if (!g) return fail(DBBC_E_OOM, "host allocation failed");
+  g->dev = di;
+  std::string err;
+  dbbc::DeviceCsr csr;
+  dbbc::IngestOut io;
+  rc = dbbc::ingest_text(text, len, flags, st, g->host, csr, io, err);
+  if (rc != DBBC_OK) return fail(rc, err);
+  for (int s = 0; s < 2; ++s) {  // the handle owns the device arrays from here
+    g->adj[s].p = csr.adj[s];
+    g->adj[s].bytes = csr.adj_bytes[s];
+    g->off[s].p = csr.off[s];
+    g->off[s].bytes = csr.off_bytes[s];
+    g->raw_ids[s].p = io.raw[s];
+    g->raw_ids[s].bytes = io.raw_bytes[s];
+  }
+  HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), kCtlWords * sizeof(unsigned long long),
+                        hipHostMallocDefault));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (info) *info = dbbc_text_info{io.lines, io.records, g->host.n_u, g->host.n_v};
+  *out = g.release();
+  return DBBC_OK;
+}
+
+int dbbc_graph_raw_ids(const dbbc_graph* g, int32_t side, int64_t* out, void* hip_stream) {
+  g_last_error.clear();
+  if (!g || !out || side < 0 || side > 1) return fail(DBBC_E_INVALID_ARG, "NULL argument or side not 0 / 1");
+  if (!g->raw_ids[side].p) return fail(DBBC_E_INVALID_ARG, "the graph was not read from text");
+  const size_t n = static_cast<size_t>(side == 0 ? g->host.n_u : g->host.n_v);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  HIP_TRY(hipMemcpyAsync(out, g->raw_ids[side].p, n * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return DBBC_OK;
+}
+
 int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
   if (!g || !out) return fail(DBBC_E_INVALID_ARG, "NULL argument");
   dbbc_stats s{};
@@ -646,7 +695,7 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
   size_t b = g->ctl.bytes + g->plan.bytes() + g->pv_plan.bytes() + g->edge_rec.bytes +
              g->edge_pos_v.bytes + g->pe_tmp.bytes;
   for (int k = 0; k < 2; ++k) {
-    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes;
+    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes + g->raw_ids[k].bytes;
     for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes;
     for (int j = 0; j < 3; ++j) b += g->pe_out[k][j].bytes;
   }

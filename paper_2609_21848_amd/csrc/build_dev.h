@@ -29,4 +29,20 @@ int build_device_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, co
                        const int8_t* sign, uint32_t flags, hipStream_t st, HostGraph& g, DeviceCsr& out,
                        std::string& err);
 
+// What a text ingestion hands to its graph handle besides the CSR: the
+// per-side compact -> raw id maps (hipMalloc'ed int64 arrays, ascending raw
+// ids; the handle frees them) and the line and record counts.
+struct IngestOut {
+  int64_t lines = 0, records = 0;
+  void* raw[2] = {nullptr, nullptr};
+  size_t raw_bytes[2] = {0, 0};
+};
+
+// Parse an edge list in text form on the device (host text, or device text
+// with DBBC_INPUT_DEVICE), compact each side's ids and build the graph as
+// build_device_graph does.  Returns a DBBC status and fills err on failure
+// (nothing is handed over then).
+int ingest_text(const char* text, int64_t len, uint32_t flags, hipStream_t st, HostGraph& g, DeviceCsr& csr,
+                IngestOut& out, std::string& err);
+
 }  // namespace dbbc

@@ -17,3 +17,4 @@ from .graphs import (  # noqa: F401
     upload_graph,
     CONFIGS,
 )
+from .text import edge_text, messy_edge_text, raw_ids  # noqa: F401

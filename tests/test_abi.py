@@ -56,6 +56,13 @@ def test_argument_errors_need_no_device():
     assert lib.dbbc_graph_create(2, 2, 1, None, None, None, 0, None, None) == dbbc.DBBC_E_INVALID_ARG
     assert lib.dbbc_graph_create(2, 2, 0, None, None, None, 0x80, None,
                                  ctypes.byref(ctypes.c_void_p())) == dbbc.DBBC_E_INVALID_ARG
+    out = ctypes.c_void_p()
+    assert lib.dbbc_graph_create_text(None, 5, 0, None, ctypes.byref(out), None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create_text(b"1 2 1", 5, 0x80, None, ctypes.byref(out), None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create_text(b"1 2 1", 5, 0, None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create_text(b"1 2 1", 1 << 40, 0, None, ctypes.byref(out),
+                                      None) == dbbc.DBBC_E_TOO_LARGE
+    assert lib.dbbc_graph_raw_ids(None, 0, None, None) == dbbc.DBBC_E_INVALID_ARG
     # NULL handles are rejected or ignored
     assert lib.dbbc_count(None, None, None, None) == dbbc.DBBC_E_INVALID_ARG
     assert lib.dbbc_count_async(None, None, None) == dbbc.DBBC_E_INVALID_ARG
