@@ -333,6 +333,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-pv", action="store_true", help="skip the per-vertex pass")
     ap.add_argument("--no-pe", action="store_true", help="skip the per-edge pass")
+    ap.add_argument("--no-ingest", action="store_true",
+                    help="skip reading the workload back from edge-list text on the device")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (for scaling the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -515,6 +517,23 @@ def main():
                            "sums_equal_four_times_counts": sums_ok}
         log(f"[bench] per-edge pass {ms_pe:.2f} ms ({w_vp / ms_pe / 1e6:.1f} GWedges/s)")
     h.close()
+    if not args.no_ingest:
+        # the same edges as "u v s" text (13-digit raw ids), read on the device:
+        # upload, line split, parse, id compaction and build
+        from synth import edge_text
+        text = edge_text(g.n_u, g.n_v, g.u, g.v, g.sign)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ht = dbbc.Graph.from_text(text, stream=stream)
+        t_text = time.perf_counter() - t
+        c_text = ht.count()
+        ht.close()
+        out["ingest"] = {"text_bytes": len(text), "records": g.m, "seconds": t_text,
+                         "gb_per_s": len(text) / t_text / 1e9, "mrecords_per_s": g.m / t_text / 1e6,
+                         "array_build_seconds": t_build, "same_counts": tuple(c_text) == tuple(first)}
+        log(f"[bench] text ingest of {len(text) / 1e9:.2f} GB ({g.m} records) in {t_text:.2f}s "
+            f"({len(text) / t_text / 1e9:.2f} GB/s); counts {'equal' if tuple(c_text) == tuple(first) else 'DIFFER'}")
+        del text
     if not args.no_batch:
         out["batched"] = bench_batched(dbbc, args.steps, args.warmup, args.batch_graphs, 64)
     if not args.no_serve:
