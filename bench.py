@@ -315,6 +315,43 @@ def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: fl
     return res
 
 
+def bench_ablation(dbbc) -> dict:
+    """The paper's wedge-separation study (Section V, Table IV) on its two
+    datasets' stand-ins: the explicit-verification baseline (every pair of
+    wedges checked on its signs) against the bucketed count, same device,
+    same results."""
+    import torch
+    from synth import config_graph
+
+    res = {}
+    for name in ("se_like", "ho_like"):
+        g = config_graph(name)
+        with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
+            ref = h.count()  # plans and warms up
+            times = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                c = h.count()
+                times.append(time.perf_counter() - t)
+                assert c == ref
+            t_b = sorted(times)[2]
+            h.count_explicit()  # warm-up (uploads the reverse positions)
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                e = h.count_explicit()
+                times.append(time.perf_counter() - t)
+            t_e = sorted(times)[1]
+        res[name] = {"edges": g.m, "balanced": ref.balanced, "butterflies": ref.total,
+                     "wedges": ref.wedges, "explicit_ms": t_e * 1e3, "bucketed_ms": t_b * 1e3,
+                     "speedup": t_e / t_b, "same_counts": tuple(e) == tuple(ref)}
+        log(f"[bench] ablation {name}: explicit {t_e * 1e3:.2f} ms, bucketed {t_b * 1e3:.3f} ms "
+            f"({t_e / t_b:.0f}x), counts {'equal' if tuple(e) == tuple(ref) else 'DIFFER'}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +370,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-pv", action="store_true", help="skip the per-vertex pass")
     ap.add_argument("--no-pe", action="store_true", help="skip the per-edge pass")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the wedge-separation study (explicit pair checks vs Lemma 1 buckets)")
     ap.add_argument("--no-ingest", action="store_true",
                     help="skip reading the workload back from edge-list text on the device")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -534,6 +573,8 @@ def main():
         log(f"[bench] text ingest of {len(text) / 1e9:.2f} GB ({g.m} records) in {t_text:.2f}s "
             f"({len(text) / t_text / 1e9:.2f} GB/s); counts {'equal' if tuple(c_text) == tuple(first) else 'DIFFER'}")
         del text
+    if not args.no_ablation:
+        out["ablation"] = bench_ablation(dbbc)
     if not args.no_batch:
         out["batched"] = bench_batched(dbbc, args.steps, args.warmup, args.batch_graphs, 64)
     if not args.no_serve:

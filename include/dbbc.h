@@ -217,6 +217,16 @@ int dbbc_count_per_vertex(dbbc_graph *g, const dbbc_options *opt, int64_t *bal_u
 int dbbc_count_per_edge(dbbc_graph *g, const dbbc_options *opt, int64_t *bal_e, int64_t *unb_e,
                         dbbc_counts *out_host, void *hip_stream);
 
+/* The baseline of the paper's symmetric / asymmetric wedge separation study
+ * (Section V, Table IV), for measuring what Lemma 1's two buckets save: the
+ * same vertex-priority wedges, but every pair of wedges of a vertex pair is
+ * checked on its four signs one by one (work proportional to the
+ * butterflies rather than the wedges).  Same results as dbbc_count (wedges =
+ * W_VP); on graphs with many butterflies it is slow by design.  Keeps the
+ * reverse positions and cuts of the CSR and per-workgroup scratch on the
+ * handle's device memory while it runs. */
+int dbbc_count_explicit(dbbc_graph *g, dbbc_counts *out_host, void *hip_stream);
+
 /* Build the handle's counting plan for opt now (NULL = defaults), so that
  * the next count with the same options starts at once; returns when the plan
  * is on the device.  Counts re-plan by themselves when the options change. */

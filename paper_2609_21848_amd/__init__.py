@@ -39,6 +39,7 @@ DBBC_BATCH_CAPTURE = 0x1
 EXPORTS = (
     "dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async", "dbbc_count_read",
     "dbbc_count_per_vertex", "dbbc_count_per_edge", "dbbc_graph_create_text", "dbbc_graph_raw_ids",
+    "dbbc_count_explicit",
     "dbbc_batch_create", "dbbc_batch_reset", "dbbc_batch_launch",
     "dbbc_batch_read",
     "dbbc_batch_count", "dbbc_batch_size", "dbbc_batch_destroy", "dbbc_count_batch", "dbbc_autotune",
@@ -135,6 +136,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_graph_create_text.argtypes = [vp, i64, u32, vp, ctypes.POINTER(vp),
                                            ctypes.POINTER(_TextInfo)]
     lib.dbbc_graph_raw_ids.argtypes = [vp, i32, vp, vp]
+    lib.dbbc_count_explicit.argtypes = [vp, ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
     lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
@@ -171,7 +173,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_version.restype = ctypes.c_char_p
     for name in ("dbbc_graph_create", "dbbc_graph_stats", "dbbc_count", "dbbc_count_async",
                  "dbbc_count_read", "dbbc_count_per_vertex", "dbbc_count_per_edge",
-                 "dbbc_graph_create_text", "dbbc_graph_raw_ids",
+                 "dbbc_graph_create_text", "dbbc_graph_raw_ids", "dbbc_count_explicit",
                  "dbbc_batch_create", "dbbc_batch_reset",
                  "dbbc_batch_launch",
                  "dbbc_batch_read", "dbbc_batch_count", "dbbc_count_batch", "dbbc_autotune",
@@ -447,6 +449,13 @@ class Graph:
         ue = torch.empty(self.m_in, dtype=torch.int64, device=dev)
         c = dbbc_count_per_edge(self.handle, be, ue, Options(**opts) if opts else None, stream)
         return c, be, ue
+
+    def count_explicit(self, stream=None) -> Counts:
+        """The explicit-verification baseline (every wedge pair checked)."""
+        c = _Counts()
+        _check(load().dbbc_count_explicit(self.handle, ctypes.byref(c), _stream_ptr(stream)),
+               "dbbc_count_explicit")
+        return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
 
     def count_async(self, stream=None, **opts) -> None:
         dbbc_count_async(self.handle, Options(**opts) if opts else None, stream)

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdbbc.so")
 SOURCES = ["build.hip", "ingest.hip", "plan.cpp", "api.cpp", "server.cpp", "count.hip", "pervertex.hip",
-           "hub.hip"]
+           "hub.hip", "explicit.hip"]
 HEADERS = ["internal.h", "kernels.h"]
 ARCH = "gfx950"
 FLAGS = [

@@ -313,6 +313,7 @@ struct dbbc_graph {
   DevBuf edge_rec, edge_pos_v;  // U-CSR position -> input record, -> V-CSR position
   DevBuf pe_tmp;          // stands in for a NULL per-edge output
   DevBuf raw_ids[2];      // graphs read from text: compact -> raw id per side
+  DevBuf ex_rev[2], ex_cut[2];  // explicit-verification baseline: rev and cut per side
   std::vector<KernelRec> timers;  // events are reused across timed counts
   size_t timers_used = 0;
   bool timed_valid = false;
@@ -695,7 +696,8 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
   size_t b = g->ctl.bytes + g->plan.bytes() + g->pv_plan.bytes() + g->edge_rec.bytes +
              g->edge_pos_v.bytes + g->pe_tmp.bytes;
   for (int k = 0; k < 2; ++k) {
-    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes + g->raw_ids[k].bytes;
+    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes + g->raw_ids[k].bytes + g->ex_rev[k].bytes +
+         g->ex_cut[k].bytes;
     for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes;
     for (int j = 0; j < 3; ++j) b += g->pe_out[k][j].bytes;
   }
@@ -716,6 +718,70 @@ int dbbc_count(dbbc_graph* g, const dbbc_options* opt, dbbc_counts* out_host, vo
   if (rc != DBBC_OK) return rc;
   HIP_TRY(hipStreamSynchronize(st));
   return finish_lone(g, out_host, opt && (opt->flags & DBBC_OPT_TIME_KERNELS));
+}
+
+int dbbc_count_explicit(dbbc_graph* g, dbbc_counts* out_host, void* hip_stream) {
+  g_last_error.clear();
+  if (!out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
+  int rc = check_graph(g);
+  if (rc != DBBC_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const dbbc::HostGraph& hg = g->host;
+  // the most wedges of one pivot (the list a workgroup holds at once)
+  int64_t cap = 1;
+  for (int s = 0; s < 2; ++s) {
+    const dbbc::HostSide& S = hg.side[s];
+    const dbbc::HostSide& O = hg.side[1 - s];
+    if (!g->ex_rev[s].p) {
+      HIP_TRY(upload(g->ex_rev[s], S.rev, st));
+      HIP_TRY(upload(g->ex_cut[s], S.cut, st));
+    }
+    for (int32_t x = 0; x < S.n; ++x) {
+      int64_t wx = 0;
+      for (uint32_t e = S.off[x] + static_cast<uint32_t>(S.cut[x]); e < S.off[x + 1]; ++e) {
+        const uint32_t y = S.adj[e] >> 1;
+        wx += static_cast<int64_t>(O.off[y + 1] - O.off[y]) - 1 - S.rev[e];
+      }
+      cap = std::max(cap, wx);
+    }
+  }
+  const int64_t nmax = std::max<int64_t>(hg.n_u, hg.n_v);
+  const int64_t per_wg = 16 * nmax + cap;
+  const int64_t budget = int64_t(8) << 30;  // scratch of all workgroups
+  const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(2 * g->dev.cus, budget / per_wg)));
+  DevBuf scratch, lists;
+  HIP_TRY(scratch.alloc(static_cast<size_t>(grid) * 16 * static_cast<size_t>(nmax)));
+  HIP_TRY(lists.alloc(static_cast<size_t>(grid) * static_cast<size_t>(cap)));
+  unsigned long long* ctl = g->ctl.as<unsigned long long>();
+  HIP_TRY(dbbc::launch_fill_u64(ctl, kCtlWords, 0ull, st));
+  uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + kCtlQueues);
+  for (int s = 0; s < 2; ++s) {
+    // counters start at zero (the layout differs per side: clear it all)
+    HIP_TRY(dbbc::launch_fill_u64(scratch.as<unsigned long long>(), static_cast<size_t>(grid) * 2 * nmax, 0ull, st));
+    dbbc::ExplicitArgs a{};
+    a.off_s = g->off[s].as<uint32_t>();
+    a.adj_s = g->adj[s].as<uint32_t>();
+    a.rev_s = g->ex_rev[s].as<int32_t>();
+    a.cut_s = g->ex_cut[s].as<int32_t>();
+    a.off_o = g->off[1 - s].as<uint32_t>();
+    a.adj_o = g->adj[1 - s].as<uint32_t>();
+    a.n_s = hg.side[s].n;
+    a.scratch = scratch.as<uint32_t>();
+    a.lists = lists.as<uint8_t>();
+    a.list_cap = cap;
+    a.queue = queues + s;
+    a.res = ctl;
+    a.err = ctl + kCtlErr;
+    HIP_TRY(dbbc::launch_explicit(a, std::min<int>(grid, std::max(1, a.n_s)), st));
+  }
+  HIP_TRY(hipMemcpyAsync(g->pinned, g->ctl.p, kCtlWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (g->pinned[kCtlErr]) return fail(DBBC_E_DEVICE, "explicit count: a pivot's wedges exceeded its list");
+  out_host->balanced = static_cast<int64_t>(g->pinned[dbbc::kResBalanced]);
+  out_host->unbalanced = static_cast<int64_t>(g->pinned[dbbc::kResUnbalanced]);
+  out_host->total = static_cast<int64_t>(g->pinned[dbbc::kResTotal]);
+  out_host->wedges = hg.wedges_vp;
+  return DBBC_OK;
 }
 
 int dbbc_graph_plan(dbbc_graph* g, const dbbc_options* opt, void* hip_stream) {

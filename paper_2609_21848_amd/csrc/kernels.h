@@ -159,6 +159,25 @@ hipError_t launch_pe_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_pe_hash(const HashArgs& a, int grid, hipStream_t st);
 hipError_t launch_edge_combine(const EdgeCombineArgs& a, int grid, hipStream_t st);
 
+// Explicit-verification count of one side's pivots (the wedge-separation
+// baseline): per-workgroup scratch of 4 x n_s words and list_cap bytes.
+struct ExplicitArgs {
+  const uint32_t* off_s;    // side s CSR offsets [n_s + 1]
+  const uint32_t* adj_s;    // side s entries
+  const int32_t* rev_s;     // per side-s entry: index of its row vertex inside the other row
+  const int32_t* cut_s;     // per side-s row: neighbours of higher priority
+  const uint32_t* off_o;    // other side's CSR
+  const uint32_t* adj_o;
+  int32_t n_s;
+  uint32_t* scratch;
+  uint8_t* lists;
+  int64_t list_cap;         // at least the wedges of any pivot
+  uint32_t* queue;
+  unsigned long long* res;  // result slot
+  unsigned long long* err;
+};
+hipError_t launch_explicit(const ExplicitArgs& a, int grid, hipStream_t st);
+
 // Copy k graphs' item lists (or reduce lists) into one list, setting each
 // entry's graph field.
 hipError_t launch_assemble_items(const AssembleSrc* srcs, int k, Item* dst, hipStream_t st);
