@@ -91,3 +91,17 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(dbbc, "_lib", None)
     with pytest.raises(ImportError):
         dbbc.load(str(tmp_path / "nope.so"))
+
+
+def test_plain_c_consumer(tmp_path):
+    # the header compiles as strict C99 and a C program links against the
+    # library and gets argument errors without a device
+    import subprocess
+    lib_dir = os.path.dirname(dbbc.LIB_PATH)
+    exe = str(tmp_path / "abi_c")
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                           f"-I{os.path.join(ROOT, 'include')}", "-o", exe,
+                           os.path.join(ROOT, "tests", "native", "abi_c.c"), f"-L{lib_dir}", "-ldbbc",
+                           f"-Wl,-rpath,{lib_dir}"])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
