@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       walk_batch<8>(sc.segs, k0, k1, adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len,
-                    DirectTallyBF{cnt, static_cast<uint32_t>(kDirectKeys + tid)});
+                    DirectTallyBF<kDirectKeys>{cnt, cnt + kDirectKeys + tid});
     }
     __syncthreads();
     if (it.flags & kItemMultiPart) {
@@ -143,7 +143,9 @@ constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
 
 __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
-  __shared__ uint32_t cnt[kReverseWaves][kReverseWords + kWave];  // counters, then one dummy per lane
+  // counters, each wavefront's array aligned to its size; one dummy word per lane
+  __shared__ __attribute__((aligned(kReverseWords * 4))) uint32_t cnt[kReverseWaves][kReverseWords];
+  __shared__ uint32_t dummies[kReverseWaves][kWave];
   __shared__ uint32_t mbase[kReverseWaves][kGather];
   __shared__ uint8_t mtag[kReverseWaves][kGather];
   // wave index, known to the compiler as wavefront-uniform
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     if (j2 < n) nxt2 = load_const(a.items, j2);
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     walk_item<8>(it, first, sc.segs, sc.other_adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len,
-                 PairTallyBF{C, static_cast<uint32_t>(kReverseWords + lane)});
+                 PairTallyBF<kReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
     wave_sync_lds();
     const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the item's keys
     if (it.flags & kItemMultiPart) {

@@ -199,11 +199,15 @@ __device__ __forceinline__ void walk_add(F& f, uint32_t e, uint32_t tag, bool va
 // wavefront, calling f.add(entry, tag, valid[, pos]) once per wedge slot.
 //  - Runs of at least long_len entries are consumed as a stream of
 //    256-entry chunks: every lane loads 4 aligned entries (16 bytes) per
-//    chunk, U chunks are in flight per lane, and a chunk's out-of-run words
-//    are masked.  The chunk loop is wavefront-uniform.  With kLaneMajor the
-//    lane's 4 entries are instead 64 apart (four 4-byte loads), so that each
-//    of the 4 calls of a chunk sees 64 consecutive positions across the
-//    lanes (per-position global atomics of a functor then coalesce).
+//    chunk, U chunks are in flight per lane, and a chunk's words past the
+//    run's end are masked.  The chunk loop is wavefront-uniform.  The 0-3
+//    entries before a long run's first 16-byte boundary are staged with the
+//    short runs, so every chunk starts inside its run and a slot's test is
+//    one compare of its offset in the chunk with the run's remaining
+//    length.  With kLaneMajor the lane's 4 entries are instead 64 apart
+//    (four 4-byte loads), so that each of the 4 calls of a chunk sees 64
+//    consecutive positions across the lanes (per-position global atomics
+//    of a functor then coalesce).
 //  - Shorter runs are staged (stage_round) so that every lane holds wedges;
 //    the loads of the first round are issued before the long stream and the
 //    next round's loads before the current round is tallied.
@@ -212,39 +216,45 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
                                           uint32_t long_len, F&& f) {
   const int lane = lane_id();
   const uint32_t start = sr.start, tag = sr.tag, len = sr.len;
-  uint64_t longm = __ballot(len >= long_len);
-  const uint32_t slen = len >= long_len ? 0u : len;
+  // long_len >= 16, so a long run keeps at least 13 entries after its head
+  const bool is_long = len >= long_len;
+  const uint32_t head = is_long ? (0u - start) & 3u : 0u;
+  uint64_t longm = __ballot(is_long);
+  const uint32_t slen = is_long ? head : len;
   uint32_t total;
   const uint32_t excl = wave_excl_scan(slen, &total);
   const uint32_t base = start - excl;
+  const uint32_t lstart = start + head, lend = start + len;
   Staged cur;
   if (total) stage_round(cur, marks, excl, slen, base, tag, total, 0, adj);
-  uint32_t cur_st = 0, cur_end = 0, cur_g = 0, cur_pos = 0;
+  uint32_t cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
+  // offset of a lane's word q in a chunk (loop-invariant)
+  uint32_t koff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) koff[q] = kLaneMajor ? lane + q * kWave : 4 * lane + q;
   while (longm || have) {
     u32x4 v[U];
-    uint32_t vst[U], vend[U], vg[U], vp[U];
+    uint32_t vrem[U], vg[U], vpos[U];
     int nv = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (!have && longm) {
         const int j = __ffsll(static_cast<unsigned long long>(longm)) - 1;
         longm &= longm - 1;
-        cur_st = readlane(start, j);
-        cur_end = cur_st + readlane(len, j);
+        cur_pos = readlane(lstart, j);
+        cur_end = readlane(lend, j);
         cur_g = readlane(tag, j);
-        cur_pos = cur_st & ~3u;
         have = true;
       }
       // The load is unconditional (no wait on registers of a skipped load):
       // lanes past the run's end and empty slots read the first entries of
-      // the array, and their words fail the index test below.
+      // the array, and their words fail the offset test below.
       const bool h = have;
       const uint32_t p = cur_pos + (kLaneMajor ? lane : 4 * lane);
-      vst[u] = cur_st;
       vg[u] = cur_g;
-      vp[u] = p;
-      vend[u] = h ? cur_end : 0u;
+      vpos[u] = cur_pos;
+      vrem[u] = h ? cur_end - cur_pos : 0u;  // entries left in the run from the chunk's start
       if (kLaneMajor) {
         const global_t<uint32_t>* a = as_global(adj);
         v[u].x = a[(h && p < cur_end) ? p : 0u];
@@ -267,10 +277,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       if (u < nv) {
         const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t idx = vp[u] + (kLaneMajor ? q * kWave : q);
-          walk_add(f, e4[q], vg[u], idx >= vst[u] && idx < vend[u], idx, 0);
-        }
+        for (int q = 0; q < 4; ++q) walk_add(f, e4[q], vg[u], koff[q] < vrem[u], vpos[u] + koff[q], 0);
       }
     }
   }
@@ -313,9 +320,12 @@ __device__ __forceinline__ SegReg first_batch(const Item& it, const Segment* __r
                            it.seg_begin + kWave < seg_end ? it.seg_begin + kWave : seg_end);
 }
 
-// Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric.
+// Packed counter increment of one wedge: +1 symmetric or +2^16 asymmetric,
+// i.e. 1 << 16 (e ^ g) taken mod 32 (only bit 0 of e and g matters).  Sums
+// are XORs mod 2, so the shift is the one multiply-add 16 e + 16 g, whose
+// bits past the fifth the shift instruction ignores.
 __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
-  return ((e ^ g) & 1u) ? 0x10000u : 1u;
+  return 1u << (((e << 4) + (g << 4)) & 31u);
 }
 
 // Tally functors for walk_regs: add(entry, g, valid) counts a valid
@@ -338,21 +348,36 @@ struct PairTally {  // 8 | 8-bit counters, two keys per 32-bit word
 };
 
 // Branch-free forms: a masked slot adds into a dummy word of its own lane
-// (dummy, past the counters) instead of switching the execution mask around
-// every atomic; dummy words are never read.
+// (past the counters) instead of switching the execution mask around every
+// atomic; dummy words are never read.  The key index is reduced modulo the
+// counter array's size (a power of two; valid keys are always below it), so
+// a key can never address past the array, and an array aligned to its own
+// size gets its LDS address from one bitwise instruction.
+template <uint32_t kWords>
 struct DirectTallyBF {
-  uint32_t* cnt;
-  uint32_t dummy;  // word index of this lane's dummy
+  uint32_t* cnt;    // kWords counters
+  uint32_t* dummy;  // this lane's dummy word
   __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    atomicAdd(&cnt[valid ? e >> 1 : dummy], wedge_inc(e, g));
+    static_assert((kWords & (kWords - 1)) == 0, "power of two");
+    atomicAdd(valid ? cnt + ((e >> 1) & (kWords - 1)) : dummy, wedge_inc(e, g));
   }
 };
 
+// 8|8-bit pair counters addressed by LDS byte address: base is aligned to
+// the array's size and a valid slot's key is below 2 kWords (every key of a
+// reverse item lies in the reverse window), so the word's address
+// base | (e & ~3) is one AND-OR instruction.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ uint32_t lds_addr(uint32_t* p) {
+  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u32*)p));
+}
+template <uint32_t kWords>
 struct PairTallyBF {
-  uint32_t* cnt;
-  uint32_t dummy;
+  uint32_t base;   // LDS address of kWords counter words (2 kWords keys), aligned to 4 kWords
+  uint32_t dummy;  // LDS address of this lane's dummy word
   __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    atomicAdd(&cnt[valid ? e >> 2 : dummy], 1u << (((e ^ (g & 1u)) & 3u) << 3));
+    const uint32_t a = valid ? base | (e & ~3u) : dummy;
+    atomicAdd((uint32_t*)(lds_u32*)static_cast<uintptr_t>(a), 1u << (((e ^ (g & 1u)) & 3u) << 3));
   }
 };
 
