@@ -35,14 +35,14 @@ constexpr int kDirectKeys = 32768;
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t cnt[kDirectKeys + kDirectThreads];  // counters, then one dummy per thread
-  __shared__ uint32_t mbase[kDirectWaves][kGather];
-  __shared__ uint8_t mtag[kDirectWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kDirectWaves][kGather];
+  __shared__ uint8_t mflag[kDirectWaves][kGather];
   __shared__ int32_t item_sh;
   __shared__ unsigned long long blk[2];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   for (int i = tid; i < kDirectKeys; i += kDirectThreads) cnt[i] = 0;
-  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&mtag[0][0])[i] = 0;
+  for (int i = tid; i < kDirectWaves * static_cast<int>(kGather); i += kDirectThreads) (&mflag[0][0])[i] = 0;
   if (tid == 0) blk[0] = blk[1] = 0;
   // Per thread, for the current graph: twice the balanced count (sum of
   // p^2 + n^2 minus the wedges) and the unbalanced count.  Only the
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<8>(sc.segs, k0, k1, adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len,
+      walk_batch<8>(sc.segs, k0, k1, adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
                     DirectTallyBF<kDirectKeys>{cnt, cnt + kDirectKeys + tid});
     }
     __syncthreads();
@@ -146,14 +146,14 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   // counters, each wavefront's array aligned to its size; one dummy word per lane
   __shared__ __attribute__((aligned(kReverseWords * 4))) uint32_t cnt[kReverseWaves][kReverseWords];
   __shared__ uint32_t dummies[kReverseWaves][kWave];
-  __shared__ uint32_t mbase[kReverseWaves][kGather];
-  __shared__ uint8_t mtag[kReverseWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kReverseWaves][kGather];
+  __shared__ uint8_t mflag[kReverseWaves][kGather];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
   for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
   wave_sync_lds();
   SqTotals tot;
   const int32_t n = a.n_items;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     Item nxt2{};
     if (j2 < n) nxt2 = load_const(a.items, j2);
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
-    walk_item<8>(it, first, sc.segs, sc.other_adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len,
+    walk_item<8, false, true>(it, first, sc.segs, sc.other_adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
                  PairTallyBF<kReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
     wave_sync_lds();
     const int32_t w_hi = (it.key_hi + 1) >> 1;  // counter words of the item's keys
@@ -196,11 +196,11 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     } else {
       // p, n <= 255 and at most 2 * kReverseWords / 64 = 64 keys per lane;
       // every key of the item lies in the window, so its swept wedges are
-      // the item's wedges (added once, by lane 0)
+      // the item's wedges (added once, by lane 0).  No test for all-zero
+      // words: a wavefront would skip only if all its 64 lanes saw zeros.
       SqSums ss;
       for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&C[wd]);
-        if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
         *reinterpret_cast<uint4*>(&C[wd]) = make_uint4(0, 0, 0, 0);
         ss.add_word(c4.x);
         ss.add_word(c4.y);
@@ -231,7 +231,7 @@ constexpr int kSmallSlots = 2 * kSmallGroupWork;
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   __shared__ uint32_t keys[kSmallWaves][kSmallSlots];
   __shared__ uint32_t vals[kSmallWaves][kSmallSlots];
-  __shared__ uint32_t marks[kSmallWaves][2][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t marks[kSmallWaves][2][kGather];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
@@ -329,8 +329,8 @@ constexpr int kHashSlots = 8192;
 __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
   __shared__ uint32_t keys[kHashSlots];
   __shared__ unsigned long long vals[kHashSlots];
-  __shared__ uint32_t mbase[kHashWaves][kGather];
-  __shared__ uint8_t mtag[kHashWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kHashWaves][kGather];
+  __shared__ uint8_t mflag[kHashWaves][kGather];
   __shared__ int32_t item_sh;
   __shared__ uint32_t work_sh;
   const int tid = threadIdx.x;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     keys[i] = kEmpty;
     vals[i] = 0;
   }
-  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&mtag[0][0])[i] = 0;
+  for (int i = tid; i < kHashWaves * static_cast<int>(kGather); i += kHashThreads) (&mflag[0][0])[i] = 0;
   Sums sums;
   uint32_t graph = kNoGraph;
   for (;;) {
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     for (uint32_t pass = 0; pass < passes; ++pass) {
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-        walk_batch<4>(sc.segs, k0, k1, sc.other_adj, Marks<uint8_t>{mbase[wave], mtag[wave]}, a.long_len, hash_tally([&](uint32_t e, uint32_t g) {
+        walk_batch<4>(sc.segs, k0, k1, sc.other_adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len, hash_tally([&](uint32_t e, uint32_t g) {
           const uint32_t key = e >> 1;
           const uint32_t hk = mix32(key);
           if (passes > 1 && (hk >> 16) % passes != pass) return;

@@ -197,8 +197,8 @@ constexpr int kPVDirectWaves = kPVDirectThreads / kWave;
 template <bool kEdge>
 __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
   __shared__ uint32_t C[2 * kPVWindow];  // P | N, or packed words
-  __shared__ uint32_t mbase[kPVDirectWaves][kGather];
-  __shared__ uint32_t mtag[kPVDirectWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVDirectWaves][kGather];
+  __shared__ uint32_t mflag[kPVDirectWaves][kGather];
   __shared__ unsigned long long cb[kPVDirectWaves][kWave], cu[kPVDirectWaves][kWave];
   __shared__ unsigned long long hbal[kPVHotKeys], hunb[kPVHotKeys];
   __shared__ int32_t item_sh;
@@ -209,10 +209,10 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
   uint32_t* const P = C;
   uint32_t* const N = C + kPVWindow;
   for (int i = tid; i < kPVHotKeys; i += kPVDirectThreads) hbal[i] = hunb[i] = 0;
-  for (int i = tid; i < kPVDirectWaves * static_cast<int>(kGather); i += kPVDirectThreads) (&mtag[0][0])[i] = 0;
+  for (int i = tid; i < kPVDirectWaves * static_cast<int>(kGather); i += kPVDirectThreads) (&mflag[0][0])[i] = 0;
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
-  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  const Marks<uint32_t> mk{mtab[wave], mflag[wave]};
   Sums sums;
   uint32_t graph = kNoGraph;
   for (;;) {
@@ -324,8 +324,8 @@ constexpr int kPVReverseWords = kMaxReverseL / 2;
 template <bool kEdge>
 __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ uint32_t cnt[kPVReverseWaves][kPVReverseWords];
-  __shared__ uint32_t mbase[kPVReverseWaves][kGather];
-  __shared__ uint32_t mtag[kPVReverseWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVReverseWaves][kGather];
+  __shared__ uint32_t mflag[kPVReverseWaves][kGather];
   __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
   __shared__ unsigned long long kbal[kMaxReverseL], kunb[kMaxReverseL];
   // wave index, known to the compiler as wavefront-uniform
@@ -334,11 +334,11 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   uint32_t* C = cnt[wave];
   for (int i = threadIdx.x; i < kMaxReverseL; i += kPVReverseThreads) kbal[i] = kunb[i] = 0;
   for (int i = lane; i < kPVReverseWords; i += kWave) C[i] = 0;
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
   wave_sync_lds();
-  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  const Marks<uint32_t> mk{mtab[wave], mflag[wave]};
   Sums sums;
   uint32_t graph = kNoGraph;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVReverseWaves;
@@ -422,8 +422,8 @@ template <bool kEdge>
 __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
   __shared__ uint32_t keys[kPVSmallWaves][kPVSmallSlots];
   __shared__ uint32_t vals[kPVSmallWaves][kPVSmallSlots];
-  __shared__ uint32_t mbase[kPVSmallWaves][kGather];
-  __shared__ uint32_t mtag[kPVSmallWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVSmallWaves][kGather];
+  __shared__ uint32_t mflag[kPVSmallWaves][kGather];
   __shared__ unsigned long long cb[kPVSmallWaves][kWave], cu[kPVSmallWaves][kWave];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -434,11 +434,11 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
     K[i] = kEmpty;
     V[i] = 0;
   }
-  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
   wave_sync_lds();
-  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  const Marks<uint32_t> mk{mtab[wave], mflag[wave]};
   Sums sums;
   uint32_t graph = kNoGraph;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVSmallWaves;
@@ -539,8 +539,8 @@ template <bool kEdge>
 __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
   __shared__ uint32_t keys[kPVHashSlots];
   __shared__ unsigned long long vals[kPVHashSlots];
-  __shared__ uint32_t mbase[kPVHashWaves][kGather];
-  __shared__ uint32_t mtag[kPVHashWaves][kGather];
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVHashWaves][kGather];
+  __shared__ uint32_t mflag[kPVHashWaves][kGather];
   __shared__ unsigned long long cb[kPVHashWaves][kWave], cu[kPVHashWaves][kWave];
   __shared__ int32_t item_sh;
   __shared__ uint32_t work_sh;
@@ -551,10 +551,10 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
     keys[i] = kEmpty;
     vals[i] = 0;
   }
-  for (int i = tid; i < kPVHashWaves * static_cast<int>(kGather); i += kPVHashThreads) (&mtag[0][0])[i] = 0;
+  for (int i = tid; i < kPVHashWaves * static_cast<int>(kGather); i += kPVHashThreads) (&mflag[0][0])[i] = 0;
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
-  const Marks<uint32_t> mk{mbase[wave], mtag[wave]};
+  const Marks<uint32_t> mk{mtab[wave], mflag[wave]};
   Sums sums;
   uint32_t graph = kNoGraph;
   for (;;) {

@@ -124,21 +124,33 @@ __device__ __forceinline__ uint32_t bpermute(uint32_t v, uint32_t src) {
 // Short runs of a batch are laid end to end: flat position t (0 <= t <
 // total) is entry base + t of its run's row, with base = start - excl of
 // the run.  A staging round covers positions [done, done + kGather), dealt
-// to lanes as t = done + 64 u + lane (coalesced loads).  Every run that
-// starts in the round, or continues into it, writes its base and its tag
-// (with bit 31 set as a presence flag) at its first position of the round
-// into the wavefront's marks buffers; a position's run is then the last
-// mark at or before it: a ballot per block of 64 positions, carried across
-// blocks.  Each lane clears the presence words it read, so they are all
-// zero between rounds.
+// to lanes as t = done + 64 u + lane (coalesced loads), and finds every
+// position's run in one of two forms (both keep their per-position LDS
+// words zero between rounds: each lane clears what it read):
+//  - marks: every run that starts in the round, or continues into it,
+//    writes its base and its tag (with the top bit set as a presence flag)
+//    at its first position of the round; a position's run is the last mark
+//    at or before it (a ballot per block of 64 positions, the highest set
+//    bit, two ds_bpermute, carried across blocks);
+//  - table: the batch's non-empty short runs are listed in lane order in a
+//    run table (base, tag) once per batch, every run that starts in the
+//    round flags its first position, and the run of position t is entry
+//    r(t) = (flags at or before t) - 1: the flags of earlier blocks
+//    (carried) plus a ballot and a masked bit count in its own block.
+//    Blocks wholly past the batch's last position are skipped.  Fewer
+//    instructions per position, one more dependent LDS read: it pays where
+//    the walk is bound by instruction issue.
 constexpr int kStageU = kGather / kWave;
 
-// TagT holds a run's tag plus the presence bit (its top bit): 8 bits for
-// plain runs (tag = g), 32 bits for small-item groups.
+// The marks buffers of a wavefront: kGather words (the marks' bases, or
+// the run table) and kGather TagT entries (the marks' tags with the
+// presence bit, or the start flags).  TagT holds a run's tag plus the
+// presence bit: 8 bits for plain runs (tag = g), 32 bits for small-item
+// groups.
 template <class TagT>
 struct Marks {
-  uint32_t* base;  // kGather words
-  TagT* tag;       // kGather entries, zero when no run starts there
+  uint32_t* base;  // kGather words, 8-byte aligned
+  TagT* tag;       // kGather entries, zero between rounds
   static constexpr uint32_t kBit = 1u << (8 * sizeof(TagT) - 1);
 };
 
@@ -182,6 +194,51 @@ __device__ __forceinline__ void stage_round(Staged& s, M mk, uint32_t excl, uint
   }
 }
 
+// Count of set bits of m in the lanes below this one.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+// Table form: list the batch's non-empty short runs (before its first
+// staging round, whose fence orders these writes before its reads).
+template <class M>
+__device__ __forceinline__ void fill_table(M mk, uint32_t slen, uint32_t base, uint32_t tag) {
+  wave_sync_lds();  // the previous batch's rounds have read the table
+  const uint64_t ne = __ballot(slen != 0);
+  if (slen != 0) {
+    const uint32_t k = mbcnt(ne);
+    *reinterpret_cast<u32x2*>(mk.base + 2 * k) = u32x2{base, tag};
+  }
+}
+
+template <class M>
+__device__ __forceinline__ void stage_round_table(Staged& s, M mk, uint32_t excl, uint32_t slen, uint32_t total,
+                                                  uint32_t done, uint32_t& carry,
+                                                  const uint32_t* __restrict__ adj) {
+  const int lane = lane_id();
+  wave_sync_lds();
+  if (slen != 0 && excl >= done && excl < done + kGather) mk.tag[excl - done] = 1;
+  wave_sync_lds();
+#pragma unroll
+  for (int u = 0; u < kStageU; ++u) {
+    s.valid[u] = false;
+    if (done + static_cast<uint32_t>(u * kWave) < total) {
+      const uint32_t f = static_cast<uint32_t>(mk.tag[u * kWave + lane]);
+      mk.tag[u * kWave + lane] = 0;
+      const uint64_t fm = __ballot(f != 0);
+      const uint32_t r = carry + mbcnt(fm) + f - 1u;  // f is 0 or 1
+      carry += static_cast<uint32_t>(__popcll(fm));
+      const u32x2 bt = *reinterpret_cast<const u32x2*>(mk.base + 2 * r);
+      const uint32_t t = done + static_cast<uint32_t>(u * kWave + lane);
+      s.valid[u] = t < total;
+      s.tag[u] = bt.y;
+      s.pos[u] = bt.x + t;
+      s.e[u] = as_global(adj)[s.valid[u] ? bt.x + t : 0u];
+    }
+  }
+}
+
 // Hand one wedge slot to a walk functor: f.add(entry, tag, valid, pos) when
 // the functor takes the entry's position in the CSR array (per-edge
 // credits), else f.add(entry, tag, valid).
@@ -211,7 +268,11 @@ __device__ __forceinline__ void walk_add(F& f, uint32_t e, uint32_t tag, bool va
 //  - Shorter runs are staged (stage_round) so that every lane holds wedges;
 //    the loads of the first round are issued before the long stream and the
 //    next round's loads before the current round is tallied.
-template <int U, bool kLaneMajor = false, class M, class F>
+// kCompact selects the issue-lean form for walks bound by instruction
+// issue: staging by run table, and chunks that lie wholly inside their run
+// tallied without the slot test.  Elsewhere (walks bound by latency, or
+// functors whose code is large) the plain form measured faster.
+template <int U, bool kLaneMajor = false, bool kCompact = false, class M, class F>
 __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, M marks,
                                           uint32_t long_len, F&& f) {
   const int lane = lane_id();
@@ -226,7 +287,15 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
   const uint32_t base = start - excl;
   const uint32_t lstart = start + head, lend = start + len;
   Staged cur;
-  if (total) stage_round(cur, marks, excl, slen, base, tag, total, 0, adj);
+  uint32_t carry = 0;  // table form: flags of the staged blocks before the current one
+  if (total) {
+    if (kCompact) {
+      fill_table(marks, slen, base, tag);
+      stage_round_table(cur, marks, excl, slen, total, 0, carry, adj);
+    } else {
+      stage_round(cur, marks, excl, slen, base, tag, total, 0, adj);
+    }
+  }
   uint32_t cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
   // offset of a lane's word q in a chunk (loop-invariant)
@@ -276,40 +345,52 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
     for (int u = 0; u < U; ++u) {
       if (u < nv) {
         const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+        if (kCompact && vrem[u] >= kChunk) {  // the whole chunk lies in the run (uniform)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) walk_add(f, e4[q], vg[u], koff[q] < vrem[u], vpos[u] + koff[q], 0);
+          for (int q = 0; q < 4; ++q) walk_add(f, e4[q], vg[u], true, vpos[u] + koff[q], 0);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) walk_add(f, e4[q], vg[u], koff[q] < vrem[u], vpos[u] + koff[q], 0);
+        }
       }
     }
   }
   for (uint32_t done = 0; done < total; done += kGather) {
     const bool more = done + kGather < total;
     Staged nxt;
-    if (more) stage_round(nxt, marks, excl, slen, base, tag, total, done + kGather, adj);
+    if (more) {
+      if (kCompact)
+        stage_round_table(nxt, marks, excl, slen, total, done + kGather, carry, adj);
+      else
+        stage_round(nxt, marks, excl, slen, base, tag, total, done + kGather, adj);
+    }
 #pragma unroll
-    for (int u = 0; u < kStageU; ++u) walk_add(f, cur.e[u], cur.tag[u], cur.valid[u], cur.pos[u], 0);
+    for (int u = 0; u < kStageU; ++u)
+      if (!kCompact || done + static_cast<uint32_t>(u * kWave) < total)
+        walk_add(f, cur.e[u], cur.tag[u], cur.valid[u], cur.pos[u], 0);
     if (!more) break;
     cur = nxt;
   }
 }
 
-template <int U, bool kTagged = false, class M, class F>
+template <int U, bool kTagged = false, bool kCompact = false, class M, class F>
 __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
                                            const uint32_t* __restrict__ adj, M marks,
                                            uint32_t long_len, F&& f) {
-  walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
+  walk_regs<U, false, kCompact>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
 }
 
 // Walk every run of an item with one wavefront; the first batch of 64 runs
 // was loaded beforehand (first).
-template <int U, bool kTagged = false, class M, class F>
+template <int U, bool kTagged = false, bool kCompact = false, class M, class F>
 __device__ __forceinline__ void walk_item(const Item& it, SegReg first, const Segment* __restrict__ segs,
                                           const uint32_t* __restrict__ adj, M marks,
                                           uint32_t long_len, F&& f) {
   const uint32_t seg_end = it.seg_begin + it.seg_count;
-  walk_regs<U>(first, adj, marks, long_len, f);
+  walk_regs<U, false, kCompact>(first, adj, marks, long_len, f);
   for (uint32_t k0 = it.seg_begin + kWave; k0 < seg_end; k0 += kWave) {
     const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-    walk_regs<U>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
+    walk_regs<U, false, kCompact>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
   }
 }
 
