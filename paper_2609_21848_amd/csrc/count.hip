@@ -82,11 +82,12 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t* __restrict__ adj = sc.other_adj;
     const uint32_t seg_end = it.seg_begin + it.seg_count;
-    for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kDirectThreads) {
-      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
-      walk_batch<8>(sc.segs, k0, k1, adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
-                    DirectTallyBF<kDirectKeys>{cnt, cnt + kDirectKeys + tid});
-    }
+    // the wavefronts take the item's segments interleaved (wavefront w the
+    // segments w, w + 16, ...), 64 per batch, so that every wavefront gets
+    // a similar mix of long and short runs
+    for (uint32_t k0 = it.seg_begin + wave; k0 < seg_end; k0 += kDirectThreads)
+      walk_batch<8>(sc.segs, k0, seg_end, adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
+                    DirectTallyBF<kDirectKeys>{cnt, cnt + kDirectKeys + tid}, kDirectWaves);
     __syncthreads();
     if (it.flags & kItemMultiPart) {
       // write the part's counters for the whole key window (zeros included)

@@ -96,9 +96,11 @@ struct SegReg {
   uint32_t start, len, tag;
 };
 
+// Segment k0 + stride * lane of [k0, k1) for each lane.
 template <bool kTagged>
-__device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1) {
-  const uint32_t k = k0 + lane_id();
+__device__ __forceinline__ SegReg load_seg(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
+                                           uint32_t stride = 1) {
+  const uint32_t k = k0 + stride * static_cast<uint32_t>(lane_id());
   SegReg r{0, 0, 0};
   if (k < k1) {
     const u32x2 w = *(const global_t<u32x2>*)(segs + k);
@@ -376,8 +378,8 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
 template <int U, bool kTagged = false, bool kCompact = false, class M, class F>
 __device__ __forceinline__ void walk_batch(const Segment* __restrict__ segs, uint32_t k0, uint32_t k1,
                                            const uint32_t* __restrict__ adj, M marks,
-                                           uint32_t long_len, F&& f) {
-  walk_regs<U, false, kCompact>(load_seg<kTagged>(segs, k0, k1), adj, marks, long_len, f);
+                                           uint32_t long_len, F&& f, uint32_t stride = 1) {
+  walk_regs<U, false, kCompact>(load_seg<kTagged>(segs, k0, k1, stride), adj, marks, long_len, f);
 }
 
 // Walk every run of an item with one wavefront; the first batch of 64 runs
