@@ -43,8 +43,8 @@
 namespace dbbc {
 namespace dev {
 
-// The runs k0 .. k1 - 1 of a batch with per-vertex tags, and each lane's mid
-// (and, with kEdge, the position of its first edge).
+// The runs k0 + stride * lane (< k1) of a batch with per-vertex tags, and
+// each lane's mid (and, with kEdge, the position of its first edge).
 struct RunEnds {
   uint32_t mid = 0, edge = 0, wide = 0;
 };
@@ -53,16 +53,17 @@ template <bool kTagged, bool kEdge>
 __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
                                               const uint32_t* __restrict__ mids,
                                               const uint32_t* __restrict__ edges, uint32_t k0, uint32_t k1,
-                                              RunEnds& re) {
-  SegReg r = load_seg<kTagged>(segs, k0, k1);
+                                              RunEnds& re, uint32_t stride = 1) {
+  SegReg r = load_seg<kTagged>(segs, k0, k1, stride);
   const uint32_t lane = static_cast<uint32_t>(lane_id());
   const uint32_t g = r.tag & 1u;
   r.tag = kTagged ? (((r.tag >> 1) << 7) | (lane << 1) | g) : ((lane << 1) | g);
-  const bool in = k0 + lane < k1;
-  const uint32_t m = in ? as_global(mids)[k0 + lane] : 0u;
+  const uint32_t k = k0 + stride * lane;
+  const bool in = k < k1;
+  const uint32_t m = in ? as_global(mids)[k] : 0u;
   re.mid = m & ~kMidWide;
   if (kEdge) {
-    re.edge = in ? as_global(edges)[k0 + lane] : 0u;
+    re.edge = in ? as_global(edges)[k] : 0u;
     re.wide = m & kMidWide;
     r.tag |= re.wide;  // the run's wedges carry the flag to the credit walk
   }
@@ -230,11 +231,11 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     const uint32_t lo = static_cast<uint32_t>(it.key_lo), hi = static_cast<uint32_t>(it.key_hi);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     const bool packed = (it.flags & kItemPacked) != 0;
-    // tally
-    for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
-      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+    // tally (the wavefronts take the item's segments interleaved, so that
+    // every wavefront gets a similar mix of long and short runs)
+    for (uint32_t k0 = it.seg_begin + wave; k0 < seg_end; k0 += kPVDirectThreads) {
       RunEnds re;
-      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
+      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, seg_end, re, kPVDirectWaves);
       if (packed)
         walk_regs<4>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
                        const uint32_t key = e >> 1;
@@ -248,10 +249,9 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     }
     __syncthreads();
     // credit the mids
-    for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kPVDirectThreads) {
-      const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
+    for (uint32_t k0 = it.seg_begin + wave; k0 < seg_end; k0 += kPVDirectThreads) {
       RunEnds re;
-      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
+      const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, seg_end, re, kPVDirectWaves);
       auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;
