@@ -230,8 +230,8 @@ constexpr int kSmallWaves = kSmallThreads / kWave;
 constexpr int kSmallSlots = 2 * kSmallGroupWork;
 
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
-  __shared__ uint32_t keys[kSmallWaves][kSmallSlots];
-  __shared__ uint32_t vals[kSmallWaves][kSmallSlots];
+  __shared__ __attribute__((aligned(16))) uint32_t keys[kSmallWaves][kSmallSlots];
+  __shared__ __attribute__((aligned(16))) uint32_t vals[kSmallWaves][kSmallSlots];
   __shared__ __attribute__((aligned(16))) uint32_t marks[kSmallWaves][2][kGather];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -266,16 +266,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     }
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
     const uint32_t kb = static_cast<uint32_t>(sc.key_bits);
-    // table size: a power of two >= 2 * work, at least 64
+    // table size: a power of two >= 2 * work, at least 64; the home slot is
+    // the top log2(size) bits of the key times 2^32 / golden ratio
+    // (multiplicative hashing: one multiply)
     uint32_t size = 64;
     while (size < 2 * it.work) size <<= 1;
     const uint32_t mask = size - 1;
+    const uint32_t hshift = 32u - static_cast<uint32_t>(__builtin_ctz(size));
     walk_item<4, true>(it, first, sc.small_segs, sc.other_adj, Marks<uint32_t>{marks[wave][0], marks[wave][1]},
                        a.long_len,
                        hash_tally([&](uint32_t e, uint32_t tag) {
                          const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
                          const uint32_t inc = wedge_inc(e, tag);
-                         uint32_t h = mix32(key) & mask;
+                         uint32_t h = (key * 0x9E3779B1u) >> hshift;
                          for (uint32_t probe = 0;; ++probe) {
                            if (probe > mask) {  // full table: cannot happen at load <= 1/2
                              atomicOr(a.err, kErrHashFull);
@@ -300,14 +303,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     SqSums ss;
     const bool hub = (it.flags & kItemHubPairs) != 0;
     const uint32_t kmask = (1u << kb) - 1u;
-    for (uint32_t h = lane; h < size; h += kWave) {
-      const uint32_t key = K[h];
-      if (key != kEmpty) {
-        const uint32_t c = Vv[h];
-        const uint32_t p = c & 0xffffu, q = c >> 16;
-        K[h] = kEmpty;
-        Vv[h] = 0;
-        if (hub && static_cast<int32_t>(key & kmask) < sc.T)  // singleton group
+    // 16-byte LDS accesses, 4 slots per lane; an empty slot's count is 0,
+    // which adds nothing to the sums
+    for (uint32_t h = 4 * lane; h < size; h += 4 * kWave) {
+      const uint4 k4 = *reinterpret_cast<const uint4*>(&K[h]);
+      const uint4 c4 = *reinterpret_cast<const uint4*>(&Vv[h]);
+      *reinterpret_cast<uint4*>(&K[h]) = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+      *reinterpret_cast<uint4*>(&Vv[h]) = make_uint4(0, 0, 0, 0);
+      const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w}, cc[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const uint32_t key = kk[q4], p = cc[q4] & 0xffffu, q = cc[q4] >> 16;
+        if (hub && key != kEmpty && static_cast<int32_t>(key & kmask) < sc.T)  // singleton group
           hub_partial(sc, it.owner, key & kmask, p, q);
         else
           ss.add(p, q);
