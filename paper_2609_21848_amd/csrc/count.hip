@@ -134,11 +134,15 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
 // Reverse items: one wavefront per item, a private LDS direct array over the
 // reverse window [0, R) (R <= kMaxReverseL).  Counters are 8-bit
 // (symmetric | asymmetric << 8) in 16-bit halves, two keys per 32-bit word:
-// an item (or part) has at most kReverseMaxSegs segments, so no byte
-// overflows.  Items are dealt to wavefronts in a fixed stride; the next
+// an item (or part) has at most kReverseCountMaxSegs segments, so no byte
+// exceeds 127.  Items are dealt to wavefronts in a fixed stride; the next
 // item's first segments and the descriptor of the one after are loaded while
 // the current item is walked.  The sweep reads the whole window with 16-byte
 // LDS loads.
+typedef int v4i __attribute__((ext_vector_type(4)));
+// sweep products an accumulator may hold before its diagonal is moved out:
+// 2000 * 64 * 127^2 < 2^31
+constexpr int32_t kAccItersMax = 2000 - 2 * kMaxReverseL / (4 * kWave);
 constexpr int kReverseThreads = 1024;
 constexpr int kReverseWaves = kReverseThreads / kWave;
 constexpr int kReverseWords = kMaxReverseL / 2;
@@ -157,6 +161,25 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
   wave_sync_lds();
   SqTotals tot;
+  // matrix-core accumulators of the sweeps (see below) and the number of
+  // products they hold; the diagonal of a 16 x 16 result is held by lanes
+  // 20 g + q (g, q < 4) in register q
+  v4i acc_sq = {0, 0, 0, 0}, acc_pn = {0, 0, 0, 0};
+  int32_t acc_iters = 0;
+  auto flush_acc = [&]() {
+    const int q = (lane & 15) - 4 * (lane >> 4);
+    int32_t dsq = 0, dpn = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      dsq = q == r ? acc_sq[r] : dsq;
+      dpn = q == r ? acc_pn[r] : dpn;
+    }
+    tot.sq += static_cast<uint32_t>(dsq);
+    tot.pn2 += static_cast<uint32_t>(dpn);
+    acc_sq = v4i{0, 0, 0, 0};
+    acc_pn = v4i{0, 0, 0, 0};
+    acc_iters = 0;
+  };
   const int32_t n = a.n_items;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kReverseWaves;
   int32_t i = static_cast<int32_t>(blockIdx.x) * kReverseWaves + wave;
@@ -173,7 +196,10 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     const SegReg first = cfirst;
     const int32_t j = i + stride, j2 = j + stride;
     if (it.graph != graph) {
-      if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+      if (graph != kNoGraph) {
+        flush_acc();
+        tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+      }
       tot = SqTotals{};
       graph = it.graph;
     }
@@ -195,28 +221,43 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
         if (2 * wd + 1 < it.key_hi) dst[2 * wd + 1] = ((c2 >> 16) & 0xffu) | ((c2 >> 24) << 16);
       }
     } else {
-      // p, n <= 255 and at most 2 * kReverseWords / 64 = 64 keys per lane;
-      // every key of the item lies in the window, so its swept wedges are
-      // the item's wedges (added once, by lane 0).  No test for all-zero
-      // words: a wavefront would skip only if all its 64 lanes saw zeros.
-      SqSums ss;
-      for (int32_t wd = 4 * lane; wd < w_hi; wd += 4 * kWave) {
-        const uint4 c4 = *reinterpret_cast<uint4*>(&C[wd]);
+      // The item's sums over its keys, Σ p^2 + n^2 and 2 Σ p n, as traces of
+      // signed 8-bit matrix products (p, n <= kReverseCountMaxSegs < 128):
+      // 16 bytes per lane form a 16 x 64 operand A, and with the same
+      // register as the other operand the product is A A^T, whose diagonal
+      // holds each row's sum of squares; with the bytes of every 16-bit half
+      // swapped (p <-> n) it holds 2 Σ p n.  The loop is uniform (the matrix
+      // core needs every lane); words past the item's keys are zero.  Every
+      // key of the item lies in the window, so its swept wedges are the
+      // item's wedges (added once, by lane 0).
+      const int32_t n_it = (w_hi + 4 * kWave - 1) / (4 * kWave);
+      for (int32_t k = 0; k < n_it; ++k) {
+        const int32_t wd = k * 4 * kWave + 4 * lane;
+        const v4i c = *reinterpret_cast<const v4i*>(&C[wd]);
         *reinterpret_cast<uint4*>(&C[wd]) = make_uint4(0, 0, 0, 0);
-        ss.add_word(c4.x);
-        ss.add_word(c4.y);
-        ss.add_word(c4.z);
-        ss.add_word(c4.w);
+        v4i cs;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          cs[q] = static_cast<int>(__builtin_amdgcn_perm(static_cast<uint32_t>(c[q]), static_cast<uint32_t>(c[q]),
+                                                         0x02030001u));
+        acc_sq = __builtin_amdgcn_mfma_i32_16x16x64_i8(c, c, acc_sq, 0, 0, 0);
+        acc_pn = __builtin_amdgcn_mfma_i32_16x16x64_i8(c, cs, acc_pn, 0, 0, 0);
       }
-      ss.w = lane == 0 ? it.work : 0u;
-      tot.add(ss);
+      acc_iters += n_it;
+      if (lane == 0) tot.w += it.work;
+      // every product adds at most 64 * 127^2 to an entry: move the
+      // diagonals out before an int32 entry could overflow
+      if (acc_iters > kAccItersMax) flush_acc();
     }
     wave_sync_lds();
     cur = nxt;
     cfirst = nfirst;
     nxt = nxt2;
   }
-  if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+  if (graph != kNoGraph) {
+    flush_acc();
+    tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+  }
 }
 
 // ---------------------------------------------------------------------------

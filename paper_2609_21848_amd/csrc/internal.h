@@ -68,6 +68,9 @@ constexpr uint32_t kSmallMaxItems = 65535;
 // Reverse items keep two 8-bit counters per key (symmetric, asymmetric), so
 // a reverse item (or item part) has at most this many segments.
 constexpr uint32_t kReverseMaxSegs = 255;
+// ... and at most this many in a count plan, whose reverse kernel sums the
+// counters' squares and products with signed 8-bit matrix products.
+constexpr uint32_t kReverseCountMaxSegs = 127;
 
 // Flags of an item.
 enum : uint32_t {

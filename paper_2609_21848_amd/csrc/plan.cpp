@@ -456,16 +456,18 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       if (kind == kReverseTail && pv && nseg > kReverseMaxSegs) {
         P.big_direct.push_back(it);  // per-vertex counts: one direct item
       } else if (kind == kReverseTail) {
-        // parts of at most kReverseMaxSegs segments (8-bit counters)
-        if (nseg <= kReverseMaxSegs) {
+        // parts of at most kReverseMaxSegs segments (8-bit counters; signed
+        // 8-bit in a count plan)
+        const uint32_t max_segs = pv ? kReverseMaxSegs : kReverseCountMaxSegs;
+        if (nseg <= max_segs) {
           P.reverse_items.push_back(it);
           return;
         }
         const int32_t first_slot = P.acc_slots;
-        for (uint32_t k = 0; k < nseg; k += kReverseMaxSegs) {
+        for (uint32_t k = 0; k < nseg; k += max_segs) {
           Item part = it;
           part.seg_begin = seg_begin + k;
-          part.seg_count = std::min(kReverseMaxSegs, nseg - k);
+          part.seg_count = std::min(max_segs, nseg - k);
           part.flags |= kItemMultiPart;
           part.acc_slot = P.acc_slots++;
           int64_t pw = 0;

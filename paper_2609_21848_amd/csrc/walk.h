@@ -531,34 +531,25 @@ __device__ __forceinline__ void emit(const Item& it, uint32_t key, uint32_t p, u
 
 // Per-key sums of squares: with W the wedges of the swept keys (sum of
 // p + n), sum C(p,2) + C(n,2) = (sum p^2 + n^2 - W) / 2 and the unbalanced
-// sum is sum p * n.  32-bit per-item accumulators (24-bit multiply-adds or
-// byte dot products): the callers bound p and n so that an item's sums stay
-// below 2^32.
+// sum is sum p * n.  32-bit per-item accumulators (24-bit multiply-adds):
+// the callers bound p and n so that an item's sums stay below 2^32.
 struct SqSums {
-  uint32_t sq = 0, pn = 0, pn2 = 0, w = 0;
+  uint32_t sq = 0, pn = 0, w = 0;
   __device__ __forceinline__ void add(uint32_t p, uint32_t n) {
     sq += __umul24(p, p);
     sq += __umul24(n, n);
     pn += __umul24(p, n);
     w += p + n;
   }
-  // Two 8|8-bit keys (bytes p0, n0, p1, n1): p0^2 + n0^2 + p1^2 + n1^2 is
-  // one byte dot product of the word with itself, and 2 (p0 n0 + p1 n1) the
-  // dot product with its bytes swapped within each 16-bit half.  The word's
-  // wedges (p0 + n0 + p1 + n1) are not added here: the caller knows them.
-  __device__ __forceinline__ void add_word(uint32_t c2) {
-    sq = __builtin_amdgcn_udot4(c2, c2, sq, false);
-    pn2 = __builtin_amdgcn_udot4(c2, __builtin_amdgcn_perm(c2, c2, 0x02030001u), pn2, false);
-  }
 };
 
-// Running per-lane totals of SqSums, flushed once per wavefront.
+// Running per-lane totals of SqSums (and of twice a sum p * n, pn2, where
+// it comes as such), flushed once per wavefront.
 struct SqTotals {
   uint64_t sq = 0, pn = 0, pn2 = 0, w = 0;
   __device__ __forceinline__ void add(const SqSums& s) {
     sq += s.sq;
     pn += s.pn;
-    pn2 += s.pn2;
     w += s.w;
   }
   __device__ __forceinline__ void flush(unsigned long long* res) const {

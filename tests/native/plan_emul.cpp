@@ -120,7 +120,7 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
     }
   }
   for (const Item& it : plan.reverse_items)
-    if ((rc = run(it, kReverseMaxSegs))) return rc;
+    if ((rc = run(it, kReverseCountMaxSegs))) return rc;
   for (const Reduce& r : plan.reduces) {
     for (int32_t key = r.key_lo; key < r.key_hi; ++key) {
       int64_t P = 0, N = 0;
