@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     // segments w, w + 16, ...), 64 per batch, so that every wavefront gets
     // a similar mix of long and short runs
     for (uint32_t k0 = it.seg_begin + wave; k0 < seg_end; k0 += kDirectThreads)
-      walk_batch<8>(sc.segs, k0, seg_end, adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
+      walk_batch<8, false, true>(sc.segs, k0, seg_end, adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
                     DirectTallyBF<kDirectKeys>{cnt, cnt + kDirectKeys + tid}, kDirectWaves);
     __syncthreads();
     if (it.flags & kItemMultiPart) {

@@ -270,10 +270,11 @@ __device__ __forceinline__ void walk_add(F& f, uint32_t e, uint32_t tag, bool va
 //  - Shorter runs are staged (stage_round) so that every lane holds wedges;
 //    the loads of the first round are issued before the long stream and the
 //    next round's loads before the current round is tallied.
-// kCompact selects the issue-lean form for walks bound by instruction
-// issue: staging by run table, and chunks that lie wholly inside their run
-// tallied without the slot test.  Elsewhere (walks bound by latency, or
-// functors whose code is large) the plain form measured faster.
+// kCompact selects the issue-lean form: staging by run table, and chunks
+// that lie wholly inside their run tallied without the slot test.  The
+// counting kernels with direct LDS counters use it; the hash-table and
+// per-vertex walks (bound by latency, or with functors whose code is large)
+// measured faster in the plain form.
 template <int U, bool kLaneMajor = false, bool kCompact = false, class M, class F>
 __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict__ adj, M marks,
                                           uint32_t long_len, F&& f) {
