@@ -32,6 +32,7 @@ namespace dev {
 constexpr int kDirectThreads = 1024;
 constexpr int kDirectWaves = kDirectThreads / kWave;
 constexpr int kDirectKeys = 32768;
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
   __shared__ uint32_t cnt[kDirectKeys + kDirectThreads];  // counters, then one dummy per thread
@@ -99,28 +100,41 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
     } else {
       // Sums of squares (see SqSums): every wedge of a single-part item lies
       // in its window, so thread 0 takes the item's wedges off once; the
-      // wedges of pairs handed to the dense path are added back.  p, n <
-      // 2^16, so squares and products are exact 24-bit multiplies.
+      // wedges of pairs handed to the dense path are added back.  A key's
+      // p + n is at most the item's runs (< 2^16), so p^2 + n^2 <= (p + n)^2
+      // and 2 p n are exact in 32 bits: one 16-bit dot product of the
+      // counter word with itself, and one with its halves swapped.
       if (tid == 0) sq2 -= static_cast<int64_t>(it.work);
       const bool hub = (it.flags & kItemHubPairs) != 0;
       const uint32_t lo = static_cast<uint32_t>(it.key_lo) & ~3u;
       const uint32_t hi = static_cast<uint32_t>(it.key_hi);
+      const uint32_t hub_hi = hub ? static_cast<uint32_t>(sc.T) : 0u;  // keys below: dense-path pairs
       for (uint32_t key = lo + 4 * tid; key < hi; key += 4 * kDirectThreads) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&cnt[key]);
         if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
         *reinterpret_cast<uint4*>(&cnt[key]) = make_uint4(0, 0, 0, 0);
         const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+        if (key < hub_hi) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t p = cv[j] & 0xffffu, n = cv[j] >> 16;
-          if (hub && static_cast<int32_t>(key + j) < sc.T) {
-            if (cv[j]) {
-              hub_partial(sc, it.owner, key + j, p, n);
-              sq2 += p + n;
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t p = cv[j] & 0xffffu, n = cv[j] >> 16;
+            if (key + j < hub_hi) {
+              if (cv[j]) {
+                hub_partial(sc, it.owner, key + j, p, n);
+                sq2 += p + n;
+              }
+            } else {
+              sq2 += static_cast<int64_t>(__umul24(p, p)) + static_cast<int64_t>(__umul24(n, n));
+              pnx += __umul24(p, n);
             }
-          } else {
-            sq2 += static_cast<int64_t>(__umul24(p, p)) + static_cast<int64_t>(__umul24(n, n));
-            pnx += __umul24(p, n);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const u16x2 h = __builtin_bit_cast(u16x2, cv[j]);
+            const u16x2 r = __builtin_bit_cast(u16x2, __builtin_amdgcn_alignbit(cv[j], cv[j], 16));
+            sq2 += __builtin_amdgcn_udot2(h, h, 0u, false);
+            pnx += __builtin_amdgcn_udot2(h, r, 0u, false) >> 1;
           }
         }
       }
