@@ -132,11 +132,12 @@ struct KernelRec {
   float ms = 0.f;
 };
 
-// One dense hub launch (one side of one graph).
+// One dense hub launch (both sides of one graph).
 struct HubLaunch {
-  dbbc::HubArgs a;
+  dbbc::HubArgs a[2];
+  int n = 0;
   int64_t tiles = 0, macs = 0;
-  const char* name = "";
+  const char* name = "hub";
 };
 
 // Everything one count (of one graph or of a batch) launches.
@@ -267,7 +268,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
   }
   for (const HubLaunch& h : L.hubs) {
     RC_TRY(tm.begin(st, h.name, 0, 0, h.tiles, h.macs));
-    HIP_TRY(dbbc::launch_hub(h.a, st));
+    HIP_TRY(dbbc::launch_hub(h.a, h.n, st));
     RC_TRY(tm.end());
   }
   return DBBC_OK;
@@ -276,24 +277,25 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
 // Dense hub launches of a graph's plan, results into res (its slot).
 void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L) {
   const dbbc::HostPlan& hp = d.host;
+  HubLaunch h;
   for (int s = 0; s < 2; ++s) {
     if (hp.T[s] == 0) continue;
     // two int32 T x T planes, cleared as T x T 64-bit words
     L.zero.push_back({d.hub_pairs[s].as<unsigned long long>(), static_cast<size_t>(hp.T[s]) * hp.T[s]});
-    HubLaunch h;
-    h.a.Bm = d.hub_Bm[s].as<int8_t>();
-    h.a.B = d.hub_B[s].as<int8_t>();
-    h.a.hub_xy = d.hub_pairs[s].as<int32_t>();
-    h.a.res = res;
-    h.a.T = hp.T[s];
-    h.a.K = d.hub_K[s];
+    dbbc::HubArgs& a = h.a[h.n++];
+    a.Bm = d.hub_Bm[s].as<int8_t>();
+    a.B = d.hub_B[s].as<int8_t>();
+    a.hub_xy = d.hub_pairs[s].as<int32_t>();
+    a.res = res;
+    a.T = hp.T[s];
+    a.K = d.hub_K[s];
     // two contractions over K for every tile of the upper triangle
-    const int64_t nt = h.a.T / 128;
-    h.tiles = nt * (nt + 1) / 2;
-    h.macs = 2 * h.tiles * 128 * 128 * static_cast<int64_t>(h.a.K);
-    h.name = s == 0 ? "hub_u" : "hub_v";
-    L.hubs.push_back(h);
+    const int64_t nt = a.T / 128;
+    const int64_t tiles = nt * (nt + 1) / 2;
+    h.tiles += tiles;
+    h.macs += 2 * tiles * 128 * 128 * static_cast<int64_t>(a.K);
   }
+  if (h.n > 0) L.hubs.push_back(h);
 }
 
 }  // namespace

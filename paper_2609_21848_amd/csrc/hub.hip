@@ -45,11 +45,20 @@ __device__ __forceinline__ int hub_slot(int row, int c) { return row * kHubKStep
 // stages ahead of the matrix work: each wavefront waits only for its own
 // loads of the stage it is about to read, then the workgroup barrier makes
 // every wavefront's part visible.
-__global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
+// Both sides of a graph share one launch: the first tiles0 workgroups work
+// on s[0], the rest on s[1] (wavefront-uniform choice).
+struct HubPair {
+  HubArgs s[2];
+  int32_t tiles0;
+};
+
+__global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubPair hp) {
   __shared__ __attribute__((aligned(16))) int8_t sm[kHubStages][2][kHubStage];
+  const bool second = static_cast<int32_t>(blockIdx.x) >= hp.tiles0;
+  const HubArgs a = second ? hp.s[1] : hp.s[0];
   // upper-triangular tile (ti <= tj) from the linear block index
   const int nt = a.T / kHubTile;
-  int t = blockIdx.x, ti = 0;
+  int t = static_cast<int>(blockIdx.x) - (second ? hp.tiles0 : 0), ti = 0;
   while (t >= nt - ti) {
     t -= nt - ti;
     ++ti;
@@ -201,12 +210,21 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubArgs a) {
 
 }  // namespace dev
 
-hipError_t launch_hub(const HubArgs& a, hipStream_t st) {
-  if (a.T <= 0) return hipSuccess;
-  if (a.T % dev::kHubTile != 0 || a.K % dev::kHubKStep != 0) return hipErrorInvalidValue;
-  const int nt = a.T / dev::kHubTile;
-  const int tiles = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(dev::k_hub, dim3(tiles), dim3(dev::kHubThreads), 0, st, a);
+hipError_t launch_hub(const HubArgs* sides, int n, hipStream_t st) {
+  dev::HubPair hp{};
+  int32_t tiles[2] = {0, 0};
+  int k = 0;
+  for (int i = 0; i < n; ++i) {
+    const HubArgs& a = sides[i];
+    if (a.T <= 0) continue;
+    if (a.T % dev::kHubTile != 0 || a.K % dev::kHubKStep != 0) return hipErrorInvalidValue;
+    const int nt = a.T / dev::kHubTile;
+    hp.s[k] = a;
+    tiles[k++] = nt * (nt + 1) / 2;
+  }
+  if (k == 0) return hipSuccess;
+  hp.tiles0 = tiles[0];
+  hipLaunchKernelGGL(dev::k_hub, dim3(tiles[0] + tiles[1]), dim3(dev::kHubThreads), 0, st, hp);
   return hipGetLastError();
 }
 

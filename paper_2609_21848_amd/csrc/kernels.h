@@ -130,7 +130,9 @@ hipError_t launch_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st);
-hipError_t launch_hub(const HubArgs& a, hipStream_t st);
+// The dense block of up to two sides (n <= 2) in one launch; sides with
+// T = 0 are skipped.
+hipError_t launch_hub(const HubArgs* sides, int n, hipStream_t st);
 // Per-vertex pass (plans made with per_vertex): direct items, reverse items,
 // small-item groups and hash items.
 hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st);

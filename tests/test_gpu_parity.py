@@ -107,7 +107,7 @@ def test_dense_hub_block_paths(dbbc):
 
 
 def test_reverse_parts_and_windows(dbbc):
-    # dense enough that reverse items exceed 255 segments (split into parts)
+    # dense enough that reverse items exceed 127 segments (split into parts)
     g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
     want = _want(g)
     with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
