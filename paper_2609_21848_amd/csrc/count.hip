@@ -334,17 +334,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
                          const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
                          const uint32_t inc = wedge_inc(e, tag);
                          uint32_t h = (key * 0x9E3779B1u) >> hshift;
+                         // one compare-and-swap per probe: it claims an
+                         // empty slot, and leaves a taken one as it was
                          for (uint32_t probe = 0;; ++probe) {
                            if (probe > mask) {  // full table: cannot happen at load <= 1/2
                              atomicOr(a.err, kErrHashFull);
                              break;
                            }
-                           uint32_t c = K[h];
-                           if (c == kEmpty) {
-                             c = atomicCAS(&K[h], kEmpty, key);
-                             if (c == kEmpty) c = key;
-                           }
-                           if (c == key) {
+                           const uint32_t c = atomicCAS(&K[h], kEmpty, key);
+                           if (c == kEmpty || c == key) {
                              atomicAdd(&Vv[h], inc);
                              break;
                            }
@@ -442,12 +440,9 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
               atomicOr(a.err, kErrHashFull);
               break;
             }
-            uint32_t cur = keys[h];
-            if (cur == kEmpty) {
-              cur = atomicCAS(&keys[h], kEmpty, key);
-              if (cur == kEmpty) cur = key;
-            }
-            if (cur == key) {
+            // one compare-and-swap per probe (claims an empty slot)
+            const uint32_t cur = atomicCAS(&keys[h], kEmpty, key);
+            if (cur == kEmpty || cur == key) {
               atomicAdd(&vals[h], inc);
               break;
             }

@@ -469,12 +469,9 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
                          atomicOr(a.err, kErrHashFull);
                          break;
                        }
-                       uint32_t c = K[h];
-                       if (c == kEmpty) {
-                         c = atomicCAS(&K[h], kEmpty, key);
-                         if (c == kEmpty) c = key;
-                       }
-                       if (c == key) {
+                       // one compare-and-swap per probe (claims an empty slot)
+                       const uint32_t c = atomicCAS(&K[h], kEmpty, key);
+                       if (c == kEmpty || c == key) {
                          atomicAdd(&V[h], inc);
                          break;
                        }
@@ -599,12 +596,9 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
                            atomicOr(a.err, kErrHashFull);
                            break;
                          }
-                         uint32_t c = keys[h];
-                         if (c == kEmpty) {
-                           c = atomicCAS(&keys[h], kEmpty, key);
-                           if (c == kEmpty) c = key;
-                         }
-                         if (c == key) {
+                         // one compare-and-swap per probe (claims an empty slot)
+                         const uint32_t c = atomicCAS(&keys[h], kEmpty, key);
+                         if (c == kEmpty || c == key) {
                            atomicAdd(&vals[h], inc);
                            break;
                          }
