@@ -311,7 +311,8 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
     int nv = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (!have && longm) {
+      if (!have) {
+        if (!longm) break;  // the batch's long runs are done (uniform)
         const int j = __ffsll(static_cast<unsigned long long>(longm)) - 1;
         longm &= longm - 1;
         cur_pos = readlane(lstart, j);
@@ -319,30 +320,27 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         cur_g = readlane(tag, j);
         have = true;
       }
-      // The load is unconditional (no wait on registers of a skipped load):
-      // lanes past the run's end and empty slots read the first entries of
-      // the array, and their words fail the offset test below.
-      const bool h = have;
+      // The load is unconditional within the chunk: lanes past the run's
+      // end read the first entries of the array, and their words fail the
+      // offset test below.
       const uint32_t p = cur_pos + (kLaneMajor ? lane : 4 * lane);
       vg[u] = cur_g;
       vpos[u] = cur_pos;
-      vrem[u] = h ? cur_end - cur_pos : 0u;  // entries left in the run from the chunk's start
+      vrem[u] = cur_end - cur_pos;  // entries left in the run from the chunk's start
       if (kLaneMajor) {
         const global_t<uint32_t>* a = as_global(adj);
-        v[u].x = a[(h && p < cur_end) ? p : 0u];
-        v[u].y = a[(h && p + kWave < cur_end) ? p + kWave : 0u];
-        v[u].z = a[(h && p + 2 * kWave < cur_end) ? p + 2 * kWave : 0u];
-        v[u].w = a[(h && p + 3 * kWave < cur_end) ? p + 3 * kWave : 0u];
+        v[u].x = a[p < cur_end ? p : 0u];
+        v[u].y = a[p + kWave < cur_end ? p + kWave : 0u];
+        v[u].z = a[p + 2 * kWave < cur_end ? p + 2 * kWave : 0u];
+        v[u].w = a[p + 3 * kWave < cur_end ? p + 3 * kWave : 0u];
       } else {
-        v[u] = *(const global_t<u32x4>*)(adj + ((h && p < cur_end) ? p : 0u));
+        v[u] = *(const global_t<u32x4>*)(adj + (p < cur_end ? p : 0u));
       }
-      if (h) {
-        nv = u + 1;
-        cur_pos += kChunk;
-        if (cur_pos >= cur_end) have = false;
-      }
+      nv = u + 1;
+      cur_pos += kChunk;
+      if (cur_pos >= cur_end) have = false;
     }
-    // slots past the last real chunk (the batch's long runs ran out) hold
+    // slots past the last issued chunk (the batch's long runs ran out) hold
     // no entries: skip them (nv is wavefront-uniform)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
