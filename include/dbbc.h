@@ -114,7 +114,7 @@ typedef struct {
 
 /* One kernel launch of the last timed count and the work it was given. */
 typedef struct {
-  char name[24];     /* "direct", "small", "hash", "reduce", "hub_u", "hub_v", ... */
+  char name[24];     /* "direct", "reverse", "small", "hash", "reduce", "hub" */
   float ms;          /* launch duration between its two HIP events */
   int64_t wedges;    /* vertex-priority wedges tallied by the launch */
   int64_t segments;  /* CSR runs (one per expanded edge) it walked */

@@ -171,6 +171,8 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
+  // the tally's AND-OR addresses need each array aligned to its size
+  if (lane == 0 && (lds_addr(C) & (kReverseWords * 4 - 1)) != 0) atomicOr(a.err, kErrLdsLayout);
   for (int i = lane; i < kReverseWords; i += kWave) C[i] = 0;
   for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
   wave_sync_lds();
