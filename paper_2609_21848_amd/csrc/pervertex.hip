@@ -323,7 +323,10 @@ constexpr int kPVReverseWords = kMaxReverseL / 2;
 
 template <bool kEdge>
 __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
-  __shared__ uint32_t cnt[kPVReverseWaves][kPVReverseWords];
+  // counters, each wavefront's array aligned to its size (the tally's
+  // AND-OR addresses); one dummy word per lane
+  __shared__ __attribute__((aligned(kPVReverseWords * 4))) uint32_t cnt[kPVReverseWaves][kPVReverseWords];
+  __shared__ uint32_t dummies[kPVReverseWaves][kWave];
   __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVReverseWaves][kGather];
   __shared__ uint32_t mflag[kPVReverseWaves][kGather];
   __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
@@ -332,6 +335,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
+  if (lane == 0 && (lds_addr(C) & (kPVReverseWords * 4 - 1)) != 0) atomicOr(a.err, kErrLdsLayout);
   for (int i = threadIdx.x; i < kMaxReverseL; i += kPVReverseThreads) kbal[i] = kunb[i] = 0;
   for (int i = lane; i < kPVReverseWords; i += kWave) C[i] = 0;
   for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
       walk_regs<4>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj, mk, a.long_len,
-                   PairTally{C});
+                   PairTallyBF<kPVReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
     }
     wave_sync_lds();
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {

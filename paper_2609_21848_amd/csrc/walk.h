@@ -412,26 +412,13 @@ __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
 
 // Tally functors for walk_regs: add(entry, g, valid) counts a valid
 // entry's wedge in the counter of its key (a non-returning LDS atomic, so a
-// wavefront never waits on its own counter updates).
-struct DirectTally {  // 16 | 16-bit counters, one 32-bit word per key
-  uint32_t* cnt;
-  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    if (valid) atomicAdd(&cnt[e >> 1], wedge_inc(e, g));
-  }
-};
-
-struct PairTally {  // 8 | 8-bit counters, two keys per 32-bit word
-  uint32_t* cnt;
-  __device__ __forceinline__ void add(uint32_t e, uint32_t g, bool valid) const {
-    // the entry's low bits select the byte: bit 0 (negative) ^ g picks the
-    // symmetric / asymmetric byte, bit 1 (key parity) the 16-bit half
-    if (valid) atomicAdd(&cnt[e >> 2], 1u << (((e ^ (g & 1u)) & 3u) << 3));
-  }
-};
-
-// Branch-free forms: a masked slot adds into a dummy word of its own lane
-// (past the counters) instead of switching the execution mask around every
-// atomic; dummy words are never read.  The key index is reduced modulo the
+// wavefront never waits on its own counter updates).  In a pair-counter
+// word (8|8-bit counters, two keys per 32-bit word) the entry's low bits
+// select the byte: bit 0 (negative) ^ g picks the symmetric / asymmetric
+// byte, bit 1 (key parity) the 16-bit half.
+// A masked slot adds into a dummy word of its own lane (outside the
+// counters) instead of switching the execution mask around every atomic;
+// dummy words are never read.  The key index is reduced modulo the
 // counter array's size (a power of two; valid keys are always below it), so
 // a key can never address past the array, and an array aligned to its own
 // size gets its LDS address from one bitwise instruction.
