@@ -209,6 +209,9 @@ def test_kernel_times(dbbc):
         h.count(flags=dbbc.DBBC_OPT_TIME_KERNELS, hub_T=1024)
         ks = h.kernel_times()
     names = [k["name"] for k in ks]
-    assert {"direct", "reverse", "small", "hash", "reduce"} <= set(names)
+    assert {"direct", "reverse", "small", "hash", "reduce", "hub"} <= set(names)
     assert all(k["ms"] >= 0 for k in ks)
     assert sum(k["wedges"] for k in ks) > 0
+    # one dense-block launch holds both sides: two contractions per tile
+    hub = [k for k in ks if k["name"] == "hub"]
+    assert len(hub) == 1 and hub[0]["macs"] > 0 and hub[0]["macs"] % (2 * 128 * 128) == 0
