@@ -113,6 +113,7 @@ struct DevPlan {
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
   dbbc::DevSideConst side[2] = {};  // host copy of the side table
+  bool any_wide = false;  // per-vertex plans: some run keeps two-word edge credits
   bool valid = false;
   size_t bytes() const {
     size_t b = segs.bytes + small_segs.bytes + small_groups.bytes + direct_items.bytes +
@@ -263,7 +264,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
     a.err = err;
     a.n_reduces = L.n[4];
     RC_TRY(tm.begin(st, "reduce", 0, 0, a.n_reduces, 0));
-    HIP_TRY(dbbc::launch_reduce(a, std::min<int>(4 * cus, std::max(1, a.n_reduces)), st));
+    HIP_TRY(dbbc::launch_reduce(a, 4 * cus, st));
     RC_TRY(tm.end());
   }
   for (const HubLaunch& h : L.hubs) {
@@ -440,6 +441,9 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   HIP_TRY(d.sides.alloc(sizeof(d.side)));
   HIP_TRY(hipMemcpyAsync(d.sides.p, d.side, sizeof(d.side), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
+  d.any_wide = false;
+  for (const auto* v : {&hp.seg_mid, &hp.small_seg_mid})
+    for (uint32_t mid : *v) d.any_wide = d.any_wide || (mid & dbbc::kMidWide) != 0;
   // the host plan keeps only what later launches need
   hp.segs.clear();
   hp.segs.shrink_to_fit();
@@ -954,6 +958,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
     a.rec = g->edge_rec.as<uint32_t>();
     a.pos_v = g->edge_pos_v.as<uint32_t>();
     a.m = g->host.m;
+    a.wide = d.any_wide ? 1 : 0;
     // the combine kernel writes both outputs: a NULL one goes to a buffer of
     // the graph's
     DevBuf& tmp = g->pe_tmp;

@@ -472,11 +472,15 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
 // Multi-part pivots: add the parts' packed counters key by key, then take
 // C(., 2) of the combined counts.
 constexpr int kReduceThreads = 256;
+constexpr int kReduceSlices = 8;  // workgroups per reduce (a few dozen reduces fill no GPU)
 
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
   Sums sums;
   uint32_t graph = kNoGraph;
-  for (int32_t r = blockIdx.x; r < a.n_reduces; r += gridDim.x) {
+  // work units: kReduceSlices interleaved key slices of every reduce
+  const int64_t units = static_cast<int64_t>(a.n_reduces) * kReduceSlices;
+  for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
+    const int32_t r = static_cast<int32_t>(unit / kReduceSlices), slice = static_cast<int32_t>(unit % kReduceSlices);
     const Reduce rd = load_const(a.reduces, r);
     if (rd.graph != graph) {
       if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
@@ -488,7 +492,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
     it.owner = rd.owner;
     it.flags = rd.flags;
     const global_t<uint32_t>* acc = as_global(sc.acc) + static_cast<size_t>(rd.acc_slot) * sc.acc_width;
-    for (int32_t key = rd.key_lo + threadIdx.x; key < rd.key_hi; key += kReduceThreads) {
+    for (int32_t key = rd.key_lo + slice * kReduceThreads + static_cast<int32_t>(threadIdx.x); key < rd.key_hi;
+         key += kReduceSlices * kReduceThreads) {
       uint32_t p = 0, n = 0;
       // eight independent part loads per step
       int32_t j = 0;
@@ -579,8 +584,10 @@ hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st) {
+hipError_t launch_reduce(const ReduceArgs& a, int max_grid, hipStream_t st) {
   if (a.n_reduces == 0) return hipSuccess;
+  const int64_t units = static_cast<int64_t>(a.n_reduces) * dev::kReduceSlices;
+  const int grid = static_cast<int>(units < max_grid ? units : max_grid);
   hipLaunchKernelGGL(dev::k_reduce, dim3(grid), dim3(dev::kReduceThreads), 0, st, a);
   return hipGetLastError();
 }

@@ -130,7 +130,7 @@ hipError_t launch_direct(const DirectArgs& a, int grid, hipStream_t st);
 hipError_t launch_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_hash(const HashArgs& a, int grid, hipStream_t st);
-hipError_t launch_reduce(const ReduceArgs& a, int grid, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs& a, int max_grid, hipStream_t st);
 // The dense block of up to two sides (n <= 2) in one launch; sides with
 // T = 0 are skipped.
 hipError_t launch_hub(const HubArgs* sides, int n, hipStream_t st);
@@ -153,6 +153,7 @@ struct EdgeCombineArgs {
   long long* out_bal;     // [m_in] by input record
   long long* out_unb;
   int64_t m;
+  int32_t wide;           // 0: no run kept two-word credits (e_wb, e_wu are all zero)
 };
 
 // The per-vertex pass with per-edge credits as well (the same plans).

@@ -664,9 +664,12 @@ __global__ __launch_bounds__(256) void k_edge_combine(EdgeCombineArgs a) {
     const uint32_t r = as_global(a.rec)[k];
     const uint32_t q = as_global(a.pos_v)[k];
     const unsigned long long p0 = as_global(a.e_pack[0])[k], p1 = as_global(a.e_pack[1])[q];
-    const unsigned long long b = (p0 & 0xffffffffull) + (p1 & 0xffffffffull) + as_global(a.e_wb[0])[k] +
-                                 as_global(a.e_wb[1])[q];
-    const unsigned long long u = (p0 >> 32) + (p1 >> 32) + as_global(a.e_wu[0])[k] + as_global(a.e_wu[1])[q];
+    unsigned long long b = (p0 & 0xffffffffull) + (p1 & 0xffffffffull);
+    unsigned long long u = (p0 >> 32) + (p1 >> 32);
+    if (a.wide) {  // uniform: the two-word arrays are read only when some run used them
+      b += as_global(a.e_wb[0])[k] + as_global(a.e_wb[1])[q];
+      u += as_global(a.e_wu[0])[k] + as_global(a.e_wu[1])[q];
+    }
     as_global(a.out_bal)[r] = static_cast<long long>(b);
     as_global(a.out_unb)[r] = static_cast<long long>(u);
   }
