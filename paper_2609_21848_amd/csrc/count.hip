@@ -104,11 +104,16 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
       // p + n is at most the item's runs (< 2^16), so p^2 + n^2 <= (p + n)^2
       // and 2 p n are exact in 32 bits: one 16-bit dot product of the
       // counter word with itself, and one with its halves swapped.
+      // With at most 8,192 runs, (p + n)^2 <= 2^26 and a thread's at most 32
+      // keys of the item sum below 2^31: the dot products then accumulate
+      // in 32 bits (sq32, pn32) and reach the 64-bit sums once per item.
       if (tid == 0) sq2 -= static_cast<int64_t>(it.work);
       const bool hub = (it.flags & kItemHubPairs) != 0;
+      const bool acc32 = it.seg_count <= 8192u;
       const uint32_t lo = static_cast<uint32_t>(it.key_lo) & ~3u;
       const uint32_t hi = static_cast<uint32_t>(it.key_hi);
       const uint32_t hub_hi = hub ? static_cast<uint32_t>(sc.T) : 0u;  // keys below: dense-path pairs
+      uint32_t sq32 = 0, pn32 = 0;
       for (uint32_t key = lo + 4 * tid; key < hi; key += 4 * kDirectThreads) {
         const uint4 c4 = *reinterpret_cast<uint4*>(&cnt[key]);
         if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
@@ -128,6 +133,14 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
               pnx += __umul24(p, n);
             }
           }
+        } else if (acc32) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const u16x2 h = __builtin_bit_cast(u16x2, cv[j]);
+            const u16x2 r = __builtin_bit_cast(u16x2, __builtin_amdgcn_alignbit(cv[j], cv[j], 16));
+            sq32 = __builtin_amdgcn_udot2(h, h, sq32, false);
+            pn32 = __builtin_amdgcn_udot2(h, r, pn32, false);
+          }
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -138,6 +151,8 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(DirectArgs a) {
           }
         }
       }
+      sq2 += sq32;
+      pnx += pn32 >> 1;  // a sum of 2 p n terms: even
     }
     __syncthreads();
   }
