@@ -291,14 +291,21 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
   const uint32_t lstart = start + head, lend = start + len;
   Staged cur;
   uint32_t carry = 0;  // table form: flags of the staged blocks before the current one
-  if (total) {
+  // The first staging round's loads go out before the long stream's (marks
+  // form) or right after its first chunk loads (issue-lean form, so that
+  // the chunk loads need not wait for them).
+  bool staged = false;
+  auto first_round = [&]() {
+    staged = true;
+    if (!total) return;
     if (kCompact) {
       fill_table(marks, slen, base, tag);
       stage_round_table(cur, marks, excl, slen, total, 0, carry, adj);
     } else {
       stage_round(cur, marks, excl, slen, base, tag, total, 0, adj);
     }
-  }
+  };
+  if (!kCompact) first_round();
   uint32_t cur_end = 0, cur_g = 0, cur_pos = 0;
   bool have = false;
   // offset of a lane's word q in a chunk (loop-invariant)
@@ -340,6 +347,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       cur_pos += kChunk;
       if (cur_pos >= cur_end) have = false;
     }
+    if (!staged) first_round();
     // slots past the last issued chunk (the batch's long runs ran out) hold
     // no entries: skip them (nv is wavefront-uniform)
 #pragma unroll
@@ -356,6 +364,7 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       }
     }
   }
+  if (!staged) first_round();
   for (uint32_t done = 0; done < total; done += kGather) {
     const bool more = done + kGather < total;
     Staged nxt;
