@@ -441,8 +441,14 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
     atomicAdd(&work_sh, w);
     __syncthreads();
     const uint32_t work = work_sh;
-    // about kHashSlots / 4 distinct keys per pass at most on average
+    // about kHashSlots / 4 distinct keys per pass at most on average; the
+    // table in use is a power of two >= twice a pass's wedges (at least 512
+    // slots), so a small item's sweep reads only that much
     const uint32_t passes = (work + kHashSlots / 4 - 1) / (kHashSlots / 4);
+    const uint32_t per_pass = (work + passes - 1) / (passes > 0 ? passes : 1);
+    uint32_t size = 512;
+    while (size < 2 * per_pass && size < static_cast<uint32_t>(kHashSlots)) size <<= 1;
+    const uint32_t mask = size - 1;
     for (uint32_t pass = 0; pass < passes; ++pass) {
       for (uint32_t k0 = it.seg_begin + wave * kWave; k0 < seg_end; k0 += kHashThreads) {
         const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
@@ -451,9 +457,9 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
           const uint32_t hk = mix32(key);
           if (passes > 1 && (hk >> 16) % passes != pass) return;
           const unsigned long long inc = ((e ^ g) & 1u) ? (1ull << 32) : 1ull;
-          uint32_t h = hk & (kHashSlots - 1);
+          uint32_t h = hk & mask;
           for (uint32_t probe = 0;; ++probe) {
-            if (probe >= static_cast<uint32_t>(kHashSlots)) {  // full table
+            if (probe > mask) {  // full table
               atomicOr(a.err, kErrHashFull);
               break;
             }
@@ -463,12 +469,12 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
               atomicAdd(&vals[h], inc);
               break;
             }
-            h = (h + 1) & (kHashSlots - 1);
+            h = (h + 1) & mask;
           }
         }));
       }
       __syncthreads();
-      for (int h = tid; h < kHashSlots; h += kHashThreads) {
+      for (int h = tid; h < static_cast<int>(size); h += kHashThreads) {
         const uint32_t key = keys[h];
         if (key != kEmpty) {
           const unsigned long long c = vals[h];
