@@ -570,7 +570,7 @@ int enqueue_lone(dbbc_graph* g, const dbbc_options* opt, hipStream_t st) {
 
 int finish_lone(dbbc_graph* g, dbbc_counts* out_host, bool timed) {
   if (g->pinned[kCtlErr] != 0)
-    return fail(DBBC_E_DEVICE, "a kernel reported an internal error (bits: 1 hash table full, 2 LDS layout, 4 item bound; got " +
+    return fail(DBBC_E_DEVICE, "a kernel reported an internal error (bits: 1 hash table full, 2 LDS layout; got " +
                                    std::to_string(g->pinned[kCtlErr]) + ")");
   if (timed) {
     for (size_t i = 0; i < g->timers_used; ++i) {
@@ -1184,7 +1184,7 @@ int dbbc_batch_read(const dbbc_batch* b, dbbc_counts* out_host) {
   const size_t k = b->gs.size();
   if (k == 0) return DBBC_OK;
   if (b->pinned[k * dbbc::kResStride] != 0)
-    return fail(DBBC_E_DEVICE, "a kernel reported an internal error (bits: 1 hash table full, 2 LDS layout, 4 item bound; got " +
+    return fail(DBBC_E_DEVICE, "a kernel reported an internal error (bits: 1 hash table full, 2 LDS layout; got " +
                                    std::to_string(b->pinned[k * dbbc::kResStride]) + ")");
   for (size_t i = 0; i < k; ++i) read_counts(b->gs[i], b->pinned + i * dbbc::kResStride, &out_host[i]);
   return DBBC_OK;

@@ -239,8 +239,6 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     Item nxt2{};
     if (j2 < n) nxt2 = load_const(a.items, j2);
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
-    // the sweep's signed 8-bit products need counters below 128
-    if (lane == 0 && it.seg_count > kReverseCountMaxSegs) atomicOr(a.err, kErrItemBound);
     walk_item<8, false, true>(it, first, sc.segs, sc.other_adj, Marks<uint8_t>{mtab[wave], mflag[wave]}, a.long_len,
                  PairTallyBF<kReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
     wave_sync_lds();

@@ -25,7 +25,6 @@ enum : int {
 enum : unsigned long long {
   kErrHashFull = 1ull,
   kErrLdsLayout = 2ull,  // an LDS array lacks the alignment its addressing assumes
-  kErrItemBound = 4ull,  // a work item exceeds a bound its kernel's counters assume
 };
 
 // Per graph and side s (the side of an item's keys): where the item's
