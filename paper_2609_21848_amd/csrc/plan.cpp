@@ -654,6 +654,15 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     plan.k_wedges[1] += grp.work;
     plan.k_segs[1] += grp.seg_count;
   }
+  // the counting kernel's reverse sweep (signed 8-bit products) needs every
+  // reverse item, or part, to have at most kReverseCountMaxSegs runs
+  const uint32_t max_segs = p.per_vertex ? kReverseMaxSegs : kReverseCountMaxSegs;
+  for (const Item& it : plan.reverse_items) {
+    if (it.seg_count > max_segs) {
+      err = "internal: a reverse item has " + std::to_string(it.seg_count) + " runs";
+      return DBBC_E_DEVICE;
+    }
+  }
   return DBBC_OK;
 }
 
