@@ -48,7 +48,8 @@ extern "C" {
 #define DBBC_E_SIGN (-3)        /* sign not +1 or -1 */
 #define DBBC_E_DUPLICATE (-4)   /* duplicate pair under DBBC_DUP_REJECT */
 #define DBBC_E_OOM (-5)         /* host or device allocation failed */
-#define DBBC_E_DEVICE (-6)      /* a HIP call or kernel launch failed */
+#define DBBC_E_DEVICE (-6)      /* a HIP call or kernel launch failed, or a kernel or the planner
+                                   reported a broken internal bound (dbbc_last_error says which) */
 #define DBBC_E_TOO_LARGE (-7)   /* sizes beyond the limits stated above */
 #define DBBC_E_NO_DEVICE (-8)   /* no gfx950 device visible */
 #define DBBC_E_PARSE (-9)       /* malformed record in an edge-list text */
