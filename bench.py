@@ -59,28 +59,66 @@ def traffic_for(config: str, kernel: str, launches_bytes: float):
             p["write_kib_per_dispatch"] * p["write_scale"]) * 1024.0
 
 
-def cpu_baseline(g, fraction: int, threads: int | None):
-    """The CPU oracle on every fraction-th pivot (a fixed hash of the vertex
-    index), timed end to end; returns GWedges/s of the sample."""
+def cpu_info() -> dict:
+    """The host CPU: model name, logical CPUs and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
+def _pivot_sample(n: int, fraction: int):
     import numpy as np
-    from oracle.vp import default_threads, vp_counts
+    idx = np.arange(n, dtype=np.int64)
+    return idx[((idx * 2654435761) >> 7) % fraction == 0].astype(np.int32)
+
+
+def cpu_baseline(g, fraction: int, fraction_1t: int, threads: int | None):
+    """The CPU oracle's count phase (Algorithm 1 Phase 5 in plain C), its
+    adjacency lists built once outside the timed region: all usable host
+    threads on every fraction-th pivot (a fixed hash of the vertex index),
+    and one thread on every fraction_1t-th.  Returns GWedges/s (value: all
+    threads) with the sample, the build time and the CPU."""
+    from oracle.vp import OracleGraph, default_threads
 
     n = g.n_u + g.n_v
-    idx = np.arange(n, dtype=np.int64)
-    pick = ((idx * 2654435761) >> 7) % fraction == 0
-    pivots = idx[pick].astype(np.int32)
     thr = threads or default_threads()
     t = time.perf_counter()
-    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, pivots=pivots, threads=thr)
+    og = OracleGraph(g.n_u, g.n_v, g.u, g.v, g.sign)
+    t_build = time.perf_counter() - t
+    piv = _pivot_sample(n, fraction)
+    t = time.perf_counter()
+    r = og.count(threads=thr, pivots=piv)
     dt = time.perf_counter() - t
+    piv1 = _pivot_sample(n, fraction_1t)
+    t = time.perf_counter()
+    r1 = og.count(threads=1, pivots=piv1)
+    dt1 = time.perf_counter() - t
+    og.close()
     return {
         "value": r.wedges / dt / 1e9,
         "unit": "GWedges/s",
         "cores": thr,
         "kind": "oracle",
-        "sample": f"oracle (plain C vertex-priority count, its own CSR build included) on "
-                  f"{len(pivots)} of {n} pivots (1 in {fraction} by a fixed hash), "
-                  f"{r.wedges} wedges in {dt:.2f} s",
+        "sample": f"oracle count phase only (plain C vertex-priority count; its adjacency lists "
+                  f"built once beforehand in {t_build:.1f} s, not timed) on {len(piv)} of {n} "
+                  f"pivots (1 in {fraction} by a fixed hash), {r.wedges} wedges in {dt:.2f} s "
+                  f"on {thr} threads",
+        "single_thread": {"value": r1.wedges / dt1 / 1e9, "unit": "GWedges/s", "cores": 1,
+                          "sample": f"{len(piv1)} of {n} pivots (1 in {fraction_1t}), "
+                                    f"{r1.wedges} wedges in {dt1:.2f} s"},
+        "oracle_build_s": t_build,
+        "cpu": cpu_info(),
     }
 
 
@@ -212,6 +250,7 @@ def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: fl
     # warm-up: every pool graph once
     for t_ in [srv.submit(i) for i in ids]:
         srv.wait(t_)
+    st0 = srv.stats()
     tickets = []
     t0 = time.perf_counter()
     u_next = 0
@@ -250,6 +289,7 @@ def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: fl
     st = srv.stats()
     lat = np.array(lat)
     span = (t_last - t_first) / 1e9
+    srv_launched = st["batched_graphs"] - st0["batched_graphs"]
     res = {
         "workload": f"pool of {n_pool} Chung-Lu graphs (m log-uniform in [1e3, 5e6], "
                     f"|U|=m/10, |V|=m/20, exponent 2.2, sign -1 w.p. 0.3), Poisson arrivals "
@@ -264,6 +304,7 @@ def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: fl
                        "max": float(lat.max())},
         "mean_batch": float(np.mean(sizes)),
         "launches": st["launches"] - st0["launches"],
+        "counts_launched": srv_launched,
         "max_queue": st["max_queue"],
         "rejected": st["rejected"],
         "evicted": st["evicted"],
@@ -275,19 +316,71 @@ def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: fl
         f"{res['latency_ms']['p50']:.2f} ms, p99 {res['latency_ms']['p99']:.2f} ms, "
         f"mean batch {res['mean_batch']:.1f}")
 
-    # saturation: 2000 requests on 200 pool graphs (drawn uniformly) submitted
-    # at once, against one launch sequence per request (dbbc_count on handles
-    # of their own, one graph at a time)
+    srv.close()
+
+    # saturation on equal work: a server that never merges requests for one
+    # graph (DBBC_SERVER_NO_MERGE), so every request costs one count, as on
+    # the plain side; 2000 requests on 200 pool graphs (drawn uniformly)
+    # submitted at once, against one launch sequence per request (dbbc_count
+    # on handles of their own, one graph at a time)
     n_sat = 2000
     subset = rng.choice(n_pool, size=min(200, n_pool), replace=False)
     sat = subset[rng.integers(0, len(subset), n_sat)]
+    uniq = sorted(set(int(i) for i in sat))
+    srv = dbbc.Server(merge=False)
+    with ThreadPoolExecutor(16) as ex:
+        sids = dict(zip(uniq, ex.map(lambda i: srv.add_graph(gs[i].n_u, gs[i].n_v, gs[i].u, gs[i].v,
+                                                             gs[i].sign), uniq)))
+    for t_ in [srv.submit(sids[i]) for i in uniq]:  # warm-up
+        srv.wait(t_)
+    st0 = srv.stats()
     t = time.perf_counter()
-    sat_t = [srv.submit(ids[i]) for i in sat]
+    sat_t = [srv.submit(sids[int(i)]) for i in sat]
     got = [srv.wait(tk) for tk in sat_t]
     dt_srv = time.perf_counter() - t
+    st1 = srv.stats()
     assert all(x[0] == dbbc.DBBC_OK for x in got)
+    counted = st1["batched_graphs"] - st0["batched_graphs"]
+    launches = st1["launches"] - st0["launches"]
+    capacity = n_sat / dt_srv
+
+    # Poisson arrivals against the same no-merge server at fractions of the
+    # saturated rate: the highest rate whose p99 stays under the bound
+    p99_bound_ms = 10.0
+    ladder = []
+    for frac in (0.25, 0.5, 0.75, 1.0):
+        rate_k = frac * capacity
+        n_k = int(min(rate_k * 2.0, 60000))
+        arr = np.cumsum(rng.exponential(1.0 / rate_k, n_k))
+        pk = subset[rng.integers(0, len(subset), n_k)]
+        tks = []
+        t0 = time.perf_counter()
+        for k in range(n_k):
+            target = t0 + arr[k]
+            while True:
+                now = time.perf_counter()
+                if now >= target:
+                    break
+                time.sleep(min(target - now, 2e-4))
+            tks.append(srv.submit(sids[int(pk[k])]))
+        t_sub_k = time.perf_counter() - t0
+        lat_k, t_lo, t_hi = [], None, None
+        for tk in tks:
+            status, c, info = srv.wait(tk)
+            assert status == dbbc.DBBC_OK
+            lat_k.append((info["t_done_ns"] - info["t_submit_ns"]) / 1e6)
+            t_lo = info["t_submit_ns"] if t_lo is None else min(t_lo, info["t_submit_ns"])
+            t_hi = info["t_done_ns"] if t_hi is None else max(t_hi, info["t_done_ns"])
+        lat_k = np.array(lat_k)
+        step = {"target_rate": rate_k, "offered_rate": n_k / t_sub_k, "requests": n_k,
+                "graphs_per_s": n_k / ((t_hi - t_lo) / 1e9),
+                "p50_ms": float(np.percentile(lat_k, 50)), "p99_ms": float(np.percentile(lat_k, 99))}
+        ladder.append(step)
+        log(f"[serve] poisson {step['offered_rate']:.0f} req/s: {step['graphs_per_s']:.0f} graphs/s, "
+            f"p50 {step['p50_ms']:.2f} ms, p99 {step['p99_ms']:.2f} ms")
     srv.close()
-    uniq = sorted(set(int(i) for i in sat))
+    ok_rates = [x["offered_rate"] for x in ladder if x["p99_ms"] <= p99_bound_ms]
+
     hs = {}
     with ThreadPoolExecutor(16) as ex:
         for i, h in zip(uniq, ex.map(lambda i: dbbc.Graph(gs[i].n_u, gs[i].n_v, gs[i].u, gs[i].v,
@@ -305,14 +398,107 @@ def bench_served(dbbc, seconds: float, n_pool: int, rate: float, upload_frac: fl
         h.close()
     res["saturated"] = {
         "requests": n_sat,
-        "graphs_per_s_served": n_sat / dt_srv,
+        "distinct_graphs": len(uniq),
+        "merge": False,
+        "counts_launched": counted,
+        "launches": launches,
+        "graphs_per_s_served": capacity,
         "graphs_per_s_plain": n_sat / dt_plain,
         "speedup_vs_plain": dt_plain / dt_srv,
         "served_equals_alone": same,
     }
-    log(f"[serve] saturated: served {n_sat / dt_srv:.0f} graphs/s, plain {n_sat / dt_plain:.0f} "
-        f"graphs/s, equal={same}")
+    res["poisson_ladder"] = {"p99_bound_ms": p99_bound_ms, "steps": ladder,
+                             "max_rate_within_bound": max(ok_rates) if ok_rates else None}
+    log(f"[serve] saturated (no merging, {counted} counts for {n_sat} requests in {launches} launches): "
+        f"served {capacity:.0f} graphs/s, plain {n_sat / dt_plain:.0f} graphs/s, equal={same}")
     return res
+
+
+def _median_count_ms(h, steps: int, warmup: int, first) -> tuple:
+    """(median wall ms of a synchronous dbbc_count, median ms of its kernels
+    by HIP events) over steps counts after warmup counts."""
+    import statistics
+
+    import paper_2609_21848_amd as dbbc
+    import torch
+
+    for _ in range(warmup):
+        assert h.count() == first
+    wall, kern = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c = h.count(flags=dbbc.DBBC_OPT_TIME_KERNELS)
+        wall.append((time.perf_counter() - t) * 1e3)
+        kern.append(sum(k["ms"] for k in h.kernel_times()))
+        assert c == first
+    return statistics.median(wall), statistics.median(kern)
+
+
+def _oracle_cache(name: str, g):
+    path = os.path.join(ROOT, "tests", "golden", "oracle_cache.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f).get(name)
+    if c and (c["n_u"], c["n_v"], c["m"]) == (g.n_u, g.n_v, g.m):
+        return (c["balanced"], c["unbalanced"], c["total"], c["wedges"])
+    return None
+
+
+def bench_config(dbbc, name: str, steps: int, warmup: int) -> dict:
+    """One named single-graph workload: t_e2e (host edge list to host counts:
+    build, plan and first count), then the count phase (median of steps
+    counts after warmup), checked against the committed oracle counts."""
+    import torch
+    from synth import config_graph
+
+    g = config_graph(name)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    h = dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign, stream=stream)
+    first = h.count()
+    t_e2e = time.perf_counter() - t
+    wall_ms, kern_ms = _median_count_ms(h, max(steps, 10), max(warmup, 3), first)
+    h.close()
+    want = _oracle_cache(name, g)
+    res = {"workload": WORKLOADS[name], "counts": first._asdict(), "t_e2e_s": t_e2e,
+           "t_count_ms": wall_ms, "t_count_kernels_ms": kern_ms,
+           "gwedges_per_s": first.wedges / (wall_ms / 1e3) / 1e9,
+           "balanced_per_s": first.balanced / (wall_ms / 1e3),
+           "butterflies_per_s": first.total / (wall_ms / 1e3),
+           "verified_vs_oracle": None if want is None else tuple(first) == want}
+    log(f"[bench] {name}: count {wall_ms:.3f} ms (kernels {kern_ms:.3f} ms), "
+        f"{res['gwedges_per_s']:.1f} GWedges/s, e2e {t_e2e * 1e3:.1f} ms, verified {res['verified_vs_oracle']}")
+    return res
+
+
+def bench_sign_study(dbbc, steps: int, warmup: int) -> dict:
+    """The sign-distribution study (Section VI): one topology (the 2M-edge
+    power-law workload) with the negative-sign probability q in {0.1, 0.3,
+    0.5, 0.7, 0.9}; each count checked against the oracle, and the spread of
+    the count time."""
+    from oracle import vp_counts
+    from synth import config_graph
+
+    rows = []
+    for q in (0.1, 0.3, 0.5, 0.7, 0.9):
+        g = config_graph("powerlaw2m", q=q)
+        r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+        with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
+            first = h.count()
+            wall_ms, kern_ms = _median_count_ms(h, max(steps, 10), max(warmup, 3), first)
+        rows.append({"q": q, "negative_fraction": float((g.sign < 0).mean()),
+                     "balanced": first.balanced, "unbalanced": first.unbalanced,
+                     "t_count_ms": wall_ms, "t_count_kernels_ms": kern_ms,
+                     "verified_vs_oracle": tuple(first) == (r.balanced, r.unbalanced, r.total, r.wedges)})
+        log(f"[bench] sign study q={q}: {wall_ms:.3f} ms (kernels {kern_ms:.3f}), "
+            f"verified {rows[-1]['verified_vs_oracle']}")
+    ts = [x["t_count_kernels_ms"] for x in rows]
+    mean = sum(ts) / len(ts)
+    return {"topology": WORKLOADS["powerlaw2m"].split(", sign")[0], "rows": rows,
+            "kernel_time_spread": (max(ts) - min(ts)) / mean}
 
 
 def bench_ablation(dbbc) -> dict:
@@ -365,7 +551,12 @@ def main():
     ap.add_argument("--sweep", default="",
                     help="option sets to time after the main run, e.g. "
                          "'hub_T=4096;long_len=64,reverse_L=2048' (reported on stderr)")
-    ap.add_argument("--cpu-fraction", type=int, default=16)
+    ap.add_argument("--cpu-fraction", type=int, default=4)
+    ap.add_argument("--cpu-fraction-1t", type=int, default=64)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-workload lines of the smaller workloads")
+    ap.add_argument("--no-sign-study", action="store_true",
+                    help="skip the sign-distribution study")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-pv", action="store_true", help="skip the per-vertex pass")
@@ -573,6 +764,11 @@ def main():
         log(f"[bench] text ingest of {len(text) / 1e9:.2f} GB ({g.m} records) in {t_text:.2f}s "
             f"({len(text) / t_text / 1e9:.2f} GB/s); counts {'equal' if tuple(c_text) == tuple(first) else 'DIFFER'}")
         del text
+    if not args.no_configs:
+        out["configs"] = {name: bench_config(dbbc, name, args.steps, args.warmup)
+                          for name in ("tiny", "powerlaw2m") if name != args.config}
+    if not args.no_sign_study:
+        out["sign_study"] = bench_sign_study(dbbc, args.steps, args.warmup)
     if not args.no_ablation:
         out["ablation"] = bench_ablation(dbbc)
     if not args.no_batch:
@@ -582,7 +778,7 @@ def main():
                                      0.01, 64)
     if not args.no_cpu:
         log("[bench] cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_fraction, None)
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_fraction, args.cpu_fraction_1t, None)
         log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.4f} GWedges/s")
     else:
         out["cpu_baseline"] = None

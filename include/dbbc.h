@@ -123,18 +123,43 @@ typedef struct {
   int64_t macs;      /* int8 multiply-accumulates (dense hub block only) */
 } dbbc_kernel_time;
 
+/* Where a handle's device memory comes from.  Every device allocation the
+ * library makes for a handle (its CSR, plans, scratch and per-vertex / per-
+ * edge buffers, and the temporary arrays of its build) goes through alloc,
+ * and each such block is returned through free when the library no longer
+ * needs it (at the latest in dbbc_graph_destroy).
+ *   alloc(bytes, hip_stream, ctx): a block of at least bytes bytes of
+ *       device memory, aligned to 256 bytes, usable on hip_stream (the
+ *       stream of the call that allocates); NULL when none is available
+ *       (the call then fails with DBBC_E_OOM)
+ *   free(ptr, hip_stream, ctx): give back a block from alloc; hip_stream is
+ *       the stream it was allocated for.  The library has waited for its own
+ *       work on the block, except work enqueued on that stream.
+ *   ctx: passed through.
+ * Both functions are called on the thread of the library call that needs
+ * them.  A NULL dbbc_allocator means hipMalloc / hipFree.  Pinned host memory
+ * (a few words per handle or batch for results) does not go through it. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *hip_stream, void *ctx);
+  void (*free)(void *ptr, void *hip_stream, void *ctx);
+  void *ctx;
+} dbbc_allocator;
+
 /* Build a graph handle from an edge list.
  *   n_u, n_v  : vertices per side (> 0 each, n_u + n_v < 2^30)
  *   m         : number of input records (>= 0)
  *   u, v, sign: m int32 / int32 / int8 values each, host memory unless
  *               DBBC_INPUT_DEVICE; borrowed for the duration of the call
  *   flags     : DBBC_INPUT_DEVICE | DBBC_DUP_REJECT
+ *   alloc     : the handle's device allocator for its whole life (copied;
+ *               NULL = hipMalloc / hipFree); both functions must be set
  *   hip_stream: stream for the uploads
  *   out       : receives the handle (unchanged on error)
  * The degree-priority relabelling (Definition 3) and the rank-ordered CSR of
  * both sides are built here and kept on the device until destroy. */
 int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t *u, const int32_t *v,
-                      const int8_t *sign, uint32_t flags, void *hip_stream, dbbc_graph **out);
+                      const int8_t *sign, uint32_t flags, const dbbc_allocator *alloc, void *hip_stream,
+                      dbbc_graph **out);
 
 /* Build a graph handle from an edge list in text form, parsed on the device
  * (the paper's Phase 1 loading aligned to whole records and Phase 2 compact
@@ -149,6 +174,7 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t *u, con
  *              blank lines and lines starting with '#' or '%' are skipped.
  *   flags    : DBBC_INPUT_DEVICE | DBBC_DUP_REJECT (duplicates: as in
  *              dbbc_graph_create, in line order)
+ *   alloc    : as for dbbc_graph_create
  *   info     : optional (host memory): lines and records read, n_u, n_v
  * Each side's distinct ids become the compact ids 0 .. n - 1 in increasing
  * raw id order; dbbc_graph_raw_ids returns the map.  Per-vertex outputs of
@@ -160,8 +186,8 @@ typedef struct {
   int64_t lines, records; /* lines in the text, edge records among them */
   int64_t n_u, n_v;       /* distinct ids per side */
 } dbbc_text_info;
-int dbbc_graph_create_text(const char *text, int64_t len, uint32_t flags, void *hip_stream,
-                           dbbc_graph **out, dbbc_text_info *info);
+int dbbc_graph_create_text(const char *text, int64_t len, uint32_t flags, const dbbc_allocator *alloc,
+                           void *hip_stream, dbbc_graph **out, dbbc_text_info *info);
 
 /* The raw id of every compact id of one side (side 0 = U, 1 = V) of a graph
  * made by dbbc_graph_create_text: n_side int64 values written to out
@@ -250,7 +276,9 @@ int dbbc_count_read(dbbc_graph *g, dbbc_counts *out_host);
  * together and each graph's sums land in its own result slot.  Counts are
  * exactly those of dbbc_count on each graph alone (same plans, same
  * arithmetic).  With DBBC_BATCH_CAPTURE the launch sequence is captured once
- * into a HIP graph and each dbbc_batch_launch replays it. */
+ * into a HIP graph and each dbbc_batch_launch replays it.  A batch's own
+ * device buffers come from the allocator of its first graph at creation
+ * (hipMalloc for an empty batch); each graph's plan from the graph's. */
 typedef struct dbbc_batch dbbc_batch;
 
 #define DBBC_BATCH_CAPTURE 0x1u
@@ -319,7 +347,9 @@ int dbbc_autotune(dbbc_graph *const *gs, int32_t k, const dbbc_options *start, i
  * max_batch graphs and batch_wedges wedges.  Requests arriving while
  * launches run join the next free slot, so several launches overlap on the
  * device; requests for a graph already being counted wait for the next
- * launch, and requests for one graph waiting together share one count.
+ * launch, and requests for one graph waiting together share one count
+ * (unless DBBC_SERVER_NO_MERGE: then every request is counted by a launch of
+ * its own graph, one request per graph and launch).
  * Uploaded graphs are built by a worker thread and admitted against
  * hbm_budget (device bytes of all resident graphs): idle uploaded graphs are
  * evicted least recently used first; an upload that still does not fit is
@@ -336,7 +366,14 @@ typedef struct {
                            alone; <= 0: 2^26 */
   int64_t batch_wedges; /* a batch stops growing at this many wedges; <= 0:
                            2^28 */
+  uint32_t flags;       /* DBBC_SERVER_* bits */
+  int32_t reserved;     /* 0 */
 } dbbc_server_config;
+
+/* dbbc_server_config.flags: never let waiting requests for one graph share a
+ * count (every request costs one count; for measuring served throughput on
+ * equal work). */
+#define DBBC_SERVER_NO_MERGE 0x1u
 
 /* What happened to one request (times from dbbc_now_ns). */
 typedef struct {

@@ -19,4 +19,4 @@ Every count is an exact Python / int64 integer.
 
 from .brute import brute_counts, brute_per_edge, brute_per_vertex, edge_counts_at  # noqa: F401
 from .pairs import pair_counts, pair_per_vertex  # noqa: F401
-from .vp import vp_counts, build as build_vp  # noqa: F401
+from .vp import OracleGraph, vp_counts, build as build_vp  # noqa: F401

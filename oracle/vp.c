@@ -169,85 +169,132 @@ static void *worker(void *arg) {
   return NULL;
 }
 
-/* Count butterflies of the graph with edges (u[i], v[i], sign[i]).
+/* The graph in the form the worker walks: per global vertex index (U first,
+ * then V) its adjacency list in input order, with each entry's sign and
+ * input record, the degrees and the tie-break ids of Definition 3. */
+typedef struct {
+  int64_t n_u, n_v, m, n;
+  int64_t *deg, *off, *ids, *adj_eid;
+  int32_t *adj;
+  int8_t *adj_sign;
+} oracle_graph;
+
+void oracle_graph_free(oracle_graph *G) {
+  if (!G) return;
+  free(G->deg);
+  free(G->off);
+  free(G->ids);
+  free(G->adj);
+  free(G->adj_sign);
+  free(G->adj_eid);
+  free(G);
+}
+
+/* Build the adjacency lists of the graph with edges (u[i], v[i], sign[i]).
  * Vertex x of U has global index x, vertex y of V has global index n_u + y.
  * id: tie-break id per global index (NULL: the global index itself).
+ * Returns NULL on bad input (ids out of range, signs not +1 / -1) or when
+ * memory runs out.  Duplicate (u, v) pairs are not allowed here. */
+oracle_graph *oracle_graph_build(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u,
+                                 const int32_t *v, const int8_t *sign, const int64_t *id) {
+  if (n_u < 0 || n_v < 0 || m < 0) return NULL;
+  oracle_graph *G = (oracle_graph *)calloc(1, sizeof(oracle_graph));
+  if (!G) return NULL;
+  int64_t n = n_u + n_v;
+  G->n_u = n_u;
+  G->n_v = n_v;
+  G->m = m;
+  G->n = n;
+  G->deg = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  G->off = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  int64_t *fill = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  G->ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  G->adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+  G->adj_sign = (int8_t *)malloc((size_t)(2 * m + 1));
+  G->adj_eid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
+  if (!G->deg || !G->off || !fill || !G->ids || !G->adj || !G->adj_sign || !G->adj_eid) goto fail;
+  for (int64_t i = 0; i < m; ++i) {
+    if (u[i] < 0 || u[i] >= n_u || v[i] < 0 || v[i] >= n_v) goto fail;
+    if (sign[i] != 1 && sign[i] != -1) goto fail;
+    G->deg[u[i]] += 1;
+    G->deg[n_u + v[i]] += 1;
+  }
+  for (int64_t x = 0; x < n; ++x) {
+    G->off[x + 1] = G->off[x] + G->deg[x];
+    G->ids[x] = id ? id[x] : x;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t a = u[i], b = n_u + v[i];
+    G->adj[G->off[a] + fill[a]] = (int32_t)b;
+    G->adj_eid[G->off[a] + fill[a]] = i;
+    G->adj_sign[G->off[a] + fill[a]++] = sign[i];
+    G->adj[G->off[b] + fill[b]] = (int32_t)a;
+    G->adj_eid[G->off[b] + fill[b]] = i;
+    G->adj_sign[G->off[b] + fill[b]++] = sign[i];
+  }
+  free(fill);
+  return G;
+fail:
+  free(fill);
+  oracle_graph_free(G);
+  return NULL;
+}
+
+/* Phase 5 over a built graph.
  * pivots / n_pivots: restrict Phase 5 to these global indices (NULL: all).
  * The per-vertex and per-pivot arrays (length n_u + n_v) and the per-edge
  * arrays (length m, indexed by input record) are optional and must be zeroed
- * by the caller.  Returns 0, or -1 on bad input / no memory.
- * Duplicate (u, v) pairs are not allowed here. */
+ * by the caller.  Returns 0, or -1 on bad input / no memory. */
+int oracle_graph_count(const oracle_graph *G, int nthreads, const int32_t *pivots, int64_t n_pivots,
+                       int64_t *per_pivot_bal, int64_t *bal_vertex, int64_t *unb_vertex,
+                       int64_t *bal_edge, int64_t *unb_edge, oracle_counts *out) {
+  if (!G || !out) return -1;
+  memset(out, 0, sizeof(*out));
+  for (int64_t k = 0; pivots && k < n_pivots; ++k)
+    if (pivots[k] < 0 || pivots[k] >= G->n) return -1;
+  job J;
+  memset(&J, 0, sizeof(J));
+  J.n = G->n;
+  J.adj_off = G->off;
+  J.adj = G->adj;
+  J.adj_sign = G->adj_sign;
+  J.adj_eid = G->adj_eid;
+  J.deg = G->deg;
+  J.id = G->ids;
+  J.pivots = pivots;
+  J.n_pivots = pivots ? n_pivots : G->n;
+  J.per_pivot_bal = per_pivot_bal;
+  J.bal_vertex = bal_vertex;
+  J.unb_vertex = unb_vertex;
+  J.bal_edge = bal_edge;
+  J.unb_edge = unb_edge;
+  pthread_mutex_init(&J.lock, NULL);
+  if (nthreads < 1) nthreads = 1;
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  if (!th) {
+    pthread_mutex_destroy(&J.lock);
+    return -1;
+  }
+  for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, worker, &J);
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(th);
+  pthread_mutex_destroy(&J.lock);
+  *out = J.sum;
+  return 0;
+}
+
+/* Build, count and free in one call (arguments as above). */
 int oracle_vp_count(int64_t n_u, int64_t n_v, int64_t m, const int32_t *u, const int32_t *v,
                     const int8_t *sign, const int64_t *id, int nthreads, const int32_t *pivots,
                     int64_t n_pivots, int64_t *per_pivot_bal, int64_t *bal_vertex,
                     int64_t *unb_vertex, int64_t *bal_edge, int64_t *unb_edge,
                     oracle_counts *out) {
-  int64_t n = n_u + n_v;
-  if (n_u < 0 || n_v < 0 || m < 0 || !out) return -1;
+  if (!out) return -1;
   memset(out, 0, sizeof(*out));
-  int64_t *deg = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
-  int64_t *off = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
-  int64_t *fill = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
-  int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
-  int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
-  int8_t *adj_sign = (int8_t *)malloc((size_t)(2 * m + 1));
-  int64_t *adj_eid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
-  int rc = -1;
-  if (!deg || !off || !fill || !ids || !adj || !adj_sign || !adj_eid) goto done;
-  for (int64_t i = 0; i < m; ++i) {
-    if (u[i] < 0 || u[i] >= n_u || v[i] < 0 || v[i] >= n_v) goto done;
-    if (sign[i] != 1 && sign[i] != -1) goto done;
-    deg[u[i]] += 1;
-    deg[n_u + v[i]] += 1;
-  }
-  for (int64_t x = 0; x < n; ++x) {
-    off[x + 1] = off[x] + deg[x];
-    ids[x] = id ? id[x] : x;
-  }
-  for (int64_t i = 0; i < m; ++i) {
-    int64_t a = u[i], b = n_u + v[i];
-    adj[off[a] + fill[a]] = (int32_t)b;
-    adj_eid[off[a] + fill[a]] = i;
-    adj_sign[off[a] + fill[a]++] = sign[i];
-    adj[off[b] + fill[b]] = (int32_t)a;
-    adj_eid[off[b] + fill[b]] = i;
-    adj_sign[off[b] + fill[b]++] = sign[i];
-  }
-  {
-    job J;
-    memset(&J, 0, sizeof(J));
-    J.n = n;
-    J.adj_off = off;
-    J.adj = adj;
-    J.adj_sign = adj_sign;
-    J.adj_eid = adj_eid;
-    J.deg = deg;
-    J.id = ids;
-    J.pivots = pivots;
-    J.n_pivots = pivots ? n_pivots : n;
-    J.per_pivot_bal = per_pivot_bal;
-    J.bal_vertex = bal_vertex;
-    J.unb_vertex = unb_vertex;
-    J.bal_edge = bal_edge;
-    J.unb_edge = unb_edge;
-    pthread_mutex_init(&J.lock, NULL);
-    if (nthreads < 1) nthreads = 1;
-    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
-    if (!th) goto done;
-    for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, worker, &J);
-    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
-    free(th);
-    pthread_mutex_destroy(&J.lock);
-    *out = J.sum;
-  }
-  rc = 0;
-done:
-  free(deg);
-  free(off);
-  free(fill);
-  free(ids);
-  free(adj);
-  free(adj_sign);
-  free(adj_eid);
+  oracle_graph *G = oracle_graph_build(n_u, n_v, m, u, v, sign, id);
+  if (!G) return -1;
+  int rc = oracle_graph_count(G, nthreads, pivots, n_pivots, per_pivot_bal, bal_vertex,
+                              unb_vertex, bal_edge, unb_edge, out);
+  oracle_graph_free(G);
   return rc;
 }

@@ -57,6 +57,14 @@ def _declare(lib):
     lib.oracle_vp_count.restype = ctypes.c_int
     lib.oracle_vp_count.argtypes = [i64, i64, i64, p, p, p, p, ctypes.c_int, p, i64,
                                     p, p, p, p, p, ctypes.POINTER(_Counts)]
+    if hasattr(lib, "oracle_graph_build"):
+        lib.oracle_graph_build.restype = p
+        lib.oracle_graph_build.argtypes = [i64, i64, i64, p, p, p, p]
+        lib.oracle_graph_count.restype = ctypes.c_int
+        lib.oracle_graph_count.argtypes = [p, ctypes.c_int, p, i64, p, p, p, p, p,
+                                           ctypes.POINTER(_Counts)]
+        lib.oracle_graph_free.restype = None
+        lib.oracle_graph_free.argtypes = [p]
     return lib
 
 
@@ -127,3 +135,41 @@ def vp_counts(n_u, n_v, u, v, sign, ids=None, threads=None, pivots=None,
     if per_edge:
         res.bal_e, res.unb_e = bal_e, unb_e
     return res
+
+
+class OracleGraph:
+    """The oracle's adjacency lists, built once (``oracle_graph_build``), so
+    that Phase 5 alone (``count``) can be run and timed apart from the
+    build."""
+
+    def __init__(self, n_u, n_v, u, v, sign):
+        self._lib = _load()
+        self.n_u, self.n_v = int(n_u), int(n_v)
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        s = np.ascontiguousarray(sign, dtype=np.int8)
+        self.m = int(u.shape[0])
+        self._h = self._lib.oracle_graph_build(self.n_u, self.n_v, self.m, u.ctypes.data,
+                                               v.ctypes.data, s.ctypes.data, None)
+        if not self._h:
+            raise ValueError("oracle_graph_build rejected the graph")
+
+    def count(self, threads=None, pivots=None) -> OracleResult:
+        """Phase 5 over every pivot, or over ``pivots`` (global indices)."""
+        piv = None if pivots is None else np.ascontiguousarray(pivots, dtype=np.int32)
+        out = _Counts()
+        rc = self._lib.oracle_graph_count(self._h, int(threads or default_threads()),
+                                          None if piv is None else piv.ctypes.data,
+                                          0 if piv is None else int(piv.shape[0]),
+                                          None, None, None, None, None, ctypes.byref(out))
+        if rc != 0:
+            raise ValueError("oracle_graph_count rejected its arguments")
+        return OracleResult(out.balanced, out.unbalanced, out.total, out.wedges, out.expansions)
+
+    def close(self):
+        if self._h:
+            self._lib.oracle_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

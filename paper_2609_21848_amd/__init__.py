@@ -34,6 +34,7 @@ DBBC_DUP_REJECT = 0x2
 DBBC_OPT_TIME_KERNELS = 0x1
 DBBC_OPT_WIDE_EDGES = 0x2
 DBBC_BATCH_CAPTURE = 0x1
+DBBC_SERVER_NO_MERGE = 0x1
 
 # every symbol declared in include/dbbc.h
 EXPORTS = (
@@ -89,7 +90,8 @@ class ServerConfig(ctypes.Structure):
     """Mirror of dbbc_server_config (zero = default)."""
     _fields_ = [("hbm_budget", ctypes.c_int64), ("slots", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("solo_wedges", ctypes.c_int64),
-                ("batch_wedges", ctypes.c_int64)]
+                ("batch_wedges", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -103,6 +105,53 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "submitted", "completed", "failed", "rejected", "uploads", "evicted", "launches",
         "batched_graphs", "max_queue", "queued", "resident_graphs", "resident_bytes")]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """Mirror of dbbc_allocator: the device allocator of a graph handle."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+_torch_alloc = None
+
+
+def torch_allocator() -> Allocator:
+    """A dbbc_allocator that takes the library's device memory from PyTorch's
+    caching allocator (``torch.cuda.caching_allocator_alloc`` on the stream
+    the library names) and gives it back with ``caching_allocator_delete``.
+    One shared instance; its callbacks stay alive with the module."""
+    global _torch_alloc
+    if _torch_alloc is None:
+        import torch
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                          int(stream or 0))
+            except Exception:  # out of memory: the library reports DBBC_E_OOM
+                return None
+
+        def _free(ptr, stream, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        _torch_alloc = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+    return _torch_alloc
+
+
+def _allocator_arg(allocator):
+    """ctypes argument for an allocator choice: "torch" (PyTorch's caching
+    allocator), None / "hip" (hipMalloc), or an Allocator."""
+    if allocator == "torch":
+        return ctypes.byref(torch_allocator())
+    if allocator is None or allocator == "hip":
+        return None
+    if isinstance(allocator, Allocator):
+        return ctypes.byref(allocator)
+    raise ValueError(f"unknown allocator {allocator!r}")
 
 
 class _TextInfo(ctypes.Structure):
@@ -126,14 +175,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         raise ImportError(f"{path} is missing: build it with `python -m paper_2609_21848_amd.build`")
     lib = ctypes.CDLL(path)
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
-    lib.dbbc_graph_create.argtypes = [i32, i32, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    lib.dbbc_graph_create.argtypes = [i32, i32, i64, vp, vp, vp, u32, vp, vp, ctypes.POINTER(vp)]
     lib.dbbc_graph_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
     lib.dbbc_count.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_per_vertex.argtypes = [vp, ctypes.POINTER(Options), vp, vp, vp, vp,
                                           ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_per_edge.argtypes = [vp, ctypes.POINTER(Options), vp, vp,
                                         ctypes.POINTER(_Counts), vp]
-    lib.dbbc_graph_create_text.argtypes = [vp, i64, u32, vp, ctypes.POINTER(vp),
+    lib.dbbc_graph_create_text.argtypes = [vp, i64, u32, vp, vp, ctypes.POINTER(vp),
                                            ctypes.POINTER(_TextInfo)]
     lib.dbbc_graph_raw_ids.argtypes = [vp, i32, vp, vp]
     lib.dbbc_count_explicit.argtypes = [vp, ctypes.POINTER(_Counts), vp]
@@ -226,23 +275,28 @@ def _edge_args(u, v, sign):
     return (u.ctypes.data, v.ctypes.data, sign.ctypes.data), 0, (u, v, sign), int(u.shape[0])
 
 
-def dbbc_graph_create(n_u: int, n_v: int, u, v, sign, flags: int = 0, stream=None) -> int:
+def dbbc_graph_create(n_u: int, n_v: int, u, v, sign, flags: int = 0, stream=None,
+                      allocator="torch") -> int:
     """Build a handle; u, v, sign as NumPy arrays or torch tensors (device
-    tensors set DBBC_INPUT_DEVICE).  Returns the opaque handle."""
+    tensors set DBBC_INPUT_DEVICE).  ``allocator``: "torch" (the handle's
+    device memory from PyTorch's caching allocator), None / "hip"
+    (hipMalloc) or an Allocator.  Returns the opaque handle."""
     lib = load()
     ptrs, f, keep, m = _edge_args(u, v, sign)
     if len(np.shape(u)) != 1 or len(keep[1]) != m or len(keep[2]) != m:
         raise ValueError("u, v and sign must be 1-D and of equal length")
     out = ctypes.c_void_p()
     _check(lib.dbbc_graph_create(int(n_u), int(n_v), m, *ptrs, int(flags) | f,
-                                 _stream_ptr(stream), ctypes.byref(out)), "dbbc_graph_create")
+                                 _allocator_arg(allocator), _stream_ptr(stream), ctypes.byref(out)),
+           "dbbc_graph_create")
     return out.value
 
 
-def dbbc_graph_create_text(text, flags: int = 0, stream=None):
+def dbbc_graph_create_text(text, flags: int = 0, stream=None, allocator="torch"):
     """Build a handle from an edge-list text parsed on the device.  text:
-    bytes / str (host), or a uint8 CUDA tensor (sets DBBC_INPUT_DEVICE).
-    Returns (handle, info dict with lines, records, n_u, n_v)."""
+    bytes / str (host), or a uint8 CUDA tensor (sets DBBC_INPUT_DEVICE);
+    ``allocator`` as for dbbc_graph_create.  Returns (handle, info dict with
+    lines, records, n_u, n_v)."""
     lib = load()
     keep = None
     if hasattr(text, "is_cuda") and text.is_cuda:
@@ -254,8 +308,8 @@ def dbbc_graph_create_text(text, flags: int = 0, stream=None):
         ptr, n = (keep.ctypes.data if keep.size else None), int(keep.size)
     out = ctypes.c_void_p()
     info = _TextInfo()
-    _check(lib.dbbc_graph_create_text(ptr, n, int(flags), _stream_ptr(stream), ctypes.byref(out),
-                                      ctypes.byref(info)), "dbbc_graph_create_text")
+    _check(lib.dbbc_graph_create_text(ptr, n, int(flags), _allocator_arg(allocator), _stream_ptr(stream),
+                                      ctypes.byref(out), ctypes.byref(info)), "dbbc_graph_create_text")
     return out.value, {k: int(getattr(info, k)) for k, _ in _TextInfo._fields_}
 
 
@@ -399,10 +453,11 @@ def dbbc_version() -> str:
 class Graph:
     """Owning wrapper: ``with Graph(n_u, n_v, u, v, sign) as g: g.count()``."""
 
-    def __init__(self, n_u, n_v, u, v, sign, flags=0, stream=None):
+    def __init__(self, n_u, n_v, u, v, sign, flags=0, stream=None, allocator="torch"):
         self.n_u, self.n_v = int(n_u), int(n_v)
         self.m_in = int(len(u))  # input records, duplicates included
-        self.handle = dbbc_graph_create(n_u, n_v, u, v, sign, flags, stream)
+        self.handle = None
+        self.handle = dbbc_graph_create(n_u, n_v, u, v, sign, flags, stream, allocator)
 
     def count(self, stream=None, **opts) -> Counts:
         return dbbc_count(self.handle, Options(**opts) if opts else None, stream)
@@ -420,11 +475,11 @@ class Graph:
         return c, bu, bv, uu, uv
 
     @classmethod
-    def from_text(cls, text, flags=0, stream=None):
+    def from_text(cls, text, flags=0, stream=None, allocator="torch"):
         """A graph read from an edge-list text on the device (ids compacted
         per side; ``raw_ids`` maps them back).  ``info`` holds the line and
         record counts."""
-        handle, info = dbbc_graph_create_text(text, flags, stream)
+        handle, info = dbbc_graph_create_text(text, flags, stream, allocator)
         g = cls.__new__(cls)
         g.handle = handle
         g.n_u, g.n_v = info["n_u"], info["n_v"]
@@ -541,9 +596,9 @@ class Server:
     answered by the library's scheduler thread (continuous batching)."""
 
     def __init__(self, hbm_budget=0, slots=0, max_batch=0, solo_wedges=0, batch_wedges=0,
-                 **opts):
+                 merge=True, **opts):
         cfg = ServerConfig(int(hbm_budget), int(slots), int(max_batch), int(solo_wedges),
-                           int(batch_wedges))
+                           int(batch_wedges), 0 if merge else DBBC_SERVER_NO_MERGE, 0)
         out = ctypes.c_void_p()
         opt = ctypes.byref(Options(**opts)) if opts else None
         _check(load().dbbc_server_create(ctypes.byref(cfg), opt, ctypes.byref(out)),

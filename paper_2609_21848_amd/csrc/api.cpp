@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "build_dev.h"
+#include "devmem.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -52,36 +53,7 @@ int current_device(DeviceInfo& di) {
   return DBBC_OK;
 }
 
-// Device memory owned by a handle, freed on destruction.
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  // keep the allocation if it is already large enough
-  hipError_t reserve(size_t n) {
-    if (n <= bytes && (p || n == 0)) return hipSuccess;
-    return alloc(n);
-  }
-  hipError_t alloc(size_t n) {
-    release();
-    if (n == 0) return hipSuccess;
-    hipError_t e = hipMalloc(&p, n);
-    if (e == hipSuccess) bytes = n;
-    return e;
-  }
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
-};
+using dbbc::DevBuf;
 
 // Copy v into b, growing b only when v does not fit.
 template <class T>
@@ -302,6 +274,7 @@ void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L) {
 }  // namespace
 
 struct dbbc_graph {
+  dbbc::DevAlloc al;  // where the handle's device memory comes from (declared first: freed last)
   dbbc::HostGraph host;
   DeviceInfo dev;
   DevBuf adj[2], off[2];
@@ -332,6 +305,7 @@ struct dbbc_graph {
 };
 
 struct dbbc_batch {
+  dbbc::DevAlloc al;  // the allocator of the batch's first graph at creation
   std::vector<dbbc_graph*> gs;
   std::vector<uint64_t> gens;  // plan generation of each graph at creation
   DeviceInfo dev;
@@ -608,10 +582,13 @@ const char* dbbc_status_string(int status) {
 }
 
 int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
-                      const int8_t* sign, uint32_t flags, void* hip_stream, dbbc_graph** out) {
+                      const int8_t* sign, uint32_t flags, const dbbc_allocator* alloc, void* hip_stream,
+                      dbbc_graph** out) {
   g_last_error.clear();
   if (!out) return fail(DBBC_E_INVALID_ARG, "out must not be NULL");
   if (flags & ~(DBBC_INPUT_DEVICE | DBBC_DUP_REJECT)) return fail(DBBC_E_INVALID_ARG, "unknown flag");
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(DBBC_E_INVALID_ARG, "an allocator needs both its alloc and its free function");
   // argument checks that need no device (the records themselves are checked
   // by the device build)
   if (n_u <= 0 || n_v <= 0 || m < 0) return fail(DBBC_E_INVALID_ARG, "n_u and n_v must be positive and m non-negative");
@@ -625,15 +602,16 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, con
   std::unique_ptr<dbbc_graph> g(new (std::nothrow) dbbc_graph());
   if (!g) return fail(DBBC_E_OOM, "host allocation failed");
   g->dev = di;
+  if (alloc) g->al.a = *alloc;
+  g->al.stream = hip_stream;
+  dbbc::AllocScope scope(g->al, hip_stream);
   std::string err;
   dbbc::DeviceCsr csr;
   rc = dbbc::build_device_graph(n_u, n_v, m, u, v, sign, flags, st, g->host, csr, err);
   if (rc != DBBC_OK) return fail(rc, err);
   for (int s = 0; s < 2; ++s) {  // the handle owns the device CSR from here
-    g->adj[s].p = csr.adj[s];
-    g->adj[s].bytes = csr.adj_bytes[s];
-    g->off[s].p = csr.off[s];
-    g->off[s].bytes = csr.off_bytes[s];
+    g->adj[s] = std::move(csr.adj[s]);
+    g->off[s] = std::move(csr.off[s]);
   }
   HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), kCtlWords * sizeof(unsigned long long),
@@ -643,11 +621,13 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, con
   return DBBC_OK;
 }
 
-int dbbc_graph_create_text(const char* text, int64_t len, uint32_t flags, void* hip_stream, dbbc_graph** out,
-                           dbbc_text_info* info) {
+int dbbc_graph_create_text(const char* text, int64_t len, uint32_t flags, const dbbc_allocator* alloc,
+                           void* hip_stream, dbbc_graph** out, dbbc_text_info* info) {
   g_last_error.clear();
   if (!out) return fail(DBBC_E_INVALID_ARG, "out must not be NULL");
   if (flags & ~(DBBC_INPUT_DEVICE | DBBC_DUP_REJECT)) return fail(DBBC_E_INVALID_ARG, "unknown flag");
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(DBBC_E_INVALID_ARG, "an allocator needs both its alloc and its free function");
   if (len < 0 || (len > 0 && !text)) return fail(DBBC_E_INVALID_ARG, "text must not be NULL and len non-negative");
   if (len >= (int64_t(1) << 31) - 1) return fail(DBBC_E_TOO_LARGE, "text longer than 2^31 - 2 bytes");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -657,18 +637,18 @@ int dbbc_graph_create_text(const char* text, int64_t len, uint32_t flags, void* 
   std::unique_ptr<dbbc_graph> g(new (std::nothrow) dbbc_graph());
   if (!g) return fail(DBBC_E_OOM, "host allocation failed");
   g->dev = di;
+  if (alloc) g->al.a = *alloc;
+  g->al.stream = hip_stream;
+  dbbc::AllocScope scope(g->al, hip_stream);
   std::string err;
   dbbc::DeviceCsr csr;
   dbbc::IngestOut io;
   rc = dbbc::ingest_text(text, len, flags, st, g->host, csr, io, err);
   if (rc != DBBC_OK) return fail(rc, err);
   for (int s = 0; s < 2; ++s) {  // the handle owns the device arrays from here
-    g->adj[s].p = csr.adj[s];
-    g->adj[s].bytes = csr.adj_bytes[s];
-    g->off[s].p = csr.off[s];
-    g->off[s].bytes = csr.off_bytes[s];
-    g->raw_ids[s].p = io.raw[s];
-    g->raw_ids[s].bytes = io.raw_bytes[s];
+    g->adj[s] = std::move(csr.adj[s]);
+    g->off[s] = std::move(csr.off[s]);
+    g->raw_ids[s] = std::move(io.raw[s]);
   }
   HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), kCtlWords * sizeof(unsigned long long),
@@ -719,6 +699,8 @@ int dbbc_count(dbbc_graph* g, const dbbc_options* opt, dbbc_counts* out_host, vo
   if (!out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
   int rc = check_graph(g);
   if (rc != DBBC_OK) return rc;
+  dbbc::AllocScope scope(g->al, hip_stream);
+
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   rc = enqueue_lone(g, opt, st);
   if (rc != DBBC_OK) return rc;
@@ -731,6 +713,8 @@ int dbbc_count_explicit(dbbc_graph* g, dbbc_counts* out_host, void* hip_stream) 
   if (!out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
   int rc = check_graph(g);
   if (rc != DBBC_OK) return rc;
+  dbbc::AllocScope scope(g->al, hip_stream);
+
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const dbbc::HostGraph& hg = g->host;
   // the most wedges of one pivot (the list a workgroup holds at once)
@@ -794,6 +778,8 @@ int dbbc_graph_plan(dbbc_graph* g, const dbbc_options* opt, void* hip_stream) {
   g_last_error.clear();
   int rc = check_graph(g);
   if (rc != DBBC_OK) return rc;
+  dbbc::AllocScope scope(g->al, hip_stream);
+
   dbbc::PlanParams p;
   uint32_t long_len = 0;
   rc = params_from(g, opt, p, long_len);
@@ -805,6 +791,8 @@ int dbbc_count_async(dbbc_graph* g, const dbbc_options* opt, void* hip_stream) {
   g_last_error.clear();
   int rc = check_graph(g);
   if (rc != DBBC_OK) return rc;
+  dbbc::AllocScope scope(g->al, hip_stream);
+
   if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
     return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
   rc = enqueue_lone(g, opt, static_cast<hipStream_t>(hip_stream));
@@ -832,6 +820,8 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
                  int64_t* bal_e, int64_t* unb_e, dbbc_counts* out_host, hipStream_t st) {
   int rc = check_graph(g);
   if (rc != DBBC_OK) return rc;
+  dbbc::AllocScope scope(g->al, st);
+
   if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
     return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
   dbbc::PlanParams p;
@@ -1035,7 +1025,10 @@ int assemble_batch(dbbc_batch* b, dbbc_graph* const* gs, int32_t k, const dbbc_o
     dbbc::PlanParams p;
     rc = params_from(gs[i], opt, p, long_len);
     if (rc != DBBC_OK) return rc;
-    rc = ensure_plan(gs[i], p, st);
+    {
+      dbbc::AllocScope plan_scope(gs[i]->al, st);  // a graph's plan comes from its own allocator
+      rc = ensure_plan(gs[i], p, st);
+    }
     if (rc != DBBC_OK) return rc;
     const dbbc::HostPlan& hp = gs[i]->plan.host;
     for (int j = 0; j < 5; ++j) tot[j] += hp.n_items_kept[j];
@@ -1046,6 +1039,7 @@ int assemble_batch(dbbc_batch* b, dbbc_graph* const* gs, int32_t k, const dbbc_o
   }
   for (int j = 0; j < 5; ++j)
     if (tot[j] > INT32_MAX) return fail(DBBC_E_TOO_LARGE, "too many work items in one batch");
+  dbbc::AllocScope scope(b->al, st);  // the batch's own buffers
   HIP_TRY(b->res.reserve(static_cast<size_t>(std::max(k, 1)) * dbbc::kResStride * sizeof(unsigned long long)));
   HIP_TRY(b->ctl.reserve(kCtlWords * sizeof(unsigned long long)));
   const size_t words = static_cast<size_t>(k) * dbbc::kResStride + 1;
@@ -1135,6 +1129,7 @@ int dbbc_batch_create(dbbc_graph* const* gs, int32_t k, const dbbc_options* opt,
   if (!b) return fail(DBBC_E_OOM, "host allocation failed");
   int rc = current_device(b->dev);
   if (rc != DBBC_OK) return rc;
+  if (k > 0) b->al = gs[0]->al;
   rc = assemble_batch(b.get(), gs, k, opt, flags, static_cast<hipStream_t>(hip_stream));
   if (rc != DBBC_OK) return rc;
   *out = b.release();
@@ -1290,6 +1285,7 @@ int dbbc_autotune(dbbc_graph* const* gs, int32_t k, const dbbc_options* start, i
     uint32_t long_len = 0;
     rc = params_from(gs[i], &cur, p, long_len);
     if (rc != DBBC_OK) return rc;
+    dbbc::AllocScope plan_scope(gs[i]->al, st);
     rc = ensure_plan(gs[i], p, st);
     if (rc != DBBC_OK) return rc;
   }

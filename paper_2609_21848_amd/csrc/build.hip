@@ -202,24 +202,10 @@ __global__ void k_wedges(const uint32_t* off, const uint32_t* adj, const int32_t
   }
 }
 
-// Device memory of one build step, freed on scope exit.
-struct Tmp {
-  void* p = nullptr;
-  Tmp() = default;
-  Tmp(const Tmp&) = delete;
-  Tmp& operator=(const Tmp&) = delete;
-  ~Tmp() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t bytes) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    return hipMalloc(&p, std::max<size_t>(bytes, 16));
-  }
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
+// Device memory of one build step, freed on scope exit (at least 16 bytes,
+// so that even an empty array has an address).
+struct Tmp : DevBuf {
+  hipError_t alloc(size_t bytes) { return DevBuf::alloc(std::max<size_t>(bytes, 16)); }
 };
 
 struct Fail {
@@ -488,12 +474,8 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
   g.wedges_vp = static_cast<int64_t>(wsum[0]);
   g.pivots_active = static_cast<int64_t>(wsum[1]);
   for (int x = 0; x < 2; ++x) {
-    out.adj[x] = adj[x].p;
-    out.adj_bytes[x] = (static_cast<size_t>(me) + kAdjPad) * 4;
-    adj[x].p = nullptr;
-    out.off[x] = off[x].p;
-    out.off_bytes[x] = (static_cast<size_t>(n[x]) + 1) * 4;
-    off[x].p = nullptr;
+    out.adj[x] = std::move(adj[x]);
+    out.off[x] = std::move(off[x]);
   }
 }
 

@@ -7,18 +7,17 @@
 #include <cstdint>
 #include <string>
 
+#include "devmem.h"
 #include "internal.h"
 
 namespace dbbc {
 
-// Device arrays a build hands to its graph handle (hipMalloc'ed; the handle
-// frees them): per side, the packed CSR entries (m words plus kAdjPad zero
-// words) and the row offsets (n + 1 words).
+// Device arrays a build hands to its graph handle (from the current
+// allocator; the handle takes them over): per side, the packed CSR entries
+// (m words plus kAdjPad zero words) and the row offsets (n + 1 words).
 struct DeviceCsr {
-  void* adj[2] = {nullptr, nullptr};
-  size_t adj_bytes[2] = {0, 0};
-  void* off[2] = {nullptr, nullptr};
-  size_t off_bytes[2] = {0, 0};
+  DevBuf adj[2];
+  DevBuf off[2];
 };
 
 // Build the relabelled CSR pair on the device from an edge list (host
@@ -30,12 +29,12 @@ int build_device_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, co
                        std::string& err);
 
 // What a text ingestion hands to its graph handle besides the CSR: the
-// per-side compact -> raw id maps (hipMalloc'ed int64 arrays, ascending raw
-// ids; the handle frees them) and the line and record counts.
+// per-side compact -> raw id maps (int64 arrays of ascending raw ids, from
+// the current allocator; the handle takes them over) and the line and record
+// counts.
 struct IngestOut {
   int64_t lines = 0, records = 0;
-  void* raw[2] = {nullptr, nullptr};
-  size_t raw_bytes[2] = {0, 0};
+  DevBuf raw[2];
 };
 
 // Parse an edge list in text form on the device (host text, or device text

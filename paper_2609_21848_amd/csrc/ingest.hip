@@ -140,23 +140,10 @@ __global__ void k_assign_ids(const uint64_t* sorted, const uint32_t* idx, const 
   }
 }
 
-struct Tmp {
-  void* p = nullptr;
-  Tmp() = default;
-  Tmp(const Tmp&) = delete;
-  Tmp& operator=(const Tmp&) = delete;
-  ~Tmp() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t bytes) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    return hipMalloc(&p, std::max<size_t>(bytes, 16));
-  }
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
+// Device memory of one step, freed on scope exit (at least 16 bytes, so
+// that even an empty array has an address).
+struct Tmp : DevBuf {
+  hipError_t alloc(size_t bytes) { return DevBuf::alloc(std::max<size_t>(bytes, 16)); }
 };
 
 struct Fail {
@@ -236,10 +223,10 @@ int64_t compact_side(CubTmp& ct, uint64_t* keys, uint64_t* keys_alt, uint32_t* i
   DEV_TRY(hipcub::DeviceScan::InclusiveSum(t, need, head.as<uint32_t>(), scan.as<uint32_t>(), static_cast<int>(m),
                                            st));
   const int64_t n = to_host_one(scan.as<uint32_t>() + (m - 1), st);
-  DEV_TRY(hipMalloc(&out.raw[side], std::max<size_t>(static_cast<size_t>(n) * 8, 16)));
-  out.raw_bytes[side] = static_cast<size_t>(n) * 8;
+  DEV_TRY(out.raw[side].alloc(std::max<size_t>(static_cast<size_t>(n) * 8, 16)));
+  out.raw[side].bytes = static_cast<size_t>(n) * 8;
   hipLaunchKernelGGL(k_assign_ids, dim3(grid_for(m)), dim3(kThreads), 0, st, keys_alt, idx_alt,
-                     head.as<uint32_t>(), scan.as<uint32_t>(), m, id, static_cast<int64_t*>(out.raw[side]));
+                     head.as<uint32_t>(), scan.as<uint32_t>(), m, id, out.raw[side].as<int64_t>());
   DEV_TRY(hipGetLastError());
   DEV_TRY(hipStreamSynchronize(st));
   return n;
@@ -348,11 +335,7 @@ int ingest_text(const char* text, int64_t len, uint32_t flags, hipStream_t st, H
   }
   auto drop_maps = [&]() {
     (void)hipStreamSynchronize(st);
-    for (int s = 0; s < 2; ++s) {
-      if (out.raw[s]) (void)hipFree(out.raw[s]);
-      out.raw[s] = nullptr;
-      out.raw_bytes[s] = 0;
-    }
+    for (int s = 0; s < 2; ++s) out.raw[s].release();
   };
   try {
     ingest(text, len, flags, st, g, csr, out);

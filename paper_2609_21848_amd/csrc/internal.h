@@ -174,6 +174,18 @@ struct HostPlan {
   std::vector<int8_t> hub_B[2], hub_Bm[2];
 };
 
+// Sizes a plan is checked against before its 32-bit indices are formed:
+// runs are addressed by uint32 indices (Item::seg_begin), work lists and
+// reduces are launched with int32 counts, accumulator slots are int32.
+struct PlanSizes {
+  uint64_t runs = 0;       // runs of the plan
+  uint64_t items = 0;      // the longest list of items of one kind
+  uint64_t reduces = 0;    // multi-part reduces
+  uint64_t acc_slots = 0;  // multi-part accumulator slots
+};
+// DBBC_OK, or DBBC_E_TOO_LARGE with err set when a size exceeds its type.
+int check_plan_sizes(const PlanSizes& z, std::string& err);
+
 // hub_slots: dense-block tiles (128 x 128 workgroups) the device runs at
 // once; the default block is trimmed so that its upper triangle of tiles
 // fits in one round.

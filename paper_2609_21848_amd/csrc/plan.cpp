@@ -21,6 +21,7 @@
 // adds before taking C(., 2).
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <string>
 #include <thread>
 
@@ -270,12 +271,12 @@ std::vector<Piece> build_pieces(const std::vector<uint32_t>& off, int32_t r0, in
   return pieces;
 }
 
-void merge_pieces(HostPlan& plan, std::vector<Piece>& pieces, std::vector<Item>& big_direct) {
+int merge_pieces(HostPlan& plan, std::vector<Piece>& pieces, std::vector<Item>& big_direct, std::string& err) {
   // every piece's place in each list, then the copies in parallel
   const size_t n = pieces.size();
   struct At {
     size_t seg, mid, small, hash, rev, big, red;
-    int32_t slot;
+    int64_t slot;
   };
   std::vector<At> at(n + 1);
   at[0] = At{plan.segs.size(), plan.seg_mid.size(), plan.small_items.size(), plan.hash_items.size(),
@@ -288,6 +289,15 @@ void merge_pieces(HostPlan& plan, std::vector<Piece>& pieces, std::vector<Item>&
     plan.w_sparse += P.w_sparse;
     plan.w_skipped += P.w_skipped;
   }
+  // runs are addressed by 32-bit indices and items by 32-bit counts: check
+  // before any index is narrowed
+  PlanSizes z{};
+  z.runs = at[n].seg;
+  z.items = std::max({at[n].small, at[n].hash, at[n].rev, at[n].big});
+  z.reduces = at[n].red;
+  z.acc_slots = static_cast<uint64_t>(at[n].slot);
+  const int rc = check_plan_sizes(z, err);
+  if (rc != DBBC_OK) return rc;
   plan.segs.resize(at[n].seg);
   plan.seg_mid.resize(at[n].mid);
   plan.seg_edge.resize(at[n].mid);
@@ -296,13 +306,13 @@ void merge_pieces(HostPlan& plan, std::vector<Piece>& pieces, std::vector<Item>&
   plan.reverse_items.resize(at[n].rev);
   big_direct.resize(at[n].big);
   plan.reduces.resize(at[n].red);
-  plan.acc_slots = at[n].slot;
+  plan.acc_slots = static_cast<int32_t>(at[n].slot);
   std::atomic<size_t> next{0};
   auto worker = [&]() {
     for (size_t i; (i = next.fetch_add(1)) < n;) {
       Piece& P = pieces[i];
       const uint32_t base = static_cast<uint32_t>(at[i].seg);
-      const int32_t slot0 = at[i].slot;
+      const int32_t slot0 = static_cast<int32_t>(at[i].slot);
       auto shift = [&](const std::vector<Item>& from, std::vector<Item>& to, size_t pos) {
         for (Item it : from) {
           it.seg_begin += base;
@@ -330,9 +340,25 @@ void merge_pieces(HostPlan& plan, std::vector<Piece>& pieces, std::vector<Item>&
   for (int t = 1; t < nt && static_cast<size_t>(t) < n; ++t) pool.emplace_back(worker);
   worker();
   for (auto& th : pool) th.join();
+  return DBBC_OK;
 }
 
 }  // namespace
+
+int check_plan_sizes(const PlanSizes& z, std::string& err) {
+  const uint64_t i32max = static_cast<uint64_t>(INT32_MAX);
+  if (z.runs > UINT32_MAX) {
+    err = "graph too large: the plan has " + std::to_string(z.runs) + " runs (at most 2^32 - 1)";
+    return DBBC_E_TOO_LARGE;
+  }
+  if (z.items > i32max || z.reduces > i32max || z.acc_slots > i32max) {
+    err = "graph too large: the plan has " + std::to_string(z.items) + " items of one kind, " +
+          std::to_string(z.reduces) + " reduces and " + std::to_string(z.acc_slots) +
+          " accumulator slots (each at most 2^31 - 1)";
+    return DBBC_E_TOO_LARGE;
+  }
+  return DBBC_OK;
+}
 
 int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err) {
   if (p.window_L < 256 || p.window_L > 32768 || p.window_L % 256 != 0) {
@@ -565,7 +591,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     }
   }
 
-  merge_pieces(plan, pieces, big_direct);
+  {
+    const int rc = merge_pieces(plan, pieces, big_direct, err);
+    if (rc != DBBC_OK) return rc;
+  }
   pieces.clear();
   pieces.shrink_to_fit();
 
@@ -597,6 +626,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       singles.push_back(it);
       continue;
     }
+    if (plan.acc_slots > INT32_MAX - static_cast<int32_t>(std::min<uint32_t>(it.seg_count, INT32_MAX))) {
+      err = "graph too large: more than 2^31 - 1 accumulator slots";
+      return DBBC_E_TOO_LARGE;
+    }
     const int32_t first_slot = plan.acc_slots;
     uint32_t k = 0;
     while (k < it.seg_count) {
@@ -626,6 +659,15 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
     r.flags = it.flags;
     r.side = it.side;
     plan.reduces.push_back(r);
+  }
+  {
+    PlanSizes z{};
+    z.runs = plan.segs.size();
+    z.items = parts.size() + singles.size();
+    z.reduces = plan.reduces.size();
+    z.acc_slots = static_cast<uint64_t>(plan.acc_slots);
+    const int rc = check_plan_sizes(z, err);
+    if (rc != DBBC_OK) return rc;
   }
   // parts first (they are the heaviest), then the single-part items
   plan.direct_items = std::move(parts);

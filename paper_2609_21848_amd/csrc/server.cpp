@@ -9,7 +9,8 @@
 // max_batch graphs and batch_wedges wedges.  Requests that arrive while
 // launches run join the next free slot, so work of several launches
 // overlaps on the device.  Several requests for one graph share its count
-// (the count is a pure function of the graph).  An uploader thread builds
+// (the count is a pure function of the graph) unless the server was made
+// with DBBC_SERVER_NO_MERGE.  An uploader thread builds
 // newly uploaded graphs, admitted against an HBM budget: idle uploaded
 // graphs are evicted oldest first to make room, and an upload that cannot
 // fit is rejected.
@@ -111,7 +112,7 @@ int make_graph(const dbbc_options* opt, int32_t n_u, int32_t n_v, int64_t m, con
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
     return sfail(DBBC_E_DEVICE, "hipStreamCreate failed");
   dbbc_graph* g = nullptr;
-  int rc = dbbc_graph_create(n_u, n_v, m, u, v, s, 0u, st, &g);
+  int rc = dbbc_graph_create(n_u, n_v, m, u, v, s, 0u, nullptr, st, &g);
   if (rc == DBBC_OK) rc = dbbc_graph_plan(g, opt, st);
   if (rc == DBBC_OK) rc = dbbc_graph_stats(g, stats);
   if (rc != DBBC_OK) {
@@ -183,8 +184,12 @@ void dbbc_server::run_scheduler() {
         const int32_t gid = reqs[tk].gid;
         GraphRec& gr = graphs[gid];
         auto it = pos.find(gid);
-        if (it != pos.end()) {  // shares a count already chosen
-          sl.tickets[it->second].push_back(tk);
+        if (it != pos.end()) {
+          if (cfg.flags & DBBC_SERVER_NO_MERGE) {  // its own count, in a later launch
+            keep.push_back(tk);
+          } else {  // shares a count already chosen
+            sl.tickets[it->second].push_back(tk);
+          }
           continue;
         }
         const bool big = gr.wedges >= cfg.solo_wedges;
@@ -339,6 +344,7 @@ int dbbc_server_create(const dbbc_server_config* cfg, const dbbc_options* opt, d
   std::unique_ptr<dbbc_server> s(new (std::nothrow) dbbc_server());
   if (!s) return sfail(DBBC_E_OOM, "host allocation failed");
   if (cfg) s->cfg = *cfg;
+  if (s->cfg.flags & ~DBBC_SERVER_NO_MERGE) return sfail(DBBC_E_INVALID_ARG, "unknown server flag");
   if (hipGetDevice(&s->device) != hipSuccess) return sfail(DBBC_E_NO_DEVICE, "no HIP device");
   if (s->cfg.slots <= 0) s->cfg.slots = 4;
   if (s->cfg.slots > 16) return sfail(DBBC_E_INVALID_ARG, "at most 16 slots");

@@ -427,10 +427,11 @@ __device__ __forceinline__ uint32_t wedge_inc(uint32_t e, uint32_t g) {
 // byte, bit 1 (key parity) the 16-bit half.
 // A masked slot adds into a dummy word of its own lane (outside the
 // counters) instead of switching the execution mask around every atomic;
-// dummy words are never read.  The key index is reduced modulo the
-// counter array's size (a power of two; valid keys are always below it), so
-// a key can never address past the array, and an array aligned to its own
-// size gets its LDS address from one bitwise instruction.
+// dummy words are never read.  DirectTallyBF reduces the key index modulo
+// its array's size (a power of two; valid keys are always below it), so a
+// key can never address past the array.  PairTallyBF does no such
+// reduction: it relies on every key of a reverse item lying in the reverse
+// window, a bound the planner checks once per plan.
 template <uint32_t kWords>
 struct DirectTallyBF {
   uint32_t* cnt;    // kWords counters

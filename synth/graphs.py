@@ -139,13 +139,18 @@ CONFIGS = {
 }
 
 
-def config_graph(name: str, scale: float = 1.0, seed=None) -> SignedGraph:
+def config_graph(name: str, scale: float = 1.0, seed=None, q=None) -> SignedGraph:
     """One of the named single-graph workloads; ``scale`` shrinks it for tests
-    (sizes and edge count multiplied by ``scale``, degree caps unchanged)."""
+    (sizes and edge count multiplied by ``scale``, degree caps unchanged);
+    ``q`` replaces the negative-sign probability.  Signs are drawn from a
+    stream of their own after the topology, so the same seed with another
+    ``q`` gives the same edges with other signs."""
     c = dict(CONFIGS[name])
     kind = c.pop("kind")
     if seed is not None:
         c["seed"] = seed
+    if q is not None:
+        c["q"] = float(q)
     if scale != 1.0:
         for k in ("n_u", "n_v", "m"):
             c[k] = max(4, int(round(c[k] * scale)))

@@ -22,10 +22,12 @@ int main(void) {
   dbbc_graph *g = NULL;
   int32_t u[2] = {0, 1}, v[2] = {0, 1};
   int8_t s[2] = {1, -1};
-  CHECK(dbbc_graph_create(0, 2, 2, u, v, s, 0, NULL, &g) == DBBC_E_INVALID_ARG && g == NULL);
+  CHECK(dbbc_graph_create(0, 2, 2, u, v, s, 0, NULL, NULL, &g) == DBBC_E_INVALID_ARG && g == NULL);
   CHECK(strlen(dbbc_last_error()) > 0);
-  CHECK(dbbc_graph_create(2, 2, 2, u, v, s, 0x80u, NULL, &g) == DBBC_E_INVALID_ARG);
-  CHECK(dbbc_graph_create_text(NULL, 4, 0, NULL, &g, NULL) == DBBC_E_INVALID_ARG);
+  CHECK(dbbc_graph_create(2, 2, 2, u, v, s, 0x80u, NULL, NULL, &g) == DBBC_E_INVALID_ARG);
+  dbbc_allocator half = {NULL, NULL, NULL};
+  CHECK(dbbc_graph_create(2, 2, 2, u, v, s, 0, &half, NULL, &g) == DBBC_E_INVALID_ARG);
+  CHECK(dbbc_graph_create_text(NULL, 4, 0, NULL, NULL, &g, NULL) == DBBC_E_INVALID_ARG);
   dbbc_counts c;
   CHECK(dbbc_count(NULL, NULL, &c, NULL) == DBBC_E_INVALID_ARG);
   CHECK(dbbc_count_per_edge(NULL, NULL, NULL, NULL, NULL, NULL) == DBBC_E_INVALID_ARG);

@@ -303,3 +303,15 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
   out[3] = g.wedges_vp;
   return 0;
 }
+
+// The planner's size guard (runs addressed by 32-bit indices, int32 item,
+// reduce and accumulator-slot counts), called with sizes chosen by the test.
+extern "C" int plan_check_sizes(uint64_t runs, uint64_t items, uint64_t reduces, uint64_t acc_slots) {
+  PlanSizes z;
+  z.runs = runs;
+  z.items = items;
+  z.reduces = reduces;
+  z.acc_slots = acc_slots;
+  std::string err;
+  return check_plan_sizes(z, err);
+}

@@ -44,7 +44,7 @@ def _create(n_u, n_v, u, v, s, flags=0):
     v = np.asarray(v, np.int32)
     s = np.asarray(s, np.int8)
     rc = lib.dbbc_graph_create(n_u, n_v, len(u), u.ctypes.data, v.ctypes.data, s.ctypes.data,
-                               flags, None, ctypes.byref(out))
+                               flags, None, None, ctypes.byref(out))
     return rc, out.value, lib.dbbc_last_error().decode()
 
 
@@ -53,14 +53,19 @@ def test_argument_errors_need_no_device():
     assert _create(0, 2, [], [], [])[0] == dbbc.DBBC_E_INVALID_ARG
     assert _create(2**29, 2**29, [0], [0], [1])[0] == dbbc.DBBC_E_TOO_LARGE
     lib = dbbc.load()
-    assert lib.dbbc_graph_create(2, 2, 1, None, None, None, 0, None, None) == dbbc.DBBC_E_INVALID_ARG
-    assert lib.dbbc_graph_create(2, 2, 0, None, None, None, 0x80, None,
+    assert lib.dbbc_graph_create(2, 2, 1, None, None, None, 0, None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create(2, 2, 0, None, None, None, 0x80, None, None,
+                                 ctypes.byref(ctypes.c_void_p())) == dbbc.DBBC_E_INVALID_ARG
+    # an allocator needs both functions
+    half = dbbc.Allocator()
+    assert lib.dbbc_graph_create(2, 2, 0, None, None, None, 0, ctypes.byref(half), None,
                                  ctypes.byref(ctypes.c_void_p())) == dbbc.DBBC_E_INVALID_ARG
     out = ctypes.c_void_p()
-    assert lib.dbbc_graph_create_text(None, 5, 0, None, ctypes.byref(out), None) == dbbc.DBBC_E_INVALID_ARG
-    assert lib.dbbc_graph_create_text(b"1 2 1", 5, 0x80, None, ctypes.byref(out), None) == dbbc.DBBC_E_INVALID_ARG
-    assert lib.dbbc_graph_create_text(b"1 2 1", 5, 0, None, None, None) == dbbc.DBBC_E_INVALID_ARG
-    assert lib.dbbc_graph_create_text(b"1 2 1", 1 << 40, 0, None, ctypes.byref(out),
+    assert lib.dbbc_graph_create_text(None, 5, 0, None, None, ctypes.byref(out), None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create_text(b"1 2 1", 5, 0x80, None, None, ctypes.byref(out),
+                                      None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create_text(b"1 2 1", 5, 0, None, None, None, None) == dbbc.DBBC_E_INVALID_ARG
+    assert lib.dbbc_graph_create_text(b"1 2 1", 1 << 40, 0, None, None, ctypes.byref(out),
                                       None) == dbbc.DBBC_E_TOO_LARGE
     assert lib.dbbc_graph_raw_ids(None, 0, None, None) == dbbc.DBBC_E_INVALID_ARG
     # NULL handles are rejected or ignored

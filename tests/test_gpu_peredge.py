@@ -1,9 +1,10 @@
 """GPU parity of the per-edge pass (dbbc_count_per_edge): for every input
 record, the balanced and unbalanced butterflies containing its edge,
 bit-exact against the oracle (and the paper's printed values on its
-figure); at the largest size, sampled edges against the oracle's local
-count and the invariants that tie the edge counts to the global and the
-per-vertex counts."""
+figure); at the largest size, every edge against digests of the oracle's
+arrays, stored values at the highest-degree vertices, sampled edges against
+the oracle's local count and the invariants that tie the edge counts to the
+global and the per-vertex counts."""
 
 import json
 import os
@@ -34,6 +35,11 @@ def dbbc():
 
 def _say(*a):
     print(*a, flush=True)
+
+
+def _digest(a) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
 
 
 def _pe(dbbc, n_u, n_v, u, v, s, **opts):
@@ -148,6 +154,14 @@ def test_skewed50m_samples_and_invariants(dbbc):
             sv.index_add_(0, torch.from_numpy(g.v.astype(np.int64)).to(dev), e_arr)
             assert torch.equal(su, 2 * pu) and torch.equal(sv, 2 * pv)
         be, ue = be.cpu().numpy(), ue.cpu().numpy()
+    # every edge against the oracle: SHA-256 of the oracle's arrays and the
+    # explicit values of edges at the highest-degree vertices (those whose
+    # runs keep two-word credits), written by make_oracle_cache.py --local
+    local = cache["local"]
+    assert _digest(be) == local["sha256"]["bal_e"], "balanced per-edge counts differ from the oracle's"
+    assert _digest(ue) == local["sha256"]["unb_e"], "unbalanced per-edge counts differ from the oracle's"
+    edges = np.array(local["edges"], np.int64)
+    assert list(be[edges]) == local["bal_e"] and list(ue[edges]) == local["unb_e"]
     # sampled edges against the oracle's count around each edge
     deg_u = np.bincount(g.u, minlength=g.n_u)
     deg_v = np.bincount(g.v, minlength=g.n_v)
@@ -159,3 +173,35 @@ def test_skewed50m_samples_and_invariants(dbbc):
     _say("skewed50m pe: sampled edges against the oracle")
     lb, lu = edge_counts_at(g.n_u, g.n_v, g.u, g.v, g.sign, some)
     assert list(be[some]) == lb and list(ue[some]) == lu
+
+
+def test_crossing_hubs_packed_and_wide_credits(dbbc):
+    """Two hubs of degree 70,000, one per side, over random edges: runs whose
+    mid is a hub have mid degree x the keys' side's largest degree >= 2^32,
+    so the planner gives them two-word credits, while every other run packs
+    both credits into one word.  Both forms in one plan, every edge and
+    vertex against the oracle."""
+    n_u = n_v = 70000
+    base = chung_lu_graph(n_u, n_v, 200000, 2.1, 2.1, 0.4, seed=21)
+    rng = np.random.default_rng(21)
+    hu, hv = 17, 23
+    u = np.concatenate([base.u, np.full(n_v, hu, np.int32), np.arange(n_u, dtype=np.int32)])
+    v = np.concatenate([base.v, np.arange(n_v, dtype=np.int32), np.full(n_u, hv, np.int32)])
+    _, first = np.unique(u.astype(np.int64) * n_v + v, return_index=True)
+    first = np.sort(first)
+    u, v = u[first], v[first]
+    s = np.where(rng.random(u.shape[0]) < 0.4, -1, 1).astype(np.int8)
+    deg_u = np.bincount(u, minlength=n_u)
+    deg_v = np.bincount(v, minlength=n_v)
+    assert int(deg_u[hu]) * int(deg_v.max()) >= 1 << 32 and int(deg_v[hv]) * int(deg_u.max()) >= 1 << 32
+    _say("crossing hubs pe", n_u, n_v, u.shape[0])
+    r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, per_edge=True)
+    with dbbc.Graph(n_u, n_v, u, v, s) as h:
+        c, be, ue = h.count_per_edge()
+        assert (c.balanced, c.unbalanced, c.total, c.wedges) == (r.balanced, r.unbalanced, r.total,
+                                                                 r.wedges)
+        assert np.array_equal(be.cpu().numpy(), r.bal_e)
+        assert np.array_equal(ue.cpu().numpy(), r.unb_e)
+        _, bu, bv, uu, uv = h.count_per_vertex()
+        for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
+            assert np.array_equal(t.cpu().numpy(), want)

@@ -1,7 +1,8 @@
 """GPU parity of the per-vertex pass (dbbc_count_per_vertex): for every
 vertex, the balanced and unbalanced butterflies containing it, bit-exact
 against the oracle (and against the paper's printed values on its figure),
-plus the invariant that each side's entries sum to twice the global counts."""
+plus the invariant that each side's entries sum to twice the global counts;
+at the largest size every vertex against digests of the oracle's arrays."""
 
 import json
 import os
@@ -30,6 +31,11 @@ def dbbc():
 
 def _say(*a):
     print(*a, flush=True)
+
+
+def _digest(a) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
 
 
 def _pv(dbbc, n_u, n_v, u, v, s, **opts):
@@ -114,3 +120,8 @@ def test_skewed50m_invariants(dbbc):
     for arr, want in ((bu, c.balanced), (bv, c.balanced), (uu, c.unbalanced), (uv, c.unbalanced)):
         assert (arr >= 0).all()
         assert int(arr.sum()) == 2 * want
+    # every vertex against the oracle: SHA-256 of the oracle's arrays,
+    # written by tests/golden/make_oracle_cache.py --local
+    digests = cache["local"]["sha256"]
+    for name, arr in (("bal_u", bu), ("bal_v", bv), ("unb_u", uu), ("unb_v", uv)):
+        assert _digest(arr) == digests[name], f"{name} differs from the oracle's"

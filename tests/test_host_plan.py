@@ -17,12 +17,21 @@ CSRC = os.path.join(ROOT, "paper_2609_21848_amd", "csrc")
 
 
 @pytest.fixture(scope="module")
-def emul(tmp_path_factory):
+def emul_lib(tmp_path_factory):
     so = str(tmp_path_factory.mktemp("emul") / "plan_emul.so")
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", so,
                            os.path.join(ROOT, "tests", "native", "plan_emul.cpp"),
                            os.path.join(ROOT, "tests", "native", "host_build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
+    u64 = ctypes.c_uint64
+    lib.plan_check_sizes.argtypes = [u64, u64, u64, u64]
+    lib.plan_check_sizes.restype = ctypes.c_int
+    return lib
+
+
+@pytest.fixture(scope="module")
+def emul(emul_lib):
+    lib = emul_lib
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.plan_emulate.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, i32, p]
 
@@ -184,3 +193,16 @@ def test_per_edge_plan_dense_graph(emul_pv):
     for L, R in [(256, 64), (-1, -1)]:
         out, _, _, be, ue = emul_pv(g, L, R, edges=True)
         assert np.array_equal(be, r.bal_e) and np.array_equal(ue, r.unb_e)
+
+
+def test_plan_size_guard(emul_lib):
+    """Plans whose run indices or item counts would not fit their 32-bit
+    fields are refused with DBBC_E_TOO_LARGE (-7) instead of wrapping."""
+    f = emul_lib.plan_check_sizes
+    u32, i32 = (1 << 32) - 1, (1 << 31) - 1
+    assert f(u32, i32, i32, i32) == 0
+    assert f(u32 + 1, 0, 0, 0) == -7
+    assert f(0, i32 + 1, 0, 0) == -7
+    assert f(0, 0, i32 + 1, 0) == -7
+    assert f(0, 0, 0, i32 + 1) == -7
+    assert f(0, 0, 0, 0) == 0

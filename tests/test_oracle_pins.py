@@ -316,3 +316,25 @@ def test_balanced_fraction_matches_iid_sign_law():
     g = config_graph("powerlaw2m", scale=0.25)
     r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
     assert abs(r.balanced / r.total - (1 + (1 - 2 * 0.25) ** 4) / 2) < 0.01
+
+
+def test_build_once_count_split_over_pivots():
+    """The oracle's separate build and count calls give the one-call counts,
+    and Phase 5 over disjoint pivot sets adds up to the whole (Theorem 1: each
+    butterfly is counted at exactly one pivot)."""
+    from oracle import OracleGraph
+    from synth import chung_lu_graph
+
+    g = chung_lu_graph(900, 700, 9000, 2.1, 1.9, 0.4, seed=3)
+    whole = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign)
+    og = OracleGraph(g.n_u, g.n_v, g.u, g.v, g.sign)
+    try:
+        r = og.count(threads=3)
+        assert (r.balanced, r.unbalanced, r.total, r.wedges) == (
+            whole.balanced, whole.unbalanced, whole.total, whole.wedges)
+        idx = np.arange(g.n_u + g.n_v)
+        parts = [og.count(threads=1, pivots=idx[idx % 3 == k]) for k in range(3)]
+        for f in ("balanced", "unbalanced", "total", "wedges", "expansions"):
+            assert sum(getattr(p, f) for p in parts) == getattr(whole, f)
+    finally:
+        og.close()

@@ -29,3 +29,13 @@ def test_raw_ids_are_distinct():
     for side in (0, 1):
         r = raw_ids(100000, side)
         assert np.unique(r).size == r.size and r.min() >= 0 and r.max() < (1 << 40)
+
+
+def test_sign_probability_keeps_topology():
+    """The sign-ratio study varies only the signs of one topology."""
+    import numpy as np
+    from synth import config_graph
+    a = config_graph("powerlaw2m", scale=0.05, q=0.1)
+    b = config_graph("powerlaw2m", scale=0.05, q=0.9)
+    assert np.array_equal(a.u, b.u) and np.array_equal(a.v, b.v)
+    assert (a.sign < 0).mean() < 0.15 and (b.sign < 0).mean() > 0.85
