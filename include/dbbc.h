@@ -254,6 +254,24 @@ int dbbc_count_per_edge(dbbc_graph *g, const dbbc_options *opt, int64_t *bal_e, 
  * handle's device memory while it runs. */
 int dbbc_count_explicit(dbbc_graph *g, dbbc_counts *out_host, void *hip_stream);
 
+/* For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid device allocation): the count of dbbc_count with no device or host
+ * allocation of any kind.  g must already be planned for opt (by
+ * dbbc_graph_plan, or by a dbbc_count with the same options); otherwise the
+ * call fails with DBBC_E_INVALID_ARG and does nothing.  The buffers the
+ * kernels write -- control words, side table, multi-part accumulators and
+ * the dense block's hub-pair partials -- live in a file-scope device array of
+ * DBBC_NOALLOC_SCRATCH_BYTES bytes of which each GPU the library runs on
+ * holds one copy until the process ends; a count that needs more fails with
+ * DBBC_E_TOO_LARGE (a smaller hub_T or window_L needs less).  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or threads) race and must be serialised by the caller.  The
+ * current device must be the graph's.  Results go to out_host (host memory)
+ * once hip_stream has drained, as for dbbc_count; kernel timing is not
+ * available.  Same counts as dbbc_count. */
+#define DBBC_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int dbbc_count_noalloc(dbbc_graph *g, const dbbc_options *opt, dbbc_counts *out_host, void *hip_stream);
+
 /* Build the handle's counting plan for opt now (NULL = defaults), so that
  * the next count with the same options starts at once; returns when the plan
  * is on the device.  Counts re-plan by themselves when the options change. */

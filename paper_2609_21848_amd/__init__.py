@@ -47,7 +47,7 @@ EXPORTS = (
     "dbbc_last_kernel_times", "dbbc_graph_destroy", "dbbc_status_string", "dbbc_last_error",
     "dbbc_version", "dbbc_graph_plan", "dbbc_now_ns", "dbbc_server_create", "dbbc_server_add_graph",
     "dbbc_server_submit", "dbbc_server_submit_upload", "dbbc_server_wait", "dbbc_server_get_stats",
-    "dbbc_server_last_error", "dbbc_server_destroy",
+    "dbbc_server_last_error", "dbbc_server_destroy", "dbbc_count_noalloc",
 )
 
 
@@ -187,6 +187,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dbbc_graph_raw_ids.argtypes = [vp, i32, vp, vp]
     lib.dbbc_count_explicit.argtypes = [vp, ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_async.argtypes = [vp, ctypes.POINTER(Options), vp]
+    lib.dbbc_count_noalloc.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(_Counts), vp]
     lib.dbbc_count_read.argtypes = [vp, ctypes.POINTER(_Counts)]
     lib.dbbc_batch_create.argtypes = [vp, i32, ctypes.POINTER(Options), u32, vp, ctypes.POINTER(vp)]
     lib.dbbc_batch_reset.argtypes = [vp, vp, i32, ctypes.POINTER(Options), u32, vp]
@@ -228,7 +229,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "dbbc_batch_read", "dbbc_batch_count", "dbbc_count_batch", "dbbc_autotune",
                  "dbbc_last_kernel_times", "dbbc_graph_plan", "dbbc_server_create",
                  "dbbc_server_add_graph", "dbbc_server_submit", "dbbc_server_submit_upload",
-                 "dbbc_server_wait", "dbbc_server_get_stats"):
+                 "dbbc_server_wait", "dbbc_server_get_stats", "dbbc_count_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -323,6 +324,15 @@ def dbbc_count(g: int, options: Options | None = None, stream=None) -> Counts:
     c = _Counts()
     opt = ctypes.byref(options) if options is not None else None
     _check(load().dbbc_count(g, opt, ctypes.byref(c), _stream_ptr(stream)), "dbbc_count")
+    return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
+
+
+def dbbc_count_noalloc(g: int, options: Options | None = None, stream=None) -> Counts:
+    """dbbc_count on a graph already planned for ``options``, with no
+    allocation (its scratch is the library's per-GPU static array)."""
+    c = _Counts()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().dbbc_count_noalloc(g, opt, ctypes.byref(c), _stream_ptr(stream)), "dbbc_count_noalloc")
     return Counts(c.balanced, c.unbalanced, c.total, c.wedges)
 
 

@@ -247,18 +247,20 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
   return DBBC_OK;
 }
 
-// Dense hub launches of a graph's plan, results into res (its slot).
-void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L) {
+// Dense hub launches of a graph's plan, results into res (its slot); the
+// hub-pair partials in hub_xy[s] (default: the plan's own buffers).
+void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L, int32_t* const* hub_xy = nullptr) {
   const dbbc::HostPlan& hp = d.host;
   HubLaunch h;
   for (int s = 0; s < 2; ++s) {
     if (hp.T[s] == 0) continue;
+    int32_t* xy = hub_xy ? hub_xy[s] : d.hub_pairs[s].as<int32_t>();
     // two int32 T x T planes, cleared as T x T 64-bit words
-    L.zero.push_back({d.hub_pairs[s].as<unsigned long long>(), static_cast<size_t>(hp.T[s]) * hp.T[s]});
+    L.zero.push_back({reinterpret_cast<unsigned long long*>(xy), static_cast<size_t>(hp.T[s]) * hp.T[s]});
     dbbc::HubArgs& a = h.a[h.n++];
     a.Bm = d.hub_Bm[s].as<int8_t>();
     a.B = d.hub_B[s].as<int8_t>();
-    a.hub_xy = d.hub_pairs[s].as<int32_t>();
+    a.hub_xy = xy;
     a.res = res;
     a.T = hp.T[s];
     a.K = d.hub_K[s];
@@ -976,9 +978,110 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   return DBBC_OK;
 }
 
+// ---- the count without allocation --------------------------------------------
+//
+// dbbc_count_noalloc runs the kernels of dbbc_count on a graph already
+// planned for its options, with every buffer the kernels write -- the
+// control block (result slot, error bits, work-queue heads), the side table,
+// the multi-part accumulators and the dense block's hub-pair partials -- in
+// one file-scope device array instead of the plan's buffers.  Each GPU the
+// library runs on holds its own copy of the array until the process ends;
+// calls on one GPU share it, so calls that overlap on one GPU race.
+
+constexpr size_t kNoAllocScratchBytes = DBBC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// The array's device address on each device, looked up once per device with
+// that device current (the host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(DBBC_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DBBC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return DBBC_OK;
+}
+
+constexpr size_t round256(size_t n) { return (n + 255) / 256 * 256; }
+
 }  // namespace
 
 extern "C" {
+
+int dbbc_count_noalloc(dbbc_graph* g, const dbbc_options* opt, dbbc_counts* out_host, void* hip_stream) {
+  g_last_error.clear();
+  if (!out_host) return fail(DBBC_E_INVALID_ARG, "NULL argument");
+  int rc = check_graph(g);
+  if (rc != DBBC_OK) return rc;
+  if (opt && (opt->flags & DBBC_OPT_TIME_KERNELS))
+    return fail(DBBC_E_INVALID_ARG, "kernel timing needs dbbc_count");
+  dbbc::PlanParams p;
+  uint32_t long_len = 0;
+  rc = params_from(g, opt, p, long_len);
+  if (rc != DBBC_OK) return rc;
+  DevPlan& d = g->plan;
+  if (!d.valid || !(d.host.p == p))
+    return fail(DBBC_E_INVALID_ARG,
+                "the graph has no plan for these options: plan it first (dbbc_graph_plan or dbbc_count)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->dev.id) return fail(DBBC_E_INVALID_ARG, "the graph lives on another device than the current one");
+  const dbbc::HostPlan& hp = d.host;
+  // scratch layout: control block, side table, accumulators, hub-pair planes
+  const size_t off_sides = round256(kCtlWords * sizeof(unsigned long long));
+  const size_t off_acc = off_sides + round256(sizeof(d.side));
+  const size_t acc_bytes = static_cast<size_t>(hp.acc_slots) * static_cast<size_t>(hp.acc_width) * sizeof(uint32_t);
+  size_t off_hub[2], end = off_acc + round256(acc_bytes);
+  for (int s = 0; s < 2; ++s) {
+    off_hub[s] = end;
+    end += round256(2 * static_cast<size_t>(hp.T[s]) * static_cast<size_t>(hp.T[s]) * sizeof(int32_t));
+  }
+  if (end > kNoAllocScratchBytes)
+    return fail(DBBC_E_TOO_LARGE, "the count needs " + std::to_string(end) + " bytes of scratch, more than the " +
+                                      std::to_string(kNoAllocScratchBytes) +
+                                      " of dbbc_count_noalloc (a smaller hub_T or window_L needs less)");
+  unsigned char* base = nullptr;
+  rc = scratch_address(dev, &base);
+  if (rc != DBBC_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int32_t* hub_xy[2] = {reinterpret_cast<int32_t*>(base + off_hub[0]), reinterpret_cast<int32_t*>(base + off_hub[1])};
+  dbbc::DevSideConst side[2] = {d.side[0], d.side[1]};
+  for (int s = 0; s < 2; ++s) {
+    side[s].acc = reinterpret_cast<uint32_t*>(base + off_acc);
+    side[s].hub_xy = hp.T[s] ? hub_xy[s] : nullptr;
+  }
+  auto* sides = reinterpret_cast<dbbc::DevSideConst*>(base + off_sides);
+  HIP_TRY(dbbc::launch_store_sides(side, sides, st));
+  LaunchSet L;
+  L.direct = d.direct_items.as<dbbc::Item>();
+  L.reverse = d.reverse_items.as<dbbc::Item>();
+  L.small = d.small_groups.as<dbbc::Item>();
+  L.hash = d.hash_items.as<dbbc::Item>();
+  L.reduces = d.reduces.as<dbbc::Reduce>();
+  for (int k = 0; k < 5; ++k) L.n[k] = hp.n_items_kept[k];
+  L.sides = sides;
+  L.ctl = reinterpret_cast<unsigned long long*>(base);
+  L.res = L.ctl;
+  L.n_res = dbbc::kResStride;
+  add_hub_launches(d, L.res, L, hub_xy);
+  L.long_len = long_len;
+  L.cus = g->dev.cus;
+  Timing tm{nullptr, 0, st};
+  rc = enqueue(L, st, tm);
+  if (rc != DBBC_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(g->pinned, L.ctl, kCtlWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return finish_lone(g, out_host, false);
+}
 
 int dbbc_count_per_vertex(dbbc_graph* g, const dbbc_options* opt, int64_t* bal_u, int64_t* bal_v,
                           int64_t* unb_u, int64_t* unb_v, dbbc_counts* out_host, void* hip_stream) {

@@ -557,9 +557,25 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
     p[i] = v;
 }
 
+// Store a graph's two side-table entries (passed by value) at dst.
+struct SidePair {
+  DevSideConst s[2];
+};
+__global__ void k_store_sides(SidePair t, DevSideConst* dst) {
+  if (threadIdx.x < 2) dst[threadIdx.x] = t.s[threadIdx.x];
+}
+
 }  // namespace dev
 
 // ---- launchers ------------------------------------------------------------------
+
+hipError_t launch_store_sides(const DevSideConst* src2, DevSideConst* dst, hipStream_t st) {
+  dev::SidePair t;
+  t.s[0] = src2[0];
+  t.s[1] = src2[1];
+  hipLaunchKernelGGL(dev::k_store_sides, dim3(1), dim3(64), 0, st, t, dst);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st) {
   if (n == 0) return hipSuccess;

@@ -126,6 +126,9 @@ struct HubArgs {
 };
 
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
+// Write the two side-table entries src2[0..2) (host values) to device
+// memory dst by a kernel (no copy from host memory).
+hipError_t launch_store_sides(const DevSideConst* src2, DevSideConst* dst, hipStream_t st);
 hipError_t launch_direct(const DirectArgs& a, int grid, hipStream_t st);
 hipError_t launch_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_reverse(const SmallArgs& a, int grid, hipStream_t st);
