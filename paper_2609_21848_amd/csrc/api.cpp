@@ -84,6 +84,12 @@ struct DevPlan {
   DevBuf seg_edge, small_seg_edge;
   DevBuf hub_pairs[2], hub_B[2], hub_Bm[2];
   int32_t hub_K[2] = {0, 0};
+  // per-vertex plans with a dense block: hub tally runs and items, the
+  // transposed signs, the counts Zc and Zc', the hub edges' CSR positions,
+  // the digit planes of the completed counts, and the digits per value
+  DevBuf hub_items, hub_segs;
+  DevBuf hub_Bt[2], hub_Bmt[2], hub_Zc[2], hub_Zcp[2], hub_pos[2], hub_rows[2], hub_cols[2];
+  int32_t hub_D[2] = {0, 0};
   dbbc::DevSideConst side[2] = {};  // host copy of the side table
   bool any_wide = false;  // per-vertex plans: some run keeps two-word edge credits
   bool valid = false;
@@ -92,7 +98,10 @@ struct DevPlan {
                hash_items.bytes + reverse_items.bytes + reduces.bytes + acc.bytes + sides.bytes +
                seg_mid.bytes + small_seg_mid.bytes + small_owner.bytes + seg_edge.bytes +
                small_seg_edge.bytes;
-    for (int s = 0; s < 2; ++s) b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes;
+    b += hub_items.bytes + hub_segs.bytes;
+    for (int s = 0; s < 2; ++s)
+      b += hub_pairs[s].bytes + hub_B[s].bytes + hub_Bm[s].bytes + hub_Bt[s].bytes + hub_Bmt[s].bytes +
+           hub_Zc[s].bytes + hub_Zcp[s].bytes + hub_pos[s].bytes + hub_rows[s].bytes + hub_cols[s].bytes;
     return b;
   }
 };
@@ -251,7 +260,7 @@ int enqueue(const LaunchSet& L, hipStream_t st, Timing& tm) {
 // hub-pair partials in hub_xy[s] (default: the plan's own buffers).
 void add_hub_launches(DevPlan& d, unsigned long long* res, LaunchSet& L, int32_t* const* hub_xy = nullptr) {
   const dbbc::HostPlan& hp = d.host;
-  HubLaunch h;
+  HubLaunch h{};
   for (int s = 0; s < 2; ++s) {
     if (hp.T[s] == 0) continue;
     int32_t* xy = hub_xy ? hub_xy[s] : d.hub_pairs[s].as<int32_t>();
@@ -359,11 +368,19 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   HIP_TRY(upload(d.reverse_items, hp.reverse_items, st));
   HIP_TRY(upload(d.reduces, hp.reduces, st));
   HIP_TRY(d.acc.alloc(static_cast<size_t>(hp.acc_slots) * hp.acc_width * sizeof(uint32_t)));
+  if (p.per_vertex) {
+    HIP_TRY(upload(d.hub_items, hp.hub_items, st));
+    HIP_TRY(upload(d.hub_segs, hp.hub_segs, st));
+  }
   for (int s = 0; s < 2; ++s) {
     d.hub_pairs[s].release();
     d.hub_B[s].release();
     d.hub_Bm[s].release();
+    for (DevBuf* b : {&d.hub_Bt[s], &d.hub_Bmt[s], &d.hub_Zc[s], &d.hub_Zcp[s], &d.hub_pos[s], &d.hub_rows[s],
+                      &d.hub_cols[s]})
+      b->release();
     d.hub_K[s] = 0;
+    d.hub_D[s] = 0;
     const int32_t T = hp.T[s], TO = hp.T[1 - s];
     if (T == 0) continue;
     HIP_TRY(d.hub_pairs[s].alloc(2 * static_cast<size_t>(T) * T * sizeof(int32_t)));
@@ -373,6 +390,51 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
     for (int32_t x = 0; x < T; ++x) {
       std::memcpy(&B[static_cast<size_t>(x) * K], &hp.hub_B[s][static_cast<size_t>(x) * TO], TO);
       std::memcpy(&Bm[static_cast<size_t>(x) * K], &hp.hub_Bm[s][static_cast<size_t>(x) * TO], TO);
+    }
+    if (p.per_vertex) {
+      // the credit products' constants: B and Bm transposed (rows y), Zc[x][y]
+      // = #{w > x : B[w][y] != 0}, Zc'[w][y] = #{x < w : Bm[x][y] != 0}, and
+      // the CSR position of every hub edge (x, y) of this side
+      const size_t TK = static_cast<size_t>(T) * K;
+      std::vector<int8_t> Bt(TK, 0), Bmt(TK, 0);
+      std::vector<int32_t> Zc(TK, 0), Zcp(TK, 0), pos(TK, -1);
+      for (int32_t x = 0; x < T; ++x)
+        for (int32_t y = 0; y < K; ++y) {
+          Bt[static_cast<size_t>(y) * T + x] = B[static_cast<size_t>(x) * K + y];
+          Bmt[static_cast<size_t>(y) * T + x] = Bm[static_cast<size_t>(x) * K + y];
+        }
+      for (int32_t y = 0; y < K; ++y) {
+        int32_t below = 0;  // rows w > x with B[w][y] != 0, for x from the bottom up
+        for (int32_t x = T - 1; x >= 0; --x) {
+          Zc[static_cast<size_t>(x) * K + y] = below;
+          below += B[static_cast<size_t>(x) * K + y] != 0;
+        }
+        int32_t above = 0;  // rows x < w with Bm[x][y] != 0
+        for (int32_t w = 0; w < T; ++w) {
+          Zcp[static_cast<size_t>(w) * K + y] = above;
+          above += Bm[static_cast<size_t>(w) * K + y] != 0;
+        }
+      }
+      const dbbc::HostSide& S = g->host.side[s];
+      for (int32_t x = 0; x < T; ++x)
+        for (uint32_t q = S.off[x]; q < S.off[x + 1]; ++q) {
+          const int32_t y = static_cast<int32_t>(S.adj[q] >> 1);
+          if (y >= TO) break;  // rows are sorted by rank
+          pos[static_cast<size_t>(x) * K + y] = static_cast<int32_t>(q);
+        }
+      HIP_TRY(upload(d.hub_Bt[s], Bt, st));
+      HIP_TRY(upload(d.hub_Bmt[s], Bmt, st));
+      HIP_TRY(upload(d.hub_Zc[s], Zc, st));
+      HIP_TRY(upload(d.hub_Zcp[s], Zcp, st));
+      HIP_TRY(upload(d.hub_pos[s], pos, st));
+      HIP_TRY(hipStreamSynchronize(st));  // the host vectors leave scope
+      // a pair's counts are at most the side's largest degree: digits of
+      // kHubDigitBits bits, enough for that bound with a signed top digit
+      int32_t D = 1;
+      while ((int64_t{1} << (dbbc::kHubDigitBits * D)) <= S.max_deg) ++D;
+      d.hub_D[s] = D;
+      HIP_TRY(d.hub_rows[s].alloc(2 * static_cast<size_t>(D) * T * T));
+      HIP_TRY(d.hub_cols[s].alloc(2 * static_cast<size_t>(D) * T * T));
     }
     HIP_TRY(upload(d.hub_B[s], B, st));
     HIP_TRY(upload(d.hub_Bm[s], Bm, st));
@@ -433,6 +495,10 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   hp.small_seg_edge.shrink_to_fit();
   hp.small_owner.clear();
   hp.small_owner.shrink_to_fit();
+  hp.hub_items.clear();
+  hp.hub_items.shrink_to_fit();
+  hp.hub_segs.clear();
+  hp.hub_segs.shrink_to_fit();
   hp.small_segs.clear();
   hp.small_segs.shrink_to_fit();
   hp.small_items.clear();
@@ -831,7 +897,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   rc = params_from(g, opt, p, long_len);
   if (rc != DBBC_OK) return rc;
   p.per_vertex = true;
-  p.hub_T = 0;
+  p.hub_T = std::min(p.hub_T, dbbc::kMaxPVHubT);
   p.wide_all = edge && opt && (opt->flags & DBBC_OPT_WIDE_EDGES);
   const int32_t n[2] = {g->host.n_u, g->host.n_v};
   const size_t m = static_cast<size_t>(g->host.m);
@@ -883,6 +949,69 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + kCtlQueues);
   const dbbc::DevSideConst* sides = d.sides.as<dbbc::DevSideConst>();
   const int cus = g->dev.cus;
+  if (hp.T[0] > 0) {
+    // The dense block (hubpv.hip): the hub pairs' sparse counts, completed
+    // and credited by the block's products, then the credits of the block's
+    // wedges; the sparse kernels below read the completed counts.
+    dbbc::HubTallyArgs ta[2];
+    for (int s = 0; s < 2; ++s) {
+      HIP_TRY(dbbc::launch_fill_u64(d.hub_pairs[s].as<unsigned long long>(),
+                                    static_cast<size_t>(hp.T[s]) * hp.T[s], 0ull, st));
+      const int32_t lo = s == 0 ? 0 : hp.n_hub_side0;
+      const int32_t hi = s == 0 ? hp.n_hub_side0 : static_cast<int32_t>(d.hub_items.bytes / sizeof(dbbc::Item));
+      ta[s] = dbbc::HubTallyArgs{};
+      ta[s].items = d.hub_items.as<dbbc::Item>() + lo;
+      ta[s].segs = d.hub_segs.as<dbbc::Segment>();
+      ta[s].other_adj = g->adj[1 - s].as<uint32_t>();
+      ta[s].hub_xy = d.hub_pairs[s].as<int32_t>();
+      ta[s].n_items = hi - lo;
+      ta[s].T = hp.T[s];
+      ta[s].long_len = long_len;
+    }
+    HIP_TRY(dbbc::launch_pv_hub_tally(ta, 2, 4 * cus, st));
+    dbbc::HubArgs ha[2];
+    for (int s = 0; s < 2; ++s) {
+      ha[s] = dbbc::HubArgs{};
+      ha[s].Bm = d.hub_Bm[s].as<int8_t>();
+      ha[s].B = d.hub_B[s].as<int8_t>();
+      ha[s].hub_xy = d.hub_pairs[s].as<int32_t>();
+      ha[s].res = ctl;
+      ha[s].T = hp.T[s];
+      ha[s].K = d.hub_K[s];
+      ha[s].orig = g->orig[s].as<int32_t>();
+      ha[s].bal = g->pv_out[s][0].as<unsigned long long>();
+      ha[s].unb = g->pv_out[s][1].as<unsigned long long>();
+    }
+    HIP_TRY(dbbc::launch_hub(ha, 2, st));
+    for (int s = 0; s < 2; ++s) {
+      dbbc::HubDigitArgs da{};
+      da.hub_xy = d.hub_pairs[s].as<int32_t>();
+      da.rows = d.hub_rows[s].as<int8_t>();
+      da.cols = d.hub_cols[s].as<int8_t>();
+      da.T = hp.T[s];
+      da.D = d.hub_D[s];
+      HIP_TRY(dbbc::launch_hub_digits(da, st));
+      for (int role = 0; role < (edge ? 2 : 1); ++role) {
+        dbbc::HubCreditArgs ca{};
+        const bool pm = role == 0;  // pivot-mid edges and mids; else end-mid edges
+        ca.A = pm ? d.hub_rows[s].as<int8_t>() : d.hub_cols[s].as<int8_t>();
+        ca.Bt = pm ? d.hub_Bt[s].as<int8_t>() : d.hub_Bmt[s].as<int8_t>();
+        ca.E = pm ? d.hub_Bm[s].as<int8_t>() : d.hub_B[s].as<int8_t>();
+        ca.Zc = pm ? d.hub_Zc[s].as<int32_t>() : d.hub_Zcp[s].as<int32_t>();
+        ca.pos = edge ? d.hub_pos[s].as<int32_t>() : nullptr;
+        ca.orig_mid = pm ? g->orig[1 - s].as<int32_t>() : nullptr;
+        ca.bal_mid = g->pv_out[1 - s][0].as<unsigned long long>();
+        ca.unb_mid = g->pv_out[1 - s][1].as<unsigned long long>();
+        ca.ewb = g->pe_out[s][1].as<unsigned long long>();
+        ca.ewu = g->pe_out[s][2].as<unsigned long long>();
+        ca.T = hp.T[s];
+        ca.K = d.hub_K[s];
+        ca.D = d.hub_D[s];
+        ca.upper = pm ? 1 : 0;
+        HIP_TRY(dbbc::launch_hub_credit(ca, st));
+      }
+    }
+  }
   // direct items: one launch per side (hot-key credits are summed per
   // workgroup for one side)
   for (int s = 0; s < 2; ++s) {
@@ -950,7 +1079,8 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
     a.rec = g->edge_rec.as<uint32_t>();
     a.pos_v = g->edge_pos_v.as<uint32_t>();
     a.m = g->host.m;
-    a.wide = d.any_wide ? 1 : 0;
+    // runs flagged wide, or the dense block's credits (kept in the two-word form)
+    a.wide = d.any_wide || hp.T[0] > 0 ? 1 : 0;
     // the combine kernel writes both outputs: a NULL one goes to a buffer of
     // the graph's
     DevBuf& tmp = g->pe_tmp;

@@ -191,6 +191,54 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubPair hp) {
         syy += static_cast<int64_t>(yv) * yv;
         sx += xv;
       }
+  if (a.bal) {
+    // per-vertex pass: store the completed counts (zeros where w is not
+    // below x) and credit each pair's C(P,2) + C(N,2) and P N to x (row
+    // sums) and w (column sums)
+    int32_t* hx = a.hub_xy;
+    int64_t cb[2] = {0, 0}, cu[2] = {0, 0};  // column sums per j
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int x = row0 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        int64_t rb = 0, ru = 0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int w = col0 + j * 32 + (lane & 31);
+          const bool keep = !diag || w > x;
+          const int64_t xv = keep ? X[i][j][q] : 0, yv = keep ? Y[i][j][q] : 0;
+          hx[static_cast<size_t>(x) * a.T + w] = static_cast<int32_t>(xv);
+          hx[TT + static_cast<size_t>(x) * a.T + w] = static_cast<int32_t>(yv);
+          const int64_t fb = (xv * xv + yv * yv - 2 * xv) / 4, fu = (xv * xv - yv * yv) / 4;
+          rb += fb;
+          ru += fu;
+          cb[j] += fb;
+          cu[j] += fu;
+        }
+#pragma unroll
+        for (int d = 16; d > 0; d >>= 1) {
+          rb += __shfl_xor(rb, d, 64);
+          ru += __shfl_xor(ru, d, 64);
+        }
+        if ((lane & 31) == 0) {
+          const int32_t id = a.orig[x];
+          if (rb) atomicAdd(&a.bal[id], static_cast<unsigned long long>(rb));
+          if (ru) atomicAdd(&a.unb[id], static_cast<unsigned long long>(ru));
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      int64_t b = cb[j], u = cu[j];
+      b += __shfl_xor(b, 32, 64);
+      u += __shfl_xor(u, 32, 64);
+      if (lane < 32) {
+        const int32_t id = a.orig[col0 + j * 32 + lane];
+        if (b) atomicAdd(&a.bal[id], static_cast<unsigned long long>(b));
+        if (u) atomicAdd(&a.unb[id], static_cast<unsigned long long>(u));
+      }
+    }
+  }
   int64_t bal = (sxx + syy - 2 * sx) / 4, unb = (sxx - syy) / 4;
   int64_t tot = bal + unb, wd = sx - x0;
 #pragma unroll

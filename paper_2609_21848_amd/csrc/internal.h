@@ -108,7 +108,7 @@ struct PlanParams {
   int32_t reverse_L = 0;
   int32_t small_work = 0;
   int32_t part_work = 0;
-  bool per_vertex = false;  // plan for the per-vertex pass (no dense block, no parts)
+  bool per_vertex = false;  // plan for the per-vertex pass (no multi-part items)
   bool wide_all = false;    // per-vertex plans: flag every run kMidWide
   bool operator==(const PlanParams& o) const {
     return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
@@ -120,6 +120,10 @@ struct PlanParams {
 // Largest reverse window: keys of a reverse item index a per-wavefront LDS
 // array of this many counters.
 constexpr int32_t kMaxReverseL = 4096;
+
+// Largest dense block of the per-vertex pass: the hub tally keeps 32-bit p
+// and n per hub endpoint in LDS.
+constexpr int32_t kMaxPVHubT = 4096;
 
 // Key window of a direct item of the per-vertex pass (32-bit counters in
 // LDS); wider windows are split into items that share their runs.
@@ -172,6 +176,14 @@ struct HostPlan {
   // dense hub block per side s (pairs on s): row-major int8 matrices
   // [T[s] x T[1-s]] of signs (B) and of signs masked to lower-priority mids (Bm)
   std::vector<int8_t> hub_B[2], hub_Bm[2];
+  // per-vertex plans with a dense block: for every hub pivot x < T[s] (one
+  // item each, both sides, side 0 first), the runs of its sparse wedges
+  // toward hub endpoints w < T[s] (mids y >= T[1 - s]), so that a tally of
+  // these alone gives the hub pairs' sparse counts before the dense block
+  // completes them; the items' keys are [x + 1, T[s])
+  std::vector<Segment> hub_segs;
+  std::vector<Item> hub_items;
+  int32_t n_hub_side0 = 0;
 };
 
 // Sizes a plan is checked against before its 32-bit indices are formed:

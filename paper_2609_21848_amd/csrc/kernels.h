@@ -117,12 +117,19 @@ struct AssembleSrc {
 // contraction length is padded with zero columns to a multiple of kHubKPad.
 constexpr int32_t kHubKPad = 64;
 struct HubArgs {
-  const int8_t* Bm;              // [T x K] row-major, K = padded mid count
-  const int8_t* B;               // [T x K]
-  const int32_t* hub_xy;         // [2 x T x T] sparse partials: p + n, then p - n
-  unsigned long long* res;       // res[0..2] sums, res[3] dense wedges
-  int32_t T;                     // rows (pairs side)
-  int32_t K;                     // padded contraction length (multiple of kHubKPad)
+  const int8_t* Bm = nullptr;    // [T x K] row-major, K = padded mid count
+  const int8_t* B = nullptr;     // [T x K]
+  int32_t* hub_xy = nullptr;     // [2 x T x T] sparse partials: p + n, then p - n
+  unsigned long long* res = nullptr;  // res[0..2] sums, res[3] dense wedges
+  int32_t T = 0;                 // rows (pairs side)
+  int32_t K = 0;                 // padded contraction length (multiple of kHubKPad)
+  // per-vertex pass only (bal != null): the completed counts X = P + N and
+  // Y = P - N of every hub pair (x, w), w below x, are stored back into
+  // hub_xy (zeros at w not below x), and each pair's C(P,2) + C(N,2) and
+  // P N are credited to both its vertices; null in the count pass
+  const int32_t* orig = nullptr;      // side rank -> input id
+  unsigned long long* bal = nullptr;  // per-vertex outputs of the side (input id order)
+  unsigned long long* unb = nullptr;
 };
 
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t st);
@@ -137,6 +144,56 @@ hipError_t launch_reduce(const ReduceArgs& a, int max_grid, hipStream_t st);
 // The dense block of up to two sides (n <= 2) in one launch; sides with
 // T = 0 are skipped.
 hipError_t launch_hub(const HubArgs* sides, int n, hipStream_t st);
+// Dense block of the per-vertex pass.
+//  - launch_pv_hub_tally: the hub pairs' sparse counts, from the plan's hub
+//    runs (one item per hub pivot x, keys (x, T)), stored as p + n and p - n
+//    into row x of hub_xy (which starts at zero).
+//  - launch_hub with bal set: completes and stores them (see HubArgs).
+//  - launch_hub_digits: the completed X and Y (upper triangle) as kHubDigits
+//    signed 7-bit digits, row-major and transposed, for the credit products.
+//  - launch_hub_credit: the credits of the block's wedges (x - y - w, y a hub
+//    mid), as products of the completed counts with the sign matrices:
+//    for the pivot-mid edge (x, y), with ZX = X B+ and ZY = Y B (B+ = |B|),
+//      2 bal = |Bm| (ZX - 2 Zc) + Bm ZY,   2 unb = |Bm| ZX - Bm ZY,
+//    Zc[x][y] = #{w > x : B[w][y] != 0}; the mid y takes the column sums;
+//    for the end-mid edge (w, y), with ZX' = X^T Bm+ and ZY' = Y^T Bm,
+//      2 bal = |B| (ZX' - 2 Zc') + B ZY',   2 unb = |B| ZX' - B ZY',
+//    Zc'[w][y] = #{x < w : Bm[x][y] != 0}.
+constexpr int kHubDigitBits = 7;  // signed digits: v = sum_k d_k 2^(7 k)
+struct HubTallyArgs {
+  const Item* items;             // hub items (keys (owner, T))
+  const Segment* segs;           // their runs
+  const uint32_t* other_adj;     // CSR entries of the other side
+  int32_t* hub_xy;               // [2 x T x T]
+  int32_t n_items;
+  int32_t T;
+  uint32_t long_len;
+};
+struct HubDigitArgs {
+  const int32_t* hub_xy;         // [2 x T x T] completed X, Y (upper triangle)
+  int8_t* rows;                  // [2 (X, Y) x D x T x T] digits, row-major (row x)
+  int8_t* cols;                  // [2 x D x T x T] digits, transposed (row w)
+  int32_t T;
+  int32_t D;                     // digits per value
+};
+struct HubCreditArgs {
+  const int8_t* A;               // [2 (X, Y) x D x T x T] digits of the left operand
+  const int8_t* Bt;              // [K x T] signs of the right operand, transposed (row y)
+  const int8_t* E;               // [T x K] signs multiplying the products: Bm (pivot-mid) or B (end-mid)
+  const int32_t* Zc;             // [T x K] the counts Zc or Zc'
+  const int32_t* pos;            // [T x K] position of edge (row, y) in the side's CSR (or -1); null: no edges
+  const int32_t* orig_mid;       // other-side rank -> input id (mid credits; null: none)
+  unsigned long long* bal_mid;   // per-vertex outputs of the other side
+  unsigned long long* unb_mid;
+  unsigned long long* ewb;       // per-edge wide credits by position in the side's CSR
+  unsigned long long* ewu;
+  int32_t T, K, D;
+  int32_t upper;                 // 1: row r contracts over t > r (pivot-mid); 0: over t < r (end-mid)
+};
+hipError_t launch_pv_hub_tally(const HubTallyArgs* sides, int n, int grid, hipStream_t st);
+hipError_t launch_hub_digits(const HubDigitArgs& a, hipStream_t st);
+hipError_t launch_hub_credit(const HubCreditArgs& a, hipStream_t st);
+
 // Per-vertex pass (plans made with per_vertex): direct items, reverse items,
 // small-item groups and hash items.
 hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st);

@@ -14,8 +14,10 @@
 // So every item is walked twice: a tally of p and n per key as in the count
 // pass, then a credit walk that reads each wedge's final p and n and adds
 // the mid's share; the sweep credits the key vertices and, summed, the
-// item's owner.  The plan of this pass has no dense block and no multi-part
-// items, so every pair's counts are complete inside one item.
+// item's owner.  The plan of this pass has no multi-part items, so every
+// pair's counts are complete inside one item -- except the hub pairs of a
+// dense block, whose completed counts the block's products leave in hub_xy
+// (hubpv.hip) before these kernels run.
 //
 // Mid credits are summed per run (a run has one mid) in registers, then per
 // batch in a per-wavefront LDS slot of the run's lane, and reach HBM as one
@@ -159,6 +161,17 @@ __device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsign
   wave_sync_lds();
 }
 
+// Completed counts of the hub pair (x, key) (dense block of the pass): the
+// block's products store X = p + n and Y = p - n in hub_xy.
+__device__ __forceinline__ void hub_counts(const DevSideConst& sc, uint32_t x, uint32_t key, uint32_t& p,
+                                           uint32_t& n) {
+  const size_t T = static_cast<size_t>(sc.T);
+  const global_t<int32_t>* h = as_global(sc.hub_xy) + x * T + key;
+  const int32_t X = h[0], Y = h[T * T];
+  p = static_cast<uint32_t>((X + Y) / 2);
+  n = static_cast<uint32_t>((X - Y) / 2);
+}
+
 // Key credits of one pair (p, n) at key vertex `key` of side s.
 struct PairCredit {
   int64_t c = 0, x = 0;  // owner sums
@@ -231,6 +244,9 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     const uint32_t lo = static_cast<uint32_t>(it.key_lo), hi = static_cast<uint32_t>(it.key_hi);
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     const bool packed = (it.flags & kItemPacked) != 0;
+    // a hub pivot's keys below T are hub pairs: their completed counts come
+    // from the dense block and their key credits were given there
+    const uint32_t hubT = (it.flags & kItemHubPairs) ? static_cast<uint32_t>(sc.T) : 0u;
     // tally (the wavefronts take the item's segments interleaved, so that
     // every wavefront gets a similar mix of long and short runs)
     for (uint32_t k0 = it.seg_begin + wave; k0 < seg_end; k0 += kPVDirectThreads) {
@@ -256,6 +272,10 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;
             if (key < lo || key >= hi) return false;
+            if (key < hubT) {
+              hub_counts(sc, static_cast<uint32_t>(it.owner), key, p, n);
+              return true;
+            }
             if (packed) {
               const uint32_t v = C[key - lo];
               p = v & 0xffffu;
@@ -281,6 +301,7 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
         C[k] = 0;
         if (!packed) N[k] = 0;
         const uint32_t key = lo + k;
+        if (key < hubT) continue;  // a hub pair: credited by the dense block
         if (key < static_cast<uint32_t>(kPVHotKeys)) {
           sums.add(p, n);
           const int64_t Pp = p, Nn = n;
@@ -460,6 +481,8 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
     const uint32_t mask = size - 1;
     const uint32_t seg_end = it.seg_begin + it.seg_count;
     auto hkey = [&](uint32_t e, uint32_t tag) { return (((tag & ~kMidWide) >> 7) << kb) | (e >> 1); };
+    // a hub pivot's group (alone in it): keys below T as in k_pv_direct
+    const uint32_t hubT = (it.flags & kItemHubPairs) ? static_cast<uint32_t>(sc.T) : 0u;
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
@@ -490,6 +513,10 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
       const SegReg sr = load_seg_pv<true, kEdge>(sc.small_segs, sc.small_seg_mid, sc.small_seg_edge, k0, k1, re);
       auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t tag, uint32_t& p, uint32_t& n) {
+            if ((e >> 1) < hubT) {
+              hub_counts(sc, static_cast<uint32_t>(it.owner), e >> 1, p, n);
+              return true;
+            }
             const uint32_t key = hkey(e, tag);
             uint32_t h = mix32(key) & mask;
             for (uint32_t probe = 0; probe <= mask; ++probe) {
@@ -516,6 +543,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
       const uint32_t v = V[h];
       K[h] = kEmpty;
       V[h] = 0;
+      if ((key & kmask) < hubT) continue;  // a hub pair: credited by the dense block
       PairCredit pc;
       pc.add(sc, key & kmask, v & 0xffffu, v >> 16, sums);
       const int32_t owner = sc.small_owner[it.acc_slot + static_cast<int32_t>(key >> kb)];

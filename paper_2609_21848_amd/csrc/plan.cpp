@@ -389,8 +389,9 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   for (int s = 0; s < 2; ++s) {
     plan.L[s] = std::min<int32_t>(p.window_L, g.side[s].n);
     plan.R[s] = std::min<int32_t>(p.reverse_L, plan.L[s]);
-    // the dense block is tiled by 128 rows; the per-vertex pass has none
-    plan.T[s] = pv ? 0 : std::min<int32_t>(p.hub_T, g.side[s].n / 128 * 128);
+    // the dense block is tiled by 128 rows (at most kMaxPVHubT in the
+    // per-vertex pass)
+    plan.T[s] = std::min<int32_t>(pv ? std::min(p.hub_T, kMaxPVHubT) : p.hub_T, g.side[s].n / 128 * 128);
   }
   // The dense path needs a block on both sides of the pair.
   if (plan.T[0] == 0 || plan.T[1] == 0) plan.T[0] = plan.T[1] = 0;
@@ -572,6 +573,57 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
       place(P, seg_begin, w, R, L, 0u, kReverseMid);
     });
     keep(std::move(rev));
+
+    // Per-vertex plans: the sparse wedges of every hub pivot toward hub
+    // endpoints, as runs of their own (the prefix below T of each of the
+    // pivot's runs through a non-hub mid).
+    if (pv && T > 0) {
+      std::vector<uint32_t> nrun(static_cast<size_t>(T) + 1, 0);
+      auto hub_runs = [&](int32_t x, auto&& emit) {
+        for (uint32_t e = S.off[x] + S.cut[x]; e < S.off[x + 1]; ++e) {
+          const uint32_t y = S.adj[e] >> 1;
+          if (static_cast<int32_t>(y) < TO) continue;  // dense wedges
+          const uint32_t start = O.off[y] + static_cast<uint32_t>(S.rev[e]) + 1;
+          const uint32_t end = O.off[y] + static_cast<uint32_t>(splitT[y]);
+          if (end > start) emit(start, end - start, e);
+        }
+      };
+      parallel_for(static_cast<size_t>(T), [&](size_t x) {
+        uint32_t c = 0;
+        hub_runs(static_cast<int32_t>(x), [&](uint32_t, uint32_t, uint32_t) { ++c; });
+        nrun[x + 1] = c;
+      });
+      for (int32_t x = 0; x < T; ++x) nrun[x + 1] += nrun[x];
+      const size_t base = plan.hub_segs.size();
+      if (base + nrun[T] > UINT32_MAX) {
+        err = "graph too large: the dense block's sparse runs exceed 2^32 - 1";
+        return DBBC_E_TOO_LARGE;
+      }
+      plan.hub_segs.resize(base + nrun[T]);
+      std::vector<Item> its(static_cast<size_t>(T));
+      parallel_for(static_cast<size_t>(T), [&](size_t x) {
+        size_t k = base + nrun[x];
+        int64_t work = 0;
+        hub_runs(static_cast<int32_t>(x), [&](uint32_t start, uint32_t len, uint32_t e) {
+          plan.hub_segs[k++] = Segment{start, (len << 1) | (S.adj[e] & 1u)};
+          work += len;
+        });
+        Item& it = its[x];
+        it = Item{};
+        it.seg_begin = static_cast<uint32_t>(base + nrun[x]);
+        it.seg_count = nrun[x + 1] - nrun[x];
+        it.owner = static_cast<int32_t>(x);
+        it.key_lo = static_cast<int32_t>(x) + 1;
+        it.key_hi = T;
+        it.acc_slot = -1;
+        it.flags = kItemHubPairs;
+        it.side = static_cast<uint32_t>(s);
+        it.work = static_cast<uint32_t>(std::min<int64_t>(work, 0xffffffffll));
+      });
+      for (const Item& it : its)
+        if (it.seg_count) plan.hub_items.push_back(it);
+      if (s == 0) plan.n_hub_side0 = static_cast<int32_t>(plan.hub_items.size());
+    }
 
     // Dense hub block of this side: B[x][y] for x < T, y < TO.
     if (T > 0) {

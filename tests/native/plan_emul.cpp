@@ -184,21 +184,27 @@ extern "C" int plan_emulate(int32_t n_u, int32_t n_v, int64_t m, const int32_t* 
 }
 
 // The per-vertex pass as the kernels take it: every item of the per-vertex
-// plan (no dense block, no parts) is tallied, then its wedges are walked
-// again to credit each mid with p - 1 (symmetric wedge) or n - 1 balanced
-// and n or p unbalanced butterflies of the pair, and each pair's
-// C(p,2) + C(n,2) and p n go to its key vertex and, summed, to the owner.
+// plan (no parts) is tallied, then its wedges are walked again to credit
+// each mid with p - 1 (symmetric wedge) or n - 1 balanced and n or p
+// unbalanced butterflies of the pair, and each pair's C(p,2) + C(n,2) and
+// p n go to its key vertex and, summed, to the owner.  With a dense block
+// (hub_T > 0): the hub items' runs are tallied first into the hub pairs'
+// sparse counts, the block's wedges (hub mids) complete them, the hub
+// pairs' key and owner credits and every credit of a block wedge are taken
+// from the completed counts (in plain loops here, by matrix products on the
+// device), and the hub items' own walks read the completed counts for hub
+// keys and leave their key credits out.
 // Outputs are per input id: bal / unb of size n_u + n_v (U first).
 extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
-                               const int8_t* sign, int32_t window_L, int32_t reverse_L, int32_t small_work,
-                               int64_t* bal, int64_t* unb, int64_t* bal_e, int64_t* unb_e,
-                               int64_t* out /* 4 */) {
+                               const int8_t* sign, int32_t hub_T, int32_t window_L, int32_t reverse_L,
+                               int32_t small_work, int64_t* bal, int64_t* unb, int64_t* bal_e, int64_t* unb_e,
+                               int64_t* out /* 5 */) {
   HostGraph g;
   std::string err;
   int rc = build_host_graph(n_u, n_v, m, u, v, sign, 0, g, err);
   if (rc) return rc;
   PlanParams p = default_params(g);
-  p.hub_T = 0;
+  if (hub_T >= 0) p.hub_T = hub_T;
   if (window_L >= 0) p.window_L = window_L;
   if (reverse_L >= 0) p.reverse_L = reverse_L;
   if (small_work >= 0) p.small_work = small_work;
@@ -224,10 +230,79 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
   const int64_t base[2] = {0, n_u};
   Acc acc;
   auto id = [&](int s, uint32_t sr) { return base[s] + g.side[s].orig[sr]; };
+  // position of the edge (x, y) in side s's CSR (x of side s, y of the other)
+  auto pos_of = [&](int s, uint32_t x, uint32_t y) -> uint32_t {
+    const HostSide& S = g.side[s];
+    for (uint32_t q = S.off[x]; q < S.off[x + 1]; ++q)
+      if ((S.adj[q] >> 1) == y) return q;
+    return 0xffffffffu;
+  };
+  // Dense block: hub pairs' counts (sparse tally of the hub runs, then the
+  // block's wedges), their key and owner credits, and the credits of every
+  // block wedge (mid, pivot-mid edge, end-mid edge).
+  std::map<std::tuple<int, int, int>, std::pair<int64_t, int64_t>> hubpn;  // (side, x, w) -> (P, N)
+  for (const Item& it : plan.hub_items) {
+    if (!(it.flags & kItemHubPairs) || it.owner >= plan.T[it.side]) return -130;
+    const HostSide& O = g.side[1 - it.side];
+    for (uint32_t k = it.seg_begin; k < it.seg_begin + it.seg_count; ++k) {
+      const Segment sg = plan.hub_segs[k];
+      for (uint32_t t = 0; t < (sg.len_g >> 1); ++t) {
+        const uint32_t e = O.adj[sg.start + t];
+        const int32_t key = (int32_t)(e >> 1);
+        if (key <= it.owner || key >= plan.T[it.side]) return -131;  // hub runs hold hub keys only
+        auto& pn = hubpn[{(int)it.side, it.owner, key}];
+        (((e ^ sg.len_g) & 1u) == 0 ? pn.first : pn.second)++;
+      }
+    }
+  }
+  for (int s = 0; s < 2 && plan.T[0] > 0; ++s) {
+    const int32_t T = plan.T[s], TO = plan.T[1 - s];
+    const std::vector<int8_t>& B = plan.hub_B[s];
+    const std::vector<int8_t>& Bm = plan.hub_Bm[s];
+    for (int32_t x = 0; x < T; ++x)
+      for (int32_t w = x + 1; w < T; ++w)
+        for (int32_t y = 0; y < TO; ++y) {
+          const int8_t a = Bm[(size_t)x * TO + y], b = B[(size_t)w * TO + y];
+          if (a && b) (a == b ? hubpn[{s, x, w}].first : hubpn[{s, x, w}].second)++;
+        }
+    for (int32_t x = 0; x < T; ++x)
+      for (int32_t w = x + 1; w < T; ++w) {
+        auto f = hubpn.find({s, x, w});
+        if (f == hubpn.end()) continue;
+        const int64_t P = f->second.first, N = f->second.second;
+        const int64_t cb = P * (P - 1) / 2 + N * (N - 1) / 2, cu = P * N;
+        acc.add(P, N);
+        bal[id(s, x)] += cb;
+        unb[id(s, x)] += cu;
+        bal[id(s, w)] += cb;
+        unb[id(s, w)] += cu;
+        for (int32_t y = 0; y < TO; ++y) {
+          const int8_t a = Bm[(size_t)x * TO + y], b = B[(size_t)w * TO + y];
+          if (!a || !b) continue;
+          const bool sym = a == b;
+          const int64_t wb = sym ? P - 1 : N - 1, wu = sym ? N : P;
+          bal[id(1 - s, y)] += wb;
+          unb[id(1 - s, y)] += wu;
+          if (bal_e) {
+            const int64_t r0 = rec(s, pos_of(s, x, y)), r1 = rec(s, pos_of(s, w, y));
+            bal_e[r0] += wb;
+            unb_e[r0] += wu;
+            bal_e[r1] += wb;
+            unb_e[r1] += wu;
+          }
+        }
+      }
+  }
+  // the completed counts of a hub pair (x, key) of side `side`
+  auto hub_lookup = [&](int side, int32_t x, int32_t key, int64_t& P, int64_t& N) {
+    auto f = hubpn.find({side, x, key});
+    P = f == hubpn.end() ? 0 : f->second.first;
+    N = f == hubpn.end() ? 0 : f->second.second;
+  };
   // one item: runs [b, b + c) of segs / mids, key filter, owner lookup
   auto run = [&](int side, const Segment* segs, const uint32_t* mids, const uint32_t* edges, uint32_t b,
                  uint32_t c, int32_t lo, int32_t hi, bool tagged, const int32_t* owners, int32_t owner,
-                 int32_t maxcnt) -> int {
+                 int32_t maxcnt, bool hub_item) -> int {
     const HostSide& O = g.side[1 - side];
     std::map<std::pair<uint32_t, uint32_t>, std::pair<int64_t, int64_t>> cnt;  // (local, key)
     for (int pass = 0; pass < 2; ++pass) {
@@ -243,12 +318,17 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
             continue;  // another key window of the same runs
           }
           const bool sym = ((e ^ gb) & 1u) == 0;
+          // a hub pair's wedge: its counts are the completed ones
+          const bool hubkey = hub_item && key < plan.T[side];
+          if (hubkey && pass == 0) continue;
           auto& pn = cnt[{local, (uint32_t)key}];
           if (pass == 0) {
             (sym ? pn.first : pn.second)++;
           } else {
+            int64_t Pk = pn.first, Nk = pn.second;
+            if (hubkey) hub_lookup(side, owners ? owners[local] : owner, key, Pk, Nk);
             const int64_t mid = id(1 - side, mids[k] & ~kMidWide);
-            const int64_t cb = sym ? pn.first - 1 : pn.second - 1, cu = sym ? pn.second : pn.first;
+            const int64_t cb = sym ? Pk - 1 : Nk - 1, cu = sym ? Nk : Pk;
             bal[mid] += cb;
             unb[mid] += cu;
             if (bal_e) {  // the run's first edge and the walked entry's edge
@@ -264,6 +344,7 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
     }
     std::map<uint32_t, std::pair<int64_t, int64_t>> own;  // per local: owner sums
     for (auto& [lk, pn] : cnt) {
+      if (hub_item && (int32_t)lk.second < plan.T[side]) continue;  // credited by the dense block
       if (pn.first > maxcnt || pn.second > maxcnt) return -123;
       const int64_t P = pn.first, N = pn.second;
       const int64_t cb = P * (P - 1) / 2 + N * (N - 1) / 2, cu = P * N;
@@ -287,20 +368,25 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
           it.key_hi - it.key_lo > ((it.flags & kItemPacked) ? kPVWindowPacked : kPVWindow))
         return -124;
       if ((it.flags & kItemPacked) && it.seg_count >= 65536) return -126;
+      if ((it.flags & kItemHubPairs) && list != &plan.direct_items) return -132;  // hub items are direct or small
       if ((rc = run(it.side, plan.segs.data(), plan.seg_mid.data(), plan.seg_edge.data(), it.seg_begin,
-                    it.seg_count, it.key_lo, it.key_hi, false, nullptr, it.owner, lim)))
+                    it.seg_count, it.key_lo, it.key_hi, false, nullptr, it.owner, lim,
+                    (it.flags & kItemHubPairs) != 0)))
         return rc;
     }
   for (const Item& grp : plan.small_groups) {
+    const bool hub = (grp.flags & kItemHubPairs) != 0;
+    if (hub && grp.key_hi != 1) return -133;  // a hub item is alone in its group
     if ((rc = run(grp.side, plan.small_segs.data(), plan.small_seg_mid.data(), plan.small_seg_edge.data(),
                   grp.seg_begin, grp.seg_count, 0, INT32_MAX - 1, true, plan.small_owner.data() + grp.acc_slot, 0,
-                  65535)))
+                  65535, hub)))
       return rc;
   }
   out[0] = acc.bal;
   out[1] = acc.unb;
   out[2] = acc.tot;
   out[3] = g.wedges_vp;
+  out[4] = plan.T[0];
   return 0;
 }
 

@@ -197,11 +197,37 @@ def test_crossing_hubs_packed_and_wide_credits(dbbc):
     _say("crossing hubs pe", n_u, n_v, u.shape[0])
     r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, per_edge=True)
     with dbbc.Graph(n_u, n_v, u, v, s) as h:
-        c, be, ue = h.count_per_edge()
-        assert (c.balanced, c.unbalanced, c.total, c.wedges) == (r.balanced, r.unbalanced, r.total,
-                                                                 r.wedges)
-        assert np.array_equal(be.cpu().numpy(), r.bal_e)
-        assert np.array_equal(ue.cpu().numpy(), r.unb_e)
-        _, bu, bv, uu, uv = h.count_per_vertex()
-        for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
-            assert np.array_equal(t.cpu().numpy(), want)
+        # without and with a dense block (which holds both hubs: pair counts
+        # of three 7-bit digits in its products)
+        for opts in ({"hub_T": 0}, {"hub_T": 256}):
+            c, be, ue = h.count_per_edge(**opts)
+            assert (c.balanced, c.unbalanced, c.total, c.wedges) == (r.balanced, r.unbalanced, r.total,
+                                                                     r.wedges)
+            assert np.array_equal(be.cpu().numpy(), r.bal_e), opts
+            assert np.array_equal(ue.cpu().numpy(), r.unb_e), opts
+            _, bu, bv, uu, uv = h.count_per_vertex(**opts)
+            for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
+                assert np.array_equal(t.cpu().numpy(), want), opts
+
+
+def test_dense_block_sweep(dbbc):
+    """The dense block in the per-edge pass: hub_T in {0, 128, ..., 4096},
+    every edge against the oracle (the block's edges take their pivot-mid
+    and end-mid credits from the credit products)."""
+    g = chung_lu_graph(9000, 8000, 200000, 2.0, 1.9, 0.4, seed=41)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_edge=True)
+    with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
+        for opts in ({"hub_T": 0}, {"hub_T": 128}, {"hub_T": 384}, {"hub_T": 1024},
+                     {"hub_T": 2048, "window_L": 2048, "reverse_L": 512}, {"hub_T": 4096},
+                     {"hub_T": 256, "flags": WIDE}):
+            _say("dense-block pe", opts)
+            c, be, ue = h.count_per_edge(**opts)
+            assert (c.balanced, c.unbalanced, c.total) == (r.balanced, r.unbalanced, r.total), opts
+            assert np.array_equal(be.cpu().numpy(), r.bal_e), opts
+            assert np.array_equal(ue.cpu().numpy(), r.unb_e), opts
+
+
+def test_dense_block_on_dense_graph(dbbc):
+    g = chung_lu_graph(1200, 1000, 300000, 3.0, 3.0, 0.45, seed=9)
+    _say("dense-block pe dense graph")
+    _check(dbbc, g, ({"hub_T": 512}, {"hub_T": 1024, "window_L": 1024, "reverse_L": 256}))

@@ -125,3 +125,27 @@ def test_skewed50m_invariants(dbbc):
     digests = cache["local"]["sha256"]
     for name, arr in (("bal_u", bu), ("bal_v", bv), ("unb_u", uu), ("unb_v", uv)):
         assert _digest(arr) == digests[name], f"{name} differs from the oracle's"
+
+
+def test_dense_block_sweep(dbbc):
+    """The dense block in the per-vertex pass: hub_T in {0, 128, ..., 4096},
+    every vertex against the oracle (the hub pairs' counts completed by the
+    block's products, their credits and the hub mids' credits computed by
+    the credit products, the rest by the sparse kernels)."""
+    g = chung_lu_graph(9000, 8000, 200000, 2.0, 1.9, 0.4, seed=41)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True)
+    with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
+        for opts in ({"hub_T": 0}, {"hub_T": 128}, {"hub_T": 384}, {"hub_T": 1024},
+                     {"hub_T": 2048, "window_L": 2048, "reverse_L": 512}, {"hub_T": 4096},
+                     {"hub_T": 256, "window_L": 256, "reverse_L": 64, "small_work": 2}):
+            _say("dense-block pv", opts)
+            c, bu, bv, uu, uv = h.count_per_vertex(**opts)
+            assert (c.balanced, c.unbalanced, c.total) == (r.balanced, r.unbalanced, r.total), opts
+            for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
+                assert np.array_equal(t.cpu().numpy(), want), opts
+
+
+def test_dense_block_on_dense_graph(dbbc):
+    g = chung_lu_graph(1200, 1000, 300000, 3.0, 3.0, 0.45, seed=9)
+    _say("dense-block pv dense graph")
+    _check(dbbc, g, ({"hub_T": 512}, {"hub_T": 1024, "window_L": 1024, "reverse_L": 256}))

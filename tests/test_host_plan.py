@@ -115,19 +115,19 @@ def emul_pv(tmp_path_factory):
                            os.path.join(ROOT, "tests", "native", "host_build.cpp"), os.path.join(CSRC, "plan.cpp")])
     lib = ctypes.CDLL(so)
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
-    lib.plan_emulate_pv.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, p, p, p, p, p]
+    lib.plan_emulate_pv.argtypes = [i32, i32, i64, p, p, p, i32, i32, i32, i32, p, p, p, p, p]
 
-    def run(g, L=-1, R=-1, sw=-1, edges=False):
+    def run(g, L=-1, R=-1, sw=-1, edges=False, T=0):
         n = g.n_u + g.n_v
         bal = np.zeros(n, np.int64)
         unb = np.zeros(n, np.int64)
         be = np.zeros(g.m, np.int64) if edges else None
         ue = np.zeros(g.m, np.int64) if edges else None
-        out = np.zeros(4, np.int64)
+        out = np.zeros(5, np.int64)
         if R < 0 and L >= 0:
             R = min(L, 4096)
         rc = lib.plan_emulate_pv(g.n_u, g.n_v, g.m, g.u.ctypes.data, g.v.ctypes.data,
-                                 g.sign.ctypes.data, L, R, sw, bal.ctypes.data, unb.ctypes.data,
+                                 g.sign.ctypes.data, T, L, R, sw, bal.ctypes.data, unb.ctypes.data,
                                  None if be is None else be.ctypes.data,
                                  None if ue is None else ue.ctypes.data, out.ctypes.data)
         assert rc == 0, rc
@@ -206,3 +206,31 @@ def test_plan_size_guard(emul_lib):
     assert f(0, 0, i32 + 1, 0) == -7
     assert f(0, 0, 0, i32 + 1) == -7
     assert f(0, 0, 0, 0) == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_per_vertex_plan_with_dense_block(emul_pv, seed):
+    """Per-vertex and per-edge plans with a dense block: hub runs, completed
+    hub-pair counts, block-wedge credits and the hub items' walks give the
+    oracle's counts."""
+    rng = np.random.default_rng(130 + seed)
+    g = chung_lu_graph(int(rng.integers(600, 2500)), int(rng.integers(600, 2500)),
+                       int(rng.integers(8000, 40000)), 2.0, 1.9, 0.4, seed=seed)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True, per_edge=True)
+    for T, L, R, sw in [(128, -1, -1, -1), (256, 256, 64, 2), (128, 512, 512, 64), (256, 1024, 128, 512)]:
+        out, bal, unb, be, ue = emul_pv(g, L, R, sw, edges=True, T=T)
+        assert out[4] == T
+        assert (out[0], out[1], out[2]) == (r.balanced, r.unbalanced, r.total), (T, L, R, sw)
+        assert np.array_equal(bal, np.concatenate([r.bal_u, r.bal_v])), (T, L, R, sw)
+        assert np.array_equal(unb, np.concatenate([r.unb_u, r.unb_v])), (T, L, R, sw)
+        assert np.array_equal(be, r.bal_e) and np.array_equal(ue, r.unb_e), (T, L, R, sw)
+
+
+def test_per_vertex_plan_dense_block_on_dense_graph(emul_pv):
+    g = chung_lu_graph(600, 500, 150000, 3.0, 3.0, 0.45, seed=9)
+    r = vp_counts(g.n_u, g.n_v, g.u, g.v, g.sign, per_vertex=True, per_edge=True)
+    for T, L, R in [(128, 256, 64), (256, 512, 256), (256, -1, -1)]:
+        out, bal, unb, be, ue = emul_pv(g, L, R, edges=True, T=T)
+        assert np.array_equal(bal, np.concatenate([r.bal_u, r.bal_v]))
+        assert np.array_equal(unb, np.concatenate([r.unb_u, r.unb_v]))
+        assert np.array_equal(be, r.bal_e) and np.array_equal(ue, r.unb_e)
