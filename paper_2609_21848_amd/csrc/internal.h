@@ -127,9 +127,10 @@ constexpr int32_t kMaxPVHubT = 4096;
 
 // Key window of a direct item of the per-vertex pass (32-bit counters in
 // LDS); wider windows are split into items that share their runs.
-constexpr int32_t kPVWindow = 8192;
+constexpr int32_t kPVWindow = 16384;
 // Items with fewer than 2^16 runs (so p, n < 2^16 for every key) pack p and
-// n into one 32-bit word and take twice the window.
+// n into one 32-bit word and take twice the window (the largest window_L:
+// one walk per pivot).
 constexpr int32_t kPVWindowPacked = 2 * kPVWindow;
 
 // Flag in a per-vertex plan's run mid (seg_mid, small_seg_mid): the mid's

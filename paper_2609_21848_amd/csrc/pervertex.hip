@@ -67,7 +67,6 @@ __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
   if (kEdge) {
     re.edge = in ? as_global(edges)[k] : 0u;
     re.wide = m & kMidWide;
-    r.tag |= re.wide;  // the run's wedges carry the flag to the credit walk
   }
   return r;
 }
@@ -77,7 +76,7 @@ __device__ __forceinline__ SegReg load_seg_pv(const Segment* __restrict__ segs,
 // lane's current run are kept in registers and added to the run's LDS slot
 // when the lane moves to another run; with kEdge every wedge's share is
 // also added to the walked entry's edge (by entry position: packed in ep,
-// or in wb and wu for a wide run).
+// or in wb and wu for a wide run: bit j of `wide` for the run of lane j).
 // Non-returning 64-bit add to global memory (device scope).
 __device__ __forceinline__ void add_global(global_t<unsigned long long>* p, unsigned long long v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -91,6 +90,7 @@ struct Credit {
   global_t<unsigned long long>* ep;
   global_t<unsigned long long>* wb;
   global_t<unsigned long long>* wu;
+  uint64_t wide = 0;  // runs (by lane) whose credits take two words
   uint32_t cur = 0xffffffffu;
   unsigned long long sb = 0, su = 0;
   __device__ __forceinline__ void put() {
@@ -114,7 +114,7 @@ struct Credit {
     sb += b;
     su += u;
     if (kEdge) {
-      if (tag & kMidWide) {
+      if ((wide >> j) & 1u) {
         if (b) add_global(wb + pos, b);
         if (u) add_global(wu + pos, u);
       } else if (b | u) {
@@ -130,8 +130,9 @@ struct Credit {
 
 template <bool kEdge, class Look>
 __device__ __forceinline__ Credit<Look, kEdge> credit(Look l, unsigned long long* cb, unsigned long long* cu,
-                                                      const DevSideConst& sc) {
+                                                      const DevSideConst& sc, const RunEnds& re) {
   Credit<Look, kEdge> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
+  if (kEdge) c.wide = __ballot(re.wide != 0);
   return c;
 }
 
@@ -199,34 +200,33 @@ struct PairCredit {
 // Direct items: one workgroup per item, p and n counters over the item's
 // key window, 32-bit each (at most kPVWindow keys) or, for items with fewer
 // than 2^16 runs (kItemPacked), 16|16 bits in one word (at most
-// kPVWindowPacked keys); windows of one pivot share their runs and skip the
-// keys of the others.  Credits of keys below
-// kPVHotKeys (the side's highest-priority vertices, the keys of most items)
-// are summed per workgroup in LDS and reach HBM once per workgroup; a launch
-// holds the items of one side.
+// kPVWindowPacked keys, the whole window of the count pass, so a pivot's
+// runs are walked once per walk); windows of one pivot share their runs and
+// skip the keys of the others.  The walks stage short runs in the run-table
+// form (a 64-entry table per wavefront), which leaves the LDS to the
+// counters.  Key credits are global atomics (the keys that many items
+// share, a side's top vertices, are the dense block's when it is on).
 constexpr int kPVDirectThreads = 1024;
-constexpr int kPVHotKeys = 2048;
 constexpr int kPVDirectWaves = kPVDirectThreads / kWave;
 
 template <bool kEdge>
 __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
-  __shared__ uint32_t C[2 * kPVWindow];  // P | N, or packed words
-  __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVDirectWaves][kGather];
-  __shared__ uint32_t mflag[kPVDirectWaves][kGather];
+  __shared__ uint32_t C[kPVWindowPacked];  // P | N, or packed words
+  __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVDirectWaves][2 * kWave];
+  __shared__ uint8_t mflag[kPVDirectWaves][kGather];
   __shared__ unsigned long long cb[kPVDirectWaves][kWave], cu[kPVDirectWaves][kWave];
-  __shared__ unsigned long long hbal[kPVHotKeys], hunb[kPVHotKeys];
   __shared__ int32_t item_sh;
+  static_assert(2 * kPVWindow == kPVWindowPacked, "P | N halves fill the packed window");
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int lane = lane_id();
-  for (int i = tid; i < 2 * kPVWindow; i += kPVDirectThreads) C[i] = 0;
+  for (int i = tid; i < kPVWindowPacked; i += kPVDirectThreads) C[i] = 0;
   uint32_t* const P = C;
   uint32_t* const N = C + kPVWindow;
-  for (int i = tid; i < kPVHotKeys; i += kPVDirectThreads) hbal[i] = hunb[i] = 0;
   for (int i = tid; i < kPVDirectWaves * static_cast<int>(kGather); i += kPVDirectThreads) (&mflag[0][0])[i] = 0;
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
-  const Marks<uint32_t> mk{mtab[wave], mflag[wave]};
+  const Marks<uint8_t> mk{mtab[wave], mflag[wave]};
   Sums sums;
   uint32_t graph = kNoGraph;
   for (;;) {
@@ -253,15 +253,16 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
       RunEnds re;
       const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, seg_end, re, kPVDirectWaves);
       if (packed)
-        walk_regs<4>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
-                       const uint32_t key = e >> 1;
-                       if (key >= lo && key < hi) atomicAdd(&C[key - lo], wedge_inc(e, tag));
-                     }));
+        walk_regs<4, false, true>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
+                                    const uint32_t key = e >> 1;
+                                    if (key >= lo && key < hi) atomicAdd(&C[key - lo], wedge_inc(e, tag));
+                                  }));
       else
-        walk_regs<4>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
-                       const uint32_t key = e >> 1;
-                       if (key >= lo && key < hi) atomicAdd(((e ^ tag) & 1u) ? &N[key - lo] : &P[key - lo], 1u);
-                     }));
+        walk_regs<4, false, true>(sr, sc.other_adj, mk, a.long_len, hash_tally([&](uint32_t e, uint32_t tag) {
+                                    const uint32_t key = e >> 1;
+                                    if (key >= lo && key < hi)
+                                      atomicAdd(((e ^ tag) & 1u) ? &N[key - lo] : &P[key - lo], 1u);
+                                  }));
     }
     __syncthreads();
     // credit the mids
@@ -286,8 +287,8 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
             }
             return true;
           },
-          cb[wave], cu[wave], sc);
-      walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
+          cb[wave], cu[wave], sc, re);
+      walk_regs<4, kEdge, true>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
@@ -302,34 +303,13 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
         if (!packed) N[k] = 0;
         const uint32_t key = lo + k;
         if (key < hubT) continue;  // a hub pair: credited by the dense block
-        if (key < static_cast<uint32_t>(kPVHotKeys)) {
-          sums.add(p, n);
-          const int64_t Pp = p, Nn = n;
-          const int64_t cb2 = Pp * (Pp - 1) / 2 + Nn * (Nn - 1) / 2, cx = Pp * Nn;
-          if (cb2) atomicAdd(&hbal[key], static_cast<unsigned long long>(cb2));
-          if (cx) atomicAdd(&hunb[key], static_cast<unsigned long long>(cx));
-          pc.c += cb2;
-          pc.x += cx;
-        } else {
-          pc.add(sc, key, p, n, sums);
-        }
+        pc.add(sc, key, p, n, sums);
       }
     }
     pc.to_owner(sc, it.owner);
     __syncthreads();
   }
   if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
-  // the workgroup's hot-key credits (all items of a launch are of one side)
-  __syncthreads();
-  if (a.n_items > 0) {
-    const Item i0 = load_const(a.items, 0);
-    const DevSideConst sc = load_const(a.sides, 2 * i0.graph + i0.side);
-    for (int k = tid; k < kPVHotKeys; k += kPVDirectThreads) {
-      const unsigned long long b = hbal[k], u = hunb[k];
-      if (b) atomicAdd(&sc.bal[sc.orig[k]], b);
-      if (u) atomicAdd(&sc.unb[sc.orig[k]], u);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -337,9 +317,11 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
 // p and n per key over the reverse window, two keys per 32-bit word.  The
 // keys are the reverse window's vertices, shared by every item of a side, so
 // their credits are summed per workgroup in LDS and reach HBM once per
-// workgroup at the end (a launch holds the items of one side).
-constexpr int kPVReverseThreads = 512;
-constexpr int kPVReverseWaves = kPVReverseThreads / kWave;
+// workgroup at the end (a launch holds the items of one side).  A pair's
+// credit is below 2^15 (p + n <= 255), so the workgroup's 32-bit key sums
+// hold up to 2^16 items (the launch sizes its grid for that).
+constexpr int kPVReverseWaves = 12;
+constexpr int kPVReverseThreads = kPVReverseWaves * kWave;
 constexpr int kPVReverseWords = kMaxReverseL / 2;
 
 template <bool kEdge>
@@ -349,9 +331,9 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ __attribute__((aligned(kPVReverseWords * 4))) uint32_t cnt[kPVReverseWaves][kPVReverseWords];
   __shared__ uint32_t dummies[kPVReverseWaves][kWave];
   __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVReverseWaves][kGather];
-  __shared__ uint32_t mflag[kPVReverseWaves][kGather];
+  __shared__ uint8_t mflag[kPVReverseWaves][kGather];
   __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
-  __shared__ unsigned long long kbal[kMaxReverseL], kunb[kMaxReverseL];
+  __shared__ uint32_t kbal[kMaxReverseL], kunb[kMaxReverseL];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
@@ -363,7 +345,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
   wave_sync_lds();
-  const Marks<uint32_t> mk{mtab[wave], mflag[wave]};
+  const Marks<uint8_t> mk{mtab[wave], mflag[wave]};
   Sums sums;
   uint32_t graph = kNoGraph;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVReverseWaves;
@@ -395,30 +377,41 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
             n = (h >> 8) & 0xffu;
             return true;
           },
-          cb[wave], cu[wave], sc);
+          cb[wave], cu[wave], sc, re);
       walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
-    PairCredit pc;
+    // the key credits: 16-byte reads of the counter words, quads of zero
+    // words skipped; a pair with one wedge adds nothing
+    int64_t oc = 0, ox = 0;  // owner sums
     auto local = [&](uint32_t key, uint32_t p, uint32_t n) {
       sums.add(p, n);
-      const int64_t P = p, N = n;
-      const int64_t cb2 = P * (P - 1) / 2 + N * (N - 1) / 2, cx = P * N;
-      if (cb2) atomicAdd(&kbal[key], static_cast<unsigned long long>(cb2));
-      if (cx) atomicAdd(&kunb[key], static_cast<unsigned long long>(cx));
-      pc.c += cb2;
-      pc.x += cx;
+      const uint32_t cb2 = p * (p - 1) / 2 + n * (n - 1) / 2, cx = p * n;
+      if (cb2) atomicAdd(&kbal[key], cb2);
+      if (cx) atomicAdd(&kunb[key], cx);
+      oc += cb2;
+      ox += cx;
     };
     const int32_t w_hi = (it.key_hi + 1) >> 1;
-    for (int32_t wd = lane; wd < w_hi; wd += kWave) {
-      const uint32_t c2 = C[wd];
-      if (!c2) continue;
-      C[wd] = 0;
-      if (c2 & 0xffffu) local(2 * wd, c2 & 0xffu, (c2 >> 8) & 0xffu);
-      if (c2 >> 16) local(2 * wd + 1, (c2 >> 16) & 0xffu, c2 >> 24);
+    for (int32_t w0 = 4 * lane; w0 < w_hi; w0 += 4 * kWave) {
+      const uint4 c4 = *reinterpret_cast<const uint4*>(&C[w0]);
+      if ((c4.x | c4.y | c4.z | c4.w) == 0) continue;
+      *reinterpret_cast<uint4*>(&C[w0]) = make_uint4(0, 0, 0, 0);
+      const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t c2 = cw[q];
+        const uint32_t wd = static_cast<uint32_t>(w0 + q);
+        if (c2 & 0xffffu) local(2 * wd, c2 & 0xffu, (c2 >> 8) & 0xffu);
+        if (c2 >> 16) local(2 * wd + 1, (c2 >> 16) & 0xffu, c2 >> 24);
+      }
     }
-    pc.to_owner(sc, it.owner);
+    const int64_t oc2 = wave_sum64(oc), ox2 = wave_sum64(ox);
+    if (lane == 0) {
+      if (oc2) atomicAdd(&sc.bal[sc.orig[it.owner]], static_cast<unsigned long long>(oc2));
+      if (ox2) atomicAdd(&sc.unb[sc.orig[it.owner]], static_cast<unsigned long long>(ox2));
+    }
     wave_sync_lds();
   }
   if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
@@ -429,9 +422,9 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     const DevSideConst sc = load_const(a.sides, 2 * i0.graph + i0.side);
     const int32_t nkeys = sc.R < kMaxReverseL ? sc.R : kMaxReverseL;
     for (int k = threadIdx.x; k < nkeys; k += kPVReverseThreads) {
-      const unsigned long long b = kbal[k], u = kunb[k];
-      if (b) atomicAdd(&sc.bal[sc.orig[k]], b);
-      if (u) atomicAdd(&sc.unb[sc.orig[k]], u);
+      const uint32_t b = kbal[k], u = kunb[k];
+      if (b) atomicAdd(&sc.bal[sc.orig[k]], static_cast<unsigned long long>(b));
+      if (u) atomicAdd(&sc.unb[sc.orig[k]], static_cast<unsigned long long>(u));
     }
   }
 }
@@ -531,7 +524,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
             atomicOr(a.err, kErrHashFull);  // a tallied key must be there
             return false;
           },
-          cb[wave], cu[wave], sc);
+          cb[wave], cu[wave], sc, re);
       walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
@@ -661,7 +654,7 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
               atomicOr(a.err, kErrHashFull);
               return false;
             },
-            cb[wave], cu[wave], sc);
+            cb[wave], cu[wave], sc, re);
         walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
         c.flush();
         flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
@@ -717,6 +710,10 @@ hipError_t direct_(const DirectArgs& a, int grid, hipStream_t st) {
 template <bool kEdge>
 hipError_t reverse_(const SmallArgs& a, int grid, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
+  // at most 2^16 items per workgroup (its 32-bit key sums)
+  const int64_t per = int64_t{1} << 16;
+  const int64_t need = (static_cast<int64_t>(a.n_items) + per - 1) / per;
+  if (grid < need) grid = static_cast<int>(need);
   hipLaunchKernelGGL(dev::k_pv_reverse<kEdge>, dim3(grid), dim3(dev::kPVReverseThreads), 0, st, a);
   return hipGetLastError();
 }
