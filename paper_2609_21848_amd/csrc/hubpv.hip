@@ -42,9 +42,10 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
-// Hub tally: one workgroup per hub pivot x, 32-bit p and n per hub endpoint
-// in LDS, the pivot's hub runs walked by its wavefronts, then row x of the
-// two planes written (p + n, p - n) for the endpoints w in (x, T).
+// Hub tally: one workgroup per hub item (a hub pivot x, or a part of a heavy
+// one), 32-bit p and n per hub endpoint in LDS, the item's hub runs walked
+// by its wavefronts, then its counts added into row x of the two planes
+// (p + n, p - n) for the endpoints w in (x, T) (the planes start at zero).
 constexpr int kHubTallyThreads = 256;
 constexpr int kHubTallyWaves = kHubTallyThreads / kWave;
 
@@ -73,13 +74,14 @@ __global__ __launch_bounds__(kHubTallyThreads) void k_pv_hub_tally(HubTallyArgs 
     }
     __syncthreads();
     const uint32_t x = static_cast<uint32_t>(it.owner);
-    global_t<int32_t>* row = as_global(a.hub_xy) + static_cast<size_t>(x) * T;
+    int32_t* row = a.hub_xy + static_cast<size_t>(x) * T;
     for (uint32_t w = x + 1 + tid; w < T; w += kHubTallyThreads) {
       const uint32_t p = P[w], n = N[w];
+      if (!(p | n)) continue;
       P[w] = 0;
       N[w] = 0;
-      row[w] = static_cast<int32_t>(p + n);
-      row[TT + w] = static_cast<int32_t>(p) - static_cast<int32_t>(n);
+      atomicAdd(&row[w], static_cast<int32_t>(p + n));
+      atomicAdd(&row[TT + w], static_cast<int32_t>(p) - static_cast<int32_t>(n));
     }
     __syncthreads();
   }

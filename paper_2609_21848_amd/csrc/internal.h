@@ -124,6 +124,8 @@ constexpr int32_t kMaxReverseL = 4096;
 // Largest dense block of the per-vertex pass: the hub tally keeps 32-bit p
 // and n per hub endpoint in LDS.
 constexpr int32_t kMaxPVHubT = 4096;
+// Work of one part of a hub pivot's tally (parts of one pivot add into its row).
+constexpr int64_t kHubTallyPartWork = int64_t{1} << 16;
 
 // Key window of a direct item of the per-vertex pass (32-bit counters in
 // LDS); wider windows are split into items that share their runs.
@@ -181,7 +183,8 @@ struct HostPlan {
   // item each, both sides, side 0 first), the runs of its sparse wedges
   // toward hub endpoints w < T[s] (mids y >= T[1 - s]), so that a tally of
   // these alone gives the hub pairs' sparse counts before the dense block
-  // completes them; the items' keys are [x + 1, T[s])
+  // completes them; the items' keys are [x + 1, T[s]); a heavy pivot's runs
+  // are split over several items (parts) of the same owner
   std::vector<Segment> hub_segs;
   std::vector<Item> hub_items;
   int32_t n_hub_side0 = 0;

@@ -82,37 +82,28 @@ __device__ __forceinline__ void add_global(global_t<unsigned long long>* p, unsi
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class Look, bool kEdge>
+template <class Look, bool kEdge, class Acc>
 struct Credit {
   Look look;
-  unsigned long long* cb;  // per-wavefront LDS: balanced credit per run lane
-  unsigned long long* cu;  // unbalanced
+  Acc* cb;  // per-wavefront LDS: balanced credit per run lane
+  Acc* cu;  // unbalanced
   global_t<unsigned long long>* ep;
   global_t<unsigned long long>* wb;
   global_t<unsigned long long>* wu;
   uint64_t wide = 0;  // runs (by lane) whose credits take two words
-  uint32_t cur = 0xffffffffu;
-  unsigned long long sb = 0, su = 0;
-  __device__ __forceinline__ void put() {
-    if (cur != 0xffffffffu) {
-      if (sb) atomicAdd(&cb[cur], sb);
-      if (su) atomicAdd(&cu[cur], su);
-    }
-    sb = su = 0;
-  }
-  __device__ __forceinline__ void add(uint32_t e, uint32_t tag, bool valid, uint32_t pos) {
+  uint32_t cur = 0xffffffffu;  // the run of the chunk slots summed in sb, su (wave-uniform)
+  Acc sb = 0, su = 0;
+  // the wedge's shares: balanced b and unbalanced u (false: not a wedge of
+  // this item or pass)
+  __device__ __forceinline__ bool share(uint32_t e, uint32_t tag, bool valid, uint32_t& b, uint32_t& u) {
     uint32_t p, n;
-    if (!valid || !look(e, tag, p, n)) return;
-    const uint32_t j = (tag >> 1) & 63u;
-    if (j != cur) {
-      put();
-      cur = j;
-    }
+    if (!valid || !look(e, tag, p, n)) return false;
     const bool sym = ((e ^ tag) & 1u) == 0;
-    const uint32_t b = sym ? p - 1u : n - 1u;
-    const uint32_t u = sym ? n : p;
-    sb += b;
-    su += u;
+    b = sym ? p - 1u : n - 1u;
+    u = sym ? n : p;
+    return true;
+  }
+  __device__ __forceinline__ void edge(uint32_t j, uint32_t pos, uint32_t b, uint32_t u) {
     if (kEdge) {
       if ((wide >> j) & 1u) {
         if (b) add_global(wb + pos, b);
@@ -122,25 +113,55 @@ struct Credit {
       }
     }
   }
+  __device__ __forceinline__ void put() {
+    if (cur != 0xffffffffu) {
+      if (sb) atomicAdd(&cb[cur], sb);
+      if (su) atomicAdd(&cu[cur], su);
+    }
+    sb = su = 0;
+  }
+  // a staged position (lanes in different runs): its shares straight to its
+  // run's LDS slot
+  __device__ __forceinline__ void add(uint32_t e, uint32_t tag, bool valid, uint32_t pos) {
+    uint32_t b, u;
+    if (!share(e, tag, valid, b, u)) return;
+    const uint32_t j = (tag >> 1) & 63u;
+    if (b) atomicAdd(&cb[j], static_cast<Acc>(b));
+    if (u) atomicAdd(&cu[j], static_cast<Acc>(u));
+    edge(j, pos, b, u);
+  }
+  // a chunk slot (every lane in the chunk's run): summed in registers until
+  // the run changes (a wave-uniform test)
+  __device__ __forceinline__ void add_chunk(uint32_t e, uint32_t tag, bool valid, uint32_t pos) {
+    const uint32_t j = (tag >> 1) & 63u;
+    if (j != cur) {
+      put();
+      cur = j;
+    }
+    uint32_t b, u;
+    if (!share(e, tag, valid, b, u)) return;
+    sb += b;
+    su += u;
+    edge(j, pos, b, u);
+  }
   __device__ __forceinline__ void flush() {
     put();
     cur = 0xffffffffu;
   }
 };
 
-template <bool kEdge, class Look>
-__device__ __forceinline__ Credit<Look, kEdge> credit(Look l, unsigned long long* cb, unsigned long long* cu,
-                                                      const DevSideConst& sc, const RunEnds& re) {
-  Credit<Look, kEdge> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
+template <bool kEdge, class Look, class Acc>
+__device__ __forceinline__ Credit<Look, kEdge, Acc> credit(Look l, Acc* cb, Acc* cu, const DevSideConst& sc,
+                                                           const RunEnds& re) {
+  Credit<Look, kEdge, Acc> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
   if (kEdge) c.wide = __ballot(re.wide != 0);
   return c;
 }
 
 // After a batch's credit walk: each lane adds its run's credits to the mid
 // (and, with kEdge, to the run's first edge).
-template <bool kEdge>
-__device__ __forceinline__ void flush_mid_credits(unsigned long long* cb, unsigned long long* cu, RunEnds re,
-                                                  const DevSideConst& sc) {
+template <bool kEdge, class Acc>
+__device__ __forceinline__ void flush_mid_credits(Acc* cb, Acc* cu, RunEnds re, const DevSideConst& sc) {
   wave_sync_lds();
   const int lane = lane_id();
   const unsigned long long b = cb[lane], u = cu[lane];
@@ -227,7 +248,22 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
   cb[wave][lane] = 0;
   cu[wave][lane] = 0;
   const Marks<uint8_t> mk{mtab[wave], mflag[wave]};
-  Sums sums;
+  Sums sums;                              // unpacked items' pairs
+  uint64_t sq64 = 0, pn64 = 0, w64 = 0;   // packed items' pairs: sums of p^2 + n^2, p n, p + n
+  auto flush_all = [&](uint32_t g) {
+    unsigned long long* res = a.res + static_cast<size_t>(g) * kResStride;
+    flush_sums(sums, res);
+    const int64_t q = wave_sum64(static_cast<int64_t>(sq64)), x = wave_sum64(static_cast<int64_t>(pn64));
+    const int64_t ww = wave_sum64(static_cast<int64_t>(w64));
+    if (lane == 0) {
+      const int64_t bal = (q - ww) / 2;
+      if (bal) atomicAdd(res + kResBalanced, static_cast<unsigned long long>(bal));
+      if (x) atomicAdd(res + kResUnbalanced, static_cast<unsigned long long>(x));
+      if (bal + x) atomicAdd(res + kResTotal, static_cast<unsigned long long>(bal + x));
+    }
+    sums = Sums{};
+    sq64 = pn64 = w64 = 0;
+  };
   uint32_t graph = kNoGraph;
   for (;;) {
     if (tid == 0) item_sh = static_cast<int32_t>(atomicAdd(a.queue, 1u));
@@ -236,8 +272,7 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     if (i >= a.n_items) break;
     const Item it = load_const(a.items, i);
     if (it.graph != graph) {
-      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
-      sums = Sums{};
+      if (graph != kNoGraph) flush_all(graph);
       graph = it.graph;
     }
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
@@ -293,7 +328,8 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
     __syncthreads();
-    // credit the keys and the owner
+    // credit the keys and the owner (packed counts: p + n < 2^16, so a
+    // key's credits fit 32 bits)
     PairCredit pc;
     for (uint32_t k = tid; k < hi - lo; k += kPVDirectThreads) {
       const uint32_t v = C[k];
@@ -303,13 +339,24 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
         if (!packed) N[k] = 0;
         const uint32_t key = lo + k;
         if (key < hubT) continue;  // a hub pair: credited by the dense block
-        pc.add(sc, key, p, n, sums);
+        if (packed) {
+          const uint32_t cb2 = (__umul24(p, p - 1u) + __umul24(n, n - 1u)) >> 1, cx = __umul24(p, n);
+          sq64 += static_cast<uint64_t>(__umul24(p, p)) + __umul24(n, n);
+          pn64 += cx;
+          w64 += p + n;
+          if (cb2) atomicAdd(&sc.bal[sc.orig[key]], static_cast<unsigned long long>(cb2));
+          if (cx) atomicAdd(&sc.unb[sc.orig[key]], static_cast<unsigned long long>(cx));
+          pc.c += cb2;
+          pc.x += cx;
+        } else {
+          pc.add(sc, key, p, n, sums);
+        }
       }
     }
     pc.to_owner(sc, it.owner);
     __syncthreads();
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  if (graph != kNoGraph) flush_all(graph);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,7 +379,8 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ uint32_t dummies[kPVReverseWaves][kWave];
   __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVReverseWaves][kGather];
   __shared__ uint8_t mflag[kPVReverseWaves][kGather];
-  __shared__ unsigned long long cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
+  // a run's mid credits: at most its length (< 4096) times 255
+  __shared__ uint32_t cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
   __shared__ uint32_t kbal[kMaxReverseL], kunb[kMaxReverseL];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -346,14 +394,14 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   cu[wave][lane] = 0;
   wave_sync_lds();
   const Marks<uint8_t> mk{mtab[wave], mflag[wave]};
-  Sums sums;
+  SqTotals tot;  // the pass's global counts, from 32-bit per-item sums
   uint32_t graph = kNoGraph;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kPVReverseWaves;
   for (int32_t i = static_cast<int32_t>(blockIdx.x) * kPVReverseWaves + wave; i < a.n_items; i += stride) {
     const Item it = load_const(a.items, i);
     if (it.graph != graph) {
-      if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
-      sums = Sums{};
+      if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+      tot = SqTotals{};
       graph = it.graph;
     }
     const DevSideConst sc = load_const(a.sides, 2 * it.graph + it.side);
@@ -383,11 +431,13 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
       flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
     }
     // the key credits: 16-byte reads of the counter words, quads of zero
-    // words skipped; a pair with one wedge adds nothing
-    int64_t oc = 0, ox = 0;  // owner sums
+    // words skipped; a pair with one wedge adds nothing.  p, n <= 255, so a
+    // lane's sums over its keys of one item stay in 32 bits.
+    SqSums ss;
+    uint32_t oc = 0, ox = 0;  // owner sums
     auto local = [&](uint32_t key, uint32_t p, uint32_t n) {
-      sums.add(p, n);
-      const uint32_t cb2 = p * (p - 1) / 2 + n * (n - 1) / 2, cx = p * n;
+      ss.add(p, n);
+      const uint32_t cb2 = (__umul24(p, p - 1u) + __umul24(n, n - 1u)) >> 1, cx = __umul24(p, n);
       if (cb2) atomicAdd(&kbal[key], cb2);
       if (cx) atomicAdd(&kunb[key], cx);
       oc += cb2;
@@ -407,6 +457,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
         if (c2 >> 16) local(2 * wd + 1, (c2 >> 16) & 0xffu, c2 >> 24);
       }
     }
+    tot.add(ss);
     const int64_t oc2 = wave_sum64(oc), ox2 = wave_sum64(ox);
     if (lane == 0) {
       if (oc2) atomicAdd(&sc.bal[sc.orig[it.owner]], static_cast<unsigned long long>(oc2));
@@ -414,7 +465,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     }
     wave_sync_lds();
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
   // the workgroup's key credits (all items of a launch are of one side)
   __syncthreads();
   if (a.n_items > 0) {

@@ -620,8 +620,26 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
         it.side = static_cast<uint32_t>(s);
         it.work = static_cast<uint32_t>(std::min<int64_t>(work, 0xffffffffll));
       });
-      for (const Item& it : its)
-        if (it.seg_count) plan.hub_items.push_back(it);
+      // heavy pivots in parts of about kHubTallyPartWork wedges (the tally
+      // adds each part's counts into the pivot's row), so that one pivot
+      // does not hold the tally's last workgroup alone
+      for (const Item& it : its) {
+        if (!it.seg_count) continue;
+        uint32_t k = it.seg_begin;
+        const uint32_t end = it.seg_begin + it.seg_count;
+        while (k < end) {
+          Item part = it;
+          part.seg_begin = k;
+          int64_t w = 0;
+          do {
+            w += plan.hub_segs[k].len_g >> 1;
+            ++k;
+          } while (k < end && w + (plan.hub_segs[k].len_g >> 1) <= kHubTallyPartWork);
+          part.seg_count = k - part.seg_begin;
+          part.work = static_cast<uint32_t>(w);
+          plan.hub_items.push_back(part);
+        }
+      }
       if (s == 0) plan.n_hub_side0 = static_cast<int32_t>(plan.hub_items.size());
     }
 

@@ -253,6 +253,18 @@ template <class F>
 __device__ __forceinline__ void walk_add(F& f, uint32_t e, uint32_t tag, bool valid, uint32_t, long) {
   f.add(e, tag, valid);
 }
+// A slot of a streamed chunk: every lane's slot belongs to the same run (the
+// chunk's), so a functor may keep per-run state wave-uniform
+// (f.add_chunk(entry, tag, valid, pos)); otherwise as walk_add.
+template <class F>
+__device__ __forceinline__ auto walk_add_chunk(F& f, uint32_t e, uint32_t tag, bool valid, uint32_t pos, int)
+    -> decltype(f.add_chunk(e, tag, valid, pos), void()) {
+  f.add_chunk(e, tag, valid, pos);
+}
+template <class F>
+__device__ __forceinline__ void walk_add_chunk(F& f, uint32_t e, uint32_t tag, bool valid, uint32_t pos, long) {
+  walk_add(f, e, tag, valid, pos, 0);
+}
 
 // Walk a batch of up to 64 runs (one per lane, in registers) with one
 // wavefront, calling f.add(entry, tag, valid[, pos]) once per wedge slot.
@@ -356,10 +368,10 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
         const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
         if (kCompact && vrem[u] >= kChunk) {  // the whole chunk lies in the run (uniform)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) walk_add(f, e4[q], vg[u], true, vpos[u] + koff[q], 0);
+          for (int q = 0; q < 4; ++q) walk_add_chunk(f, e4[q], vg[u], true, vpos[u] + koff[q], 0);
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) walk_add(f, e4[q], vg[u], koff[q] < vrem[u], vpos[u] + koff[q], 0);
+          for (int q = 0; q < 4; ++q) walk_add_chunk(f, e4[q], vg[u], koff[q] < vrem[u], vpos[u] + koff[q], 0);
         }
       }
     }
