@@ -33,6 +33,7 @@ DBBC_INPUT_DEVICE = 0x1
 DBBC_DUP_REJECT = 0x2
 DBBC_OPT_TIME_KERNELS = 0x1
 DBBC_OPT_WIDE_EDGES = 0x2
+DBBC_OPT_HOST_PLAN = 0x4
 DBBC_BATCH_CAPTURE = 0x1
 DBBC_SERVER_NO_MERGE = 0x1
 

@@ -14,8 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdbbc.so")
 SOURCES = ["build.hip", "ingest.hip", "plan.cpp", "api.cpp", "server.cpp", "count.hip", "pervertex.hip",
-           "hub.hip", "hubpv.hip", "explicit.hip"]
-HEADERS = ["internal.h", "kernels.h", "walk.h", "devmem.h", "build_dev.h"]
+           "hub.hip", "hubpv.hip", "explicit.hip", "plan_dev.hip"]
+HEADERS = ["internal.h", "kernels.h", "walk.h", "devmem.h", "build_dev.h", "plan_dev.h"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -15,6 +15,7 @@
 #include "devmem.h"
 #include "internal.h"
 #include "kernels.h"
+#include "plan_dev.h"
 
 namespace {
 
@@ -294,13 +295,14 @@ struct dbbc_graph {
   DevPlan plan;
   uint64_t plan_gen = 0;  // bumped whenever the device plan is rebuilt
   DevPlan pv_plan;        // plan of the per-vertex pass
-  DevBuf orig[2];         // side rank -> input id, per side (per-vertex pass)
+  DevBuf orig[2];         // side rank -> input id, per side
+  DevBuf rev[2], cut[2], grank[2];  // per entry: position in the other row; per row: higher-priority
+                                    // prefix; per row: global rank (the planners' input)
   DevBuf pv_out[2][2];    // per-vertex outputs [side][balanced, unbalanced]
   DevBuf pe_out[2][3];    // per-edge credits by CSR position [side][packed, wide bal, wide unb]
   DevBuf edge_rec, edge_pos_v;  // U-CSR position -> input record, -> V-CSR position
   DevBuf pe_tmp;          // stands in for a NULL per-edge output
   DevBuf raw_ids[2];      // graphs read from text: compact -> raw id per side
-  DevBuf ex_rev[2], ex_cut[2];  // explicit-verification baseline: rev and cut per side
   std::vector<KernelRec> timers;  // events are reused across timed counts
   size_t timers_used = 0;
   bool timed_valid = false;
@@ -342,6 +344,52 @@ struct dbbc_batch {
 
 namespace {
 
+// The handle takes over the device arrays of its build.
+void take_csr(dbbc_graph* g, dbbc::DeviceCsr& csr) {
+  for (int s = 0; s < 2; ++s) {
+    g->adj[s] = std::move(csr.adj[s]);
+    g->off[s] = std::move(csr.off[s]);
+    g->rev[s] = std::move(csr.rev[s]);
+    g->cut[s] = std::move(csr.cut[s]);
+    g->grank[s] = std::move(csr.grank[s]);
+    g->orig[s] = std::move(csr.ord[s]);
+  }
+  g->edge_rec = std::move(csr.rec);
+}
+
+dbbc::DevGraphView view_of(const dbbc_graph* g) {
+  dbbc::DevGraphView v;
+  v.n[0] = g->host.n_u;
+  v.n[1] = g->host.n_v;
+  v.m = g->host.m;
+  for (int s = 0; s < 2; ++s) {
+    v.off[s] = g->off[s].as<uint32_t>();
+    v.adj[s] = g->adj[s].as<uint32_t>();
+    v.rev[s] = g->rev[s].as<int32_t>();
+    v.cut[s] = g->cut[s].as<int32_t>();
+    v.grank[s] = g->grank[s].as<int32_t>();
+    v.ord[s] = g->orig[s].as<int32_t>();
+  }
+  v.rec = g->edge_rec.as<uint32_t>();
+  return v;
+}
+
+// The host copy of the graph's arrays (for the host planner), made once.
+int ensure_host(dbbc_graph* g, hipStream_t st) {
+  if (g->host.arrays) return DBBC_OK;
+  std::string err;
+  const int rc = dbbc::fetch_host_arrays(view_of(g), g->host, st, err);
+  return rc == DBBC_OK ? DBBC_OK : fail(rc, err);
+}
+
+// Count plans are made on the device unless the caller asks for the host
+// planner, or the graph's entries or candidate items exceed the int sizes
+// of the device scans; per-vertex plans are made on the host.
+bool plans_on_device(const dbbc_graph* g, const dbbc::PlanParams& p) {
+  if (p.per_vertex || p.host_planner) return false;
+  return 3 * (static_cast<int64_t>(g->host.n_u) + g->host.n_v) + 1 <= INT32_MAX && g->host.m + 1 <= INT32_MAX;
+}
+
 int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, DevPlan& d) {
   if (d.valid && d.host.p == p) return DBBC_OK;
   d.valid = false;
@@ -349,41 +397,74 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   std::string err;
   dbbc::HostPlan hp;
   int rc;
-  try {
-    rc = dbbc::make_plan(g->host, p, hp, err);
-  } catch (const std::bad_alloc&) {
-    return fail(DBBC_E_OOM, "host allocation failed while planning");
-  }
-  if (rc != DBBC_OK) return fail(rc, err);
-  HIP_TRY(upload(d.segs, hp.segs, st));
-  HIP_TRY(upload(d.seg_mid, hp.seg_mid, st));
-  HIP_TRY(upload(d.small_seg_mid, hp.small_seg_mid, st));
-  HIP_TRY(upload(d.seg_edge, hp.seg_edge, st));
-  HIP_TRY(upload(d.small_seg_edge, hp.small_seg_edge, st));
-  HIP_TRY(upload(d.small_owner, hp.small_owner, st));
-  HIP_TRY(upload(d.small_segs, hp.small_segs, st));
-  HIP_TRY(upload(d.small_groups, hp.small_groups, st));
-  HIP_TRY(upload(d.direct_items, hp.direct_items, st));
-  HIP_TRY(upload(d.hash_items, hp.hash_items, st));
-  HIP_TRY(upload(d.reverse_items, hp.reverse_items, st));
-  HIP_TRY(upload(d.reduces, hp.reduces, st));
-  HIP_TRY(d.acc.alloc(static_cast<size_t>(hp.acc_slots) * hp.acc_width * sizeof(uint32_t)));
-  if (p.per_vertex) {
-    HIP_TRY(upload(d.hub_items, hp.hub_items, st));
-    HIP_TRY(upload(d.hub_segs, hp.hub_segs, st));
+  const bool on_device = plans_on_device(g, p);
+  for (DevBuf* b : {&d.seg_mid, &d.small_seg_mid, &d.seg_edge, &d.small_seg_edge, &d.small_owner, &d.hub_items,
+                    &d.hub_segs})
+    b->release();
+  if (on_device) {
+    dbbc::DevPlanLists out;
+    rc = dbbc::make_plan_device(view_of(g), p, st, hp, out, err);
+    if (rc != DBBC_OK) return fail(rc, err);
+    d.segs = std::move(out.segs);
+    d.small_segs = std::move(out.small_segs);
+    d.small_groups = std::move(out.small_groups);
+    d.direct_items = std::move(out.direct_items);
+    d.hash_items = std::move(out.hash_items);
+    d.reverse_items = std::move(out.reverse_items);
+    d.reduces = std::move(out.reduces);
+    d.acc = std::move(out.acc);
+    for (int s = 0; s < 2; ++s) {
+      d.hub_B[s] = std::move(out.hub_B[s]);
+      d.hub_Bm[s] = std::move(out.hub_Bm[s]);
+      d.hub_K[s] = out.hub_K[s];
+    }
+  } else {
+    rc = ensure_host(g, st);
+    if (rc != DBBC_OK) return rc;
+    try {
+      rc = dbbc::make_plan(g->host, p, hp, err);
+    } catch (const std::bad_alloc&) {
+      return fail(DBBC_E_OOM, "host allocation failed while planning");
+    }
+    if (rc != DBBC_OK) return fail(rc, err);
+    HIP_TRY(upload(d.segs, hp.segs, st));
+    HIP_TRY(upload(d.seg_mid, hp.seg_mid, st));
+    HIP_TRY(upload(d.small_seg_mid, hp.small_seg_mid, st));
+    HIP_TRY(upload(d.seg_edge, hp.seg_edge, st));
+    HIP_TRY(upload(d.small_seg_edge, hp.small_seg_edge, st));
+    HIP_TRY(upload(d.small_owner, hp.small_owner, st));
+    HIP_TRY(upload(d.small_segs, hp.small_segs, st));
+    HIP_TRY(upload(d.small_groups, hp.small_groups, st));
+    HIP_TRY(upload(d.direct_items, hp.direct_items, st));
+    HIP_TRY(upload(d.hash_items, hp.hash_items, st));
+    HIP_TRY(upload(d.reverse_items, hp.reverse_items, st));
+    HIP_TRY(upload(d.reduces, hp.reduces, st));
+    HIP_TRY(d.acc.alloc(static_cast<size_t>(hp.acc_slots) * hp.acc_width * sizeof(uint32_t)));
+    if (p.per_vertex) {
+      HIP_TRY(upload(d.hub_items, hp.hub_items, st));
+      HIP_TRY(upload(d.hub_segs, hp.hub_segs, st));
+    }
+    hp.n_items_kept[0] = static_cast<int32_t>(d.direct_items.bytes / sizeof(dbbc::Item));
+    hp.n_items_kept[1] = static_cast<int32_t>(d.reverse_items.bytes / sizeof(dbbc::Item));
+    hp.n_items_kept[2] = static_cast<int32_t>(d.small_groups.bytes / sizeof(dbbc::Item));
+    hp.n_items_kept[3] = static_cast<int32_t>(d.hash_items.bytes / sizeof(dbbc::Item));
+    hp.n_items_kept[4] = static_cast<int32_t>(d.reduces.bytes / sizeof(dbbc::Reduce));
   }
   for (int s = 0; s < 2; ++s) {
     d.hub_pairs[s].release();
-    d.hub_B[s].release();
-    d.hub_Bm[s].release();
+    if (!on_device) {
+      d.hub_B[s].release();
+      d.hub_Bm[s].release();
+      d.hub_K[s] = 0;
+    }
     for (DevBuf* b : {&d.hub_Bt[s], &d.hub_Bmt[s], &d.hub_Zc[s], &d.hub_Zcp[s], &d.hub_pos[s], &d.hub_rows[s],
                       &d.hub_cols[s]})
       b->release();
-    d.hub_K[s] = 0;
     d.hub_D[s] = 0;
     const int32_t T = hp.T[s], TO = hp.T[1 - s];
     if (T == 0) continue;
     HIP_TRY(d.hub_pairs[s].alloc(2 * static_cast<size_t>(T) * T * sizeof(int32_t)));
+    if (on_device) continue;  // the device planner wrote B and Bm
     // pad the contraction dimension to a multiple of kHubKPad
     const int32_t K = (TO + dbbc::kHubKPad - 1) / dbbc::kHubKPad * dbbc::kHubKPad;
     std::vector<int8_t> B(static_cast<size_t>(T) * K, 0), Bm(static_cast<size_t>(T) * K, 0);
@@ -507,11 +588,6 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
     v->clear();
     v->shrink_to_fit();
   }
-  hp.n_items_kept[0] = static_cast<int32_t>(d.direct_items.bytes / sizeof(dbbc::Item));
-  hp.n_items_kept[1] = static_cast<int32_t>(d.reverse_items.bytes / sizeof(dbbc::Item));
-  hp.n_items_kept[2] = static_cast<int32_t>(d.small_groups.bytes / sizeof(dbbc::Item));
-  hp.n_items_kept[3] = static_cast<int32_t>(d.hash_items.bytes / sizeof(dbbc::Item));
-  hp.n_items_kept[4] = static_cast<int32_t>(d.reduces.bytes / sizeof(dbbc::Reduce));
   hp.reduces.clear();
   hp.reduces.shrink_to_fit();
   d.host = std::move(hp);
@@ -534,8 +610,9 @@ int params_from(const dbbc_graph* g, const dbbc_options* opt, dbbc::PlanParams& 
   p = g->defaults;
   long_len = kDefaultLongLen;
   if (!opt) return DBBC_OK;
-  if (opt->flags & ~(DBBC_OPT_TIME_KERNELS | DBBC_OPT_WIDE_EDGES))
+  if (opt->flags & ~(DBBC_OPT_TIME_KERNELS | DBBC_OPT_WIDE_EDGES | DBBC_OPT_HOST_PLAN))
     return fail(DBBC_E_INVALID_ARG, "unknown dbbc_options flag");
+  p.host_planner = (opt->flags & DBBC_OPT_HOST_PLAN) != 0;
   if (opt->hub_T >= 0) p.hub_T = opt->hub_T;
   if (opt->window_L >= 0) p.window_L = opt->window_L;
   if (opt->reverse_L >= 0) p.reverse_L = opt->reverse_L;
@@ -677,10 +754,7 @@ int dbbc_graph_create(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, con
   dbbc::DeviceCsr csr;
   rc = dbbc::build_device_graph(n_u, n_v, m, u, v, sign, flags, st, g->host, csr, err);
   if (rc != DBBC_OK) return fail(rc, err);
-  for (int s = 0; s < 2; ++s) {  // the handle owns the device CSR from here
-    g->adj[s] = std::move(csr.adj[s]);
-    g->off[s] = std::move(csr.off[s]);
-  }
+  take_csr(g.get(), csr);
   HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), kCtlWords * sizeof(unsigned long long),
                         hipHostMallocDefault));
@@ -713,11 +787,8 @@ int dbbc_graph_create_text(const char* text, int64_t len, uint32_t flags, const 
   dbbc::IngestOut io;
   rc = dbbc::ingest_text(text, len, flags, st, g->host, csr, io, err);
   if (rc != DBBC_OK) return fail(rc, err);
-  for (int s = 0; s < 2; ++s) {  // the handle owns the device arrays from here
-    g->adj[s] = std::move(csr.adj[s]);
-    g->off[s] = std::move(csr.off[s]);
-    g->raw_ids[s] = std::move(io.raw[s]);
-  }
+  take_csr(g.get(), csr);
+  for (int s = 0; s < 2; ++s) g->raw_ids[s] = std::move(io.raw[s]);
   HIP_TRY(g->ctl.alloc(kCtlWords * sizeof(unsigned long long)));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), kCtlWords * sizeof(unsigned long long),
                         hipHostMallocDefault));
@@ -750,8 +821,8 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
   size_t b = g->ctl.bytes + g->plan.bytes() + g->pv_plan.bytes() + g->edge_rec.bytes +
              g->edge_pos_v.bytes + g->pe_tmp.bytes;
   for (int k = 0; k < 2; ++k) {
-    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes + g->raw_ids[k].bytes + g->ex_rev[k].bytes +
-         g->ex_cut[k].bytes;
+    b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes + g->raw_ids[k].bytes + g->rev[k].bytes +
+         g->cut[k].bytes + g->grank[k].bytes;
     for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes;
     for (int j = 0; j < 3; ++j) b += g->pe_out[k][j].bytes;
   }
@@ -784,16 +855,14 @@ int dbbc_count_explicit(dbbc_graph* g, dbbc_counts* out_host, void* hip_stream) 
   dbbc::AllocScope scope(g->al, hip_stream);
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  rc = ensure_host(g, st);
+  if (rc != DBBC_OK) return rc;
   const dbbc::HostGraph& hg = g->host;
   // the most wedges of one pivot (the list a workgroup holds at once)
   int64_t cap = 1;
   for (int s = 0; s < 2; ++s) {
     const dbbc::HostSide& S = hg.side[s];
     const dbbc::HostSide& O = hg.side[1 - s];
-    if (!g->ex_rev[s].p) {
-      HIP_TRY(upload(g->ex_rev[s], S.rev, st));
-      HIP_TRY(upload(g->ex_cut[s], S.cut, st));
-    }
     for (int32_t x = 0; x < S.n; ++x) {
       int64_t wx = 0;
       for (uint32_t e = S.off[x] + static_cast<uint32_t>(S.cut[x]); e < S.off[x + 1]; ++e) {
@@ -819,8 +888,8 @@ int dbbc_count_explicit(dbbc_graph* g, dbbc_counts* out_host, void* hip_stream) 
     dbbc::ExplicitArgs a{};
     a.off_s = g->off[s].as<uint32_t>();
     a.adj_s = g->adj[s].as<uint32_t>();
-    a.rev_s = g->ex_rev[s].as<int32_t>();
-    a.cut_s = g->ex_cut[s].as<int32_t>();
+    a.rev_s = g->rev[s].as<int32_t>();
+    a.cut_s = g->cut[s].as<int32_t>();
     a.off_o = g->off[1 - s].as<uint32_t>();
     a.adj_o = g->adj[1 - s].as<uint32_t>();
     a.n_s = hg.side[s].n;
@@ -899,24 +968,24 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   p.per_vertex = true;
   p.hub_T = std::min(p.hub_T, dbbc::kMaxPVHubT);
   p.wide_all = edge && opt && (opt->flags & DBBC_OPT_WIDE_EDGES);
+  rc = ensure_host(g, st);
+  if (rc != DBBC_OK) return rc;
   const int32_t n[2] = {g->host.n_u, g->host.n_v};
   const size_t m = static_cast<size_t>(g->host.m);
   for (int s = 0; s < 2; ++s) {
-    if (!g->orig[s].p) HIP_TRY(upload(g->orig[s], g->host.side[s].orig, st));
     for (int k = 0; k < 2; ++k)
       HIP_TRY(g->pv_out[s][k].reserve(static_cast<size_t>(n[s]) * sizeof(unsigned long long)));
   }
   if (edge) {
     for (int s = 0; s < 2; ++s)
       for (int k = 0; k < 3; ++k) HIP_TRY(g->pe_out[s][k].reserve(m * sizeof(unsigned long long)));
-    if (!g->edge_rec.p && m > 0) {
+    if (!g->edge_pos_v.p && m > 0) {
       const dbbc::HostSide& U = g->host.side[0];
       const dbbc::HostSide& V = g->host.side[1];
       std::vector<uint32_t> pos_v(m);
       for (size_t k = 0; k < m; ++k)
         pos_v[k] = V.off[U.adj[k] >> 1] + static_cast<uint32_t>(U.rev[k]);
       HIP_TRY(upload(g->edge_pos_v, pos_v, st));
-      HIP_TRY(upload(g->edge_rec, U.rec, st));
       HIP_TRY(hipStreamSynchronize(st));  // pos_v leaves scope
     }
   }

@@ -202,6 +202,30 @@ __global__ void k_wedges(const uint32_t* off, const uint32_t* adj, const int32_t
   }
 }
 
+// Entries of the top T x T block of side 0 for T = 4096, 2048, 1024 (the
+// dense block's fill, which picks its default size): per row x < 4096, the
+// entries of rank below each T, by binary search.
+__global__ void k_hub_nnz(const uint32_t* off, const uint32_t* adj, int32_t n, unsigned long long* res) {
+  const int32_t rows = min(n, 4096);
+  for (int32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < rows; x += gridDim.x * blockDim.x) {
+    const uint32_t b = off[x], e = off[x + 1];
+    for (int k = 0; k < 3; ++k) {
+      const int32_t T = 4096 >> k;
+      if (x >= T) continue;
+      const uint32_t key = static_cast<uint32_t>(T) << 1;
+      uint32_t lo = b, hi = e;
+      while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (adj[mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo > b) atomicAdd(&res[k], static_cast<unsigned long long>(lo - b));
+    }
+  }
+}
+
 // Device memory of one build step, freed on scope exit (at least 16 bytes,
 // so that even an empty array has an address).
 struct Tmp : DevBuf {
@@ -289,11 +313,11 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
     v = dv.as<int32_t>();
     s = ds.as<int8_t>();
   }
-  Tmp small;  // 4 u64 words: bad[2], wedge sums[2]
-  DEV_TRY(small.alloc(4 * sizeof(unsigned long long)));
+  Tmp small;  // 7 u64 words: bad[2], wedge sums[2], hub block entries[3]
+  DEV_TRY(small.alloc(7 * sizeof(unsigned long long)));
   unsigned long long* words = small.as<unsigned long long>();
   DEV_TRY(launch_fill_u64(words, 2, ~0ull, st));
-  DEV_TRY(launch_fill_u64(words + 2, 2, 0ull, st));
+  DEV_TRY(launch_fill_u64(words + 2, 5, 0ull, st));
   if (m) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(m)), dim3(kThreads), 0, st, u, v, s, m, n_u, n_v, words);
     DEV_TRY(hipGetLastError());
@@ -354,7 +378,9 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
 
   // 2. degrees and priority orders
   const int32_t n[2] = {n_u, n_v};
-  Tmp deg[2], ord[2], sr[2], grank[2];
+  Tmp deg[2], sr[2];
+  DevBuf* ord = out.ord;
+  DevBuf* grank = out.grank;
   for (int x = 0; x < 2; ++x) {
     DEV_TRY(deg[x].alloc(static_cast<size_t>(n[x]) * 4));
     DEV_TRY(ord[x].alloc(static_cast<size_t>(n[x]) * 4));
@@ -397,11 +423,14 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
   // 3. the two CSRs: rows by own side rank, neighbours by the other's
   const int32_t* ends[2] = {u, v};
   const int bitsv[2] = {ubits, vbits};
-  Tmp by[2], off[2], adj[2], rev[2], cut[2], dbr;
+  Tmp by1, off[2], adj[2], dbr;
+  DevBuf* by[2] = {&out.rec, &by1};
+  DevBuf* rev = out.rev;
+  DevBuf* cut = out.cut;
   DEV_TRY(dbr.alloc((static_cast<size_t>(std::max(n_u, n_v)) + 1) * 4));
   for (int x = 0; x < 2; ++x) {
     const int o = 1 - x;
-    DEV_TRY(by[x].alloc(static_cast<size_t>(me) * 4));
+    DEV_TRY(by[x]->alloc(static_cast<size_t>(me) * 4));
     DEV_TRY(off[x].alloc((static_cast<size_t>(n[x]) + 1) * 4));
     DEV_TRY(adj[x].alloc((static_cast<size_t>(me) + kAdjPad) * 4));
     DEV_TRY(rev[x].alloc(static_cast<size_t>(me) * 4));
@@ -412,9 +441,9 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
                          ends[o], sr[x].as<int32_t>(), sr[o].as<int32_t>(), bitsv[o], k0.as<uint64_t>(),
                          v0.as<uint32_t>());
       DEV_TRY(hipGetLastError());
-      sort_pairs(ct, k0.as<uint64_t>(), k1.as<uint64_t>(), v0.as<uint32_t>(), by[x].as<uint32_t>(), me,
+      sort_pairs(ct, k0.as<uint64_t>(), k1.as<uint64_t>(), v0.as<uint32_t>(), by[x]->as<uint32_t>(), me,
                  bitsv[x] + bitsv[o], st);
-      hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(me)), dim3(kThreads), 0, st, by[x].as<uint32_t>(), me, ends[o], s,
+      hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(me)), dim3(kThreads), 0, st, by[x]->as<uint32_t>(), me, ends[o], s,
                          sr[o].as<int32_t>(), adj[x].as<uint32_t>());
       DEV_TRY(hipGetLastError());
     }
@@ -431,10 +460,10 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
   if (me) {
     Tmp pos_v;
     DEV_TRY(pos_v.alloc(M * 4));
-    hipLaunchKernelGGL(k_record_pos, dim3(grid_for(me)), dim3(kThreads), 0, st, by[1].as<uint32_t>(), me,
+    hipLaunchKernelGGL(k_record_pos, dim3(grid_for(me)), dim3(kThreads), 0, st, by[1]->as<uint32_t>(), me,
                        pos_v.as<uint32_t>());
     DEV_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_rev, dim3(grid_for(me)), dim3(kThreads), 0, st, by[0].as<uint32_t>(), me, u, v,
+    hipLaunchKernelGGL(k_rev, dim3(grid_for(me)), dim3(kThreads), 0, st, by[0]->as<uint32_t>(), me, u, v,
                        sr[0].as<int32_t>(), sr[1].as<int32_t>(), off[0].as<uint32_t>(), off[1].as<uint32_t>(),
                        pos_v.as<uint32_t>(), rev[0].as<int32_t>(), rev[1].as<int32_t>());
     DEV_TRY(hipGetLastError());
@@ -454,25 +483,24 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
     DEV_TRY(hipGetLastError());
   }
 
-  // 4. the host copy the planner reads
+  hipLaunchKernelGGL(k_hub_nnz, dim3(16), dim3(kThreads), 0, st, off[0].as<uint32_t>(), adj[0].as<uint32_t>(), n[0],
+                     words + 4);
+  DEV_TRY(hipGetLastError());
+
+  // 4. the sizes the host keeps (the arrays stay on the device)
   for (int x = 0; x < 2; ++x) {
     HostSide& S = g.side[x];
+    S = HostSide{};
     S.n = n[x];
     S.max_deg = maxdeg[x];
-    to_host(S.off, off[x].p, static_cast<size_t>(n[x]) + 1, st);
-    to_host(S.adj, adj[x].p, static_cast<size_t>(me), st);
-    to_host(S.rev, rev[x].p, static_cast<size_t>(me), st);
-    to_host(S.cut, cut[x].p, static_cast<size_t>(n[x]), st);
-    to_host(S.grank, grank[x].p, static_cast<size_t>(n[x]), st);
-    to_host(S.orig, ord[x].p, static_cast<size_t>(n[x]), st);
   }
-  to_host(g.side[0].rec, by[0].p, static_cast<size_t>(me), st);
-  g.side[1].rec.clear();
-  unsigned long long wsum[2];
+  g.arrays = false;
+  unsigned long long wsum[5];
   DEV_TRY(hipMemcpyAsync(wsum, words + 2, sizeof(wsum), hipMemcpyDeviceToHost, st));
   DEV_TRY(hipStreamSynchronize(st));
   g.wedges_vp = static_cast<int64_t>(wsum[0]);
   g.pivots_active = static_cast<int64_t>(wsum[1]);
+  for (int k = 0; k < 3; ++k) g.hub_nnz[k] = static_cast<int64_t>(wsum[2 + k]);
   for (int x = 0; x < 2; ++x) {
     out.adj[x] = std::move(adj[x]);
     out.off[x] = std::move(off[x]);
@@ -480,6 +508,36 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
 }
 
 }  // namespace
+
+int fetch_host_arrays(const DevGraphView& d, HostGraph& g, hipStream_t st, std::string& err) {
+  if (g.arrays) return DBBC_OK;
+  try {
+    const size_t me = static_cast<size_t>(g.m);
+    for (int x = 0; x < 2; ++x) {
+      HostSide& S = g.side[x];
+      const size_t n = static_cast<size_t>(S.n);
+      to_host(S.off, d.off[x], n + 1, st);
+      to_host(S.adj, d.adj[x], me, st);
+      to_host(S.rev, d.rev[x], me, st);
+      to_host(S.cut, d.cut[x], n, st);
+      to_host(S.grank, d.grank[x], n, st);
+      to_host(S.orig, d.ord[x], n, st);
+    }
+    to_host(g.side[0].rec, d.rec, me, st);
+    g.side[1].rec.clear();
+    DEV_TRY(hipStreamSynchronize(st));
+  } catch (const Fail& f) {
+    err = f.msg;
+    (void)hipStreamSynchronize(st);
+    return f.status;
+  } catch (const std::bad_alloc&) {
+    err = "host allocation failed while copying the graph";
+    (void)hipStreamSynchronize(st);
+    return DBBC_E_OOM;
+  }
+  g.arrays = true;
+  return DBBC_OK;
+}
 
 int build_device_graph(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u, const int32_t* v,
                        const int8_t* sign, uint32_t flags, hipStream_t st, HostGraph& g, DeviceCsr& out,

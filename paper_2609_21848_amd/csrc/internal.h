@@ -34,11 +34,16 @@ struct HostGraph {
   int64_t dups_dropped = 0;
   int64_t wedges_vp = 0;
   int64_t pivots_active = 0;
-  HostSide side[2];  // 0 = U, 1 = V
+  // entries of the top T x T block of side 0 (rows and columns in priority
+  // order) for T = 4096, 2048, 1024; -1 where not counted at build time
+  int64_t hub_nnz[3] = {-1, -1, -1};
+  bool arrays = false;  // the per-row and per-entry arrays of side[] are filled
+  HostSide side[2];     // 0 = U, 1 = V
 };
 
-// The graph is built on the device (build.hip, build_device_graph); the
-// host keeps the copy above for planning.
+// The graph is built on the device (build.hip, build_device_graph), which
+// fills the sizes above; the arrays of side[] are copied from the device
+// only for the host planner (per-vertex plans).
 
 // ---- counting plan -----------------------------------------------------------
 
@@ -110,10 +115,11 @@ struct PlanParams {
   int32_t part_work = 0;
   bool per_vertex = false;  // plan for the per-vertex pass (no multi-part items)
   bool wide_all = false;    // per-vertex plans: flag every run kMidWide
+  bool host_planner = false;  // count plans: make the plan on the host
   bool operator==(const PlanParams& o) const {
     return hub_T == o.hub_T && window_L == o.window_L && reverse_L == o.reverse_L &&
            small_work == o.small_work && part_work == o.part_work && per_vertex == o.per_vertex &&
-           wide_all == o.wide_all;
+           wide_all == o.wide_all && host_planner == o.host_planner;
   }
 };
 
@@ -206,6 +212,11 @@ int check_plan_sizes(const PlanSizes& z, std::string& err);
 // once; the default block is trimmed so that its upper triangle of tiles
 // fits in one round.
 PlanParams default_params(const HostGraph& g, int32_t hub_slots = 512);
+// Checks of the plan knobs (a DBBC status; err filled on failure).
+int check_plan_params(const PlanParams& p, std::string& err);
+// The windows L, R, the dense block T per side and the accumulator width of
+// a plan of a graph with n[s] vertices per side.
+void plan_windows(const int32_t n[2], const PlanParams& p, HostPlan& plan);
 int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err);
 
 }  // namespace dbbc

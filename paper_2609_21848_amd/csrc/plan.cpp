@@ -32,6 +32,8 @@ namespace dbbc {
 // Density of the top T x T block of the bi-adjacency matrix (rows and
 // columns in priority order).
 double hub_density(const HostGraph& g, int32_t T) {
+  for (int k = 0; k < 3; ++k)
+    if ((4096 >> k) == T && g.hub_nnz[k] >= 0) return static_cast<double>(g.hub_nnz[k]) / (static_cast<double>(T) * T);
   const HostSide& S = g.side[0];
   int64_t nnz = 0;
   for (int32_t x = 0; x < T; ++x) {
@@ -360,7 +362,7 @@ int check_plan_sizes(const PlanSizes& z, std::string& err) {
   return DBBC_OK;
 }
 
-int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err) {
+int check_plan_params(const PlanParams& p, std::string& err) {
   if (p.window_L < 256 || p.window_L > 32768 || p.window_L % 256 != 0) {
     err = "window_L must be a multiple of 256 in [256, 32768]";
     return DBBC_E_INVALID_ARG;
@@ -383,18 +385,35 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
           "] and part_work at least 4096";
     return DBBC_E_INVALID_ARG;
   }
-  plan = HostPlan();
-  plan.p = p;
+  return DBBC_OK;
+}
+
+void plan_windows(const int32_t n[2], const PlanParams& p, HostPlan& plan) {
   const bool pv = p.per_vertex;
   for (int s = 0; s < 2; ++s) {
-    plan.L[s] = std::min<int32_t>(p.window_L, g.side[s].n);
+    plan.L[s] = std::min<int32_t>(p.window_L, n[s]);
     plan.R[s] = std::min<int32_t>(p.reverse_L, plan.L[s]);
     // the dense block is tiled by 128 rows (at most kMaxPVHubT in the
     // per-vertex pass)
-    plan.T[s] = std::min<int32_t>(pv ? std::min(p.hub_T, kMaxPVHubT) : p.hub_T, g.side[s].n / 128 * 128);
+    plan.T[s] = std::min<int32_t>(pv ? std::min(p.hub_T, kMaxPVHubT) : p.hub_T, n[s] / 128 * 128);
   }
   // The dense path needs a block on both sides of the pair.
   if (plan.T[0] == 0 || plan.T[1] == 0) plan.T[0] = plan.T[1] = 0;
+  plan.acc_width = std::max(plan.L[0], plan.L[1]);
+}
+
+int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::string& err) {
+  {
+    const int rc = check_plan_params(p, err);
+    if (rc != DBBC_OK) return rc;
+  }
+  plan = HostPlan();
+  plan.p = p;
+  const bool pv = p.per_vertex;
+  {
+    const int32_t n[2] = {g.side[0].n, g.side[1].n};
+    plan_windows(n, p, plan);
+  }
 
   std::vector<Item> big_direct;
   // pieces of both sides in plan order (side 0 forward, side 0 reverse,
@@ -674,9 +693,6 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   order.reserve(big_direct.size());
   for (size_t i = 0; i < big_direct.size(); ++i) order.push_back({item_work(plan, big_direct[i]), i});
   std::sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
-  int32_t width = 0;
-  for (int s = 0; s < 2; ++s) width = std::max(width, plan.L[s]);
-  plan.acc_width = width;
   std::vector<Item> parts, singles;
   for (auto& [work, i] : order) {
     const Item& it = big_direct[i];
