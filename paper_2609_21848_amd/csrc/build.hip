@@ -67,12 +67,35 @@ __global__ void k_last_of_run(const uint64_t* keys, int64_t m, uint8_t* keep) {
   GRID_STRIDE(i, m) keep[i] = (i + 1 == m || keys[i + 1] != keys[i]) ? 1 : 0;
 }
 
-__global__ void k_degrees(const uint32_t* kept, int64_t me, const int32_t* u, const int32_t* v, uint32_t* deg_u,
+// Degrees from the sorted (u, v) keys of all records and their keep flags.
+// Records of one u are adjacent: each wavefront adds the kept records of a
+// run of equal u with one atomic (the heavy rows' counters would otherwise
+// take one atomic per edge); the v counters take one atomic per kept record.
+__global__ void k_degrees(const uint64_t* keys, const uint8_t* keep, int64_t m, int vbits, uint32_t* deg_u,
                           uint32_t* deg_v) {
-  GRID_STRIDE(k, me) {
-    const uint32_t r = kept[k];
-    atomicAdd(&deg_u[u[r]], 1u);
-    atomicAdd(&deg_v[v[r]], 1u);
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const uint64_t vmask = (uint64_t{1} << vbits) - 1;
+  // whole wavefronts loop together (the run sums use the whole wavefront)
+  const int64_t span = (m + 63) / 64 * 64;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < span;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const bool in = i < m;
+    const uint64_t key = in ? keys[i] : ~uint64_t{0};
+    const bool kept = in && keep[i];
+    const uint32_t u = static_cast<uint32_t>(key >> vbits);
+    const uint32_t u_prev = __shfl_up(u, 1, 64);
+    const bool head = lane == 0 || u != u_prev;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long keeps = __ballot(kept);
+    if (kept) atomicAdd(&deg_v[key & vmask], 1u);
+    if (head && in) {
+      // this lane's run: lanes [lane, next head)
+      const unsigned long long later = heads & ~((2ull << lane) - 1ull);
+      const int next = later ? __builtin_ctzll(later) : 64;
+      const unsigned long long upto = next == 64 ? ~0ull : ((1ull << next) - 1ull);
+      const uint32_t c = static_cast<uint32_t>(__popcll(keeps & upto & ~((1ull << lane) - 1ull)));
+      if (c) atomicAdd(&deg_u[u], c);
+    }
   }
 }
 
@@ -389,8 +412,8 @@ void build(int32_t n_u, int32_t n_v, int64_t m, const int32_t* u_in, const int32
     DEV_TRY(hipMemsetAsync(deg[x].p, 0, static_cast<size_t>(n[x]) * 4, st));
   }
   if (me) {
-    hipLaunchKernelGGL(k_degrees, dim3(grid_for(me)), dim3(kThreads), 0, st, kept.as<uint32_t>(), me, u, v,
-                       deg[0].as<uint32_t>(), deg[1].as<uint32_t>());
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(m)), dim3(kThreads), 0, st, k1.as<uint64_t>(), keep.as<uint8_t>(), m,
+                       vbits, deg[0].as<uint32_t>(), deg[1].as<uint32_t>());
     DEV_TRY(hipGetLastError());
   }
   Tmp dmax;

@@ -294,76 +294,74 @@ __device__ unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
+// Each candidate's list counts; the statistics are summed per thread over
+// its candidates, then per wavefront, then once per wavefront into stats.
 __global__ void k_count(PSide P, PlanCount* counts, unsigned long long* stats) {
   const int64_t nc = 3 * static_cast<int64_t>(P.n);
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  // whole wavefronts loop together (the statistics are summed per wavefront)
-  const int64_t span = (nc + 63) / 64 * 64;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < span; i += stride) {
-    unsigned long long w[4] = {0, 0, 0, 0}, r[4] = {0, 0, 0, 0}, sparse = 0, skipped = 0;
-    if (i < nc) {
-      const int32_t x = static_cast<int32_t>(i / 3);
-      const int k = static_cast<int>(i % 3);
-      const Cand c = classify<true>(P, x, k);
-      PlanCount q{};
-      int slot = -1;
-      switch (c.cls) {
-        case kSmallC:
-          q.small_runs = c.nseg;
-          q.small_items = 1;
-          slot = 1;
-          break;
-        case kHashC:
-          q.big_runs = c.nseg;
-          q.hash = 1;
-          slot = 2;
-          break;
-        case kDirectC:
-          q.big_runs = c.nseg;
-          q.direct = 1;
-          if (c.split) {
-            q.direct_parts = c.nparts;
-            q.direct_split = 1;
-          }
-          slot = 0;
-          break;
-        case kRevC:
-          q.big_runs = c.nseg;
-          if (c.nparts) {
-            q.rev = c.nparts;
-            q.rev_reduces = 1;
-            q.rev_acc = c.nparts;
-          } else {
-            q.rev = 1;
-          }
-          slot = 3;
-          break;
-        default:
-          skipped = c.work;
-          break;
-      }
-      if (slot >= 0) {
-        w[slot] = c.work;
-        r[slot] = c.nseg;
-        sparse = c.work;
-      }
-      counts[P.cand0 + i] = q;
+  unsigned long long w[4] = {0, 0, 0, 0}, r[4] = {0, 0, 0, 0}, sparse = 0, skipped = 0;
+  GRID_STRIDE(i, nc) {
+    const int32_t x = static_cast<int32_t>(i / 3);
+    const int k = static_cast<int>(i % 3);
+    const Cand c = classify<true>(P, x, k);
+    PlanCount q{};
+    int slot = -1;
+    switch (c.cls) {
+      case kSmallC:
+        q.small_runs = c.nseg;
+        q.small_items = 1;
+        slot = 1;
+        break;
+      case kHashC:
+        q.big_runs = c.nseg;
+        q.hash = 1;
+        slot = 2;
+        break;
+      case kDirectC:
+        q.big_runs = c.nseg;
+        q.direct = 1;
+        if (c.split) {
+          q.direct_parts = c.nparts;
+          q.direct_split = 1;
+        }
+        slot = 0;
+        break;
+      case kRevC:
+        q.big_runs = c.nseg;
+        if (c.nparts) {
+          q.rev = c.nparts;
+          q.rev_reduces = 1;
+          q.rev_acc = c.nparts;
+        } else {
+          q.rev = 1;
+        }
+        slot = 3;
+        break;
+      default:
+        skipped += c.work;
+        break;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      w[j] = wave_sum(w[j]);
-      r[j] = wave_sum(r[j]);
+      w[j] += j == slot ? c.work : 0ull;
+      r[j] += j == slot ? c.nseg : 0u;
     }
-    sparse = wave_sum(sparse);
-    skipped = wave_sum(skipped);
-    if ((threadIdx.x & 63) == 0) {
-      for (int j = 0; j < 4; ++j) {
-        if (w[j]) atomicAdd(&stats[kStWedges + j], w[j]);
-        if (r[j]) atomicAdd(&stats[kStRuns + j], r[j]);
-      }
-      if (sparse) atomicAdd(&stats[kStSparse], sparse);
-      if (skipped) atomicAdd(&stats[kStSkipped], skipped);
+    if (slot >= 0) sparse += c.work;
+    counts[P.cand0 + i] = q;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    w[j] = wave_sum(w[j]);
+    r[j] = wave_sum(r[j]);
+  }
+  sparse = wave_sum(sparse);
+  skipped = wave_sum(skipped);
+  if ((threadIdx.x & 63) == 0) {
+    for (int j = 0; j < 4; ++j) {
+      if (w[j]) atomicAdd(&stats[kStWedges + j], w[j]);
+      if (r[j]) atomicAdd(&stats[kStRuns + j], r[j]);
     }
+    if (sparse) atomicAdd(&stats[kStSparse], sparse);
+    if (skipped) atomicAdd(&stats[kStSkipped], skipped);
   }
 }
 
@@ -795,8 +793,9 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   PD_TRY(launch_fill_u64(stats, kStWords, 0ull, st));
   PD_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(counts + nc), sizeof(PlanCount) / 8, 0ull, st));
   for (int s = 0; s < 2; ++s) {
-    hipLaunchKernelGGL(k_count, dim3(grid_for(3 * static_cast<int64_t>(g.n[s]))), dim3(kThreads), 0, st, S.s[s],
-                       counts, stats);
+    // a few candidates per thread: the statistics are reduced once per thread
+    const int grid = std::min(grid_for(3 * static_cast<int64_t>(g.n[s])), 2048);
+    hipLaunchKernelGGL(k_count, dim3(grid), dim3(kThreads), 0, st, S.s[s], counts, stats);
     PD_TRY(hipGetLastError());
   }
   exclusive_scan(ct, counts, pos, PlanCountSum{}, nc + 1, st);
