@@ -301,10 +301,47 @@ constexpr int kSmallThreads = 256;
 constexpr int kSmallWaves = kSmallThreads / kWave;
 constexpr int kSmallSlots = 2 * kSmallGroupWork;
 
+// Insertion of a group's wedges into its hash table, with no divergent
+// branch: every lane issues every probe's compare-and-swap and add, lanes
+// with nothing (left) to insert aim them at their own sink word, and the
+// probe loop ends when the wavefront has no pending lane (a ballot).  One
+// compare-and-swap per probe claims an empty slot or finds the key; the
+// count is added to the slot found.
+struct SmallInsert {
+  uint32_t* K;
+  uint32_t* V;
+  uint32_t* sink;  // this lane's sink word
+  uint32_t kb, hshift, mask;
+  unsigned long long* err;
+  __device__ __forceinline__ void add(uint32_t e, uint32_t tag, bool valid) const {
+    const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
+    const uint32_t inc = wedge_inc(e, tag);
+    uint32_t h = (key * 0x9E3779B1u) >> hshift;
+    bool pend = valid;
+    for (uint32_t probe = 0;; ++probe) {
+      const uint32_t c = atomicCAS(pend ? &K[h] : sink, kEmpty, key);
+      const bool hit = pend && (c == kEmpty || c == key);
+      atomicAdd(hit ? &V[h] : sink, inc);
+      pend = pend && !hit;
+      if (__ballot(pend) == 0) break;
+      if (probe == mask) {  // full table: cannot happen at load <= 1/2
+        if (lane_id() == 0) atomicOr(err, kErrHashFull);
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+  }
+};
+
 __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t keys[kSmallWaves][kSmallSlots];
   __shared__ __attribute__((aligned(16))) uint32_t vals[kSmallWaves][kSmallSlots];
-  __shared__ __attribute__((aligned(16))) uint32_t marks[kSmallWaves][2][kGather];
+  // staging marks: bases, and 16-bit tags (item index in the group << 1 | g,
+  // with the presence bit; a group holds at most kSmallMaxItems items)
+  __shared__ __attribute__((aligned(16))) uint32_t mbase[kSmallWaves][kGather];
+  __shared__ uint16_t mtag[kSmallWaves][kGather];
+  __shared__ uint32_t sinks[kSmallWaves][kWave];
+  static_assert(2 * kSmallMaxItems + 1 < (1u << 15), "group tags fit 15 bits");
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
@@ -314,7 +351,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     K[i] = kEmpty;
     Vv[i] = 0;
   }
-  for (int i = lane; i < 2 * static_cast<int>(kGather); i += kWave) (&marks[wave][0][0])[i] = 0;
+  for (int i = lane; i < static_cast<int>(kGather); i += kWave) mtag[wave][i] = 0;
   wave_sync_lds();
   SqTotals tot;
   const int32_t stride = static_cast<int32_t>(gridDim.x) * kSmallWaves;
@@ -341,53 +378,47 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     // table size: a power of two >= 2 * work, at least 64; the home slot is
     // the top log2(size) bits of the key times 2^32 / golden ratio
     // (multiplicative hashing: one multiply)
-    uint32_t size = 64;
-    while (size < 2 * it.work) size <<= 1;
+    const uint32_t w2 = 2 * it.work;
+    const uint32_t size = w2 <= 64 ? 64u : 1u << (32 - __builtin_clz(w2 - 1));
     const uint32_t mask = size - 1;
     const uint32_t hshift = 32u - static_cast<uint32_t>(__builtin_ctz(size));
-    walk_item<4, true>(it, first, sc.small_segs, sc.other_adj, Marks<uint32_t>{marks[wave][0], marks[wave][1]},
-                       a.long_len,
-                       hash_tally([&](uint32_t e, uint32_t tag) {
-                         const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
-                         const uint32_t inc = wedge_inc(e, tag);
-                         uint32_t h = (key * 0x9E3779B1u) >> hshift;
-                         // one compare-and-swap per probe: it claims an
-                         // empty slot, and leaves a taken one as it was
-                         for (uint32_t probe = 0;; ++probe) {
-                           if (probe > mask) {  // full table: cannot happen at load <= 1/2
-                             atomicOr(a.err, kErrHashFull);
-                             break;
-                           }
-                           const uint32_t c = atomicCAS(&K[h], kEmpty, key);
-                           if (c == kEmpty || c == key) {
-                             atomicAdd(&Vv[h], inc);
-                             break;
-                           }
-                           h = (h + 1) & mask;
-                         }
-                       }));
+    walk_item<4, true>(it, first, sc.small_segs, sc.other_adj, Marks<uint16_t>{mbase[wave], mtag[wave]}, a.long_len,
+                       SmallInsert{K, Vv, &sinks[wave][lane], kb, hshift, mask, a.err});
     if (j < a.n_items) nfirst = first_batch<true>(nxt, load_const(a.sides, 2 * nxt.graph + nxt.side).small_segs);
     wave_sync_lds();
     // p, n <= kSmallGroupWork per key and sum p + n <= kSmallGroupWork
-    // per group, so the group's sums of squares stay below 2^19
+    // per group, so the group's sums of squares stay below 2^19.  16-byte
+    // LDS accesses, 4 slots per lane; an empty slot's count is 0, which adds
+    // nothing to the sums.
     SqSums ss;
-    const bool hub = (it.flags & kItemHubPairs) != 0;
-    const uint32_t kmask = (1u << kb) - 1u;
-    // 16-byte LDS accesses, 4 slots per lane; an empty slot's count is 0,
-    // which adds nothing to the sums
-    for (uint32_t h = 4 * lane; h < size; h += 4 * kWave) {
-      const uint4 k4 = *reinterpret_cast<const uint4*>(&K[h]);
-      const uint4 c4 = *reinterpret_cast<const uint4*>(&Vv[h]);
-      *reinterpret_cast<uint4*>(&K[h]) = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
-      *reinterpret_cast<uint4*>(&Vv[h]) = make_uint4(0, 0, 0, 0);
-      const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w}, cc[4] = {c4.x, c4.y, c4.z, c4.w};
+    if (!(it.flags & kItemHubPairs)) {
+      // the keys are only reset
+      for (uint32_t h = 4 * lane; h < size; h += 4 * kWave) {
+        const uint4 c4 = *reinterpret_cast<const uint4*>(&Vv[h]);
+        *reinterpret_cast<uint4*>(&K[h]) = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+        *reinterpret_cast<uint4*>(&Vv[h]) = make_uint4(0, 0, 0, 0);
+        ss.add(c4.x & 0xffffu, c4.x >> 16);
+        ss.add(c4.y & 0xffffu, c4.y >> 16);
+        ss.add(c4.z & 0xffffu, c4.z >> 16);
+        ss.add(c4.w & 0xffffu, c4.w >> 16);
+      }
+    } else {
+      // a hub pivot's item (alone in its group): keys below T are hub pairs
+      const uint32_t kmask = (1u << kb) - 1u;
+      for (uint32_t h = 4 * lane; h < size; h += 4 * kWave) {
+        const uint4 k4 = *reinterpret_cast<const uint4*>(&K[h]);
+        const uint4 c4 = *reinterpret_cast<const uint4*>(&Vv[h]);
+        *reinterpret_cast<uint4*>(&K[h]) = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+        *reinterpret_cast<uint4*>(&Vv[h]) = make_uint4(0, 0, 0, 0);
+        const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w}, cc[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) {
-        const uint32_t key = kk[q4], p = cc[q4] & 0xffffu, q = cc[q4] >> 16;
-        if (hub && key != kEmpty && static_cast<int32_t>(key & kmask) < sc.T)  // singleton group
-          hub_partial(sc, it.owner, key & kmask, p, q);
-        else
-          ss.add(p, q);
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const uint32_t key = kk[q4], p = cc[q4] & 0xffffu, q = cc[q4] >> 16;
+          if (key != kEmpty && static_cast<int32_t>(key & kmask) < sc.T)
+            hub_partial(sc, it.owner, key & kmask, p, q);
+          else
+            ss.add(p, q);
+        }
       }
     }
     tot.add(ss);

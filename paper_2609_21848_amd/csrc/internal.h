@@ -68,7 +68,9 @@ enum ItemKind : uint8_t {
 // many slots).  Inside a group, segments carry the item's index in the group
 // in the high half of len_g: (index << 16) | (len << 1) | g.
 constexpr uint32_t kSmallGroupWork = 512;
-constexpr uint32_t kSmallMaxItems = 65535;
+// ... and at most this many items (the walk's staging tags of a group's
+// runs, item index << 1 | g with a presence bit, fit 16 bits).
+constexpr uint32_t kSmallMaxItems = 16383;
 
 // Reverse items keep two 8-bit counters per key (symmetric, asymmetric), so
 // a reverse item (or item part) has at most this many segments.
