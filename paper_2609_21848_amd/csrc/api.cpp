@@ -299,6 +299,7 @@ struct dbbc_graph {
   DevBuf rev[2], cut[2], grank[2];  // per entry: position in the other row; per row: higher-priority
                                     // prefix; per row: global rank (the planners' input)
   DevBuf pv_out[2][2];    // per-vertex outputs [side][balanced, unbalanced]
+  DevBuf pv_keys[2];      // per side: the direct items' key credits by rank (balanced, then unbalanced)
   DevBuf pe_out[2][3];    // per-edge credits by CSR position [side][packed, wide bal, wide unb]
   DevBuf edge_rec, edge_pos_v;  // U-CSR position -> input record, -> V-CSR position
   DevBuf pe_tmp;          // stands in for a NULL per-edge output
@@ -547,6 +548,8 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
       c.unb = g->pv_out[s][1].as<unsigned long long>();
       c.bal_mid = g->pv_out[1 - s][0].as<unsigned long long>();
       c.unb_mid = g->pv_out[1 - s][1].as<unsigned long long>();
+      c.key_bal = g->pv_keys[s].as<unsigned long long>();
+      c.key_unb = c.key_bal + dbbc::kPVKeyRanks;
       c.seg_edge = d.seg_edge.as<uint32_t>();
       c.small_seg_edge = d.small_seg_edge.as<uint32_t>();
       c.epack = g->pe_out[s][0].as<unsigned long long>();
@@ -824,6 +827,7 @@ int dbbc_graph_stats(const dbbc_graph* g, dbbc_stats* out) {
     b += g->adj[k].bytes + g->off[k].bytes + g->orig[k].bytes + g->raw_ids[k].bytes + g->rev[k].bytes +
          g->cut[k].bytes + g->grank[k].bytes;
     for (int j = 0; j < 2; ++j) b += g->pv_out[k][j].bytes;
+    b += g->pv_keys[k].bytes;
     for (int j = 0; j < 3; ++j) b += g->pe_out[k][j].bytes;
   }
   s.device_bytes = static_cast<int64_t>(b);
@@ -950,6 +954,11 @@ int dbbc_count_read(dbbc_graph* g, dbbc_counts* out_host) {
 
 namespace {
 
+// Direct items' keys lie below the window, at most 32,768 ranks (the widest
+// window_L), so the rank-indexed key sums cover them.
+static_assert(dbbc::kPVKeyRanks >= dbbc::kPVWindowPacked && dbbc::kPVWindowPacked == 32768,
+              "key sums cover the widest window");
+
 // The per-vertex pass, with per-edge credits when edge is set: tally and
 // credit walks over every item of the per-vertex plan, then (per-edge) the
 // combination of the two CSRs' credits into input-record order.
@@ -975,6 +984,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   for (int s = 0; s < 2; ++s) {
     for (int k = 0; k < 2; ++k)
       HIP_TRY(g->pv_out[s][k].reserve(static_cast<size_t>(n[s]) * sizeof(unsigned long long)));
+    HIP_TRY(g->pv_keys[s].reserve(2 * static_cast<size_t>(dbbc::kPVKeyRanks) * sizeof(unsigned long long)));
   }
   if (edge) {
     for (int s = 0; s < 2; ++s)
@@ -1081,8 +1091,11 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
       }
     }
   }
-  // direct items: one launch per side (hot-key credits are summed per
-  // workgroup for one side)
+  // direct items: one launch per side; their key credits are summed by rank
+  // and added to the outputs after both launches
+  for (int s = 0; s < 2; ++s)
+    HIP_TRY(dbbc::launch_fill_u64(g->pv_keys[s].as<unsigned long long>(), 2 * static_cast<size_t>(dbbc::kPVKeyRanks),
+                                  0ull, st));
   for (int s = 0; s < 2; ++s) {
     const int32_t lo = s == 0 ? 0 : hp.n_direct_side0;
     const int32_t hi = s == 0 ? hp.n_direct_side0 : hp.n_items_kept[0];
@@ -1097,6 +1110,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
     const int grid = std::min<int>(cus, std::max(1, a.n_items));
     HIP_TRY(edge ? dbbc::launch_pe_direct(a, grid, st) : dbbc::launch_pv_direct(a, grid, st));
   }
+  for (int s = 0; s < 2; ++s) HIP_TRY(dbbc::launch_pv_key_flush(sides, s, hp.L[s], st));
   // reverse items: one launch per side (their key credits are summed per
   // workgroup for one side's reverse window)
   for (int s = 0; s < 2; ++s) {

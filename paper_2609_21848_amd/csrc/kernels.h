@@ -51,6 +51,10 @@ struct DevSideConst {
   unsigned long long* unb;
   unsigned long long* bal_mid;    // ... of the other side
   unsigned long long* unb_mid;
+  // key credits of the direct items by side-s rank (their keys are below
+  // the window, kPVKeyRanks), added to bal / unb after the direct launches
+  unsigned long long* key_bal;
+  unsigned long long* key_unb;
   // per-edge credits (per-edge pass only): every wedge credits its two
   // edges, the run's first edge (a position in side s's CSR) and the walked
   // entry (a position in the other side's CSR).  Credits of runs without the
@@ -197,6 +201,11 @@ hipError_t launch_hub_credit(const HubCreditArgs& a, hipStream_t st);
 // Per-vertex pass (plans made with per_vertex): direct items, reverse items,
 // small-item groups and hash items.
 hipError_t launch_pv_direct(const DirectArgs& a, int grid, hipStream_t st);
+// Largest rank a per-vertex direct item's key may have (the widest window),
+// and the adding of the rank-indexed key credits of side s (ranks below n)
+// into its per-vertex outputs.
+constexpr int32_t kPVKeyRanks = 32768;
+hipError_t launch_pv_key_flush(const DevSideConst* sides, int32_t s, int32_t n, hipStream_t st);
 hipError_t launch_pv_reverse(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_pv_small(const SmallArgs& a, int grid, hipStream_t st);
 hipError_t launch_pv_hash(const HashArgs& a, int grid, hipStream_t st);

@@ -329,7 +329,9 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     }
     __syncthreads();
     // credit the keys and the owner (packed counts: p + n < 2^16, so a
-    // key's credits fit 32 bits)
+    // key's credits fit 32 bits).  Key credits go to the rank-indexed sums
+    // (the threads' keys are consecutive: one instruction's atomics touch a
+    // few cache lines, where input-id order would scatter them over 64).
     PairCredit pc;
     for (uint32_t k = tid; k < hi - lo; k += kPVDirectThreads) {
       const uint32_t v = C[k];
@@ -344,12 +346,18 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
           sq64 += static_cast<uint64_t>(__umul24(p, p)) + __umul24(n, n);
           pn64 += cx;
           w64 += p + n;
-          if (cb2) atomicAdd(&sc.bal[sc.orig[key]], static_cast<unsigned long long>(cb2));
-          if (cx) atomicAdd(&sc.unb[sc.orig[key]], static_cast<unsigned long long>(cx));
+          if (cb2) atomicAdd(&sc.key_bal[key], static_cast<unsigned long long>(cb2));
+          if (cx) atomicAdd(&sc.key_unb[key], static_cast<unsigned long long>(cx));
           pc.c += cb2;
           pc.x += cx;
         } else {
-          pc.add(sc, key, p, n, sums);
+          sums.add(p, n);
+          const int64_t P64 = p, N64 = n;
+          const int64_t cb64 = P64 * (P64 - 1) / 2 + N64 * (N64 - 1) / 2, cx64 = P64 * N64;
+          if (cb64) atomicAdd(&sc.key_bal[key], static_cast<unsigned long long>(cb64));
+          if (cx64) atomicAdd(&sc.key_unb[key], static_cast<unsigned long long>(cx64));
+          pc.c += cb64;
+          pc.x += cx64;
         }
       }
     }
@@ -357,6 +365,20 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     __syncthreads();
   }
   if (graph != kNoGraph) flush_all(graph);
+}
+
+// The direct items' key credits of side s (by rank, ranks below n) into the
+// per-vertex outputs (input-id order).
+__global__ void k_pv_key_flush(const DevSideConst* sides, int32_t s, int32_t n) {
+  const DevSideConst sc = load_const(sides, s);
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const unsigned long long b = sc.key_bal[k], u = sc.key_unb[k];
+    if (b | u) {
+      const int32_t id = sc.orig[k];
+      if (b) atomicAdd(&sc.bal[id], b);
+      if (u) atomicAdd(&sc.unb[id], u);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -793,6 +815,12 @@ hipError_t launch_pe_direct(const DirectArgs& a, int grid, hipStream_t st) { ret
 hipError_t launch_pe_reverse(const SmallArgs& a, int grid, hipStream_t st) { return reverse_<true>(a, grid, st); }
 hipError_t launch_pe_small(const SmallArgs& a, int grid, hipStream_t st) { return small_<true>(a, grid, st); }
 hipError_t launch_pe_hash(const HashArgs& a, int grid, hipStream_t st) { return hash_<true>(a, grid, st); }
+
+hipError_t launch_pv_key_flush(const DevSideConst* sides, int32_t s, int32_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_pv_key_flush, dim3((n + 255) / 256), dim3(256), 0, st, sides, s, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_edge_combine(const EdgeCombineArgs& a, int grid, hipStream_t st) {
   if (a.m == 0) return hipSuccess;
