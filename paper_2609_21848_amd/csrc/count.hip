@@ -392,16 +392,26 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     // nothing to the sums.
     SqSums ss;
     if (!(it.flags & kItemHubPairs)) {
-      // the keys are only reset
+      // the keys are only reset; a slot's p^2 + n^2 and 2 p n are 16-bit dot
+      // products of its count word with itself and with its halves swapped,
+      // and the sum of p + n over the group is its work
+      uint32_t sq32 = 0, pn32 = 0;
       for (uint32_t h = 4 * lane; h < size; h += 4 * kWave) {
         const uint4 c4 = *reinterpret_cast<const uint4*>(&Vv[h]);
         *reinterpret_cast<uint4*>(&K[h]) = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
         *reinterpret_cast<uint4*>(&Vv[h]) = make_uint4(0, 0, 0, 0);
-        ss.add(c4.x & 0xffffu, c4.x >> 16);
-        ss.add(c4.y & 0xffffu, c4.y >> 16);
-        ss.add(c4.z & 0xffffu, c4.z >> 16);
-        ss.add(c4.w & 0xffffu, c4.w >> 16);
+        const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const u16x2 hh = __builtin_bit_cast(u16x2, cv[q4]);
+          const u16x2 rr = __builtin_bit_cast(u16x2, __builtin_amdgcn_alignbit(cv[q4], cv[q4], 16));
+          sq32 = __builtin_amdgcn_udot2(hh, hh, sq32, false);
+          pn32 = __builtin_amdgcn_udot2(hh, rr, pn32, false);
+        }
       }
+      tot.sq += sq32;
+      tot.pn2 += pn32;
+      if (lane == 0) tot.w += it.work;
     } else {
       // a hub pivot's item (alone in its group): keys below T are hub pairs
       const uint32_t kmask = (1u << kb) - 1u;
