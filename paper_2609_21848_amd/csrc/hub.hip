@@ -54,11 +54,16 @@ struct HubPair {
 
 __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubPair hp) {
   __shared__ __attribute__((aligned(16))) int8_t sm[kHubStages][2][kHubStage];
-  const bool second = static_cast<int32_t>(blockIdx.x) >= hp.tiles0;
+  // workgroups are dealt to the 8 XCDs in turn: give each XCD a run of
+  // consecutive tiles (rows of the upper triangle share their Bm panel)
+  const int nb = static_cast<int>(gridDim.x), b = static_cast<int>(blockIdx.x);
+  const int q8 = nb / 8;
+  const int lin = b < 8 * q8 ? (b % 8) * q8 + b / 8 : b;
+  const bool second = lin >= hp.tiles0;
   const HubArgs a = second ? hp.s[1] : hp.s[0];
   // upper-triangular tile (ti <= tj) from the linear block index
   const int nt = a.T / kHubTile;
-  int t = static_cast<int>(blockIdx.x) - (second ? hp.tiles0 : 0), ti = 0;
+  int t = lin - (second ? hp.tiles0 : 0), ti = 0;
   while (t >= nt - ti) {
     t -= nt - ti;
     ++ti;
