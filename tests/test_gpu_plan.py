@@ -123,3 +123,24 @@ def test_empty_and_tiny_graphs(dbbc):
                 c = h.count(flags=flags)
                 assert (c.balanced, c.unbalanced, c.total, c.wedges) == (r.balanced, r.unbalanced, r.total,
                                                                          r.wedges)
+
+
+def test_planners_agree_at_full_size(dbbc):
+    # the 50M-edge workload: both planners' counts equal the oracle's cached
+    # counts, and every counting kernel gets the same wedges and runs
+    import json
+    import os
+
+    from golden_io import GOLDEN
+    from synth import config_graph
+    with open(os.path.join(GOLDEN, "oracle_cache.json")) as f:
+        cache = json.load(f)["skewed50m"]
+    g = config_graph("skewed50m")
+    want = (cache["balanced"], cache["unbalanced"], cache["total"], cache["wedges"])
+    with dbbc.Graph(g.n_u, g.n_v, g.u, g.v, g.sign) as h:
+        for opts in ({}, dict(window_L=8192, reverse_L=1024, part_work=1 << 20)):
+            _say("planners at full size", opts)
+            got_d, per_d, _ = _timed(dbbc, h, **opts)
+            got_h, per_h, _ = _timed(dbbc, h, flags=dbbc.DBBC_OPT_HOST_PLAN, **opts)
+            assert got_d == want and got_h == want, opts
+            assert per_d == per_h, (opts, per_d, per_h)
