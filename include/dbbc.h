@@ -112,11 +112,12 @@ typedef struct {
  * words (the form the pass uses for edges that may lie in 2^32 or more
  * butterflies) instead of one packed word; for testing the two forms. */
 #define DBBC_OPT_WIDE_EDGES 0x2u
-/* dbbc_options.flags, counts: make the count plan with the host planner (a
- * copy of the graph's arrays to host memory, then loops over its pivots)
- * instead of the device planner's kernels; both split the same wedges into
- * work items (Algorithm 1, Eq. 1), so the counts are the same; for testing
- * the two planners against each other. */
+/* dbbc_options.flags, counts and the per-vertex and per-edge passes: make
+ * the plan with the host planner (a copy of the graph's arrays to host
+ * memory, then loops over its pivots) instead of the device planner's
+ * kernels; both split the same wedges into work items (Algorithm 1, Eq. 1),
+ * so the results are the same; for testing the two planners against each
+ * other. */
 #define DBBC_OPT_HOST_PLAN 0x4u
 
 /* One kernel launch of the last timed count and the work it was given. */

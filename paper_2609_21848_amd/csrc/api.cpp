@@ -370,6 +370,7 @@ dbbc::DevGraphView view_of(const dbbc_graph* g) {
     v.cut[s] = g->cut[s].as<int32_t>();
     v.grank[s] = g->grank[s].as<int32_t>();
     v.ord[s] = g->orig[s].as<int32_t>();
+    v.max_deg[s] = g->host.side[s].max_deg;
   }
   v.rec = g->edge_rec.as<uint32_t>();
   return v;
@@ -383,12 +384,13 @@ int ensure_host(dbbc_graph* g, hipStream_t st) {
   return rc == DBBC_OK ? DBBC_OK : fail(rc, err);
 }
 
-// Count plans are made on the device unless the caller asks for the host
-// planner, or the graph's entries or candidate items exceed the int sizes
-// of the device scans; per-vertex plans are made on the host.
+// Plans are made on the device unless the caller asks for the host planner,
+// or the graph's entries or candidate items (three per vertex, four in a
+// per-vertex plan) exceed the int sizes of the device scans.
 bool plans_on_device(const dbbc_graph* g, const dbbc::PlanParams& p) {
-  if (p.per_vertex || p.host_planner) return false;
-  return 3 * (static_cast<int64_t>(g->host.n_u) + g->host.n_v) + 1 <= INT32_MAX && g->host.m + 1 <= INT32_MAX;
+  if (p.host_planner) return false;
+  const int64_t kinds = p.per_vertex ? 4 : 3;
+  return kinds * (static_cast<int64_t>(g->host.n_u) + g->host.n_v) + 1 <= INT32_MAX && g->host.m + 1 <= INT32_MAX;
 }
 
 int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, DevPlan& d) {
@@ -414,11 +416,24 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
     d.reverse_items = std::move(out.reverse_items);
     d.reduces = std::move(out.reduces);
     d.acc = std::move(out.acc);
+    d.seg_mid = std::move(out.seg_mid);
+    d.seg_edge = std::move(out.seg_edge);
+    d.small_seg_mid = std::move(out.small_seg_mid);
+    d.small_seg_edge = std::move(out.small_seg_edge);
+    d.small_owner = std::move(out.small_owner);
+    d.hub_items = std::move(out.hub_items);
+    d.hub_segs = std::move(out.hub_segs);
     for (int s = 0; s < 2; ++s) {
       d.hub_B[s] = std::move(out.hub_B[s]);
       d.hub_Bm[s] = std::move(out.hub_Bm[s]);
       d.hub_K[s] = out.hub_K[s];
+      d.hub_Bt[s] = std::move(out.hub_Bt[s]);
+      d.hub_Bmt[s] = std::move(out.hub_Bmt[s]);
+      d.hub_Zc[s] = std::move(out.hub_Zc[s]);
+      d.hub_Zcp[s] = std::move(out.hub_Zcp[s]);
+      d.hub_pos[s] = std::move(out.hub_pos[s]);
     }
+    d.any_wide = out.any_wide;
   } else {
     rc = ensure_host(g, st);
     if (rc != DBBC_OK) return rc;
@@ -454,18 +469,27 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   for (int s = 0; s < 2; ++s) {
     d.hub_pairs[s].release();
     if (!on_device) {
-      d.hub_B[s].release();
-      d.hub_Bm[s].release();
+      for (DevBuf* b : {&d.hub_B[s], &d.hub_Bm[s], &d.hub_Bt[s], &d.hub_Bmt[s], &d.hub_Zc[s], &d.hub_Zcp[s],
+                        &d.hub_pos[s]})
+        b->release();
       d.hub_K[s] = 0;
     }
-    for (DevBuf* b : {&d.hub_Bt[s], &d.hub_Bmt[s], &d.hub_Zc[s], &d.hub_Zcp[s], &d.hub_pos[s], &d.hub_rows[s],
-                      &d.hub_cols[s]})
-      b->release();
+    d.hub_rows[s].release();
+    d.hub_cols[s].release();
     d.hub_D[s] = 0;
     const int32_t T = hp.T[s], TO = hp.T[1 - s];
     if (T == 0) continue;
     HIP_TRY(d.hub_pairs[s].alloc(2 * static_cast<size_t>(T) * T * sizeof(int32_t)));
-    if (on_device) continue;  // the device planner wrote B and Bm
+    if (p.per_vertex) {
+      // a pair's counts are at most the side's largest degree: digits of
+      // kHubDigitBits bits, enough for that bound with a signed top digit
+      int32_t D = 1;
+      while ((int64_t{1} << (dbbc::kHubDigitBits * D)) <= g->host.side[s].max_deg) ++D;
+      d.hub_D[s] = D;
+      HIP_TRY(d.hub_rows[s].alloc(2 * static_cast<size_t>(D) * T * T));
+      HIP_TRY(d.hub_cols[s].alloc(2 * static_cast<size_t>(D) * T * T));
+    }
+    if (on_device) continue;  // the device planner wrote B, Bm and the credit products' constants
     // pad the contraction dimension to a multiple of kHubKPad
     const int32_t K = (TO + dbbc::kHubKPad - 1) / dbbc::kHubKPad * dbbc::kHubKPad;
     std::vector<int8_t> B(static_cast<size_t>(T) * K, 0), Bm(static_cast<size_t>(T) * K, 0);
@@ -510,13 +534,6 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
       HIP_TRY(upload(d.hub_Zcp[s], Zcp, st));
       HIP_TRY(upload(d.hub_pos[s], pos, st));
       HIP_TRY(hipStreamSynchronize(st));  // the host vectors leave scope
-      // a pair's counts are at most the side's largest degree: digits of
-      // kHubDigitBits bits, enough for that bound with a signed top digit
-      int32_t D = 1;
-      while ((int64_t{1} << (dbbc::kHubDigitBits * D)) <= S.max_deg) ++D;
-      d.hub_D[s] = D;
-      HIP_TRY(d.hub_rows[s].alloc(2 * static_cast<size_t>(D) * T * T));
-      HIP_TRY(d.hub_cols[s].alloc(2 * static_cast<size_t>(D) * T * T));
     }
     HIP_TRY(upload(d.hub_B[s], B, st));
     HIP_TRY(upload(d.hub_Bm[s], Bm, st));
@@ -563,9 +580,11 @@ int ensure_plan_into(dbbc_graph* g, const dbbc::PlanParams& p, hipStream_t st, D
   HIP_TRY(d.sides.alloc(sizeof(d.side)));
   HIP_TRY(hipMemcpyAsync(d.sides.p, d.side, sizeof(d.side), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
-  d.any_wide = false;
-  for (const auto* v : {&hp.seg_mid, &hp.small_seg_mid})
-    for (uint32_t mid : *v) d.any_wide = d.any_wide || (mid & dbbc::kMidWide) != 0;
+  if (!on_device) {
+    d.any_wide = false;
+    for (const auto* v : {&hp.seg_mid, &hp.small_seg_mid})
+      for (uint32_t mid : *v) d.any_wide = d.any_wide || (mid & dbbc::kMidWide) != 0;
+  }
   // the host plan keeps only what later launches need
   hp.segs.clear();
   hp.segs.shrink_to_fit();
@@ -977,8 +996,6 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   p.per_vertex = true;
   p.hub_T = std::min(p.hub_T, dbbc::kMaxPVHubT);
   p.wide_all = edge && opt && (opt->flags & DBBC_OPT_WIDE_EDGES);
-  rc = ensure_host(g, st);
-  if (rc != DBBC_OK) return rc;
   const int32_t n[2] = {g->host.n_u, g->host.n_v};
   const size_t m = static_cast<size_t>(g->host.m);
   for (int s = 0; s < 2; ++s) {
@@ -989,14 +1006,11 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
   if (edge) {
     for (int s = 0; s < 2; ++s)
       for (int k = 0; k < 3; ++k) HIP_TRY(g->pe_out[s][k].reserve(m * sizeof(unsigned long long)));
-    if (!g->edge_pos_v.p && m > 0) {
-      const dbbc::HostSide& U = g->host.side[0];
-      const dbbc::HostSide& V = g->host.side[1];
-      std::vector<uint32_t> pos_v(m);
-      for (size_t k = 0; k < m; ++k)
-        pos_v[k] = V.off[U.adj[k] >> 1] + static_cast<uint32_t>(U.rev[k]);
-      HIP_TRY(upload(g->edge_pos_v, pos_v, st));
-      HIP_TRY(hipStreamSynchronize(st));  // pos_v leaves scope
+    if (!g->edge_pos_v.p && m > 0) {  // U-CSR position -> V-CSR position of every edge
+      HIP_TRY(g->edge_pos_v.alloc(m * sizeof(uint32_t)));
+      std::string err;
+      rc = dbbc::edge_positions_device(view_of(g), g->edge_pos_v.as<uint32_t>(), st, err);
+      if (rc != DBBC_OK) return fail(rc, err);
     }
   }
   rc = ensure_plan_into(g, p, st, g->pv_plan);

@@ -1,7 +1,7 @@
-// Counting plan built on the device: the work split of make_plan (plan.cpp)
-// for a count, computed from the device CSR with kernels, scans and sorts
-// (the binning step of Algorithm 1 that sizes each pivot's work, Eq. 1,
-// done per CSR entry instead of per pivot on the host).
+// Plans built on the device: the work split of make_plan (plan.cpp), for a
+// count or for the per-vertex pass, computed from the device CSR with
+// kernels, scans and sorts (the binning step of Algorithm 1 that sizes each
+// pivot's work, Eq. 1, done per CSR entry instead of per pivot on the host).
 //
 // Per side s, every CSR entry e of row x, with mid y = adj[e] >> 1, yields at
 // most one run of each kind:
@@ -11,7 +11,10 @@
 //      hub mid (y < T') starts past the dense block;
 //   R  reverse (x >= L): the prefix of row y below both the reverse window
 //      R and y's own higher-priority prefix cut[y];
-//   M  reverse-mid (x >= L, R < L): the part of that prefix in [R, L).
+//   M  reverse-mid (x >= L, R < L): the part of that prefix in [R, L);
+//   H  per-vertex plans, hub pivots (x < T) through non-hub mids (y >= T'):
+//      the part of the forward run below T (the hub pairs' sparse wedges,
+//      tallied apart and completed by the dense block).
 // Each (row, kind) is one candidate item.  Exclusive scans of the run flags
 // and lengths over the entries give every candidate's run count and work as
 // a difference of two scan values, and every run's place in its item.  The
@@ -19,13 +22,19 @@
 // small, hash, direct, reverse); one scan of the candidates' list counts
 // places every item in its list and every run in segs or small_segs.
 //
+// Per-vertex plans also record every run's mid (flagged kMidWide where its
+// credits may need two words) and first-edge position, and the owner of
+// every small item; they have no multi-part items (a direct item is cut into
+// key windows that share its runs) and reverse endpoints with more than
+// kReverseMaxSegs runs become direct items.
 // Where the result differs from make_plan's, both are valid plans of the
 // same wedges (the counts are the same):
 //   - items and runs are listed in candidate order (row, then kind);
 //   - small items are grouped greedily within chunks of kGroupChunk items;
 //   - a split direct item starts a new part at every run that holds a
 //     multiple of part_work in its wedge range (and every kPartMaxRuns
-//     runs), so a part has at most part_work wedges plus its first run.
+//     runs), so a part has at most part_work wedges plus its first run; the
+//     hub pivots' tally items are cut the same way at kHubTallyPartWork.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
@@ -42,8 +51,8 @@ namespace {
 
 constexpr int kThreads = 256;
 
-enum : int { kF = 0, kR = 1, kM = 2 };                                 // run kinds
-enum : int { kSkip = 0, kSmallC = 1, kHashC = 2, kDirectC = 3, kRevC = 4 };  // item classes
+enum : int { kF = 0, kR = 1, kM = 2, kH = 3 };  // run kinds (kH: per-vertex plans only)
+enum : int { kSkip = 0, kSmallC = 1, kHashC = 2, kDirectC = 3, kRevC = 4, kHubC = 5 };  // item classes
 
 constexpr uint32_t kPartMaxRuns = 65535;  // runs of a direct part (16-bit per-part counters)
 constexpr int kGroupChunk = 256;          // small items grouped per chunk
@@ -82,15 +91,19 @@ struct PSide {
   const int32_t* splitR;
   const int32_t* splitT;
   const uint32_t* row;    // row of every entry
-  uint32_t* len[3];       // run length per kind and entry (m + 1, the last 0)
-  uint32_t* cnt[3];       // exclusive scans of len > 0
-  unsigned long long* wsum[3];  // exclusive scans of len
-  uint32_t* bnd[2];       // kinds F and M: exclusive scans of part-start flags
+  uint32_t* len[4];       // run length per kind and entry (m + 1, the last 0)
+  uint32_t* cnt[4];       // exclusive scans of len > 0
+  unsigned long long* wsum[4];  // exclusive scans of len
+  uint32_t* bnd[3];       // kinds F, M (split direct items) and H: exclusive scans of part-start flags
   int32_t* rmax;          // per row: largest key of its reverse runs
   int32_t n, no, L, R, T, TO;
+  int32_t nk;             // run kinds (candidates per row): 3, or 4 in per-vertex plans
+  bool pv;                // a per-vertex plan
+  bool wide_all;          // per-vertex plans: flag every run kMidWide
+  unsigned long long max_deg;  // largest degree of the side (the wide-credit bound)
   int64_t m;
   uint32_t side;
-  int64_t cand0;          // index of the side's first candidate (3 per row)
+  int64_t cand0;          // index of the side's first candidate (nk per row)
   uint32_t small_work;
   unsigned long long part_work;
 };
@@ -117,6 +130,13 @@ __device__ Run run_at(const PSide& P, int k, int32_t x, uint32_t e) {
     } else {
       end = P.ooff[y + 1];
     }
+    return Run{start, end > start ? end - start : 0u};
+  }
+  if (k == kH) {  // hub pivot x through a non-hub mid: the run's keys below T
+    if (x >= P.T || static_cast<int32_t>(y) < P.TO || e < P.off[x] + static_cast<uint32_t>(P.cut[x]))
+      return Run{0, 0};
+    const uint32_t start = yb + static_cast<uint32_t>(P.rev[e]) + 1;
+    const uint32_t end = yb + static_cast<uint32_t>(P.splitT[y]);
     return Run{start, end > start ? end - start : 0u};
   }
   if (x < P.L) return Run{0, 0};
@@ -146,6 +166,19 @@ template <bool kParts>
 __device__ Cand classify(const PSide& P, int32_t x, int k) {
   Cand c{};
   c.cls = kSkip;
+  if (k == kH) {  // a hub pivot's tally item (per-vertex plans): kept with one run
+    if (x >= P.T) return c;
+    const uint32_t b = P.off[x], e = P.off[x + 1];
+    c.nseg = P.cnt[kH][e] - P.cnt[kH][b];
+    if (c.nseg == 0) return c;
+    c.work = P.wsum[kH][e] - P.wsum[kH][b];
+    c.cls = kHubC;
+    c.key_lo = x + 1;
+    c.key_hi = P.T;
+    c.flags = kItemHubPairs;
+    if (kParts) c.nparts = P.bnd[2][e] - P.bnd[2][b];
+    return c;
+  }
   if (k != kF && (x < P.L || (k == kM && P.R == P.L))) return c;
   const uint32_t b = P.off[x], e = P.off[x + 1];
   c.nseg = P.cnt[k][e] - P.cnt[k][b];
@@ -164,6 +197,10 @@ __device__ Cand classify(const PSide& P, int32_t x, int k) {
     // rows are sorted by rank: the keys stop at the largest run end
     c.key_lo = 0;
     c.key_hi = min(P.R, max(P.rmax[x], 0) + 1);
+    if (P.pv) {  // no parts: one reverse item, or a direct item past kReverseMaxSegs runs
+      c.cls = c.nseg > kReverseMaxSegs ? kDirectC : kRevC;
+      return c;
+    }
     c.cls = kRevC;
     c.nparts = c.nseg <= kReverseCountMaxSegs ? 0u : (c.nseg + kReverseCountMaxSegs - 1) / kReverseCountMaxSegs;
   } else {
@@ -171,7 +208,7 @@ __device__ Cand classify(const PSide& P, int32_t x, int k) {
     c.key_hi = P.L;
     c.cls = small ? kSmallC : kDirectC;
   }
-  if (c.cls == kDirectC && (c.work > P.part_work || c.nseg > kPartMaxRuns)) {
+  if (c.cls == kDirectC && !P.pv && (c.work > P.part_work || c.nseg > kPartMaxRuns)) {
     c.split = true;
     if (kParts) {
       const uint32_t* bs = P.bnd[k == kF ? 0 : 1];
@@ -228,8 +265,7 @@ __global__ void k_run_lengths(PSide P) {
   GRID_STRIDE(e64, P.m) {
     const uint32_t e = static_cast<uint32_t>(e64);
     const int32_t x = static_cast<int32_t>(P.row[e]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < P.nk; ++k) {
       const Run r = run_at(P, k, x, e);
       P.len[k][e] = r.len;
       if (k == kR && r.len > 0) atomicMax(&P.rmax[x], static_cast<int32_t>(P.oadj[r.start + r.len - 1] >> 1));
@@ -237,9 +273,10 @@ __global__ void k_run_lengths(PSide P) {
   }
 }
 
-// Part-start flags of the runs of split direct items (kinds F and M): the
-// first run, every kPartMaxRuns-th run, and every run whose wedge range
-// [pex, pex + len) of the item holds a multiple of part_work.
+// Part-start flags of the runs of split direct items (kinds F and M) and of
+// the hub pivots' tally items (kind H): the first run, every kPartMaxRuns-th
+// run, and every run whose wedge range [pex, pex + len) of the item holds a
+// multiple of the part budget (part_work, or kHubTallyPartWork).
 __global__ void k_part_flags(PSide P, int k, uint32_t* flag) {
   GRID_STRIDE(e64, P.m) {
     const uint32_t e = static_cast<uint32_t>(e64);
@@ -248,11 +285,12 @@ __global__ void k_part_flags(PSide P, int k, uint32_t* flag) {
     if (len > 0) {
       const int32_t x = static_cast<int32_t>(P.row[e]);
       const Cand c = classify<false>(P, x, k);
-      if (c.split) {
+      if (c.split || c.cls == kHubC) {
         const uint32_t b = P.off[x];
         const uint32_t j = P.cnt[k][e] - P.cnt[k][b];
         const unsigned long long pex = P.wsum[k][e] - P.wsum[k][b];
-        const unsigned long long pw = P.part_work;
+        const unsigned long long pw =
+            k == kH ? static_cast<unsigned long long>(kHubTallyPartWork) : P.part_work;
         f = (j % kPartMaxRuns == 0 || (pex + len - 1) / pw != (pex - 1) / pw) ? 1u : 0u;
       }
     }
@@ -264,7 +302,8 @@ __global__ void k_part_flags(PSide P, int k, uint32_t* flag) {
 struct PlanCount {
   unsigned long long big_runs;    // runs in segs (hash, direct and reverse items)
   unsigned long long small_runs;  // runs in small_segs
-  uint32_t small_items, hash, direct, direct_parts, direct_split, rev, rev_reduces, rev_acc;
+  unsigned long long hub_runs;    // runs in hub_segs (per-vertex plans)
+  uint32_t small_items, hash, direct, direct_parts, direct_split, rev, rev_reduces, rev_acc, hub_parts, pad;
 };
 
 struct PlanCountSum {
@@ -272,6 +311,9 @@ struct PlanCountSum {
     PlanCount r;
     r.big_runs = a.big_runs + b.big_runs;
     r.small_runs = a.small_runs + b.small_runs;
+    r.hub_runs = a.hub_runs + b.hub_runs;
+    r.hub_parts = a.hub_parts + b.hub_parts;
+    r.pad = 0;
     r.small_items = a.small_items + b.small_items;
     r.hash = a.hash + b.hash;
     r.direct = a.direct + b.direct;
@@ -294,17 +336,26 @@ __device__ unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
+// Per-vertex plans: the key windows of a direct item (kPVWindowPacked keys
+// with packed counters, for fewer than 2^16 runs; else kPVWindow keys).
+__device__ int32_t pv_window(uint32_t nseg) { return nseg < 65536u ? kPVWindowPacked : kPVWindow; }
+__device__ uint32_t pv_window_count(int32_t key_lo, int32_t key_hi, uint32_t nseg) {
+  const uint32_t win = static_cast<uint32_t>(pv_window(nseg));
+  return (static_cast<uint32_t>(key_hi - key_lo) + win - 1) / win;
+}
+
 // Each candidate's list counts; the statistics are summed per thread over
 // its candidates, then per wavefront, then once per wavefront into stats.
 __global__ void k_count(PSide P, PlanCount* counts, unsigned long long* stats) {
-  const int64_t nc = 3 * static_cast<int64_t>(P.n);
+  const int64_t nc = P.nk * static_cast<int64_t>(P.n);
   unsigned long long w[4] = {0, 0, 0, 0}, r[4] = {0, 0, 0, 0}, sparse = 0, skipped = 0;
   GRID_STRIDE(i, nc) {
-    const int32_t x = static_cast<int32_t>(i / 3);
-    const int k = static_cast<int>(i % 3);
+    const int32_t x = static_cast<int32_t>(i / P.nk);
+    const int k = static_cast<int>(i % P.nk);
     const Cand c = classify<true>(P, x, k);
     PlanCount q{};
     int slot = -1;
+    uint32_t mult = 1;
     switch (c.cls) {
       case kSmallC:
         q.small_runs = c.nseg;
@@ -324,6 +375,7 @@ __global__ void k_count(PSide P, PlanCount* counts, unsigned long long* stats) {
           q.direct_split = 1;
         }
         slot = 0;
+        if (P.pv) mult = pv_window_count(c.key_lo, c.key_hi, c.nseg);  // the windows share the runs
         break;
       case kRevC:
         q.big_runs = c.nseg;
@@ -336,14 +388,18 @@ __global__ void k_count(PSide P, PlanCount* counts, unsigned long long* stats) {
         }
         slot = 3;
         break;
+      case kHubC:  // the dense block's sparse wedges: not in the kernels' statistics
+        q.hub_runs = c.nseg;
+        q.hub_parts = c.nparts;
+        break;
       default:
         skipped += c.work;
         break;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      w[j] += j == slot ? c.work : 0ull;
-      r[j] += j == slot ? c.nseg : 0u;
+      w[j] += j == slot ? c.work * mult : 0ull;
+      r[j] += j == slot ? static_cast<unsigned long long>(c.nseg) * mult : 0ull;
     }
     if (slot >= 0) sparse += c.work;
     counts[P.cand0 + i] = q;
@@ -378,6 +434,7 @@ struct DirectMeta {
 
 struct ItemOut {
   Item* small;         // small items (grouped later)
+  int32_t* small_owner;  // per-vertex plans: the owner of every small item
   Item* hash;          // hash items, unordered
   unsigned long long* hash_key;
   Item* direct;        // direct items, unordered
@@ -388,12 +445,12 @@ struct ItemOut {
 };
 
 __global__ void k_items(PSide P, const PlanCount* pos, ItemOut o) {
-  const int64_t nc = 3 * static_cast<int64_t>(P.n);
+  const int64_t nc = P.nk * static_cast<int64_t>(P.n);
   GRID_STRIDE(i, nc) {
-    const int32_t x = static_cast<int32_t>(i / 3);
-    const int k = static_cast<int>(i % 3);
+    const int32_t x = static_cast<int32_t>(i / P.nk);
+    const int k = static_cast<int>(i % P.nk);
     const Cand c = classify<true>(P, x, k);
-    if (c.cls == kSkip) continue;
+    if (c.cls == kSkip || c.cls == kHubC) continue;  // hub tally items: k_hub_parts
     const PlanCount q = pos[P.cand0 + i];
     Item it{};
     it.seg_count = c.nseg;
@@ -408,6 +465,7 @@ __global__ void k_items(PSide P, const PlanCount* pos, ItemOut o) {
     if (c.cls == kSmallC) {
       it.seg_begin = static_cast<uint32_t>(q.small_runs);
       o.small[q.small_items] = it;
+      if (P.pv) o.small_owner[q.small_items] = x;
       continue;
     }
     it.seg_begin = static_cast<uint32_t>(q.big_runs);
@@ -416,7 +474,11 @@ __global__ void k_items(PSide P, const PlanCount* pos, ItemOut o) {
       o.hash_key[q.hash] = c.work;
     } else if (c.cls == kDirectC) {
       o.direct[q.direct] = it;
-      o.direct_key[q.direct] = c.work;
+      // per-vertex plans: side 0 first, then heaviest first (ascending keys);
+      // count plans: heaviest first (descending keys)
+      o.direct_key[q.direct] =
+          P.pv ? (static_cast<unsigned long long>(P.side) << 48) | ((1ull << 48) - 1 - min(c.work, (1ull << 48) - 1))
+               : c.work;
       o.direct_meta[q.direct] = DirectMeta{x, static_cast<uint32_t>(k) | (P.side << 2), c.split ? c.nparts : 0u,
                                            q.direct_parts};
     } else if (c.nparts == 0) {
@@ -455,7 +517,7 @@ __global__ void k_items(PSide P, const PlanCount* pos, ItemOut o) {
 // to the dense path stays alone.  Pass 0 counts each chunk's groups; pass 1
 // writes them and each item's index in its group.
 template <int kPass>
-__global__ void k_group(const Item* small, int64_t n_small, int32_t kb0, int32_t kb1, uint32_t* chunk_groups,
+__global__ void k_group(const Item* small, int64_t n_small, int32_t kb0, int32_t kb1, bool pv, uint32_t* chunk_groups,
                         Item* groups, uint32_t* local_of) {
   const int64_t n_chunks = (n_small + kGroupChunk - 1) / kGroupChunk;
   GRID_STRIDE(ch, n_chunks) {
@@ -482,7 +544,7 @@ __global__ void k_group(const Item* small, int64_t n_small, int32_t kb0, int32_t
         grp = Item{};
         grp.seg_begin = it.seg_begin;
         grp.owner = it.owner;
-        grp.acc_slot = -1;
+        grp.acc_slot = pv ? static_cast<int32_t>(i) : -1;  // per-vertex plans: owners are listed per item
         grp.flags = it.flags & kItemHubPairs;
         grp.side = it.side;
         local = 0;
@@ -509,6 +571,14 @@ struct RunOut {
   Segment* small_segs;
   const uint32_t* local_of;  // small item -> index in its group
   uint32_t* part_start;      // split direct items: the entry of each part's first run
+  // per-vertex plans
+  uint32_t* seg_mid;         // each run's mid (| kMidWide), and its first edge's position
+  uint32_t* seg_edge;
+  uint32_t* small_seg_mid;
+  uint32_t* small_seg_edge;
+  Segment* hub_segs;         // the hub pivots' tally runs
+  uint32_t* hub_part_start;  // ... the entry of each tally item's first run
+  uint32_t* any_wide;        // set when some run is flagged kMidWide
 };
 
 // Every run into its item's place: segs[item's first + j] for the j-th run
@@ -519,19 +589,45 @@ __global__ void k_runs(PSide P, const PlanCount* pos, RunOut o) {
     const int32_t x = static_cast<int32_t>(P.row[e]);
     const uint32_t b = P.off[x];
     const uint32_t g = P.adj[e] & 1u;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    // per-vertex plans: the run's mid, flagged when its credits may reach
+    // 2^32 (the mid's degree times the side's largest degree)
+    uint32_t mid = 0;
+    if (P.pv) {
+      const uint32_t y = P.adj[e] >> 1;
+      const unsigned long long dy = P.ooff[y + 1] - P.ooff[y];
+      const bool wide = P.wide_all || dy * P.max_deg >= (1ull << 32);
+      mid = y | (wide ? kMidWide : 0u);
+    }
+    for (int k = 0; k < P.nk; ++k) {
       if (P.len[k][e] == 0) continue;
       const Cand c = classify<true>(P, x, k);
       if (c.cls == kSkip) continue;
-      const PlanCount q = pos[P.cand0 + 3 * static_cast<int64_t>(x) + k];
+      const PlanCount q = pos[P.cand0 + P.nk * static_cast<int64_t>(x) + k];
       const Run r = run_at(P, k, x, e);
       const uint32_t j = P.cnt[k][e] - P.cnt[k][b];
       const uint32_t len_g = (r.len << 1) | g;
+      if (c.cls == kHubC) {
+        o.hub_segs[q.hub_runs + j] = Segment{r.start, len_g};
+        const uint32_t* bs = P.bnd[2];
+        if (bs[e + 1] != bs[e]) o.hub_part_start[q.hub_parts + (bs[e] - bs[b])] = e;
+        continue;
+      }
+      if (P.pv && (mid & kMidWide) && *reinterpret_cast<volatile uint32_t*>(o.any_wide) == 0)
+        atomicOr(o.any_wide, 1u);
       if (c.cls == kSmallC) {
-        o.small_segs[q.small_runs + j] = Segment{r.start, (o.local_of[q.small_items] << 16) | len_g};
+        const size_t at = q.small_runs + j;
+        o.small_segs[at] = Segment{r.start, (o.local_of[q.small_items] << 16) | len_g};
+        if (P.pv) {
+          o.small_seg_mid[at] = mid;
+          o.small_seg_edge[at] = e;
+        }
       } else {
-        o.segs[q.big_runs + j] = Segment{r.start, len_g};
+        const size_t at = q.big_runs + j;
+        o.segs[at] = Segment{r.start, len_g};
+        if (P.pv) {
+          o.seg_mid[at] = mid;
+          o.seg_edge[at] = e;
+        }
         if (c.split) {
           const uint32_t* bs = P.bnd[k == kF ? 0 : 1];
           if (bs[e + 1] != bs[e]) o.part_start[q.direct_parts + (bs[e] - bs[b])] = e;
@@ -552,6 +648,36 @@ __global__ void k_rev_part_work(Item* rev, int64_t n, const Segment* segs) {
   }
 }
 
+// The hub pivots' tally items (per-vertex plans), one per part of each
+// pivot's hub runs (parts start at the flagged runs).
+__global__ void k_hub_parts(PSide P, const PlanCount* pos, const uint32_t* part_start, Item* out) {
+  GRID_STRIDE(x64, P.T) {
+    const int32_t x = static_cast<int32_t>(x64);
+    const Cand c = classify<true>(P, x, kH);
+    if (c.cls != kHubC) continue;
+    const PlanCount q = pos[P.cand0 + P.nk * static_cast<int64_t>(x) + kH];
+    const uint32_t b = P.off[x], end = P.off[x + 1];
+    const uint32_t* cnt = P.cnt[kH];
+    const unsigned long long* ws = P.wsum[kH];
+    for (uint32_t p = 0; p < c.nparts; ++p) {
+      const uint32_t es = part_start[q.hub_parts + p];
+      const uint32_t en = p + 1 < c.nparts ? part_start[q.hub_parts + p + 1] : end;
+      Item it{};
+      it.seg_begin = static_cast<uint32_t>(q.hub_runs) + (cnt[es] - cnt[b]);
+      it.seg_count = cnt[en] - cnt[es];
+      it.owner = x;
+      it.key_lo = c.key_lo;
+      it.key_hi = c.key_hi;
+      it.acc_slot = -1;
+      it.flags = c.flags;
+      it.side = P.side;
+      it.work = dsat32(ws[en] - ws[es]);
+      it.graph = 0;
+      out[q.hub_parts + p] = it;
+    }
+  }
+}
+
 __global__ void k_gather_items(const Item* in, const uint32_t* perm, int64_t n, Item* out) {
   GRID_STRIDE(i, n) out[i] = in[perm[i]];
 }
@@ -568,8 +694,14 @@ struct DirectCountSum {
   }
 };
 
-__global__ void k_direct_count(const DirectMeta* meta, const uint32_t* perm, int64_t n, DirectCount* out) {
+__global__ void k_direct_count(const Item* direct, const DirectMeta* meta, const uint32_t* perm, int64_t n, bool pv,
+                               DirectCount* out) {
   GRID_STRIDE(i, n) {
+    if (pv) {  // every item as its key windows, in order
+      const Item& it = direct[perm[i]];
+      out[i] = DirectCount{pv_window_count(it.key_lo, it.key_hi, it.seg_count), 0u, 0u};
+      continue;
+    }
     const uint32_t np = meta[perm[i]].nparts;
     out[i] = DirectCount{np, np ? 0u : 1u, np ? 1u : 0u};
   }
@@ -581,6 +713,8 @@ struct DirectOut {
   uint32_t n_parts;     // parts of all split items (the singles follow)
   uint32_t acc0;        // first accumulator slot of the direct parts
   uint32_t red0;        // first reduce of the split direct items
+  bool pv;              // per-vertex plan: key windows
+  uint32_t* side0;      // per-vertex plans: the count of side-0 windows
 };
 
 __global__ void k_direct_write(PSides S, const Item* direct, const DirectMeta* meta, const uint32_t* perm,
@@ -589,6 +723,20 @@ __global__ void k_direct_write(PSides S, const Item* direct, const DirectMeta* m
     const Item it = direct[perm[i]];
     const DirectMeta md = meta[perm[i]];
     const DirectCount q = pos[i];
+    if (o.pv) {
+      const uint32_t nw = pv_window_count(it.key_lo, it.key_hi, it.seg_count);
+      const bool packed = it.seg_count < 65536u;
+      const int32_t win = pv_window(it.seg_count);
+      for (uint32_t w = 0; w < nw; ++w) {
+        Item iw = it;
+        iw.key_lo = it.key_lo + static_cast<int32_t>(w) * win;
+        iw.key_hi = min(it.key_hi, iw.key_lo + win);
+        if (packed) iw.flags |= kItemPacked;
+        o.items[q.parts + w] = iw;
+      }
+      if (it.side == 0) atomicAdd(o.side0, nw);
+      continue;
+    }
     if (md.nparts == 0) {
       o.items[o.n_parts + q.single] = it;
       continue;
@@ -624,8 +772,10 @@ __global__ void k_direct_write(PSides S, const Item* direct, const DirectMeta* m
 
 // The dense block's signs: B[x][y] for x < T, y < T' (rows of K bytes), and
 // Bm keeps those of mids above x in the global order.
+// (pos, per-vertex plans: the CSR position of every hub edge)
 __global__ void k_hub_signs(const uint32_t* off, const uint32_t* adj, const uint32_t* rows, const int32_t* grank_s,
-                            const int32_t* grank_o, int32_t T, int32_t TO, int32_t K, int8_t* B, int8_t* Bm) {
+                            const int32_t* grank_o, int32_t T, int32_t TO, int32_t K, int8_t* B, int8_t* Bm,
+                            int32_t* pos) {
   const int64_t ne = off[T];
   GRID_STRIDE(e, ne) {
     const uint32_t x = rows[e];
@@ -635,7 +785,42 @@ __global__ void k_hub_signs(const uint32_t* off, const uint32_t* adj, const uint
     const size_t at = static_cast<size_t>(x) * K + y;
     B[at] = sg;
     if (grank_o[y] > grank_s[x]) Bm[at] = sg;
+    if (pos) pos[at] = static_cast<int32_t>(e);
   }
+}
+
+// The transposes of B and Bm (K x T): Bt[y][x] = B[x][y].
+__global__ void k_hub_transpose(const int8_t* B, const int8_t* Bm, int32_t T, int32_t K, int8_t* Bt, int8_t* Bmt) {
+  const int64_t n = static_cast<int64_t>(T) * K;
+  GRID_STRIDE(i, n) {  // i = y T + x: coalesced writes
+    const int64_t y = i / T, x = i % T;
+    Bt[i] = B[x * K + y];
+    Bmt[i] = Bm[x * K + y];
+  }
+}
+
+// Per column y: Zc[x][y] = #{w > x : B[w][y] != 0} and
+// Zc'[w][y] = #{x < w : Bm[x][y] != 0} (T x K each).
+__global__ void k_hub_col_counts(const int8_t* B, const int8_t* Bm, int32_t T, int32_t K, int32_t* Zc, int32_t* Zcp) {
+  GRID_STRIDE(y, K) {
+    int32_t below = 0;
+    for (int32_t x = T - 1; x >= 0; --x) {
+      Zc[static_cast<size_t>(x) * K + y] = below;
+      below += B[static_cast<size_t>(x) * K + y] != 0;
+    }
+    int32_t above = 0;
+    for (int32_t w = 0; w < T; ++w) {
+      Zcp[static_cast<size_t>(w) * K + y] = above;
+      above += Bm[static_cast<size_t>(w) * K + y] != 0;
+    }
+  }
+}
+
+// U-CSR position k -> V-CSR position of the same edge: row y = adj_u[k] >> 1
+// of V, at the entry's reverse position.
+__global__ void k_edge_positions(const uint32_t* adj_u, const int32_t* rev_u, const uint32_t* off_v, int64_t m,
+                                 uint32_t* out) {
+  GRID_STRIDE(k, m) out[k] = off_v[adj_u[k] >> 1] + static_cast<uint32_t>(rev_u[k]);
 }
 
 // ---- host side ------------------------------------------------------------------
@@ -691,6 +876,14 @@ void sort_desc(CubTmp& ct, const unsigned long long* kin, unsigned long long* ko
                                                       st));
 }
 
+void sort_asc(CubTmp& ct, const unsigned long long* kin, unsigned long long* kout, const uint32_t* vin,
+              uint32_t* vout, int64_t n, hipStream_t st) {
+  size_t need = 0;
+  PD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, static_cast<int>(n), 0, 64, st));
+  void* t = ct.get(need);
+  PD_TRY(hipcub::DeviceRadixSort::SortPairs(t, need, kin, kout, vin, vout, static_cast<int>(n), 0, 64, st));
+}
+
 template <class T>
 T* alloc_n(DevBuf& b, int64_t n) {
   PD_TRY(b.alloc(static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(T)));
@@ -699,7 +892,7 @@ T* alloc_n(DevBuf& b, int64_t n) {
 
 // One side's scratch arrays.
 struct SideBufs {
-  DevBuf rows, rows_tmp, splitL, splitR, splitT, rmax, len[3], cnt[3], wsum[3], bnd[2];
+  DevBuf rows, rows_tmp, splitL, splitR, splitT, rmax, len[4], cnt[4], wsum[4], bnd[3];
 };
 
 void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& hp, DevPlanLists& out) {
@@ -726,7 +919,11 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     P.TO = hp.T[o];
     P.m = m;
     P.side = static_cast<uint32_t>(s);
-    P.cand0 = s == 0 ? 0 : 3 * static_cast<int64_t>(g.n[0]);
+    P.pv = p.per_vertex;
+    P.nk = P.pv ? 4 : 3;
+    P.wide_all = p.wide_all;
+    P.max_deg = static_cast<unsigned long long>(g.max_deg[s]);
+    P.cand0 = s == 0 ? 0 : P.nk * static_cast<int64_t>(g.n[0]);
     P.small_work = static_cast<uint32_t>(p.small_work);
     P.part_work = static_cast<unsigned long long>(p.part_work);
     // the row of every entry
@@ -754,7 +951,7 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     P.splitT = sT;
     P.rmax = alloc_n<int32_t>(B.rmax, P.n);
     fill_u32(reinterpret_cast<uint32_t*>(P.rmax), P.n, 0u, st);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < P.nk; ++k) {
       P.len[k] = alloc_n<uint32_t>(B.len[k], m + 1);
       fill_u32(P.len[k] + m, 1, 0u, st);
     }
@@ -762,18 +959,19 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
       hipLaunchKernelGGL(k_run_lengths, dim3(grid_for(m)), dim3(kThreads), 0, st, P);
       PD_TRY(hipGetLastError());
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < P.nk; ++k) {
       P.cnt[k] = alloc_n<uint32_t>(B.cnt[k], m + 1);
       P.wsum[k] = alloc_n<unsigned long long>(B.wsum[k], m + 1);
       exclusive_sum(ct, rocprim::make_transform_iterator(P.len[k], NonZero{}), P.cnt[k], m + 1, st);
       exclusive_sum(ct, rocprim::make_transform_iterator(P.len[k], Widen{}), P.wsum[k], m + 1, st);
     }
-    // part starts of split direct items (kinds F and M); the flags borrow
-    // the row scratch of the other kind's scan
+    // part starts of split direct items (kinds F and M; count plans) or of
+    // the hub pivots' tally items (kind H; per-vertex plans)
     DevBuf flags;
     uint32_t* fl = alloc_n<uint32_t>(flags, m + 1);
-    for (int j = 0; j < 2; ++j) {
-      const int k = j == 0 ? kF : kM;
+    for (int j = 0; j < 3; ++j) {
+      if ((j == 2) != P.pv) continue;
+      const int k = j == 0 ? kF : j == 1 ? kM : kH;
       fill_u32(fl + m, 1, 0u, st);
       if (m > 0) {
         hipLaunchKernelGGL(k_part_flags, dim3(grid_for(m)), dim3(kThreads), 0, st, P, k, fl);
@@ -785,7 +983,8 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   }
 
   // candidates of both sides, one scan of their list counts
-  const int64_t nc = 3 * (static_cast<int64_t>(g.n[0]) + g.n[1]);
+  const int nk = S.s[0].nk;
+  const int64_t nc = nk * (static_cast<int64_t>(g.n[0]) + g.n[1]);
   DevBuf counts_b, pos_b, stats_b;
   PlanCount* counts = alloc_n<PlanCount>(counts_b, nc + 1);
   PlanCount* pos = alloc_n<PlanCount>(pos_b, nc + 1);
@@ -794,21 +993,22 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   PD_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(counts + nc), sizeof(PlanCount) / 8, 0ull, st));
   for (int s = 0; s < 2; ++s) {
     // a few candidates per thread: the statistics are reduced once per thread
-    const int grid = std::min(grid_for(3 * static_cast<int64_t>(g.n[s])), 2048);
+    const int grid = std::min(grid_for(nk * static_cast<int64_t>(g.n[s])), 2048);
     hipLaunchKernelGGL(k_count, dim3(grid), dim3(kThreads), 0, st, S.s[s], counts, stats);
     PD_TRY(hipGetLastError());
   }
   exclusive_scan(ct, counts, pos, PlanCountSum{}, nc + 1, st);
   counts_b.release();
-  PlanCount tot{};
+  PlanCount tot{}, at1{};  // the totals, and the positions of side 1's first candidate
   unsigned long long hstats[kStWords];
   PD_TRY(hipMemcpyAsync(&tot, pos + nc, sizeof(tot), hipMemcpyDeviceToHost, st));
+  PD_TRY(hipMemcpyAsync(&at1, pos + S.s[1].cand0, sizeof(at1), hipMemcpyDeviceToHost, st));
   PD_TRY(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, st));
   PD_TRY(hipStreamSynchronize(st));
   {
     PlanSizes z{};
-    z.runs = std::max(tot.big_runs, tot.small_runs);
-    z.items = std::max<uint64_t>({tot.small_items, tot.hash, tot.rev,
+    z.runs = std::max({tot.big_runs, tot.small_runs, tot.hub_runs});
+    z.items = std::max<uint64_t>({tot.small_items, tot.hash, tot.rev, tot.hub_parts,
                                   uint64_t{tot.direct_parts} + tot.direct - tot.direct_split});
     z.reduces = uint64_t{tot.rev_reduces} + tot.direct_split;
     z.acc_slots = uint64_t{tot.rev_acc} + tot.direct_parts;
@@ -817,7 +1017,7 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     if (rc != DBBC_OK) throw Fail{rc, err};
   }
   const int64_t n_small = tot.small_items, n_hash = tot.hash, n_direct = tot.direct, n_rev = tot.rev;
-  const int64_t n_dir_items = int64_t{tot.direct_parts} + tot.direct - tot.direct_split;
+  int64_t n_dir_items = int64_t{tot.direct_parts} + tot.direct - tot.direct_split;  // per-vertex: the windows
   const int64_t n_reduces = int64_t{tot.rev_reduces} + tot.direct_split;
   const int64_t acc_slots = int64_t{tot.rev_acc} + tot.direct_parts;
 
@@ -832,8 +1032,9 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   io.direct_meta = alloc_n<DirectMeta>(direct_meta_b, n_direct);
   io.rev = alloc_n<Item>(out.reverse_items, n_rev);
   io.reduces = alloc_n<Reduce>(out.reduces, n_reduces);
+  if (p.per_vertex) io.small_owner = alloc_n<int32_t>(out.small_owner, n_small);
   for (int s = 0; s < 2; ++s) {
-    hipLaunchKernelGGL(k_items, dim3(grid_for(3 * static_cast<int64_t>(g.n[s]))), dim3(kThreads), 0, st, S.s[s],
+    hipLaunchKernelGGL(k_items, dim3(grid_for(nk * static_cast<int64_t>(g.n[s]))), dim3(kThreads), 0, st, S.s[s],
                        pos, io);
     PD_TRY(hipGetLastError());
   }
@@ -852,7 +1053,7 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   fill_u32(chunk_cnt + n_chunks, 1, 0u, st);
   if (n_chunks > 0) {
     hipLaunchKernelGGL(k_group<0>, dim3(grid_for(n_chunks)), dim3(kThreads), 0, st, io.small, n_small, hp.key_bits[0],
-                       hp.key_bits[1], chunk_cnt, nullptr, nullptr);
+                       hp.key_bits[1], p.per_vertex, chunk_cnt, nullptr, nullptr);
     PD_TRY(hipGetLastError());
   }
   exclusive_sum(ct, chunk_cnt, chunk_pos, n_chunks + 1, st);
@@ -862,7 +1063,7 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   Item* groups = alloc_n<Item>(out.small_groups, n_groups);
   if (n_chunks > 0) {
     hipLaunchKernelGGL(k_group<1>, dim3(grid_for(n_chunks)), dim3(kThreads), 0, st, io.small, n_small,
-                       hp.key_bits[0], hp.key_bits[1], chunk_pos, groups, local_of);
+                       hp.key_bits[0], hp.key_bits[1], p.per_vertex, chunk_pos, groups, local_of);
     PD_TRY(hipGetLastError());
   }
 
@@ -872,6 +1073,17 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   ro.small_segs = alloc_n<Segment>(out.small_segs, static_cast<int64_t>(tot.small_runs));
   ro.local_of = local_of;
   ro.part_start = alloc_n<uint32_t>(part_start_b, tot.direct_parts);
+  DevBuf hub_part_start_b, wide_b;
+  if (p.per_vertex) {
+    ro.seg_mid = alloc_n<uint32_t>(out.seg_mid, static_cast<int64_t>(tot.big_runs));
+    ro.seg_edge = alloc_n<uint32_t>(out.seg_edge, static_cast<int64_t>(tot.big_runs));
+    ro.small_seg_mid = alloc_n<uint32_t>(out.small_seg_mid, static_cast<int64_t>(tot.small_runs));
+    ro.small_seg_edge = alloc_n<uint32_t>(out.small_seg_edge, static_cast<int64_t>(tot.small_runs));
+    ro.hub_segs = alloc_n<Segment>(out.hub_segs, static_cast<int64_t>(tot.hub_runs));
+    ro.hub_part_start = alloc_n<uint32_t>(hub_part_start_b, tot.hub_parts);
+    ro.any_wide = alloc_n<uint32_t>(wide_b, 2);  // [0]: a wide run; [1]: side-0 direct windows
+    fill_u32(ro.any_wide, 2, 0u, st);
+  }
   for (int s = 0; s < 2; ++s) {
     if (g.m == 0) break;
     hipLaunchKernelGGL(k_runs, dim3(grid_for(g.m)), dim3(kThreads), 0, st, S.s[s], pos, ro);
@@ -880,6 +1092,15 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
   if (n_rev > 0) {
     hipLaunchKernelGGL(k_rev_part_work, dim3(grid_for(n_rev)), dim3(kThreads), 0, st, io.rev, n_rev, ro.segs);
     PD_TRY(hipGetLastError());
+  }
+  if (p.per_vertex) {  // the hub pivots' tally items, side 0 first
+    Item* hub_items = alloc_n<Item>(out.hub_items, tot.hub_parts);
+    for (int s = 0; s < 2; ++s) {
+      if (S.s[s].T == 0) continue;
+      hipLaunchKernelGGL(k_hub_parts, dim3(grid_for(S.s[s].T)), dim3(kThreads), 0, st, S.s[s], pos,
+                         ro.hub_part_start, hub_items);
+      PD_TRY(hipGetLastError());
+    }
   }
 
   // hash items, heaviest first
@@ -905,20 +1126,40 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     dout.n_parts = tot.direct_parts;
     dout.acc0 = tot.rev_acc;
     dout.red0 = tot.rev_reduces;
+    dout.pv = p.per_vertex;
+    dout.side0 = p.per_vertex ? ro.any_wide + 1 : nullptr;
     if (n_direct > 0) {
       unsigned long long* kout = alloc_n<unsigned long long>(kout_b, n_direct);
       uint32_t* vin = alloc_n<uint32_t>(vin_b, n_direct);
       uint32_t* perm = alloc_n<uint32_t>(perm_b, n_direct);
       hipLaunchKernelGGL(k_iota, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, vin, n_direct);
       PD_TRY(hipGetLastError());
-      sort_desc(ct, io.direct_key, kout, vin, perm, n_direct, st);
+      if (p.per_vertex)  // side 0 first, heaviest first within a side (ascending keys)
+        sort_asc(ct, io.direct_key, kout, vin, perm, n_direct, st);
+      else
+        sort_desc(ct, io.direct_key, kout, vin, perm, n_direct, st);
       DevBuf dc_b, dpos_b;
       DirectCount* dc = alloc_n<DirectCount>(dc_b, n_direct + 1);
       DirectCount* dpos = alloc_n<DirectCount>(dpos_b, n_direct + 1);
-      hipLaunchKernelGGL(k_direct_count, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, io.direct_meta, perm,
-                         n_direct, dc);
+      hipLaunchKernelGGL(k_direct_count, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, io.direct, io.direct_meta,
+                         perm, n_direct, p.per_vertex, dc);
       PD_TRY(hipGetLastError());
-      exclusive_scan(ct, dc, dpos, DirectCountSum{}, n_direct, st);
+      if (p.per_vertex) {  // the windows' total sizes the list
+        fill_u32(reinterpret_cast<uint32_t*>(dc + n_direct), sizeof(DirectCount) / 4, 0u, st);
+        exclusive_scan(ct, dc, dpos, DirectCountSum{}, n_direct + 1, st);
+        DirectCount t{};
+        PD_TRY(hipMemcpyAsync(&t, dpos + n_direct, sizeof(t), hipMemcpyDeviceToHost, st));
+        PD_TRY(hipStreamSynchronize(st));
+        n_dir_items = t.parts;
+        PlanSizes z{};
+        z.items = static_cast<uint64_t>(n_dir_items);
+        std::string err;
+        const int rc = check_plan_sizes(z, err);
+        if (rc != DBBC_OK) throw Fail{rc, err};
+        dout.items = alloc_n<Item>(out.direct_items, n_dir_items);
+      } else {
+        exclusive_scan(ct, dc, dpos, DirectCountSum{}, n_direct, st);
+      }
       hipLaunchKernelGGL(k_direct_write, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, S, io.direct,
                          io.direct_meta, perm, dpos, n_direct, ro.part_start, dout);
       PD_TRY(hipGetLastError());
@@ -938,14 +1179,40 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     int8_t* Bm = alloc_n<int8_t>(out.hub_Bm[s], static_cast<int64_t>(TK));
     PD_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(Bs), TK / 8, 0ull, st));
     PD_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(Bm), TK / 8, 0ull, st));
-    hipLaunchKernelGGL(k_hub_signs, dim3(grid_for(static_cast<int64_t>(g.m))), dim3(kThreads), 0, st, g.off[s],
-                       g.adj[s], S.s[s].row, g.grank[s], g.grank[1 - s], T, TO, K, Bs, Bm);
-    PD_TRY(hipGetLastError());
+    int32_t* hpos = nullptr;
+    if (p.per_vertex) {  // T K is a multiple of 128 kHubKPad: whole words
+      hpos = alloc_n<int32_t>(out.hub_pos[s], static_cast<int64_t>(TK));
+      PD_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(hpos), TK / 2, ~0ull, st));
+    }
+    if (g.m > 0) {
+      hipLaunchKernelGGL(k_hub_signs, dim3(grid_for(static_cast<int64_t>(g.m))), dim3(kThreads), 0, st, g.off[s],
+                         g.adj[s], S.s[s].row, g.grank[s], g.grank[1 - s], T, TO, K, Bs, Bm, hpos);
+      PD_TRY(hipGetLastError());
+    }
+    if (p.per_vertex) {  // the credit products' constants
+      int8_t* Bt = alloc_n<int8_t>(out.hub_Bt[s], static_cast<int64_t>(TK));
+      int8_t* Bmt = alloc_n<int8_t>(out.hub_Bmt[s], static_cast<int64_t>(TK));
+      int32_t* Zc = alloc_n<int32_t>(out.hub_Zc[s], static_cast<int64_t>(TK));
+      int32_t* Zcp = alloc_n<int32_t>(out.hub_Zcp[s], static_cast<int64_t>(TK));
+      hipLaunchKernelGGL(k_hub_transpose, dim3(grid_for(static_cast<int64_t>(TK))), dim3(kThreads), 0, st, Bs, Bm,
+                         T, K, Bt, Bmt);
+      PD_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_hub_col_counts, dim3(grid_for(K)), dim3(kThreads), 0, st, Bs, Bm, T, K, Zc, Zcp);
+      PD_TRY(hipGetLastError());
+    }
     out.hub_K[s] = K;
   }
+  uint32_t flags_h[2] = {0, 0};
+  if (p.per_vertex) PD_TRY(hipMemcpyAsync(flags_h, ro.any_wide, sizeof(flags_h), hipMemcpyDeviceToHost, st));
   PD_TRY(hipStreamSynchronize(st));
+  out.any_wide = flags_h[0] != 0;
 
   hp.acc_slots = static_cast<int32_t>(acc_slots);
+  hp.n_reverse_side0 = static_cast<int32_t>(at1.rev);
+  if (p.per_vertex) {
+    hp.n_direct_side0 = static_cast<int32_t>(flags_h[1]);
+    hp.n_hub_side0 = static_cast<int32_t>(at1.hub_parts);
+  }
   hp.n_items_kept[0] = static_cast<int32_t>(n_dir_items);
   hp.n_items_kept[1] = static_cast<int32_t>(n_rev);
   hp.n_items_kept[2] = static_cast<int32_t>(n_groups);
@@ -963,14 +1230,10 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
 
 int make_plan_device(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& hp, DevPlanLists& out,
                      std::string& err) {
-  if (p.per_vertex) {
-    err = "internal: the device planner makes count plans only";
-    return DBBC_E_INVALID_ARG;
-  }
   int rc = check_plan_params(p, err);
   if (rc != DBBC_OK) return rc;
   // hipCUB takes int sizes: candidates and entries (plus one) must fit
-  if (3 * (static_cast<int64_t>(g.n[0]) + g.n[1]) + 1 > INT32_MAX || g.m + 1 > INT32_MAX) {
+  if ((p.per_vertex ? 4 : 3) * (static_cast<int64_t>(g.n[0]) + g.n[1]) + 1 > INT32_MAX || g.m + 1 > INT32_MAX) {
     err = "graph too large for the device planner";
     return DBBC_E_TOO_LARGE;
   }
@@ -987,6 +1250,22 @@ int make_plan_device(const DevGraphView& g, const PlanParams& p, hipStream_t st,
     err = "host allocation failed while planning";
     (void)hipStreamSynchronize(st);
     return DBBC_E_OOM;
+  }
+  return DBBC_OK;
+}
+
+}  // namespace dbbc
+
+namespace dbbc {
+
+int edge_positions_device(const DevGraphView& g, uint32_t* out, hipStream_t st, std::string& err) {
+  if (g.m == 0) return DBBC_OK;
+  hipLaunchKernelGGL(k_edge_positions, dim3(grid_for(g.m)), dim3(kThreads), 0, st, g.adj[0], g.rev[0], g.off[1], g.m,
+                     out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    err = std::string("edge positions: ") + hipGetErrorString(e);
+    return DBBC_E_DEVICE;
   }
   return DBBC_OK;
 }

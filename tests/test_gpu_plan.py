@@ -1,12 +1,16 @@
 """GPU: the device planner against the host planner and the oracle.
 
-Count plans are made on the device by default (kernels and scans over the
-CSR entries); DBBC_OPT_HOST_PLAN makes them with the host planner.  Both split
+Plans are made on the device by default (kernels and scans over the CSR
+entries); DBBC_OPT_HOST_PLAN makes them with the host planner.  Both split
 the same vertex-priority wedges (Algorithm 1, with each pivot's work sized as
 in Eq. 1) into the same classes of work items, so per counting kernel the
 wedges and the CSR runs handed to it must be equal, and both counts must equal
 the oracle's.  The grouping of small items and the parts of heavy items may
 differ between the planners; the item counts are therefore not compared.
+Per-vertex and per-edge plans (tagged runs, key windows, the hub pivots'
+tally items, the dense block's credit constants) are checked through their
+results: every vertex's and every edge's counts from both planners equal the
+oracle's.
 """
 
 import numpy as np
@@ -144,3 +148,48 @@ def test_planners_agree_at_full_size(dbbc):
             got_h, per_h, _ = _timed(dbbc, h, flags=dbbc.DBBC_OPT_HOST_PLAN, **opts)
             assert got_d == want and got_h == want, opts
             assert per_d == per_h, (opts, per_d, per_h)
+
+
+WIDE = 0x2  # DBBC_OPT_WIDE_EDGES
+
+
+def test_per_vertex_and_per_edge_planners_agree(dbbc):
+    graphs = [
+        ("chung_lu_3k", _as_tuple(chung_lu_graph(3000, 2500, 60000, 2.0, 1.9, 0.4, seed=5)),
+         ({}, dict(window_L=256, reverse_L=64, small_work=2), dict(hub_T=256, window_L=512, reverse_L=128))),
+        ("planted_reverse_parts", _planted_reverse_parts(),
+         (dict(window_L=256, reverse_L=64), dict(hub_T=128, window_L=256, reverse_L=64))),
+        ("dense", _as_tuple(chung_lu_graph(1200, 1000, 300000, 3.0, 3.0, 0.45, seed=9)),
+         (dict(hub_T=512), dict(hub_T=1024, window_L=1024, reverse_L=256), dict(hub_T=0, window_L=256))),
+    ]
+    for name, (n_u, n_v, u, v, s), opts_list in graphs:
+        r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, per_edge=True)
+        with dbbc.Graph(n_u, n_v, u, v, s) as h:
+            for opts in opts_list:
+                for flags in (0, dbbc.DBBC_OPT_HOST_PLAN):
+                    _say("per-vertex planners", name, opts, flags)
+                    c, bu, bv, uu, uv = h.count_per_vertex(flags=flags, **opts)
+                    assert (c.balanced, c.unbalanced, c.total) == (r.balanced, r.unbalanced, r.total)
+                    for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
+                        assert np.array_equal(t.cpu().numpy(), want), (name, opts, flags)
+                    for f in (flags, flags | WIDE):
+                        c, be, ue = h.count_per_edge(flags=f, **opts)
+                        assert (c.balanced, c.unbalanced, c.total) == (r.balanced, r.unbalanced, r.total)
+                        assert np.array_equal(be.cpu().numpy(), r.bal_e), (name, opts, f)
+                        assert np.array_equal(ue.cpu().numpy(), r.unb_e), (name, opts, f)
+
+
+def test_per_vertex_empty_and_tiny_graphs(dbbc):
+    cases = [(1, 1, [], [], []), (2, 3, [0], [2], [-1]), (3, 3, [0, 0, 1, 1], [0, 1, 0, 1], [1, -1, -1, 1])]
+    for n_u, n_v, u, v, s in cases:
+        u = np.asarray(u, np.int32)
+        v = np.asarray(v, np.int32)
+        s = np.asarray(s, np.int8)
+        r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, per_edge=True)
+        with dbbc.Graph(n_u, n_v, u, v, s) as h:
+            for flags in (0, dbbc.DBBC_OPT_HOST_PLAN):
+                _, bu, bv, uu, uv = h.count_per_vertex(flags=flags)
+                for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
+                    assert np.array_equal(t.cpu().numpy(), want), (n_u, n_v, flags)
+                _, be, ue = h.count_per_edge(flags=flags)
+                assert np.array_equal(be.cpu().numpy(), r.bal_e) and np.array_equal(ue.cpu().numpy(), r.unb_e)
