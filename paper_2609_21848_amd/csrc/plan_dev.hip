@@ -714,7 +714,6 @@ struct DirectOut {
   uint32_t acc0;        // first accumulator slot of the direct parts
   uint32_t red0;        // first reduce of the split direct items
   bool pv;              // per-vertex plan: key windows
-  uint32_t* side0;      // per-vertex plans: the count of side-0 windows
 };
 
 __global__ void k_direct_write(PSides S, const Item* direct, const DirectMeta* meta, const uint32_t* perm,
@@ -734,7 +733,6 @@ __global__ void k_direct_write(PSides S, const Item* direct, const DirectMeta* m
         if (packed) iw.flags |= kItemPacked;
         o.items[q.parts + w] = iw;
       }
-      if (it.side == 0) atomicAdd(o.side0, nw);
       continue;
     }
     if (md.nparts == 0) {
@@ -1081,8 +1079,8 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     ro.small_seg_edge = alloc_n<uint32_t>(out.small_seg_edge, static_cast<int64_t>(tot.small_runs));
     ro.hub_segs = alloc_n<Segment>(out.hub_segs, static_cast<int64_t>(tot.hub_runs));
     ro.hub_part_start = alloc_n<uint32_t>(hub_part_start_b, tot.hub_parts);
-    ro.any_wide = alloc_n<uint32_t>(wide_b, 2);  // [0]: a wide run; [1]: side-0 direct windows
-    fill_u32(ro.any_wide, 2, 0u, st);
+    ro.any_wide = alloc_n<uint32_t>(wide_b, 1);
+    fill_u32(ro.any_wide, 1, 0u, st);
   }
   for (int s = 0; s < 2; ++s) {
     if (g.m == 0) break;
@@ -1127,7 +1125,6 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     dout.acc0 = tot.rev_acc;
     dout.red0 = tot.rev_reduces;
     dout.pv = p.per_vertex;
-    dout.side0 = p.per_vertex ? ro.any_wide + 1 : nullptr;
     if (n_direct > 0) {
       unsigned long long* kout = alloc_n<unsigned long long>(kout_b, n_direct);
       uint32_t* vin = alloc_n<uint32_t>(vin_b, n_direct);
@@ -1144,13 +1141,17 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
       hipLaunchKernelGGL(k_direct_count, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, io.direct, io.direct_meta,
                          perm, n_direct, p.per_vertex, dc);
       PD_TRY(hipGetLastError());
-      if (p.per_vertex) {  // the windows' total sizes the list
+      if (p.per_vertex) {
+        // the windows' total sizes the list; side 0's items come first (at1.direct
+        // of them), so the windows before side 1's first item are side 0's
         fill_u32(reinterpret_cast<uint32_t*>(dc + n_direct), sizeof(DirectCount) / 4, 0u, st);
         exclusive_scan(ct, dc, dpos, DirectCountSum{}, n_direct + 1, st);
-        DirectCount t{};
+        DirectCount t{}, t0{};
         PD_TRY(hipMemcpyAsync(&t, dpos + n_direct, sizeof(t), hipMemcpyDeviceToHost, st));
+        PD_TRY(hipMemcpyAsync(&t0, dpos + at1.direct, sizeof(t0), hipMemcpyDeviceToHost, st));
         PD_TRY(hipStreamSynchronize(st));
         n_dir_items = t.parts;
+        hp.n_direct_side0 = static_cast<int32_t>(t0.parts);
         PlanSizes z{};
         z.items = static_cast<uint64_t>(n_dir_items);
         std::string err;
@@ -1202,17 +1203,14 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
     }
     out.hub_K[s] = K;
   }
-  uint32_t flags_h[2] = {0, 0};
-  if (p.per_vertex) PD_TRY(hipMemcpyAsync(flags_h, ro.any_wide, sizeof(flags_h), hipMemcpyDeviceToHost, st));
+  uint32_t wide_h = 0;
+  if (p.per_vertex) PD_TRY(hipMemcpyAsync(&wide_h, ro.any_wide, sizeof(wide_h), hipMemcpyDeviceToHost, st));
   PD_TRY(hipStreamSynchronize(st));
-  out.any_wide = flags_h[0] != 0;
+  out.any_wide = wide_h != 0;
 
   hp.acc_slots = static_cast<int32_t>(acc_slots);
   hp.n_reverse_side0 = static_cast<int32_t>(at1.rev);
-  if (p.per_vertex) {
-    hp.n_direct_side0 = static_cast<int32_t>(flags_h[1]);
-    hp.n_hub_side0 = static_cast<int32_t>(at1.hub_parts);
-  }
+  if (p.per_vertex) hp.n_hub_side0 = static_cast<int32_t>(at1.hub_parts);
   hp.n_items_kept[0] = static_cast<int32_t>(n_dir_items);
   hp.n_items_kept[1] = static_cast<int32_t>(n_rev);
   hp.n_items_kept[2] = static_cast<int32_t>(n_groups);
