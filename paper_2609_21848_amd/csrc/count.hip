@@ -285,10 +285,9 @@ __global__ __launch_bounds__(kReverseThreads) void k_reverse(SmallArgs a) {
     cfirst = nfirst;
     nxt = nxt2;
   }
-  if (graph != kNoGraph) {
-    flush_acc();
-    tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
-  }
+  if (graph != kNoGraph) flush_acc();
+  __shared__ WaveSums wsum[kReverseWaves];
+  flush_block_end(tot, graph, wsum, kReverseWaves, a.res);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,7 +433,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs a) {
     tot.add(ss);
     wave_sync_lds();
   }
-  if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+  __shared__ WaveSums wsum[kSmallWaves];
+  flush_block_end(tot, graph, wsum, kSmallWaves, a.res);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,7 +527,8 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
       __syncthreads();
     }
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  __shared__ WaveSums wsum[kHashWaves];
+  flush_block_end(sums, graph, wsum, kHashWaves, a.res);
 }
 
 // ---------------------------------------------------------------------------
@@ -577,7 +578,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs a) {
       if (p | n) emit(it, static_cast<uint32_t>(key), p, n, sc, sums);
     }
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  __shared__ WaveSums wsum[kReduceThreads / kWave];
+  flush_block_end(sums, graph, wsum, kReduceThreads / kWave, a.res);
 }
 
 // Batch assembly: block b copies graph b's list, setting the graph index.

@@ -253,11 +253,22 @@ __global__ __launch_bounds__(kHubThreads, 2) void k_hub(HubPair hp) {
     tot += __shfl_xor(tot, d, 64);
     wd += __shfl_xor(wd, d, 64);
   }
+  // one set of atomics per workgroup: every workgroup adds to the same four
+  // words, and atomics to one address are serialized (per wavefront they
+  // took half the kernel's time)
+  __shared__ int64_t wsum[kHubThreads / 64][4];
   if (lane == 0) {
-    if (bal) atomicAdd(a.res + 0, static_cast<unsigned long long>(bal));
-    if (unb) atomicAdd(a.res + 1, static_cast<unsigned long long>(unb));
-    if (tot) atomicAdd(a.res + 2, static_cast<unsigned long long>(tot));
-    if (wd) atomicAdd(a.res + 3, static_cast<unsigned long long>(wd));
+    wsum[wave][0] = bal;
+    wsum[wave][1] = unb;
+    wsum[wave][2] = tot;
+    wsum[wave][3] = wd;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    int64_t v = 0;
+#pragma unroll
+    for (int w = 0; w < kHubThreads / 64; ++w) v += wsum[w][tid];
+    if (v) atomicAdd(a.res + tid, static_cast<unsigned long long>(v));
   }
 }
 

@@ -364,7 +364,13 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     pc.to_owner(sc, it.owner);
     __syncthreads();
   }
-  if (graph != kNoGraph) flush_all(graph);
+  {
+    const int64_t q = wave_sum64(static_cast<int64_t>(sq64)), x = wave_sum64(static_cast<int64_t>(pn64));
+    const int64_t ww = wave_sum64(static_cast<int64_t>(w64));
+    __shared__ WaveSums wsum[kPVDirectWaves];
+    flush_block_end(wave_sum64(sums.bal) + (q - ww) / 2, wave_sum64(sums.unb) + x, graph, wsum, kPVDirectWaves,
+                    a.res);
+  }
 }
 
 // The direct items' key credits of side s (by rank, ranks below n) into the
@@ -487,7 +493,8 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     }
     wave_sync_lds();
   }
-  if (graph != kNoGraph) tot.flush(a.res + static_cast<size_t>(graph) * kResStride);
+  __shared__ WaveSums wsum[kPVReverseWaves];
+  flush_block_end(tot, graph, wsum, kPVReverseWaves, a.res);
   // the workgroup's key credits (all items of a launch are of one side)
   __syncthreads();
   if (a.n_items > 0) {
@@ -618,7 +625,8 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
     }
     wave_sync_lds();
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  __shared__ WaveSums wsum[kPVSmallWaves];
+  flush_block_end(sums, graph, wsum, kPVSmallWaves, a.res);
 }
 
 // ---------------------------------------------------------------------------
@@ -745,7 +753,8 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
     }
     pc.to_owner(sc, it.owner);
   }
-  if (graph != kNoGraph) flush_sums(sums, a.res + static_cast<size_t>(graph) * kResStride);
+  __shared__ WaveSums wsum[kPVHashWaves];
+  flush_block_end(sums, graph, wsum, kPVHashWaves, a.res);
 }
 
 // ---------------------------------------------------------------------------

@@ -573,6 +573,58 @@ struct SqTotals {
   }
 };
 
+// The last flush of a launch, taken by every wavefront of a workgroup at
+// the kernel's end: each wavefront's sums go to LDS, and one thread adds them
+// to the result slots once per graph (a run of wavefronts of one graph).
+// Every wavefront of a launch adds to the same few words, and atomics to one
+// address are serialized, so per-wavefront atomics would cost a few
+// microseconds per thousand wavefronts at the end of the kernel.
+struct WaveSums {
+  int64_t bal, unb;
+  uint32_t graph, pad;
+};
+// bal, unb: the wavefront's balanced and unbalanced counts (wavefront-uniform)
+__device__ __forceinline__ void flush_block_end(int64_t bal, int64_t unb, uint32_t graph, WaveSums* sh, int nwaves,
+                                                unsigned long long* res) {
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  if (lane_id() == 0) sh[wave] = WaveSums{bal, unb, graph, 0u};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t g = kNoGraph;
+    int64_t b = 0, u = 0;
+    auto add = [&]() {
+      unsigned long long* r = res + static_cast<size_t>(g) * kResStride;
+      if (b) atomicAdd(r + kResBalanced, static_cast<unsigned long long>(b));
+      if (u) atomicAdd(r + kResUnbalanced, static_cast<unsigned long long>(u));
+      if (b + u) atomicAdd(r + kResTotal, static_cast<unsigned long long>(b + u));
+    };
+    for (int w = 0; w < nwaves; ++w) {
+      const WaveSums v = sh[w];
+      if (v.graph == kNoGraph) continue;  // a wavefront without items
+      if (v.graph != g) {
+        if (g != kNoGraph) add();
+        g = v.graph;
+        b = u = 0;
+      }
+      b += v.bal;
+      u += v.unb;
+    }
+    if (g != kNoGraph) add();
+  }
+}
+__device__ __forceinline__ void flush_block_end(const SqTotals& t, uint32_t graph, WaveSums* sh, int nwaves,
+                                                unsigned long long* res) {
+  const int64_t q = wave_sum64(static_cast<int64_t>(t.sq));
+  const int64_t x = wave_sum64(static_cast<int64_t>(t.pn)) + wave_sum64(static_cast<int64_t>(t.pn2)) / 2;
+  const int64_t ww = wave_sum64(static_cast<int64_t>(t.w));
+  flush_block_end((q - ww) / 2, x, graph, sh, nwaves, res);
+}
+// (Sums: its total is bal + unb, C(p + n, 2) = C(p, 2) + C(n, 2) + p n)
+__device__ __forceinline__ void flush_block_end(const Sums& s, uint32_t graph, WaveSums* sh, int nwaves,
+                                                unsigned long long* res) {
+  flush_block_end(wave_sum64(s.bal), wave_sum64(s.unb), graph, sh, nwaves, res);
+}
+
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
