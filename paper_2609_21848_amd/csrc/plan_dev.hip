@@ -798,16 +798,42 @@ __global__ void k_hub_transpose(const int8_t* B, const int8_t* Bm, int32_t T, in
 }
 
 // Per column y: Zc[x][y] = #{w > x : B[w][y] != 0} and
-// Zc'[w][y] = #{x < w : Bm[x][y] != 0} (T x K each).
-__global__ void k_hub_col_counts(const int8_t* B, const int8_t* Bm, int32_t T, int32_t K, int32_t* Zc, int32_t* Zcp) {
-  GRID_STRIDE(y, K) {
-    int32_t below = 0;
-    for (int32_t x = T - 1; x >= 0; --x) {
+// Zc'[w][y] = #{x < w : Bm[x][y] != 0} (T x K each), in chunks of
+// kColChunk rows: the nonzeros of every (column, chunk), then per (column,
+// chunk) the counts of the chunks below (above) it and a walk of its rows.
+constexpr int32_t kColChunk = 128;
+
+__global__ void k_hub_chunk_counts(const int8_t* B, const int8_t* Bm, int32_t T, int32_t K, uint32_t* cB,
+                                   uint32_t* cBm) {
+  const int32_t nch = (T + kColChunk - 1) / kColChunk;
+  const int64_t n = static_cast<int64_t>(nch) * K;
+  GRID_STRIDE(i, n) {  // i = c K + y: coalesced reads of row x
+    const int32_t c = static_cast<int32_t>(i / K), y = static_cast<int32_t>(i % K);
+    uint32_t nb = 0, nbm = 0;
+    for (int32_t x = c * kColChunk; x < min(T, (c + 1) * kColChunk); ++x) {
+      nb += B[static_cast<size_t>(x) * K + y] != 0;
+      nbm += Bm[static_cast<size_t>(x) * K + y] != 0;
+    }
+    cB[i] = nb;
+    cBm[i] = nbm;
+  }
+}
+
+__global__ void k_hub_col_counts(const int8_t* B, const int8_t* Bm, int32_t T, int32_t K, const uint32_t* cB,
+                                 const uint32_t* cBm, int32_t* Zc, int32_t* Zcp) {
+  const int32_t nch = (T + kColChunk - 1) / kColChunk;
+  const int64_t n = static_cast<int64_t>(nch) * K;
+  GRID_STRIDE(i, n) {
+    const int32_t c = static_cast<int32_t>(i / K), y = static_cast<int32_t>(i % K);
+    int32_t below = 0, above = 0;
+    for (int32_t d = c + 1; d < nch; ++d) below += static_cast<int32_t>(cB[static_cast<size_t>(d) * K + y]);
+    for (int32_t d = 0; d < c; ++d) above += static_cast<int32_t>(cBm[static_cast<size_t>(d) * K + y]);
+    const int32_t x0 = c * kColChunk, x1 = min(T, (c + 1) * kColChunk);
+    for (int32_t x = x1 - 1; x >= x0; --x) {
       Zc[static_cast<size_t>(x) * K + y] = below;
       below += B[static_cast<size_t>(x) * K + y] != 0;
     }
-    int32_t above = 0;
-    for (int32_t w = 0; w < T; ++w) {
+    for (int32_t w = x0; w < x1; ++w) {
       Zcp[static_cast<size_t>(w) * K + y] = above;
       above += Bm[static_cast<size_t>(w) * K + y] != 0;
     }
@@ -1198,8 +1224,16 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
       hipLaunchKernelGGL(k_hub_transpose, dim3(grid_for(static_cast<int64_t>(TK))), dim3(kThreads), 0, st, Bs, Bm,
                          T, K, Bt, Bmt);
       PD_TRY(hipGetLastError());
-      hipLaunchKernelGGL(k_hub_col_counts, dim3(grid_for(K)), dim3(kThreads), 0, st, Bs, Bm, T, K, Zc, Zcp);
+      const int64_t ncol = static_cast<int64_t>((T + kColChunk - 1) / kColChunk) * K;
+      DevBuf cb_b, cbm_b;
+      uint32_t* cB = alloc_n<uint32_t>(cb_b, ncol);
+      uint32_t* cBm = alloc_n<uint32_t>(cbm_b, ncol);
+      hipLaunchKernelGGL(k_hub_chunk_counts, dim3(grid_for(ncol)), dim3(kThreads), 0, st, Bs, Bm, T, K, cB, cBm);
       PD_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_hub_col_counts, dim3(grid_for(ncol)), dim3(kThreads), 0, st, Bs, Bm, T, K, cB, cBm, Zc,
+                         Zcp);
+      PD_TRY(hipGetLastError());
+      PD_TRY(hipStreamSynchronize(st));  // cb_b, cbm_b leave scope
     }
     out.hub_K[s] = K;
   }
