@@ -148,8 +148,13 @@ __device__ __forceinline__ void add_u64(unsigned long long* p, int64_t v) {
 
 __global__ __launch_bounds__(kCrThreads, 2) void k_hub_credit(HubCreditArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t sm[kCrStages][3][kCrStage];
-  const int nrt = a.T / kCrTile;
-  const int ti = static_cast<int>(blockIdx.x) % nrt, tj = static_cast<int>(blockIdx.x) / nrt;
+  // tiles heaviest first (the longest contractions: small row tiles when
+  // contracting over t > r, large ones over t < r), so that the light ones
+  // fill the last round; runs of consecutive tiles per XCD, as in the
+  // count's block, would put the heavy tiles on few XCDs
+  const int nrt = a.T / kCrTile, nct = a.K / kCrTile;
+  const int heavy = static_cast<int>(blockIdx.x) / nct, tj = static_cast<int>(blockIdx.x) % nct;
+  const int ti = a.upper ? heavy : nrt - 1 - heavy;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
