@@ -138,10 +138,21 @@ constexpr int64_t kHubTallyPartWork = int64_t{1} << 16;
 // Key window of a direct item of the per-vertex pass (32-bit counters in
 // LDS); wider windows are split into items that share their runs.
 constexpr int32_t kPVWindow = 16384;
-// Items with fewer than 2^16 runs (so p, n < 2^16 for every key) pack p and
-// n into one 32-bit word and take twice the window (the largest window_L:
-// one walk per pivot).
+// Items whose keys' p and n stay below 2^16 pack p and n into one 32-bit
+// word and take twice the window (the largest window_L: one walk per pivot);
+// see pv_packed.
 constexpr int32_t kPVWindowPacked = 2 * kPVWindow;
+
+// Whether a per-vertex direct item may pack its counters: a key gets at most
+// one wedge per run, and a pair's p + n is at most the key's degree.  So an
+// item with fewer than 2^16 runs packs; so does a hub pivot's item when every
+// key past the dense block has degree below 2^16 (deg_T: the degree of the
+// side's row T, the largest among its rows from T on; 0 when T is the side's
+// size): its keys below T are hub pairs, whose counters are never read, and
+// an overflow there stays inside the key's own word.
+constexpr bool pv_packed(uint32_t seg_count, bool hub, int64_t deg_T) {
+  return seg_count < 65536u || (hub && deg_T < 65536);
+}
 
 // Flag in a per-vertex plan's run mid (seg_mid, small_seg_mid): the mid's
 // degree times the largest degree of the keys' side reaches 2^32, so an edge

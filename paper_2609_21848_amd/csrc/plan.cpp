@@ -697,7 +697,10 @@ int make_plan(const HostGraph& g, const PlanParams& p, HostPlan& plan, std::stri
   for (auto& [work, i] : order) {
     const Item& it = big_direct[i];
     if (pv) {  // whole items, key windows of at most kPVWindow(Packed) keys
-      const bool packed = it.seg_count < 65536;
+      const HostSide& S = g.side[it.side];
+      const int32_t T = plan.T[it.side];
+      const int64_t deg_T = T < S.n ? static_cast<int64_t>(S.off[T + 1] - S.off[T]) : 0;
+      const bool packed = pv_packed(it.seg_count, (it.flags & kItemHubPairs) != 0, deg_T);
       const int32_t win = packed ? kPVWindowPacked : kPVWindow;
       for (int32_t lo = it.key_lo; lo < it.key_hi; lo += win) {
         Item w = it;

@@ -337,10 +337,13 @@ __device__ unsigned long long wave_sum(unsigned long long v) {
 }
 
 // Per-vertex plans: the key windows of a direct item (kPVWindowPacked keys
-// with packed counters, for fewer than 2^16 runs; else kPVWindow keys).
-__device__ int32_t pv_window(uint32_t nseg) { return nseg < 65536u ? kPVWindowPacked : kPVWindow; }
-__device__ uint32_t pv_window_count(int32_t key_lo, int32_t key_hi, uint32_t nseg) {
-  const uint32_t win = static_cast<uint32_t>(pv_window(nseg));
+// with packed counters, see pv_packed; else kPVWindow keys).
+__device__ bool pv_item_packed(const PSide& P, uint32_t nseg, uint32_t flags) {
+  const int64_t deg_T = P.T < P.n ? static_cast<int64_t>(P.off[P.T + 1] - P.off[P.T]) : 0;
+  return pv_packed(nseg, (flags & kItemHubPairs) != 0, deg_T);
+}
+__device__ uint32_t pv_window_count(int32_t key_lo, int32_t key_hi, bool packed) {
+  const uint32_t win = static_cast<uint32_t>(packed ? kPVWindowPacked : kPVWindow);
   return (static_cast<uint32_t>(key_hi - key_lo) + win - 1) / win;
 }
 
@@ -375,7 +378,8 @@ __global__ void k_count(PSide P, PlanCount* counts, unsigned long long* stats) {
           q.direct_split = 1;
         }
         slot = 0;
-        if (P.pv) mult = pv_window_count(c.key_lo, c.key_hi, c.nseg);  // the windows share the runs
+        if (P.pv)  // the windows share the runs
+          mult = pv_window_count(c.key_lo, c.key_hi, pv_item_packed(P, c.nseg, c.flags));
         break;
       case kRevC:
         q.big_runs = c.nseg;
@@ -694,12 +698,13 @@ struct DirectCountSum {
   }
 };
 
-__global__ void k_direct_count(const Item* direct, const DirectMeta* meta, const uint32_t* perm, int64_t n, bool pv,
-                               DirectCount* out) {
+__global__ void k_direct_count(PSides S, const Item* direct, const DirectMeta* meta, const uint32_t* perm, int64_t n,
+                               bool pv, DirectCount* out) {
   GRID_STRIDE(i, n) {
     if (pv) {  // every item as its key windows, in order
       const Item& it = direct[perm[i]];
-      out[i] = DirectCount{pv_window_count(it.key_lo, it.key_hi, it.seg_count), 0u, 0u};
+      const bool packed = pv_item_packed(S.s[it.side], it.seg_count, it.flags);
+      out[i] = DirectCount{pv_window_count(it.key_lo, it.key_hi, packed), 0u, 0u};
       continue;
     }
     const uint32_t np = meta[perm[i]].nparts;
@@ -723,9 +728,9 @@ __global__ void k_direct_write(PSides S, const Item* direct, const DirectMeta* m
     const DirectMeta md = meta[perm[i]];
     const DirectCount q = pos[i];
     if (o.pv) {
-      const uint32_t nw = pv_window_count(it.key_lo, it.key_hi, it.seg_count);
-      const bool packed = it.seg_count < 65536u;
-      const int32_t win = pv_window(it.seg_count);
+      const bool packed = pv_item_packed(S.s[it.side], it.seg_count, it.flags);
+      const uint32_t nw = pv_window_count(it.key_lo, it.key_hi, packed);
+      const int32_t win = packed ? kPVWindowPacked : kPVWindow;
       for (uint32_t w = 0; w < nw; ++w) {
         Item iw = it;
         iw.key_lo = it.key_lo + static_cast<int32_t>(w) * win;
@@ -1164,8 +1169,8 @@ void plan(const DevGraphView& g, const PlanParams& p, hipStream_t st, HostPlan& 
       DevBuf dc_b, dpos_b;
       DirectCount* dc = alloc_n<DirectCount>(dc_b, n_direct + 1);
       DirectCount* dpos = alloc_n<DirectCount>(dpos_b, n_direct + 1);
-      hipLaunchKernelGGL(k_direct_count, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, io.direct, io.direct_meta,
-                         perm, n_direct, p.per_vertex, dc);
+      hipLaunchKernelGGL(k_direct_count, dim3(grid_for(n_direct)), dim3(kThreads), 0, st, S, io.direct,
+                         io.direct_meta, perm, n_direct, p.per_vertex, dc);
       PD_TRY(hipGetLastError());
       if (p.per_vertex) {
         // the windows' total sizes the list; side 0's items come first (at1.direct

@@ -367,7 +367,12 @@ extern "C" int plan_emulate_pv(int32_t n_u, int32_t n_v, int64_t m, const int32_
       if (list == &plan.direct_items &&
           it.key_hi - it.key_lo > ((it.flags & kItemPacked) ? kPVWindowPacked : kPVWindow))
         return -124;
-      if ((it.flags & kItemPacked) && it.seg_count >= 65536) return -126;
+      if (it.flags & kItemPacked) {  // packed counters only where no key can reach 2^16
+        const HostSide& S = g.side[it.side];
+        const int32_t T = plan.T[it.side];
+        const int64_t deg_T = T < S.n ? static_cast<int64_t>(S.off[T + 1] - S.off[T]) : 0;
+        if (!pv_packed(it.seg_count, (it.flags & kItemHubPairs) != 0, deg_T)) return -126;
+      }
       if ((it.flags & kItemHubPairs) && list != &plan.direct_items) return -132;  // hub items are direct or small
       if ((rc = run(it.side, plan.segs.data(), plan.seg_mid.data(), plan.seg_edge.data(), it.seg_begin,
                     it.seg_count, it.key_lo, it.key_hi, false, nullptr, it.owner, lim,
