@@ -82,8 +82,11 @@ __device__ __forceinline__ void add_global(global_t<unsigned long long>* p, unsi
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class Look, bool kEdge, class Acc>
+template <class Look, bool kEdge, class Acc, bool kHoist = false>
 struct Credit {
+  // kHoist: a staging round's four slots read their counters before any is
+  // used (add_staged); Look must then be branch-free and safe for any entry
+  static constexpr bool kStaged = kHoist;
   Look look;
   Acc* cb;  // per-wavefront LDS: balanced credit per run lane
   Acc* cu;  // unbalanced
@@ -130,6 +133,24 @@ struct Credit {
     if (u) atomicAdd(&cu[j], static_cast<Acc>(u));
     edge(j, pos, b, u);
   }
+  // a staging round's slots (their runs' LDS slots take the shares)
+  __device__ __forceinline__ void add_staged(const Staged& s) {
+    uint32_t p[kStageU], n[kStageU];
+    bool ok[kStageU];
+#pragma unroll
+    for (int q = 0; q < kStageU; ++q) ok[q] = look(s.valid[q] ? s.e[q] : 0u, s.tag[q], p[q], n[q]) && s.valid[q];
+#pragma unroll
+    for (int q = 0; q < kStageU; ++q) {
+      if (!ok[q]) continue;
+      const bool sym = ((s.e[q] ^ s.tag[q]) & 1u) == 0;
+      const uint32_t b = sym ? p[q] - 1u : n[q] - 1u;
+      const uint32_t u = sym ? n[q] : p[q];
+      const uint32_t j = (s.tag[q] >> 1) & 63u;
+      if (b) atomicAdd(&cb[j], static_cast<Acc>(b));
+      if (u) atomicAdd(&cu[j], static_cast<Acc>(u));
+      edge(j, s.pos[q], b, u);
+    }
+  }
   // a chunk slot (every lane in the chunk's run): summed in registers until
   // the run changes (a wave-uniform test)
   __device__ __forceinline__ void add_chunk(uint32_t e, uint32_t tag, bool valid, uint32_t pos) {
@@ -150,10 +171,10 @@ struct Credit {
   }
 };
 
-template <bool kEdge, class Look, class Acc>
-__device__ __forceinline__ Credit<Look, kEdge, Acc> credit(Look l, Acc* cb, Acc* cu, const DevSideConst& sc,
-                                                           const RunEnds& re) {
-  Credit<Look, kEdge, Acc> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
+template <bool kEdge, bool kHoist = false, class Look, class Acc>
+__device__ __forceinline__ Credit<Look, kEdge, Acc, kHoist> credit(Look l, Acc* cb, Acc* cu, const DevSideConst& sc,
+                                                                   const RunEnds& re) {
+  Credit<Look, kEdge, Acc, kHoist> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
   if (kEdge) c.wide = __ballot(re.wide != 0);
   return c;
 }
@@ -437,18 +458,18 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
-      walk_regs<4>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj, mk, a.long_len,
-                   PairTallyBF<kPVReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
+      walk_regs<4, false, true>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj,
+                                mk, a.long_len, PairTallyBF<kPVReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
     }
     wave_sync_lds();
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
       const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
-      auto c = credit<kEdge>(
+      auto c = credit<kEdge, true>(
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
-            const uint32_t key = e >> 1;
-            const uint32_t h = C[key >> 1] >> ((key & 1u) << 4);
+            const uint32_t key = e >> 1;  // (masked: the hoisted reads also take masked slots)
+            const uint32_t h = C[(key >> 1) & (kPVReverseWords - 1)] >> ((key & 1u) << 4);
             p = h & 0xffu;
             n = (h >> 8) & 0xffu;
             return true;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels.h"
@@ -266,6 +267,13 @@ __device__ __forceinline__ void walk_add_chunk(F& f, uint32_t e, uint32_t tag, b
   walk_add(f, e, tag, valid, pos, 0);
 }
 
+// A functor that takes a staging round's slots at once (add_staged(Staged)),
+// flagged by a static member kStaged.
+template <class F, class = void>
+struct HasStaged : std::false_type {};
+template <class F>
+struct HasStaged<F, std::enable_if_t<F::kStaged>> : std::true_type {};
+
 // Walk a batch of up to 64 runs (one per lane, in registers) with one
 // wavefront, calling f.add(entry, tag, valid[, pos]) once per wedge slot.
 //  - Runs of at least long_len entries are consumed as a stream of
@@ -386,10 +394,14 @@ __device__ __forceinline__ void walk_regs(SegReg sr, const uint32_t* __restrict_
       else
         stage_round(nxt, marks, excl, slen, base, tag, total, done + kGather, adj);
     }
+    if constexpr (HasStaged<std::remove_reference_t<F>>::value) {
+      f.add_staged(cur);
+    } else {
 #pragma unroll
-    for (int u = 0; u < kStageU; ++u)
-      if (!kCompact || done + static_cast<uint32_t>(u * kWave) < total)
-        walk_add(f, cur.e[u], cur.tag[u], cur.valid[u], cur.pos[u], 0);
+      for (int u = 0; u < kStageU; ++u)
+        if (!kCompact || done + static_cast<uint32_t>(u * kWave) < total)
+          walk_add(f, cur.e[u], cur.tag[u], cur.valid[u], cur.pos[u], 0);
+    }
     if (!more) break;
     cur = nxt;
   }
