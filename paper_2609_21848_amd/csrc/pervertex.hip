@@ -82,14 +82,15 @@ __device__ __forceinline__ void add_global(global_t<unsigned long long>* p, unsi
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class Look, bool kEdge, class Acc, bool kHoist = false>
+template <class Look, bool kEdge, class Acc, bool kHoist = false, bool kPack = false>
 struct Credit {
   // kHoist: a staging round's four slots read their counters before any is
   // used (add_staged); Look must then be branch-free and safe for any entry
   static constexpr bool kStaged = kHoist;
   Look look;
-  Acc* cb;  // per-wavefront LDS: balanced credit per run lane
-  Acc* cu;  // unbalanced
+  Acc* cb;  // per-wavefront LDS: balanced credit per run lane (kPack: both,
+            // balanced in the low and unbalanced in the high 32 bits)
+  Acc* cu;  // unbalanced (unused with kPack)
   global_t<unsigned long long>* ep;
   global_t<unsigned long long>* wb;
   global_t<unsigned long long>* wu;
@@ -116,11 +117,18 @@ struct Credit {
       }
     }
   }
-  __device__ __forceinline__ void put() {
-    if (cur != 0xffffffffu) {
-      if (sb) atomicAdd(&cb[cur], sb);
-      if (su) atomicAdd(&cu[cur], su);
+  // a run's LDS slot takes b and u: one 64-bit add with kPack (each half
+  // stays below 2^32: the caller's runs bound their credits)
+  __device__ __forceinline__ void slot_add(uint32_t j, Acc b, Acc u) {
+    if constexpr (kPack) {
+      if (b | u) atomicAdd(&cb[j], (u << 32) | b);
+    } else {
+      if (b) atomicAdd(&cb[j], b);
+      if (u) atomicAdd(&cu[j], u);
     }
+  }
+  __device__ __forceinline__ void put() {
+    if (cur != 0xffffffffu) slot_add(cur, sb, su);
     sb = su = 0;
   }
   // a staged position (lanes in different runs): its shares straight to its
@@ -129,8 +137,7 @@ struct Credit {
     uint32_t b, u;
     if (!share(e, tag, valid, b, u)) return;
     const uint32_t j = (tag >> 1) & 63u;
-    if (b) atomicAdd(&cb[j], static_cast<Acc>(b));
-    if (u) atomicAdd(&cu[j], static_cast<Acc>(u));
+    slot_add(j, b, u);
     edge(j, pos, b, u);
   }
   // a staging round's slots (their runs' LDS slots take the shares)
@@ -146,8 +153,7 @@ struct Credit {
       const uint32_t b = sym ? p[q] - 1u : n[q] - 1u;
       const uint32_t u = sym ? n[q] : p[q];
       const uint32_t j = (s.tag[q] >> 1) & 63u;
-      if (b) atomicAdd(&cb[j], static_cast<Acc>(b));
-      if (u) atomicAdd(&cu[j], static_cast<Acc>(u));
+      slot_add(j, b, u);
       edge(j, s.pos[q], b, u);
     }
   }
@@ -171,12 +177,31 @@ struct Credit {
   }
 };
 
-template <bool kEdge, bool kHoist = false, class Look, class Acc>
-__device__ __forceinline__ Credit<Look, kEdge, Acc, kHoist> credit(Look l, Acc* cb, Acc* cu, const DevSideConst& sc,
-                                                                   const RunEnds& re) {
-  Credit<Look, kEdge, Acc, kHoist> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o), as_global(sc.ewu_o)};
+template <bool kEdge, bool kHoist = false, bool kPack = false, class Look, class Acc>
+__device__ __forceinline__ Credit<Look, kEdge, Acc, kHoist, kPack> credit(Look l, Acc* cb, Acc* cu,
+                                                                          const DevSideConst& sc, const RunEnds& re) {
+  static_assert(!kPack || sizeof(Acc) == 8, "packed slots are 64-bit");
+  Credit<Look, kEdge, Acc, kHoist, kPack> c{l, cb, cu, as_global(sc.epack_o), as_global(sc.ewb_o),
+                                            as_global(sc.ewu_o)};
   if (kEdge) c.wide = __ballot(re.wide != 0);
   return c;
+}
+
+// A run's credits b and u to its mid (and, with kEdge, to its first edge).
+template <bool kEdge>
+__device__ __forceinline__ void mid_credits_out(unsigned long long b, unsigned long long u, RunEnds re,
+                                                const DevSideConst& sc) {
+  const int32_t id = sc.orig_mid[re.mid];
+  if (b) atomicAdd(&sc.bal_mid[id], b);
+  if (u) atomicAdd(&sc.unb_mid[id], u);
+  if (kEdge) {
+    if (re.wide) {
+      if (b) add_global(as_global(sc.ewb) + re.edge, b);
+      if (u) add_global(as_global(sc.ewu) + re.edge, u);
+    } else {  // the run's credits are below 2^32 (no wide flag)
+      add_global(as_global(sc.epack) + re.edge, (u << 32) | b);
+    }
+  }
 }
 
 // After a batch's credit walk: each lane adds its run's credits to the mid
@@ -189,17 +214,21 @@ __device__ __forceinline__ void flush_mid_credits(Acc* cb, Acc* cu, RunEnds re, 
   if (b | u) {
     cb[lane] = 0;
     cu[lane] = 0;
-    const int32_t id = sc.orig_mid[re.mid];
-    if (b) atomicAdd(&sc.bal_mid[id], b);
-    if (u) atomicAdd(&sc.unb_mid[id], u);
-    if (kEdge) {
-      if (re.wide) {
-        if (b) add_global(as_global(sc.ewb) + re.edge, b);
-        if (u) add_global(as_global(sc.ewu) + re.edge, u);
-      } else {  // the run's credits are below 2^32 (no wide flag)
-        add_global(as_global(sc.epack) + re.edge, (u << 32) | b);
-      }
-    }
+    mid_credits_out<kEdge>(b, u, re, sc);
+  }
+  wave_sync_lds();
+}
+
+// The same for packed slots (balanced | unbalanced << 32).
+template <bool kEdge>
+__device__ __forceinline__ void flush_mid_credits_packed(unsigned long long* cbu, RunEnds re,
+                                                         const DevSideConst& sc) {
+  wave_sync_lds();
+  const int lane = lane_id();
+  const unsigned long long v = cbu[lane];
+  if (v) {
+    cbu[lane] = 0;
+    mid_credits_out<kEdge>(v & 0xffffffffull, v >> 32, re, sc);
   }
   wave_sync_lds();
 }
@@ -428,19 +457,21 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   __shared__ uint32_t dummies[kPVReverseWaves][kWave];
   __shared__ __attribute__((aligned(16))) uint32_t mtab[kPVReverseWaves][kGather];
   __shared__ uint8_t mflag[kPVReverseWaves][kGather];
-  // a run's mid credits: at most its length (< 4096) times 255
-  __shared__ uint32_t cb[kPVReverseWaves][kWave], cu[kPVReverseWaves][kWave];
-  __shared__ uint32_t kbal[kMaxReverseL], kunb[kMaxReverseL];
+  // a run's mid credits, balanced | unbalanced << 32: each at most the
+  // run's length (< 4096) times 255
+  __shared__ unsigned long long cbu[kPVReverseWaves][kWave];
+  // the workgroup's key credits, balanced | unbalanced << 32 (each half
+  // below 2^31, see above)
+  __shared__ unsigned long long ksum[kMaxReverseL];
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
   uint32_t* C = cnt[wave];
   if (lane == 0 && (lds_addr(C) & (kPVReverseWords * 4 - 1)) != 0) atomicOr(a.err, kErrLdsLayout);
-  for (int i = threadIdx.x; i < kMaxReverseL; i += kPVReverseThreads) kbal[i] = kunb[i] = 0;
+  for (int i = threadIdx.x; i < kMaxReverseL; i += kPVReverseThreads) ksum[i] = 0;
   for (int i = lane; i < kPVReverseWords; i += kWave) C[i] = 0;
   for (int i = lane; i < static_cast<int>(kGather); i += kWave) mflag[wave][i] = 0;
-  cb[wave][lane] = 0;
-  cu[wave][lane] = 0;
+  cbu[wave][lane] = 0;
   wave_sync_lds();
   const Marks<uint8_t> mk{mtab[wave], mflag[wave]};
   SqTotals tot;  // the pass's global counts, from 32-bit per-item sums
@@ -466,7 +497,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
       const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re);
-      auto c = credit<kEdge, true>(
+      auto c = credit<kEdge, true, true>(
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;  // (masked: the hoisted reads also take masked slots)
             const uint32_t h = C[(key >> 1) & (kPVReverseWords - 1)] >> ((key & 1u) << 4);
@@ -474,10 +505,10 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
             n = (h >> 8) & 0xffu;
             return true;
           },
-          cb[wave], cu[wave], sc, re);
+          cbu[wave], static_cast<unsigned long long*>(nullptr), sc, re);
       walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
-      flush_mid_credits<kEdge>(cb[wave], cu[wave], re, sc);
+      flush_mid_credits_packed<kEdge>(cbu[wave], re, sc);
     }
     // the key credits: 16-byte reads of the counter words, quads of zero
     // words skipped; a pair with one wedge adds nothing.  p, n <= 255, so a
@@ -487,8 +518,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     auto local = [&](uint32_t key, uint32_t p, uint32_t n) {
       ss.add(p, n);
       const uint32_t cb2 = (__umul24(p, p - 1u) + __umul24(n, n - 1u)) >> 1, cx = __umul24(p, n);
-      if (cb2) atomicAdd(&kbal[key], cb2);
-      if (cx) atomicAdd(&kunb[key], cx);
+      if (cb2 | cx) atomicAdd(&ksum[key], (static_cast<unsigned long long>(cx) << 32) | cb2);
       oc += cb2;
       ox += cx;
     };
@@ -523,9 +553,9 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     const DevSideConst sc = load_const(a.sides, 2 * i0.graph + i0.side);
     const int32_t nkeys = sc.R < kMaxReverseL ? sc.R : kMaxReverseL;
     for (int k = threadIdx.x; k < nkeys; k += kPVReverseThreads) {
-      const uint32_t b = kbal[k], u = kunb[k];
-      if (b) atomicAdd(&sc.bal[sc.orig[k]], static_cast<unsigned long long>(b));
-      if (u) atomicAdd(&sc.unb[sc.orig[k]], static_cast<unsigned long long>(u));
+      const unsigned long long v = ksum[k], b = v & 0xffffffffull, u = v >> 32;
+      if (b) atomicAdd(&sc.bal[sc.orig[k]], b);
+      if (u) atomicAdd(&sc.unb[sc.orig[k]], u);
     }
   }
 }
