@@ -1177,7 +1177,17 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
     a.pos_v = g->edge_pos_v.as<uint32_t>();
     a.m = g->host.m;
     // runs flagged wide, or the dense block's credits (kept in the two-word form)
-    a.wide = d.any_wide || hp.T[0] > 0 ? 1 : 0;
+    a.wide = d.any_wide || hp.T[0] > 0 || hp.T[1] > 0 ? 1 : 0;
+    a.off_u = g->off[0].as<uint32_t>();
+    a.off_v = g->off[1].as<uint32_t>();
+    a.adj_u = g->adj[0].as<uint32_t>();
+    a.n_u = g->host.n_u;
+    a.n_v = g->host.n_v;
+    a.T_u = hp.T[0];
+    a.T_v = hp.T[1];
+    a.max_deg_u = static_cast<unsigned long long>(g->host.side[0].max_deg);
+    a.max_deg_v = static_cast<unsigned long long>(g->host.side[1].max_deg);
+    a.wide_all = hp.p.wide_all ? 1 : 0;
     // the combine kernel writes both outputs: a NULL one goes to a buffer of
     // the graph's
     DevBuf& tmp = g->pe_tmp;

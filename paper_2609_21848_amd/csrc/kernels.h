@@ -223,6 +223,18 @@ struct EdgeCombineArgs {
   long long* out_unb;
   int64_t m;
   int32_t wide;           // 0: no run kept two-word credits (e_wb, e_wu are all zero)
+  // Which edges can hold two-word credits (all with wide_all): those whose U
+  // or V end has degree d with d * (the other side's largest degree) >= 2^32
+  // (their runs are flagged wide), and the dense block's rows (U ranks
+  // below T_u, V ranks below T_v).  Side ranks are in non-increasing degree
+  // order, so both sets are rank prefixes, found from the row offsets.
+  const uint32_t* off_u;  // [n_u + 1] U-CSR row offsets
+  const uint32_t* off_v;  // [n_v + 1]
+  const uint32_t* adj_u;  // [m] U-CSR entries (V rank << 1 | negative)
+  int32_t n_u, n_v;
+  int32_t T_u, T_v;
+  unsigned long long max_deg_u, max_deg_v;
+  int32_t wide_all;
 };
 
 // The per-vertex pass with per-edge credits as well (the same plans).

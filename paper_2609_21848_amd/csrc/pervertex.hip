@@ -812,7 +812,35 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
 // Per-edge outputs in input-record order: each edge's credits from both
 // CSRs (as a run's first edge on one side and as a walked entry on the
 // other) added together.  One thread per U-CSR position, grid-stride.
+// The first rank of a side whose degree d has d * other < 2^32 (degrees do
+// not increase with rank).
+__device__ int32_t first_narrow_rank(const uint32_t* off, int32_t n, unsigned long long other) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    const unsigned long long d = as_global(off)[mid + 1] - as_global(off)[mid];
+    if (d * other >= (1ull << 32))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(256) void k_edge_combine(EdgeCombineArgs a) {
+  // edges that can hold two-word credits: U-CSR positions below kcut (their
+  // U end is a wide mid or a dense-block row) or V ends ranked below vcut
+  int64_t kcut = 0;
+  uint32_t vcut = 0;
+  if (a.wide) {
+    if (a.wide_all) {
+      kcut = a.m;
+    } else {
+      const int32_t nu = max(first_narrow_rank(a.off_u, a.n_u, a.max_deg_v), a.T_u);
+      kcut = as_global(a.off_u)[nu];
+      vcut = static_cast<uint32_t>(max(first_narrow_rank(a.off_v, a.n_v, a.max_deg_u), a.T_v));
+    }
+  }
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < a.m; k += stride) {
     const uint32_t r = as_global(a.rec)[k];
@@ -820,7 +848,9 @@ __global__ __launch_bounds__(256) void k_edge_combine(EdgeCombineArgs a) {
     const unsigned long long p0 = as_global(a.e_pack[0])[k], p1 = as_global(a.e_pack[1])[q];
     unsigned long long b = (p0 & 0xffffffffull) + (p1 & 0xffffffffull);
     unsigned long long u = (p0 >> 32) + (p1 >> 32);
-    if (a.wide) {  // uniform: the two-word arrays are read only when some run used them
+    // the two-word words of other edges are zero: not read (the V side's
+    // are at random positions, a cache line each)
+    if (k < kcut || (as_global(a.adj_u)[k] >> 1) < vcut) {
       b += as_global(a.e_wb[0])[k] + as_global(a.e_wb[1])[q];
       u += as_global(a.e_wu[0])[k] + as_global(a.e_wu[1])[q];
     }
