@@ -1097,6 +1097,10 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
         ca.unb_mid = g->pv_out[1 - s][1].as<unsigned long long>();
         ca.ewb = g->pe_out[s][1].as<unsigned long long>();
         ca.ewu = g->pe_out[s][2].as<unsigned long long>();
+        ca.epack = g->pe_out[s][0].as<unsigned long long>();
+        ca.off = g->off[s].as<uint32_t>();
+        ca.n = s ? g->host.n_v : g->host.n_u;
+        ca.max_deg_other = static_cast<unsigned long long>(g->host.side[1 - s].max_deg);
         ca.T = hp.T[s];
         ca.K = d.hub_K[s];
         ca.D = d.hub_D[s];
@@ -1183,8 +1187,6 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
     a.adj_u = g->adj[0].as<uint32_t>();
     a.n_u = g->host.n_u;
     a.n_v = g->host.n_v;
-    a.T_u = hp.T[0];
-    a.T_v = hp.T[1];
     a.max_deg_u = static_cast<unsigned long long>(g->host.side[0].max_deg);
     a.max_deg_v = static_cast<unsigned long long>(g->host.side[1].max_deg);
     a.wide_all = hp.p.wide_all ? 1 : 0;

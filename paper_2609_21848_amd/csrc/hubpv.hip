@@ -168,6 +168,8 @@ __global__ __launch_bounds__(kCrThreads, 2) void k_hub_credit(HubCreditArgs a) {
   const v4i ones = {0x01010101, 0x01010101, 0x01010101, 0x01010101};
   const int ar = (wave >> 1) * 64 + r, br = (wave & 1) * 64 + r;
   const int ch = lane >> 5;
+  // edge credits of rows below nw take two words, the others one packed word
+  const int32_t nw = a.pos ? first_narrow_rank(a.off, a.n, a.max_deg_other) : 0;
   // the loads of one stage: each wavefront fills 2 x 1 KB of each operand
   int srow[2], scol[2], dst[2];
 #pragma unroll
@@ -273,8 +275,16 @@ __global__ __launch_bounds__(kCrThreads, 2) void k_hub_credit(HubCreditArgs a) {
           if (a.pos) {
             const int32_t pq = as_global(a.pos)[at];
             if (pq >= 0) {
-              if (bal) add_u64(a.ewb + pq, bal);
-              if (unb) add_u64(a.ewu + pq, unb);
+              if (rr < nw) {
+                if (bal) add_u64(a.ewb + pq, bal);
+                if (unb) add_u64(a.ewu + pq, unb);
+              } else if (bal | unb) {
+                // the packed word is the integer sum of balanced + 2^32 x
+                // unbalanced: negative digit shares wrap and are made good,
+                // and both final sums are below 2^32 on this row
+                add_u64(a.epack + pq,
+                        static_cast<int64_t>(static_cast<uint64_t>(bal) + (static_cast<uint64_t>(unb) << 32)));
+              }
             }
           }
         }

@@ -191,6 +191,12 @@ struct HubCreditArgs {
   unsigned long long* unb_mid;
   unsigned long long* ewb;       // per-edge wide credits by position in the side's CSR
   unsigned long long* ewu;
+  unsigned long long* epack;     // per-edge packed credits (balanced | unbalanced << 32)
+  // rows whose degree d has d * max_deg_other < 2^32 keep their edges'
+  // credits in the packed words, the others in ewb and ewu
+  const uint32_t* off;           // [n + 1] the side's CSR row offsets
+  int32_t n;
+  unsigned long long max_deg_other;
   int32_t T, K, D;
   int32_t upper;                 // 1: row r contracts over t > r (pivot-mid); 0: over t < r (end-mid)
 };
@@ -225,14 +231,13 @@ struct EdgeCombineArgs {
   int32_t wide;           // 0: no run kept two-word credits (e_wb, e_wu are all zero)
   // Which edges can hold two-word credits (all with wide_all): those whose U
   // or V end has degree d with d * (the other side's largest degree) >= 2^32
-  // (their runs are flagged wide), and the dense block's rows (U ranks
-  // below T_u, V ranks below T_v).  Side ranks are in non-increasing degree
+  // (the runs of such mids are flagged wide, and the dense block keeps such
+  // rows' credits in two words).  Side ranks are in non-increasing degree
   // order, so both sets are rank prefixes, found from the row offsets.
   const uint32_t* off_u;  // [n_u + 1] U-CSR row offsets
   const uint32_t* off_v;  // [n_v + 1]
   const uint32_t* adj_u;  // [m] U-CSR entries (V rank << 1 | negative)
   int32_t n_u, n_v;
-  int32_t T_u, T_v;
   unsigned long long max_deg_u, max_deg_v;
   int32_t wide_all;
 };

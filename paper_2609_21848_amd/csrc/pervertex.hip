@@ -812,33 +812,17 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
 // Per-edge outputs in input-record order: each edge's credits from both
 // CSRs (as a run's first edge on one side and as a walked entry on the
 // other) added together.  One thread per U-CSR position, grid-stride.
-// The first rank of a side whose degree d has d * other < 2^32 (degrees do
-// not increase with rank).
-__device__ int32_t first_narrow_rank(const uint32_t* off, int32_t n, unsigned long long other) {
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = lo + (hi - lo) / 2;
-    const unsigned long long d = as_global(off)[mid + 1] - as_global(off)[mid];
-    if (d * other >= (1ull << 32))
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(256) void k_edge_combine(EdgeCombineArgs a) {
-  // edges that can hold two-word credits: U-CSR positions below kcut (their
-  // U end is a wide mid or a dense-block row) or V ends ranked below vcut
+  // edges that can hold two-word credits: U-CSR positions below kcut (rows
+  // of U ranks below the first narrow one) or V ends ranked below vcut
   int64_t kcut = 0;
   uint32_t vcut = 0;
   if (a.wide) {
     if (a.wide_all) {
       kcut = a.m;
     } else {
-      const int32_t nu = max(first_narrow_rank(a.off_u, a.n_u, a.max_deg_v), a.T_u);
-      kcut = as_global(a.off_u)[nu];
-      vcut = static_cast<uint32_t>(max(first_narrow_rank(a.off_v, a.n_v, a.max_deg_u), a.T_v));
+      kcut = as_global(a.off_u)[first_narrow_rank(a.off_u, a.n_u, a.max_deg_v)];
+      vcut = static_cast<uint32_t>(first_narrow_rank(a.off_v, a.n_v, a.max_deg_u));
     }
   }
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;

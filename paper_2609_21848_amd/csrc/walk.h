@@ -591,6 +591,24 @@ struct SqTotals {
 // Every wavefront of a launch adds to the same few words, and atomics to one
 // address are serialized, so per-wavefront atomics would cost a few
 // microseconds per thousand wavefronts at the end of the kernel.
+// The first rank of a side whose degree d has d * other < 2^32 (side ranks
+// are in non-increasing degree order).  Edges at rows of lower rank, or
+// whose mid in a run is of lower rank, may hold per-edge credits of 2^32 or
+// more: two-word credits; any other edge's credits stay below 2^32 (an edge
+// (x, y) lies in at most (deg x - 1)(deg y - 1) butterflies).
+__device__ __forceinline__ int32_t first_narrow_rank(const uint32_t* off, int32_t n, unsigned long long other) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    const unsigned long long d = as_global(off)[mid + 1] - as_global(off)[mid];
+    if (d * other >= (1ull << 32))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 struct WaveSums {
   int64_t bal, unb;
   uint32_t graph, pad;
