@@ -1101,6 +1101,7 @@ int local_counts(dbbc_graph* g, const dbbc_options* opt, int64_t* const vout[2][
         ca.off = g->off[s].as<uint32_t>();
         ca.n = s ? g->host.n_v : g->host.n_u;
         ca.max_deg_other = static_cast<unsigned long long>(g->host.side[1 - s].max_deg);
+        ca.wide_all = hp.p.wide_all ? 1 : 0;
         ca.T = hp.T[s];
         ca.K = d.hub_K[s];
         ca.D = d.hub_D[s];

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kCrThreads, 2) void k_hub_credit(HubCreditArgs a) {
   const int ar = (wave >> 1) * 64 + r, br = (wave & 1) * 64 + r;
   const int ch = lane >> 5;
   // edge credits of rows below nw take two words, the others one packed word
-  const int32_t nw = a.pos ? first_narrow_rank(a.off, a.n, a.max_deg_other) : 0;
+  const int32_t nw = !a.pos ? 0 : a.wide_all ? a.T : first_narrow_rank(a.off, a.n, a.max_deg_other);
   // the loads of one stage: each wavefront fills 2 x 1 KB of each operand
   int srow[2], scol[2], dst[2];
 #pragma unroll

@@ -59,7 +59,8 @@ struct DevSideConst {
   // edges, the run's first edge (a position in side s's CSR) and the walked
   // entry (a position in the other side's CSR).  Credits of runs without the
   // kMidWide flag go to one word per edge, balanced in the low and
-  // unbalanced in the high 32 bits; those of wide runs to two words.
+  // unbalanced in the high 32 bits; those of wide runs to two words.  (The
+  // dense block splits its edges the same way, by row.)
   const uint32_t* seg_edge;       // position of every run's first edge in side s's CSR
   const uint32_t* small_seg_edge; // ... of every run of small_segs
   unsigned long long* epack;      // [m] by position in side s's CSR
@@ -193,10 +194,11 @@ struct HubCreditArgs {
   unsigned long long* ewu;
   unsigned long long* epack;     // per-edge packed credits (balanced | unbalanced << 32)
   // rows whose degree d has d * max_deg_other < 2^32 keep their edges'
-  // credits in the packed words, the others in ewb and ewu
+  // credits in the packed words, the others (all with wide_all) in ewb and ewu
   const uint32_t* off;           // [n + 1] the side's CSR row offsets
   int32_t n;
   unsigned long long max_deg_other;
+  int32_t wide_all;
   int32_t T, K, D;
   int32_t upper;                 // 1: row r contracts over t > r (pivot-mid); 0: over t < r (end-mid)
 };
