@@ -354,6 +354,24 @@ __global__ __launch_bounds__(kPVDirectThreads) void k_pv_direct(DirectArgs a) {
     for (uint32_t k0 = it.seg_begin + wave; k0 < seg_end; k0 += kPVDirectThreads) {
       RunEnds re;
       const SegReg sr = load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, seg_end, re, kPVDirectWaves);
+      if (packed && hubT == 0) {
+        // p, n < 2^16 and at most kPVWindowPacked keys per window: a run's
+        // credits per window stay below 2^31, so one packed LDS word per run
+        auto c = credit<kEdge, false, true>(
+            [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
+              const uint32_t key = e >> 1;
+              if (key < lo || key >= hi) return false;
+              const uint32_t v = C[key - lo];
+              p = v & 0xffffu;
+              n = v >> 16;
+              return true;
+            },
+            cb[wave], static_cast<unsigned long long*>(nullptr), sc, re);
+        walk_regs<4, kEdge, true>(sr, sc.other_adj, mk, a.long_len, c);
+        c.flush();
+        flush_mid_credits_packed<kEdge>(cb[wave], re, sc);
+        continue;
+      }
       auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t, uint32_t& p, uint32_t& n) {
             const uint32_t key = e >> 1;
@@ -635,6 +653,31 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
       const SegReg sr = load_seg_pv<true, kEdge>(sc.small_segs, sc.small_seg_mid, sc.small_seg_edge, k0, k1, re);
+      if (hubT == 0) {
+        // a plain group has at most kSmallGroupWork wedges: a run's credits
+        // stay below 2^18, so one packed LDS word per run
+        auto c = credit<kEdge, false, true>(
+            [&](uint32_t e, uint32_t tag, uint32_t& p, uint32_t& n) {
+              const uint32_t key = hkey(e, tag);
+              uint32_t h = mix32(key) & mask;
+              for (uint32_t probe = 0; probe <= mask; ++probe) {
+                if (K[h] == key) {
+                  const uint32_t v = V[h];
+                  p = v & 0xffffu;
+                  n = v >> 16;
+                  return true;
+                }
+                h = (h + 1) & mask;
+              }
+              atomicOr(a.err, kErrHashFull);  // a tallied key must be there
+              return false;
+            },
+            cb[wave], static_cast<unsigned long long*>(nullptr), sc, re);
+        walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
+        c.flush();
+        flush_mid_credits_packed<kEdge>(cb[wave], re, sc);
+        continue;
+      }
       auto c = credit<kEdge>(
           [&](uint32_t e, uint32_t tag, uint32_t& p, uint32_t& n) {
             if ((e >> 1) < hubT) {
