@@ -198,13 +198,17 @@ def test_crossing_hubs_packed_and_wide_credits(dbbc):
     r = vp_counts(n_u, n_v, u, v, s, per_vertex=True, per_edge=True)
     with dbbc.Graph(n_u, n_v, u, v, s) as h:
         # without and with a dense block (which holds both hubs: pair counts
-        # of three 7-bit digits in its products)
-        for opts in ({"hub_T": 0}, {"hub_T": 256}):
+        # of three 7-bit digits in its products; the hubs' rows keep their
+        # edge credits in two words, its other rows in one packed word, and
+        # with the wide-edges option every row in two words)
+        for opts in ({"hub_T": 0}, {"hub_T": 256}, {"hub_T": 256, "flags": WIDE}):
             c, be, ue = h.count_per_edge(**opts)
             assert (c.balanced, c.unbalanced, c.total, c.wedges) == (r.balanced, r.unbalanced, r.total,
                                                                      r.wedges)
             assert np.array_equal(be.cpu().numpy(), r.bal_e), opts
             assert np.array_equal(ue.cpu().numpy(), r.unb_e), opts
+            if "flags" in opts:
+                continue
             _, bu, bv, uu, uv = h.count_per_vertex(**opts)
             for t, want in ((bu, r.bal_u), (bv, r.bal_v), (uu, r.unb_u), (uv, r.unb_v)):
                 assert np.array_equal(t.cpu().numpy(), want), opts
