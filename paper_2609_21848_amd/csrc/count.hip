@@ -305,7 +305,10 @@ constexpr int kSmallSlots = 2 * kSmallGroupWork;
 // with nothing (left) to insert aim them at their own sink word, and the
 // probe loop ends when the wavefront has no pending lane (a ballot).  One
 // compare-and-swap per probe claims an empty slot or finds the key; the
-// count is added to the slot found.
+// count is added to the slot found.  Probes step by an odd stride from a
+// second multiplicative hash of the key (double hashing): without linear
+// probing's clusters the wavefront's longest probe chain, which every lane
+// waits for, is shorter.
 struct SmallInsert {
   uint32_t* K;
   uint32_t* V;
@@ -316,6 +319,7 @@ struct SmallInsert {
     const uint32_t key = ((tag >> 1) << kb) | (e >> 1);
     const uint32_t inc = wedge_inc(e, tag);
     uint32_t h = (key * 0x9E3779B1u) >> hshift;
+    const uint32_t step = ((key * 0x85EBCA6Bu) >> hshift) | 1u;  // odd: size probes visit every slot
     bool pend = valid;
     for (uint32_t probe = 0;; ++probe) {
       const uint32_t c = atomicCAS(pend ? &K[h] : sink, kEmpty, key);
@@ -327,7 +331,7 @@ struct SmallInsert {
         if (lane_id() == 0) atomicOr(err, kErrHashFull);
         break;
       }
-      h = (h + 1) & mask;
+      h = (h + step) & mask;
     }
   }
 };
@@ -499,6 +503,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
           if (passes > 1 && (hk >> 16) % passes != pass) return;
           const unsigned long long inc = ((e ^ g) & 1u) ? (1ull << 32) : 1ull;
           uint32_t h = hk & mask;
+          const uint32_t st = probe_step(key, mask);
           for (uint32_t probe = 0;; ++probe) {
             if (probe > mask) {  // full table
               atomicOr(a.err, kErrHashFull);
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(kHashThreads) void k_hash(HashArgs a) {
               atomicAdd(&vals[h], inc);
               break;
             }
-            h = (h + 1) & mask;
+            h = (h + st) & mask;
           }
         }));
       }

@@ -633,6 +633,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
                      const uint32_t key = hkey(e, tag);
                      const uint32_t inc = ((e ^ tag) & 1u) ? 0x10000u : 1u;
                      uint32_t h = mix32(key) & mask;
+                     const uint32_t st = probe_step(key, mask);
                      for (uint32_t probe = 0;; ++probe) {
                        if (probe > mask) {  // full table: cannot happen at load <= 1/2
                          atomicOr(a.err, kErrHashFull);
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
                          atomicAdd(&V[h], inc);
                          break;
                        }
-                       h = (h + 1) & mask;
+                       h = (h + st) & mask;
                      }
                    }));
     }
@@ -660,6 +661,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
             [&](uint32_t e, uint32_t tag, uint32_t& p, uint32_t& n) {
               const uint32_t key = hkey(e, tag);
               uint32_t h = mix32(key) & mask;
+              const uint32_t st = probe_step(key, mask);
               for (uint32_t probe = 0; probe <= mask; ++probe) {
                 if (K[h] == key) {
                   const uint32_t v = V[h];
@@ -667,7 +669,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
                   n = v >> 16;
                   return true;
                 }
-                h = (h + 1) & mask;
+                h = (h + st) & mask;
               }
               atomicOr(a.err, kErrHashFull);  // a tallied key must be there
               return false;
@@ -686,6 +688,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
             }
             const uint32_t key = hkey(e, tag);
             uint32_t h = mix32(key) & mask;
+            const uint32_t st = probe_step(key, mask);
             for (uint32_t probe = 0; probe <= mask; ++probe) {
               if (K[h] == key) {
                 const uint32_t v = V[h];
@@ -693,7 +696,7 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
                 n = v >> 16;
                 return true;
               }
-              h = (h + 1) & mask;
+              h = (h + st) & mask;
             }
             atomicOr(a.err, kErrHashFull);  // a tallied key must be there
             return false;
@@ -791,6 +794,7 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
                        if (!mine(key, hk)) return;
                        const unsigned long long inc = ((e ^ tag) & 1u) ? (1ull << 32) : 1ull;
                        uint32_t h = hk & (kPVHashSlots - 1);
+                       const uint32_t st = probe_step(key, kPVHashSlots - 1);
                        for (uint32_t probe = 0;; ++probe) {
                          if (probe >= static_cast<uint32_t>(kPVHashSlots)) {
                            atomicOr(a.err, kErrHashFull);
@@ -802,7 +806,7 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
                            atomicAdd(&vals[h], inc);
                            break;
                          }
-                         h = (h + 1) & (kPVHashSlots - 1);
+                         h = (h + st) & (kPVHashSlots - 1);
                        }
                      }));
       }
@@ -817,6 +821,7 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
               uint32_t hk;
               if (!mine(key, hk)) return false;
               uint32_t h = hk & (kPVHashSlots - 1);
+              const uint32_t st = probe_step(key, kPVHashSlots - 1);
               for (int probe = 0; probe < kPVHashSlots; ++probe) {
                 if (keys[h] == key) {
                   const unsigned long long v = vals[h];
@@ -824,7 +829,7 @@ __global__ __launch_bounds__(kPVHashThreads) void k_pv_hash(HashArgs a) {
                   n = static_cast<uint32_t>(v >> 32);
                   return true;
                 }
-                h = (h + 1) & (kPVHashSlots - 1);
+                h = (h + st) & (kPVHashSlots - 1);
               }
               atomicOr(a.err, kErrHashFull);
               return false;

@@ -655,6 +655,13 @@ __device__ __forceinline__ void flush_block_end(const Sums& s, uint32_t graph, W
   flush_block_end(wave_sum64(s.bal), wave_sum64(s.unb), graph, sh, nwaves, res);
 }
 
+// Probe stride of key in a power-of-two table (mask = size - 1): odd, so
+// size probes visit every slot; from a multiplicative hash independent of
+// the home slot's (double hashing: no clusters of consecutive taken slots).
+__device__ __forceinline__ uint32_t probe_step(uint32_t key, uint32_t mask) {
+  return (((key * 0x85EBCA6Bu) >> 16) | 1u) & mask;
+}
+
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
