@@ -305,7 +305,7 @@ constexpr int kSmallSlots = 2 * kSmallGroupWork;
 // with nothing (left) to insert aim them at their own sink word, and the
 // probe loop ends when the wavefront has no pending lane (a ballot).  One
 // compare-and-swap per probe claims an empty slot or finds the key; the
-// count is added to the slot found.  Probes step by an odd stride from a
+// count is added to the slot found once the loop ends.  Probes step by an odd stride from a
 // second multiplicative hash of the key (double hashing): without linear
 // probing's clusters the wavefront's longest probe chain, which every lane
 // waits for, is shorter.
@@ -321,10 +321,11 @@ struct SmallInsert {
     uint32_t h = (key * 0x9E3779B1u) >> hshift;
     const uint32_t step = ((key * 0x85EBCA6Bu) >> hshift) | 1u;  // odd: size probes visit every slot
     bool pend = valid;
+    uint32_t at = 0;  // the slot found
     for (uint32_t probe = 0;; ++probe) {
       const uint32_t c = atomicCAS(pend ? &K[h] : sink, kEmpty, key);
       const bool hit = pend && (c == kEmpty || c == key);
-      atomicAdd(hit ? &V[h] : sink, inc);
+      at = hit ? h : at;
       pend = pend && !hit;
       if (__ballot(pend) == 0) break;
       if (probe == mask) {  // full table: cannot happen at load <= 1/2
@@ -333,6 +334,7 @@ struct SmallInsert {
       }
       h = (h + step) & mask;
     }
+    atomicAdd(valid && !pend ? &V[at] : sink, inc);
   }
 };
 
