@@ -301,14 +301,14 @@ constexpr int kSmallWaves = kSmallThreads / kWave;
 constexpr int kSmallSlots = 2 * kSmallGroupWork;
 
 // Insertion of a group's wedges into its hash table, with no divergent
-// branch: every lane issues every probe's compare-and-swap and add, lanes
-// with nothing (left) to insert aim them at their own sink word, and the
-// probe loop ends when the wavefront has no pending lane (a ballot).  One
-// compare-and-swap per probe claims an empty slot or finds the key; the
-// count is added to the slot found once the loop ends.  Probes step by an odd stride from a
-// second multiplicative hash of the key (double hashing): without linear
-// probing's clusters the wavefront's longest probe chain, which every lane
-// waits for, is shorter.
+// branch: every lane issues every probe's compare-and-swap, a lane with
+// nothing (left) to insert aims it at its own sink word, and the probe loop
+// ends when the wavefront has no pending lane (a ballot).  One
+// compare-and-swap per probe claims an empty slot or finds the key; after
+// the loop each lane adds its count to the slot found (or to its sink).
+// Probes step by an odd stride from a second multiplicative hash of the key
+// (double hashing): without linear probing's clusters the wavefront's
+// longest probe chain, which every lane waits for, is shorter.
 struct SmallInsert {
   uint32_t* K;
   uint32_t* V;
