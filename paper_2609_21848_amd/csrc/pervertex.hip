@@ -716,9 +716,11 @@ __global__ __launch_bounds__(kPVSmallThreads) void k_pv_small(SmallArgs a) {
       if ((key & kmask) < hubT) continue;  // a hub pair: credited by the dense block
       PairCredit pc;
       pc.add(sc, key & kmask, v & 0xffffu, v >> 16, sums);
-      const int32_t owner = sc.small_owner[it.acc_slot + static_cast<int32_t>(key >> kb)];
-      if (pc.c) atomicAdd(&sc.bal[sc.orig[owner]], static_cast<unsigned long long>(pc.c));
-      if (pc.x) atomicAdd(&sc.unb[sc.orig[owner]], static_cast<unsigned long long>(pc.x));
+      if (pc.c | pc.x) {  // a pair with one wedge credits nothing
+        const int32_t id = sc.orig[sc.small_owner[it.acc_slot + static_cast<int32_t>(key >> kb)]];
+        if (pc.c) atomicAdd(&sc.bal[id], static_cast<unsigned long long>(pc.c));
+        if (pc.x) atomicAdd(&sc.unb[id], static_cast<unsigned long long>(pc.x));
+      }
     }
     wave_sync_lds();
   }
