@@ -481,6 +481,9 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
   // the workgroup's key credits, balanced | unbalanced << 32 (each half
   // below 2^31, see above)
   __shared__ unsigned long long ksum[kMaxReverseL];
+  // chunk slots in flight per walk: 8 where the registers allow (the
+  // per-edge walks keep 4)
+  constexpr int kU = kEdge ? 4 : 8;
   // wave index, known to the compiler as wavefront-uniform
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = lane_id();
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
     for (uint32_t k0 = it.seg_begin; k0 < seg_end; k0 += kWave) {
       const uint32_t k1 = k0 + kWave < seg_end ? k0 + kWave : seg_end;
       RunEnds re;
-      walk_regs<4, false, true>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj,
+      walk_regs<kU, false, true>(load_seg_pv<false, kEdge>(sc.segs, sc.seg_mid, sc.seg_edge, k0, k1, re), sc.other_adj,
                                 mk, a.long_len, PairTallyBF<kPVReverseWords>{lds_addr(C), lds_addr(&dummies[wave][lane])});
     }
     wave_sync_lds();
@@ -524,7 +527,7 @@ __global__ __launch_bounds__(kPVReverseThreads) void k_pv_reverse(SmallArgs a) {
             return true;
           },
           cbu[wave], static_cast<unsigned long long*>(nullptr), sc, re);
-      walk_regs<4, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
+      walk_regs<kU, kEdge>(sr, sc.other_adj, mk, a.long_len, c);
       c.flush();
       flush_mid_credits_packed<kEdge>(cbu[wave], re, sc);
     }
